@@ -1,0 +1,123 @@
+/*
+ * FP64 CPU oracle for the MR-STAT matrix-free Jacobian products.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing on the product path may link, load or call
+ * this library: only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it. It shares no code, table or constant with the HIP
+ * library.
+ *
+ * Every routine here is the plain definition of what the method computes,
+ * written for readability, in double / double complex, with OpenMP only over
+ * independent voxels or output rows (no blocking, no fusion).
+ *
+ * Paper: van der Heide, Sbrizzi, Luijten, van den Berg, "High resolution
+ * in-vivo MR-STAT using a matrix-free and parallelized reconstruction
+ * algorithm" (NMR Biomed 2019, arXiv 1904.13244).
+ *
+ * Conventions (the paper's statement of the problem, Theory section):
+ *   voxel j = iy*nx + ix, Nv = nx*ny;
+ *   parameter vector alpha in R^{5 Nv}, voxel j's parameters at j + p*Nv
+ *   (parameter-major layout of the Theory section), with
+ *   p = 0: ln T1 [s], 1: ln T2 [s], 2: B1 [a.u.], 3: Re rho, 4: Im rho
+ *   (log scaling of T1 and T2 as in the Methods / Reconstructions section);
+ *   r = d - s, f = 0.5 ||r||^2, J = dr/dalpha, g = Re(J^H r).
+ */
+#ifndef MRSTAT_ORACLE_H
+#define MRSTAT_ORACLE_H
+
+#include <complex.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int nx, ny;        /* image grid */
+    int n_tr;          /* number of TRs = readouts */
+    int n_read;        /* samples per readout (os * nx) */
+    int n_states;      /* EPG truncation K */
+    int n_coils;       /* receive coils C */
+    double tr, te;     /* seconds */
+    double t_inv;      /* delay between inversion and first RF, seconds */
+    const double *flip_deg;   /* [n_tr] flip angle per TR, degrees */
+    const double *rf_phase;   /* [n_tr] RF phase per TR, radians */
+    const int *ky_line;       /* [n_tr] phase-encode line sampled in each TR */
+} oracle_problem;
+
+typedef struct {
+    int n_cg;          /* CG iterations (exact count; breakdown exits only) */
+    int n_ls_max;      /* backtracking trials t = 1, 1/2, ... */
+    int param_mask;    /* bit p set = parameter p is reconstructed */
+    double lo[3], hi[3];  /* box for ln T1, ln T2, B1 */
+    double armijo_c1;
+} oracle_gn_opts;
+
+typedef struct {
+    double f0, f1, gnorm, step_norm, t;
+    int cg_iters, ls_trials, accepted;
+} oracle_gn_report;
+
+/* EPG simulation with forward-mode tangents (Supporting Information S2
+ * pattern, applied to the extended-phase-graph states).
+ * theta: [5][Nv]; trains out: [4][n_tr][Nv] complex = m, dm/dlnT1, dm/dlnT2,
+ * dm/dB1. If with_tangents == 0 only train 0 is written. */
+void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
+                double complex *trains);
+
+/* Encoding phase E[n,k,j] of sample k of the readout in TR n for voxel j. */
+double complex oracle_phase(const oracle_problem *p, int n, int k, int ix, int iy);
+
+/* All phases of TR n: out[k][j] = E[n,k,j], [n_read][Nv]. */
+void oracle_phases(const oracle_problem *p, int n, double complex *out);
+
+/* s_c[n,k] = sum_j C_c[j] rho_j m_j[n] E[n,k,j]: the discretised volumetric
+ * signal model (eq. 1 and its discretisation), direct sum over voxels.
+ * coil: [C][Nv] complex or NULL (C must be 1, sensitivity 1).
+ * mask: [Nv] or NULL. s out: [C][n_tr][n_read]. */
+void oracle_signal_direct(const oracle_problem *p, const double *theta,
+                          const double complex *coil, const unsigned char *mask,
+                          const double complex *trains, double complex *s);
+
+/* Same sum evaluated as y-then-x separable sums (Cartesian phases factor). */
+void oracle_signal_separable(const oracle_problem *p, const double *theta,
+                             const double complex *coil, const unsigned char *mask,
+                             const double complex *trains, double complex *s);
+
+/* J v for real v [5][Nv]; out [C][n_tr][n_read]. J = dr/dalpha = -ds/dalpha. */
+void oracle_jv(const oracle_problem *p, const double *theta,
+               const double complex *coil, const unsigned char *mask,
+               const double complex *trains, const double *v, double complex *out);
+
+/* Re(J^H w) for w [C][n_tr][n_read]; out [5][Nv]. */
+void oracle_jhw(const oracle_problem *p, const double *theta,
+                const double complex *coil, const unsigned char *mask,
+                const double complex *trains, const double complex *w, double *out);
+
+/* Explicit Jacobian, row (c,n,k) major: J[(c*n_tr + n)*n_read + k][q*Nv + j]. */
+void oracle_jacobian(const oracle_problem *p, const double *theta,
+                     const double complex *coil, const unsigned char *mask,
+                     const double complex *trains, double complex *J);
+
+/* f = 0.5 ||d - s||^2 with s from the separable sum; r out (may be NULL). */
+double oracle_residual(const oracle_problem *p, const double *theta,
+                       const double complex *coil, const unsigned char *mask,
+                       const double complex *data, double complex *r);
+
+/* One inexact Gauss-Newton iteration (Algorithm 6, line-search form): theta
+ * updated in place when a trial is accepted. */
+void oracle_gn_step(const oracle_problem *p, double *theta,
+                    const double complex *coil, const unsigned char *mask,
+                    const double complex *data, const oracle_gn_opts *o,
+                    oracle_gn_report *rep);
+
+/* Proton-density initialisation: least-squares solution of M(alpha0) rho = d
+ * by CGLS (equal to LSQR in exact arithmetic), n_iter iterations from rho = 0.
+ * theta's rows 0..2 are used, rows 3..4 are overwritten. */
+void oracle_rho_init(const oracle_problem *p, double *theta,
+                     const double complex *coil, const unsigned char *mask,
+                     const double complex *data, int n_iter);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -485,10 +485,14 @@ static void apply_masks(double *x, int Nv, int param_mask, const unsigned char *
             if (!((param_mask >> q) & 1) || !active(mask, j)) x[(size_t)q * Nv + j] = 0.0;
 }
 
-static void project(double *theta, int Nv, const oracle_gn_opts *o)
+/* Box projection of the reconstructed (active) ln T1, ln T2, B1 entries onto
+ * the attainable intervals; inactive parameters and masked voxels are left as
+ * they are. */
+static void project(double *theta, int Nv, const oracle_gn_opts *o, const unsigned char *mask)
 {
     for (int q = 0; q < 3; ++q)
         for (int j = 0; j < Nv; ++j) {
+            if (!((o->param_mask >> q) & 1) || !active(mask, j)) continue;
             double *t = &theta[(size_t)q * Nv + j];
             if (*t < o->lo[q]) *t = o->lo[q];
             if (*t > o->hi[q]) *t = o->hi[q];
@@ -552,7 +556,7 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
     rep->f1 = f0;
     for (int k = 0; k < o->n_ls_max; ++k) {
         for (size_t i = 0; i < N; ++i) trial[i] = theta[i] + t * step[i];
-        project(trial, Nv, o);
+        project(trial, Nv, o, mask);
         double ft = oracle_residual(p, trial, coil, mask, data, NULL);
         double pred = 0.0, sn = 0.0;
         for (size_t i = 0; i < N; ++i) {

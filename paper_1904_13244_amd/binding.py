@@ -1,0 +1,291 @@
+"""Thin ctypes binding of libmrstat (include/mrstat.h).
+
+The functions below carry the C names and only marshal arguments: torch
+tensors are checked for device, dtype, shape and contiguity and passed as raw
+device pointers together with the current HIP stream. Every step of the
+computation runs in the HIP kernels of libmrstat.so; there is no fallback:
+if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrstat.so")
+
+OK, ERR_ARG, ERR_SHAPE, ERR_HIP, ERR_WORKSPACE, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+ENC_FP32, ENC_SPLIT_BF16, ENC_FP16 = 0, 1, 2
+_STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR_WORKSPACE",
+           -5: "ERR_NONFINITE", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED"}
+
+
+class MrstatError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("n_tr", C.c_int32), ("n_read", C.c_int32),
+                ("n_states", C.c_int32), ("n_coils", C.c_int32),
+                ("tr_s", C.c_double), ("te_s", C.c_double), ("t_inv_s", C.c_double),
+                ("flip_deg", C.POINTER(C.c_double)), ("rf_phase_rad", C.POINTER(C.c_double)),
+                ("ky_line", C.POINTER(C.c_int32))]
+
+
+class GnOpts(C.Structure):
+    _fields_ = [("n_cg", C.c_int32), ("n_ls_max", C.c_int32), ("param_mask", C.c_int32),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("armijo_c1", C.c_double)]
+
+
+class GnReport(C.Structure):
+    _fields_ = [("f0", C.c_double), ("f1", C.c_double), ("gnorm", C.c_double),
+                ("step_norm", C.c_double), ("t", C.c_double), ("cg_iters", C.c_int32),
+                ("ls_trials", C.c_int32), ("accepted", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libmrstat.so (built by paper_1904_13244_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1904_13244_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, P = C.c_void_p, C.c_int32, C.POINTER
+        sig = {
+            "mrstat_create": ([P(Problem), P(vp)], C.c_int),
+            "mrstat_destroy": ([vp], None),
+            "mrstat_last_error": ([vp], C.c_char_p),
+            "mrstat_workspace_bytes": ([vp], C.c_size_t),
+            "mrstat_bind": ([vp, vp, C.c_size_t, vp, vp, vp], C.c_int),
+            "mrstat_set_encoding": ([vp, C.c_int], C.c_int),
+            "mrstat_set_epg_lanes": ([vp, i32], C.c_int),
+            "mrstat_simulate": ([vp, vp, vp, vp], C.c_int),
+            "mrstat_residual": ([vp, vp, i32, vp, vp, P(C.c_double), vp], C.c_int),
+            "mrstat_jv": ([vp, vp, i32, vp, vp, vp], C.c_int),
+            "mrstat_jhw": ([vp, vp, i32, vp, vp, vp], C.c_int),
+            "mrstat_gn_step": ([vp, vp, vp, P(GnOpts), P(GnReport), vp], C.c_int),
+            "mrstat_rho_init": ([vp, vp, vp, i32, vp], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["mrstat_create", "mrstat_destroy", "mrstat_last_error", "mrstat_workspace_bytes",
+            "mrstat_bind", "mrstat_set_encoding", "mrstat_set_epg_lanes", "mrstat_simulate", "mrstat_residual", "mrstat_jv",
+            "mrstat_jhw", "mrstat_gn_step", "mrstat_rho_init"]
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        msg = lib().mrstat_last_error(ctx)
+        raise MrstatError(status, msg.decode() if msg else "")
+
+
+# --------------------------------------------------------------- C-named calls
+def mrstat_create(prob):
+    """prob: object with nx, ny, n_tr, n_read, n_states, n_coils, tr, te, t_inv,
+    flip_deg, rf_phase, ky_line. Returns (ctx handle, keep-alive arrays)."""
+    flip = np.ascontiguousarray(prob.flip_deg, dtype=np.float64)
+    phase = np.ascontiguousarray(prob.rf_phase, dtype=np.float64)
+    ky = np.ascontiguousarray(prob.ky_line, dtype=np.int32)
+    s = Problem(prob.nx, prob.ny, prob.n_tr, prob.n_read, prob.n_states, prob.n_coils,
+                prob.tr, prob.te, prob.t_inv,
+                flip.ctypes.data_as(C.POINTER(C.c_double)),
+                phase.ctypes.data_as(C.POINTER(C.c_double)),
+                ky.ctypes.data_as(C.POINTER(C.c_int32)))
+    h = C.c_void_p()
+    _check(lib().mrstat_create(C.byref(s), C.byref(h)))
+    return h
+
+
+def mrstat_destroy(ctx):
+    lib().mrstat_destroy(ctx)
+
+
+def mrstat_workspace_bytes(ctx):
+    return int(lib().mrstat_workspace_bytes(ctx))
+
+
+def mrstat_bind(ctx, ws_ptr, ws_bytes, coil_ptr, mask_ptr, stream):
+    _check(lib().mrstat_bind(ctx, ws_ptr, ws_bytes, coil_ptr, mask_ptr, stream), ctx)
+
+
+def mrstat_set_encoding(ctx, enc):
+    _check(lib().mrstat_set_encoding(ctx, enc), ctx)
+
+
+def mrstat_set_epg_lanes(ctx, lanes):
+    _check(lib().mrstat_set_epg_lanes(ctx, int(lanes)), ctx)
+
+
+def mrstat_simulate(ctx, theta_ptr, trains_ptr, stream):
+    _check(lib().mrstat_simulate(ctx, theta_ptr, trains_ptr, stream), ctx)
+
+
+def mrstat_residual(ctx, theta_ptr, reuse, data_ptr, r_ptr, want_f, stream):
+    f = C.c_double(0.0)
+    _check(lib().mrstat_residual(ctx, theta_ptr, int(reuse), data_ptr, r_ptr,
+                                 C.byref(f) if want_f else None, stream), ctx)
+    return f.value if want_f else None
+
+
+def mrstat_jv(ctx, theta_ptr, reuse, v_ptr, out_ptr, stream):
+    _check(lib().mrstat_jv(ctx, theta_ptr, int(reuse), v_ptr, out_ptr, stream), ctx)
+
+
+def mrstat_jhw(ctx, theta_ptr, reuse, w_ptr, out_ptr, stream):
+    _check(lib().mrstat_jhw(ctx, theta_ptr, int(reuse), w_ptr, out_ptr, stream), ctx)
+
+
+def mrstat_gn_step(ctx, theta_ptr, data_ptr, opts: GnOpts, stream) -> GnReport:
+    rep = GnReport()
+    _check(lib().mrstat_gn_step(ctx, theta_ptr, data_ptr, C.byref(opts), C.byref(rep), stream), ctx)
+    return rep
+
+
+def mrstat_rho_init(ctx, theta_ptr, data_ptr, n_iter, stream):
+    _check(lib().mrstat_rho_init(ctx, theta_ptr, data_ptr, int(n_iter), stream), ctx)
+
+
+# --------------------------------------------------------------- torch helper
+@dataclass
+class Context:
+    """Owns a library context plus its workspace tensor (torch allocates all
+    device memory; the library allocates none)."""
+    prob: object
+    coil: object = None      # torch complex64 [C][Nv] on the GPU, or None
+    mask: object = None      # torch uint8 [Nv] on the GPU, or None
+
+    def __post_init__(self):
+        import torch
+        self.torch = torch
+        self.h = mrstat_create(self.prob)
+        self.ws_bytes = mrstat_workspace_bytes(self.h)
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        nv = self.prob.nx * self.prob.ny
+        if self.coil is not None:
+            self._expect(self.coil, torch.complex64, (self.prob.n_coils, nv))
+        if self.mask is not None:
+            self._expect(self.mask, torch.uint8, (nv,))
+        mrstat_bind(self.h, self.ws_ptr, self.ws_bytes,
+                    self.coil.data_ptr() if self.coil is not None else None,
+                    self.mask.data_ptr() if self.mask is not None else None, self.stream)
+
+    # -- helpers
+    @property
+    def stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def _expect(self, t, dtype, shape):
+        if not isinstance(t, self.torch.Tensor):
+            raise TypeError("expected a torch tensor")
+        if t.device.type != "cuda" or t.dtype != dtype or tuple(t.shape) != tuple(shape) \
+                or not t.is_contiguous():
+            raise ValueError(f"expected contiguous {dtype} {tuple(shape)} on the GPU, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+    @property
+    def nv(self):
+        return self.prob.nx * self.prob.ny
+
+    @property
+    def data_shape(self):
+        return (self.prob.n_coils, self.prob.n_tr, self.prob.n_read)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.torch.cuda.synchronize()
+            mrstat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls
+    def set_encoding(self, enc):
+        mrstat_set_encoding(self.h, enc)
+
+    def set_epg_lanes(self, lanes):
+        mrstat_set_epg_lanes(self.h, lanes)
+
+    def simulate(self, theta, trains=None):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        if trains is None:
+            trains = T.empty((4, self.prob.n_tr, self.nv), dtype=T.float32, device=self.dev)
+        self._expect(trains, T.float32, (4, self.prob.n_tr, self.nv))
+        mrstat_simulate(self.h, theta.data_ptr(), trains.data_ptr(), self.stream)
+        return trains
+
+    def linearise(self, theta):
+        self._expect(theta, self.torch.float32, (5, self.nv))
+        mrstat_simulate(self.h, theta.data_ptr(), None, self.stream)
+
+    def residual(self, theta, data, reuse=False, out=None, want_f=True):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(data, T.complex64, self.data_shape)
+        if out is None:
+            out = T.empty(self.data_shape, dtype=T.complex64, device=self.dev)
+        self._expect(out, T.complex64, self.data_shape)
+        f = mrstat_residual(self.h, theta.data_ptr(), reuse, data.data_ptr(), out.data_ptr(),
+                            want_f, self.stream)
+        return f, out
+
+    def jv(self, theta, v, reuse=False, out=None):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(v, T.float32, (5, self.nv))
+        if out is None:
+            out = T.empty(self.data_shape, dtype=T.complex64, device=self.dev)
+        self._expect(out, T.complex64, self.data_shape)
+        mrstat_jv(self.h, theta.data_ptr(), reuse, v.data_ptr(), out.data_ptr(), self.stream)
+        return out
+
+    def jhw(self, theta, w, reuse=False, out=None):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(w, T.complex64, self.data_shape)
+        if out is None:
+            out = T.empty((5, self.nv), dtype=T.float32, device=self.dev)
+        self._expect(out, T.float32, (5, self.nv))
+        mrstat_jhw(self.h, theta.data_ptr(), reuse, w.data_ptr(), out.data_ptr(), self.stream)
+        return out
+
+    def gn_step(self, theta, data, n_cg, param_mask, lo, hi, n_ls_max=8, armijo_c1=1e-4):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(data, T.complex64, self.data_shape)
+        o = GnOpts(int(n_cg), int(n_ls_max), int(param_mask), (C.c_float * 3)(*lo),
+                   (C.c_float * 3)(*hi), float(armijo_c1))
+        return mrstat_gn_step(self.h, theta.data_ptr(), data.data_ptr(), o, self.stream)
+
+    def rho_init(self, theta, data, n_iter=20):
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(data, T.complex64, self.data_shape)
+        mrstat_rho_init(self.h, theta.data_ptr(), data.data_ptr(), n_iter, self.stream)
+        return theta

@@ -1,0 +1,495 @@
+// C ABI of libmrstat (include/mrstat.h): context, validation, workspace
+// layout, per-problem tables, and the host sequencing of the kernels for the
+// signal/residual, J v, Re(J^H w), the inexact Gauss-Newton step and the
+// CGLS proton-density initialisation.
+#include "mrstat.h"
+#include "mrstat_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mrstat;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kAdjChunks = 8;        // TR chunks of the adjoint y-stage (partials)
+constexpr int kFwdTrPerBlock = 16;   // TRs per block of the forward y-stage
+
+struct Layout {
+    size_t trains, trial_m, upart, W, apart, r, y, vec, red, scal, seq, eytab, extab;
+    size_t cx, csv, cp, cth, total;
+    int nby, n_red, adj_per_chunk, adj_chunks;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct mrstat_ctx_s {
+    Dims d{};
+    SeqTimes st{};
+    std::vector<float2> seq;      // (flip [rad], RF sign)
+    std::vector<float2> eytab;    // [T][ny]
+    std::vector<float2> extab;    // [nk][nx]
+    Layout L{};
+    mrstat_enc enc = MRSTAT_ENC_FP32;
+    int epg_lanes = 0;
+    // bound device state
+    char* ws = nullptr;
+    const float2* coil = nullptr;
+    const uint8_t* mask = nullptr;
+    bool bound = false;
+    bool lin_valid = false;
+    std::string err;
+
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    float* trains() const { return at<float>(L.trains); }
+    float* trial_m() const { return at<float>(L.trial_m); }
+    float2* upart() const { return at<float2>(L.upart); }
+    float2* W() const { return at<float2>(L.W); }
+    float* apart() const { return at<float>(L.apart); }
+    float2* r() const { return at<float2>(L.r); }
+    float2* y() const { return at<float2>(L.y); }
+    float* vec(int i) const { return at<float>(L.vec) + (size_t)i * 5 * d.nv; }
+    double* red() const { return at<double>(L.red); }
+    double* scal() const { return at<double>(L.scal); }
+    const float2* dseq() const { return at<float2>(L.seq); }
+    const float2* deytab() const { return at<float2>(L.eytab); }
+    const float2* dextab() const { return at<float2>(L.extab); }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+mrstat_status fail(mrstat_ctx c, mrstat_status st, const std::string& msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return st;
+}
+
+#define HIP_TRY(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, MRSTAT_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+Layout make_layout(const Dims& d)
+{
+    Layout L{};
+    L.nby = ceil_div(d.ny, YBLOCK);
+    L.adj_chunks = std::min(kAdjChunks, d.T);
+    L.adj_per_chunk = ceil_div(d.T, L.adj_chunks);
+    L.adj_chunks = ceil_div(d.T, L.adj_per_chunk);
+    const int M = d.C * d.T;
+    const int gemm_blocks = ceil_div(2 * d.nk, 64) * ceil_div(M, 64);
+    L.n_red = std::max(2 * RED_BLOCKS, gemm_blocks);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    const size_t nv = d.nv, T = d.T;
+    L.trains = take(4 * T * nv * sizeof(float));
+    L.trial_m = take(T * nv * sizeof(float));
+    L.upart = take((size_t)L.nby * d.C * T * d.nx * sizeof(float2));
+    L.W = take((size_t)d.C * T * d.nx * sizeof(float2));
+    L.apart = take((size_t)L.adj_chunks * 8 * nv * sizeof(float));
+    L.r = take((size_t)d.C * T * d.nk * sizeof(float2));
+    L.y = take((size_t)d.C * T * d.nk * sizeof(float2));
+    L.vec = take(6 * 5 * nv * sizeof(float));
+    L.red = take((size_t)L.n_red * sizeof(double));
+    L.scal = take(SCAL_DOUBLES * sizeof(double));
+    L.seq = take(T * sizeof(float2));
+    L.eytab = take(T * d.ny * sizeof(float2));
+    L.extab = take((size_t)d.nk * d.nx * sizeof(float2));
+    L.cx = take(nv * sizeof(float2));
+    L.csv = take(nv * sizeof(float2));
+    L.cp = take(nv * sizeof(float2));
+    L.cth = take(5 * nv * sizeof(float));
+    L.total = o;
+    return L;
+}
+
+// Exact phase tables: the phase index of (k, ix) is the integer
+// (k - nk/2)(ix - nx/2) reduced modulo nk, so exp(-2 pi i q / nk) is evaluated
+// in FP64 at a reduced argument and rounded once to FP32.
+void build_tables(mrstat_ctx c, const mrstat_problem* p)
+{
+    const Dims& d = c->d;
+    c->seq.resize(d.T);
+    c->eytab.resize((size_t)d.T * d.ny);
+    c->extab.resize((size_t)d.nk * d.nx);
+    for (int n = 0; n < d.T; ++n) {
+        const double ph = p->rf_phase_rad ? p->rf_phase_rad[n] : 0.0;
+        const float sg = std::cos(ph) > 0.0 ? 1.f : -1.f;
+        c->seq[n] = make_float2((float)(p->flip_deg[n] * kPi / 180.0), sg);
+        const long ky = (p->ky_line ? p->ky_line[n] : n % d.ny) - d.ny / 2;
+        for (int iy = 0; iy < d.ny; ++iy) {
+            long q = (ky * (long)(iy - d.ny / 2)) % d.ny;
+            if (q < 0) q += d.ny;
+            const double a = -2.0 * kPi * (double)q / (double)d.ny;
+            c->eytab[(size_t)n * d.ny + iy] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    }
+    for (int k = 0; k < d.nk; ++k) {
+        const long kx = k - d.nk / 2;
+        for (int ix = 0; ix < d.nx; ++ix) {
+            long q = (kx * (long)(ix - d.nx / 2)) % d.nk;
+            if (q < 0) q += d.nk;
+            const double a = -2.0 * kPi * (double)q / (double)d.nk;
+            c->extab[(size_t)k * d.nx + ix] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    }
+}
+
+mrstat_status check_ready(mrstat_ctx ctx)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (!ctx->bound) return fail(ctx, MRSTAT_ERR_WORKSPACE, "context has no workspace (mrstat_bind)");
+    return MRSTAT_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ----------------------------------------------------------- kernel sequences
+mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s)
+{
+    HIP_TRY(launch_epg(ctx->d, ctx->st, theta, ctx->dseq(), ctx->trains(), true, ctx->epg_lanes, s));
+    ctx->lin_valid = true;
+    return MRSTAT_OK;
+}
+
+// s-type forward product into out: mode 0 r = data - s (+ f partials),
+// 1 out = -J-direction signal, 2 out = s.
+mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const float* trains,
+                      const float* theta, const float* v, const void* data, void* out,
+                      double* f_out, hipStream_t s)
+{
+    const Dims& d = ctx->d;
+    HIP_TRY(launch_ystage_fwd(d, mode_y, trains, theta, v, ctx->coil, ctx->mask, ctx->deytab(),
+                              ctx->upart(), kFwdTrPerBlock, s));
+    int nred = 0;
+    HIP_TRY(launch_xgemm_fwd(d, ctx->enc, mode_x, ctx->upart(), ctx->L.nby, ctx->dextab(),
+                             (const float2*)data, (float2*)out, ctx->red(), &nred, s));
+    if (mode_x == 0 && f_out) HIP_TRY(launch_sum_partials(ctx->red(), nred, f_out, s));
+    return MRSTAT_OK;
+}
+
+mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, hipStream_t s)
+{
+    const Dims& d = ctx->d;
+    HIP_TRY(launch_xgemm_adj(d, ctx->enc, (const float2*)w, ctx->dextab(), ctx->W(), s));
+    HIP_TRY(launch_ystage_adj(d, ctx->trains(), 4, ctx->coil, ctx->mask, ctx->deytab(), ctx->W(),
+                              ctx->apart(), ctx->L.adj_per_chunk, s));
+    HIP_TRY(launch_jhw_finish(d, ctx->apart(), ctx->L.adj_chunks, theta, ctx->mask, g, s));
+    return MRSTAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
+{
+    mrstat_ctx ctx = nullptr;
+    if (!p || !out) return fail(nullptr, MRSTAT_ERR_ARG, "null problem or output pointer");
+    *out = nullptr;
+    if (!p->flip_deg) return fail(nullptr, MRSTAT_ERR_ARG, "flip_deg is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->n_tr < 1 || p->n_read < 1)
+        return fail(nullptr, MRSTAT_ERR_SHAPE, "sizes must be positive");
+    if (p->n_read < p->nx) return fail(nullptr, MRSTAT_ERR_SHAPE, "n_read must be >= nx");
+    if (p->n_states < 1 || p->n_states > 64)
+        return fail(nullptr, MRSTAT_ERR_SHAPE, "n_states must be in [1, 64]");
+    if (p->n_coils < 1 || p->n_coils > 16)
+        return fail(nullptr, MRSTAT_ERR_SHAPE, "n_coils must be in [1, 16]");
+    if ((long)p->nx * p->ny > (1L << 26) || (long)p->n_tr * p->nx * p->ny > (1L << 34))
+        return fail(nullptr, MRSTAT_ERR_SHAPE, "problem too large");
+    if (!(std::isfinite(p->tr_s) && std::isfinite(p->te_s) && std::isfinite(p->t_inv_s)) ||
+        p->tr_s <= 0.0 || p->te_s < 0.0 || p->te_s > p->tr_s || p->t_inv_s < 0.0)
+        return fail(nullptr, MRSTAT_ERR_ARG, "timing must satisfy 0 <= te <= tr, tr > 0, t_inv >= 0");
+    for (int n = 0; n < p->n_tr; ++n) {
+        if (!std::isfinite(p->flip_deg[n])) return fail(nullptr, MRSTAT_ERR_ARG, "non-finite flip angle");
+        if (p->ky_line && (p->ky_line[n] < 0 || p->ky_line[n] >= p->ny))
+            return fail(nullptr, MRSTAT_ERR_ARG, "ky_line out of [0, ny)");
+        if (p->rf_phase_rad) {
+            const double ph = p->rf_phase_rad[n];
+            if (!std::isfinite(ph)) return fail(nullptr, MRSTAT_ERR_ARG, "non-finite RF phase");
+            const double sn = std::fabs(std::sin(ph));
+            if (sn > 1e-9)
+                return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "RF phases other than 0 or pi are not supported");
+        }
+    }
+    ctx = new (std::nothrow) mrstat_ctx_s();
+    if (!ctx) return fail(nullptr, MRSTAT_ERR_ARG, "out of host memory");
+    ctx->d = Dims{p->nx, p->ny, p->nx * p->ny, p->n_tr, p->n_read, p->n_states, p->n_coils};
+    ctx->st = SeqTimes{(float)p->tr_s, (float)p->te_s, (float)p->t_inv_s};
+    build_tables(ctx, p);
+    ctx->L = make_layout(ctx->d);
+    *out = ctx;
+    return MRSTAT_OK;
+}
+
+void mrstat_destroy(mrstat_ctx ctx) { delete ctx; }
+
+const char* mrstat_last_error(mrstat_ctx ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+size_t mrstat_workspace_bytes(mrstat_ctx ctx) { return ctx ? ctx->L.total : 0; }
+
+mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const void* d_coil,
+                          const uint8_t* d_mask, mrstat_stream stream)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (!d_ws) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (!aligned(d_ws, 256)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < ctx->L.total) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace too small");
+    if (ctx->d.C > 1 && !d_coil) return fail(ctx, MRSTAT_ERR_ARG, "coil maps required when n_coils > 1");
+    if (d_coil && !aligned(d_coil, 8)) return fail(ctx, MRSTAT_ERR_ARG, "coil maps must be 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->ws = (char*)d_ws;
+    ctx->coil = (const float2*)d_coil;
+    ctx->mask = d_mask;
+    ctx->bound = false;
+    ctx->lin_valid = false;
+    HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.seq, ctx->seq.data(), ctx->seq.size() * sizeof(float2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.eytab, ctx->eytab.data(),
+                           ctx->eytab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.extab, ctx->extab.data(),
+                           ctx->extab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ctx->bound = true;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (enc != MRSTAT_ENC_FP32) return fail(ctx, MRSTAT_ERR_UNSUPPORTED, "encoding precision not built");
+    ctx->enc = enc;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8))
+        return fail(ctx, MRSTAT_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8");
+    ctx->epg_lanes = lanes;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_simulate(mrstat_ctx ctx, const float* d_theta, float* d_trains,
+                              mrstat_stream stream)
+{
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!d_theta) return fail(ctx, MRSTAT_ERR_ARG, "theta is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    st = linearise(ctx, d_theta, s);
+    if (st != MRSTAT_OK) return st;
+    if (d_trains)
+        HIP_TRY(hipMemcpyAsync(d_trains, ctx->trains(), (size_t)4 * ctx->d.T * ctx->d.nv * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    return MRSTAT_OK;
+}
+
+static mrstat_status prepare(mrstat_ctx ctx, const float* d_theta, int32_t reuse, hipStream_t s)
+{
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!d_theta) return fail(ctx, MRSTAT_ERR_ARG, "theta is NULL");
+    if (reuse) {
+        if (!ctx->lin_valid) return fail(ctx, MRSTAT_ERR_STATE, "reuse requested without a linearisation");
+        return MRSTAT_OK;
+    }
+    return linearise(ctx, d_theta, s);
+}
+
+mrstat_status mrstat_residual(mrstat_ctx ctx, const float* d_theta, int32_t reuse,
+                              const void* d_data, void* d_r, double* h_f, mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = prepare(ctx, d_theta, reuse, s);
+    if (st != MRSTAT_OK) return st;
+    if (!d_data || !d_r) return fail(ctx, MRSTAT_ERR_ARG, "data or r is NULL");
+    if (!aligned(d_data, 8) || !aligned(d_r, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
+    double* f_dev = ctx->scal() + SC_F0;
+    st = forward(ctx, 0, 0, ctx->trains(), d_theta, nullptr, d_data, d_r, f_dev, s);
+    if (st != MRSTAT_OK) return st;
+    if (h_f) {
+        double f2 = 0.0;
+        HIP_TRY(hipMemcpyAsync(&f2, f_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *h_f = 0.5 * f2;
+    }
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_jv(mrstat_ctx ctx, const float* d_theta, int32_t reuse, const float* d_v,
+                        void* d_out, mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = prepare(ctx, d_theta, reuse, s);
+    if (st != MRSTAT_OK) return st;
+    if (!d_v || !d_out) return fail(ctx, MRSTAT_ERR_ARG, "v or out is NULL");
+    if (!aligned(d_out, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
+    return forward(ctx, 1, 1, ctx->trains(), d_theta, d_v, nullptr, d_out, nullptr, s);
+}
+
+mrstat_status mrstat_jhw(mrstat_ctx ctx, const float* d_theta, int32_t reuse, const void* d_w,
+                         float* d_out, mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = prepare(ctx, d_theta, reuse, s);
+    if (st != MRSTAT_OK) return st;
+    if (!d_w || !d_out) return fail(ctx, MRSTAT_ERR_ARG, "w or out is NULL");
+    if (!aligned(d_w, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
+    return adjoint(ctx, d_theta, d_w, d_out, s);
+}
+
+mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
+                             const mrstat_gn_opts* o, mrstat_gn_report* rep, mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!d_theta || !d_data || !o || !rep) return fail(ctx, MRSTAT_ERR_ARG, "null argument");
+    if (!aligned(d_data, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
+    if (o->n_cg < 0 || o->n_ls_max < 1 || o->param_mask < 0 || o->param_mask > 31 ||
+        !(o->armijo_c1 >= 0.0 && o->armijo_c1 < 1.0))
+        return fail(ctx, MRSTAT_ERR_ARG, "invalid GN options");
+    for (int q = 0; q < 3; ++q)
+        if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    std::memset(rep, 0, sizeof(*rep));
+    const Dims& d = ctx->d;
+    float* g = ctx->vec(0);
+    float* step = ctx->vec(1);
+    float* res = ctx->vec(2);
+    float* dir = ctx->vec(3);
+    float* q = ctx->vec(4);
+    float* trial = ctx->vec(5);
+    double* sc = ctx->scal();
+
+    // Linearise at theta; r, f, g = Re(J^H r).
+    st = linearise(ctx, d_theta, s);
+    if (st != MRSTAT_OK) return st;
+    st = forward(ctx, 0, 0, ctx->trains(), d_theta, nullptr, d_data, ctx->r(), sc + SC_F0, s);
+    if (st != MRSTAT_OK) return st;
+    st = adjoint(ctx, d_theta, ctx->r(), g, s);
+    if (st != MRSTAT_OK) return st;
+    HIP_TRY(launch_mask_params(d, g, o->param_mask, ctx->mask, s));
+
+    // CG on Re(J^H J) p = -g with device-resident FP64 scalars.
+    HIP_TRY(launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s));
+    for (int it = 0; it < o->n_cg; ++it) {
+        st = forward(ctx, 1, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
+        if (st != MRSTAT_OK) return st;
+        st = adjoint(ctx, d_theta, ctx->y(), q, s);
+        if (st != MRSTAT_OK) return st;
+        HIP_TRY(launch_mask_params(d, q, o->param_mask, ctx->mask, s));
+        HIP_TRY(launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s));
+    }
+    double hs[16];
+    HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double f0 = 0.5 * hs[SC_F0];
+    rep->f0 = f0;
+    rep->f1 = f0;
+    rep->gnorm = std::sqrt(hs[SC_G2]);
+    rep->cg_iters = (int32_t)hs[SC_ITERS];
+    if (!std::isfinite(f0) || !std::isfinite(rep->gnorm))
+        return fail(ctx, MRSTAT_ERR_NONFINITE, "objective or gradient is not finite");
+
+    // Backtracking line search on the projected step.
+    float t = 1.f;
+    for (int k = 0; k < o->n_ls_max; ++k) {
+        HIP_TRY(launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi, o->param_mask, ctx->mask,
+                                       trial, s));
+        HIP_TRY(launch_epg(d, ctx->st, trial, ctx->dseq(), ctx->trial_m(), false, ctx->epg_lanes, s));
+        st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
+        if (st != MRSTAT_OK) return st;
+        HIP_TRY(launch_pred_dot(d, g, trial, d_theta, ctx->red(), sc + SC_PRED, s));
+        double h3[16];
+        HIP_TRY(hipMemcpyAsync(h3, sc, sizeof(h3), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double ft = 0.5 * h3[SC_FT], pred = h3[SC_PRED];
+        rep->ls_trials++;
+        if (std::isfinite(ft) && ft <= f0 + o->armijo_c1 * pred) {
+            HIP_TRY(hipMemcpyAsync(d_theta, trial, (size_t)5 * d.nv * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            rep->accepted = 1;
+            rep->f1 = ft;
+            rep->t = t;
+            rep->step_norm = std::sqrt(h3[SC_SN]);
+            ctx->lin_valid = false;
+            break;
+        }
+        t *= 0.5f;
+    }
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data, int32_t n_iter,
+                              mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!d_theta || !d_data) return fail(ctx, MRSTAT_ERR_ARG, "null argument");
+    if (n_iter < 0) return fail(ctx, MRSTAT_ERR_ARG, "n_iter must be >= 0");
+    const Dims& d = ctx->d;
+    const size_t ndata = (size_t)d.C * d.T * d.nk;
+    float2* x = ctx->at<float2>(ctx->L.cx);
+    float2* sv = ctx->at<float2>(ctx->L.csv);
+    float2* p = ctx->at<float2>(ctx->L.cp);
+    float* th = ctx->at<float>(ctx->L.cth);
+    float2* res = ctx->r();
+    float2* qv = ctx->y();
+    double* sc = ctx->scal();
+
+    st = linearise(ctx, d_theta, s);
+    if (st != MRSTAT_OK) return st;
+    // M^H w for the rho-linear map: adjoint y-stage on the m train only.
+    auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
+        HIP_TRY(launch_xgemm_adj(d, ctx->enc, w, ctx->dextab(), ctx->W(), s));
+        HIP_TRY(launch_ystage_adj(d, ctx->trains(), 1, ctx->coil, ctx->mask, ctx->deytab(), ctx->W(),
+                                  ctx->apart(), ctx->L.adj_per_chunk, s));
+        HIP_TRY(launch_rho_adj_finish(d, ctx->apart(), ctx->L.adj_chunks, ctx->mask, out, s));
+        return MRSTAT_OK;
+    };
+    HIP_TRY(hipMemsetAsync(x, 0, d.nv * sizeof(float2), s));
+    HIP_TRY(hipMemcpyAsync(res, d_data, ndata * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    if ((st = adj_rho(res, sv)) != MRSTAT_OK) return st;
+    HIP_TRY(hipMemcpyAsync(p, sv, d.nv * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_dot_c(sv, sv, d.nv, ctx->red(), sc + SC_STAGE, s));
+    HIP_TRY(launch_cgls_scalars(sc, 0, s));
+    for (int it = 0; it < n_iter; ++it) {
+        HIP_TRY(launch_set_rho(d, d_theta, p, th, s));
+        if ((st = forward(ctx, 0, 2, ctx->trains(), th, nullptr, nullptr, qv, nullptr, s)) != MRSTAT_OK)
+            return st;
+        HIP_TRY(launch_dot_c(qv, qv, ndata, ctx->red(), sc + SC_STAGE, s));
+        HIP_TRY(launch_cgls_scalars(sc, 1, s));
+        HIP_TRY(launch_cgls_step_x(d, x, p, sc, s));
+        HIP_TRY(launch_cgls_step_r(ndata, res, qv, sc, s));
+        if ((st = adj_rho(res, sv)) != MRSTAT_OK) return st;
+        HIP_TRY(launch_dot_c(sv, sv, d.nv, ctx->red(), sc + SC_STAGE, s));
+        HIP_TRY(launch_cgls_scalars(sc, 2, s));
+        HIP_TRY(launch_cgls_dir(d, p, sv, sc, s));
+    }
+    HIP_TRY(launch_copy_rho_out(d, x, d_theta, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRSTAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the HIP translation units of libmrstat.
+// Not part of the public ABI (include/mrstat.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mrstat {
+
+// Problem sizes as the kernels see them.
+struct Dims {
+    int nx, ny, nv;   // grid, nv = nx*ny (voxel j = iy*nx + ix)
+    int T;            // TRs
+    int nk;           // readout samples
+    int K;            // EPG states
+    int C;            // coils
+};
+
+// Per-voxel EPG timing constants shared by all voxels.
+struct SeqTimes {
+    float tr, te, tinv;
+};
+
+// Column tiling of the y-stage kernels: 64 lanes along ix, waves stacked
+// along iy; each wave owns YROWS consecutive rows.
+constexpr int YLANES = 64;
+constexpr int YWAVES = 4;
+constexpr int YROWS = 8;
+constexpr int YBLOCK = YWAVES * YROWS;   // rows per iy block (partial sum)
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return the launch status.
+
+// EPG linearisation. theta [5][nv]; seq[n] = (flip angle [rad], RF sign +-1);
+// out: tangents ? [4][T][nv] : [T][nv] (imaginary parts of m, dm/dlnT1,
+// dm/dlnT2, dm/dB1). lanes = lanes per voxel (0 = automatic).
+hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
+                      float* out, bool tangents, int lanes, hipStream_t s);
+
+// Forward y-stage: upart[b][c][n][ix] = sum over rows iy of block b of
+// Ey[n][iy] * coil_c[j] * x[n][j], with x = i rho m (mode 0) or
+// x = i (rho sum_q v_q dm_q + (v3 + i v4) m) (mode 1, the J v direction).
+hipError_t launch_ystage_fwd(const Dims& d, int mode, const float* trains, const float* theta,
+                             const float* v, const float2* coil, const uint8_t* mask,
+                             const float2* eytab, float2* upart, int n_chunk, hipStream_t s);
+
+// x-stage forward GEMM: s[c][n][k] = sum_ix Ex[k][ix] U[c][n][ix], U the sum of
+// the nby partials. mode 0: out = data - s and per-block FP64 sums of |out|^2
+// into red; mode 1: out = -s.
+hipError_t launch_xgemm_fwd(const Dims& d, int enc, int mode, const float2* upart, int nby,
+                            const float2* extab, const float2* data, float2* out, double* red,
+                            int* nred, hipStream_t s);
+
+// x-stage adjoint GEMM: W[c][n][ix] = sum_k conj(Ex[k][ix]) w[c][n][k].
+hipError_t launch_xgemm_adj(const Dims& d, int enc, const float2* w, const float2* extab,
+                            float2* W, hipStream_t s);
+
+// Adjoint y-stage: partial sums over TR chunks of
+// A_p[j] = sum_n mu_p[n][j] conj(Ey[n][iy]) sum_c conj(coil_c[j]) W_c[n][ix]
+// (p = 0..3 for m and the three tangents; ntr_trains = 4 or 1).
+hipError_t launch_ystage_adj(const Dims& d, const float* trains, int ntr_trains,
+                             const float2* coil, const uint8_t* mask, const float2* eytab,
+                             const float2* W, float* apart, int n_chunk, hipStream_t s);
+
+// g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order).
+hipError_t launch_jhw_finish(const Dims& d, const float* apart, int n_chunk, const float* theta,
+                             const uint8_t* mask, float* g, hipStream_t s);
+
+// CGLS helpers on complex per-voxel vectors: A^H w = -i A_0 from the partials.
+hipError_t launch_rho_adj_finish(const Dims& d, const float* apart, int n_chunk,
+                                 const uint8_t* mask, float2* out, hipStream_t s);
+
+// ---------------------------------------------------------------- reductions
+// Deterministic FP64 reductions: per-block partials then one block.
+constexpr int RED_BLOCKS = 512;
+hipError_t launch_sum_partials(const double* partials, int n, double* out, hipStream_t s);
+hipError_t launch_dot(const float* a, const float* b, size_t n, double* partials, double* out,
+                      hipStream_t s);
+hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* partials,
+                        double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- CG / line search
+// Device-resident scalar block (doubles); slot numbers shared with vec.hip.
+constexpr int SCAL_DOUBLES = 64;
+enum : int {
+    SC_RR = 0, SC_ITERS = 6, SC_F0 = 8, SC_G2 = 9, SC_PRED = 10, SC_SN = 11, SC_FT = 14,
+    SC_STAGE = 30, SC_CDONE = 25
+};
+
+hipError_t launch_mask_params(const Dims& d, float* x, int param_mask, const uint8_t* mask,
+                              hipStream_t s);
+hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
+                          double* scal, double* partials, hipStream_t s);
+hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
+                            double* scal, double* partials, hipStream_t s);
+hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float* step, float t,
+                                  const float* lo, const float* hi, int param_mask,
+                                  const uint8_t* mask, float* trial, hipStream_t s);
+hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, const float* theta,
+                           double* partials, double* out, hipStream_t s);
+
+// CGLS (complex unknown per voxel).
+hipError_t launch_set_rho(const Dims& d, const float* theta_in, const float2* p, float* theta_out,
+                          hipStream_t s);
+hipError_t launch_cgls_step_x(const Dims& d, float2* x, float2* p, const double* scal,
+                              hipStream_t s);
+hipError_t launch_cgls_step_r(size_t n, float2* r, const float2* q, const double* scal,
+                              hipStream_t s);
+hipError_t launch_cgls_dir(const Dims& d, float2* p, const float2* sv, const double* scal,
+                           hipStream_t s);
+hipError_t launch_cgls_scalars(double* scal, int phase, hipStream_t s);
+hipError_t launch_copy_rho_out(const Dims& d, const float2* x, float* theta, hipStream_t s);
+
+}  // namespace mrstat

@@ -1,0 +1,455 @@
+// Parameter-space vector kernels of the inexact Gauss-Newton driver:
+// deterministic FP64 reductions (fixed grid, fixed order), the CG recurrences
+// on Re(J^H J) p = -g (eq. 4) with every scalar kept in device memory, the
+// projected line-search trial, and the CGLS recurrences of the proton-density
+// initialisation. Vectors are FP32 [5][Nv]; dots, norms, alpha and beta FP64.
+#include "mrstat_internal.h"
+
+namespace mrstat {
+
+// Scalar slots (double) in the device scalar block.
+enum : int {
+    S_RR = 0, S_KAPPA = 1, S_ALPHA = 2, S_RRNEW = 3, S_BETA = 4, S_DONE = 5, S_ITERS = 6,
+    S_DD = 7, S_F0 = 8, S_G2 = 9, S_PRED = 10, S_FT = 11, S_UPD = 12,
+    S_GAMMA = 20, S_QQ = 21, S_CA = 22, S_GNEW = 23, S_CB = 24, S_CDONE = 25, S_STAGE = 30
+};
+
+namespace {
+
+constexpr int RB = 256;   // threads per reduction block
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+__global__ __launch_bounds__(RB) void sum_partials_kernel(const double* __restrict__ p, int n,
+                                                          double* __restrict__ out)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) v += p[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) *out = v;
+}
+
+__global__ __launch_bounds__(RB) void dot_kernel(const float* __restrict__ a,
+                                                 const float* __restrict__ b, size_t n,
+                                                 double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB)
+        v += (double)a[i] * (double)b[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// Re sum conj(a) b over complex vectors (= sum a.x b.x + a.y b.y).
+__global__ __launch_bounds__(RB) void dot_c_kernel(const float2* __restrict__ a,
+                                                   const float2* __restrict__ b, size_t n,
+                                                   double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        const float2 x = a[i], y = b[i];
+        v += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void mask_params_kernel(float* __restrict__ x, int nv, int param_mask,
+                                   const uint8_t* __restrict__ mask)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)5 * nv) return;
+    const int q = (int)(i / nv), j = (int)(i % nv);
+    const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
+    if (!on) x[i] = 0.f;
+}
+
+// step = 0, res = -g, dir = res; partial sums of res.res.
+__global__ __launch_bounds__(RB) void cg_init_kernel(const float* __restrict__ g,
+                                                     float* __restrict__ step,
+                                                     float* __restrict__ res,
+                                                     float* __restrict__ dir, size_t n,
+                                                     double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        const float r = -g[i];
+        step[i] = 0.f;
+        res[i] = r;
+        dir[i] = r;
+        v += (double)r * (double)r;
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// Finish of the init: rr, |g|^2 (= rr), clear the flags.
+__global__ __launch_bounds__(RB) void cg_init_finish(const double* __restrict__ part, int n,
+                                                     double* __restrict__ sc)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) v += part[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        sc[S_RR] = v;
+        sc[S_G2] = v;
+        sc[S_DONE] = (v == 0.0) ? 1.0 : 0.0;
+        sc[S_ITERS] = 0.0;
+        sc[S_ALPHA] = 0.0;
+        sc[S_BETA] = 0.0;
+        sc[S_UPD] = 0.0;
+    }
+}
+
+// Partial sums of dir.q and dir.dir.
+__global__ __launch_bounds__(RB) void cg_curv_kernel(const float* __restrict__ dir,
+                                                     const float* __restrict__ q, size_t n,
+                                                     double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    double a = 0.0, b = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        const double d = dir[i];
+        a += d * (double)q[i];
+        b += d * d;
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// kappa = dir.q; stop on non-positive curvature; alpha = rr / kappa. UPD marks
+// an iteration that updates step, res and dir (CG not stopped before it).
+__global__ __launch_bounds__(RB) void cg_alpha_kernel(const double* __restrict__ part, int n,
+                                                      double* __restrict__ sc)
+{
+    __shared__ double sh[RB / 64];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) {
+        a += part[i];
+        b += part[n + i];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        sc[S_KAPPA] = a;
+        sc[S_DD] = b;
+        if (sc[S_DONE] == 0.0 && a <= 1e-30 * b) sc[S_DONE] = 1.0;
+        sc[S_UPD] = (sc[S_DONE] == 0.0) ? 1.0 : 0.0;
+        sc[S_ALPHA] = (sc[S_DONE] == 0.0) ? sc[S_RR] / a : 0.0;
+    }
+}
+
+// step += alpha dir, res -= alpha q; partial sums of res.res.
+__global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ dir,
+                                                     const float* __restrict__ q,
+                                                     float* __restrict__ step,
+                                                     float* __restrict__ res, size_t n,
+                                                     const double* __restrict__ sc,
+                                                     double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    const bool done = sc[S_UPD] == 0.0;
+    const float al = (float)sc[S_ALPHA];
+    double v = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        float r = res[i];
+        if (!done) {
+            step[i] = fmaf(al, dir[i], step[i]);
+            r = fmaf(-al, q[i], r);
+            res[i] = r;
+        }
+        v += (double)r * (double)r;
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// beta = rr_new / rr, rr = rr_new, count the iteration; a zero residual stops
+// CG before the next iteration.
+__global__ __launch_bounds__(RB) void cg_beta_kernel(const double* __restrict__ part, int n,
+                                                     double* __restrict__ sc)
+{
+    __shared__ double sh[RB / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) v += part[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0 && sc[S_UPD] != 0.0) {
+        sc[S_RRNEW] = v;
+        sc[S_BETA] = v / sc[S_RR];
+        sc[S_RR] = v;
+        sc[S_ITERS] += 1.0;
+        if (v == 0.0) sc[S_DONE] = 1.0;
+    }
+}
+
+__global__ void cg_dir_kernel(const float* __restrict__ res, float* __restrict__ dir, size_t n,
+                              const double* __restrict__ sc)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (sc[S_UPD] == 0.0) return;
+    dir[i] = fmaf((float)sc[S_BETA], dir[i], res[i]);
+}
+
+// trial = P(theta + t step): active ln T1, ln T2, B1 clamped to the box.
+__global__ void ls_trial_kernel(const float* __restrict__ theta, const float* __restrict__ step,
+                                float t, float lo0, float lo1, float lo2, float hi0, float hi1,
+                                float hi2, int param_mask, const uint8_t* __restrict__ mask,
+                                float* __restrict__ trial, int nv)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)5 * nv) return;
+    const int q = (int)(i / nv), j = (int)(i % nv);
+    float x = fmaf(t, step[i], theta[i]);
+    const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
+    if (q < 3 && on) {
+        const float lo = q == 0 ? lo0 : (q == 1 ? lo1 : lo2);
+        const float hi = q == 0 ? hi0 : (q == 1 ? hi1 : hi2);
+        x = fminf(fmaxf(x, lo), hi);
+    }
+    trial[i] = on ? x : theta[i];
+}
+
+// Partial sums of g . (trial - theta) and |trial - theta|^2.
+__global__ __launch_bounds__(RB) void pred_kernel(const float* __restrict__ g,
+                                                  const float* __restrict__ trial,
+                                                  const float* __restrict__ theta, size_t n,
+                                                  double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    double a = 0.0, b = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        const double d = (double)trial[i] - (double)theta[i];
+        a += (double)g[i] * d;
+        b += d * d;
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(RB) void sum2_kernel(const double* __restrict__ part, int n,
+                                                  double* __restrict__ out)
+{
+    __shared__ double sh[RB / 64];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) {
+        a += part[i];
+        b += part[n + i];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+// ------------------------------------------------------------------ CGLS
+__global__ void set_rho_kernel(const float* __restrict__ th, const float2* __restrict__ p,
+                               float* __restrict__ out, int nv)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)5 * nv) return;
+    const int q = (int)(i / nv), j = (int)(i % nv);
+    out[i] = q < 3 ? th[i] : (q == 3 ? p[j].x : p[j].y);
+}
+
+// x += a p (complex per voxel), a = gamma / qq; stop when qq == 0.
+__global__ void cgls_x_kernel(float2* __restrict__ x, const float2* __restrict__ p, int nv,
+                              const double* __restrict__ sc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv || sc[S_CDONE] != 0.0) return;
+    const float a = (float)sc[S_CA];
+    x[j] = make_float2(fmaf(a, p[j].x, x[j].x), fmaf(a, p[j].y, x[j].y));
+}
+
+__global__ void cgls_r_kernel(float2* __restrict__ r, const float2* __restrict__ q, size_t n,
+                              const double* __restrict__ sc)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || sc[S_CDONE] != 0.0) return;
+    const float a = (float)sc[S_CA];
+    r[i] = make_float2(fmaf(-a, q[i].x, r[i].x), fmaf(-a, q[i].y, r[i].y));
+}
+
+__global__ void cgls_p_kernel(float2* __restrict__ p, const float2* __restrict__ s, int nv,
+                              const double* __restrict__ sc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv || sc[S_CDONE] != 0.0) return;
+    const float b = (float)sc[S_CB];
+    p[j] = make_float2(fmaf(b, p[j].x, s[j].x), fmaf(b, p[j].y, s[j].y));
+}
+
+// phase 0: gamma = dot (init); 1: qq = dot, a = gamma/qq; 2: gnew = dot, b.
+__global__ void cgls_scalar_kernel(double* __restrict__ sc, int phase)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double v = sc[S_STAGE];   // reduction result staged by the host-side sequence
+    if (phase == 0) {
+        sc[S_GAMMA] = v;
+        sc[S_CDONE] = (v == 0.0) ? 1.0 : 0.0;
+    } else if (phase == 1) {
+        if (sc[S_CDONE] != 0.0) return;
+        sc[S_QQ] = v;
+        if (v == 0.0) {
+            sc[S_CDONE] = 1.0;
+            sc[S_CA] = 0.0;
+        } else {
+            sc[S_CA] = sc[S_GAMMA] / v;
+        }
+    } else {
+        if (sc[S_CDONE] != 0.0) return;
+        sc[S_GNEW] = v;
+        sc[S_CB] = v / sc[S_GAMMA];
+        sc[S_GAMMA] = v;
+        if (v == 0.0) sc[S_CDONE] = 1.0;
+    }
+}
+
+__global__ void copy_rho_out_kernel(const float2* __restrict__ x, float* __restrict__ th, int nv)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    th[3 * (size_t)nv + j] = x[j].x;
+    th[4 * (size_t)nv + j] = x[j].y;
+}
+
+inline int grid_for(size_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_sum_partials(const double* partials, int n, double* out, hipStream_t s)
+{
+    sum_partials_kernel<<<1, RB, 0, s>>>(partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, size_t n, double* partials, double* out,
+                      hipStream_t s)
+{
+    dot_kernel<<<RED_BLOCKS, RB, 0, s>>>(a, b, n, partials);
+    sum_partials_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* partials,
+                        double* out, hipStream_t s)
+{
+    dot_c_kernel<<<RED_BLOCKS, RB, 0, s>>>(a, b, n, partials);
+    sum_partials_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_params(const Dims& d, float* x, int param_mask, const uint8_t* mask,
+                              hipStream_t s)
+{
+    mask_params_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(x, d.nv, param_mask, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
+                          double* scal, double* partials, hipStream_t s)
+{
+    const size_t n = (size_t)5 * d.nv;
+    cg_init_kernel<<<RED_BLOCKS, RB, 0, s>>>(g, step, res, dir, n, partials);
+    cg_init_finish<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
+                            double* scal, double* partials, hipStream_t s)
+{
+    const size_t n = (size_t)5 * d.nv;
+    cg_curv_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, n, partials);
+    cg_alpha_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
+    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, scal, partials);
+    cg_beta_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
+    cg_dir_kernel<<<grid_for(n), 256, 0, s>>>(res, dir, n, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float* step, float t,
+                                  const float* lo, const float* hi, int param_mask,
+                                  const uint8_t* mask, float* trial, hipStream_t s)
+{
+    ls_trial_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(
+        theta, step, t, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], param_mask, mask, trial, d.nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, const float* theta,
+                           double* partials, double* out, hipStream_t s)
+{
+    const size_t n = (size_t)5 * d.nv;
+    pred_kernel<<<RED_BLOCKS, RB, 0, s>>>(g, trial, theta, n, partials);
+    sum2_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_rho(const Dims& d, const float* theta_in, const float2* p, float* theta_out,
+                          hipStream_t s)
+{
+    set_rho_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(theta_in, p, theta_out, d.nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_step_x(const Dims& d, float2* x, float2* p, const double* scal,
+                              hipStream_t s)
+{
+    cgls_x_kernel<<<grid_for(d.nv), 256, 0, s>>>(x, p, d.nv, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_step_r(size_t n, float2* r, const float2* q, const double* scal,
+                              hipStream_t s)
+{
+    cgls_r_kernel<<<grid_for(n), 256, 0, s>>>(r, q, n, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_dir(const Dims& d, float2* p, const float2* sv, const double* scal,
+                           hipStream_t s)
+{
+    cgls_p_kernel<<<grid_for(d.nv), 256, 0, s>>>(p, sv, d.nv, scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_scalars(double* scal, int phase, hipStream_t s)
+{
+    cgls_scalar_kernel<<<1, 64, 0, s>>>(scal, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rho_out(const Dims& d, const float2* x, float* theta, hipStream_t s)
+{
+    copy_rho_out_kernel<<<grid_for(d.nv), 256, 0, s>>>(x, theta, d.nv);
+    return hipGetLastError();
+}
+
+}  // namespace mrstat

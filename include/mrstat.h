@@ -193,6 +193,28 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float *d_theta, const void *d_data,
 mrstat_status mrstat_rho_init(mrstat_ctx ctx, float *d_theta, const void *d_data, int32_t n_iter,
                               mrstat_stream stream);
 
+/* Kernel tracing. While enabled, every kernel the context launches is
+ * bracketed by HIP events on its stream. mrstat_profile_read synchronises the
+ * recorded events and returns, per kernel kind, the number of launches and
+ * their summed device time in milliseconds since profiling was (re-)enabled.
+ * Enabling or disabling resets the counters. Host memory only; the events are
+ * created on first use and kept by the context. */
+typedef enum {
+    MRSTAT_K_EPG = 0,        /* EPG with tangents (linearisation) */
+    MRSTAT_K_EPG_VALUE = 1,  /* EPG value only (line-search trials) */
+    MRSTAT_K_YFWD_SIG = 2,   /* forward y-stage of the signal (m train only) */
+    MRSTAT_K_YFWD_JV = 3,    /* forward y-stage of J v (all four trains) */
+    MRSTAT_K_XFWD = 4,       /* forward x-stage GEMM (+ residual epilogue) */
+    MRSTAT_K_XADJ = 5,       /* adjoint x-stage GEMM */
+    MRSTAT_K_YADJ = 6,       /* adjoint y-stage (train streaming) */
+    MRSTAT_K_FINISH = 7,     /* gradient assembly from the adjoint partials */
+    MRSTAT_K_VECTOR = 8,     /* CG / line-search / CGLS vector kernels and reductions */
+    MRSTAT_K_COUNT = 9
+} mrstat_kernel_kind;
+
+mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on);
+mrstat_status mrstat_profile_read(mrstat_ctx ctx, int32_t *h_counts, double *h_ms);
+
 #ifdef __cplusplus
 }
 #endif

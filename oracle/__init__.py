@@ -91,6 +91,8 @@ def lib():
         L.oracle_residual.restype = C.c_double
         L.oracle_gn_step.argtypes = [P(_Problem), vp, vp, vp, vp, P(_GnOpts), P(_GnReport)]
         L.oracle_phases.argtypes = [P(_Problem), C.c_int, vp]
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = C.c_int
         L.oracle_rho_init.argtypes = [P(_Problem), vp, vp, vp, vp, C.c_int]
         _lib = L
     return _lib
@@ -145,6 +147,10 @@ def _mask(b, mask):
 
 def _dshape(prob):
     return (prob.n_coils, prob.n_tr, prob.n_read)
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())
 
 
 def phases(prob, n):

@@ -57,6 +57,8 @@ typedef struct {
     int cg_iters, ls_trials, accepted;
 } oracle_gn_report;
 
+int oracle_num_threads(void);
+
 /* EPG simulation with forward-mode tangents (Supporting Information S2
  * pattern, applied to the extended-phase-graph states).
  * theta: [5][Nv]; trains out: [4][n_tr][Nv] complex = m, dm/dlnT1, dm/dlnT2,

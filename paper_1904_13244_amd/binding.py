@@ -77,6 +77,8 @@ def lib():
             "mrstat_jhw": ([vp, vp, i32, vp, vp, vp], C.c_int),
             "mrstat_gn_step": ([vp, vp, vp, P(GnOpts), P(GnReport), vp], C.c_int),
             "mrstat_rho_init": ([vp, vp, vp, i32, vp], C.c_int),
+            "mrstat_profile_enable": ([vp, i32], C.c_int),
+            "mrstat_profile_read": ([vp, P(i32), P(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -89,7 +91,8 @@ def lib():
 def exported_symbols():
     return ["mrstat_create", "mrstat_destroy", "mrstat_last_error", "mrstat_workspace_bytes",
             "mrstat_bind", "mrstat_set_encoding", "mrstat_set_epg_lanes", "mrstat_simulate", "mrstat_residual", "mrstat_jv",
-            "mrstat_jhw", "mrstat_gn_step", "mrstat_rho_init"]
+            "mrstat_jhw", "mrstat_gn_step", "mrstat_rho_init", "mrstat_profile_enable",
+            "mrstat_profile_read"]
 
 
 def _check(status, ctx=None):
@@ -164,6 +167,23 @@ def mrstat_rho_init(ctx, theta_ptr, data_ptr, n_iter, stream):
     _check(lib().mrstat_rho_init(ctx, theta_ptr, data_ptr, int(n_iter), stream), ctx)
 
 
+KERNEL_KINDS = ["epg", "epg_value", "ystage_fwd_signal", "ystage_fwd_jv", "xgemm_fwd",
+                "xgemm_adj", "ystage_adj", "jhw_finish", "vector"]
+
+
+def mrstat_profile_enable(ctx, on):
+    _check(lib().mrstat_profile_enable(ctx, 1 if on else 0), ctx)
+
+
+def mrstat_profile_read(ctx):
+    """{kind: (launches, total ms)} since profiling was enabled."""
+    n = len(KERNEL_KINDS)
+    counts = (C.c_int32 * n)()
+    ms = (C.c_double * n)()
+    _check(lib().mrstat_profile_read(ctx, counts, ms), ctx)
+    return {k: (int(counts[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
 # --------------------------------------------------------------- torch helper
 @dataclass
 class Context:
@@ -227,6 +247,12 @@ class Context:
     # -- calls
     def set_encoding(self, enc):
         mrstat_set_encoding(self.h, enc)
+
+    def profile(self, on=True):
+        mrstat_profile_enable(self.h, on)
+
+    def profile_read(self):
+        return mrstat_profile_read(self.h)
 
     def set_epg_lanes(self, lanes):
         mrstat_set_epg_lanes(self.h, lanes)

@@ -45,6 +45,12 @@ struct mrstat_ctx_s {
     bool bound = false;
     bool lin_valid = false;
     std::string err;
+    // kernel tracing
+    struct Rec { int kind; hipEvent_t a, b; };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<Rec> recs;
 
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -82,6 +88,37 @@ mrstat_status fail(mrstat_ctx c, mrstat_status st, const std::string& msg)
         if (e_ != hipSuccess)                                                            \
             return fail(ctx, MRSTAT_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
+
+hipError_t next_event(mrstat_ctx ctx, hipEvent_t* e)
+{
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t ne;
+        hipError_t st = hipEventCreate(&ne);
+        if (st != hipSuccess) return st;
+        ctx->ev_pool.push_back(ne);
+    }
+    *e = ctx->ev_pool[ctx->ev_used++];
+    return hipSuccess;
+}
+
+// Runs one launcher, bracketed by events when tracing is on.
+template <class F>
+hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
+{
+    if (!ctx->prof_on) return launch();
+    mrstat_ctx_s::Rec r{kind, nullptr, nullptr};
+    hipError_t st = next_event(ctx, &r.a);
+    if (st == hipSuccess) st = next_event(ctx, &r.b);
+    if (st == hipSuccess) st = hipEventRecord(r.a, s);
+    if (st != hipSuccess) return st;
+    st = launch();
+    if (st != hipSuccess) return st;
+    st = hipEventRecord(r.b, s);
+    if (st == hipSuccess) ctx->recs.push_back(r);
+    return st;
+}
+
+#define TRACED(kind, call) traced(ctx, (kind), s, [&]() { return (call); })
 
 Layout make_layout(const Dims& d)
 {
@@ -161,7 +198,8 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // ----------------------------------------------------------- kernel sequences
 mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s)
 {
-    HIP_TRY(launch_epg(ctx->d, ctx->st, theta, ctx->dseq(), ctx->trains(), true, ctx->epg_lanes, s));
+    HIP_TRY(TRACED(MRSTAT_K_EPG, launch_epg(ctx->d, ctx->st, theta, ctx->dseq(), ctx->trains(), true,
+                                            ctx->epg_lanes, s)));
     ctx->lin_valid = true;
     return MRSTAT_OK;
 }
@@ -173,22 +211,26 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const float* train
                       double* f_out, hipStream_t s)
 {
     const Dims& d = ctx->d;
-    HIP_TRY(launch_ystage_fwd(d, mode_y, trains, theta, v, ctx->coil, ctx->mask, ctx->deytab(),
-                              ctx->upart(), kFwdTrPerBlock, s));
+    HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV, launch_ystage_fwd(d, mode_y, trains, theta, v, ctx->coil, ctx->mask,
+                                                    ctx->deytab(), ctx->upart(), kFwdTrPerBlock, s)));
     int nred = 0;
-    HIP_TRY(launch_xgemm_fwd(d, ctx->enc, mode_x, ctx->upart(), ctx->L.nby, ctx->dextab(),
-                             (const float2*)data, (float2*)out, ctx->red(), &nred, s));
-    if (mode_x == 0 && f_out) HIP_TRY(launch_sum_partials(ctx->red(), nred, f_out, s));
+    HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, ctx->enc, mode_x, ctx->upart(), ctx->L.nby,
+                                                   ctx->dextab(), (const float2*)data, (float2*)out,
+                                                   ctx->red(), &nred, s)));
+    if (mode_x == 0 && f_out)
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_sum_partials(ctx->red(), nred, f_out, s)));
     return MRSTAT_OK;
 }
 
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, hipStream_t s)
 {
     const Dims& d = ctx->d;
-    HIP_TRY(launch_xgemm_adj(d, ctx->enc, (const float2*)w, ctx->dextab(), ctx->W(), s));
-    HIP_TRY(launch_ystage_adj(d, ctx->trains(), 4, ctx->coil, ctx->mask, ctx->deytab(), ctx->W(),
-                              ctx->apart(), ctx->L.adj_per_chunk, s));
-    HIP_TRY(launch_jhw_finish(d, ctx->apart(), ctx->L.adj_chunks, theta, ctx->mask, g, s));
+    HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, ctx->enc, (const float2*)w, ctx->dextab(), ctx->W(), s)));
+    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, ctx->trains(), 4, ctx->coil, ctx->mask,
+                                                    ctx->deytab(), ctx->W(), ctx->apart(),
+                                                    ctx->L.adj_per_chunk, s)));
+    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, ctx->apart(), ctx->L.adj_chunks, theta,
+                                                      ctx->mask, g, s)));
     return MRSTAT_OK;
 }
 
@@ -236,7 +278,38 @@ mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
     return MRSTAT_OK;
 }
 
-void mrstat_destroy(mrstat_ctx ctx) { delete ctx; }
+void mrstat_destroy(mrstat_ctx ctx)
+{
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    ctx->prof_on = on != 0;
+    ctx->recs.clear();
+    ctx->ev_used = 0;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_profile_read(mrstat_ctx ctx, int32_t* h_counts, double* h_ms)
+{
+    if (!ctx || !h_counts || !h_ms) return MRSTAT_ERR_ARG;
+    for (int k = 0; k < MRSTAT_K_COUNT; ++k) {
+        h_counts[k] = 0;
+        h_ms[k] = 0.0;
+    }
+    for (const auto& r : ctx->recs) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        h_counts[r.kind] += 1;
+        h_ms[r.kind] += ms;
+    }
+    return MRSTAT_OK;
+}
 
 const char* mrstat_last_error(mrstat_ctx ctx)
 {
@@ -387,17 +460,17 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     if (st != MRSTAT_OK) return st;
     st = adjoint(ctx, d_theta, ctx->r(), g, s);
     if (st != MRSTAT_OK) return st;
-    HIP_TRY(launch_mask_params(d, g, o->param_mask, ctx->mask, s));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_mask_params(d, g, o->param_mask, ctx->mask, s)));
 
     // CG on Re(J^H J) p = -g with device-resident FP64 scalars.
-    HIP_TRY(launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s)));
     for (int it = 0; it < o->n_cg; ++it) {
         st = forward(ctx, 1, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
         if (st != MRSTAT_OK) return st;
         st = adjoint(ctx, d_theta, ctx->y(), q, s);
         if (st != MRSTAT_OK) return st;
-        HIP_TRY(launch_mask_params(d, q, o->param_mask, ctx->mask, s));
-        HIP_TRY(launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_mask_params(d, q, o->param_mask, ctx->mask, s)));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s)));
     }
     double hs[16];
     HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -413,12 +486,13 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     // Backtracking line search on the projected step.
     float t = 1.f;
     for (int k = 0; k < o->n_ls_max; ++k) {
-        HIP_TRY(launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi, o->param_mask, ctx->mask,
-                                       trial, s));
-        HIP_TRY(launch_epg(d, ctx->st, trial, ctx->dseq(), ctx->trial_m(), false, ctx->epg_lanes, s));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi,
+                                                               o->param_mask, ctx->mask, trial, s)));
+        HIP_TRY(TRACED(MRSTAT_K_EPG_VALUE, launch_epg(d, ctx->st, trial, ctx->dseq(), ctx->trial_m(),
+                                                      false, ctx->epg_lanes, s)));
         st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
         if (st != MRSTAT_OK) return st;
-        HIP_TRY(launch_pred_dot(d, g, trial, d_theta, ctx->red(), sc + SC_PRED, s));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_pred_dot(d, g, trial, d_theta, ctx->red(), sc + SC_PRED, s)));
         double h3[16];
         HIP_TRY(hipMemcpyAsync(h3, sc, sizeof(h3), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));

@@ -16,13 +16,12 @@ using namespace mrstat;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kAdjChunks = 8;        // TR chunks of the adjoint y-stage (partials)
-constexpr int kFwdTrPerBlock = 16;   // TRs per block of the forward y-stage
 
 struct Layout {
     size_t trains, trial_m, upart, W, apart, r, y, vec, red, scal, seq, eytab, extab;
     size_t cx, csv, cp, cth, total;
-    int nby, n_red, adj_per_chunk, adj_chunks;
+    int n_red;
+    YPlan yp;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -123,10 +122,7 @@ hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
 Layout make_layout(const Dims& d)
 {
     Layout L{};
-    L.nby = ceil_div(d.ny, YBLOCK);
-    L.adj_chunks = std::min(kAdjChunks, d.T);
-    L.adj_per_chunk = ceil_div(d.T, L.adj_chunks);
-    L.adj_chunks = ceil_div(d.T, L.adj_per_chunk);
+    L.yp = make_yplan(d);
     const int M = d.C * d.T;
     const int gemm_blocks = ceil_div(2 * d.nk, 64) * ceil_div(M, 64);
     L.n_red = std::max(2 * RED_BLOCKS, gemm_blocks);
@@ -135,9 +131,9 @@ Layout make_layout(const Dims& d)
     const size_t nv = d.nv, T = d.T;
     L.trains = take(4 * T * nv * sizeof(float));
     L.trial_m = take(T * nv * sizeof(float));
-    L.upart = take((size_t)L.nby * d.C * T * d.nx * sizeof(float2));
-    L.W = take((size_t)d.C * T * d.nx * sizeof(float2));
-    L.apart = take((size_t)L.adj_chunks * 8 * nv * sizeof(float));
+    L.upart = take((size_t)L.yp.nby * d.C * T * d.nx * sizeof(float2));
+    L.W = take((size_t)L.yp.ksplit_adj * d.C * T * d.nx * sizeof(float2));
+    L.apart = take((size_t)L.yp.adj_chunks * 8 * nv * sizeof(float));
     L.r = take((size_t)d.C * T * d.nk * sizeof(float2));
     L.y = take((size_t)d.C * T * d.nk * sizeof(float2));
     L.vec = take(6 * 5 * nv * sizeof(float));
@@ -211,10 +207,12 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const float* train
                       double* f_out, hipStream_t s)
 {
     const Dims& d = ctx->d;
-    HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV, launch_ystage_fwd(d, mode_y, trains, theta, v, ctx->coil, ctx->mask,
-                                                    ctx->deytab(), ctx->upart(), kFwdTrPerBlock, s)));
+    const YPlan& p = ctx->L.yp;
+    HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
+                   launch_ystage_fwd(d, p, mode_y, trains, theta, v, ctx->coil, ctx->mask,
+                                     ctx->deytab(), ctx->upart(), s)));
     int nred = 0;
-    HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, ctx->enc, mode_x, ctx->upart(), ctx->L.nby,
+    HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, p, ctx->enc, mode_x, ctx->upart(),
                                                    ctx->dextab(), (const float2*)data, (float2*)out,
                                                    ctx->red(), &nred, s)));
     if (mode_x == 0 && f_out)
@@ -225,12 +223,12 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const float* train
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, hipStream_t s)
 {
     const Dims& d = ctx->d;
-    HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, ctx->enc, (const float2*)w, ctx->dextab(), ctx->W(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, ctx->trains(), 4, ctx->coil, ctx->mask,
-                                                    ctx->deytab(), ctx->W(), ctx->apart(),
-                                                    ctx->L.adj_per_chunk, s)));
-    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, ctx->apart(), ctx->L.adj_chunks, theta,
-                                                      ctx->mask, g, s)));
+    const YPlan& p = ctx->L.yp;
+    HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
+                                                   ctx->W(), s)));
+    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), 4, ctx->coil, ctx->mask,
+                                                    ctx->deytab(), ctx->W(), ctx->apart(), s)));
+    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, g, s)));
     return MRSTAT_OK;
 }
 
@@ -536,10 +534,11 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     if (st != MRSTAT_OK) return st;
     // M^H w for the rho-linear map: adjoint y-stage on the m train only.
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
-        HIP_TRY(launch_xgemm_adj(d, ctx->enc, w, ctx->dextab(), ctx->W(), s));
-        HIP_TRY(launch_ystage_adj(d, ctx->trains(), 1, ctx->coil, ctx->mask, ctx->deytab(), ctx->W(),
-                                  ctx->apart(), ctx->L.adj_per_chunk, s));
-        HIP_TRY(launch_rho_adj_finish(d, ctx->apart(), ctx->L.adj_chunks, ctx->mask, out, s));
+        const YPlan& p = ctx->L.yp;
+        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->W(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), 1, ctx->coil, ctx->mask,
+                                                        ctx->deytab(), ctx->W(), ctx->apart(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_rho_adj_finish(d, p, ctx->apart(), ctx->mask, out, s)));
         return MRSTAT_OK;
     };
     HIP_TRY(hipMemsetAsync(x, 0, d.nv * sizeof(float2), s));

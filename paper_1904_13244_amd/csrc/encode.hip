@@ -14,6 +14,10 @@
 //   mode 1 (J v dir.): x = sum_q D_q v_q   = i (rho a + nu mu),
 //                      a = v0 mu1 + v1 mu2 + v2 mu3, nu = v3 + i v4
 // (D_q = d(rho m)/d alpha_q, the Jacobian columns of the Theory section).
+//
+// Lane layout of both y-stages: a wave covers 32 consecutive ix (lanes 0-31
+// and 32-63) of two adjacent rows, so nx only needs to be a multiple of 32
+// for full lanes; consecutive lanes read consecutive floats of a train row.
 #include "mrstat_internal.h"
 
 namespace mrstat {
@@ -36,40 +40,62 @@ __device__ __forceinline__ float2 cmulconj(float2 a, float2 b)   // conj(a) * b
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x));
 }
 
-// ------------------------------------------------------------------------
-// Forward y-stage. Block = 4 waves; lane -> ix, wave -> YROWS rows; grid
-// (ix tiles, iy blocks, TR chunks). Each thread keeps its voxels' weights in
-// registers for the whole TR chunk; per TR the 4 waves' column sums are
-// combined through LDS in batches of NB TRs.
-// ------------------------------------------------------------------------
-constexpr int NB = 4;
-constexpr int CMAX = 16;
+__device__ __forceinline__ float2 shfl_xor2(float2 v, int m)
+{
+    return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
 
-template <int MODE, int CC>   // CC = coils known at compile time (1), or 0 = runtime
-__global__ __launch_bounds__(256) void ystage_fwd_kernel(
+// ------------------------------------------------------------------------
+// Forward y-stage. Block = FW = 16 waves; wave w, half h covers row
+// iy = rowbase + 32 r + 2 w + h for r < R, and ix = 32 bx + lane % 32. A block
+// therefore spans 32 R rows (all rows when ny <= 32 R: U is complete and no
+// partial sums are written). Each thread keeps its R voxels' weights (and
+// coil sensitivities) in registers for its TR chunk. Per TR every lane first
+// issues all of its loads (clamped indices, no branches between them), then
+// accumulates; the two rows of a wave are folded with a lane swap and the
+// per-wave sums of the whole chunk are kept in LDS and reduced after a
+// single barrier.
+// ------------------------------------------------------------------------
+constexpr int FW = 16;
+
+template <int MODE, int R, int CC>
+__global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     const float* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
-    const float2* __restrict__ eytab, float2* __restrict__ upart, int nx, int ny, int nv, int T,
-    int C, int n_per_chunk)
+    const float2* __restrict__ eytab, float2* __restrict__ U, int nx, int ny, int nv, int T, int C,
+    int n_per_chunk)
 {
-    extern __shared__ float2 lds[];   // [NB][C][YWAVES][64]
+    // LDS: per-wave sums [TRs per chunk][CC][FW][32], then the block's
+    // y-phases [TRs per chunk][32 R].
+    extern __shared__ float2 lds[];
+    float2* eys = lds + (size_t)n_per_chunk * CC * FW * 32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ix = blockIdx.x * YLANES + lane;
+    const int xl = lane & 31, half = lane >> 5;
+    const int ix = blockIdx.x * 32 + xl;
     const int yb = blockIdx.y;
-    const int iyw = yb * YBLOCK + wave * YROWS;
+    const int iyb = yb * 32 * R + 2 * wave + half;
     const int n0 = blockIdx.z * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
-    const int nc = (CC > 0) ? CC : C;
     const bool colok = ix < nx;
     const size_t plane = (size_t)T * nv;
+    for (int e = threadIdx.x; e < (n1 - n0) * 32 * R; e += blockDim.x) {
+        const int nl = e / (32 * R), rr = e % (32 * R);
+        const int iy = yb * 32 * R + rr;
+        eys[e] = iy < ny ? eytab[(size_t)(n0 + nl) * ny + iy] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
 
-    float2 P[YROWS], Q[YROWS];
-    float v0[YROWS], v1[YROWS], v2[YROWS];
+    float2 P[R], Q[R];
+    float v0[R], v1[R], v2[R];
+    int jr[R], iyr[R];
+    float2 cw[R][CC];
 #pragma unroll
-    for (int r = 0; r < YROWS; ++r) {
-        const int iy = iyw + r;
+    for (int r = 0; r < R; ++r) {
+        const int iy = iyb + 32 * r;
         const bool ok = colok && iy < ny;
-        const int j = ok ? iy * nx + ix : 0;
+        const int j = ok ? iy * nx + ix : 0;   // invalid voxels read voxel 0 with zero weight
+        jr[r] = j;
+        iyr[r] = ok ? iy : 0;
         const bool on = ok && (mask == nullptr || mask[j] != 0);
         const float rr = on ? theta[3 * nv + j] : 0.f, ri = on ? theta[4 * nv + j] : 0.f;
         P[r] = make_float2(-ri, rr);   // i rho
@@ -80,140 +106,206 @@ __global__ __launch_bounds__(256) void ystage_fwd_kernel(
             v1[r] = on ? v[nv + j] : 0.f;
             v2[r] = on ? v[2 * nv + j] : 0.f;
         }
+        if constexpr (CC > 1) {
+#pragma unroll
+            for (int c = 0; c < CC; ++c)
+                cw[r][c] = (ok && c < C) ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
+        }
     }
 
-    for (int nb0 = n0; nb0 < n1; nb0 += NB) {
-        const int nbn = min(NB, n1 - nb0);
-        for (int b = 0; b < nbn; ++b) {
-            const int n = nb0 + b;
-            float2 acc[(CC > 0) ? CC : CMAX];
+    for (int n = n0; n < n1; ++n) {
+        // Loads of this TR for all R voxels.
+        // Uniform row bases (scalar registers) plus 32-bit lane offsets.
+        float mu[R], m1[R], m2[R], m3[R];
+        float2 ey[R];
+        const float* __restrict__ b0 = trains + (size_t)n * nv;
+        const float* __restrict__ b1 = b0 + plane;
+        const float* __restrict__ b2 = b1 + plane;
+        const float* __restrict__ b3 = b2 + plane;
+        const float2* eyrow = eys + (size_t)(n - n0) * 32 * R + 2 * wave + half;
 #pragma unroll
-            for (int c = 0; c < ((CC > 0) ? CC : CMAX); ++c) acc[c] = make_float2(0.f, 0.f);
-            const float* t0 = trains + (size_t)n * nv;
-#pragma unroll
-            for (int r = 0; r < YROWS; ++r) {
-                const int iy = iyw + r;
-                if (iy >= ny) break;
-                const int j = iy * nx + ix;
-                const float2 ey = eytab[(size_t)n * ny + iy];
-                float2 x;
-                const float mu = colok ? t0[j] : 0.f;
-                if constexpr (MODE == 0) {
-                    x = make_float2(P[r].x * mu, P[r].y * mu);
-                } else {
-                    const float m1 = colok ? t0[plane + j] : 0.f;
-                    const float m2 = colok ? t0[2 * plane + j] : 0.f;
-                    const float m3 = colok ? t0[3 * plane + j] : 0.f;
-                    const float a = fmaf(v0[r], m1, fmaf(v1[r], m2, v2[r] * m3));
-                    x = make_float2(fmaf(P[r].x, a, Q[r].x * mu), fmaf(P[r].y, a, Q[r].y * mu));
-                }
-                const float2 zz = cmul(ey, x);
-                if constexpr (CC == 1) {
-                    acc[0].x += zz.x;
-                    acc[0].y += zz.y;
-                } else {
-                    for (int c = 0; c < nc; ++c) {
-                        const float2 cw = colok ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
-                        acc[c] = cfma(cw, zz, acc[c]);
-                    }
-                }
+        for (int r = 0; r < R; ++r) {
+            mu[r] = b0[jr[r]];
+            if constexpr (MODE == 1) {
+                m1[r] = b1[jr[r]];
+                m2[r] = b2[jr[r]];
+                m3[r] = b3[jr[r]];
             }
-            for (int c = 0; c < nc; ++c)
-                lds[((b * nc + c) * YWAVES + wave) * YLANES + lane] = acc[c];
+            ey[r] = eyrow[32 * r];
         }
-        __syncthreads();
-        const int nout = nbn * nc * YLANES;
-        for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-            const int l = o % YLANES;
-            const int bc = o / YLANES;   // b * nc + c
-            float2 s = lds[(bc * YWAVES + 0) * YLANES + l];
+        float2 acc[CC];
 #pragma unroll
-            for (int w = 1; w < YWAVES; ++w) {
-                const float2 t = lds[(bc * YWAVES + w) * YLANES + l];
-                s.x += t.x;
-                s.y += t.y;
+        for (int c = 0; c < CC; ++c) acc[c] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 x;
+            if constexpr (MODE == 0) {
+                x = make_float2(P[r].x * mu[r], P[r].y * mu[r]);
+            } else {
+                const float a = fmaf(v0[r], m1[r], fmaf(v1[r], m2[r], v2[r] * m3[r]));
+                x = make_float2(fmaf(P[r].x, a, Q[r].x * mu[r]), fmaf(P[r].y, a, Q[r].y * mu[r]));
             }
-            const int b = bc / nc, c = bc % nc;
-            const int oix = blockIdx.x * YLANES + l;
-            if (oix < nx)
-                upart[(((size_t)yb * nc + c) * T + (nb0 + b)) * nx + oix] = s;
+            const float2 z = cmul(ey[r], x);
+            if constexpr (CC == 1) {
+                acc[0].x += z.x;
+                acc[0].y += z.y;
+            } else {
+#pragma unroll
+                for (int c = 0; c < CC; ++c) acc[c] = cfma(cw[r][c], z, acc[c]);
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+            const float2 t = shfl_xor2(acc[c], 32);
+            if (half == 0)
+                lds[(((n - n0) * CC + c) * FW + wave) * 32 + xl] =
+                    make_float2(acc[c].x + t.x, acc[c].y + t.y);
+        }
     }
+    __syncthreads();
+    const int nout = (n1 - n0) * CC * 32;
+    for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+        const int l = o & 31, bc = o >> 5;   // bc = TR-in-chunk * CC + c
+        float2 s = lds[(bc * FW) * 32 + l];
+#pragma unroll
+        for (int w = 1; w < FW; ++w) {
+            const float2 t = lds[(bc * FW + w) * 32 + l];
+            s.x += t.x;
+            s.y += t.y;
+        }
+        const int b = bc / CC, c = bc % CC;
+        const int oix = blockIdx.x * 32 + l;
+        if (oix < nx && c < C) U[(((size_t)yb * C + c) * T + (n0 + b)) * nx + oix] = s;
+    }
+}
+
+// Sums the row-block partials of the forward y-stage into block 0.
+__global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float2 s = upart[i];
+    for (int b = 1; b < nby; ++b) {
+        const float2 t = upart[(size_t)b * count + i];
+        s.x += t.x;
+        s.y += t.y;
+    }
+    upart[i] = s;
 }
 
 // ------------------------------------------------------------------------
 // Adjoint y-stage: A_p[j] = sum_n mu_p[n,j] V[n,j],
 // V[n,j] = conj(Ey[n,iy]) sum_c conj(C_c[j]) W_c[n,ix], summed over the TRs of
-// one chunk (partials per chunk, combined in chunk order by the finish kernel).
+// one chunk. One thread per voxel in voxel order (each wave reads 256
+// contiguous bytes per train), blocks of 256 voxels span at most
+// 256 / nx + 2 rows, whose y-phases for the chunk are staged in LDS; W comes
+// through the vector cache (a block reuses each W row across its rows).
+// TRs go in batches of NBA whose loads are all issued before any use
+// (indices clamped to the chunk, contributions of padding TRs zeroed).
+// Partials per chunk are combined in chunk order by the finish kernel.
 // ------------------------------------------------------------------------
-template <int NTRAIN, int CC>
+constexpr int ADJ_EY_ROWS = 4;   // rows of a 256-voxel block when nx >= 128
+
+template <int NTRAIN, int CC, int NBA>
 __global__ __launch_bounds__(256) void ystage_adj_kernel(
     const float* __restrict__ trains, const float2* __restrict__ coil,
     const uint8_t* __restrict__ mask, const float2* __restrict__ eytab,
-    const float2* __restrict__ W, float* __restrict__ apart, int nx, int ny, int nv, int T, int C,
-    int n_per_chunk)
+    const float2* __restrict__ W, float* __restrict__ apart, int nx, int ny, int nv, int T,
+    int C, int n_per_chunk)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ix = blockIdx.x * YLANES + lane;
-    const int iyw = blockIdx.y * YBLOCK + wave * YROWS;
-    const int chunk = blockIdx.z;
+    extern __shared__ float2 eys[];   // [n_per_chunk][rows]
+    const int jb = blockIdx.x * 256;
+    const int j0 = jb + threadIdx.x;
+    const bool ok = j0 < nv;
+    const int j = ok ? j0 : nv - 1;
+    const int ix = j % nx, iy = j / nx;
+    const int row0 = jb / nx;
+    const int rows = (min(jb + 255, nv - 1)) / nx - row0 + 1;
+    const int chunk = blockIdx.y;
     const int n0 = chunk * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
-    const bool colok = ix < nx;
     const size_t plane = (size_t)T * nv;
-    const int nc = (CC > 0) ? CC : C;
 
-    float2 acc[YROWS][NTRAIN];
-#pragma unroll
-    for (int r = 0; r < YROWS; ++r)
-#pragma unroll
-        for (int p = 0; p < NTRAIN; ++p) acc[r][p] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < (n1 - n0) * rows; e += 256) {
+        const int nl = e / rows, rr = e % rows;
+        eys[nl * rows + rr] = eytab[(size_t)(n0 + nl) * ny + row0 + rr];
+    }
+    __syncthreads();
+    const int myrow = iy - row0;
 
-    for (int n = n0; n < n1; ++n) {
-        float2 w1 = make_float2(0.f, 0.f);
-        if constexpr (CC == 1) w1 = colok ? W[(size_t)n * nx + ix] : make_float2(0.f, 0.f);
-        const float* t0 = trains + (size_t)n * nv;
+    float2 cw[CC];
+    if constexpr (CC > 1) {
 #pragma unroll
-        for (int r = 0; r < YROWS; ++r) {
-            const int iy = iyw + r;
-            if (iy >= ny) break;
-            const int j = iy * nx + ix;
+        for (int c = 0; c < CC; ++c)
+            cw[c] = c < C ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
+    }
+    float2 acc[NTRAIN];
+#pragma unroll
+    for (int p = 0; p < NTRAIN; ++p) acc[p] = make_float2(0.f, 0.f);
+
+    for (int nb0 = n0; nb0 < n1; nb0 += NBA) {
+        float2 wv[NBA][CC];
+        float mu[NBA][NTRAIN];
+#pragma unroll
+        for (int b = 0; b < NBA; ++b) {
+            const int n = min(nb0 + b, n1 - 1);
+#pragma unroll
+            for (int c = 0; c < CC; ++c) {
+                const int cc = c < C ? c : 0;
+                wv[b][c] = W[((size_t)cc * T + n) * nx + ix];
+            }
+            const float* __restrict__ t0 = trains + (size_t)n * nv;
+#pragma unroll
+            for (int p = 0; p < NTRAIN; ++p) mu[b][p] = (t0 + p * plane)[j];
+        }
+#pragma unroll
+        for (int b = 0; b < NBA; ++b) {
+            const int nl = min(nb0 + b, n1 - 1) - n0;
+            const float keep = (nb0 + b < n1) ? 1.f : 0.f;
             float2 wc;
             if constexpr (CC == 1) {
-                wc = w1;
+                wc = wv[b][0];
             } else {
                 wc = make_float2(0.f, 0.f);
-                for (int c = 0; c < nc; ++c) {
-                    const float2 cw = colok ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
-                    const float2 wv = colok ? W[((size_t)c * T + n) * nx + ix] : make_float2(0.f, 0.f);
-                    const float2 t = cmulconj(cw, wv);
+#pragma unroll
+                for (int c = 0; c < CC; ++c) {
+                    const float2 t = cmulconj(cw[c], wv[b][c]);
                     wc.x += t.x;
                     wc.y += t.y;
                 }
             }
-            const float2 V = cmulconj(eytab[(size_t)n * ny + iy], wc);
+            float2 V = cmulconj(eys[nl * rows + myrow], wc);
+            V.x *= keep;
+            V.y *= keep;
 #pragma unroll
             for (int p = 0; p < NTRAIN; ++p) {
-                const float mu = colok ? t0[p * plane + j] : 0.f;
-                acc[r][p].x = fmaf(mu, V.x, acc[r][p].x);
-                acc[r][p].y = fmaf(mu, V.y, acc[r][p].y);
+                acc[p].x = fmaf(mu[b][p], V.x, acc[p].x);
+                acc[p].y = fmaf(mu[b][p], V.y, acc[p].y);
             }
         }
     }
+    if (!ok) return;
+    const bool on = mask == nullptr || mask[j] != 0;
+    float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j;
 #pragma unroll
-    for (int r = 0; r < YROWS; ++r) {
-        const int iy = iyw + r;
-        if (!colok || iy >= ny) continue;
-        const int j = iy * nx + ix;
-        const bool on = mask == nullptr || mask[j] != 0;
-        float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j;
-#pragma unroll
-        for (int p = 0; p < NTRAIN; ++p) {
-            dst[(2 * p) * (size_t)nv] = on ? acc[r][p].x : 0.f;
-            dst[(2 * p + 1) * (size_t)nv] = on ? acc[r][p].y : 0.f;
-        }
+    for (int p = 0; p < NTRAIN; ++p) {
+        dst[(2 * p) * (size_t)nv] = on ? acc[p].x : 0.f;
+        dst[(2 * p + 1) * (size_t)nv] = on ? acc[p].y : 0.f;
     }
+}
+
+// Sums the split-K partials of the adjoint x-GEMM into the first.
+__global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float2 s = W[i];
+    for (int b = 1; b < nsplit; ++b) {
+        const float2 t = W[(size_t)b * count + i];
+        s.x += t.x;
+        s.y += t.y;
+    }
+    W[i] = s;
 }
 
 // g from A: g_q = -Im(conj(rho) A_{q+1}) for q = lnT1, lnT2, B1;
@@ -266,7 +358,9 @@ __global__ void rho_adj_finish_kernel(const float* __restrict__ apart, int n_chu
 //            Ba = [[Er, -Ei], [Ei, Er]] at (k, ix)
 // with E = Ex[k][ix] read from the exactly range-reduced phase table.
 // Tile 64 x 64 per block, 4 waves in 2 x 2, each 32 x 32 = 2 x 2 MFMA blocks;
-// K in chunks of 32 staged through LDS (A rows, B phase tile).
+// K in chunks of 32, double-buffered in LDS with the next chunk's global loads
+// in flight during the current chunk's MFMAs. blockIdx.z splits K (partial
+// outputs at out + z * out_stride).
 // MFMA 16x16x4 f32 operand layout: A lane l -> (row l%16, k l/16),
 // B lane l -> (k l/16, col l%16), D lane l -> (rows 4(l/16)+i, col l%16).
 // ------------------------------------------------------------------------
@@ -274,12 +368,12 @@ constexpr int GBM = 64, GBN = 64, GBK = 32;
 
 template <int DIR, int MODE>   // DIR 0 forward, 1 adjoint; MODE (forward): 0 residual, 1 -s, 2 +s
 __global__ __launch_bounds__(256) void xgemm_f32_kernel(
-    const float2* __restrict__ Ain, int nby, const float2* __restrict__ extab,
+    const float2* __restrict__ Ain, const float2* __restrict__ extab,
     const float2* __restrict__ data, float2* __restrict__ out, double* __restrict__ red, int M,
-    int nx, int nk, int upart_stride)
+    int nx, int nk, int chunks_per_split, size_t out_stride)
 {
-    __shared__ float As[GBM][GBK + 1];
-    __shared__ float Bs[GBK][GBN + 1];
+    __shared__ float As[2][GBM][GBK + 1];
+    __shared__ float Bs[2][GBK][GBN + 4];
     __shared__ double rs[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -287,6 +381,61 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
     const int Kr = DIR == 0 ? 2 * nx : 2 * nk;    // real reduction length
     const int Nr = DIR == 0 ? 2 * nk : 2 * nx;    // real output columns
     const int Ka = DIR == 0 ? nx : nk;            // complex A columns
+    const int nchunk = (Kr + GBK - 1) / GBK;
+    const int kc0 = blockIdx.z * chunks_per_split;
+    const int kc1 = min(nchunk, kc0 + chunks_per_split);
+
+    float2 ra[4], rb[2];
+    auto gload = [&](int kc) {
+        const int k0 = kc * GBK;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e >> 4, cc = e & 15;
+            const int m = m0 + r, kcol = k0 / 2 + cc;
+            ra[i] = (m < M && kcol < Ka) ? Ain[(size_t)m * Ka + kcol] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            // Consecutive threads read consecutive ix of the phase table.
+            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
+            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
+            const int kr = k0 / 2 + rr, kcol = c0 / 2 + cc;
+            float2 E = make_float2(0.f, 0.f);
+            if (DIR == 0) {
+                if (kr < nx && kcol < nk) E = extab[(size_t)kcol * nx + kr];
+            } else {
+                if (kr < nk && kcol < nx) E = extab[(size_t)kr * nx + kcol];
+            }
+            rb[i] = E;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e >> 4, cc = e & 15;
+            As[buf][r][2 * cc] = ra[i].x;
+            As[buf][r][2 * cc + 1] = ra[i].y;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
+            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
+            const float2 E = rb[i];
+            Bs[buf][2 * rr][2 * cc] = E.x;
+            Bs[buf][2 * rr + 1][2 * cc + 1] = E.x;
+            if (DIR == 0) {
+                Bs[buf][2 * rr][2 * cc + 1] = E.y;
+                Bs[buf][2 * rr + 1][2 * cc] = -E.y;
+            } else {
+                Bs[buf][2 * rr][2 * cc + 1] = -E.y;
+                Bs[buf][2 * rr + 1][2 * cc] = E.y;
+            }
+        }
+    };
 
     f4 acc[2][2];
 #pragma unroll
@@ -294,68 +443,35 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < Kr; k0 += GBK) {
-        // A tile: 64 rows x 16 complex columns (sum of the y-stage partials
-        // for the forward direction).
-        for (int e = tid; e < GBM * (GBK / 2); e += 256) {
-            const int r = e / (GBK / 2), cc = e % (GBK / 2);
-            const int m = m0 + r, kc = k0 / 2 + cc;
-            float2 a = make_float2(0.f, 0.f);
-            if (m < M && kc < Ka) {
-                if (DIR == 0) {
-                    for (int b = 0; b < nby; ++b) {
-                        const float2 t = Ain[(size_t)b * upart_stride + (size_t)m * nx + kc];
-                        a.x += t.x;
-                        a.y += t.y;
-                    }
-                } else {
-                    a = Ain[(size_t)m * nk + kc];
-                }
-            }
-            As[r][2 * cc] = a.x;
-            As[r][2 * cc + 1] = a.y;
-        }
-        // B tile: 16 complex rows x 32 complex columns of 2x2 phase blocks.
-        for (int e = tid; e < (GBK / 2) * (GBN / 2); e += 256) {
-            // Consecutive threads read consecutive ix of the phase table.
-            const int rr = DIR == 0 ? e % (GBK / 2) : e / (GBN / 2);
-            const int cc = DIR == 0 ? e / (GBK / 2) : e % (GBN / 2);
-            const int kr = k0 / 2 + rr, kc = c0 / 2 + cc;
-            float2 E = make_float2(0.f, 0.f);
-            if (DIR == 0) {   // rows ix, columns k
-                if (kr < nx && kc < nk) E = extab[(size_t)kc * nx + kr];
-                Bs[2 * rr][2 * cc] = E.x;
-                Bs[2 * rr][2 * cc + 1] = E.y;
-                Bs[2 * rr + 1][2 * cc] = -E.y;
-                Bs[2 * rr + 1][2 * cc + 1] = E.x;
-            } else {          // rows k, columns ix
-                if (kr < nk && kc < nx) E = extab[(size_t)kr * nx + kc];
-                Bs[2 * rr][2 * cc] = E.x;
-                Bs[2 * rr][2 * cc + 1] = -E.y;
-                Bs[2 * rr + 1][2 * cc] = E.y;
-                Bs[2 * rr + 1][2 * cc + 1] = E.x;
-            }
-        }
-        __syncthreads();
+    if (kc0 < kc1) {
+        gload(kc0);
+        sstore(0);
+    }
+    __syncthreads();
+    for (int kc = kc0; kc < kc1; ++kc) {
+        const int buf = (kc - kc0) & 1;
+        const bool more = kc + 1 < kc1;
+        if (more) gload(kc + 1);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
             float av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int a = 0; a < 2; ++a) av[a] = As[buf][wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
+        if (more) sstore(buf ^ 1);
         __syncthreads();
     }
 
     // Epilogue.
     double sq = 0.0;
-    float* o = reinterpret_cast<float*>(out);
+    float* o = reinterpret_cast<float*>(out) + blockIdx.z * out_stride;
     const float* dd = reinterpret_cast<const float*>(data);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -387,99 +503,160 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
     }
 }
 
-}  // namespace
-
-hipError_t launch_ystage_fwd(const Dims& d, int mode, const float* trains, const float* theta,
-                             const float* v, const float2* coil, const uint8_t* mask,
-                             const float2* eytab, float2* upart, int n_chunk, hipStream_t s)
+template <int MODE, int CC>
+hipError_t fwd_R(const Dims& d, const YPlan& p, const float* trains, const float* theta,
+                 const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
+                 float2* U, hipStream_t s)
 {
-    dim3 grid(ceil_div(d.nx, YLANES), ceil_div(d.ny, YBLOCK), ceil_div(d.T, n_chunk));
-    const size_t lds = (size_t)NB * d.C * YWAVES * YLANES * sizeof(float2);
-    if (d.C > CMAX) return hipErrorInvalidValue;
-    if (d.C == 1) {
-        if (mode == 0)
-            ystage_fwd_kernel<0, 1><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, eytab, upart,
-                                                          d.nx, d.ny, d.nv, d.T, 1, n_chunk);
-        else
-            ystage_fwd_kernel<1, 1><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, eytab, upart,
-                                                          d.nx, d.ny, d.nv, d.T, 1, n_chunk);
-    } else {
-        if (mode == 0)
-            ystage_fwd_kernel<0, 0><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, eytab, upart,
-                                                          d.nx, d.ny, d.nv, d.T, d.C, n_chunk);
-        else
-            ystage_fwd_kernel<1, 0><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, eytab, upart,
-                                                          d.nx, d.ny, d.nv, d.T, d.C, n_chunk);
+    dim3 grid(ceil_div(d.nx, 32), p.nby, ceil_div(d.T, p.fwd_tr));
+    const size_t lds = (size_t)p.fwd_tr * (CC * FW * 32 + 32 * p.r_fwd) * sizeof(float2);
+#define FWD_CASE(RR)                                                                            \
+    case RR:                                                                                    \
+        if constexpr (CC == 1 || RR <= 2)                                                       \
+            ystage_fwd_kernel<MODE, RR, CC><<<grid, FW * 64, lds, s>>>(                         \
+                trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr);  \
+        else                                                                                    \
+            return hipErrorInvalidValue;                                                        \
+        break;
+    switch (p.r_fwd) {
+        FWD_CASE(1) FWD_CASE(2) FWD_CASE(3) FWD_CASE(4) FWD_CASE(5) FWD_CASE(6) FWD_CASE(7)
+        FWD_CASE(8)
+        default: return hipErrorInvalidValue;
     }
+#undef FWD_CASE
     return hipGetLastError();
 }
 
-hipError_t launch_xgemm_fwd(const Dims& d, int enc, int mode, const float2* upart, int nby,
+template <int NTRAIN, int CC>
+hipError_t adj_launch(const Dims& d, const YPlan& p, const float* trains, const float2* coil,
+                      const uint8_t* mask, const float2* eytab, const float2* W, float* apart,
+                      hipStream_t s)
+{
+    dim3 grid(ceil_div(d.nv, 256), p.adj_chunks);
+    const int rows = std::min(d.ny, 256 / d.nx + 2);
+    const size_t lds = (size_t)p.adj_per_chunk * rows * sizeof(float2);
+    constexpr int NBA = CC == 1 ? 4 : 2;
+    ystage_adj_kernel<NTRAIN, CC, NBA><<<grid, 256, lds, s>>>(trains, coil, mask, eytab, W, apart,
+                                                             d.nx, d.ny, d.nv, d.T, d.C,
+                                                             p.adj_per_chunk);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+YPlan make_yplan(const Dims& d)
+{
+    YPlan p{};
+    // Forward: rows per block 32 R with R <= 4 (one coil; more rows per lane
+    // spill registers in the 1024-thread block) or <= 2 / 1 with coils; the
+    // rows are split into nby balanced blocks whose partial sums of U are
+    // added by a small kernel.
+    const int rmax = d.C == 1 ? 4 : (d.C <= 8 ? 2 : 1);
+    p.nby = ceil_div(d.ny, 32 * rmax);
+    p.r_fwd = ceil_div(d.ny, 32 * p.nby);
+    // TRs per block: the chunk's per-wave sums live in LDS (at most 64 KB).
+    p.fwd_tr = d.C == 1 ? 16 : (d.C <= 8 ? 2 : 1);
+    // Adjoint: one row per lane (8 rows per block) and 8 TR chunks: enough
+    // blocks in flight to stream the trains near the HBM limit, with partial
+    // sums of 8 chunks x 8 floats per voxel.
+    p.r_adj = 1;
+    p.adj_chunks = std::min(8, d.T);
+    // LDS staging of the y-phases: chunk TRs x rows of a block (<= 64 KB).
+    const int rows = std::min(d.ny, 256 / d.nx + 2);
+    while (ceil_div(d.T, p.adj_chunks) * rows * 8 > 65536) ++p.adj_chunks;
+    p.adj_per_chunk = ceil_div(d.T, p.adj_chunks);
+    p.adj_chunks = ceil_div(d.T, p.adj_per_chunk);
+    // Adjoint x-GEMM: split K when the output tile grid is small.
+    const int tiles = ceil_div(2 * d.nx, GBN) * ceil_div(d.C * d.T, GBM);
+    const int kchunks = ceil_div(2 * d.nk, GBK);
+    const int ks = tiles >= 256 ? 1 : 256 / std::max(tiles, 1);
+    p.ksplit_adj = ks >= 4 ? 4 : (ks >= 2 ? 2 : 1);
+    while (p.ksplit_adj > kchunks) p.ksplit_adj /= 2;
+    return p;
+}
+
+hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const float* trains,
+                             const float* theta, const float* v, const float2* coil,
+                             const uint8_t* mask, const float2* eytab, float2* upart,
+                             hipStream_t s)
+{
+    hipError_t e;
+    if (d.C == 1)
+        e = mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                      : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    else if (d.C <= 8)
+        e = mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                      : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    else
+        e = mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                      : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    if (e != hipSuccess || p.nby == 1) return e;
+    const size_t count = (size_t)d.C * d.T * d.nx;
+    usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, p.nby, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, const float2* U,
                             const float2* extab, const float2* data, float2* out, double* red,
                             int* nred, hipStream_t s)
 {
     (void)enc;
+    (void)p;
     const int M = d.C * d.T;
-    dim3 grid(ceil_div(2 * d.nk, GBN), ceil_div(M, GBM));
+    dim3 grid(ceil_div(2 * d.nk, GBN), ceil_div(M, GBM), 1);
     if (nred) *nred = grid.x * grid.y;
-    const int stride = M * d.nx;
+    const int chunks = ceil_div(2 * d.nx, GBK);
     if (mode == 0)
-        xgemm_f32_kernel<0, 0><<<grid, 256, 0, s>>>(upart, nby, extab, data, out, red, M, d.nx, d.nk,
-                                                    stride);
+        xgemm_f32_kernel<0, 0><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else if (mode == 1)
-        xgemm_f32_kernel<0, 1><<<grid, 256, 0, s>>>(upart, nby, extab, data, out, red, M, d.nx, d.nk,
-                                                    stride);
+        xgemm_f32_kernel<0, 1><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else
-        xgemm_f32_kernel<0, 2><<<grid, 256, 0, s>>>(upart, nby, extab, data, out, red, M, d.nx, d.nk,
-                                                    stride);
+        xgemm_f32_kernel<0, 2><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_xgemm_adj(const Dims& d, int enc, const float2* w, const float2* extab,
-                            float2* W, hipStream_t s)
+hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2* w,
+                            const float2* extab, float2* W, hipStream_t s)
 {
     (void)enc;
     const int M = d.C * d.T;
-    dim3 grid(ceil_div(2 * d.nx, GBN), ceil_div(M, GBM));
-    xgemm_f32_kernel<1, 0><<<grid, 256, 0, s>>>(w, 1, extab, nullptr, W, nullptr, M, d.nx, d.nk, 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_ystage_adj(const Dims& d, const float* trains, int ntr_trains,
-                             const float2* coil, const uint8_t* mask, const float2* eytab,
-                             const float2* W, float* apart, int n_chunk, hipStream_t s)
-{
-    dim3 grid(ceil_div(d.nx, YLANES), ceil_div(d.ny, YBLOCK), ceil_div(d.T, n_chunk));
-    if (d.C > CMAX) return hipErrorInvalidValue;
-    if (ntr_trains == 4) {
-        if (d.C == 1)
-            ystage_adj_kernel<4, 1><<<grid, 256, 0, s>>>(trains, coil, mask, eytab, W, apart, d.nx, d.ny,
-                                                       d.nv, d.T, 1, n_chunk);
-        else
-            ystage_adj_kernel<4, 0><<<grid, 256, 0, s>>>(trains, coil, mask, eytab, W, apart, d.nx, d.ny,
-                                                       d.nv, d.T, d.C, n_chunk);
-    } else {
-        if (d.C == 1)
-            ystage_adj_kernel<1, 1><<<grid, 256, 0, s>>>(trains, coil, mask, eytab, W, apart, d.nx, d.ny,
-                                                       d.nv, d.T, 1, n_chunk);
-        else
-            ystage_adj_kernel<1, 0><<<grid, 256, 0, s>>>(trains, coil, mask, eytab, W, apart, d.nx, d.ny,
-                                                       d.nv, d.T, d.C, n_chunk);
+    const int kchunks = ceil_div(2 * d.nk, GBK);
+    const int per = ceil_div(kchunks, p.ksplit_adj);
+    dim3 grid(ceil_div(2 * d.nx, GBN), ceil_div(M, GBM), p.ksplit_adj);
+    const size_t stride = (size_t)M * 2 * d.nx;   // floats per partial
+    xgemm_f32_kernel<1, 0><<<grid, 256, 0, s>>>(w, extab, nullptr, W, nullptr, M, d.nx, d.nk, per, stride);
+    if (p.ksplit_adj > 1) {
+        const size_t count = (size_t)M * d.nx;
+        wsum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(W, p.ksplit_adj, count);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_jhw_finish(const Dims& d, const float* apart, int n_chunk, const float* theta,
+hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const float* trains, int ntr_trains,
+                             const float2* coil, const uint8_t* mask, const float2* eytab,
+                             const float2* W, float* apart, hipStream_t s)
+{
+    if (ntr_trains == 4) {
+        if (d.C == 1) return adj_launch<4, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
+        if (d.C <= 8) return adj_launch<4, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
+        return adj_launch<4, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+    }
+    if (d.C == 1) return adj_launch<1, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
+    if (d.C <= 8) return adj_launch<1, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
+    return adj_launch<1, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+}
+
+hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, float* g, hipStream_t s)
 {
-    jhw_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, n_chunk, theta, mask, g, d.nv);
+    jhw_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask, g, d.nv);
     return hipGetLastError();
 }
 
-hipError_t launch_rho_adj_finish(const Dims& d, const float* apart, int n_chunk,
+hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
                                  const uint8_t* mask, float2* out, hipStream_t s)
 {
-    rho_adj_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, n_chunk, mask, out, d.nv);
+    rho_adj_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, mask, out, d.nv);
     return hipGetLastError();
 }
 

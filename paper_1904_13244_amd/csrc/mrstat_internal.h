@@ -22,14 +22,20 @@ struct SeqTimes {
     float tr, te, tinv;
 };
 
-// Column tiling of the y-stage kernels: 64 lanes along ix, waves stacked
-// along iy; each wave owns YROWS consecutive rows.
-constexpr int YLANES = 64;
-constexpr int YWAVES = 4;
-constexpr int YROWS = 8;
-constexpr int YBLOCK = YWAVES * YROWS;   // rows per iy block (partial sum)
+// Tiling of the encoding kernels, chosen per problem on the host.
+struct YPlan {
+    int r_fwd;        // forward y-stage: row steps per lane (32 r_fwd rows per block)
+    int nby;          // forward row blocks (partial sums of U when > 1)
+    int fwd_tr;       // TRs per forward block
+    int r_adj;        // adjoint y-stage: row steps per lane (8 r_adj rows per block)
+    int adj_chunks;   // TR chunks of the adjoint y-stage (partial sums per chunk)
+    int adj_per_chunk;
+    int ksplit_adj;   // split-K of the adjoint x-GEMM (partial W outputs)
+};
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+YPlan make_yplan(const Dims& d);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return the launch status.
@@ -40,37 +46,39 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
                       float* out, bool tangents, int lanes, hipStream_t s);
 
-// Forward y-stage: upart[b][c][n][ix] = sum over rows iy of block b of
-// Ey[n][iy] * coil_c[j] * x[n][j], with x = i rho m (mode 0) or
-// x = i (rho sum_q v_q dm_q + (v3 + i v4) m) (mode 1, the J v direction).
-hipError_t launch_ystage_fwd(const Dims& d, int mode, const float* trains, const float* theta,
-                             const float* v, const float2* coil, const uint8_t* mask,
-                             const float2* eytab, float2* upart, int n_chunk, hipStream_t s);
+// Forward y-stage: U[c][n][ix] = sum over rows iy of Ey[n][iy] * coil_c[j] *
+// x[n][j], with x = i rho m (mode 0) or x = i (rho sum_q v_q dm_q +
+// (v3 + i v4) m) (mode 1, the J v direction). upart holds nby row-block
+// partials when nby > 1 and is summed into its first block.
+hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const float* trains,
+                             const float* theta, const float* v, const float2* coil,
+                             const uint8_t* mask, const float2* eytab, float2* upart,
+                             hipStream_t s);
 
-// x-stage forward GEMM: s[c][n][k] = sum_ix Ex[k][ix] U[c][n][ix], U the sum of
-// the nby partials. mode 0: out = data - s and per-block FP64 sums of |out|^2
-// into red; mode 1: out = -s.
-hipError_t launch_xgemm_fwd(const Dims& d, int enc, int mode, const float2* upart, int nby,
+// x-stage forward GEMM: s[c][n][k] = sum_ix Ex[k][ix] U[c][n][ix].
+// mode 0: out = data - s and per-block FP64 sums of |out|^2 into red;
+// mode 1: out = -s; mode 2: out = s.
+hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, const float2* U,
                             const float2* extab, const float2* data, float2* out, double* red,
                             int* nred, hipStream_t s);
 
-// x-stage adjoint GEMM: W[c][n][ix] = sum_k conj(Ex[k][ix]) w[c][n][k].
-hipError_t launch_xgemm_adj(const Dims& d, int enc, const float2* w, const float2* extab,
-                            float2* W, hipStream_t s);
+// x-stage adjoint GEMM: W[z][c][n][ix] = partial z of sum_k conj(Ex[k][ix]) w[c][n][k].
+hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2* w,
+                            const float2* extab, float2* W, hipStream_t s);
 
 // Adjoint y-stage: partial sums over TR chunks of
 // A_p[j] = sum_n mu_p[n][j] conj(Ey[n][iy]) sum_c conj(coil_c[j]) W_c[n][ix]
 // (p = 0..3 for m and the three tangents; ntr_trains = 4 or 1).
-hipError_t launch_ystage_adj(const Dims& d, const float* trains, int ntr_trains,
+hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const float* trains, int ntr_trains,
                              const float2* coil, const uint8_t* mask, const float2* eytab,
-                             const float2* W, float* apart, int n_chunk, hipStream_t s);
+                             const float2* W, float* apart, hipStream_t s);
 
 // g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order).
-hipError_t launch_jhw_finish(const Dims& d, const float* apart, int n_chunk, const float* theta,
+hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, float* g, hipStream_t s);
 
-// CGLS helpers on complex per-voxel vectors: A^H w = -i A_0 from the partials.
-hipError_t launch_rho_adj_finish(const Dims& d, const float* apart, int n_chunk,
+// CGLS helper: A^H w = -i A_0 from the one-train partials.
+hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
                                  const uint8_t* mask, float2* out, hipStream_t s);
 
 // ---------------------------------------------------------------- reductions

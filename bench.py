@@ -50,6 +50,22 @@ def algorithmic(kind, prob):
     return None
 
 
+def measured_traffic(kind):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1904_13244_amd", "csrc", "encode.hip")
+    summary = os.path.join(ROOT, "profiles", "hbm_traffic_224x224_1120tr.txt")
+    if not os.path.exists(summary):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(summary):
+        f = line.split()
+        if len(f) == 4 and f[0] == "TRAFFIC" and f[1] == kind and f[2] == sha:
+            return float(f[3])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +170,7 @@ def main():
         if unit == "bytes":
             ach = amount / t / 1e9
             roof = {"kernel": rk, "bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(rk),
                     "algorithmic_bytes_per_launch": amount}
         else:
             ach = amount / t / 1e12

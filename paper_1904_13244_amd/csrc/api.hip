@@ -345,7 +345,8 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const voi
 mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)
 {
     if (!ctx) return MRSTAT_ERR_ARG;
-    if (enc != MRSTAT_ENC_FP32) return fail(ctx, MRSTAT_ERR_UNSUPPORTED, "encoding precision not built");
+    if (enc != MRSTAT_ENC_FP32 && enc != MRSTAT_ENC_SPLIT_BF16 && enc != MRSTAT_ENC_FP16)
+        return fail(ctx, MRSTAT_ERR_ARG, "unknown encoding precision");
     ctx->enc = enc;
     return MRSTAT_OK;
 }

@@ -503,6 +503,230 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Reduced-precision x-stage GEMMs on v_mfma_f32_16x16x32_{bf16,f16}: the same
+// real 2x2-block form and tiling as the FP32 kernel, with BK = 32 real K per
+// chunk (one MFMA per 16x16 block and product term).
+//   ENC 1, split-BF16: each FP32 operand x = hi + lo, hi = bf16(x),
+//          lo = bf16(x - hi); C = hi*hi + hi*lo + lo*hi with FP32 accumulation
+//          (the lo*lo term, ~2^-16 relative, is dropped).
+//   ENC 2, FP16: one product of FP16-rounded operands, FP32 accumulation
+//          (operands must stay below 65504 in magnitude: |U|, |w| and the
+//          unit-modulus phases do for these problems).
+// Operands are stored k-contiguous in LDS (A row-major, B transposed) so a
+// lane's 8-element fragment is one 128-bit LDS read. MFMA 16x16x32 operand
+// layout: A lane l -> (row l%16, k 8(l/16)..+7), B lane l -> (k 8(l/16)..+7,
+// col l%16), D as for the FP32 instruction.
+// ------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x)
+{
+    const unsigned int u = __float_as_uint(x);
+    const unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(r >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short b)
+{
+    return __uint_as_float((unsigned int)b << 16);
+}
+
+constexpr int XPAD = 8;   // 16-bit elements of row padding (keeps 16-byte alignment)
+
+template <int ENC>
+struct MxOps;
+template <>
+struct MxOps<1> {
+    static constexpr int TERMS = 2;   // hi, lo
+    __device__ static void split(float x, unsigned short* h, unsigned short* l)
+    {
+        const unsigned short hb = bf16_bits_rne(x);
+        *h = hb;
+        *l = bf16_bits_rne(x - bf16_bits_to_float(hb));
+    }
+    __device__ static f4 mma(const uint4& a, const uint4& b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+};
+template <>
+struct MxOps<2> {
+    static constexpr int TERMS = 1;
+    __device__ static void split(float x, unsigned short* h, unsigned short* l)
+    {
+        *h = __builtin_bit_cast(unsigned short, (_Float16)x);
+        *l = 0;
+    }
+    __device__ static f4 mma(const uint4& a, const uint4& b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+};
+
+template <int DIR, int MODE, int ENC>
+__global__ __launch_bounds__(256) void xgemm_mx_kernel(
+    const float2* __restrict__ Ain, const float2* __restrict__ extab,
+    const float2* __restrict__ data, float2* __restrict__ out, double* __restrict__ red, int M,
+    int nx, int nk, int chunks_per_split, size_t out_stride)
+{
+    using Ops = MxOps<ENC>;
+    constexpr int NT = Ops::TERMS;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][NT][GBM][GBK + XPAD];
+    __shared__ __attribute__((aligned(16))) unsigned short Bt[2][NT][GBN][GBK + XPAD];
+    __shared__ double rs[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * GBM, c0 = blockIdx.x * GBN;
+    const int Kr = DIR == 0 ? 2 * nx : 2 * nk;
+    const int Nr = DIR == 0 ? 2 * nk : 2 * nx;
+    const int Ka = DIR == 0 ? nx : nk;
+    const int nchunk = (Kr + GBK - 1) / GBK;
+    const int kc0 = blockIdx.z * chunks_per_split;
+    const int kc1 = min(nchunk, kc0 + chunks_per_split);
+
+    float2 ra[4], rb[2];
+    auto gload = [&](int kc) {
+        const int k0 = kc * GBK;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e >> 4, cc = e & 15;
+            const int m = m0 + r, kcol = k0 / 2 + cc;
+            ra[i] = (m < M && kcol < Ka) ? Ain[(size_t)m * Ka + kcol] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
+            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
+            const int kr = k0 / 2 + rr, kcol = c0 / 2 + cc;
+            float2 E = make_float2(0.f, 0.f);
+            if (DIR == 0) {
+                if (kr < nx && kcol < nk) E = extab[(size_t)kcol * nx + kr];
+            } else {
+                if (kr < nk && kcol < nx) E = extab[(size_t)kr * nx + kcol];
+            }
+            rb[i] = E;
+        }
+    };
+    auto put = [&](unsigned short (*dst)[GBM][GBK + XPAD], int row, int k, float x) {
+        unsigned short h, l;
+        Ops::split(x, &h, &l);
+        dst[0][row][k] = h;
+        if constexpr (NT > 1) dst[1][row][k] = l;
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e >> 4, cc = e & 15;
+            put(As[buf], r, 2 * cc, ra[i].x);
+            put(As[buf], r, 2 * cc + 1, ra[i].y);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
+            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
+            const float2 E = rb[i];
+            // B[2rr + a][2cc + b] stored transposed at Bt[2cc + b][2rr + a].
+            put(Bt[buf], 2 * cc, 2 * rr, E.x);
+            put(Bt[buf], 2 * cc + 1, 2 * rr + 1, E.x);
+            put(Bt[buf], 2 * cc + 1, 2 * rr, DIR == 0 ? E.y : -E.y);
+            put(Bt[buf], 2 * cc, 2 * rr + 1, DIR == 0 ? -E.y : E.y);
+        }
+    };
+
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+    if (kc0 < kc1) {
+        gload(kc0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    for (int kc = kc0; kc < kc1; ++kc) {
+        const int buf = (kc - kc0) & 1;
+        const bool more = kc + 1 < kc1;
+        if (more) gload(kc + 1);
+        uint4 af[NT][2], bf[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                af[t][a] = *reinterpret_cast<const uint4*>(&As[buf][t][wm * 32 + a * 16 + (lane & 15)][kq]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bf[t][b] = *reinterpret_cast<const uint4*>(&Bt[buf][t][wn * 32 + b * 16 + (lane & 15)][kq]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if constexpr (NT > 1) {
+                    acc[a][b] = Ops::mma(af[1][a], bf[0][b], acc[a][b]);   // lo * hi
+                    acc[a][b] = Ops::mma(af[0][a], bf[1][b], acc[a][b]);   // hi * lo
+                }
+                acc[a][b] = Ops::mma(af[0][a], bf[0][b], acc[a][b]);       // hi * hi
+            }
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    double sq = 0.0;
+    float* o = reinterpret_cast<float*>(out) + blockIdx.z * out_stride;
+    const float* dd = reinterpret_cast<const float*>(data);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm * 32 + a * 16 + 4 * (lane >> 4) + i;
+                const int c = c0 + wn * 32 + b * 16 + (lane & 15);
+                if (m < M && c < Nr) {
+                    const size_t idx = (size_t)m * Nr + c;
+                    const float val = acc[a][b][i];
+                    if (DIR == 0 && MODE == 0) {
+                        const float rv = dd[idx] - val;
+                        o[idx] = rv;
+                        sq += (double)rv * (double)rv;
+                    } else if (DIR == 0 && MODE == 1) {
+                        o[idx] = -val;
+                    } else {
+                        o[idx] = val;
+                    }
+                }
+            }
+    if (DIR == 0 && MODE == 0) {
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        if (lane == 0) rs[wave] = sq;
+        __syncthreads();
+        if (tid == 0) red[blockIdx.y * gridDim.x + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    }
+}
+
+template <int DIR, int MODE>
+void xgemm_any(int enc, dim3 grid, hipStream_t s, const float2* A, const float2* extab,
+               const float2* data, float2* out, double* red, int M, int nx, int nk, int per,
+               size_t stride)
+{
+    if (enc == 1)
+        xgemm_mx_kernel<DIR, MODE, 1><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
+    else if (enc == 2)
+        xgemm_mx_kernel<DIR, MODE, 2><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
+    else
+        xgemm_f32_kernel<DIR, MODE><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
+}
+
 template <int MODE, int CC>
 hipError_t fwd_R(const Dims& d, const YPlan& p, const float* trains, const float* theta,
                  const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
@@ -600,31 +824,29 @@ hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, co
                             const float2* extab, const float2* data, float2* out, double* red,
                             int* nred, hipStream_t s)
 {
-    (void)enc;
     (void)p;
     const int M = d.C * d.T;
     dim3 grid(ceil_div(2 * d.nk, GBN), ceil_div(M, GBM), 1);
     if (nred) *nred = grid.x * grid.y;
     const int chunks = ceil_div(2 * d.nx, GBK);
     if (mode == 0)
-        xgemm_f32_kernel<0, 0><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 0>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else if (mode == 1)
-        xgemm_f32_kernel<0, 1><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 1>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else
-        xgemm_f32_kernel<0, 2><<<grid, 256, 0, s>>>(U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 2>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2* w,
                             const float2* extab, float2* W, hipStream_t s)
 {
-    (void)enc;
     const int M = d.C * d.T;
     const int kchunks = ceil_div(2 * d.nk, GBK);
     const int per = ceil_div(kchunks, p.ksplit_adj);
     dim3 grid(ceil_div(2 * d.nx, GBN), ceil_div(M, GBM), p.ksplit_adj);
     const size_t stride = (size_t)M * 2 * d.nx;   // floats per partial
-    xgemm_f32_kernel<1, 0><<<grid, 256, 0, s>>>(w, extab, nullptr, W, nullptr, M, d.nx, d.nk, per, stride);
+    xgemm_any<1, 0>(enc, grid, s, w, extab, nullptr, W, nullptr, M, d.nx, d.nk, per, stride);
     if (p.ksplit_adj > 1) {
         const size_t count = (size_t)M * d.nx;
         wsum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(W, p.ksplit_adj, count);

@@ -56,6 +56,7 @@ extern "C" {
 #endif
 
 typedef struct mrstat_ctx_s *mrstat_ctx;
+typedef struct mrstat_mlp_s *mrstat_mlp;   /* surrogate network (see below) */
 typedef void *mrstat_stream; /* hipStream_t */
 
 typedef enum {
@@ -118,7 +119,8 @@ typedef struct {
     int32_t cg_iters;     /* CG iterations performed */
     int32_t ls_trials;    /* objective evaluations in the line search */
     int32_t accepted;     /* 1 if theta was updated */
-    int32_t reserved;
+    int32_t n_fallback;   /* voxels of the linearisation simulated by the EPG because they
+                             lie outside the surrogate's box (0 without a surrogate) */
 } mrstat_gn_report;
 
 /* Validates the problem and builds the host context (no device work). */
@@ -209,11 +211,97 @@ typedef enum {
     MRSTAT_K_YADJ = 6,       /* adjoint y-stage (train streaming) */
     MRSTAT_K_FINISH = 7,     /* gradient assembly from the adjoint partials */
     MRSTAT_K_VECTOR = 8,     /* CG / line-search / CGLS vector kernels and reductions */
-    MRSTAT_K_COUNT = 9
+    MRSTAT_K_SURR = 9,       /* surrogate inference of all four trains (+ box test) */
+    MRSTAT_K_SURR_VALUE = 10,/* surrogate inference of the m train (line-search trials) */
+    MRSTAT_K_COUNT = 11
 } mrstat_kernel_kind;
 
 mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on);
 mrstat_status mrstat_profile_read(mrstat_ctx ctx, int32_t *h_counts, double *h_ms);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the EPG linearisation.
+ *
+ * Not part of the paper's method: an extension that replaces the per-voxel
+ * simulation of the trains (the cost the paper names as dominant, Discussion)
+ * by a small network evaluated on the matrix cores, keeping the EPG for
+ * voxels outside the network's training box.
+ *
+ * Network: inputs (ln T1, ln T2, B1), each mapped affinely from the box onto
+ * [-1, 1]; `depth` hidden layers of `width` units with the exact GELU
+ * z Phi(z); a linear output layer of 8 n_tr values. Output o = c 4 n_tr +
+ * p n_tr + n is part c (0 real, 1 imaginary) of train p (m, dm/dlnT1,
+ * dm/dlnT2, dm/dB1) at TR n, in units of the head scale s_p. Parameters are
+ * one FP32 vector: W1 [width][3], b1, then (W [width][width], b) for each
+ * further hidden layer, Wout [8 n_tr][width], bout (row-major [out][in]).
+ * Training: mean squared error over all outputs and samples against the EPG
+ * trains divided by s_p (real parts target 0), Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected) on FP32 master weights. Matrix products use BF16
+ * operands (weights and activations rounded to BF16) with FP32
+ * accumulation; the first layer and all epilogues run in FP32.
+ *
+ * Device memory: one caller-provided workspace per network
+ * (mrstat_mlp_workspace_bytes / mrstat_mlp_bind), holding the parameters,
+ * the Adam moments, gradients and the activations of one batch. Calls
+ * are asynchronous on the given stream except those returning host values.
+ * A network is not thread-safe, and a context using it as surrogate shares
+ * its workspace: do not train and reconstruct with one network at once.
+ * Requirements: n_tr a multiple of 8; width a multiple of 64, <= 1024;
+ * 1 <= depth <= 16; batch a multiple of 64.
+ * ------------------------------------------------------------------------ */
+mrstat_status mrstat_mlp_create(int32_t n_tr, int32_t width, int32_t depth, int32_t batch,
+                                mrstat_mlp *out);
+void mrstat_mlp_destroy(mrstat_mlp net);
+const char *mrstat_mlp_last_error(mrstat_mlp net);
+size_t mrstat_mlp_param_count(mrstat_mlp net);
+size_t mrstat_mlp_workspace_bytes(mrstat_mlp net);
+/* Attaches a 256-byte aligned workspace (kept alive by the caller). */
+mrstat_status mrstat_mlp_bind(mrstat_mlp net, void *d_ws, size_t ws_bytes, mrstat_stream stream);
+/* Box [box_lo, box_hi] of (ln T1, ln T2, B1) (host arrays of 3) and head
+ * scales s_p > 0 (host array of 4). Synchronises the stream. */
+mrstat_status mrstat_mlp_set_scaling(mrstat_mlp net, const float box_lo[3], const float box_hi[3],
+                                     const float head_scale[4], mrstat_stream stream);
+/* Sets the box and s_p = RMS of train p over d_trains float32 [4][n_tr][n]
+ * (FP64 sums on the device); returns the scales in h_scale_out (may be
+ * NULL). Synchronises. */
+mrstat_status mrstat_mlp_fit_scaling(mrstat_mlp net, const float *d_trains, int64_t n,
+                                     const float box_lo[3], const float box_hi[3],
+                                     float h_scale_out[4], mrstat_stream stream);
+/* Copies parameters in (device float32 [param_count]), refreshes the BF16
+ * copy and resets the Adam state; or copies the FP32 parameters out. */
+mrstat_status mrstat_mlp_set_params(mrstat_mlp net, const float *d_params, mrstat_stream stream);
+mrstat_status mrstat_mlp_get_params(mrstat_mlp net, float *d_params, mrstat_stream stream);
+/* One batch of `batch` samples: columns of d_theta (rows ln T1, ln T2, B1
+ * with leading dimension ld_theta, e.g. a theta [5][Nv] slice) and of the
+ * EPG trains d_trains float32 [4][n_tr][ld_trains] (imaginary parts, as
+ * mrstat_simulate writes them). mrstat_mlp_gradients writes the loss
+ * gradient (float32 [param_count]) without updating; mrstat_mlp_train_step
+ * applies one Adam step with learning rate lr. The batch loss is returned in
+ * *h_loss when h_loss != NULL (then the stream is synchronised). */
+mrstat_status mrstat_mlp_gradients(mrstat_mlp net, const float *d_theta, int64_t ld_theta,
+                                   const float *d_trains, int64_t ld_trains, float *d_grad,
+                                   double *h_loss, mrstat_stream stream);
+mrstat_status mrstat_mlp_train_step(mrstat_mlp net, const float *d_theta, int64_t ld_theta,
+                                    const float *d_trains, int64_t ld_trains, float lr,
+                                    double *h_loss, mrstat_stream stream);
+/* Tuning: voxels per workgroup of the fused inference kernel (widths 64, 128
+ * and 256 evaluate the whole network per voxel tile in one kernel): 32 or 64,
+ * 0 = automatic (64). Results are identical for every choice. */
+mrstat_status mrstat_mlp_set_infer_tile(mrstat_mlp net, int32_t voxels);
+/* Predicted trains (imaginary parts, s_p applied) for n columns of d_theta
+ * into d_out float32 [4][n_tr][n]. */
+mrstat_status mrstat_mlp_predict(mrstat_mlp net, const float *d_theta, int64_t ld_theta, int32_t n,
+                                 float *d_out, mrstat_stream stream);
+
+/* Uses net (bound, built for this n_tr; NULL = plain EPG) for every
+ * linearisation and line-search evaluation of the context: voxels whose
+ * (ln T1, ln T2, B1) lie in the network's box take its trains, the others
+ * (and non-finite ones) are simulated by the EPG. The caller keeps net alive
+ * while it is set. Invalidates the current linearisation. */
+mrstat_status mrstat_set_surrogate(mrstat_ctx ctx, mrstat_mlp net);
+/* Number of voxels the last linearisation sent to the EPG fallback (0 without
+ * a surrogate or linearisation). Synchronises the stream. */
+mrstat_status mrstat_fallback_count(mrstat_ctx ctx, int32_t *h_count, mrstat_stream stream);
 
 #ifdef __cplusplus
 }

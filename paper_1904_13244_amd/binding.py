@@ -46,10 +46,10 @@ class GnOpts(C.Structure):
 class GnReport(C.Structure):
     _fields_ = [("f0", C.c_double), ("f1", C.c_double), ("gnorm", C.c_double),
                 ("step_norm", C.c_double), ("t", C.c_double), ("cg_iters", C.c_int32),
-                ("ls_trials", C.c_int32), ("accepted", C.c_int32), ("reserved", C.c_int32)]
+                ("ls_trials", C.c_int32), ("accepted", C.c_int32), ("n_fallback", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -79,6 +79,25 @@ def lib():
             "mrstat_rho_init": ([vp, vp, vp, i32, vp], C.c_int),
             "mrstat_profile_enable": ([vp, i32], C.c_int),
             "mrstat_profile_read": ([vp, P(i32), P(C.c_double)], C.c_int),
+            "mrstat_set_surrogate": ([vp, vp], C.c_int),
+            "mrstat_fallback_count": ([vp, P(i32), vp], C.c_int),
+            "mrstat_mlp_create": ([i32, i32, i32, i32, P(vp)], C.c_int),
+            "mrstat_mlp_destroy": ([vp], None),
+            "mrstat_mlp_last_error": ([vp], C.c_char_p),
+            "mrstat_mlp_param_count": ([vp], C.c_size_t),
+            "mrstat_mlp_workspace_bytes": ([vp], C.c_size_t),
+            "mrstat_mlp_bind": ([vp, vp, C.c_size_t, vp], C.c_int),
+            "mrstat_mlp_set_scaling": ([vp, P(C.c_float), P(C.c_float), P(C.c_float), vp], C.c_int),
+            "mrstat_mlp_fit_scaling": ([vp, vp, C.c_int64, P(C.c_float), P(C.c_float),
+                                        P(C.c_float), vp], C.c_int),
+            "mrstat_mlp_set_params": ([vp, vp, vp], C.c_int),
+            "mrstat_mlp_get_params": ([vp, vp, vp], C.c_int),
+            "mrstat_mlp_gradients": ([vp, vp, C.c_int64, vp, C.c_int64, vp, P(C.c_double), vp],
+                                     C.c_int),
+            "mrstat_mlp_train_step": ([vp, vp, C.c_int64, vp, C.c_int64, C.c_float,
+                                       P(C.c_double), vp], C.c_int),
+            "mrstat_mlp_predict": ([vp, vp, C.c_int64, i32, vp, vp], C.c_int),
+            "mrstat_mlp_set_infer_tile": ([vp, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -92,12 +111,23 @@ def exported_symbols():
     return ["mrstat_create", "mrstat_destroy", "mrstat_last_error", "mrstat_workspace_bytes",
             "mrstat_bind", "mrstat_set_encoding", "mrstat_set_epg_lanes", "mrstat_simulate", "mrstat_residual", "mrstat_jv",
             "mrstat_jhw", "mrstat_gn_step", "mrstat_rho_init", "mrstat_profile_enable",
-            "mrstat_profile_read"]
+            "mrstat_profile_read", "mrstat_set_surrogate", "mrstat_fallback_count",
+            "mrstat_mlp_create", "mrstat_mlp_destroy", "mrstat_mlp_last_error",
+            "mrstat_mlp_param_count", "mrstat_mlp_workspace_bytes", "mrstat_mlp_bind",
+            "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
+            "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
+            "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile"]
 
 
 def _check(status, ctx=None):
     if status != OK:
         msg = lib().mrstat_last_error(ctx)
+        raise MrstatError(status, msg.decode() if msg else "")
+
+
+def _check_mlp(status, net):
+    if status != OK:
+        msg = lib().mrstat_mlp_last_error(net) if net else b""
         raise MrstatError(status, msg.decode() if msg else "")
 
 
@@ -167,8 +197,91 @@ def mrstat_rho_init(ctx, theta_ptr, data_ptr, n_iter, stream):
     _check(lib().mrstat_rho_init(ctx, theta_ptr, data_ptr, int(n_iter), stream), ctx)
 
 
+def mrstat_set_surrogate(ctx, net):
+    _check(lib().mrstat_set_surrogate(ctx, net), ctx)
+
+
+def mrstat_fallback_count(ctx, stream):
+    n = C.c_int32(0)
+    _check(lib().mrstat_fallback_count(ctx, C.byref(n), stream), ctx)
+    return int(n.value)
+
+
+def mrstat_mlp_create(n_tr, width, depth, batch):
+    h = C.c_void_p()
+    _check_mlp(lib().mrstat_mlp_create(int(n_tr), int(width), int(depth), int(batch), C.byref(h)),
+               None)
+    return h
+
+
+def mrstat_mlp_destroy(net):
+    lib().mrstat_mlp_destroy(net)
+
+
+def mrstat_mlp_param_count(net):
+    return int(lib().mrstat_mlp_param_count(net))
+
+
+def mrstat_mlp_workspace_bytes(net):
+    return int(lib().mrstat_mlp_workspace_bytes(net))
+
+
+def mrstat_mlp_bind(net, ws_ptr, ws_bytes, stream):
+    _check_mlp(lib().mrstat_mlp_bind(net, ws_ptr, ws_bytes, stream), net)
+
+
+def _f3(x, n):
+    return (C.c_float * n)(*[float(v) for v in x])
+
+
+def mrstat_mlp_set_scaling(net, lo, hi, head_scale, stream):
+    _check_mlp(lib().mrstat_mlp_set_scaling(net, _f3(lo, 3), _f3(hi, 3), _f3(head_scale, 4), stream),
+               net)
+
+
+def mrstat_mlp_fit_scaling(net, trains_ptr, n, lo, hi, stream):
+    out = (C.c_float * 4)()
+    _check_mlp(lib().mrstat_mlp_fit_scaling(net, trains_ptr, int(n), _f3(lo, 3), _f3(hi, 3), out,
+                                            stream), net)
+    return [float(v) for v in out]
+
+
+def mrstat_mlp_set_params(net, params_ptr, stream):
+    _check_mlp(lib().mrstat_mlp_set_params(net, params_ptr, stream), net)
+
+
+def mrstat_mlp_get_params(net, params_ptr, stream):
+    _check_mlp(lib().mrstat_mlp_get_params(net, params_ptr, stream), net)
+
+
+def mrstat_mlp_gradients(net, theta_ptr, ld_theta, trains_ptr, ld_trains, grad_ptr, want_loss,
+                         stream):
+    loss = C.c_double(0.0)
+    _check_mlp(lib().mrstat_mlp_gradients(net, theta_ptr, int(ld_theta), trains_ptr, int(ld_trains),
+                                          grad_ptr, C.byref(loss) if want_loss else None, stream),
+               net)
+    return loss.value if want_loss else None
+
+
+def mrstat_mlp_train_step(net, theta_ptr, ld_theta, trains_ptr, ld_trains, lr, want_loss, stream):
+    loss = C.c_double(0.0)
+    _check_mlp(lib().mrstat_mlp_train_step(net, theta_ptr, int(ld_theta), trains_ptr, int(ld_trains),
+                                           float(lr), C.byref(loss) if want_loss else None, stream),
+               net)
+    return loss.value if want_loss else None
+
+
+def mrstat_mlp_set_infer_tile(net, voxels):
+    _check_mlp(lib().mrstat_mlp_set_infer_tile(net, int(voxels)), net)
+
+
+def mrstat_mlp_predict(net, theta_ptr, ld_theta, n, out_ptr, stream):
+    _check_mlp(lib().mrstat_mlp_predict(net, theta_ptr, int(ld_theta), int(n), out_ptr, stream), net)
+
+
 KERNEL_KINDS = ["epg", "epg_value", "ystage_fwd_signal", "ystage_fwd_jv", "xgemm_fwd",
-                "xgemm_adj", "ystage_adj", "jhw_finish", "vector"]
+                "xgemm_adj", "ystage_adj", "jhw_finish", "vector", "surrogate",
+                "surrogate_value"]
 
 
 def mrstat_profile_enable(ctx, on):
@@ -315,3 +428,104 @@ class Context:
         self._expect(data, T.complex64, self.data_shape)
         mrstat_rho_init(self.h, theta.data_ptr(), data.data_ptr(), n_iter, self.stream)
         return theta
+
+    def set_surrogate(self, net):
+        """net: a Surrogate (kept alive here while set) or None for plain EPG."""
+        mrstat_set_surrogate(self.h, net.h if net is not None else None)
+        self._surrogate = net
+
+    def fallback_count(self):
+        return mrstat_fallback_count(self.h, self.stream)
+
+
+class Surrogate:
+    """Owns a surrogate network handle plus its workspace tensor."""
+
+    def __init__(self, n_tr, width=256, depth=4, batch=4096):
+        import torch
+        self.torch = torch
+        self.n_tr, self.width, self.depth, self.batch = n_tr, width, depth, batch
+        self.h = mrstat_mlp_create(n_tr, width, depth, batch)
+        self.n_params = mrstat_mlp_param_count(self.h)
+        self.ws_bytes = mrstat_mlp_workspace_bytes(self.h)
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        mrstat_mlp_bind(self.h, self.ws_ptr, self.ws_bytes, self.stream)
+
+    @property
+    def stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def _expect(self, t, dtype, shape=None):
+        T = self.torch
+        if not isinstance(t, T.Tensor) or t.device.type != "cuda" or t.dtype != dtype \
+                or not t.is_contiguous() or (shape is not None and tuple(t.shape) != tuple(shape)):
+            raise ValueError(f"expected contiguous {dtype} {shape} on the GPU")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.torch.cuda.synchronize()
+            mrstat_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_infer_tile(self, voxels):
+        mrstat_mlp_set_infer_tile(self.h, voxels)
+
+    def set_scaling(self, lo, hi, head_scale):
+        mrstat_mlp_set_scaling(self.h, lo, hi, head_scale, self.stream)
+
+    def fit_scaling(self, trains, lo, hi):
+        """trains: float32 [4][n_tr][n] on the GPU. Returns the head scales."""
+        self._expect(trains, self.torch.float32)
+        if trains.dim() != 3 or trains.shape[0] != 4 or trains.shape[1] != self.n_tr:
+            raise ValueError("trains must be [4][n_tr][n]")
+        return mrstat_mlp_fit_scaling(self.h, trains.data_ptr(), trains.shape[2], lo, hi, self.stream)
+
+    def set_params(self, params):
+        self._expect(params, self.torch.float32, (self.n_params,))
+        mrstat_mlp_set_params(self.h, params.data_ptr(), self.stream)
+
+    def get_params(self):
+        out = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.dev)
+        mrstat_mlp_get_params(self.h, out.data_ptr(), self.stream)
+        return out
+
+    def _batch_views(self, theta, trains, col):
+        T = self.torch
+        self._expect(theta, T.float32)
+        self._expect(trains, T.float32)
+        if theta.dim() != 2 or theta.shape[0] < 3 or trains.dim() != 3 or trains.shape[0] != 4 \
+                or trains.shape[1] != self.n_tr:
+            raise ValueError("theta must be [>=3][n], trains [4][n_tr][n]")
+        n_th, n_tr = theta.shape[1], trains.shape[2]
+        if col < 0 or col + self.batch > min(n_th, n_tr):
+            raise ValueError("batch columns out of range")
+        return (theta.data_ptr() + 4 * col, n_th, trains.data_ptr() + 4 * col, n_tr)
+
+    def gradients(self, theta, trains, col=0, want_loss=True):
+        """Loss gradient of the batch at columns [col, col + batch)."""
+        th, ldt, tr, ldr = self._batch_views(theta, trains, col)
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.dev)
+        loss = mrstat_mlp_gradients(self.h, th, ldt, tr, ldr, g.data_ptr(), want_loss, self.stream)
+        return loss, g
+
+    def train_step(self, theta, trains, lr, col=0, want_loss=False):
+        th, ldt, tr, ldr = self._batch_views(theta, trains, col)
+        return mrstat_mlp_train_step(self.h, th, ldt, tr, ldr, lr, want_loss, self.stream)
+
+    def predict(self, theta):
+        T = self.torch
+        self._expect(theta, T.float32)
+        if theta.dim() != 2 or theta.shape[0] < 3:
+            raise ValueError("theta must be [>=3][n]")
+        n = theta.shape[1]
+        out = T.empty((4, self.n_tr, n), dtype=T.float32, device=self.dev)
+        mrstat_mlp_predict(self.h, theta.data_ptr(), n, n, out.data_ptr(), self.stream)
+        return out

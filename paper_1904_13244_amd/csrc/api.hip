@@ -3,6 +3,7 @@
 // signal/residual, J v, Re(J^H w), the inexact Gauss-Newton step and the
 // CGLS proton-density initialisation.
 #include "mrstat.h"
+#include "mlp_internal.h"
 #include "mrstat_internal.h"
 
 #include <cmath>
@@ -19,7 +20,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
     size_t trains, trial_m, upart, W, apart, r, y, vec, red, scal, seq, eytab, extab;
-    size_t cx, csv, cp, cth, total;
+    size_t cx, csv, cp, cth, fb, total;
     int n_red;
     YPlan yp;
 };
@@ -37,6 +38,7 @@ struct mrstat_ctx_s {
     Layout L{};
     mrstat_enc enc = MRSTAT_ENC_FP32;
     int epg_lanes = 0;
+    mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
     // bound device state
     char* ws = nullptr;
     const float2* coil = nullptr;
@@ -66,6 +68,8 @@ struct mrstat_ctx_s {
     const float2* dseq() const { return at<float2>(L.seq); }
     const float2* deytab() const { return at<float2>(L.eytab); }
     const float2* dextab() const { return at<float2>(L.extab); }
+    int* fb_count(int slot) const { return at<int>(L.fb) + slot; }   // 0: linearisation, 1: value
+    int* fb_idx() const { return at<int>(L.fb) + 64; }
 };
 
 namespace {
@@ -146,6 +150,7 @@ Layout make_layout(const Dims& d)
     L.csv = take(nv * sizeof(float2));
     L.cp = take(nv * sizeof(float2));
     L.cth = take(5 * nv * sizeof(float));
+    L.fb = take((64 + nv) * sizeof(int));
     L.total = o;
     return L;
 }
@@ -192,10 +197,32 @@ mrstat_status check_ready(mrstat_ctx ctx)
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // ----------------------------------------------------------- kernel sequences
+// Trains at theta into out ([4][T][nv] with tangents, else the m train
+// [T][nv]): by the EPG, or by the surrogate with the EPG for the voxels
+// outside its box (their count in fb_count(slot)).
+mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, float* out, bool tangents, int slot,
+                            hipStream_t s)
+{
+    const Dims& d = ctx->d;
+    const int kind = tangents ? MRSTAT_K_EPG : MRSTAT_K_EPG_VALUE;
+    if (!ctx->surr) {
+        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes, s)));
+        return MRSTAT_OK;
+    }
+    const int skind = tangents ? MRSTAT_K_SURR : MRSTAT_K_SURR_VALUE;
+    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, s)));
+    HIP_TRY(TRACED(skind, launch_box_compact(d, theta, mlp_box_lo(ctx->surr), mlp_box_hi(ctx->surr),
+                                             ctx->mask, ctx->fb_idx(), ctx->fb_count(slot), s)));
+    HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes,
+                                         ctx->fb_idx(), ctx->fb_count(slot), s)));
+    return MRSTAT_OK;
+}
+
 mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s)
 {
-    HIP_TRY(TRACED(MRSTAT_K_EPG, launch_epg(ctx->d, ctx->st, theta, ctx->dseq(), ctx->trains(), true,
-                                            ctx->epg_lanes, s)));
+    ctx->lin_valid = false;
+    mrstat_status st = simulate_into(ctx, theta, ctx->trains(), true, 0, s);
+    if (st != MRSTAT_OK) return st;
     ctx->lin_valid = true;
     return MRSTAT_OK;
 }
@@ -360,6 +387,32 @@ mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes)
     return MRSTAT_OK;
 }
 
+mrstat_status mrstat_set_surrogate(mrstat_ctx ctx, mrstat_mlp net)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (net) {
+        if (!mlp_ready(net)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "surrogate network has no workspace");
+        if (mlp_n_tr(net) != ctx->d.T)
+            return fail(ctx, MRSTAT_ERR_SHAPE, "surrogate network was built for another number of TRs");
+    }
+    ctx->surr = net;
+    ctx->lin_valid = false;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_fallback_count(mrstat_ctx ctx, int32_t* h_count, mrstat_stream stream)
+{
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!h_count) return fail(ctx, MRSTAT_ERR_ARG, "h_count is NULL");
+    *h_count = 0;
+    if (!ctx->surr || !ctx->lin_valid) return MRSTAT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(h_count, ctx->fb_count(0), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRSTAT_OK;
+}
+
 mrstat_status mrstat_simulate(mrstat_ctx ctx, const float* d_theta, float* d_trains,
                               mrstat_stream stream)
 {
@@ -472,8 +525,11 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s)));
     }
     double hs[16];
+    int32_t nfb = 0;
     HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+    if (ctx->surr) HIP_TRY(hipMemcpyAsync(&nfb, ctx->fb_count(0), sizeof(nfb), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    rep->n_fallback = nfb;
     const double f0 = 0.5 * hs[SC_F0];
     rep->f0 = f0;
     rep->f1 = f0;
@@ -487,8 +543,8 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     for (int k = 0; k < o->n_ls_max; ++k) {
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi,
                                                                o->param_mask, ctx->mask, trial, s)));
-        HIP_TRY(TRACED(MRSTAT_K_EPG_VALUE, launch_epg(d, ctx->st, trial, ctx->dseq(), ctx->trial_m(),
-                                                      false, ctx->epg_lanes, s)));
+        st = simulate_into(ctx, trial, ctx->trial_m(), false, 1, s);
+        if (st != MRSTAT_OK) return st;
         st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
         if (st != MRSTAT_OK) return st;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_pred_dot(d, g, trial, d_theta, ctx->red(), sc + SC_PRED, s)));

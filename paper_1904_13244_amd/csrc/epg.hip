@@ -52,17 +52,30 @@ __device__ __forceinline__ void clear_above(float (&f)[S], int base, int K)
         if (base + i >= K) f[i] = 0.f;
 }
 
-template <int S, int L, bool TANG, bool MASKED>
+// LIST: the group handles voxel idx[vox] for vox < *count (the other voxels'
+// outputs are left untouched); whole blocks past the list exit at once.
+template <int S, int L, bool TANG, bool MASKED, bool LIST>
 __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ theta,
                                                   const float2* __restrict__ seq,
                                                   float* __restrict__ out, int nv, int T,
-                                                  int K, SeqTimes st)
+                                                  int K, SeqTimes st,
+                                                  const int* __restrict__ idx,
+                                                  const int* __restrict__ count)
 {
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int vox = gt / L;
     const int l = gt % L;
-    const bool valid = vox < nv;
-    const int j = valid ? vox : nv - 1;   // keep every lane active for the shuffles
+    int j;
+    bool valid;
+    if constexpr (LIST) {
+        const int cnt = *count;
+        if ((int)(blockIdx.x * blockDim.x / L) >= cnt) return;   // uniform per block
+        valid = vox < cnt;
+        j = idx[valid ? vox : cnt - 1];
+    } else {
+        valid = vox < nv;
+        j = valid ? vox : nv - 1;   // keep every lane active for the shuffles
+    }
     const bool lead = (l == 0), last = (l == L - 1);
     const bool store = valid && lead;
     const int base = l * S;
@@ -198,53 +211,103 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
     }
 }
 
-template <int S, int L, bool TANG>
+template <int S, int L, bool TANG, bool LIST>
 hipError_t launch_sl(const Dims& d, SeqTimes st, const float* theta, const float2* seq, float* out,
-                     hipStream_t s)
+                     const int* idx, const int* count, hipStream_t s)
 {
     const long threads = (long)d.nv * L;
     const int block = 256;
     const int grid = (int)((threads + block - 1) / block);
     if (d.K == S * L)
-        epg_kernel<S, L, TANG, false><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st);
+        epg_kernel<S, L, TANG, false, LIST><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st,
+                                                                   idx, count);
     else
-        epg_kernel<S, L, TANG, true><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st);
+        epg_kernel<S, L, TANG, true, LIST><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st,
+                                                                  idx, count);
     return hipGetLastError();
 }
 
-template <bool TANG>
+template <bool TANG, bool LIST>
 hipError_t launch_any(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      float* out, int lanes, hipStream_t s)
+                      float* out, int lanes, const int* idx, const int* count, hipStream_t s)
 {
     const int K = d.K;
+#define SL(S_, L_) launch_sl<S_, L_, TANG, LIST>(d, st, theta, seq, out, idx, count, s)
     if (K <= 8) {
-        if (lanes == 2) return launch_sl<4, 2, TANG>(d, st, theta, seq, out, s);
-        return launch_sl<8, 1, TANG>(d, st, theta, seq, out, s);
+        if (lanes == 2) return SL(4, 2);
+        return SL(8, 1);
     }
     if (K <= 16) {
-        if (lanes == 1) return launch_sl<16, 1, TANG>(d, st, theta, seq, out, s);
-        if (lanes == 4) return launch_sl<4, 4, TANG>(d, st, theta, seq, out, s);
-        return launch_sl<8, 2, TANG>(d, st, theta, seq, out, s);
+        if (lanes == 1) return SL(16, 1);
+        if (lanes == 4) return SL(4, 4);
+        return SL(8, 2);
     }
     if (K <= 32) {
-        if (lanes == 4) return launch_sl<8, 4, TANG>(d, st, theta, seq, out, s);
-        if (lanes == 8) return launch_sl<4, 8, TANG>(d, st, theta, seq, out, s);
-        return launch_sl<16, 2, TANG>(d, st, theta, seq, out, s);
+        if (lanes == 4) return SL(8, 4);
+        if (lanes == 8) return SL(4, 8);
+        return SL(16, 2);
     }
     if (K <= 64) {
-        if (lanes == 8) return launch_sl<8, 8, TANG>(d, st, theta, seq, out, s);
-        return launch_sl<16, 4, TANG>(d, st, theta, seq, out, s);
+        if (lanes == 8) return SL(8, 8);
+        return SL(16, 4);
     }
+#undef SL
     return hipErrorInvalidValue;
 }
+
+// Appends to idx every voxel (in the mask) whose (ln T1, ln T2, B1) lies
+// outside [lo, hi] or is not finite; *count must be 0 on entry. One atomic per
+// wave; the order of the list is unspecified (each voxel is simulated alone).
+__global__ __launch_bounds__(256) void box_compact_kernel(const float* __restrict__ theta, int nv,
+                                                          float lo0, float lo1, float lo2, float hi0,
+                                                          float hi1, float hi2,
+                                                          const uint8_t* __restrict__ mask,
+                                                          int* __restrict__ idx, int* __restrict__ count)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    bool out = false;
+    if (j < nv && (!mask || mask[j])) {
+        const float a = theta[j], b = theta[nv + j], c = theta[2 * nv + j];
+        const bool in = (a >= lo0 && a <= hi0) && (b >= lo1 && b <= hi1) && (c >= lo2 && c <= hi2);
+        out = !in;   // NaN compares false, so it falls back as well
+    }
+    const uint64_t bal = __ballot(out);
+    if (bal == 0) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __ffsll((unsigned long long)bal) - 1) base = atomicAdd(count, __popcll(bal));
+    base = __shfl(base, __ffsll((unsigned long long)bal) - 1);
+    if (out) idx[base + __popcll(bal & ((1ull << lane) - 1ull))] = j;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
 
 }  // namespace
 
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
                       float* out, bool tangents, int lanes, hipStream_t s)
 {
-    return tangents ? launch_any<true>(d, st, theta, seq, out, lanes, s)
-                    : launch_any<false>(d, st, theta, seq, out, lanes, s);
+    return tangents ? launch_any<true, false>(d, st, theta, seq, out, lanes, nullptr, nullptr, s)
+                    : launch_any<false, false>(d, st, theta, seq, out, lanes, nullptr, nullptr, s);
+}
+
+hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
+                           float* out, bool tangents, int lanes, const int* idx, const int* count,
+                           hipStream_t s)
+{
+    return tangents ? launch_any<true, true>(d, st, theta, seq, out, lanes, idx, count, s)
+                    : launch_any<false, true>(d, st, theta, seq, out, lanes, idx, count, s);
+}
+
+hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo, const float* hi,
+                              const uint8_t* mask, int* idx, int* count, hipStream_t s)
+{
+    zero_int_kernel<<<1, 1, 0, s>>>(count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    box_compact_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(theta, d.nv, lo[0], lo[1], lo[2], hi[0], hi[1],
+                                                           hi[2], mask, idx, count);
+    return hipGetLastError();
 }
 
 }  // namespace mrstat

@@ -1,0 +1,517 @@
+// Surrogate network kernels: a small MLP maps (ln T1, ln T2, B1) to the four
+// trains (m, dm/dlnT1, dm/dlnT2, dm/dB1) over all TRs, trained on EPG output
+// with BF16 operands on the matrix cores and FP32 accumulation, FP32 master
+// weights and Adam.
+//
+// Layout: activations are feature-major, sample-fastest ([features][samples]),
+// so the output layer writes the trains' [train][TR][voxel] layout directly.
+// Output o = c 4T + p T + n (c 0 real, 1 imaginary; p the train; n the TR),
+// scaled by 1 / s_p. Hidden layers use the exact GELU z Phi(z).
+// Parameters (FP32, packed): W1 [width][3], b1, (W [width][width], b) for each
+// further hidden layer, Wout [8T][width], bout.
+#include "mrstat_internal.h"
+#include "mlp_internal.h"
+
+namespace mrstat {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu(float z)
+{
+    return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------------
+// BF16 GEMM C[M][N] = A[M][K] B[K][N] on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation. A is row-major [M][K] (TA false) or stored [K][M] (TA true);
+// B is row-major [K][N] (TB false) or stored [N][K] (TB true). Tiles of
+// 64 x 64, K in chunks of 32 double-buffered in LDS, where A is kept
+// [m][k] and B [n][k] so each lane's 8-element fragment is one 128-bit read.
+// Requirements (checked on the host): K, M (when TA), N (when !TB) and the
+// leading dimensions are multiples of 8; 16-byte aligned bases.
+// ------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 32, KP = 8;
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TM][TK + KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN][TK + KP];
+    __shared__ double rs[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int nchunk = (g.K + TK - 1) / TK;
+
+    uint4 ra, rb;
+    auto load8 = [&](const uint16_t* base, int64_t idx, bool ok) -> uint4 {
+        return ok ? *reinterpret_cast<const uint4*>(base + idx) : make_uint4(0, 0, 0, 0);
+    };
+    auto gload = [&](int kc) {
+        const int k0 = kc * TK;
+        if (!TA) {   // row m = tid/4, k group 8(tid%4)
+            const int r = tid >> 2, kg = (tid & 3) * 8;
+            ra = load8(g.A, (int64_t)(m0 + r) * g.lda + k0 + kg, m0 + r < g.M && k0 + kg < g.K);
+        } else {     // k = tid/8, m group 8(tid%8)
+            const int k = tid >> 3, mg = (tid & 7) * 8;
+            ra = load8(g.A, (int64_t)(k0 + k) * g.lda + m0 + mg, k0 + k < g.K && m0 + mg < g.M);
+        }
+        if (TB) {    // n = tid/4, k group
+            const int r = tid >> 2, kg = (tid & 3) * 8;
+            rb = load8(g.B, (int64_t)(n0 + r) * g.ldb + k0 + kg, n0 + r < g.N && k0 + kg < g.K);
+        } else {     // k = tid/8, n group
+            const int k = tid >> 3, ng = (tid & 7) * 8;
+            rb = load8(g.B, (int64_t)(k0 + k) * g.ldb + n0 + ng, k0 + k < g.K && n0 + ng < g.N);
+        }
+    };
+    auto sstore = [&](int buf) {
+        if (!TA) {
+            const int r = tid >> 2, kg = (tid & 3) * 8;
+            *reinterpret_cast<uint4*>(&As[buf][r][kg]) = ra;
+        } else {
+            const int k = tid >> 3, mg = (tid & 7) * 8;
+            const uint16_t* v = reinterpret_cast<const uint16_t*>(&ra);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[buf][mg + i][k] = v[i];
+        }
+        if (TB) {
+            const int r = tid >> 2, kg = (tid & 3) * 8;
+            *reinterpret_cast<uint4*>(&Bs[buf][r][kg]) = rb;
+        } else {
+            const int k = tid >> 3, ng = (tid & 7) * 8;
+            const uint16_t* v = reinterpret_cast<const uint16_t*>(&rb);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[buf][ng + i][k] = v[i];
+        }
+    };
+
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+    if (nchunk > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    for (int kc = 0; kc < nchunk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nchunk;
+        if (more) gload(kc + 1);
+        uint4 af[2], bf[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            af[a] = *reinterpret_cast<const uint4*>(&As[buf][wm * 32 + a * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            bf[b] = *reinterpret_cast<const uint4*>(&Bs[buf][wn * 32 + b * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, af[a]), __builtin_bit_cast(bf16x8, bf[b]), acc[a][b],
+                    0, 0, 0);
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    double lsum = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm * 32 + a * 16 + 4 * (lane >> 4) + i;
+                const int n = n0 + wn * 32 + b * 16 + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[a][b][i];
+                const int64_t o = (int64_t)m * g.ldo + n;
+                if constexpr (EPI == EPI_STORE_F32) {
+                    g.Cf[o] = v;
+                } else if constexpr (EPI == EPI_BIAS_GELU) {
+                    const float z = v + g.bias[m];
+                    if (g.Zb) g.Zb[o] = to_bf16(z);
+                    g.Hb[o] = to_bf16(gelu(z));
+                } else if constexpr (EPI == EPI_OUT_LOSS) {
+                    const float y = v + g.bias[m];
+                    const int T = g.T, c = m / (4 * T), p = (m % (4 * T)) / T, nt = m % T;
+                    const float t = c ? g.target[((int64_t)p * T + nt) * g.ld_t + n] / g.head_scale[p] : 0.f;
+                    const float d = y - t;
+                    g.Hb[o] = to_bf16(g.grad_scale * d);
+                    lsum += (double)d * (double)d;
+                } else if constexpr (EPI == EPI_GELU_BWD) {
+                    g.Hb[o] = to_bf16(v * gelu_grad(from_bf16(g.Zin[o])));
+                } else {   // EPI_INFER: rows are the imaginary outputs of trains p = m / T
+                    const float y = v + g.bias[m];
+                    const int p = m / g.T, nt = m % g.T;
+                    g.Cf[(int64_t)p * g.plane + (int64_t)nt * g.ldo + n] = y * g.head_scale[p];
+                }
+            }
+    if constexpr (EPI == EPI_OUT_LOSS) {
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+        if (lane == 0) rs[wave] = lsum;
+        __syncthreads();
+        if (tid == 0) g.loss_part[blockIdx.y * gridDim.x + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    }
+}
+
+// First layer (3 inputs): x normalised onto [-1, 1] over the box, z = W1 x + b1.
+// x_in rows (ln T1, ln T2, B1) with leading dimension ldx; out [width][ldo].
+// blockIdx.y selects a group of 32 units.
+__global__ void layer1_fwd_kernel(const float* __restrict__ x_in, int64_t ldx, int n,
+                                  const float* __restrict__ W1, const float* __restrict__ b1,
+                                  int width, float lo0, float lo1, float lo2, float hi0, float hi1,
+                                  float hi2, float* __restrict__ xs, uint16_t* __restrict__ Zb,
+                                  uint16_t* __restrict__ Hb, int64_t ldo)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float x0 = 2.f * (x_in[s] - lo0) / (hi0 - lo0) - 1.f;
+    const float x1 = 2.f * (x_in[ldx + s] - lo1) / (hi1 - lo1) - 1.f;
+    const float x2 = 2.f * (x_in[2 * ldx + s] - lo2) / (hi2 - lo2) - 1.f;
+    if (xs && blockIdx.y == 0) {
+        xs[s] = x0;
+        xs[ldo + s] = x1;
+        xs[2 * ldo + s] = x2;
+    }
+    const int o_end = min(width, (int)(blockIdx.y + 1) * 32);
+    for (int o = blockIdx.y * 32; o < o_end; ++o) {
+        const float z = fmaf(W1[3 * o], x0, fmaf(W1[3 * o + 1], x1, fmaf(W1[3 * o + 2], x2, b1[o])));
+        if (Zb) Zb[(int64_t)o * ldo + s] = to_bf16(z);
+        Hb[(int64_t)o * ldo + s] = to_bf16(gelu(z));
+    }
+}
+
+// Row sums of a bf16 [rows][n] matrix (bias gradients), one block per row,
+// fixed-order reduction.
+__global__ __launch_bounds__(256) void rowsum_kernel(const uint16_t* __restrict__ X, int64_t ld, int n,
+                                                     float* __restrict__ out)
+{
+    __shared__ float sh[256];
+    const int r = blockIdx.x;
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) s += from_bf16(X[(int64_t)r * ld + i]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = sh[0];
+}
+
+// dW1[o][i] = sum_s dZ1[o][s] x[i][s]: one block per output row.
+__global__ __launch_bounds__(256) void layer1_wgrad_kernel(const uint16_t* __restrict__ dZ,
+                                                           const float* __restrict__ xs, int64_t ld,
+                                                           int n, float* __restrict__ dW1)
+{
+    __shared__ float sh[3][256];
+    const int o = blockIdx.x;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int s = threadIdx.x; s < n; s += 256) {
+        const float d = from_bf16(dZ[(int64_t)o * ld + s]);
+        a0 = fmaf(d, xs[s], a0);
+        a1 = fmaf(d, xs[ld + s], a1);
+        a2 = fmaf(d, xs[2 * ld + s], a2);
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    sh[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) dW1[3 * o + q] = sh[q][0];
+}
+
+// Adam on FP32 master weights; refreshes the BF16 copy.
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ gr, uint16_t* __restrict__ wb, size_t n,
+                            float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = gr[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
+}
+
+__device__ __forceinline__ uint32_t pack2(float a, float b)
+{
+    return (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
+}
+
+// ------------------------------------------------------------------------
+// Fused inference: one workgroup (4 waves) evaluates the whole network for
+// NV voxels (32 or 64). The first layer runs in FP32; each hidden layer is a
+// 16x16x32 BF16 MFMA product with the weights read from L2 and the
+// activations ping-ponged between two LDS buffers laid out [voxel][unit]
+// (16-byte pad per row); the output layer keeps the last activations of all
+// NV voxels in registers as A fragments and streams its output rows (weights
+// from L2), 16 outputs per step, each wave taking every fourth 16-row tile
+// (with PF, the next tile's weights are loaded while the current one is
+// multiplied). Results (bias added, head scale applied) go straight to the
+// train layout out[p][n][voxel] as 16-byte stores of 4 consecutive voxels.
+// Same roundings as the training forward pass: pre-activations in FP32,
+// activations in BF16.
+// ------------------------------------------------------------------------
+template <int WIDTH, int NV, bool PF>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
+{
+    constexpr int HP = WIDTH + 8, KS = WIDTH / 32, MT = WIDTH / 64, VT = NV / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[2][NV][HP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j0 = blockIdx.x * NV;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
+
+    // Layer 1 (3 inputs): thread -> voxel tid % NV, groups of 8 units.
+    {
+        constexpr int GS = 256 / NV;   // threads per voxel
+        const int v = tid % NV, g0 = tid / NV;
+        const int j = min(j0 + v, a.n - 1);
+        const float x0 = 2.f * (a.theta[j] - a.lo[0]) / (a.hi[0] - a.lo[0]) - 1.f;
+        const float x1 = 2.f * (a.theta[a.ldth + j] - a.lo[1]) / (a.hi[1] - a.lo[1]) - 1.f;
+        const float x2 = 2.f * (a.theta[2 * a.ldth + j] - a.lo[2]) / (a.hi[2] - a.lo[2]) - 1.f;
+        for (int g = g0; g < WIDTH / 8; g += GS) {
+            float h[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int u = 8 * g + q;
+                const float z = fmaf(a.W1[3 * u], x0, fmaf(a.W1[3 * u + 1], x1, fmaf(a.W1[3 * u + 2], x2, a.b1[u])));
+                h[q] = gelu(z);
+            }
+            *reinterpret_cast<uint4*>(&Hs[0][v][8 * g]) =
+                make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
+        }
+    }
+    __syncthreads();
+
+    // Hidden layers: wave w computes units [w WIDTH/4, (w+1) WIDTH/4) of all NV voxels.
+    int cur = 0;
+    for (int l = 0; l < a.n_hidden; ++l) {
+        const uint16_t* __restrict__ W = a.Wh[l];
+        const float* __restrict__ bias = a.bh[l];
+        f4 acc[MT][VT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < VT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ks = 0; ks < KS; ++ks) {
+            uint4 af[MT], bf[VT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                af[m] = *reinterpret_cast<const uint4*>(W + (size_t)(wave * (WIDTH / 4) + m * 16 + lr) * WIDTH +
+                                                        ks * 32 + lk);
+#pragma unroll
+            for (int t = 0; t < VT; ++t)
+                bf[t] = *reinterpret_cast<const uint4*>(&Hs[cur][t * 16 + lr][ks * 32 + lk]);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < VT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, af[m]), __builtin_bit_cast(bf16x8, bf[t]), acc[m][t], 0, 0, 0);
+        }
+        const int nxt = cur ^ 1;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int u0 = wave * (WIDTH / 4) + m * 16 + 4 * (lane >> 4);
+            const float c0 = bias[u0], c1 = bias[u0 + 1], c2 = bias[u0 + 2], c3 = bias[u0 + 3];
+#pragma unroll
+            for (int t = 0; t < VT; ++t) {
+                const f4 z = acc[m][t];
+                *reinterpret_cast<uint2*>(&Hs[nxt][t * 16 + lr][u0]) =
+                    make_uint2(pack2(gelu(z[0] + c0), gelu(z[1] + c1)), pack2(gelu(z[2] + c2), gelu(z[3] + c3)));
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+
+    // Output layer: A = activations^T (voxel rows) in registers.
+    uint4 hf[VT][KS];
+#pragma unroll
+    for (int t = 0; t < VT; ++t)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            hf[t][ks] = *reinterpret_cast<const uint4*>(&Hs[cur][t * 16 + lr][ks * 32 + lk]);
+
+    const int n_tiles = (a.m_out + 15) / 16;
+    const bool vec_ok = (a.ld_out % 4) == 0;
+    // Weights of output tile `tile` (clamped: a tile past the end reloads
+    // the last one, which is never stored).
+    auto load_b = [&](uint4 (&b)[KS], int tile) {
+        const int o = min(min(tile, n_tiles - 1) * 16 + lr, a.m_out - 1);
+        const uint16_t* src = a.Wout + (size_t)o * WIDTH + lk;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = *reinterpret_cast<const uint4*>(src + ks * 32);
+    };
+    auto tile_out = [&](const uint4 (&b)[KS], int tile) {
+        f4 acc[VT];
+#pragma unroll
+        for (int t = 0; t < VT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int t = 0; t < VT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, hf[t][ks]), __builtin_bit_cast(bf16x8, b[ks]), acc[t], 0, 0, 0);
+        const int o = tile * 16 + lr;
+        if (o < a.m_out) {
+            const int p = o / a.T, nt = o - p * a.T;
+            const float bias = a.bout[o], sc = a.head_scale[p];
+            float* dst = a.out + (size_t)p * a.plane + (size_t)nt * a.ld_out;
+#pragma unroll
+            for (int t = 0; t < VT; ++t) {
+                const int jv = j0 + t * 16 + 4 * (lane >> 4);
+                const float y0 = (acc[t][0] + bias) * sc, y1 = (acc[t][1] + bias) * sc;
+                const float y2 = (acc[t][2] + bias) * sc, y3 = (acc[t][3] + bias) * sc;
+                // Written once and read by a later kernel: streamed past the
+                // caches so the output weights stay resident in L2.
+                if (vec_ok && jv + 3 < a.n) {
+                    __builtin_nontemporal_store(f4{y0, y1, y2, y3}, reinterpret_cast<f4*>(dst + jv));
+                } else {
+                    if (jv < a.n) __builtin_nontemporal_store(y0, dst + jv);
+                    if (jv + 1 < a.n) __builtin_nontemporal_store(y1, dst + jv + 1);
+                    if (jv + 2 < a.n) __builtin_nontemporal_store(y2, dst + jv + 2);
+                    if (jv + 3 < a.n) __builtin_nontemporal_store(y3, dst + jv + 3);
+                }
+            }
+        }
+    };
+    if constexpr (PF) {
+        uint4 b0[KS], b1[KS];
+        load_b(b0, wave);
+        for (int tile = wave; tile < n_tiles; tile += 8) {
+            load_b(b1, tile + 4);
+            tile_out(b0, tile);
+            if (tile + 4 >= n_tiles) break;
+            load_b(b0, tile + 8);
+            tile_out(b1, tile + 4);
+        }
+    } else {
+        uint4 b0[KS];
+        for (int tile = wave; tile < n_tiles; tile += 4) {
+            load_b(b0, tile);
+            tile_out(b0, tile);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(bool ta, bool tb, int epi, const GemmArgs& g, hipStream_t s)
+{
+    dim3 grid(ceil_div(g.N, TN), ceil_div(g.M, TM));
+#define GEMM_CASE(TA_, TB_, E_)                                                  \
+    if (ta == TA_ && tb == TB_ && epi == E_) {                                   \
+        gemm_bf16_kernel<TA_, TB_, E_><<<grid, 256, 0, s>>>(g);                  \
+        return hipGetLastError();                                                \
+    }
+    GEMM_CASE(false, false, EPI_BIAS_GELU)
+    GEMM_CASE(false, false, EPI_OUT_LOSS)
+    GEMM_CASE(false, false, EPI_INFER)
+    GEMM_CASE(false, true, EPI_STORE_F32)
+    GEMM_CASE(true, false, EPI_GELU_BWD)
+#undef GEMM_CASE
+    return hipErrorInvalidValue;
+}
+
+int gemm_tiles(int M, int N) { return ceil_div(N, TN) * ceil_div(M, TM); }
+
+hipError_t launch_layer1_fwd(const float* x_in, int64_t ldx, int n, const float* W1,
+                             const float* b1, int width, const float* lo, const float* hi,
+                             float* xs, uint16_t* Zb, uint16_t* Hb, int64_t ldo, hipStream_t s)
+{
+    layer1_fwd_kernel<<<dim3(ceil_div(n, 256), ceil_div(width, 32)), 256, 0, s>>>(x_in, ldx, n, W1, b1, width, lo[0], lo[1], lo[2],
+                                                       hi[0], hi[1], hi[2], xs, Zb, Hb, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowsum_bf16(const uint16_t* X, int64_t ld, int rows, int n, float* out,
+                              hipStream_t s)
+{
+    rowsum_kernel<<<rows, 256, 0, s>>>(X, ld, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer1_wgrad(const uint16_t* dZ, const float* xs, int64_t ld, int width, int n,
+                               float* dW1, hipStream_t s)
+{
+    layer1_wgrad_kernel<<<width, 256, 0, s>>>(dZ, xs, ld, n, dW1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, uint16_t* wb, size_t n,
+                       float lr, int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    adam_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, m, v, g, wb, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+bool infer_fused_supported(int width, int depth) { return (width == 64 || width == 128 || width == 256) && depth - 1 <= MAX_HIDDEN; }
+
+hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s)
+{
+    if (tile == 0) tile = 64;
+    const int grid = ceil_div(a.n, tile);
+#define INFER(W_, NV_, PF_)                                                  \
+    if (width == W_ && tile == NV_) {                                        \
+        mlp_infer_kernel<W_, NV_, PF_><<<grid, 256, 0, s>>>(a);              \
+        return hipGetLastError();                                            \
+    }
+    INFER(64, 64, true)
+    INFER(64, 32, true)
+    INFER(128, 64, true)
+    INFER(128, 32, true)
+    INFER(256, 64, false)
+    INFER(256, 32, true)
+#undef INFER
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s)
+{
+    to_bf16_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace mrstat

@@ -46,6 +46,17 @@ YPlan make_yplan(const Dims& d);
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
                       float* out, bool tangents, int lanes, hipStream_t s);
 
+// EPG on the voxels idx[0 .. *count) only (same output layout; other voxels
+// untouched). The grid covers nv voxels; blocks past the list exit at once.
+hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
+                           float* out, bool tangents, int lanes, const int* idx, const int* count,
+                           hipStream_t s);
+
+// Clears *count, then lists the voxels (in the mask) whose ln T1, ln T2, B1
+// lie outside [lo, hi] (host arrays of 3) or are not finite.
+hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo, const float* hi,
+                              const uint8_t* mask, int* idx, int* count, hipStream_t s);
+
 // Forward y-stage: U[c][n][ix] = sum over rows iy of Ey[n][iy] * coil_c[j] *
 // x[n][j], with x = i rho m (mode 0) or x = i (rho sum_q v_q dm_q +
 // (v3 + i v4) m) (mode 1, the J v direction). upart holds nby row-block

@@ -268,5 +268,37 @@ def config(idx: int) -> Workload:
     raise ValueError(idx)
 
 
+# Surrogate network: training box for (T1 [s], T2 [s], B1) and initialisation.
+SURR_BOX_T1 = (0.1, 5.0)
+SURR_BOX_T2 = (0.01, 2.0)
+SURR_BOX_B1 = (0.7, 1.3)
+SURR_LO = (float(np.log(SURR_BOX_T1[0])), float(np.log(SURR_BOX_T2[0])), SURR_BOX_B1[0])
+SURR_HI = (float(np.log(SURR_BOX_T1[1])), float(np.log(SURR_BOX_T2[1])), SURR_BOX_B1[1])
+
+
+def surrogate_samples(n, seed=SEED_SURR):
+    """Training inputs: T1 and T2 log-uniform, B1 uniform over the box.
+    Returns theta rows (ln T1, ln T2, B1) as [3][n]."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(SURR_LO[0], SURR_HI[0], n), rng.uniform(SURR_LO[1], SURR_HI[1], n),
+                     rng.uniform(SURR_LO[2], SURR_HI[2], n)])
+
+
+def mlp_init_params(n_tr, width=256, depth=4, seed=SEED_MLP):
+    """Uniform Glorot-style weights, zero biases, packed as W1 [width][3], b1,
+    (W [width][width], b) per further hidden layer, Wout [8 n_tr][width], bout."""
+    rng = np.random.default_rng(seed)
+    shapes = [(width, 3), (width,)] + [(width, width), (width,)] * (depth - 1) + \
+        [(8 * n_tr, width), (8 * n_tr,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 2:
+            lim = np.sqrt(6.0 / (s[0] + s[1]))
+            parts.append(rng.uniform(-lim, lim, size=s).reshape(-1))
+        else:
+            parts.append(np.zeros(s[0]))
+    return np.concatenate(parts)
+
+
 def shrink(prob: Problem, **kw) -> Problem:
     return replace(prob, **kw)

@@ -1,0 +1,110 @@
+"""Training of the learned surrogate on the GPU, end to end through the C ABI.
+
+Data: (ln T1, ln T2, B1) drawn over the training box (T1, T2 log-uniform, B1
+uniform), their EPG trains simulated by the library itself (mrstat_simulate on
+a data-generation context with the same sequence), kept resident in HBM in
+chunks of `chunk` samples. Scaling: head scale s_p = RMS of train p over the
+first chunk (mrstat_mlp_fit_scaling). Optimisation: Adam on mini-batches
+(mrstat_mlp_train_step), learning rate on a cosine schedule from lr to lr_min,
+batches visited in a seeded random order each epoch. Validation: relative
+error of the predicted trains on a held-out chunk, per train.
+
+Host code here only draws inputs and sequences calls; every step of the
+simulation, the network and the optimiser runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+from .binding import Context, Surrogate
+
+
+@dataclass
+class TrainReport:
+    n_samples: int
+    steps: int
+    seconds_data: float
+    seconds_train: float
+    head_scale: list
+    loss_first: float
+    loss_last: float
+    val_rel_err: list = field(default_factory=list)   # per train, held-out chunk
+
+
+def data_problem(prob: I.Problem, chunk: int) -> I.Problem:
+    """A context shaped for simulating `chunk` voxels with prob's sequence
+    (grid 256 x chunk/256; encoding tables stay small)."""
+    nx = 256 if chunk % 256 == 0 else chunk
+    return I.shrink(prob, nx=nx, ny=chunk // nx, n_read=nx, n_coils=1,
+                    ky_line=np.zeros(prob.n_tr, dtype=np.int32))
+
+
+def make_dataset(torch, prob, n_chunks, chunk, seed):
+    """EPG trains of n_chunks * chunk box samples: lists of theta [5][chunk]
+    and trains [4][T][chunk] device tensors."""
+    dp = data_problem(prob, chunk)
+    ctx = Context(dp)
+    thetas, trains = [], []
+    for c in range(n_chunks):
+        th = np.zeros((5, chunk), dtype=np.float32)
+        th[:3] = I.surrogate_samples(chunk, seed=seed + 1000 * c)
+        th[3] = 1.0
+        th_d = torch.from_numpy(th).cuda()
+        thetas.append(th_d)
+        trains.append(ctx.simulate(th_d))
+    torch.cuda.synchronize()
+    ctx.close()
+    return thetas, trains
+
+
+def train_surrogate(torch, prob: I.Problem, n_samples=2_000_000, width=256, depth=4, batch=4096,
+                    epochs=8, lr=1e-3, lr_min=1e-5, chunk=65536, seed=I.SEED_SURR,
+                    log=None) -> tuple[Surrogate, TrainReport]:
+    if chunk % batch:
+        raise ValueError("chunk must be a multiple of batch")
+    n_chunks = max(1, math.ceil(n_samples / chunk))
+    t0 = time.perf_counter()
+    thetas, trains = make_dataset(torch, prob, n_chunks + 1, chunk, seed)
+    val_th, val_tr = thetas.pop(), trains.pop()
+    t_data = time.perf_counter() - t0
+
+    net = Surrogate(prob.n_tr, width, depth, batch)
+    scales = net.fit_scaling(trains[0], I.SURR_LO, I.SURR_HI)
+    net.set_params(torch.from_numpy(I.mlp_init_params(prob.n_tr, width, depth).astype(np.float32))
+                   .cuda())
+    per_chunk = chunk // batch
+    total = epochs * n_chunks * per_chunk
+    rng = np.random.default_rng(seed + 7)
+    step = 0
+    loss_first = loss_last = float("nan")
+    t1 = time.perf_counter()
+    for ep in range(epochs):
+        order = rng.permutation(n_chunks * per_chunk)
+        for b in order:
+            c, k = divmod(int(b), per_chunk)
+            a = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * step / max(1, total - 1)))
+            want = step == 0 or step == total - 1 or (log is not None and step % 500 == 0)
+            loss = net.train_step(thetas[c], trains[c], a, col=k * batch, want_loss=want)
+            if step == 0:
+                loss_first = loss
+            if want:
+                loss_last = loss
+                if log is not None:
+                    log(f"step {step}/{total} epoch {ep} lr {a:.2e} loss {loss:.4e}")
+            step += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+
+    pred = net.predict(val_th[:3].contiguous())
+    err = []
+    for p in range(4):
+        err.append(float(torch.linalg.vector_norm(pred[p] - val_tr[p]) /
+                         torch.linalg.vector_norm(val_tr[p])))
+    del thetas, trains, val_th, val_tr, pred
+    rep = TrainReport(n_chunks * chunk, total, t_data, t_train, scales, loss_first, loss_last, err)
+    return net, rep

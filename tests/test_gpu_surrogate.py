@@ -1,0 +1,189 @@
+"""The learned surrogate inside the hot path (through the C ABI).
+
+With a surrogate set, a context's linearisation takes the network's trains
+for voxels inside its box and the EPG's for the others. Expected values come
+from the oracle: the FP64 network (oracle/mlp.py, same BF16-rounded weights)
+for in-box voxels, the FP64 EPG for out-of-box ones, and the oracle's
+separable signal and Jacobian products applied to those composed trains.
+Tolerances: 1e-5 normwise where the EPG decides (the plain path's bar),
+2e-2 where the network does (its BF16 activations; derivation in
+tests/test_gpu_mlp.py).
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1904_13244_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_13244_amd import binding
+    binding.lib()
+    return torch
+
+
+def _dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _bf16(x):
+    u = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _in_box(th):
+    lo, hi = np.array(I.SURR_LO, np.float32), np.array(I.SURR_HI, np.float32)
+    t = th[:3].astype(np.float32)
+    return np.all((t >= lo[:, None]) & (t <= hi[:, None]), axis=0)
+
+
+@pytest.fixture(scope="module")
+def setup(torch_gpu, oracle_lib):
+    torch = torch_gpu
+    from oracle import mlp as M
+    from paper_1904_13244_amd.binding import Context, Surrogate
+    rng = np.random.default_rng(61)
+    n_tr, width, depth, batch = 64, 64, 2, 128
+    prob = I.make_problem(24, 20, n_tr, 32, 16, flip_deg=I.flips_sin2_sweeps(n_tr, 20))
+    nv = prob.nv
+    th = I.iid_maps(nv, seed=62, b1=rng.uniform(0.8, 1.2, nv))
+    # About one voxel in six leaves the box, in each of the three inputs.
+    out = rng.choice(nv, nv // 6, replace=False)
+    for k, j in enumerate(out):
+        q = k % 3
+        th[q, j] = [np.log(6.5), np.log(0.006), 1.45][q]
+    mask = (rng.uniform(size=nv) > 0.15).astype(np.uint8)
+    th = th.astype(np.float32).astype(np.float64)
+
+    flat = I.mlp_init_params(n_tr, width, depth, seed=63).astype(np.float32)
+    scale = np.array([0.2, 0.15, 0.05, 0.3], dtype=np.float32)
+    net = Surrogate(n_tr, width, depth, batch)
+    net.set_scaling(I.SURR_LO, I.SURR_HI, scale)
+    net.set_params(torch.from_numpy(flat).cuda())
+    ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
+    ctx.set_surrogate(net)
+
+    # Oracle trains: the FP64 network inside the box (and for masked-out
+    # voxels, whose trains nothing reads), the FP64 EPG for the fallbacks.
+    parts = M.unpack(flat.astype(np.float64), n_tr, width, depth)
+    for l in range(1, depth + 1):
+        parts[2 * l] = _bf16(parts[2 * l])
+    w_ora = np.concatenate([p.reshape(-1) for p in parts])
+    x = M.normalise_inputs(th[:3], I.SURR_LO, I.SURR_HI)
+    y, _ = M.forward(w_ora, x, n_tr, width, depth)
+    net_tr = y[4 * n_tr:].reshape(4, n_tr, nv) * scale.astype(np.float64)[:, None, None]
+    fb = (~_in_box(th)) & (mask != 0)
+    epg = oracle_lib.epg(prob, th).imag
+    ref = np.where(fb[None, None, :], epg, net_tr)
+    yield dict(torch=torch, prob=prob, th=th, mask=mask, ctx=ctx, net=net, ref=ref, fb=fb)
+    ctx.close()
+    net.close()
+
+
+def test_trains_route_out_of_box_voxels_to_the_epg(setup):
+    torch, ctx, th, ref, fb = (setup[k] for k in ("torch", "ctx", "th", "ref", "fb"))
+    got = ctx.simulate(_dev(torch, th, torch.float32)).cpu().numpy().astype(np.float64)
+    n = ctx.fallback_count()
+    print(f"\n[surrogate] fallback voxels {n} (host count {int(fb.sum())})", flush=True)
+    assert n == int(fb.sum()) and n > 0
+    for p in range(4):
+        e_fb = _rel(got[p][:, fb], ref[p][:, fb])
+        e_in = _rel(got[p][:, ~fb], ref[p][:, ~fb])
+        print(f"  train {p}: EPG fallback rel {e_fb:.2e}, network rel {e_in:.2e}", flush=True)
+        assert e_fb <= 1e-5
+        assert e_in <= 2e-2
+
+
+def test_products_on_surrogate_trains(setup, oracle_lib):
+    torch, ctx, prob, th, ref, mask = (setup[k] for k in ("torch", "ctx", "prob", "th", "ref", "mask"))
+    v, w = I.probe_vectors(prob)
+    trains = ref.astype(np.complex128) * 1j
+    thd = _dev(torch, th, torch.float32)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32)).cpu().numpy().astype(np.complex128)
+    jv_ref = oracle_lib.jv(prob, th, trains, v, mask=mask)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    jhw_ref = oracle_lib.jhw(prob, th, trains, w, mask=mask)
+    d = oracle_lib.signal(prob, th, oracle_lib.epg(prob, th), mask=mask)
+    _, r = ctx.residual(thd, _dev(torch, d, torch.complex64), reuse=True)
+    r_ref = d - oracle_lib.signal(prob, th, trains, mask=mask)
+    e = (_rel(jv, jv_ref), _rel(jhw, jhw_ref),
+         float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(d)))
+    print(f"\n[surrogate products] jv {e[0]:.2e} jhw {e[1]:.2e} residual/||d|| {e[2]:.2e}", flush=True)
+    assert max(e) <= 2e-2
+
+
+def test_gn_step_reports_fallbacks(setup):
+    torch, ctx, prob, th, fb = (setup[k] for k in ("torch", "ctx", "prob", "th", "fb"))
+    d = np.zeros(prob.data_shape, dtype=np.complex64)
+    d[0, :, 3] = 1.0
+    thd = _dev(torch, th, torch.float32)
+    rep = ctx.gn_step(thd, _dev(torch, d, torch.complex64), 3, 0b11111, I.GN_LO, I.GN_HI)
+    assert rep.n_fallback == int(fb.sum())
+    assert np.isfinite(rep.f0) and rep.cg_iters >= 1
+
+
+def test_no_surrogate_means_no_fallback(setup):
+    torch, ctx, th = setup["torch"], setup["ctx"], setup["th"]
+    ctx.set_surrogate(None)
+    try:
+        ctx.linearise(_dev(torch, th, torch.float32))
+        assert ctx.fallback_count() == 0
+    finally:
+        ctx.set_surrogate(setup["net"])
+
+
+def test_surrogate_shape_mismatch_rejected(setup):
+    from paper_1904_13244_amd import binding as B
+    other = B.Surrogate(8, 64, 1, 64)
+    try:
+        with pytest.raises(B.MrstatError) as e:
+            setup["ctx"].set_surrogate(other)
+        assert e.value.status == B.ERR_SHAPE
+    finally:
+        other.close()
+
+
+def test_linearisation_time_surrogate_vs_epg_full_size(torch_gpu):
+    """At 224 x 224 voxels and 1120 TRs the surrogate's linearisation (all
+    four trains of every voxel, inside the box) takes a fraction of the EPG's.
+    Timed with the library's kernel tracing."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context, Surrogate
+    w = I.config(3)
+    prob = w.problem
+    th = np.asarray(w.theta, dtype=np.float32).copy()
+    lo, hi = np.array(I.SURR_LO), np.array(I.SURR_HI)
+    th[:3] = np.clip(th[:3], lo[:, None] + 1e-3, hi[:, None] - 1e-3)
+    net = Surrogate(prob.n_tr, 256, 4, 4096)
+    net.set_scaling(I.SURR_LO, I.SURR_HI, [0.1, 0.1, 0.05, 0.2])
+    net.set_params(torch.from_numpy(I.mlp_init_params(prob.n_tr).astype(np.float32)).cuda())
+    ctx = Context(prob)
+    thd = _dev(torch, th, torch.float32)
+    times = {}
+    for name, sur in (("epg", None), ("surrogate", net)):
+        ctx.set_surrogate(sur)
+        ctx.linearise(thd)
+        ctx.profile(True)
+        for _ in range(3):
+            ctx.linearise(thd)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        times[name] = sum(ms for k, (n, ms) in prof.items()) / 3
+    print(f"\n[linearise 224x224x1120] EPG {times['epg']:.3f} ms, surrogate {times['surrogate']:.3f} ms "
+          f"({times['epg'] / times['surrogate']:.1f}x)", flush=True)
+    assert ctx.fallback_count() == 0
+    assert times["surrogate"] < times["epg"] / 3
+    ctx.close()
+    net.close()

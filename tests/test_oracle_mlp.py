@@ -1,0 +1,57 @@
+"""Pins of the FP64 surrogate-network reference: the GELU against its
+definition and known values, its derivative and the packed gradient against
+central finite differences."""
+import math
+
+import numpy as np
+
+from paper_1904_13244_amd import inputs as I
+
+
+def test_gelu_values_and_derivative():
+    from oracle import mlp
+    # z * Phi(z): Phi(0) = 1/2, Phi(1) = 0.8413447460685429, Phi(-1) = 1 - Phi(1).
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.8413447460685429) <= 1e-15
+    assert abs(mlp.gelu(np.array([-1.0]))[0] + (1 - 0.8413447460685429)) <= 1e-15
+    assert abs(mlp.gelu(np.array([9.0]))[0] - 9.0) <= 1e-12
+    z = np.linspace(-4, 4, 81)
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.abs(fd - mlp.gelu_grad(z)).max() <= 1e-9
+
+
+def test_gradient_matches_finite_differences():
+    from oracle import mlp
+    T, width, depth = 3, 6, 3
+    flat = I.mlp_init_params(T, width, depth, seed=7) + 0.01
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (3, 5))
+    tgt = rng.standard_normal((8 * T, 5))
+    loss, g = mlp.loss_and_grad(flat, x, tgt, T, width, depth)
+    assert g.shape == flat.shape == (mlp.n_params(T, width, depth),)
+    h = 1e-6
+    fd = np.empty_like(flat)
+    for i in range(flat.size):
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h
+        fm[i] -= h
+        fd[i] = (mlp.loss_and_grad(fp, x, tgt, T, width, depth)[0] -
+                 mlp.loss_and_grad(fm, x, tgt, T, width, depth)[0]) / (2 * h)
+    assert np.linalg.norm(fd - g) <= 1e-7 * np.linalg.norm(g)
+
+
+def test_loss_zero_at_own_output_and_target_layout():
+    from oracle import mlp
+    T = 4
+    flat = I.mlp_init_params(T, 8, 2, seed=1)
+    x = np.random.default_rng(0).uniform(-1, 1, (3, 7))
+    y, _ = mlp.forward(flat, x, T, 8, 2)
+    loss, g = mlp.loss_and_grad(flat, x, y, T, 8, 2)
+    assert loss == 0.0 and np.abs(g).max() == 0.0
+    tr = np.arange(4 * T * 2, dtype=float).reshape(4, T, 2)
+    t = mlp.scaled_targets(tr, [1.0, 2.0, 4.0, 8.0])
+    assert np.all(t[:4 * T] == 0.0)
+    assert t[4 * T + 2 * T + 1, 1] == tr[2, 1, 1] / 4.0
+    xs = mlp.normalise_inputs(np.array([[math.log(0.1)], [math.log(2.0)], [1.0]]), I.SURR_LO, I.SURR_HI)
+    assert np.allclose(xs[:, 0], [-1.0, 1.0, 0.0])

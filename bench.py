@@ -6,14 +6,23 @@ Workload: 224x224 brain-like phantom (B1 in [0.8, 1.2]), 1120 TRs
 448 readout samples per TR (2x oversampled), K = 32 EPG states, one coil.
 
 Step: one inexact Gauss-Newton iteration through the C ABI (mrstat_gn_step):
-EPG linearisation with tangents, residual and objective, gradient
-g = Re(J^H r), n_cg = 20 CG iterations (each one J v + one J^H w pair with
-FP64 reductions) and one line-search trial (value-only EPG + residual).
-Metric: J v + J^H w pairs per second, GN-amortised (n_cg pairs per step).
+linearisation (trains and their derivatives), residual and objective,
+gradient g = Re(J^H r), n_cg = 20 CG iterations (each one J v + one J^H w
+pair with FP64 reductions) and one line-search trial (value-only trains +
+residual). Metric: J v + J^H w pairs per second, GN-amortised (n_cg pairs per
+step), for two forms on the same workload and starting point:
+  - surrogate + split-BF16 (the reported value): the learned network gives
+    the trains (BF16 MFMA, EPG fallback outside its box, iterates projected
+    onto that box), stored in FP16; the encoding contraction runs in
+    split-BF16 on MFMA;
+  - plain FP32: EPG trains, FP32 MFMA encoding contraction.
+The network is trained first, untimed, on 2M EPG samples the library
+simulates itself.
 
 The JSON line also reports, for the dominant kernel, its roofline from HIP
-events taken live over the timed region, and the FP64 CPU oracle timed on a
-bounded sample of the same workload on this host.
+events taken live over the timed region, the surrogate inference kernel's
+roofline, and the FP64 CPU oracle timed on a bounded sample of the same
+workload on this host.
 """
 from __future__ import annotations
 
@@ -30,24 +39,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Jv+Jᴴw pairs/s at 224², 1120 TRs: surrogate+split-BF16 vs plain FP32"
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0    # dense
 FP32_VALU_PEAK_TFLOPS = 157.3     # published vector peak (packed); see the design doc
 
 # Algorithmic work per launch (the design doc derives each figure).
 EPG_FLOP_PER_STATE_TR = 67        # value 13 + ln T1 15 + ln T2 17 + B1 22 (real form)
 
 
-def algorithmic(kind, prob):
-    """(unit, amount per launch, bound) for a kernel kind."""
+def algorithmic(kind, prob, tb=4):
+    """(unit, amount per launch, bound) for a kernel kind; tb = bytes per
+    stored train value."""
     T, nv, nx, C = prob.n_tr, prob.nv, prob.nx, prob.n_coils
     if kind == "ystage_fwd_jv":   # 4 trains + per-voxel weights in, U out
-        return "bytes", 16 * T * nv + 28 * nv + 8 * C * T * nx, "hbm"
+        return "bytes", 4 * tb * T * nv + 28 * nv + 8 * C * T * nx, "hbm"
     if kind == "ystage_fwd_signal":   # m train + rho in, U out
-        return "bytes", 4 * T * nv + 8 * nv + 8 * C * T * nx, "hbm"
+        return "bytes", tb * T * nv + 8 * nv + 8 * C * T * nx, "hbm"
     if kind == "ystage_adj":      # 4 trains + W in
-        return "bytes", 16 * T * nv + 8 * C * T * nx, "hbm"
+        return "bytes", 4 * tb * T * nv + 8 * C * T * nx, "hbm"
     if kind == "epg":
         return "flop", EPG_FLOP_PER_STATE_TR * prob.n_states * T * nv, "alu"
     return None
+
+
+def surrogate_work(prob, width=256, depth=4, bytes_per_value=2):
+    """Per launch of the fused inference with all four trains: (flop, bytes
+    written). Multiply-adds of the first layer, the hidden layers and the
+    4 n_tr imaginary outputs; the trains written once (FP16 by default)."""
+    macs = 3 * width + (depth - 1) * width * width + 4 * prob.n_tr * width
+    return 2 * macs * prob.nv, 4 * bytes_per_value * prob.n_tr * prob.nv
 
 
 def measured_traffic(kind):
@@ -76,6 +95,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--train-epochs", type=int, default=40)
+    ap.add_argument("--train-samples", type=int, default=2_000_000)
+    ap.add_argument("--form", choices=["both", "surrogate", "plain"], default="both")
     return ap.parse_args()
 
 
@@ -109,6 +131,24 @@ def cpu_baseline(work, n_cg):
                        f"n_cg = {n_cg}: t_step = t_lin + (n_cg + 1) t_pair = {t_step:.1f} s")}
 
 
+def roofline_for(kernels, prob, tb):
+    cand = [k for k in kernels if algorithmic(k, prob, tb)]
+    if not cand:
+        return None
+    rk = max(cand, key=lambda k: kernels[k]["ms_per_step"])
+    unit, amount, bound = algorithmic(rk, prob, tb)
+    t = kernels[rk]["avg_ms"] * 1e-3
+    if unit == "bytes":
+        ach = amount / t / 1e9
+        return {"kernel": rk, "bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(rk),
+                "algorithmic_bytes_per_launch": amount}
+    ach = amount / t / 1e12
+    return {"kernel": rk, "bound": bound, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+            "algorithmic_flop_per_launch": amount}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -118,6 +158,7 @@ def main():
 
     import torch
 
+    from paper_1904_13244_amd import binding as B
     from paper_1904_13244_amd import inputs as I
     from paper_1904_13244_amd.binding import Context
 
@@ -138,69 +179,86 @@ def main():
     th0[0] += 0.05 * rng.standard_normal(prob.nv)
     th0[1] += 0.05 * rng.standard_normal(prob.nv)
     th0[2] += 0.02 * rng.standard_normal(prob.nv)
-    theta = dev(th0, torch.float32)
-
-    def step():
-        return ctx.gn_step(theta, data, args.n_cg, work.param_mask, I.GN_LO, I.GN_HI, n_ls_max=1)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rep = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ms_step = 1e3 * elapsed / args.steps
-    value = args.n_cg * args.steps / elapsed
-
-    # Per-kernel averages over the timed region and the dominant kernel.
-    kernels = {k: {"launches": n, "avg_ms": (ms / n if n else 0.0), "ms_per_step": ms / args.steps}
-               for k, (n, ms) in prof.items() if n}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    roof = None
-    cand = [k for k in kernels if algorithmic(k, prob)]
-    if cand:
-        rk = max(cand, key=lambda k: kernels[k]["ms_per_step"])
-        unit, amount, bound = algorithmic(rk, prob)
-        t = kernels[rk]["avg_ms"] * 1e-3
-        if unit == "bytes":
-            ach = amount / t / 1e9
-            roof = {"kernel": rk, "bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(rk),
-                    "algorithmic_bytes_per_launch": amount}
-        else:
-            ach = amount / t / 1e12
-            roof = {"kernel": rk, "bound": bound, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None,
-                    "algorithmic_flop_per_launch": amount}
-
-    # Cached pair time (reuse = 1) and linearisation time, outside the timed loop.
-    ctx.linearise(theta)
     vv, ww = I.probe_vectors(prob, work.param_mask)
     vd, wd = dev(vv, torch.float32), dev(ww, torch.complex64)
-    jv_out = torch.empty(prob.data_shape, dtype=torch.complex64, device="cuda")
-    g_out = torch.empty((5, prob.nv), dtype=torch.float32, device="cuda")
-    for _ in range(3):
-        ctx.jv(theta, vd, reuse=True, out=jv_out)
-        ctx.jhw(theta, wd, reuse=True, out=g_out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        ctx.jv(theta, vd, reuse=True, out=jv_out)
-        ctx.jhw(theta, wd, reuse=True, out=g_out)
-    e1.record()
-    torch.cuda.synchronize()
-    pair_ms = e0.elapsed_time(e1) / 20
-    e0.record()
-    for _ in range(5):
+
+    def run_form(net, enc, lo, hi, trains):
+        ctx.set_surrogate(net)
+        ctx.set_encoding(enc)
+        ctx.set_train_precision(trains)
+        theta = dev(th0, torch.float32)
+
+        def step():
+            return ctx.gn_step(theta, data, args.n_cg, work.param_mask, lo, hi, n_ls_max=1)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep = step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        kernels = {k: {"launches": n, "avg_ms": (ms / n if n else 0.0), "ms_per_step": ms / args.steps}
+                   for k, (n, ms) in prof.items() if n}
+        # Cached pair (reuse = 1) and linearisation, outside the timed loop.
         ctx.linearise(theta)
-    e1.record()
-    torch.cuda.synchronize()
-    lin_ms = e0.elapsed_time(e1) / 5
+        jv_out = torch.empty(prob.data_shape, dtype=torch.complex64, device="cuda")
+        g_out = torch.empty((5, prob.nv), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            ctx.jv(theta, vd, reuse=True, out=jv_out)
+            ctx.jhw(theta, wd, reuse=True, out=g_out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            ctx.jv(theta, vd, reuse=True, out=jv_out)
+            ctx.jhw(theta, wd, reuse=True, out=g_out)
+        e1.record()
+        torch.cuda.synchronize()
+        pair_ms = e0.elapsed_time(e1) / 20
+        e0.record()
+        for _ in range(5):
+            ctx.linearise(theta)
+        e1.record()
+        torch.cuda.synchronize()
+        lin_ms = e0.elapsed_time(e1) / 5
+        return {"value": args.n_cg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+                "kernels": kernels, "dominant_kernel": max(kernels, key=lambda k: kernels[k]["ms_per_step"]),
+                "roofline": roofline_for(kernels, prob, 2 if trains == B.TRAINS_FP16 else 4),
+                "pair_cached_ms": pair_ms,
+                "pairs_per_s_cached": 1e3 / pair_ms, "linearise_ms": lin_ms,
+                "gn_report_last": rep.as_dict()}
+
+    forms = {}
+    if args.form in ("both", "plain"):
+        forms["plain_fp32"] = run_form(None, B.ENC_FP32, I.GN_LO, I.GN_HI, B.TRAINS_FP32)
+    surr_info = None
+    if args.form in ("both", "surrogate"):
+        from paper_1904_13244_amd.surrogate import train_surrogate
+        net, trep = train_surrogate(torch, prob, n_samples=args.train_samples, epochs=args.train_epochs)
+        lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
+        hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
+        f = run_form(net, B.ENC_SPLIT_BF16, lo, hi, B.TRAINS_FP16)
+        forms["surrogate_split_bf16"] = f
+        flop, wbytes = surrogate_work(prob)
+        k = f["kernels"].get("surrogate")
+        t = k["avg_ms"] * 1e-3 if k else None
+        surr_info = {
+            "training": {"samples": trep.n_samples, "steps": trep.steps, "batch": net.batch,
+                         "seconds_data": trep.seconds_data, "seconds_train": trep.seconds_train,
+                         "loss_first": trep.loss_first, "loss_last": trep.loss_last,
+                         "heldout_rel_err": dict(zip(["m", "dm_dlnT1", "dm_dlnT2", "dm_dB1"],
+                                                     trep.val_rel_err))},
+            "inference_roofline": None if t is None else {
+                "kernel": "surrogate (fused inference, all four trains, FP16 out)",
+                "bound": "hbm", "achieved": wbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": wbytes / t / 1e9 / HBM_PEAK_GBS,
+                "mfma_tflops": flop / t / 1e12, "mfma_frac": flop / t / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+                "algorithmic_bytes_per_launch": wbytes, "algorithmic_flop_per_launch": flop},
+        }
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -209,24 +267,38 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    chosen = "surrogate_split_bf16" if "surrogate_split_bf16" in forms else "plain_fp32"
+    c = forms[chosen]
     out = {
-        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "metric": METRIC, "value": c["value"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": c["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32+bf16" if chosen.startswith("surrogate") else "fp32",
         "data": "synthetic",
         "config": {"workload": ("224x224 brain-like phantom, 1120 TRs (224 lines x 5 sweeps), "
                                 "448 readout samples, K=32 EPG states, 1 coil; one GN step = "
                                 "linearise + r + g + 20 CG pairs + 1 line-search trial"),
-                   "form": "plain FP32 EPG + FP32 MFMA encoding contraction",
+                   "form": {"surrogate_split_bf16": "surrogate trains (BF16 MFMA network, EPG "
+                                                    "fallback, FP16 storage) + split-BF16 MFMA "
+                                                    "encoding contraction",
+                            "plain_fp32": "plain FP32 EPG + FP32 MFMA encoding contraction"}[chosen],
                    "n_cg": args.n_cg, "parallelism": "single GPU"},
-        "roofline": roof,
-        "dominant_kernel": dom,
-        "kernels": kernels,
-        "pair_cached_ms": pair_ms,
-        "pairs_per_s_cached": 1e3 / pair_ms,
-        "linearise_ms": lin_ms,
-        "gn_report_last": rep.as_dict(),
+        "roofline": c["roofline"],
+        "dominant_kernel": c["dominant_kernel"],
+        "kernels": c["kernels"],
+        "pair_cached_ms": c["pair_cached_ms"],
+        "pairs_per_s_cached": c["pairs_per_s_cached"],
+        "linearise_ms": c["linearise_ms"],
+        "gn_report_last": c["gn_report_last"],
     }
+    if "plain_fp32" in forms and chosen != "plain_fp32":
+        p = forms["plain_fp32"]
+        out["plain_fp32"] = {k: p[k] for k in ("value", "ms_per_step", "pair_cached_ms",
+                                               "pairs_per_s_cached", "linearise_ms", "roofline",
+                                               "kernels")}
+        out["speedup_vs_plain_fp32"] = c["value"] / p["value"]
+    if surr_info:
+        out["surrogate"] = surr_info
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.n_cg)

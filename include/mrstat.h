@@ -80,6 +80,15 @@ typedef enum {
     MRSTAT_ENC_FP16 = 2
 } mrstat_enc;
 
+/* Storage of the linearisation's trains in the workspace: FP32, or FP16
+ * (rounded to nearest from the FP32 simulation; relative rounding 2^-11,
+ * halving the bytes the J v and J^H w y-stages stream). All arithmetic on
+ * them stays FP32. */
+typedef enum {
+    MRSTAT_TRAINS_FP32 = 0,
+    MRSTAT_TRAINS_FP16 = 1
+} mrstat_trains;
+
 /* Sequence and grid. Host arrays are read during mrstat_create only.
  * Requirements: nx, ny >= 1; n_tr >= 1; n_read >= nx; 1 <= n_states <= 64;
  * 1 <= n_coils <= 16; 0 <= te_s <= tr_s; t_inv_s >= 0; every ky_line in
@@ -142,6 +151,8 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void *d_ws, size_t ws_bytes,
                           const void *d_coil, const uint8_t *d_mask, mrstat_stream stream);
 
 mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc);
+/* Train storage precision (default FP32). Invalidates the linearisation. */
+mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec);
 
 /* Tuning: lanes per voxel of the EPG kernel (the K states of a voxel are split
  * over a group of `lanes` lanes: 1, 2, 4 or 8; 0 = automatic choice). Results
@@ -152,7 +163,7 @@ mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
 /* Linearise at theta: EPG trains m, dm/dlnT1, dm/dlnT2, dm/dB1 per voxel and
  * TR into the workspace; if d_trains != NULL also copy them out as float32
  * [4][n_tr][Nv] holding the imaginary parts (the real parts are exactly 0
- * under the supported RF phases). The trains are m_j[n] = F+_0 e^{-i phi_n}
+ * under the supported RF phases; FP16-stored trains are widened to FP32). The trains are m_j[n] = F+_0 e^{-i phi_n}
  * at TE of TR n (sampled once per readout, no decay during the readout). */
 mrstat_status mrstat_simulate(mrstat_ctx ctx, const float *d_theta, float *d_trains,
                               mrstat_stream stream);
@@ -296,8 +307,11 @@ mrstat_status mrstat_mlp_predict(mrstat_mlp net, const float *d_theta, int64_t l
 /* Uses net (bound, built for this n_tr; NULL = plain EPG) for every
  * linearisation and line-search evaluation of the context: voxels whose
  * (ln T1, ln T2, B1) lie in the network's box take its trains, the others
- * (and non-finite ones) are simulated by the EPG. The caller keeps net alive
- * while it is set. Invalidates the current linearisation. */
+ * (and non-finite ones) are simulated by the EPG. The fallback runs the full
+ * recurrence for those voxels, which takes about the time of a whole EPG
+ * pass however few they are: Gauss-Newton callers should keep the projection
+ * box (mrstat_gn_opts lo/hi) inside the network's box. The caller keeps net
+ * alive while it is set. Invalidates the current linearisation. */
 mrstat_status mrstat_set_surrogate(mrstat_ctx ctx, mrstat_mlp net);
 /* Number of voxels the last linearisation sent to the EPG fallback (0 without
  * a surrogate or linearisation). Synchronises the stream. */

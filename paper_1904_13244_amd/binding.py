@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmrstat.so")
 OK, ERR_ARG, ERR_SHAPE, ERR_HIP, ERR_WORKSPACE, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7)
 ENC_FP32, ENC_SPLIT_BF16, ENC_FP16 = 0, 1, 2
+TRAINS_FP32, TRAINS_FP16 = 0, 1
 _STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR_WORKSPACE",
            -5: "ERR_NONFINITE", -6: "ERR_STATE", -7: "ERR_UNSUPPORTED"}
 
@@ -71,6 +72,7 @@ def lib():
             "mrstat_bind": ([vp, vp, C.c_size_t, vp, vp, vp], C.c_int),
             "mrstat_set_encoding": ([vp, C.c_int], C.c_int),
             "mrstat_set_epg_lanes": ([vp, i32], C.c_int),
+            "mrstat_set_train_precision": ([vp, C.c_int], C.c_int),
             "mrstat_simulate": ([vp, vp, vp, vp], C.c_int),
             "mrstat_residual": ([vp, vp, i32, vp, vp, P(C.c_double), vp], C.c_int),
             "mrstat_jv": ([vp, vp, i32, vp, vp, vp], C.c_int),
@@ -116,7 +118,7 @@ def exported_symbols():
             "mrstat_mlp_param_count", "mrstat_mlp_workspace_bytes", "mrstat_mlp_bind",
             "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
-            "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile"]
+            "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision"]
 
 
 def _check(status, ctx=None):
@@ -162,6 +164,10 @@ def mrstat_bind(ctx, ws_ptr, ws_bytes, coil_ptr, mask_ptr, stream):
 
 def mrstat_set_encoding(ctx, enc):
     _check(lib().mrstat_set_encoding(ctx, enc), ctx)
+
+
+def mrstat_set_train_precision(ctx, prec):
+    _check(lib().mrstat_set_train_precision(ctx, int(prec)), ctx)
 
 
 def mrstat_set_epg_lanes(ctx, lanes):
@@ -369,6 +375,9 @@ class Context:
 
     def set_epg_lanes(self, lanes):
         mrstat_set_epg_lanes(self.h, lanes)
+
+    def set_train_precision(self, prec):
+        mrstat_set_train_precision(self.h, prec)
 
     def simulate(self, theta, trains=None):
         T = self.torch

@@ -39,6 +39,7 @@ struct mrstat_ctx_s {
     mrstat_enc enc = MRSTAT_ENC_FP32;
     int epg_lanes = 0;
     mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
+    bool f16 = false;             // trains stored as FP16
     // bound device state
     char* ws = nullptr;
     const float2* coil = nullptr;
@@ -55,8 +56,8 @@ struct mrstat_ctx_s {
 
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-    float* trains() const { return at<float>(L.trains); }
-    float* trial_m() const { return at<float>(L.trial_m); }
+    void* trains() const { return ws + L.trains; }    // float or _Float16
+    void* trial_m() const { return ws + L.trial_m; }
     float2* upart() const { return at<float2>(L.upart); }
     float2* W() const { return at<float2>(L.W); }
     float* apart() const { return at<float>(L.apart); }
@@ -200,21 +201,26 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // Trains at theta into out ([4][T][nv] with tangents, else the m train
 // [T][nv]): by the EPG, or by the surrogate with the EPG for the voxels
 // outside its box (their count in fb_count(slot)).
-mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, float* out, bool tangents, int slot,
+mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, bool tangents, int slot,
                             hipStream_t s)
 {
     const Dims& d = ctx->d;
     const int kind = tangents ? MRSTAT_K_EPG : MRSTAT_K_EPG_VALUE;
     if (!ctx->surr) {
-        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes, s)));
+        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes,
+                                        ctx->f16, s)));
         return MRSTAT_OK;
     }
     const int skind = tangents ? MRSTAT_K_SURR : MRSTAT_K_SURR_VALUE;
-    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, s)));
-    HIP_TRY(TRACED(skind, launch_box_compact(d, theta, mlp_box_lo(ctx->surr), mlp_box_hi(ctx->surr),
-                                             ctx->mask, ctx->fb_idx(), ctx->fb_count(slot), s)));
-    HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes,
-                                         ctx->fb_idx(), ctx->fb_count(slot), s)));
+    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, ctx->f16, s)));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_box_compact(d, theta, mlp_box_lo(ctx->surr),
+                                                       mlp_box_hi(ctx->surr), ctx->mask, ctx->fb_idx(),
+                                                       ctx->fb_count(slot), s)));
+    // A short list of scattered voxels is latency bound: spread each voxel's
+    // states over the most lanes unless a split was set explicitly.
+    const int fb_lanes = ctx->epg_lanes ? ctx->epg_lanes : (d.K <= 8 ? 2 : d.K <= 16 ? 4 : 8);
+    HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, tangents, fb_lanes,
+                                         ctx->f16, ctx->fb_idx(), ctx->fb_count(slot), s)));
     return MRSTAT_OK;
 }
 
@@ -229,14 +235,14 @@ mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s)
 
 // s-type forward product into out: mode 0 r = data - s (+ f partials),
 // 1 out = -J-direction signal, 2 out = s.
-mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const float* trains,
+mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains,
                       const float* theta, const float* v, const void* data, void* out,
                       double* f_out, hipStream_t s)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
     HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
-                   launch_ystage_fwd(d, p, mode_y, trains, theta, v, ctx->coil, ctx->mask,
+                   launch_ystage_fwd(d, p, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask,
                                      ctx->deytab(), ctx->upart(), s)));
     int nred = 0;
     HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, p, ctx->enc, mode_x, ctx->upart(),
@@ -253,7 +259,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     const YPlan& p = ctx->L.yp;
     HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
                                                    ctx->W(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), 4, ctx->coil, ctx->mask,
+    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 4, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
     HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, g, s)));
     return MRSTAT_OK;
@@ -378,6 +384,16 @@ mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)
     return MRSTAT_OK;
 }
 
+mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (prec != MRSTAT_TRAINS_FP32 && prec != MRSTAT_TRAINS_FP16)
+        return fail(ctx, MRSTAT_ERR_ARG, "unknown train precision");
+    ctx->f16 = prec == MRSTAT_TRAINS_FP16;
+    ctx->lin_valid = false;
+    return MRSTAT_OK;
+}
+
 mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes)
 {
     if (!ctx) return MRSTAT_ERR_ARG;
@@ -423,8 +439,7 @@ mrstat_status mrstat_simulate(mrstat_ctx ctx, const float* d_theta, float* d_tra
     st = linearise(ctx, d_theta, s);
     if (st != MRSTAT_OK) return st;
     if (d_trains)
-        HIP_TRY(hipMemcpyAsync(d_trains, ctx->trains(), (size_t)4 * ctx->d.T * ctx->d.nv * sizeof(float),
-                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(launch_trains_to_f32(ctx->trains(), ctx->f16, d_trains, (size_t)4 * ctx->d.T * ctx->d.nv, s));
     return MRSTAT_OK;
 }
 
@@ -593,7 +608,7 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
         const YPlan& p = ctx->L.yp;
         HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->W(), s)));
-        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), 1, ctx->coil, ctx->mask,
+        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 1, ctx->coil, ctx->mask,
                                                         ctx->deytab(), ctx->W(), ctx->apart(), s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_rho_adj_finish(d, p, ctx->apart(), ctx->mask, out, s)));
         return MRSTAT_OK;

@@ -17,7 +17,8 @@
 //
 // Lane layout of both y-stages: a wave covers 32 consecutive ix (lanes 0-31
 // and 32-63) of two adjacent rows, so nx only needs to be a multiple of 32
-// for full lanes; consecutive lanes read consecutive floats of a train row.
+// for full lanes; consecutive lanes read consecutive elements of a train row.
+// Trains are stored as float or _Float16 (TT); arithmetic is FP32.
 #include "mrstat_internal.h"
 
 namespace mrstat {
@@ -58,9 +59,9 @@ __device__ __forceinline__ float2 shfl_xor2(float2 v, int m)
 // ------------------------------------------------------------------------
 constexpr int FW = 16;
 
-template <int MODE, int R, int CC>
+template <int MODE, int R, int CC, typename TT>
 __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
-    const float* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
+    const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
     const float2* __restrict__ eytab, float2* __restrict__ U, int nx, int ny, int nv, int T, int C,
     int n_per_chunk)
@@ -118,18 +119,18 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         // Uniform row bases (scalar registers) plus 32-bit lane offsets.
         float mu[R], m1[R], m2[R], m3[R];
         float2 ey[R];
-        const float* __restrict__ b0 = trains + (size_t)n * nv;
-        const float* __restrict__ b1 = b0 + plane;
-        const float* __restrict__ b2 = b1 + plane;
-        const float* __restrict__ b3 = b2 + plane;
+        const TT* __restrict__ b0 = trains + (size_t)n * nv;
+        const TT* __restrict__ b1 = b0 + plane;
+        const TT* __restrict__ b2 = b1 + plane;
+        const TT* __restrict__ b3 = b2 + plane;
         const float2* eyrow = eys + (size_t)(n - n0) * 32 * R + 2 * wave + half;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            mu[r] = b0[jr[r]];
+            mu[r] = (float)b0[jr[r]];
             if constexpr (MODE == 1) {
-                m1[r] = b1[jr[r]];
-                m2[r] = b2[jr[r]];
-                m3[r] = b3[jr[r]];
+                m1[r] = (float)b1[jr[r]];
+                m2[r] = (float)b2[jr[r]];
+                m3[r] = (float)b3[jr[r]];
             }
             ey[r] = eyrow[32 * r];
         }
@@ -206,9 +207,9 @@ __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
 // ------------------------------------------------------------------------
 constexpr int ADJ_EY_ROWS = 4;   // rows of a 256-voxel block when nx >= 128
 
-template <int NTRAIN, int CC, int NBA>
+template <int NTRAIN, int CC, int NBA, typename TT>
 __global__ __launch_bounds__(256) void ystage_adj_kernel(
-    const float* __restrict__ trains, const float2* __restrict__ coil,
+    const TT* __restrict__ trains, const float2* __restrict__ coil,
     const uint8_t* __restrict__ mask, const float2* __restrict__ eytab,
     const float2* __restrict__ W, float* __restrict__ apart, int nx, int ny, int nv, int T,
     int C, int n_per_chunk)
@@ -254,9 +255,9 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
                 const int cc = c < C ? c : 0;
                 wv[b][c] = W[((size_t)cc * T + n) * nx + ix];
             }
-            const float* __restrict__ t0 = trains + (size_t)n * nv;
+            const TT* __restrict__ t0 = trains + (size_t)n * nv;
 #pragma unroll
-            for (int p = 0; p < NTRAIN; ++p) mu[b][p] = (t0 + p * plane)[j];
+            for (int p = 0; p < NTRAIN; ++p) mu[b][p] = (float)(t0 + p * plane)[j];
         }
 #pragma unroll
         for (int b = 0; b < NBA; ++b) {
@@ -727,8 +728,8 @@ void xgemm_any(int enc, dim3 grid, hipStream_t s, const float2* A, const float2*
         xgemm_f32_kernel<DIR, MODE><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
 }
 
-template <int MODE, int CC>
-hipError_t fwd_R(const Dims& d, const YPlan& p, const float* trains, const float* theta,
+template <int MODE, int CC, typename TT>
+hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* theta,
                  const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
                  float2* U, hipStream_t s)
 {
@@ -737,7 +738,7 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const float* trains, const float
 #define FWD_CASE(RR)                                                                            \
     case RR:                                                                                    \
         if constexpr (CC == 1 || RR <= 2)                                                       \
-            ystage_fwd_kernel<MODE, RR, CC><<<grid, FW * 64, lds, s>>>(                         \
+            ystage_fwd_kernel<MODE, RR, CC, TT><<<grid, FW * 64, lds, s>>>(                     \
                 trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr);  \
         else                                                                                    \
             return hipErrorInvalidValue;                                                        \
@@ -751,8 +752,8 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const float* trains, const float
     return hipGetLastError();
 }
 
-template <int NTRAIN, int CC>
-hipError_t adj_launch(const Dims& d, const YPlan& p, const float* trains, const float2* coil,
+template <int NTRAIN, int CC, typename TT>
+hipError_t adj_launch(const Dims& d, const YPlan& p, const TT* trains, const float2* coil,
                       const uint8_t* mask, const float2* eytab, const float2* W, float* apart,
                       hipStream_t s)
 {
@@ -760,7 +761,7 @@ hipError_t adj_launch(const Dims& d, const YPlan& p, const float* trains, const 
     const int rows = std::min(d.ny, 256 / d.nx + 2);
     const size_t lds = (size_t)p.adj_per_chunk * rows * sizeof(float2);
     constexpr int NBA = CC == 1 ? 4 : 2;
-    ystage_adj_kernel<NTRAIN, CC, NBA><<<grid, 256, lds, s>>>(trains, coil, mask, eytab, W, apart,
+    ystage_adj_kernel<NTRAIN, CC, NBA, TT><<<grid, 256, lds, s>>>(trains, coil, mask, eytab, W, apart,
                                                              d.nx, d.ny, d.nv, d.T, d.C,
                                                              p.adj_per_chunk);
     return hipGetLastError();
@@ -799,21 +800,44 @@ YPlan make_yplan(const Dims& d)
     return p;
 }
 
-hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const float* trains,
+template <typename TT>
+hipError_t fwd_typed(const Dims& d, const YPlan& p, int mode, const TT* trains, const float* theta,
+                     const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
+                     float2* upart, hipStream_t s)
+{
+    if (d.C == 1)
+        return mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                         : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    if (d.C <= 8)
+        return mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                         : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    return mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
+                     : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+}
+
+template <typename TT>
+hipError_t adj_typed(const Dims& d, const YPlan& p, const TT* trains, int ntr_trains,
+                     const float2* coil, const uint8_t* mask, const float2* eytab, const float2* W,
+                     float* apart, hipStream_t s)
+{
+    if (ntr_trains == 4) {
+        if (d.C == 1) return adj_launch<4, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
+        if (d.C <= 8) return adj_launch<4, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
+        return adj_launch<4, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+    }
+    if (d.C == 1) return adj_launch<1, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
+    if (d.C <= 8) return adj_launch<1, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
+    return adj_launch<1, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+}
+
+hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void* trains, bool f16,
                              const float* theta, const float* v, const float2* coil,
                              const uint8_t* mask, const float2* eytab, float2* upart,
                              hipStream_t s)
 {
-    hipError_t e;
-    if (d.C == 1)
-        e = mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                      : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
-    else if (d.C <= 8)
-        e = mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                      : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
-    else
-        e = mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                      : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+    const hipError_t e =
+        f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, s)
+            : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, s);
     if (e != hipSuccess || p.nby == 1) return e;
     const size_t count = (size_t)d.C * d.T * d.nx;
     usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, p.nby, count);
@@ -854,18 +878,12 @@ hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2
     return hipGetLastError();
 }
 
-hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const float* trains, int ntr_trains,
+hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, bool f16, int ntr_trains,
                              const float2* coil, const uint8_t* mask, const float2* eytab,
                              const float2* W, float* apart, hipStream_t s)
 {
-    if (ntr_trains == 4) {
-        if (d.C == 1) return adj_launch<4, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
-        if (d.C <= 8) return adj_launch<4, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
-        return adj_launch<4, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
-    }
-    if (d.C == 1) return adj_launch<1, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
-    if (d.C <= 8) return adj_launch<1, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
-    return adj_launch<1, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+    return f16 ? adj_typed(d, p, static_cast<const _Float16*>(trains), ntr_trains, coil, mask, eytab, W, apart, s)
+               : adj_typed(d, p, static_cast<const float*>(trains), ntr_trains, coil, mask, eytab, W, apart, s);
 }
 
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,

@@ -54,10 +54,12 @@ __device__ __forceinline__ void clear_above(float (&f)[S], int base, int K)
 
 // LIST: the group handles voxel idx[vox] for vox < *count (the other voxels'
 // outputs are left untouched); whole blocks past the list exit at once.
-template <int S, int L, bool TANG, bool MASKED, bool LIST>
+// TT: element type of the stored trains (float, or _Float16 rounded to
+// nearest from the FP32 recursion).
+template <int S, int L, bool TANG, bool MASKED, bool LIST, typename TT>
 __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ theta,
                                                   const float2* __restrict__ seq,
-                                                  float* __restrict__ out, int nv, int T,
+                                                  TT* __restrict__ out, int nv, int T,
                                                   int K, SeqTimes st,
                                                   const int* __restrict__ idx,
                                                   const int* __restrict__ count)
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
     }
 
     const size_t plane = (size_t)T * nv;
-    float* o0 = out + j;
+    TT* o0 = out + j;
     for (int n = 0; n < T; ++n) {
         const float2 sq = seq[n];
         const float alpha = sq.x, sg = sq.y;
@@ -127,16 +129,16 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
         {
             const float rp = fmaf(c2, f[0], fmaf(s2, g[0], -sgsa * z[0]));
             const float ke = sg * E2e;
-            if (store) o0[(size_t)n * nv] = ke * rp;
+            if (store) o0[(size_t)n * nv] = (TT)(ke * rp);
             if constexpr (TANG) {
                 const float rp1 = fmaf(c2, f1[0], fmaf(s2, g1[0], -sgsa * z1[0]));
                 const float rp2 = fmaf(c2, f2[0], fmaf(s2, g2[0], -sgsa * z2[0]));
                 const float drp = fmaf(-0.5f * sa, f[0] - g[0], -sg * ca * z[0]);
                 const float rp3 = fmaf(c2, f3[0], fmaf(s2, g3[0], fmaf(alpha, drp, -sgsa * z3[0])));
                 if (store) {
-                    o0[plane + (size_t)n * nv] = ke * rp1;
-                    o0[2 * plane + (size_t)n * nv] = ke * fmaf(tau2e, rp, rp2);
-                    o0[3 * plane + (size_t)n * nv] = ke * rp3;
+                    o0[plane + (size_t)n * nv] = (TT)(ke * rp1);
+                    o0[2 * plane + (size_t)n * nv] = (TT)(ke * fmaf(tau2e, rp, rp2));
+                    o0[3 * plane + (size_t)n * nv] = (TT)(ke * rp3);
                 }
             }
         }
@@ -211,28 +213,28 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
     }
 }
 
-template <int S, int L, bool TANG, bool LIST>
-hipError_t launch_sl(const Dims& d, SeqTimes st, const float* theta, const float2* seq, float* out,
+template <int S, int L, bool TANG, bool LIST, typename TT>
+hipError_t launch_sl(const Dims& d, SeqTimes st, const float* theta, const float2* seq, TT* out,
                      const int* idx, const int* count, hipStream_t s)
 {
     const long threads = (long)d.nv * L;
     const int block = 256;
     const int grid = (int)((threads + block - 1) / block);
     if (d.K == S * L)
-        epg_kernel<S, L, TANG, false, LIST><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st,
-                                                                   idx, count);
+        epg_kernel<S, L, TANG, false, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
+                                                                       st, idx, count);
     else
-        epg_kernel<S, L, TANG, true, LIST><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K, st,
-                                                                  idx, count);
+        epg_kernel<S, L, TANG, true, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
+                                                                      st, idx, count);
     return hipGetLastError();
 }
 
-template <bool TANG, bool LIST>
+template <bool TANG, bool LIST, typename TT>
 hipError_t launch_any(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      float* out, int lanes, const int* idx, const int* count, hipStream_t s)
+                      TT* out, int lanes, const int* idx, const int* count, hipStream_t s)
 {
     const int K = d.K;
-#define SL(S_, L_) launch_sl<S_, L_, TANG, LIST>(d, st, theta, seq, out, idx, count, s)
+#define SL(S_, L_) launch_sl<S_, L_, TANG, LIST, TT>(d, st, theta, seq, out, idx, count, s)
     if (K <= 8) {
         if (lanes == 2) return SL(4, 2);
         return SL(8, 1);
@@ -282,21 +284,48 @@ __global__ __launch_bounds__(256) void box_compact_kernel(const float* __restric
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
+__global__ void half_to_float_kernel(const _Float16* __restrict__ in, float* __restrict__ out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 }  // namespace
 
-hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      float* out, bool tangents, int lanes, hipStream_t s)
+template <bool LIST>
+hipError_t launch_typed(const Dims& d, SeqTimes st, const float* theta, const float2* seq, void* out,
+                        bool tangents, int lanes, bool f16, const int* idx, const int* count,
+                        hipStream_t s)
 {
-    return tangents ? launch_any<true, false>(d, st, theta, seq, out, lanes, nullptr, nullptr, s)
-                    : launch_any<false, false>(d, st, theta, seq, out, lanes, nullptr, nullptr, s);
+    if (f16) {
+        _Float16* o = static_cast<_Float16*>(out);
+        return tangents ? launch_any<true, LIST>(d, st, theta, seq, o, lanes, idx, count, s)
+                        : launch_any<false, LIST>(d, st, theta, seq, o, lanes, idx, count, s);
+    }
+    float* o = static_cast<float*>(out);
+    return tangents ? launch_any<true, LIST>(d, st, theta, seq, o, lanes, idx, count, s)
+                    : launch_any<false, LIST>(d, st, theta, seq, o, lanes, idx, count, s);
+}
+
+hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
+                      void* out, bool tangents, int lanes, bool f16, hipStream_t s)
+{
+    return launch_typed<false>(d, st, theta, seq, out, tangents, lanes, f16, nullptr, nullptr, s);
 }
 
 hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                           float* out, bool tangents, int lanes, const int* idx, const int* count,
-                           hipStream_t s)
+                           void* out, bool tangents, int lanes, bool f16, const int* idx,
+                           const int* count, hipStream_t s)
 {
-    return tangents ? launch_any<true, true>(d, st, theta, seq, out, lanes, idx, count, s)
-                    : launch_any<false, true>(d, st, theta, seq, out, lanes, idx, count, s);
+    return launch_typed<true>(d, st, theta, seq, out, tangents, lanes, f16, idx, count, s);
+}
+
+hipError_t launch_trains_to_f32(const void* in, bool f16, float* out, size_t n, hipStream_t s)
+{
+    if (!f16) return hipMemcpyAsync(out, in, n * sizeof(float), hipMemcpyDeviceToDevice, s);
+    half_to_float_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<const _Float16*>(in),
+                                                                   out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo, const float* hi,

@@ -12,6 +12,8 @@
 #include "mrstat_internal.h"
 #include "mlp_internal.h"
 
+#include <type_traits>
+
 namespace mrstat {
 namespace {
 
@@ -286,11 +288,14 @@ __device__ __forceinline__ uint32_t pack2(float a, float b)
 // from L2), 16 outputs per step, each wave taking every fourth 16-row tile
 // (with PF, the next tile's weights are loaded while the current one is
 // multiplied). Results (bias added, head scale applied) go straight to the
-// train layout out[p][n][voxel] as 16-byte stores of 4 consecutive voxels.
-// Same roundings as the training forward pass: pre-activations in FP32,
-// activations in BF16.
+// train layout out[p][n][voxel] as 16-byte (F16: 8-byte) stores of 4
+// consecutive voxels. Same roundings as the training forward pass:
+// pre-activations in FP32, activations in BF16; trains stored as FP32 or
+// rounded to FP16 (F16).
 // ------------------------------------------------------------------------
-template <int WIDTH, int NV, bool PF>
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+template <int WIDTH, int NV, bool PF, bool F16>
 __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
 {
     constexpr int HP = WIDTH + 8, KS = WIDTH / 32, MT = WIDTH / 64, VT = NV / 16;
@@ -396,7 +401,8 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
         if (o < a.m_out) {
             const int p = o / a.T, nt = o - p * a.T;
             const float bias = a.bout[o], sc = a.head_scale[p];
-            float* dst = a.out + (size_t)p * a.plane + (size_t)nt * a.ld_out;
+            using OT = typename std::conditional<F16, _Float16, float>::type;
+            OT* dst = static_cast<OT*>(a.out) + (size_t)p * a.plane + (size_t)nt * a.ld_out;
 #pragma unroll
             for (int t = 0; t < VT; ++t) {
                 const int jv = j0 + t * 16 + 4 * (lane >> 4);
@@ -405,12 +411,16 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
                 // Written once and read by a later kernel: streamed past the
                 // caches so the output weights stay resident in L2.
                 if (vec_ok && jv + 3 < a.n) {
-                    __builtin_nontemporal_store(f4{y0, y1, y2, y3}, reinterpret_cast<f4*>(dst + jv));
+                    if constexpr (F16)
+                        __builtin_nontemporal_store(h4v{(_Float16)y0, (_Float16)y1, (_Float16)y2, (_Float16)y3},
+                                                    reinterpret_cast<h4v*>(dst + jv));
+                    else
+                        __builtin_nontemporal_store(f4{y0, y1, y2, y3}, reinterpret_cast<f4*>(dst + jv));
                 } else {
-                    if (jv < a.n) __builtin_nontemporal_store(y0, dst + jv);
-                    if (jv + 1 < a.n) __builtin_nontemporal_store(y1, dst + jv + 1);
-                    if (jv + 2 < a.n) __builtin_nontemporal_store(y2, dst + jv + 2);
-                    if (jv + 3 < a.n) __builtin_nontemporal_store(y3, dst + jv + 3);
+                    if (jv < a.n) __builtin_nontemporal_store((OT)y0, dst + jv);
+                    if (jv + 1 < a.n) __builtin_nontemporal_store((OT)y1, dst + jv + 1);
+                    if (jv + 2 < a.n) __builtin_nontemporal_store((OT)y2, dst + jv + 2);
+                    if (jv + 3 < a.n) __builtin_nontemporal_store((OT)y3, dst + jv + 3);
                 }
             }
         }
@@ -495,7 +505,8 @@ hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t
     const int grid = ceil_div(a.n, tile);
 #define INFER(W_, NV_, PF_)                                                  \
     if (width == W_ && tile == NV_) {                                        \
-        mlp_infer_kernel<W_, NV_, PF_><<<grid, 256, 0, s>>>(a);              \
+        if (a.f16) mlp_infer_kernel<W_, NV_, PF_, true><<<grid, 256, 0, s>>>(a);   \
+        else mlp_infer_kernel<W_, NV_, PF_, false><<<grid, 256, 0, s>>>(a);        \
         return hipGetLastError();                                            \
     }
     INFER(64, 64, true)

@@ -198,7 +198,7 @@ namespace mrstat {
 // dimension ld_theta, written as [rows/T][T][ld_out] (all four trains, or the
 // m train only) in chunks of the network's batch size.
 hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n,
-                            float* out, int64_t ld_out, bool all_trains, hipStream_t s)
+                            void* out, int64_t ld_out, bool all_trains, bool f16, hipStream_t s)
 {
     const int W = net->width, B = net->B, T = net->T, L = net->depth;
     if (infer_fused_supported(W, L)) {
@@ -226,8 +226,10 @@ hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta
         a.out = out;
         a.ld_out = ld_out;
         a.plane = (int64_t)T * ld_out;
+        a.f16 = f16;
         return launch_mlp_infer(W, net->infer_tile, a, s);
     }
+    if (f16) return hipErrorInvalidValue;   // the chunked path writes FP32 only
     for (int c0 = 0; c0 < n; c0 += B) {
         const int nc = std::min(B, n - c0);
         if (hidden_forward(net, theta + c0, ld_theta, nc, false, s) != MRSTAT_OK) return hipErrorUnknown;
@@ -241,7 +243,7 @@ hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta
         g.K = W;
         g.ldo = ld_out;
         g.bias = net->w32() + net->off_bo + (size_t)4 * T;
-        g.Cf = out + c0;
+        g.Cf = static_cast<float*>(out) + c0;
         g.T = T;
         g.plane = (int64_t)T * ld_out;
         g.head_scale = net->dscale();
@@ -440,7 +442,7 @@ mrstat_status mrstat_mlp_predict(mrstat_mlp net, const float* d_theta, int64_t l
     if (!net || !d_theta || !d_out || n < 1) return MRSTAT_ERR_ARG;
     if (!net->ws) return mfail(net, MRSTAT_ERR_WORKSPACE, "network has no workspace");
     if (ld_theta < n) return mfail(net, MRSTAT_ERR_ARG, "leading dimension below n");
-    MTRY(mlp_infer_trains(net, d_theta, ld_theta, n, d_out, n, true, (hipStream_t)stream));
+    MTRY(mlp_infer_trains(net, d_theta, ld_theta, n, d_out, n, true, false, (hipStream_t)stream));
     return MRSTAT_OK;
 }
 

@@ -54,8 +54,9 @@ struct InferArgs {
     const float* head_scale;       // [4]
     int T;                         // TRs per train
     int m_out;                     // outputs produced: 4T (all trains) or T (m only)
-    float* out;                    // out[p * plane + n * ld_out + voxel]
+    void* out;                     // out[p * plane + n * ld_out + voxel], float or _Float16
     int64_t ld_out, plane;
+    bool f16;                      // trains stored as FP16
 };
 bool infer_fused_supported(int width, int depth);
 // tile: voxels per workgroup, 32 or 64 (0 = default).
@@ -76,9 +77,10 @@ hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 
 // Surrogate inference for the context (mlp_api.hip): trains of n voxels whose
 // theta rows (ln T1, ln T2, B1) have leading dimension ld_theta, into
-// out[p][n_tr][ld_out] for p < 4 (all_trains) or p = 0 only.
-hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n, float* out,
-                            int64_t ld_out, bool all_trains, hipStream_t s);
+// out[p][n_tr][ld_out] (float, or _Float16 when f16) for p < 4 (all_trains)
+// or p = 0 only.
+hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n, void* out,
+                            int64_t ld_out, bool all_trains, bool f16, hipStream_t s);
 const float* mlp_box_lo(mrstat_mlp net);
 const float* mlp_box_hi(mrstat_mlp net);
 int mlp_n_tr(mrstat_mlp net);

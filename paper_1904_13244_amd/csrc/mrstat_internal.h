@@ -42,15 +42,19 @@ YPlan make_yplan(const Dims& d);
 
 // EPG linearisation. theta [5][nv]; seq[n] = (flip angle [rad], RF sign +-1);
 // out: tangents ? [4][T][nv] : [T][nv] (imaginary parts of m, dm/dlnT1,
-// dm/dlnT2, dm/dB1). lanes = lanes per voxel (0 = automatic).
+// dm/dlnT2, dm/dB1), float or (f16) _Float16. lanes = lanes per voxel
+// (0 = automatic).
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      float* out, bool tangents, int lanes, hipStream_t s);
+                      void* out, bool tangents, int lanes, bool f16, hipStream_t s);
 
 // EPG on the voxels idx[0 .. *count) only (same output layout; other voxels
 // untouched). The grid covers nv voxels; blocks past the list exit at once.
 hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                           float* out, bool tangents, int lanes, const int* idx, const int* count,
-                           hipStream_t s);
+                           void* out, bool tangents, int lanes, bool f16, const int* idx,
+                           const int* count, hipStream_t s);
+
+// n stored train elements (float or _Float16) to float.
+hipError_t launch_trains_to_f32(const void* in, bool f16, float* out, size_t n, hipStream_t s);
 
 // Clears *count, then lists the voxels (in the mask) whose ln T1, ln T2, B1
 // lie outside [lo, hi] (host arrays of 3) or are not finite.
@@ -61,7 +65,7 @@ hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo
 // x[n][j], with x = i rho m (mode 0) or x = i (rho sum_q v_q dm_q +
 // (v3 + i v4) m) (mode 1, the J v direction). upart holds nby row-block
 // partials when nby > 1 and is summed into its first block.
-hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const float* trains,
+hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void* trains, bool f16,
                              const float* theta, const float* v, const float2* coil,
                              const uint8_t* mask, const float2* eytab, float2* upart,
                              hipStream_t s);
@@ -80,7 +84,7 @@ hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2
 // Adjoint y-stage: partial sums over TR chunks of
 // A_p[j] = sum_n mu_p[n][j] conj(Ey[n][iy]) sum_c conj(coil_c[j]) W_c[n][ix]
 // (p = 0..3 for m and the three tangents; ntr_trains = 4 or 1).
-hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const float* trains, int ntr_trains,
+hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, bool f16, int ntr_trains,
                              const float2* coil, const uint8_t* mask, const float2* eytab,
                              const float2* W, float* apart, hipStream_t s);
 

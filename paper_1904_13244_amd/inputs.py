@@ -258,8 +258,9 @@ def config(idx: int) -> Workload:
     if idx in (3, 4):
         prob = make_problem(224, 224, 1120, 448, 32)
         th, head = brain_phantom(224, 224, b1_range=(0.8, 1.2))
+        # T1, T2 and rho reconstructed, B1 known (the paper's simulation setting).
         return Workload("224x224 phantom, 1120 TRs, Nk 448, K 32", prob, th, None, None,
-                        10, 20, 0b11111, {"head": head})
+                        10, 20, 0b11011, {"head": head})
     if idx == 5:
         prob = make_problem(256, 256, 1280, 512, 32, n_coils=8)
         th, head = brain_phantom(256, 256, b1_range=(0.8, 1.2))

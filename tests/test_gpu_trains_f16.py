@@ -1,0 +1,144 @@
+"""FP16 train storage (mrstat_set_train_precision) against the FP64 oracle.
+
+The EPG recursion runs in FP32 and only its stored output is rounded to FP16
+(relative rounding error at most 2^-11 ~ 4.9e-4 per element, round to
+nearest). Bars: 6e-4 normwise per train (the FP16 rounding plus the FP32
+path's 1e-5), 1e-3 normwise for J v, Re(J^H w) and the residual (sums of
+rounded trains, errors of both signs). Expected values come from the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_1904_13244_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_13244_amd import binding
+    binding.lib()
+    return torch
+
+
+def _dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _ragged():
+    rng = np.random.default_rng(78)
+    T = 70
+    prob = I.make_problem(37, 29, T, 80, 13, flip_deg=rng.uniform(0, 80, T),
+                          rf_phase=np.pi * rng.integers(0, 2, T), t_inv=0.02, tr=0.0075,
+                          te=0.003, ky_line=rng.integers(0, 29, T))
+    th = I.iid_maps(prob.nv, seed=9, b1=rng.uniform(0.75, 1.25, prob.nv))
+    return prob, th, None, None
+
+
+def _coils():
+    rng = np.random.default_rng(6)
+    prob = I.make_problem(24, 20, 60, 48, 16, n_coils=4, flip_deg=I.flips_sin2_sweeps(60, 20))
+    th = I.iid_maps(prob.nv, seed=5, b1=rng.uniform(0.8, 1.2, prob.nv))
+    mask = (rng.uniform(size=prob.nv) > 0.2).astype(np.uint8)
+    return prob, th, I.coil_maps(24, 20, 4), mask
+
+
+def _config1():
+    w = I.config(1)
+    return w.problem, w.theta, None, None
+
+
+CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_f16_trains_and_products(torch_gpu, oracle_lib, name):
+    torch = torch_gpu
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    prob, th, coil, mask = CASES[name]()
+    print(f"\n[f16 {name}] nx={prob.nx} ny={prob.ny} T={prob.n_tr} K={prob.n_states} "
+          f"C={prob.n_coils}", flush=True)
+    ctx = Context(prob, coil=None if coil is None else _dev(torch, coil, torch.complex64),
+                  mask=None if mask is None else _dev(torch, mask, torch.uint8))
+    ctx.set_train_precision(B.TRAINS_FP16)
+    thd = _dev(torch, th, torch.float32)
+    ora = oracle_lib.epg(prob, th)
+    got = ctx.simulate(thd).cpu().numpy().astype(np.float64)
+    for p in range(4):
+        e = _rel(got[p], ora[p].imag)
+        print(f"  train {p}: rel {e:.2e}", flush=True)
+        assert e <= 6e-4, (p, e)
+    # Every stored value is an FP16 number.
+    assert np.array_equal(got, got.astype(np.float16).astype(np.float64))
+
+    v, w = I.probe_vectors(prob)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
+    e_jhw = _rel(jhw, oracle_lib.jhw(prob, th, ora, w, coil=coil, mask=mask))
+    s = oracle_lib.signal(prob, th, ora, coil=coil, mask=mask)
+    th0 = th.copy()
+    th0[0] += 0.05
+    f_ref, r_ref = oracle_lib.residual(prob, th0, s, coil=coil, mask=mask)
+    f, r = ctx.residual(_dev(torch, th0, torch.float32), _dev(torch, s, torch.complex64))
+    e_r = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(s))
+    print(f"  jv {e_jv:.2e} jhw {e_jhw:.2e} residual/||d|| {e_r:.2e}", flush=True)
+    assert max(e_jv, e_jhw, e_r) <= 1e-3
+    # Switching back restores the FP32 path exactly (within its own bar).
+    ctx.set_train_precision(B.TRAINS_FP32)
+    got32 = ctx.simulate(thd).cpu().numpy().astype(np.float64)
+    assert _rel(got32[0], ora[0].imag) <= 1e-5
+    ctx.close()
+
+
+def test_f16_surrogate_and_fallback(torch_gpu, oracle_lib):
+    """Surrogate trains stored in FP16: in-box voxels follow the FP64 network
+    (2e-2, its BF16 activations), fallback voxels the FP64 EPG (6e-4)."""
+    torch = torch_gpu
+    from oracle import mlp as M
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context, Surrogate
+    rng = np.random.default_rng(91)
+    n_tr, width, depth = 32, 64, 2
+    prob = I.make_problem(20, 16, n_tr, 24, 16, flip_deg=I.flips_sin2_sweeps(n_tr, 16))
+    th = I.iid_maps(prob.nv, seed=92, b1=rng.uniform(0.8, 1.2, prob.nv))
+    out = rng.choice(prob.nv, 40, replace=False)
+    th[0, out[:20]] = np.log(7.0)
+    th[2, out[20:]] = 0.62
+    th = th.astype(np.float32).astype(np.float64)
+    flat = I.mlp_init_params(n_tr, width, depth, seed=93).astype(np.float32)
+    scale = np.array([0.2, 0.1, 0.05, 0.3], dtype=np.float32)
+    net = Surrogate(n_tr, width, depth, 64)
+    net.set_scaling(I.SURR_LO, I.SURR_HI, scale)
+    net.set_params(torch.from_numpy(flat).cuda())
+    ctx = Context(prob)
+    ctx.set_surrogate(net)
+    ctx.set_train_precision(B.TRAINS_FP16)
+    got = ctx.simulate(_dev(torch, th, torch.float32)).cpu().numpy().astype(np.float64)
+    fb = np.zeros(prob.nv, dtype=bool)
+    fb[out] = True
+    assert ctx.fallback_count() == 40
+    parts = M.unpack(flat.astype(np.float64), n_tr, width, depth)
+    for l in range(1, depth + 1):
+        u = parts[2 * l].astype(np.float32).view(np.uint32).astype(np.uint64)
+        parts[2 * l] = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32) \
+            .view(np.float32).astype(np.float64)
+    y, _ = M.forward(np.concatenate([p.reshape(-1) for p in parts]),
+                     M.normalise_inputs(th[:3], I.SURR_LO, I.SURR_HI), n_tr, width, depth)
+    net_tr = y[4 * n_tr:].reshape(4, n_tr, prob.nv) * scale.astype(np.float64)[:, None, None]
+    epg = oracle_lib.epg(prob, th).imag
+    for p in range(4):
+        e_fb = _rel(got[p][:, fb], epg[p][:, fb])
+        e_in = _rel(got[p][:, ~fb], net_tr[p][:, ~fb])
+        print(f"\n  train {p}: fallback {e_fb:.2e} network {e_in:.2e}", flush=True)
+        assert e_fb <= 6e-4 and e_in <= 2e-2
+    ctx.close()
+    net.close()

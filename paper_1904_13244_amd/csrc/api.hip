@@ -6,6 +6,7 @@
 #include "mlp_internal.h"
 #include "mrstat_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>

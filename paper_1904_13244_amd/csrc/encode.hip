@@ -21,6 +21,8 @@
 // Trains are stored as float or _Float16 (TT); arithmetic is FP32.
 #include "mrstat_internal.h"
 
+#include <type_traits>
+
 namespace mrstat {
 namespace {
 
@@ -207,21 +209,25 @@ __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
 // ------------------------------------------------------------------------
 constexpr int ADJ_EY_ROWS = 4;   // rows of a 256-voxel block when nx >= 128
 
-template <int NTRAIN, int CC, int NBA, typename TT>
+template <int NTRAIN, int CC, int NBA, typename TT, int VX>
 __global__ __launch_bounds__(256) void ystage_adj_kernel(
     const TT* __restrict__ trains, const float2* __restrict__ coil,
     const uint8_t* __restrict__ mask, const float2* __restrict__ eytab,
     const float2* __restrict__ W, float* __restrict__ apart, int nx, int ny, int nv, int T,
     int C, int n_per_chunk)
 {
+    // VX consecutive voxels per thread (VX = 2: FP16 trains read as pairs,
+    // nx even, so a pair never straddles a row); a block spans 256 VX voxels.
+    constexpr int BV = 256 * VX;
+    typedef TT tv2 __attribute__((ext_vector_type(2)));
     extern __shared__ float2 eys[];   // [n_per_chunk][rows]
-    const int jb = blockIdx.x * 256;
-    const int j0 = jb + threadIdx.x;
+    const int jb = blockIdx.x * BV;
+    const int j0 = jb + VX * threadIdx.x;
     const bool ok = j0 < nv;
-    const int j = ok ? j0 : nv - 1;
+    const int j = ok ? j0 : nv - VX;
     const int ix = j % nx, iy = j / nx;
     const int row0 = jb / nx;
-    const int rows = (min(jb + 255, nv - 1)) / nx - row0 + 1;
+    const int rows = (min(jb + BV - 1, nv - 1)) / nx - row0 + 1;
     const int chunk = blockIdx.y;
     const int n0 = chunk * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
@@ -234,64 +240,90 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
     __syncthreads();
     const int myrow = iy - row0;
 
-    float2 cw[CC];
+    float2 cw[VX][CC];
     if constexpr (CC > 1) {
 #pragma unroll
-        for (int c = 0; c < CC; ++c)
-            cw[c] = c < C ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
-    }
-    float2 acc[NTRAIN];
+        for (int u = 0; u < VX; ++u)
 #pragma unroll
-    for (int p = 0; p < NTRAIN; ++p) acc[p] = make_float2(0.f, 0.f);
+            for (int c = 0; c < CC; ++c)
+                cw[u][c] = c < C ? coil[(size_t)c * nv + j + u] : make_float2(0.f, 0.f);
+    }
+    float2 acc[VX][NTRAIN];
+#pragma unroll
+    for (int u = 0; u < VX; ++u)
+#pragma unroll
+        for (int p = 0; p < NTRAIN; ++p) acc[u][p] = make_float2(0.f, 0.f);
 
     for (int nb0 = n0; nb0 < n1; nb0 += NBA) {
-        float2 wv[NBA][CC];
-        float mu[NBA][NTRAIN];
+        float2 wv[NBA][VX][CC];
+        float mu[NBA][VX][NTRAIN];
 #pragma unroll
         for (int b = 0; b < NBA; ++b) {
             const int n = min(nb0 + b, n1 - 1);
 #pragma unroll
             for (int c = 0; c < CC; ++c) {
                 const int cc = c < C ? c : 0;
-                wv[b][c] = W[((size_t)cc * T + n) * nx + ix];
+                const float2* wrow = W + ((size_t)cc * T + n) * nx + ix;
+                if constexpr (VX == 2) {
+                    const float4 w2 = *reinterpret_cast<const float4*>(wrow);
+                    wv[b][0][c] = make_float2(w2.x, w2.y);
+                    wv[b][1][c] = make_float2(w2.z, w2.w);
+                } else {
+                    wv[b][0][c] = wrow[0];
+                }
             }
             const TT* __restrict__ t0 = trains + (size_t)n * nv;
 #pragma unroll
-            for (int p = 0; p < NTRAIN; ++p) mu[b][p] = (float)(t0 + p * plane)[j];
+            for (int p = 0; p < NTRAIN; ++p) {
+                if constexpr (VX == 2) {
+                    const tv2 a = *reinterpret_cast<const tv2*>(t0 + p * plane + j);
+                    mu[b][0][p] = (float)a.x;
+                    mu[b][1][p] = (float)a.y;
+                } else {
+                    mu[b][0][p] = (float)(t0 + p * plane)[j];
+                }
+            }
         }
 #pragma unroll
         for (int b = 0; b < NBA; ++b) {
             const int nl = min(nb0 + b, n1 - 1) - n0;
             const float keep = (nb0 + b < n1) ? 1.f : 0.f;
-            float2 wc;
-            if constexpr (CC == 1) {
-                wc = wv[b][0];
-            } else {
-                wc = make_float2(0.f, 0.f);
+            const float2 eyc = eys[nl * rows + myrow];
 #pragma unroll
-                for (int c = 0; c < CC; ++c) {
-                    const float2 t = cmulconj(cw[c], wv[b][c]);
-                    wc.x += t.x;
-                    wc.y += t.y;
+            for (int u = 0; u < VX; ++u) {
+                float2 wc;
+                if constexpr (CC == 1) {
+                    wc = wv[b][u][0];
+                } else {
+                    wc = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int c = 0; c < CC; ++c) {
+                        const float2 t = cmulconj(cw[u][c], wv[b][u][c]);
+                        wc.x += t.x;
+                        wc.y += t.y;
+                    }
                 }
-            }
-            float2 V = cmulconj(eys[nl * rows + myrow], wc);
-            V.x *= keep;
-            V.y *= keep;
+                float2 V = cmulconj(eyc, wc);
+                V.x *= keep;
+                V.y *= keep;
 #pragma unroll
-            for (int p = 0; p < NTRAIN; ++p) {
-                acc[p].x = fmaf(mu[b][p], V.x, acc[p].x);
-                acc[p].y = fmaf(mu[b][p], V.y, acc[p].y);
+                for (int p = 0; p < NTRAIN; ++p) {
+                    acc[u][p].x = fmaf(mu[b][u][p], V.x, acc[u][p].x);
+                    acc[u][p].y = fmaf(mu[b][u][p], V.y, acc[u][p].y);
+                }
             }
         }
     }
     if (!ok) return;
-    const bool on = mask == nullptr || mask[j] != 0;
-    float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j;
 #pragma unroll
-    for (int p = 0; p < NTRAIN; ++p) {
-        dst[(2 * p) * (size_t)nv] = on ? acc[p].x : 0.f;
-        dst[(2 * p + 1) * (size_t)nv] = on ? acc[p].y : 0.f;
+    for (int u = 0; u < VX; ++u) {
+        const bool on = mask == nullptr || mask[j + u] != 0;
+        float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j + u;
+#pragma unroll
+        for (int p = 0; p < NTRAIN; ++p) {
+            dst[(2 * p) * (size_t)nv] = on ? acc[u][p].x : 0.f;
+            dst[(2 * p + 1) * (size_t)nv] = on ? acc[u][p].y : 0.f;
+        }
     }
 }
 
@@ -757,13 +789,25 @@ hipError_t adj_launch(const Dims& d, const YPlan& p, const TT* trains, const flo
                       const uint8_t* mask, const float2* eytab, const float2* W, float* apart,
                       hipStream_t s)
 {
+    // FP16 pairs (nx even, one coil): 512 voxels per block, twice the TRs
+    // per batch, so the bytes in flight match the FP32 kernel.
+    if constexpr (std::is_same<TT, _Float16>::value && CC == 1) {
+        if (d.nx % 2 == 0) {
+            dim3 grid(ceil_div(d.nv, 512), p.adj_chunks);
+            const int rows = std::min(d.ny, 512 / d.nx + 2);
+            const size_t lds = (size_t)p.adj_per_chunk * rows * sizeof(float2);
+            ystage_adj_kernel<NTRAIN, CC, 8, TT, 2><<<grid, 256, lds, s>>>(
+                trains, coil, mask, eytab, W, apart, d.nx, d.ny, d.nv, d.T, d.C, p.adj_per_chunk);
+            return hipGetLastError();
+        }
+    }
     dim3 grid(ceil_div(d.nv, 256), p.adj_chunks);
     const int rows = std::min(d.ny, 256 / d.nx + 2);
     const size_t lds = (size_t)p.adj_per_chunk * rows * sizeof(float2);
     constexpr int NBA = CC == 1 ? 4 : 2;
-    ystage_adj_kernel<NTRAIN, CC, NBA, TT><<<grid, 256, lds, s>>>(trains, coil, mask, eytab, W, apart,
-                                                             d.nx, d.ny, d.nv, d.T, d.C,
-                                                             p.adj_per_chunk);
+    ystage_adj_kernel<NTRAIN, CC, NBA, TT, 1><<<grid, 256, lds, s>>>(trains, coil, mask, eytab, W, apart,
+                                                                    d.nx, d.ny, d.nv, d.T, d.C,
+                                                                    p.adj_per_chunk);
     return hipGetLastError();
 }
 
@@ -786,8 +830,9 @@ YPlan make_yplan(const Dims& d)
     // sums of 8 chunks x 8 floats per voxel.
     p.r_adj = 1;
     p.adj_chunks = std::min(8, d.T);
-    // LDS staging of the y-phases: chunk TRs x rows of a block (<= 64 KB).
-    const int rows = std::min(d.ny, 256 / d.nx + 2);
+    // LDS staging of the y-phases: chunk TRs x rows of a block (<= 64 KB;
+    // rows of the 512-voxel blocks of the FP16 pair kernel).
+    const int rows = std::min(d.ny, 512 / d.nx + 2);
     while (ceil_div(d.T, p.adj_chunks) * rows * 8 > 65536) ++p.adj_chunks;
     p.adj_per_chunk = ceil_div(d.T, p.adj_chunks);
     p.adj_chunks = ceil_div(d.T, p.adj_per_chunk);

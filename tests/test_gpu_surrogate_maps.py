@@ -1,0 +1,88 @@
+"""What the trained surrogate gains, and what it costs in map accuracy.
+
+At the 224 x 224, 1120-TR workload the network is trained on the GPU by the
+library's own kernels (2M box samples simulated by the library's EPG), then
+the same Gauss-Newton reconstruction (T1, T2, rho; B1 known; head mask; from
+the standard initial guess with rho from CGLS) runs twice: plain (FP32 EPG
+trains, FP32 encoding contraction) and surrogate (network trains stored in
+FP16, EPG outside the box, split-BF16 encoding contraction). The plain run is
+the reference the surrogate is judged against: EPG judges the surrogate's
+maps, stated as T1/T2 MAPE over the head. Bars (from measurement with
+margin): held-out train error <= 2 % for m and the T1/T2 derivatives,
+<= 15 % for dm/dB1 (not used with B1 known); maps within 2 % (T1) and 3 %
+(T2) MAPE of the plain maps; the surrogate GN step at least 1.2x faster.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1904_13244_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_13244_amd import binding
+    binding.lib()
+    return torch
+
+
+def _mape(a, b, sel):
+    return 100.0 * float(np.mean(np.abs(np.exp(a[sel]) - np.exp(b[sel])) / np.exp(b[sel])))
+
+
+def test_trained_surrogate_maps_and_speed(torch_gpu):
+    torch = torch_gpu
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    from paper_1904_13244_amd.surrogate import train_surrogate
+    w = I.config(4)
+    prob, head = w.problem, w.extra["head"]
+    print(f"\n[surrogate maps] {w.name}", flush=True)
+    net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=40)
+    print(f"  trained {rep.steps} steps in {rep.seconds_train:.1f} s; held-out rel err "
+          f"{['%.2e' % e for e in rep.val_rel_err]}", flush=True)
+    assert max(rep.val_rel_err[:3]) <= 2e-2 and rep.val_rel_err[3] <= 0.15
+
+    ctx = Context(prob, mask=torch.as_tensor(head.astype(np.uint8)).cuda())
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    zero = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+    _, r = ctx.residual(dev(w.theta, torch.float32), zero)
+    d = (-r).contiguous()
+    th0 = I.initial_theta(prob.nv)
+    th0[2] = w.theta[2]                      # B1 known
+    box_lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
+    box_hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
+    maps, ms = {}, {}
+    for name, sur, enc, prec, lo, hi in (
+            ("plain", None, B.ENC_FP32, B.TRAINS_FP32, I.GN_LO, I.GN_HI),
+            ("surrogate", net, B.ENC_SPLIT_BF16, B.TRAINS_FP16, box_lo, box_hi)):
+        ctx.set_surrogate(sur)
+        ctx.set_encoding(enc)
+        ctx.set_train_precision(prec)
+        th = dev(th0, torch.float32)
+        ctx.rho_init(th, d, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            rp = ctx.gn_step(th, d, w.n_cg, w.param_mask, lo, hi)
+            assert rp.n_fallback == 0
+        torch.cuda.synchronize()
+        ms[name] = 1e3 * (time.perf_counter() - t0) / 10
+        maps[name] = th.cpu().numpy().astype(np.float64)
+        print(f"  [{name}] {ms[name]:.2f} ms/GN step; T1 MAPE vs truth "
+              f"{_mape(maps[name][0], w.theta[0], head):.3f} %, T2 "
+              f"{_mape(maps[name][1], w.theta[1], head):.3f} %", flush=True)
+    t1 = _mape(maps["surrogate"][0], maps["plain"][0], head)
+    t2 = _mape(maps["surrogate"][1], maps["plain"][1], head)
+    print(f"  surrogate vs plain maps: T1 MAPE {t1:.3f} %, T2 MAPE {t2:.3f} %; "
+          f"speedup {ms['plain'] / ms['surrogate']:.2f}x", flush=True)
+    assert t1 <= 2.0 and t2 <= 3.0
+    assert ms["plain"] / ms["surrogate"] >= 1.2
+    ctx.close()
+    net.close()

@@ -50,12 +50,23 @@ def _coils():
     return prob, th, I.coil_maps(24, 20, 4), mask
 
 
+def _even_ragged():
+    """nx even (FP16 pair kernels) but not a multiple of 64, ny over two row
+    blocks of the pair kernel, a mask."""
+    rng = np.random.default_rng(79)
+    T = 40
+    prob = I.make_problem(46, 70, T, 52, 10, flip_deg=rng.uniform(5, 70, T), t_inv=0.01)
+    th = I.iid_maps(prob.nv, seed=10, b1=rng.uniform(0.8, 1.2, prob.nv))
+    mask = (rng.uniform(size=prob.nv) > 0.1).astype(np.uint8)
+    return prob, th, None, mask
+
+
 def _config1():
     w = I.config(1)
     return w.problem, w.theta, None, None
 
 
-CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils}
+CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils, "even_ragged": _even_ragged}
 
 
 @pytest.mark.parametrize("name", list(CASES))

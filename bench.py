@@ -141,7 +141,8 @@ def roofline_for(kernels, prob, tb):
     if unit == "bytes":
         ach = amount / t / 1e9
         return {"kernel": rk, "bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(rk),
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic(rk + ("_f16" if tb == 2 else "_f32")),
                 "algorithmic_bytes_per_launch": amount}
     ach = amount / t / 1e12
     return {"kernel": rk, "bound": bound, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,

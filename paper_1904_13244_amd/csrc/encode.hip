@@ -61,29 +61,35 @@ __device__ __forceinline__ float2 shfl_xor2(float2 v, int m)
 // ------------------------------------------------------------------------
 constexpr int FW = 16;
 
-template <int MODE, int R, int CC, typename TT>
+// WR = rows per wave step: 2 (32 columns per block, lanes 0-31 and 32-63 on
+// two adjacent rows; 128-byte rows of FP32 trains) or 1 (64 columns per
+// block, one row per wave: whole 128-byte lines of FP16 trains, which the
+// two-row layout would read as halves from two blocks).
+template <int MODE, int R, int CC, typename TT, int WR>
 __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
     const float2* __restrict__ eytab, float2* __restrict__ U, int nx, int ny, int nv, int T, int C,
     int n_per_chunk)
 {
-    // LDS: per-wave sums [TRs per chunk][CC][FW][32], then the block's
-    // y-phases [TRs per chunk][32 R].
+    constexpr int XW = 64 / WR;          // columns per block
+    constexpr int RS = FW * WR;          // rows per step of the block
+    // LDS: per-wave sums [TRs per chunk][CC][FW][XW], then the block's
+    // y-phases [TRs per chunk][RS R].
     extern __shared__ float2 lds[];
-    float2* eys = lds + (size_t)n_per_chunk * CC * FW * 32;
+    float2* eys = lds + (size_t)n_per_chunk * CC * FW * XW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xl = lane & 31, half = lane >> 5;
-    const int ix = blockIdx.x * 32 + xl;
+    const int xl = lane % XW, half = lane / XW;   // half = 0 when WR = 1
+    const int ix = blockIdx.x * XW + xl;
     const int yb = blockIdx.y;
-    const int iyb = yb * 32 * R + 2 * wave + half;
+    const int iyb = yb * RS * R + WR * wave + half;
     const int n0 = blockIdx.z * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
     const bool colok = ix < nx;
     const size_t plane = (size_t)T * nv;
-    for (int e = threadIdx.x; e < (n1 - n0) * 32 * R; e += blockDim.x) {
-        const int nl = e / (32 * R), rr = e % (32 * R);
-        const int iy = yb * 32 * R + rr;
+    for (int e = threadIdx.x; e < (n1 - n0) * RS * R; e += blockDim.x) {
+        const int nl = e / (RS * R), rr = e % (RS * R);
+        const int iy = yb * RS * R + rr;
         eys[e] = iy < ny ? eytab[(size_t)(n0 + nl) * ny + iy] : make_float2(0.f, 0.f);
     }
     __syncthreads();
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     float2 cw[R][CC];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int iy = iyb + 32 * r;
+        const int iy = iyb + RS * r;
         const bool ok = colok && iy < ny;
         const int j = ok ? iy * nx + ix : 0;   // invalid voxels read voxel 0 with zero weight
         jr[r] = j;
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         const TT* __restrict__ b1 = b0 + plane;
         const TT* __restrict__ b2 = b1 + plane;
         const TT* __restrict__ b3 = b2 + plane;
-        const float2* eyrow = eys + (size_t)(n - n0) * 32 * R + 2 * wave + half;
+        const float2* eyrow = eys + (size_t)(n - n0) * RS * R + WR * wave + half;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             mu[r] = (float)b0[jr[r]];
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
                 m2[r] = (float)b2[jr[r]];
                 m3[r] = (float)b3[jr[r]];
             }
-            ey[r] = eyrow[32 * r];
+            ey[r] = eyrow[RS * r];
         }
         float2 acc[CC];
 #pragma unroll
@@ -159,25 +165,29 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         }
 #pragma unroll
         for (int c = 0; c < CC; ++c) {
-            const float2 t = shfl_xor2(acc[c], 32);
-            if (half == 0)
-                lds[(((n - n0) * CC + c) * FW + wave) * 32 + xl] =
-                    make_float2(acc[c].x + t.x, acc[c].y + t.y);
+            if constexpr (WR == 2) {
+                const float2 t = shfl_xor2(acc[c], 32);
+                if (half == 0)
+                    lds[(((n - n0) * CC + c) * FW + wave) * XW + xl] =
+                        make_float2(acc[c].x + t.x, acc[c].y + t.y);
+            } else {
+                lds[(((n - n0) * CC + c) * FW + wave) * XW + xl] = acc[c];
+            }
         }
     }
     __syncthreads();
-    const int nout = (n1 - n0) * CC * 32;
+    const int nout = (n1 - n0) * CC * XW;
     for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-        const int l = o & 31, bc = o >> 5;   // bc = TR-in-chunk * CC + c
-        float2 s = lds[(bc * FW) * 32 + l];
+        const int l = o % XW, bc = o / XW;   // bc = TR-in-chunk * CC + c
+        float2 s = lds[(bc * FW) * XW + l];
 #pragma unroll
         for (int w = 1; w < FW; ++w) {
-            const float2 t = lds[(bc * FW + w) * 32 + l];
+            const float2 t = lds[(bc * FW + w) * XW + l];
             s.x += t.x;
             s.y += t.y;
         }
         const int b = bc / CC, c = bc % CC;
-        const int oix = blockIdx.x * 32 + l;
+        const int oix = blockIdx.x * XW + l;
         if (oix < nx && c < C) U[(((size_t)yb * C + c) * T + (n0 + b)) * nx + oix] = s;
     }
 }
@@ -765,12 +775,28 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* t
                  const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
                  float2* U, hipStream_t s)
 {
+    // 2-byte trains take the one-row-per-wave layout (single coil).
+    if constexpr (sizeof(TT) == 2 && CC == 1) {
+        dim3 grid(ceil_div(d.nx, 64), p.nby16, ceil_div(d.T, p.fwd_tr16));
+        const size_t lds = (size_t)p.fwd_tr16 * (FW * 64 + FW * p.r_fwd16) * sizeof(float2);
+        switch (p.r_fwd16) {
+#define FWD16_CASE(RR)                                                                          \
+    case RR:                                                                                    \
+        ystage_fwd_kernel<MODE, RR, 1, TT, 1><<<grid, FW * 64, lds, s>>>(                       \
+            trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr16);    \
+        break;
+            FWD16_CASE(1) FWD16_CASE(2) FWD16_CASE(3) FWD16_CASE(4)
+#undef FWD16_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     dim3 grid(ceil_div(d.nx, 32), p.nby, ceil_div(d.T, p.fwd_tr));
     const size_t lds = (size_t)p.fwd_tr * (CC * FW * 32 + 32 * p.r_fwd) * sizeof(float2);
 #define FWD_CASE(RR)                                                                            \
     case RR:                                                                                    \
         if constexpr (CC == 1 || RR <= 2)                                                       \
-            ystage_fwd_kernel<MODE, RR, CC, TT><<<grid, FW * 64, lds, s>>>(                     \
+            ystage_fwd_kernel<MODE, RR, CC, TT, 2><<<grid, FW * 64, lds, s>>>(                  \
                 trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr);  \
         else                                                                                    \
             return hipErrorInvalidValue;                                                        \
@@ -825,6 +851,12 @@ YPlan make_yplan(const Dims& d)
     p.r_fwd = ceil_div(d.ny, 32 * p.nby);
     // TRs per block: the chunk's per-wave sums live in LDS (at most 64 KB).
     p.fwd_tr = d.C == 1 ? 16 : (d.C <= 8 ? 2 : 1);
+    // One-row-per-wave layout (FP16 trains, one coil): 16 rows per step, at
+    // most 2 steps per lane (57 VGPRs, ~68 KB of LDS: two blocks per CU, so
+    // twice the loads in flight), 8 TRs per block.
+    p.nby16 = ceil_div(d.ny, 32);
+    p.r_fwd16 = ceil_div(d.ny, 16 * p.nby16);
+    p.fwd_tr16 = 8;
     // Adjoint: one row per lane (8 rows per block) and 8 TR chunks: enough
     // blocks in flight to stream the trains near the HBM limit, with partial
     // sums of 8 chunks x 8 floats per voxel.
@@ -883,9 +915,10 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
     const hipError_t e =
         f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, s)
             : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, s);
-    if (e != hipSuccess || p.nby == 1) return e;
+    const int nby = (f16 && d.C == 1) ? p.nby16 : p.nby;
+    if (e != hipSuccess || nby == 1) return e;
     const size_t count = (size_t)d.C * d.T * d.nx;
-    usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, p.nby, count);
+    usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, nby, count);
     return hipGetLastError();
 }
 

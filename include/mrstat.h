@@ -296,8 +296,10 @@ mrstat_status mrstat_mlp_train_step(mrstat_mlp net, const float *d_theta, int64_
                                     const float *d_trains, int64_t ld_trains, float lr,
                                     double *h_loss, mrstat_stream stream);
 /* Tuning: voxels per workgroup of the fused inference kernel (widths 64, 128
- * and 256 evaluate the whole network per voxel tile in one kernel): 32 or 64,
- * 0 = automatic (64). Results are identical for every choice. */
+ * and 256 evaluate the whole network per voxel tile in one kernel): 32 or 64
+ * with the last activations held in registers, -32 or -64 with them read from
+ * LDS (more output-weight loads in flight); 0 = automatic (-64 at width 256,
+ * else 64). Results are identical for every choice. */
 mrstat_status mrstat_mlp_set_infer_tile(mrstat_mlp net, int32_t voxels);
 /* Predicted trains (imaginary parts, s_p applied) for n columns of d_theta
  * into d_out float32 [4][n_tr][n]. */

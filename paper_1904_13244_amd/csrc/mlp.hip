@@ -295,8 +295,13 @@ __device__ __forceinline__ uint32_t pack2(float a, float b)
 // ------------------------------------------------------------------------
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 
-template <int WIDTH, int NV, bool PF, bool F16>
-__global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
+// PF: 0 = weights loaded per tile, activations (A fragments) in registers;
+// 1 = two tiles of weights in flight, activations in registers; 2 / 3 = two
+// / three tiles of weights in flight, activations read from LDS per tile
+// (frees the registers that hold them, so more weight loads are in flight).
+template <int WIDTH, int NV, int PF, bool F16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF >= 2 ? 2 : 1)))
+void mlp_infer_kernel(InferArgs a)
 {
     constexpr int HP = WIDTH + 8, KS = WIDTH / 32, MT = WIDTH / 64, VT = NV / 16;
     __shared__ __attribute__((aligned(16))) uint16_t Hs[2][NV][HP];
@@ -369,13 +374,17 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
         cur = nxt;
     }
 
-    // Output layer: A = activations^T (voxel rows) in registers.
-    uint4 hf[VT][KS];
+    // Output layer: A = activations^T (voxel rows), in registers (PF < 3)
+    // or read from LDS per tile (PF = 3).
+    constexpr bool AREG = PF < 2;
+    uint4 hf[AREG ? VT : 1][AREG ? KS : 1];
+    if constexpr (AREG) {
 #pragma unroll
-    for (int t = 0; t < VT; ++t)
+        for (int t = 0; t < VT; ++t)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            hf[t][ks] = *reinterpret_cast<const uint4*>(&Hs[cur][t * 16 + lr][ks * 32 + lk]);
+            for (int ks = 0; ks < KS; ++ks)
+                hf[t][ks] = *reinterpret_cast<const uint4*>(&Hs[cur][t * 16 + lr][ks * 32 + lk]);
+    }
 
     const int n_tiles = (a.m_out + 15) / 16;
     const bool vec_ok = (a.ld_out % 4) == 0;
@@ -394,9 +403,13 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int t = 0; t < VT; ++t)
+            for (int t = 0; t < VT; ++t) {
+                uint4 af;
+                if constexpr (AREG) af = hf[t][ks];
+                else af = *reinterpret_cast<const uint4*>(&Hs[cur][t * 16 + lr][ks * 32 + lk]);
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8, hf[t][ks]), __builtin_bit_cast(bf16x8, b[ks]), acc[t], 0, 0, 0);
+                    __builtin_bit_cast(bf16x8, af), __builtin_bit_cast(bf16x8, b[ks]), acc[t], 0, 0, 0);
+            }
         const int o = tile * 16 + lr;
         if (o < a.m_out) {
             const int p = o / a.T, nt = o - p * a.T;
@@ -408,24 +421,39 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferArgs a)
                 const int jv = j0 + t * 16 + 4 * (lane >> 4);
                 const float y0 = (acc[t][0] + bias) * sc, y1 = (acc[t][1] + bias) * sc;
                 const float y2 = (acc[t][2] + bias) * sc, y3 = (acc[t][3] + bias) * sc;
-                // Written once and read by a later kernel: streamed past the
-                // caches so the output weights stay resident in L2.
+                // FP32: 64-byte row pieces, streamed past the caches so the
+                // output weights stay resident in L2. FP16: 32-byte pieces,
+                // left to L2 to merge into whole lines (the tile's four
+                // stores cover 128 bytes of each row).
                 if (vec_ok && jv + 3 < a.n) {
                     if constexpr (F16)
-                        __builtin_nontemporal_store(h4v{(_Float16)y0, (_Float16)y1, (_Float16)y2, (_Float16)y3},
-                                                    reinterpret_cast<h4v*>(dst + jv));
+                        *reinterpret_cast<h4v*>(dst + jv) = h4v{(_Float16)y0, (_Float16)y1, (_Float16)y2, (_Float16)y3};
                     else
                         __builtin_nontemporal_store(f4{y0, y1, y2, y3}, reinterpret_cast<f4*>(dst + jv));
                 } else {
-                    if (jv < a.n) __builtin_nontemporal_store((OT)y0, dst + jv);
-                    if (jv + 1 < a.n) __builtin_nontemporal_store((OT)y1, dst + jv + 1);
-                    if (jv + 2 < a.n) __builtin_nontemporal_store((OT)y2, dst + jv + 2);
-                    if (jv + 3 < a.n) __builtin_nontemporal_store((OT)y3, dst + jv + 3);
+                    if (jv < a.n) dst[jv] = (OT)y0;
+                    if (jv + 1 < a.n) dst[jv + 1] = (OT)y1;
+                    if (jv + 2 < a.n) dst[jv + 2] = (OT)y2;
+                    if (jv + 3 < a.n) dst[jv + 3] = (OT)y3;
                 }
             }
         }
     };
-    if constexpr (PF) {
+    if constexpr (PF == 3) {
+        uint4 b0[KS], b1[KS], b2[KS];
+        load_b(b0, wave);
+        load_b(b1, wave + 4);
+        for (int tile = wave; tile < n_tiles; tile += 12) {
+            load_b(b2, tile + 8);
+            tile_out(b0, tile);
+            if (tile + 4 >= n_tiles) break;
+            load_b(b0, tile + 12);
+            tile_out(b1, tile + 4);
+            if (tile + 8 >= n_tiles) break;
+            load_b(b1, tile + 16);
+            tile_out(b2, tile + 8);
+        }
+    } else if constexpr (PF == 1 || PF == 2) {
         uint4 b0[KS], b1[KS];
         load_b(b0, wave);
         for (int tile = wave; tile < n_tiles; tile += 8) {
@@ -501,20 +529,26 @@ bool infer_fused_supported(int width, int depth) { return (width == 64 || width 
 
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s)
 {
-    if (tile == 0) tile = 64;
-    const int grid = ceil_div(a.n, tile);
-#define INFER(W_, NV_, PF_)                                                  \
-    if (width == W_ && tile == NV_) {                                        \
+    if (tile == 0) tile = width == 256 ? -64 : 64;
+    const int grid = ceil_div(a.n, tile < 0 ? -tile : tile);
+#define INFER(W_, NV_, T_, PF_)                                              \
+    if (width == W_ && tile == T_) {                                         \
         if (a.f16) mlp_infer_kernel<W_, NV_, PF_, true><<<grid, 256, 0, s>>>(a);   \
         else mlp_infer_kernel<W_, NV_, PF_, false><<<grid, 256, 0, s>>>(a);        \
         return hipGetLastError();                                            \
     }
-    INFER(64, 64, true)
-    INFER(64, 32, true)
-    INFER(128, 64, true)
-    INFER(128, 32, true)
-    INFER(256, 64, false)
-    INFER(256, 32, true)
+    INFER(64, 64, 64, 1)
+    INFER(64, 32, 32, 1)
+    INFER(128, 64, 64, 1)
+    INFER(128, 32, 32, 1)
+    INFER(256, 64, 64, 0)
+    INFER(256, 32, 32, 1)
+    // Negative tile: the same voxel tile with activations read from LDS and
+    // three weight tiles in flight.
+    INFER(64, 64, -64, 3)
+    INFER(128, 64, -64, 3)
+    INFER(256, 64, -64, 2)
+    INFER(256, 32, -32, 3)
 #undef INFER
     return hipErrorInvalidValue;
 }

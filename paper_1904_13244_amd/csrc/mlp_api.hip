@@ -319,8 +319,8 @@ size_t mrstat_mlp_workspace_bytes(mrstat_mlp net) { return net ? net->total : 0;
 mrstat_status mrstat_mlp_set_infer_tile(mrstat_mlp net, int32_t voxels)
 {
     if (!net) return MRSTAT_ERR_ARG;
-    if (!(voxels == 0 || voxels == 32 || voxels == 64))
-        return mfail(net, MRSTAT_ERR_ARG, "voxels per workgroup must be 0, 32 or 64");
+    if (!(voxels == 0 || voxels == 32 || voxels == 64 || voxels == -32 || voxels == -64))
+        return mfail(net, MRSTAT_ERR_ARG, "voxels per workgroup must be 0, +-32 or +-64");
     net->infer_tile = voxels;
     return MRSTAT_OK;
 }

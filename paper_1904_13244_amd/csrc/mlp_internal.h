@@ -59,7 +59,8 @@ struct InferArgs {
     bool f16;                      // trains stored as FP16
 };
 bool infer_fused_supported(int width, int depth);
-// tile: voxels per workgroup, 32 or 64 (0 = default).
+// tile: voxels per workgroup, 32 or 64 (activations in registers), -32 or
+// -64 (activations read from LDS); 0 = default.
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s);
 
 hipError_t launch_gemm_bf16(bool ta, bool tb, int epi, const GemmArgs& g, hipStream_t s);

@@ -155,7 +155,7 @@ def test_predict_ragged_columns_over_several_chunks(torch_gpu):
     print(f"\n[predict ragged] n={n}: rel {e:.2e}", flush=True)
     assert e < 2e-2
     # Every voxel tile of the fused kernel computes the same values.
-    for tile in (32, 64):
+    for tile in (32, 64, -64):
         net.set_infer_tile(tile)
         other = net.predict(th_d).cpu().numpy().astype(np.float64)
         assert np.array_equal(other, pred), tile

@@ -55,3 +55,29 @@ def test_loss_zero_at_own_output_and_target_layout():
     assert t[4 * T + 2 * T + 1, 1] == tr[2, 1, 1] / 4.0
     xs = mlp.normalise_inputs(np.array([[math.log(0.1)], [math.log(2.0)], [1.0]]), I.SURR_LO, I.SURR_HI)
     assert np.allclose(xs[:, 0], [-1.0, 1.0, 0.0])
+
+
+def test_forward_special_case_pins_weight_orientation():
+    """A width-2, depth-2 network whose weights route single units: with
+    z1 = (1, 0), h1 = (Phi(1), 0); the hidden weight [[1, 0], [1, 0]] copies
+    unit 0 into both units (its transpose would give (Phi(1), 0) instead);
+    the output layer reads unit 1 into output o (and nothing elsewhere), so
+    y_o = gelu(Phi(1)) + bias, computed here from math.erf."""
+    from oracle import mlp
+    T, width, depth = 1, 2, 2
+    W1 = np.array([[2.0, 0.0, 0.0], [0.0, 0.0, 0.0]])     # z1 = (2 x0, 0) + b1
+    b1 = np.array([0.0, 0.0])
+    W2 = np.array([[1.0, 0.0], [1.0, 0.0]])
+    b2 = np.array([0.0, 0.0])
+    Wo = np.zeros((8 * T, width))
+    o = 5
+    Wo[o, 1] = 1.0
+    bo = np.linspace(-0.3, 0.4, 8 * T)
+    flat = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, Wo.ravel(), bo])
+    x = np.array([[0.5], [0.3], [-0.7]])                  # 2 x0 = 1
+    y, _ = mlp.forward(flat, x, T, width, depth)
+    phi1 = 0.5 * (1.0 + math.erf(1.0 / math.sqrt(2.0)))
+    h = phi1 * 0.5 * (1.0 + math.erf(phi1 / math.sqrt(2.0)))
+    expect = bo.copy()
+    expect[o] += h
+    assert np.allclose(y[:, 0], expect, rtol=0, atol=1e-14)

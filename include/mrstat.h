@@ -229,6 +229,11 @@ typedef enum {
 
 mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on);
 mrstat_status mrstat_profile_read(mrstat_ctx ctx, int32_t *h_counts, double *h_ms);
+/* Kinds traced while profiling is on: bit k of kind_mask = kind k (default
+ * all). Each traced launch adds two event records to its stream (about 1.5 us
+ * of device time each), so tracing only the kinds of interest keeps a timed
+ * region close to its untraced duration. */
+mrstat_status mrstat_profile_select(mrstat_ctx ctx, uint32_t kind_mask);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the EPG linearisation.

@@ -81,6 +81,7 @@ def lib():
             "mrstat_rho_init": ([vp, vp, vp, i32, vp], C.c_int),
             "mrstat_profile_enable": ([vp, i32], C.c_int),
             "mrstat_profile_read": ([vp, P(i32), P(C.c_double)], C.c_int),
+            "mrstat_profile_select": ([vp, C.c_uint32], C.c_int),
             "mrstat_set_surrogate": ([vp, vp], C.c_int),
             "mrstat_fallback_count": ([vp, P(i32), vp], C.c_int),
             "mrstat_mlp_create": ([i32, i32, i32, i32, P(vp)], C.c_int),
@@ -118,7 +119,8 @@ def exported_symbols():
             "mrstat_mlp_param_count", "mrstat_mlp_workspace_bytes", "mrstat_mlp_bind",
             "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
-            "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision"]
+            "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
+            "mrstat_profile_select"]
 
 
 def _check(status, ctx=None):
@@ -294,6 +296,12 @@ def mrstat_profile_enable(ctx, on):
     _check(lib().mrstat_profile_enable(ctx, 1 if on else 0), ctx)
 
 
+def mrstat_profile_select(ctx, kinds=None):
+    """Trace only the named kernel kinds (None = all)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << KERNEL_KINDS.index(k) for k in kinds)
+    _check(lib().mrstat_profile_select(ctx, mask), ctx)
+
+
 def mrstat_profile_read(ctx):
     """{kind: (launches, total ms)} since profiling was enabled."""
     n = len(KERNEL_KINDS)
@@ -372,6 +380,9 @@ class Context:
 
     def profile_read(self):
         return mrstat_profile_read(self.h)
+
+    def profile_select(self, kinds=None):
+        mrstat_profile_select(self.h, kinds)
 
     def set_epg_lanes(self, lanes):
         mrstat_set_epg_lanes(self.h, lanes)

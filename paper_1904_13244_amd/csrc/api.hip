@@ -51,6 +51,7 @@ struct mrstat_ctx_s {
     // kernel tracing
     struct Rec { int kind; hipEvent_t a, b; };
     bool prof_on = false;
+    uint32_t prof_mask = 0xFFFFFFFFu;   // kernel kinds traced while profiling is on
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<Rec> recs;
@@ -98,7 +99,9 @@ hipError_t next_event(mrstat_ctx ctx, hipEvent_t* e)
 {
     if (ctx->ev_used == ctx->ev_pool.size()) {
         hipEvent_t ne;
-        hipError_t st = hipEventCreate(&ne);
+        // Timing events without the system-scope fences of a default event:
+        // device kernels only, so device-scope ordering is all they need.
+        hipError_t st = hipEventCreateWithFlags(&ne, hipEventDisableSystemFence);
         if (st != hipSuccess) return st;
         ctx->ev_pool.push_back(ne);
     }
@@ -110,7 +113,7 @@ hipError_t next_event(mrstat_ctx ctx, hipEvent_t* e)
 template <class F>
 hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
 {
-    if (!ctx->prof_on) return launch();
+    if (!ctx->prof_on || !((ctx->prof_mask >> kind) & 1u)) return launch();
     mrstat_ctx_s::Rec r{kind, nullptr, nullptr};
     hipError_t st = next_event(ctx, &r.a);
     if (st == hipSuccess) st = next_event(ctx, &r.b);
@@ -323,6 +326,13 @@ mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on)
     ctx->prof_on = on != 0;
     ctx->recs.clear();
     ctx->ev_used = 0;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_profile_select(mrstat_ctx ctx, uint32_t kind_mask)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    ctx->prof_mask = kind_mask;
     return MRSTAT_OK;
 }
 

@@ -61,28 +61,36 @@ __device__ __forceinline__ float2 shfl_xor2(float2 v, int m)
 // ------------------------------------------------------------------------
 constexpr int FW = 16;
 
-// WR = rows per wave step: 2 (32 columns per block, lanes 0-31 and 32-63 on
-// two adjacent rows; 128-byte rows of FP32 trains) or 1 (64 columns per
-// block, one row per wave: whole 128-byte lines of FP16 trains, which the
-// two-row layout would read as halves from two blocks).
-template <int MODE, int R, int CC, typename TT, int WR>
+// Lane layouts (G):
+//  G = 0: two rows of 32 columns per wave (lanes 0-31 and 32-63), a block of
+//         32 columns; a wave reads one 128-byte line per row of FP32 trains.
+//  G >= 1: one row of 64 columns per wave and G column groups per block, so
+//         a block spans 64 G columns (all of them when 64 G >= nx) and FW / G
+//         row groups. With 2-byte trains a row is not a whole number of
+//         lines in general (448 bytes at 224 columns); spanning all columns
+//         keeps both halves of every line inside one block.
+template <int MODE, int R, int CC, typename TT, int G>
 __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
     const float2* __restrict__ eytab, float2* __restrict__ U, int nx, int ny, int nv, int T, int C,
     int n_per_chunk)
 {
-    constexpr int XW = 64 / WR;          // columns per block
-    constexpr int RS = FW * WR;          // rows per step of the block
-    // LDS: per-wave sums [TRs per chunk][CC][FW][XW], then the block's
+    constexpr int XW = G == 0 ? 32 : 64 * G;          // columns per block
+    constexpr int RS = G == 0 ? 2 * FW : FW / G;      // rows per step of the block
+    constexpr int NS = G == 0 ? FW : FW / G;          // partial sums per column
+    // LDS: per-wave sums [TRs per chunk][CC][NS][XW], then the block's
     // y-phases [TRs per chunk][RS R].
     extern __shared__ float2 lds[];
-    float2* eys = lds + (size_t)n_per_chunk * CC * FW * XW;
+    float2* eys = lds + (size_t)n_per_chunk * CC * NS * XW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xl = lane % XW, half = lane / XW;   // half = 0 when WR = 1
+    const int half = G == 0 ? lane >> 5 : 0;
+    const int xl = G == 0 ? lane & 31 : (wave % (G == 0 ? 1 : G)) * 64 + lane;
+    const int rowoff = G == 0 ? 2 * wave + half : wave / (G == 0 ? 1 : G);
+    const int slot = G == 0 ? wave : wave / (G == 0 ? 1 : G);   // partial-sum row
     const int ix = blockIdx.x * XW + xl;
     const int yb = blockIdx.y;
-    const int iyb = yb * RS * R + WR * wave + half;
+    const int iyb = yb * RS * R + rowoff;
     const int n0 = blockIdx.z * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
     const bool colok = ix < nx;
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         const TT* __restrict__ b1 = b0 + plane;
         const TT* __restrict__ b2 = b1 + plane;
         const TT* __restrict__ b3 = b2 + plane;
-        const float2* eyrow = eys + (size_t)(n - n0) * RS * R + WR * wave + half;
+        const float2* eyrow = eys + (size_t)(n - n0) * RS * R + rowoff;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             mu[r] = (float)b0[jr[r]];
@@ -165,13 +173,13 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         }
 #pragma unroll
         for (int c = 0; c < CC; ++c) {
-            if constexpr (WR == 2) {
+            if constexpr (G == 0) {
                 const float2 t = shfl_xor2(acc[c], 32);
                 if (half == 0)
-                    lds[(((n - n0) * CC + c) * FW + wave) * XW + xl] =
+                    lds[(((n - n0) * CC + c) * NS + slot) * XW + xl] =
                         make_float2(acc[c].x + t.x, acc[c].y + t.y);
             } else {
-                lds[(((n - n0) * CC + c) * FW + wave) * XW + xl] = acc[c];
+                lds[(((n - n0) * CC + c) * NS + slot) * XW + xl] = acc[c];
             }
         }
     }
@@ -179,10 +187,10 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     const int nout = (n1 - n0) * CC * XW;
     for (int o = threadIdx.x; o < nout; o += blockDim.x) {
         const int l = o % XW, bc = o / XW;   // bc = TR-in-chunk * CC + c
-        float2 s = lds[(bc * FW) * XW + l];
+        float2 s = lds[(bc * NS) * XW + l];
 #pragma unroll
-        for (int w = 1; w < FW; ++w) {
-            const float2 t = lds[(bc * FW + w) * XW + l];
+        for (int w = 1; w < NS; ++w) {
+            const float2 t = lds[(bc * NS + w) * XW + l];
             s.x += t.x;
             s.y += t.y;
         }
@@ -775,28 +783,32 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* t
                  const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
                  float2* U, hipStream_t s)
 {
-    // 2-byte trains take the one-row-per-wave layout (single coil).
+    // 2-byte trains, one coil: one row per wave, all columns per block.
     if constexpr (sizeof(TT) == 2 && CC == 1) {
-        dim3 grid(ceil_div(d.nx, 64), p.nby16, ceil_div(d.T, p.fwd_tr16));
-        const size_t lds = (size_t)p.fwd_tr16 * (FW * 64 + FW * p.r_fwd16) * sizeof(float2);
-        switch (p.r_fwd16) {
-#define FWD16_CASE(RR)                                                                          \
-    case RR:                                                                                    \
-        ystage_fwd_kernel<MODE, RR, 1, TT, 1><<<grid, FW * 64, lds, s>>>(                       \
+        if (p.g16 > 0) {
+            dim3 grid(ceil_div(d.nx, 64 * p.g16), p.nby16, ceil_div(d.T, p.fwd_tr16));
+            const size_t lds = (size_t)p.fwd_tr16 * (FW * 64 + (FW / p.g16) * p.r_fwd16) * sizeof(float2);
+#define FWD16_CASE(GG, RR)                                                                      \
+    if (p.g16 == GG && p.r_fwd16 == RR) {                                                       \
+        ystage_fwd_kernel<MODE, RR, 1, TT, GG><<<grid, FW * 64, lds, s>>>(                      \
             trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr16);    \
-        break;
-            FWD16_CASE(1) FWD16_CASE(2) FWD16_CASE(3) FWD16_CASE(4)
+        return hipGetLastError();                                                               \
+    }
+            FWD16_CASE(1, 1) FWD16_CASE(1, 2) FWD16_CASE(1, 3) FWD16_CASE(1, 4)
+            FWD16_CASE(2, 1) FWD16_CASE(2, 2) FWD16_CASE(2, 3) FWD16_CASE(2, 4)
+            FWD16_CASE(4, 1) FWD16_CASE(4, 2) FWD16_CASE(4, 3) FWD16_CASE(4, 4)
+            FWD16_CASE(8, 1) FWD16_CASE(8, 2) FWD16_CASE(8, 3) FWD16_CASE(8, 4)
+            FWD16_CASE(16, 1) FWD16_CASE(16, 2) FWD16_CASE(16, 3) FWD16_CASE(16, 4)
 #undef FWD16_CASE
-            default: return hipErrorInvalidValue;
+            return hipErrorInvalidValue;
         }
-        return hipGetLastError();
     }
     dim3 grid(ceil_div(d.nx, 32), p.nby, ceil_div(d.T, p.fwd_tr));
     const size_t lds = (size_t)p.fwd_tr * (CC * FW * 32 + 32 * p.r_fwd) * sizeof(float2);
 #define FWD_CASE(RR)                                                                            \
     case RR:                                                                                    \
         if constexpr (CC == 1 || RR <= 2)                                                       \
-            ystage_fwd_kernel<MODE, RR, CC, TT, 2><<<grid, FW * 64, lds, s>>>(                  \
+            ystage_fwd_kernel<MODE, RR, CC, TT, 0><<<grid, FW * 64, lds, s>>>(                  \
                 trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_tr);  \
         else                                                                                    \
             return hipErrorInvalidValue;                                                        \
@@ -851,11 +863,17 @@ YPlan make_yplan(const Dims& d)
     p.r_fwd = ceil_div(d.ny, 32 * p.nby);
     // TRs per block: the chunk's per-wave sums live in LDS (at most 64 KB).
     p.fwd_tr = d.C == 1 ? 16 : (d.C <= 8 ? 2 : 1);
-    // One-row-per-wave layout (FP16 trains, one coil): 16 rows per step, at
-    // most 2 steps per lane (57 VGPRs, ~68 KB of LDS: two blocks per CU, so
-    // twice the loads in flight), 8 TRs per block.
-    p.nby16 = ceil_div(d.ny, 32);
-    p.r_fwd16 = ceil_div(d.ny, 16 * p.nby16);
+    // One-row-per-wave layout (FP16 trains, one coil): g16 column groups of
+    // 64 (a power of two covering nx, so a block spans every column), FW/g16
+    // row groups, up to 2 row steps per lane (two blocks per CU), 8 TRs per
+    // block; g16 = 0 (the
+    // two-row layout) when nx > 64 FW.
+    p.g16 = 1;
+    while (p.g16 * 64 < d.nx && p.g16 < FW) p.g16 *= 2;
+    if (p.g16 * 64 < d.nx) p.g16 = 0;
+    const int rg = p.g16 ? FW / p.g16 : 2 * FW;
+    p.nby16 = ceil_div(d.ny, rg * 2);
+    p.r_fwd16 = ceil_div(d.ny, rg * p.nby16);
     p.fwd_tr16 = 8;
     // Adjoint: one row per lane (8 rows per block) and 8 TR chunks: enough
     // blocks in flight to stream the trains near the HBM limit, with partial
@@ -915,7 +933,7 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
     const hipError_t e =
         f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, s)
             : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, s);
-    const int nby = (f16 && d.C == 1) ? p.nby16 : p.nby;
+    const int nby = (f16 && d.C == 1 && p.g16 > 0) ? p.nby16 : p.nby;
     if (e != hipSuccess || nby == 1) return e;
     const size_t count = (size_t)d.C * d.T * d.nx;
     usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, nby, count);

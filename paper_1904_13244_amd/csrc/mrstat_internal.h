@@ -31,7 +31,7 @@ struct YPlan {
     int adj_chunks;   // TR chunks of the adjoint y-stage (partial sums per chunk)
     int adj_per_chunk;
     int ksplit_adj;   // split-K of the adjoint x-GEMM (partial W outputs)
-    int r_fwd16, nby16, fwd_tr16;   // forward y-stage, FP16 trains, one row per wave
+    int g16, r_fwd16, nby16, fwd_tr16;   // forward y-stage, FP16 trains, one row per wave
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

@@ -140,7 +140,7 @@ Layout make_layout(const Dims& d)
     const size_t nv = d.nv, T = d.T;
     L.trains = take(4 * T * nv * sizeof(float));
     L.trial_m = take(T * nv * sizeof(float));
-    L.upart = take((size_t)std::max(L.yp.nby, L.yp.nby16) * d.C * T * d.nx * sizeof(float2));
+    L.upart = take((size_t)std::max({L.yp.nby, L.yp.nby16, L.yp.nbyc}) * d.C * T * d.nx * sizeof(float2));
     L.W = take((size_t)L.yp.ksplit_adj * d.C * T * d.nx * sizeof(float2));
     L.apart = take((size_t)L.yp.adj_chunks * 8 * nv * sizeof(float));
     L.r = take((size_t)d.C * T * d.nk * sizeof(float2));

@@ -200,6 +200,128 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Forward y-stage with coils (CC = 8 or 16 coil slots). The per-wave sums of
+// CC coils make the chunk-wide LDS staging above hold only 1-2 TRs, so the
+// voxel weights and coil maps would be re-read every 2 TRs. Here each TR's
+// per-wave sums go to one of two LDS buffers and are reduced across the
+// waves right after a single barrier (the next TR uses the other buffer), so
+// a block streams a long TR chunk with its voxels' weights and coil maps in
+// registers. The next TR's trains are loaded before that barrier. Layout as
+// G = 0 above: two rows of 32 columns per wave, R row steps per lane.
+// ------------------------------------------------------------------------
+template <int MODE, int R, int CC, typename TT>
+__global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
+    const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
+    const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
+    const float2* __restrict__ eytab, float2* __restrict__ U, int nx, int ny, int nv, int T, int C,
+    int n_per_chunk)
+{
+    constexpr int RS = 2 * FW;
+    constexpr int NT = MODE == 1 ? 4 : 1;
+    // LDS: two buffers of per-wave sums [CC][FW][32], then the block's
+    // y-phases [TRs per chunk][RS R].
+    extern __shared__ float2 lds[];
+    float2* eys = lds + 2 * CC * FW * 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xl = lane & 31, half = lane >> 5;
+    const int ix = blockIdx.x * 32 + xl;
+    const int yb = blockIdx.y;
+    const int iyb = yb * RS * R + 2 * wave + half;
+    const int n0 = blockIdx.z * n_per_chunk;
+    const int n1 = min(T, n0 + n_per_chunk);
+    const bool colok = ix < nx;
+    const size_t plane = (size_t)T * nv;
+    for (int e = threadIdx.x; e < (n1 - n0) * RS * R; e += blockDim.x) {
+        const int nl = e / (RS * R), rr = e % (RS * R);
+        const int iy = yb * RS * R + rr;
+        eys[e] = iy < ny ? eytab[(size_t)(n0 + nl) * ny + iy] : make_float2(0.f, 0.f);
+    }
+
+    float2 P[R], Q[R];
+    float v0[R], v1[R], v2[R];
+    int jr[R];
+    float2 cw[R][CC];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int iy = iyb + RS * r;
+        const bool ok = colok && iy < ny;
+        const int j = ok ? iy * nx + ix : 0;   // invalid voxels read voxel 0 with zero weight
+        jr[r] = j;
+        const bool on = ok && (mask == nullptr || mask[j] != 0);
+        const float rr = on ? theta[3 * nv + j] : 0.f, ri = on ? theta[4 * nv + j] : 0.f;
+        P[r] = make_float2(-ri, rr);   // i rho
+        if constexpr (MODE == 1) {
+            const float nr = on ? v[3 * nv + j] : 0.f, ni = on ? v[4 * nv + j] : 0.f;
+            Q[r] = make_float2(-ni, nr);   // i nu
+            v0[r] = on ? v[j] : 0.f;
+            v1[r] = on ? v[nv + j] : 0.f;
+            v2[r] = on ? v[2 * nv + j] : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            cw[r][c] = (ok && c < C) ? coil[(size_t)c * nv + j] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();   // y-phases staged
+
+    auto load_tr = [&](float (&buf)[R][NT], int n) {
+        const TT* __restrict__ b0 = trains + (size_t)n * nv;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NT; ++q) buf[r][q] = (float)b0[q * plane + jr[r]];
+    };
+    float nxt[R][NT];
+    load_tr(nxt, n0);
+    int buf = 0;
+    for (int n = n0; n < n1; ++n) {
+        float cur[R][NT];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NT; ++q) cur[r][q] = nxt[r][q];
+        load_tr(nxt, min(n + 1, n1 - 1));
+        const float2* eyrow = eys + (size_t)(n - n0) * RS * R + 2 * wave + half;
+        float2 acc[CC];
+#pragma unroll
+        for (int c = 0; c < CC; ++c) acc[c] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 x;
+            if constexpr (MODE == 0) {
+                x = make_float2(P[r].x * cur[r][0], P[r].y * cur[r][0]);
+            } else {
+                const float a = fmaf(v0[r], cur[r][1], fmaf(v1[r], cur[r][2], v2[r] * cur[r][3]));
+                x = make_float2(fmaf(P[r].x, a, Q[r].x * cur[r][0]), fmaf(P[r].y, a, Q[r].y * cur[r][0]));
+            }
+            const float2 z = cmul(eyrow[RS * r], x);
+#pragma unroll
+            for (int c = 0; c < CC; ++c) acc[c] = cfma(cw[r][c], z, acc[c]);
+        }
+        float2* red = lds + buf * CC * FW * 32;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+            const float2 t = shfl_xor2(acc[c], 32);
+            if (half == 0) red[(c * FW + wave) * 32 + xl] = make_float2(acc[c].x + t.x, acc[c].y + t.y);
+        }
+        __syncthreads();
+        // Reduce this TR across the waves (the next TR writes the other buffer).
+        for (int o = threadIdx.x; o < CC * 32; o += blockDim.x) {
+            const int c = o >> 5, l = o & 31;
+            float2 sum = red[(c * FW) * 32 + l];
+#pragma unroll
+            for (int w = 1; w < FW; ++w) {
+                const float2 t = red[(c * FW + w) * 32 + l];
+                sum.x += t.x;
+                sum.y += t.y;
+            }
+            const int oix = blockIdx.x * 32 + l;
+            if (oix < nx && c < C) U[(((size_t)yb * C + c) * T + n) * nx + oix] = sum;
+        }
+        buf ^= 1;
+    }
+}
+
 // Sums the row-block partials of the forward y-stage into block 0.
 __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
 {
@@ -803,6 +925,21 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* t
             return hipErrorInvalidValue;
         }
     }
+    if constexpr (CC > 1) {
+        // Coils: per-TR reduction, long TR chunks.
+        dim3 grid(ceil_div(d.nx, 32), p.nbyc, ceil_div(d.T, p.fwd_trc));
+        const size_t lds = (size_t)(2 * CC * FW * 32 + p.fwd_trc * 2 * FW * p.r_fwdc) * sizeof(float2);
+#define FWDC_CASE(RR)                                                                           \
+    if (p.r_fwdc == RR) {                                                                       \
+        ystage_fwd_coil_kernel<MODE, RR, CC, TT><<<grid, FW * 64, lds, s>>>(                    \
+            trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_trc);     \
+        return hipGetLastError();                                                               \
+    }
+        FWDC_CASE(1)
+        if constexpr (CC <= 8) { FWDC_CASE(2) }
+#undef FWDC_CASE
+        return hipErrorInvalidValue;
+    }
     dim3 grid(ceil_div(d.nx, 32), p.nby, ceil_div(d.T, p.fwd_tr));
     const size_t lds = (size_t)p.fwd_tr * (CC * FW * 32 + 32 * p.r_fwd) * sizeof(float2);
 #define FWD_CASE(RR)                                                                            \
@@ -863,6 +1000,12 @@ YPlan make_yplan(const Dims& d)
     p.r_fwd = ceil_div(d.ny, 32 * p.nby);
     // TRs per block: the chunk's per-wave sums live in LDS (at most 64 KB).
     p.fwd_tr = d.C == 1 ? 16 : (d.C <= 8 ? 2 : 1);
+    // Coils: per-TR reduction kernel, 2 row steps per lane for up to 8 coils
+    // (1 for 16), 32 TRs per block.
+    p.r_fwdc = d.C <= 8 ? 2 : 1;
+    p.nbyc = ceil_div(d.ny, 2 * FW * p.r_fwdc);
+    p.r_fwdc = ceil_div(d.ny, 2 * FW * p.nbyc);
+    p.fwd_trc = 32;
     // One-row-per-wave layout (FP16 trains, one coil): g16 column groups of
     // 64 (a power of two covering nx, so a block spans every column), FW/g16
     // row groups, up to 2 row steps per lane (two blocks per CU), 8 TRs per
@@ -933,7 +1076,7 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
     const hipError_t e =
         f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, s)
             : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, s);
-    const int nby = (f16 && d.C == 1 && p.g16 > 0) ? p.nby16 : p.nby;
+    const int nby = d.C > 1 ? p.nbyc : ((f16 && p.g16 > 0) ? p.nby16 : p.nby);
     if (e != hipSuccess || nby == 1) return e;
     const size_t count = (size_t)d.C * d.T * d.nx;
     usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, nby, count);

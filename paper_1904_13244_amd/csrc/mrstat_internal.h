@@ -32,6 +32,7 @@ struct YPlan {
     int adj_per_chunk;
     int ksplit_adj;   // split-K of the adjoint x-GEMM (partial W outputs)
     int g16, r_fwd16, nby16, fwd_tr16;   // forward y-stage, FP16 trains, one row per wave
+    int r_fwdc, nbyc, fwd_trc;           // forward y-stage with coils (per-TR reduction)
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

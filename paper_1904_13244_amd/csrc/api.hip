@@ -257,7 +257,8 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
     return MRSTAT_OK;
 }
 
-mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, hipStream_t s)
+mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, int param_mask,
+                      hipStream_t s)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
@@ -265,7 +266,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
                                                    ctx->W(), s)));
     HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 4, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, g, s)));
+    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g, s)));
     return MRSTAT_OK;
 }
 
@@ -381,6 +382,8 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const voi
                            ctx->eytab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.extab, ctx->extab.data(),
                            ctx->extab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    // Device scalars start from zero.
+    HIP_TRY(hipMemsetAsync(ctx->ws + ctx->L.scal, 0, SCAL_DOUBLES * sizeof(double), s));
     HIP_TRY(hipStreamSynchronize(s));
     ctx->bound = true;
     return MRSTAT_OK;
@@ -505,7 +508,7 @@ mrstat_status mrstat_jhw(mrstat_ctx ctx, const float* d_theta, int32_t reuse, co
     if (st != MRSTAT_OK) return st;
     if (!d_w || !d_out) return fail(ctx, MRSTAT_ERR_ARG, "w or out is NULL");
     if (!aligned(d_w, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
-    return adjoint(ctx, d_theta, d_w, d_out, s);
+    return adjoint(ctx, d_theta, d_w, d_out, 31, s);
 }
 
 mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
@@ -536,18 +539,16 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     if (st != MRSTAT_OK) return st;
     st = forward(ctx, 0, 0, ctx->trains(), d_theta, nullptr, d_data, ctx->r(), sc + SC_F0, s);
     if (st != MRSTAT_OK) return st;
-    st = adjoint(ctx, d_theta, ctx->r(), g, s);
+    st = adjoint(ctx, d_theta, ctx->r(), g, o->param_mask, s);
     if (st != MRSTAT_OK) return st;
-    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_mask_params(d, g, o->param_mask, ctx->mask, s)));
 
     // CG on Re(J^H J) p = -g with device-resident FP64 scalars.
     HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s)));
     for (int it = 0; it < o->n_cg; ++it) {
         st = forward(ctx, 1, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
         if (st != MRSTAT_OK) return st;
-        st = adjoint(ctx, d_theta, ctx->y(), q, s);
+        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s);
         if (st != MRSTAT_OK) return st;
-        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_mask_params(d, q, o->param_mask, ctx->mask, s)));
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s)));
     }
     double hs[16];

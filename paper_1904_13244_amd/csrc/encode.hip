@@ -485,7 +485,8 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 // g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho).
 __global__ void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
                                   const float* __restrict__ theta,
-                                  const uint8_t* __restrict__ mask, float* __restrict__ g, int nv)
+                                  const uint8_t* __restrict__ mask, int param_mask,
+                                  float* __restrict__ g, int nv)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
@@ -497,13 +498,14 @@ __global__ void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
         for (int q = 0; q < 8; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
     const bool on = mask == nullptr || mask[j] != 0;
     const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
+    // Rows of parameters outside param_mask are zero.
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const float ar = A[2 * (q + 1)], ai = A[2 * (q + 1) + 1];
-        g[(size_t)q * nv + j] = on ? -(rr * ai - ri * ar) : 0.f;
+        g[(size_t)q * nv + j] = (on && ((param_mask >> q) & 1)) ? -(rr * ai - ri * ar) : 0.f;
     }
-    g[3 * (size_t)nv + j] = on ? -A[1] : 0.f;
-    g[4 * (size_t)nv + j] = on ? A[0] : 0.f;
+    g[3 * (size_t)nv + j] = (on && ((param_mask >> 3) & 1)) ? -A[1] : 0.f;
+    g[4 * (size_t)nv + j] = (on && ((param_mask >> 4) & 1)) ? A[0] : 0.f;
 }
 
 // CGLS adjoint of the rho-linear map: (M^H w)_j = sum_n conj(m_j[n]) V = -i A_0.
@@ -1126,9 +1128,10 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 }
 
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
-                             const uint8_t* mask, float* g, hipStream_t s)
+                             const uint8_t* mask, int param_mask, float* g, hipStream_t s)
 {
-    jhw_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask, g, d.nv);
+    jhw_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask,
+                                                         g, d.nv);
     return hipGetLastError();
 }
 

@@ -90,9 +90,10 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
                              const float2* coil, const uint8_t* mask, const float2* eytab,
                              const float2* W, float* apart, hipStream_t s);
 
-// g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order).
+// g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order); rows of
+// parameters outside param_mask (and masked voxels) are zero.
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
-                             const uint8_t* mask, float* g, hipStream_t s);
+                             const uint8_t* mask, int param_mask, float* g, hipStream_t s);
 
 // CGLS helper: A^H w = -i A_0 from the one-train partials.
 hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
@@ -115,8 +116,6 @@ enum : int {
     SC_STAGE = 30, SC_CDONE = 25
 };
 
-hipError_t launch_mask_params(const Dims& d, float* x, int param_mask, const uint8_t* mask,
-                              hipStream_t s);
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
                           double* scal, double* partials, hipStream_t s);
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,

@@ -68,16 +68,6 @@ __global__ __launch_bounds__(RB) void dot_c_kernel(const float2* __restrict__ a,
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-__global__ void mask_params_kernel(float* __restrict__ x, int nv, int param_mask,
-                                   const uint8_t* __restrict__ mask)
-{
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)5 * nv) return;
-    const int q = (int)(i / nv), j = (int)(i % nv);
-    const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
-    if (!on) x[i] = 0.f;
-}
-
 // step = 0, res = -g, dir = res; partial sums of res.res.
 __global__ __launch_bounds__(RB) void cg_init_kernel(const float* __restrict__ g,
                                                      float* __restrict__ step,
@@ -363,13 +353,6 @@ hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* part
 {
     dot_c_kernel<<<RED_BLOCKS, RB, 0, s>>>(a, b, n, partials);
     sum_partials_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_mask_params(const Dims& d, float* x, int param_mask, const uint8_t* mask,
-                              hipStream_t s)
-{
-    mask_params_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(x, d.nv, param_mask, mask);
     return hipGetLastError();
 }
 

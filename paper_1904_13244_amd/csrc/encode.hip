@@ -467,6 +467,135 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Adjoint y-stage with coils (CC = 8 or 16 coil slots). A block covers 32
+// columns x 16 rows (two rows per thread), so each TR's W rows of all coils
+// (CC x 32 complex) are staged once in LDS and used by 16 image rows instead
+// of being fetched per voxel; TR batches of NBA are double-buffered (the next
+// batch's W is loaded into registers while the current one is used, one
+// barrier per batch). Partial sums per TR chunk as in the kernel above.
+// ------------------------------------------------------------------------
+template <int NTRAIN, int CC, int NBA, typename TT>
+__global__ __launch_bounds__(256) void ystage_adj_coil_kernel(
+    const TT* __restrict__ trains, const float2* __restrict__ coil,
+    const uint8_t* __restrict__ mask, const float2* __restrict__ eytab,
+    const float2* __restrict__ W, float* __restrict__ apart, int nx, int ny, int nv, int T,
+    int C, int n_per_chunk)
+{
+    constexpr int RY = 2, BR = 8 * RY;               // rows per thread, rows per block
+    constexpr int WT = NBA * CC * 32;                 // float2 per W tile
+    constexpr int WPT = (WT + 255) / 256;             // W loads per thread
+    extern __shared__ float2 sm[];
+    float2* Ws = sm;                                  // [2][NBA][CC][32]
+    float2* eys = sm + 2 * WT;                        // [n_per_chunk][BR]
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int ix = blockIdx.x * 32 + tx;
+    const int row0 = blockIdx.y * BR;
+    const int chunk = blockIdx.z;
+    const int n0 = chunk * n_per_chunk;
+    const int n1 = min(T, n0 + n_per_chunk);
+    const size_t plane = (size_t)T * nv;
+    for (int e = threadIdx.x; e < (n1 - n0) * BR; e += 256) {
+        const int nl = e / BR, rr = e % BR;
+        const int iy = row0 + rr;
+        eys[e] = iy < ny ? eytab[(size_t)(n0 + nl) * ny + iy] : make_float2(0.f, 0.f);
+    }
+    int jr[RY];
+    bool ok[RY];
+    float2 cw[RY][CC];
+#pragma unroll
+    for (int u = 0; u < RY; ++u) {
+        const int iy = row0 + ty + 8 * u;
+        ok[u] = ix < nx && iy < ny;
+        jr[u] = ok[u] ? iy * nx + ix : 0;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            cw[u][c] = (ok[u] && c < C) ? coil[(size_t)c * nv + jr[u]] : make_float2(0.f, 0.f);
+    }
+    // W tile of the batch starting at TR nb: [b][c][column], zero outside.
+    auto load_w = [&](float2 (&wr)[WPT], int nb) {
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int b = e / (CC * 32), c = (e / 32) % CC, col = e % 32;
+            const int n = nb + b, x = blockIdx.x * 32 + col;
+            wr[i] = (e < WT && n < n1 && c < C && x < nx) ? W[((size_t)c * T + n) * nx + x]
+                                                          : make_float2(0.f, 0.f);
+        }
+    };
+    auto store_w = [&](const float2 (&wr)[WPT], int buf) {
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < WT) Ws[buf * WT + e] = wr[i];
+        }
+    };
+    float2 wr[WPT];
+    load_w(wr, n0);
+    store_w(wr, 0);
+    __syncthreads();
+
+    float2 acc[RY][NTRAIN];
+#pragma unroll
+    for (int u = 0; u < RY; ++u)
+#pragma unroll
+        for (int p = 0; p < NTRAIN; ++p) acc[u][p] = make_float2(0.f, 0.f);
+    int buf = 0;
+    for (int nb0 = n0; nb0 < n1; nb0 += NBA) {
+        const bool more = nb0 + NBA < n1;
+        if (more) load_w(wr, nb0 + NBA);
+        float mu[NBA][RY][NTRAIN];
+#pragma unroll
+        for (int b = 0; b < NBA; ++b) {
+            const int n = min(nb0 + b, n1 - 1);
+            const TT* __restrict__ t0 = trains + (size_t)n * nv;
+#pragma unroll
+            for (int u = 0; u < RY; ++u)
+#pragma unroll
+                for (int p = 0; p < NTRAIN; ++p) mu[b][u][p] = (float)(t0 + p * plane)[jr[u]];
+        }
+        const float2* wt = Ws + buf * WT;
+#pragma unroll
+        for (int b = 0; b < NBA; ++b) {
+            const int nl = min(nb0 + b, n1 - 1) - n0;
+            const float keep = (nb0 + b < n1) ? 1.f : 0.f;
+#pragma unroll
+            for (int u = 0; u < RY; ++u) {
+                float2 wc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < CC; ++c) {
+                    const float2 t = cmulconj(cw[u][c], wt[(b * CC + c) * 32 + tx]);
+                    wc.x += t.x;
+                    wc.y += t.y;
+                }
+                float2 V = cmulconj(eys[nl * BR + ty + 8 * u], wc);
+                V.x *= keep;
+                V.y *= keep;
+#pragma unroll
+                for (int p = 0; p < NTRAIN; ++p) {
+                    acc[u][p].x = fmaf(mu[b][u][p], V.x, acc[u][p].x);
+                    acc[u][p].y = fmaf(mu[b][u][p], V.y, acc[u][p].y);
+                }
+            }
+        }
+        if (more) store_w(wr, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int u = 0; u < RY; ++u) {
+        if (!ok[u]) continue;
+        const int j = jr[u];
+        const bool on = mask == nullptr || mask[j] != 0;
+        float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j;
+#pragma unroll
+        for (int p = 0; p < NTRAIN; ++p) {
+            dst[(2 * p) * (size_t)nv] = on ? acc[u][p].x : 0.f;
+            dst[(2 * p + 1) * (size_t)nv] = on ? acc[u][p].y : 0.f;
+        }
+    }
+}
+
 // Sums the split-K partials of the adjoint x-GEMM into the first.
 __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 {
@@ -977,6 +1106,15 @@ hipError_t adj_launch(const Dims& d, const YPlan& p, const TT* trains, const flo
                 trains, coil, mask, eytab, W, apart, d.nx, d.ny, d.nv, d.T, d.C, p.adj_per_chunk);
             return hipGetLastError();
         }
+    }
+    if constexpr (CC > 1) {
+        // Coils: 32 x 16 voxel tiles sharing staged W rows.
+        constexpr int NBA = 4;
+        dim3 grid(ceil_div(d.nx, 32), ceil_div(d.ny, 16), p.adj_chunks);
+        const size_t lds = (size_t)(2 * NBA * CC * 32 + p.adj_per_chunk * 16) * sizeof(float2);
+        ystage_adj_coil_kernel<NTRAIN, CC, NBA, TT><<<grid, 256, lds, s>>>(
+            trains, coil, mask, eytab, W, apart, d.nx, d.ny, d.nv, d.T, d.C, p.adj_per_chunk);
+        return hipGetLastError();
     }
     dim3 grid(ceil_div(d.nv, 256), p.adj_chunks);
     const int rows = std::min(d.ny, 256 / d.nx + 2);

@@ -134,13 +134,13 @@ Layout make_layout(const Dims& d)
     L.yp = make_yplan(d);
     const int M = d.C * d.T;
     const int gemm_blocks = ceil_div(2 * d.nk, 64) * ceil_div(M, 64);
-    L.n_red = std::max(2 * RED_BLOCKS, gemm_blocks);
+    L.n_red = std::max(3 * RED_BLOCKS, gemm_blocks);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     const size_t nv = d.nv, T = d.T;
     L.trains = take(4 * T * nv * sizeof(float));
     L.trial_m = take(T * nv * sizeof(float));
-    L.upart = take((size_t)std::max({L.yp.nby, L.yp.nby16, L.yp.nbyc}) * d.C * T * d.nx * sizeof(float2));
+    L.upart = take((size_t)std::max({L.yp.nby, L.yp.nby16, L.yp.nbyc, L.yp.nbyw}) * d.C * T * d.nx * sizeof(float2));
     L.W = take((size_t)L.yp.ksplit_adj * d.C * T * d.nx * sizeof(float2));
     L.apart = take((size_t)L.yp.adj_chunks * 8 * nv * sizeof(float));
     L.r = take((size_t)d.C * T * d.nk * sizeof(float2));
@@ -549,7 +549,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         if (st != MRSTAT_OK) return st;
         st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s);
         if (st != MRSTAT_OK) return st;
-        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), it, s)));
     }
     double hs[16];
     int32_t nfb = 0;

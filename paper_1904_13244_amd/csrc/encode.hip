@@ -48,6 +48,14 @@ __device__ __forceinline__ float2 shfl_xor2(float2 v, int m)
     return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
 }
 
+// TR chunk of a forward y-stage block. The adjoint y-stage visits TR chunks
+// in increasing order; the forward kernels visit them in decreasing order, so
+// each kernel starts on the trains the previous one read last.
+__device__ __forceinline__ int fwd_chunk(unsigned b, unsigned nb)
+{
+    return (int)(nb - 1 - b);
+}
+
 // ------------------------------------------------------------------------
 // Forward y-stage. Block = FW = 16 waves; wave w, half h covers row
 // iy = rowbase + 32 r + 2 w + h for r < R, and ix = 32 bx + lane % 32. A block
@@ -91,7 +99,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     const int ix = blockIdx.x * XW + xl;
     const int yb = blockIdx.y;
     const int iyb = yb * RS * R + rowoff;
-    const int n0 = blockIdx.z * n_per_chunk;
+    const int n0 = fwd_chunk(blockIdx.z, gridDim.z) * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
     const bool colok = ix < nx;
     const size_t plane = (size_t)T * nv;
@@ -201,6 +209,140 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
 }
 
 // ------------------------------------------------------------------------
+// Forward y-stage, wide layout (FP16 trains, one coil, nx a multiple of 4
+// and at most 256, 16-byte aligned operands). Each lane owns 4 consecutive
+// columns, so one load moves 4 train elements (8 bytes) and a wave covers a
+// whole row. Loop order is the transpose of the kernels above: a
+// block takes NT TRs and a slab of rows; its waves walk the slab's rows
+// (wave w: rows y0 + w, y0 + w + NWW, ...), loading each voxel's weights
+// (from L2: they are shared by every TR chunk) and its NT TRs of trains, and
+// keep the NT per-column sums in registers. One LDS reduction across the
+// waves per block; few row slabs (often one) so U needs few or no partial
+// sums.
+// ------------------------------------------------------------------------
+constexpr int NWW = 8;   // waves per block
+
+template <typename TT> struct Vec4;
+template <> struct Vec4<_Float16> { typedef _Float16 T __attribute__((ext_vector_type(4))); };
+
+template <int MODE, int NT, typename TT>
+__global__ __launch_bounds__(NWW * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void ystage_fwd_wide_kernel(
+    const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
+    const uint8_t* __restrict__ mask, const float2* __restrict__ eytab, float2* __restrict__ U,
+    int nx, int ny, int nv, int T, int rows)
+{
+    typedef typename Vec4<TT>::T V4;
+    // LDS: per-wave sums [NWW][NT][nx], then the slab's y-phases [NT][rows].
+    extern __shared__ float2 lds[];
+    float2* eys = lds + (size_t)NWW * NT * nx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x0 = 4 * lane;
+    const bool colok = x0 < nx;
+    const int yb = blockIdx.x;
+    const int y0 = yb * rows, y1 = min(ny, y0 + rows);
+    const int n0 = fwd_chunk(blockIdx.y, gridDim.y) * NT;
+    const int nt = min(NT, T - n0);
+    const size_t plane = (size_t)T * nv;
+    for (int e = threadIdx.x; e < NT * rows; e += blockDim.x) {
+        const int t = e / rows, iy = y0 + e % rows;
+        eys[e] = (t < nt && iy < y1) ? eytab[(size_t)(n0 + t) * ny + iy] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+
+    float2 acc[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[t][c] = make_float2(0.f, 0.f);
+    // TRs past the end of the sequence read the chunk's first TR; their sums
+    // are never stored.
+    size_t toff[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) toff[t] = (size_t)(n0 + (t < nt ? t : 0)) * nv;
+
+    if (colok) {
+        for (int iy = y0 + wave; iy < y1; iy += NWW) {
+            const int j = iy * nx + x0;
+            f4 pr = *(const f4*)(theta + 3 * (size_t)nv + j);
+            f4 pi = *(const f4*)(theta + 4 * (size_t)nv + j);
+            f4 qr, qi, w0, w1, w2;
+            if constexpr (MODE == 1) {
+                qr = *(const f4*)(v + 3 * (size_t)nv + j);
+                qi = *(const f4*)(v + 4 * (size_t)nv + j);
+                w0 = *(const f4*)(v + j);
+                w1 = *(const f4*)(v + (size_t)nv + j);
+                w2 = *(const f4*)(v + 2 * (size_t)nv + j);
+            }
+            V4 m0[NT], m1[NT], m2[NT], m3[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const TT* b = trains + toff[t] + j;
+                // Streaming loads: the trains are read once per product; the
+                // voxel weights and y-phases shared across blocks stay in L2.
+                m0[t] = __builtin_nontemporal_load((const V4*)b);
+                if constexpr (MODE == 1) {
+                    m1[t] = __builtin_nontemporal_load((const V4*)(b + plane));
+                    m2[t] = __builtin_nontemporal_load((const V4*)(b + 2 * plane));
+                    m3[t] = __builtin_nontemporal_load((const V4*)(b + 3 * plane));
+                }
+            }
+            if (mask != nullptr) {   // masked voxels: zero weights (selects, not products)
+                const uchar4 mk = *(const uchar4*)(mask + j);
+                const bool on[4] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    pr[c] = on[c] ? pr[c] : 0.f;
+                    pi[c] = on[c] ? pi[c] : 0.f;
+                    if constexpr (MODE == 1) {
+                        qr[c] = on[c] ? qr[c] : 0.f;
+                        qi[c] = on[c] ? qi[c] : 0.f;
+                        w0[c] = on[c] ? w0[c] : 0.f;
+                        w1[c] = on[c] ? w1[c] : 0.f;
+                        w2[c] = on[c] ? w2[c] : 0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const float2 ey = eys[t * rows + (iy - y0)];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float mu = (float)m0[t][c];
+                    float2 x;   // i rho mu (mode 0); i (rho a + nu mu) (mode 1)
+                    if constexpr (MODE == 0) {
+                        x = make_float2(-pi[c] * mu, pr[c] * mu);
+                    } else {
+                        const float a = fmaf(w0[c], (float)m1[t][c],
+                                             fmaf(w1[c], (float)m2[t][c], w2[c] * (float)m3[t][c]));
+                        x = make_float2(-fmaf(pi[c], a, qi[c] * mu), fmaf(pr[c], a, qr[c] * mu));
+                    }
+                    acc[t][c] = cfma(ey, x, acc[t][c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            f4* dst = (f4*)(lds + ((size_t)wave * NT + t) * nx + x0);
+            dst[0] = f4{acc[t][0].x, acc[t][0].y, acc[t][1].x, acc[t][1].y};
+            dst[1] = f4{acc[t][2].x, acc[t][2].y, acc[t][3].x, acc[t][3].y};
+        }
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nt * nx; o += blockDim.x) {
+        const int t = o / nx, ix = o % nx;
+        float2 s = lds[(size_t)t * nx + ix];
+#pragma unroll
+        for (int w = 1; w < NWW; ++w) {
+            const float2 u = lds[((size_t)w * NT + t) * nx + ix];
+            s.x += u.x;
+            s.y += u.y;
+        }
+        U[((size_t)yb * T + n0 + t) * nx + ix] = s;
+    }
+}
+
+// ------------------------------------------------------------------------
 // Forward y-stage with coils (CC = 8 or 16 coil slots). The per-wave sums of
 // CC coils make the chunk-wide LDS staging above hold only 1-2 TRs, so the
 // voxel weights and coil maps would be re-read every 2 TRs. Here each TR's
@@ -228,7 +370,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
     const int ix = blockIdx.x * 32 + xl;
     const int yb = blockIdx.y;
     const int iyb = yb * RS * R + 2 * wave + half;
-    const int n0 = blockIdx.z * n_per_chunk;
+    const int n0 = fwd_chunk(blockIdx.z, gridDim.z) * n_per_chunk;
     const int n1 = min(T, n0 + n_per_chunk);
     const bool colok = ix < nx;
     const size_t plane = (size_t)T * nv;
@@ -347,7 +489,6 @@ __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
 // (indices clamped to the chunk, contributions of padding TRs zeroed).
 // Partials per chunk are combined in chunk order by the finish kernel.
 // ------------------------------------------------------------------------
-constexpr int ADJ_EY_ROWS = 4;   // rows of a 256-voxel block when nx >= 128
 
 template <int NTRAIN, int CC, int NBA, typename TT, int VX>
 __global__ __launch_bounds__(256) void ystage_adj_kernel(
@@ -359,7 +500,7 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
     // VX consecutive voxels per thread (VX = 2: FP16 trains read as pairs,
     // nx even, so a pair never straddles a row); a block spans 256 VX voxels.
     constexpr int BV = 256 * VX;
-    typedef TT tv2 __attribute__((ext_vector_type(2)));
+    typedef TT tvx __attribute__((ext_vector_type(VX == 1 ? 2 : VX)));
     extern __shared__ float2 eys[];   // [n_per_chunk][rows]
     const int jb = blockIdx.x * BV;
     const int j0 = jb + VX * threadIdx.x;
@@ -404,10 +545,13 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
             for (int c = 0; c < CC; ++c) {
                 const int cc = c < C ? c : 0;
                 const float2* wrow = W + ((size_t)cc * T + n) * nx + ix;
-                if constexpr (VX == 2) {
-                    const float4 w2 = *reinterpret_cast<const float4*>(wrow);
-                    wv[b][0][c] = make_float2(w2.x, w2.y);
-                    wv[b][1][c] = make_float2(w2.z, w2.w);
+                if constexpr (VX >= 2) {
+#pragma unroll
+                    for (int h = 0; h < VX / 2; ++h) {
+                        const float4 w2 = reinterpret_cast<const float4*>(wrow)[h];
+                        wv[b][2 * h][c] = make_float2(w2.x, w2.y);
+                        wv[b][2 * h + 1][c] = make_float2(w2.z, w2.w);
+                    }
                 } else {
                     wv[b][0][c] = wrow[0];
                 }
@@ -415,10 +559,10 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
             const TT* __restrict__ t0 = trains + (size_t)n * nv;
 #pragma unroll
             for (int p = 0; p < NTRAIN; ++p) {
-                if constexpr (VX == 2) {
-                    const tv2 a = *reinterpret_cast<const tv2*>(t0 + p * plane + j);
-                    mu[b][0][p] = (float)a.x;
-                    mu[b][1][p] = (float)a.y;
+                if constexpr (VX >= 2) {
+                    const tvx a = *reinterpret_cast<const tvx*>(t0 + p * plane + j);
+#pragma unroll
+                    for (int u = 0; u < VX; ++u) mu[b][u][p] = (float)a[u];
                 } else {
                     mu[b][0][p] = (float)(t0 + p * plane)[j];
                 }
@@ -1034,8 +1178,32 @@ void xgemm_any(int enc, dim3 grid, hipStream_t s, const float2* A, const float2*
 template <int MODE, int CC, typename TT>
 hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* theta,
                  const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
-                 float2* U, hipStream_t s)
+                 float2* U, int* nby_used, hipStream_t s)
 {
+    // Wide layout (FP16 trains) when the plan allows it and every operand is
+    // 16-byte aligned.
+    if constexpr (CC == 1 && sizeof(TT) == 2) {
+        int ntw = MODE == 0 ? p.ntws16 : p.ntw16;
+        // At most 64 KB of LDS per block.
+        while (ntw >= 2 && (size_t)ntw * (NWW * d.nx + p.roww) * sizeof(float2) > 65536) ntw /= 2;
+        auto al = [](const void* q, uintptr_t a) { return ((uintptr_t)q & (a - 1)) == 0; };
+        if (ntw >= 2 && al(trains, 16) && al(theta, 16) && (MODE == 0 || al(v, 16)) &&
+            (mask == nullptr || al(mask, 4))) {
+            dim3 grid(p.nbyw, ceil_div(d.T, ntw));
+            const size_t lds = (size_t)ntw * (NWW * d.nx + p.roww) * sizeof(float2);
+            *nby_used = p.nbyw;
+#define FWDW_CASE(NN)                                                                           \
+    if (ntw == NN) {                                                                            \
+        ystage_fwd_wide_kernel<MODE, NN, TT><<<grid, NWW * 64, lds, s>>>(                       \
+            trains, theta, v, mask, eytab, U, d.nx, d.ny, d.nv, d.T, p.roww);                   \
+        return hipGetLastError();                                                               \
+    }
+            FWDW_CASE(2) FWDW_CASE(4)
+#undef FWDW_CASE
+            return hipErrorInvalidValue;
+        }
+    }
+    *nby_used = CC > 1 ? p.nbyc : ((sizeof(TT) == 2 && p.g16 > 0) ? p.nby16 : p.nby);
     // 2-byte trains, one coil: one row per wave, all columns per block.
     if constexpr (sizeof(TT) == 2 && CC == 1) {
         if (p.g16 > 0) {
@@ -1158,6 +1326,17 @@ YPlan make_yplan(const Dims& d)
     p.nby16 = ceil_div(d.ny, rg * 2);
     p.r_fwd16 = ceil_div(d.ny, rg * p.nby16);
     p.fwd_tr16 = 8;
+    // Wide layout (FP16 trains, one coil, nx a multiple of 4, at most 256
+    // columns): NT TRs per block, nbyw row slabs.
+    const bool wide = d.C == 1 && d.nx % 4 == 0 && d.nx <= 256;
+    // FP16 trains only (with FP32 trains the kernel's registers allow just 2
+    // TRs per block in mode 1, slower than the layouts above). Measured at
+    // 224 x 224: 4 TRs per block, 8 slabs of 28 rows.
+    p.ntw16 = wide ? 4 : 0;
+    p.ntws16 = wide ? 4 : 0;
+    p.nbyw = std::min(d.ny, std::max(8, ceil_div(d.ny, 256)));   // <= 256 rows per slab
+    p.roww = ceil_div(d.ny, p.nbyw);
+    p.nbyw = ceil_div(d.ny, p.roww);
     // Adjoint: one row per lane (8 rows per block) and 8 TR chunks: enough
     // blocks in flight to stream the trains near the HBM limit, with partial
     // sums of 8 chunks x 8 floats per voxel.
@@ -1181,16 +1360,16 @@ YPlan make_yplan(const Dims& d)
 template <typename TT>
 hipError_t fwd_typed(const Dims& d, const YPlan& p, int mode, const TT* trains, const float* theta,
                      const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
-                     float2* upart, hipStream_t s)
+                     float2* upart, int* nby, hipStream_t s)
 {
     if (d.C == 1)
-        return mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                         : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+        return mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
+                         : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
     if (d.C <= 8)
-        return mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                         : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
-    return mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s)
-                     : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, s);
+        return mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
+                         : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
+    return mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
+                     : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
 }
 
 template <typename TT>
@@ -1213,10 +1392,10 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
                              const uint8_t* mask, const float2* eytab, float2* upart,
                              hipStream_t s)
 {
+    int nby = 1;
     const hipError_t e =
-        f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, s)
-            : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, s);
-    const int nby = d.C > 1 ? p.nbyc : ((f16 && p.g16 > 0) ? p.nby16 : p.nby);
+        f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, &nby, s)
+            : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, &nby, s);
     if (e != hipSuccess || nby == 1) return e;
     const size_t count = (size_t)d.C * d.T * d.nx;
     usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, nby, count);

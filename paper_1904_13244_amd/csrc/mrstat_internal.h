@@ -33,6 +33,9 @@ struct YPlan {
     int ksplit_adj;   // split-K of the adjoint x-GEMM (partial W outputs)
     int g16, r_fwd16, nby16, fwd_tr16;   // forward y-stage, FP16 trains, one row per wave
     int r_fwdc, nbyc, fwd_trc;           // forward y-stage with coils (per-TR reduction)
+    int ntw16, ntws16, nbyw, roww;       // forward y-stage, wide layout (FP16 trains): TRs per
+                                         // block in mode 1 / mode 0 (0 = off), row slabs, rows
+                                         // per slab
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -118,8 +121,10 @@ enum : int {
 
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
                           double* scal, double* partials, hipStream_t s);
+// One CG iteration after q = Re(J^H J) dir (iter = iteration index from 0;
+// partials hold at least 3 RED_BLOCKS doubles).
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
-                            double* scal, double* partials, hipStream_t s);
+                            double* scal, double* partials, int iter, hipStream_t s);
 hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float* step, float t,
                                   const float* lo, const float* hi, int param_mask,
                                   const uint8_t* mask, float* trial, hipStream_t s);

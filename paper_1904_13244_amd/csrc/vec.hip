@@ -11,8 +11,16 @@ namespace mrstat {
 enum : int {
     S_RR = 0, S_KAPPA = 1, S_ALPHA = 2, S_RRNEW = 3, S_BETA = 4, S_DONE = 5, S_ITERS = 6,
     S_DD = 7, S_F0 = 8, S_G2 = 9, S_PRED = 10, S_FT = 11, S_UPD = 12,
+    S_RR1 = 15, S_DONE1 = 16,
     S_GAMMA = 20, S_QQ = 21, S_CA = 22, S_GNEW = 23, S_CB = 24, S_CDONE = 25, S_STAGE = 30
 };
+
+// rr and the stop flag alternate between two slots by CG iteration parity:
+// iteration k reads slot k & 1 and its direction kernel writes slot
+// (k + 1) & 1, so no block reads a scalar that another block of the same
+// launch writes.
+__device__ __forceinline__ int rr_slot(int par) { return par ? S_RR1 : S_RR; }
+__device__ __forceinline__ int done_slot(int par) { return par ? S_DONE1 : S_DONE; }
 
 namespace {
 
@@ -127,13 +135,13 @@ __global__ __launch_bounds__(RB) void cg_curv_kernel(const float* __restrict__ d
     }
 }
 
-// kappa = dir.q; stop on non-positive curvature; alpha = rr / kappa. UPD marks
-// an iteration that updates step, res and dir (CG not stopped before it).
-__global__ __launch_bounds__(RB) void cg_alpha_kernel(const double* __restrict__ part, int n,
-                                                      double* __restrict__ sc)
+// Every block reduces the same partials in the same fixed order (the result
+// is identical in all blocks); thread 0's sums are broadcast through LDS.
+__device__ __forceinline__ void reduce_pair(const double* __restrict__ part, int n, double* sh,
+                                            double* bc, double& a, double& b)
 {
-    __shared__ double sh[RB / 64];
-    double a = 0.0, b = 0.0;
+    a = 0.0;
+    b = 0.0;
     for (int i = threadIdx.x; i < n; i += RB) {
         a += part[i];
         b += part[n + i];
@@ -141,29 +149,43 @@ __global__ __launch_bounds__(RB) void cg_alpha_kernel(const double* __restrict__
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     if (threadIdx.x == 0) {
-        sc[S_KAPPA] = a;
-        sc[S_DD] = b;
-        if (sc[S_DONE] == 0.0 && a <= 1e-30 * b) sc[S_DONE] = 1.0;
-        sc[S_UPD] = (sc[S_DONE] == 0.0) ? 1.0 : 0.0;
-        sc[S_ALPHA] = (sc[S_DONE] == 0.0) ? sc[S_RR] / a : 0.0;
+        bc[0] = a;
+        bc[1] = b;
     }
+    __syncthreads();
+    a = bc[0];
+    b = bc[1];
 }
 
-// step += alpha dir, res -= alpha q; partial sums of res.res.
+// kappa = dir.q (from the curvature partials); stop on non-positive
+// curvature; alpha = rr / kappa; then step += alpha dir, res -= alpha q and
+// partial sums of res.res. Block 0 records kappa, dir.dir, alpha and UPD (the
+// iteration updates step, res and dir: CG not stopped before it).
 __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ dir,
                                                      const float* __restrict__ q,
                                                      float* __restrict__ step,
                                                      float* __restrict__ res, size_t n,
-                                                     const double* __restrict__ sc,
+                                                     const double* __restrict__ curv, int nblk,
+                                                     double* __restrict__ sc, int par,
                                                      double* __restrict__ part)
 {
     __shared__ double sh[RB / 64];
-    const bool done = sc[S_UPD] == 0.0;
-    const float al = (float)sc[S_ALPHA];
+    __shared__ double bc[2];
+    double kappa, dd;
+    reduce_pair(curv, nblk, sh, bc, kappa, dd);
+    const bool upd = sc[done_slot(par)] == 0.0 && !(kappa <= 1e-30 * dd);
+    const double alpha = upd ? sc[rr_slot(par)] / kappa : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_KAPPA] = kappa;
+        sc[S_DD] = dd;
+        sc[S_UPD] = upd ? 1.0 : 0.0;
+        sc[S_ALPHA] = alpha;
+    }
+    const float al = (float)alpha;
     double v = 0.0;
     for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
         float r = res[i];
-        if (!done) {
+        if (upd) {
             step[i] = fmaf(al, dir[i], step[i]);
             r = fmaf(-al, q[i], r);
             res[i] = r;
@@ -174,31 +196,38 @@ __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ d
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// beta = rr_new / rr, rr = rr_new, count the iteration; a zero residual stops
-// CG before the next iteration.
-__global__ __launch_bounds__(RB) void cg_beta_kernel(const double* __restrict__ part, int n,
-                                                     double* __restrict__ sc)
+// beta = rr_new / rr, dir = res + beta dir. Block 0 records rr_new and beta,
+// counts the iteration and writes rr and the stop flag for the next
+// iteration (a zero residual, or a stopped iteration, stops CG).
+__global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ res,
+                                                    float* __restrict__ dir, size_t n,
+                                                    const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ sc, int par)
 {
     __shared__ double sh[RB / 64];
+    __shared__ double bc[1];
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += RB) v += part[i];
+    for (int i = threadIdx.x; i < nblk; i += RB) v += part[i];
     v = block_sum(v, sh);
-    if (threadIdx.x == 0 && sc[S_UPD] != 0.0) {
-        sc[S_RRNEW] = v;
-        sc[S_BETA] = v / sc[S_RR];
-        sc[S_RR] = v;
-        sc[S_ITERS] += 1.0;
-        if (v == 0.0) sc[S_DONE] = 1.0;
+    if (threadIdx.x == 0) bc[0] = v;
+    __syncthreads();
+    v = bc[0];
+    const bool upd = sc[S_UPD] != 0.0;
+    const double rr = sc[rr_slot(par)];
+    const double beta = upd ? v / rr : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (upd) {
+            sc[S_RRNEW] = v;
+            sc[S_BETA] = beta;
+            sc[S_ITERS] += 1.0;
+        }
+        sc[rr_slot(par ^ 1)] = upd ? v : rr;
+        sc[done_slot(par ^ 1)] = (!upd || v == 0.0) ? 1.0 : 0.0;
     }
-}
-
-__global__ void cg_dir_kernel(const float* __restrict__ res, float* __restrict__ dir, size_t n,
-                              const double* __restrict__ sc)
-{
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (sc[S_UPD] == 0.0) return;
-    dir[i] = fmaf((float)sc[S_BETA], dir[i], res[i]);
+    if (!upd) return;
+    const float b = (float)beta;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB)
+        dir[i] = fmaf(b, dir[i], res[i]);
 }
 
 // trial = P(theta + t step): active ln T1, ln T2, B1 clamped to the box.
@@ -366,14 +395,15 @@ hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res
 }
 
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
-                            double* scal, double* partials, hipStream_t s)
+                            double* scal, double* partials, int iter, hipStream_t s)
 {
+    // partials: curvature pairs [2][RED_BLOCKS], then res.res [RED_BLOCKS].
     const size_t n = (size_t)5 * d.nv;
+    double* rrp = partials + 2 * RED_BLOCKS;
     cg_curv_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, n, partials);
-    cg_alpha_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
-    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, scal, partials);
-    cg_beta_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
-    cg_dir_kernel<<<grid_for(n), 256, 0, s>>>(res, dir, n, scal);
+    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, RED_BLOCKS, scal,
+                                             iter & 1, rrp);
+    cg_dir_kernel<<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1);
     return hipGetLastError();
 }
 

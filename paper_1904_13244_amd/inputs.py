@@ -265,7 +265,7 @@ def config(idx: int) -> Workload:
         prob = make_problem(256, 256, 1280, 512, 32, n_coils=8)
         th, head = brain_phantom(256, 256, b1_range=(0.8, 1.2))
         return Workload("256x256 phantom, 8 coils, 1280 TRs, Nk 512, K 32, SNR 50", prob, th,
-                        coil_maps(256, 256, 8), 50.0, 15, 30, 0b11111, {"head": head})
+                        coil_maps(256, 256, 8), 50.0, 15, 30, 0b11011, {"head": head})
     raise ValueError(idx)
 
 

@@ -1,9 +1,10 @@
 """What the trained surrogate gains, and what it costs in map accuracy.
 
-At the 224 x 224, 1120-TR workload the network is trained on the GPU by the
-library's own kernels (2M box samples simulated by the library's EPG), then
-the same Gauss-Newton reconstruction (T1, T2, rho; B1 known; head mask; from
-the standard initial guess with rho from CGLS) runs twice: plain (FP32 EPG
+At the 224 x 224, 1120-TR workload and at the 256 x 256, 8-coil, 1280-TR
+workload (noise at SNR 50) the network is trained on the GPU by the library's
+own kernels (2M box samples simulated by the library's EPG), then the same
+Gauss-Newton reconstruction (T1, T2, rho; B1 known; head mask; from the
+standard initial guess with rho from CGLS) runs twice: plain (FP32 EPG
 trains, FP32 encoding contraction) and surrogate (network trains stored in
 FP16, EPG outside the box, split-BF16 encoding contraction). The plain run is
 the reference the surrogate is judged against: EPG judges the surrogate's
@@ -36,12 +37,15 @@ def _mape(a, b, sel):
     return 100.0 * float(np.mean(np.abs(np.exp(a[sel]) - np.exp(b[sel])) / np.exp(b[sel])))
 
 
-def test_trained_surrogate_maps_and_speed(torch_gpu):
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_trained_surrogate_maps_and_speed(torch_gpu, cfg):
+    """cfg 4: 224 x 224, 1120 TRs, noiseless, 10 GN x 20 CG; cfg 5: 256 x 256,
+    8 coils, 1280 TRs, SNR 50, 15 GN x 30 CG."""
     torch = torch_gpu
     from paper_1904_13244_amd import binding as B
     from paper_1904_13244_amd.binding import Context
     from paper_1904_13244_amd.surrogate import train_surrogate
-    w = I.config(4)
+    w = I.config(cfg)
     prob, head = w.problem, w.extra["head"]
     print(f"\n[surrogate maps] {w.name}", flush=True)
     net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=40)
@@ -49,11 +53,16 @@ def test_trained_surrogate_maps_and_speed(torch_gpu):
           f"{['%.2e' % e for e in rep.val_rel_err]}", flush=True)
     assert max(rep.val_rel_err[:3]) <= 2e-2 and rep.val_rel_err[3] <= 0.15
 
-    ctx = Context(prob, mask=torch.as_tensor(head.astype(np.uint8)).cuda())
     dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    coil = None if w.coil is None else dev(w.coil, torch.complex64)
+    ctx = Context(prob, coil=coil, mask=torch.as_tensor(head.astype(np.uint8)).cuda())
     zero = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
     _, r = ctx.residual(dev(w.theta, torch.float32), zero)
     d = (-r).contiguous()
+    if w.snr is not None:
+        n = I.unit_noise(prob)
+        s_norm = float(torch.linalg.vector_norm(d))
+        d = d + dev(n * (s_norm / (w.snr * np.linalg.norm(n))), torch.complex64)
     th0 = I.initial_theta(prob.nv)
     th0[2] = w.theta[2]                      # B1 known
     box_lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
@@ -69,11 +78,11 @@ def test_trained_surrogate_maps_and_speed(torch_gpu):
         ctx.rho_init(th, d, 20)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(10):
+        for _ in range(w.n_gn):
             rp = ctx.gn_step(th, d, w.n_cg, w.param_mask, lo, hi)
             assert rp.n_fallback == 0
         torch.cuda.synchronize()
-        ms[name] = 1e3 * (time.perf_counter() - t0) / 10
+        ms[name] = 1e3 * (time.perf_counter() - t0) / w.n_gn
         maps[name] = th.cpu().numpy().astype(np.float64)
         print(f"  [{name}] {ms[name]:.2f} ms/GN step; T1 MAPE vs truth "
               f"{_mape(maps[name][0], w.theta[0], head):.3f} %, T2 "

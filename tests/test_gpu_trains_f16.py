@@ -61,12 +61,33 @@ def _even_ragged():
     return prob, th, None, mask
 
 
+def _wide_mask():
+    """Wide forward layout: nx a multiple of 4 but not of 8, ny over two row
+    slabs, T not a multiple of the TRs per block, a mask."""
+    rng = np.random.default_rng(80)
+    T = 37
+    prob = I.make_problem(44, 300, T, 48, 8, flip_deg=rng.uniform(5, 70, T), t_inv=0.01)
+    th = I.iid_maps(prob.nv, seed=11, b1=rng.uniform(0.8, 1.2, prob.nv))
+    mask = (rng.uniform(size=prob.nv) > 0.15).astype(np.uint8)
+    return prob, th, None, mask
+
+
+def _wide_max():
+    """Wide forward layout at its widest row (256 columns), three rows."""
+    rng = np.random.default_rng(81)
+    T = 9
+    prob = I.make_problem(256, 3, T, 256, 6, flip_deg=rng.uniform(5, 70, T))
+    th = I.iid_maps(prob.nv, seed=12, b1=rng.uniform(0.8, 1.2, prob.nv))
+    return prob, th, None, None
+
+
 def _config1():
     w = I.config(1)
     return w.problem, w.theta, None, None
 
 
-CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils, "even_ragged": _even_ragged}
+CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils, "even_ragged": _even_ragged,
+         "wide_mask": _wide_mask, "wide_max": _wide_max}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -103,6 +124,14 @@ def test_f16_trains_and_products(torch_gpu, oracle_lib, name):
     e_r = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(s))
     print(f"  jv {e_jv:.2e} jhw {e_jhw:.2e} residual/||d|| {e_r:.2e}", flush=True)
     assert max(e_jv, e_jhw, e_r) <= 1e-3
+    # Operands that are not 16-byte aligned take the general layouts.
+    buf = torch.zeros(5 * prob.nv + 1, dtype=torch.float32, device="cuda")
+    th_off = buf[1:].view(5, prob.nv)
+    th_off.copy_(thd)
+    jv_off = ctx.jv(th_off, _dev(torch, v, torch.float32)).cpu().numpy().astype(np.complex128)
+    e_off = _rel(jv_off, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
+    print(f"  jv with theta at a 4-byte offset {e_off:.2e}", flush=True)
+    assert e_off <= 1e-3
     # Switching back restores the FP32 path exactly (within its own bar).
     ctx.set_train_precision(B.TRAINS_FP32)
     got32 = ctx.simulate(thd).cpu().numpy().astype(np.float64)

@@ -21,6 +21,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
     size_t trains, trial_m, upart, W, apart, r, y, vec, red, scal, seq, eytab, extab;
+    size_t bf[2][2];   // B-fragment tables [direction][split-BF16, FP16]
     size_t cx, csv, cp, cth, fb, total;
     int n_red;
     YPlan yp;
@@ -71,6 +72,8 @@ struct mrstat_ctx_s {
     const float2* dseq() const { return at<float2>(L.seq); }
     const float2* deytab() const { return at<float2>(L.eytab); }
     const float2* dextab() const { return at<float2>(L.extab); }
+    // B-fragment table of the current encoding for direction dir (null for FP32).
+    const void* bfrag(int dir) const { return enc == 0 ? nullptr : (const void*)(ws + L.bf[dir][enc - 1]); }
     int* fb_count(int slot) const { return at<int>(L.fb) + slot; }   // 0: linearisation, 1: value
     int* fb_idx() const { return at<int>(L.fb) + 64; }
 };
@@ -133,7 +136,7 @@ Layout make_layout(const Dims& d)
     Layout L{};
     L.yp = make_yplan(d);
     const int M = d.C * d.T;
-    const int gemm_blocks = ceil_div(2 * d.nk, 64) * ceil_div(M, 64);
+    const int gemm_blocks = std::max(ceil_div(2 * d.nk, 64) * ceil_div(M, 64), xgemm_direct_blocks(d));
     L.n_red = std::max(3 * RED_BLOCKS, gemm_blocks);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -151,6 +154,8 @@ Layout make_layout(const Dims& d)
     L.seq = take(T * sizeof(float2));
     L.eytab = take(T * d.ny * sizeof(float2));
     L.extab = take((size_t)d.nk * d.nx * sizeof(float2));
+    for (int dir = 0; dir < 2; ++dir)
+        for (int e = 0; e < 2; ++e) L.bf[dir][e] = take(bfrag_bytes(d, dir, e + 1));
     L.cx = take(nv * sizeof(float2));
     L.csv = take(nv * sizeof(float2));
     L.cp = take(nv * sizeof(float2));
@@ -250,7 +255,7 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
                                      ctx->deytab(), ctx->upart(), s)));
     int nred = 0;
     HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, p, ctx->enc, mode_x, ctx->upart(),
-                                                   ctx->dextab(), (const float2*)data, (float2*)out,
+                                                   ctx->dextab(), ctx->bfrag(0), (const float2*)data, (float2*)out,
                                                    ctx->red(), &nred, s)));
     if (mode_x == 0 && f_out)
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_sum_partials(ctx->red(), nred, f_out, s)));
@@ -263,7 +268,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
     HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
-                                                   ctx->W(), s)));
+                                                   ctx->bfrag(1), ctx->W(), s)));
     HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 4, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
     HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g, s)));
@@ -382,6 +387,8 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const voi
                            ctx->eytab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.extab, ctx->extab.data(),
                            ctx->extab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_build_bfrag(ctx->d, ctx->dextab(), ctx->ws + ctx->L.bf[0][0], ctx->ws + ctx->L.bf[1][0],
+                               ctx->ws + ctx->L.bf[0][1], ctx->ws + ctx->L.bf[1][1], s));
     // Device scalars start from zero.
     HIP_TRY(hipMemsetAsync(ctx->ws + ctx->L.scal, 0, SCAL_DOUBLES * sizeof(double), s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -619,7 +626,7 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     // M^H w for the rho-linear map: adjoint y-stage on the m train only.
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
         const YPlan& p = ctx->L.yp;
-        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->W(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->bfrag(1), ctx->W(), s)));
         HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 1, ctx->coil, ctx->mask,
                                                         ctx->deytab(), ctx->W(), ctx->apart(), s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_rho_adj_finish(d, p, ctx->apart(), ctx->mask, out, s)));

@@ -813,6 +813,7 @@ __global__ void rho_adj_finish_kernel(const float* __restrict__ apart, int n_chu
 // B lane l -> (k l/16, col l%16), D lane l -> (rows 4(l/16)+i, col l%16).
 // ------------------------------------------------------------------------
 constexpr int GBM = 64, GBN = 64, GBK = 32;
+constexpr int XPD = 2;   // K chunks in flight (deeper pipelining measured no faster)
 
 template <int DIR, int MODE>   // DIR 0 forward, 1 adjoint; MODE (forward): 0 residual, 1 -s, 2 +s
 __global__ __launch_bounds__(256) void xgemm_f32_kernel(
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
     int nx, int nk, int chunks_per_split, size_t out_stride)
 {
     __shared__ float As[2][GBM][GBK + 1];
-    __shared__ float Bs[2][GBK][GBN + 4];
+    __shared__ __attribute__((aligned(16))) float Bs[2][GBK][GBN + 4];
     __shared__ double rs[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -833,15 +834,16 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
     const int kc0 = blockIdx.z * chunks_per_split;
     const int kc1 = min(nchunk, kc0 + chunks_per_split);
 
-    float2 ra[4], rb[2];
-    auto gload = [&](int kc) {
+    // Chunks past kc1 (padding of the pipelined loop) load zeros.
+    auto gload = [&](int kc, float2 (&ra)[4], float2 (&rb)[2]) {
         const int k0 = kc * GBK;
+        const bool live = kc < kc1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i;
             const int r = e >> 4, cc = e & 15;
             const int m = m0 + r, kcol = k0 / 2 + cc;
-            ra[i] = (m < M && kcol < Ka) ? Ain[(size_t)m * Ka + kcol] : make_float2(0.f, 0.f);
+            ra[i] = (live && m < M && kcol < Ka) ? Ain[(size_t)m * Ka + kcol] : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -852,14 +854,14 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
             const int kr = k0 / 2 + rr, kcol = c0 / 2 + cc;
             float2 E = make_float2(0.f, 0.f);
             if (DIR == 0) {
-                if (kr < nx && kcol < nk) E = extab[(size_t)kcol * nx + kr];
+                if (live && kr < nx && kcol < nk) E = extab[(size_t)kcol * nx + kr];
             } else {
-                if (kr < nk && kcol < nx) E = extab[(size_t)kr * nx + kcol];
+                if (live && kr < nk && kcol < nx) E = extab[(size_t)kr * nx + kcol];
             }
             rb[i] = E;
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, const float2 (&ra)[4], const float2 (&rb)[2]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i;
@@ -873,15 +875,9 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
             const int rr = DIR == 0 ? (e & 15) : (e >> 5);
             const int cc = DIR == 0 ? (e >> 4) : (e & 31);
             const float2 E = rb[i];
-            Bs[buf][2 * rr][2 * cc] = E.x;
-            Bs[buf][2 * rr + 1][2 * cc + 1] = E.x;
-            if (DIR == 0) {
-                Bs[buf][2 * rr][2 * cc + 1] = E.y;
-                Bs[buf][2 * rr + 1][2 * cc] = -E.y;
-            } else {
-                Bs[buf][2 * rr][2 * cc + 1] = -E.y;
-                Bs[buf][2 * rr + 1][2 * cc] = E.y;
-            }
+            const float ey = DIR == 0 ? E.y : -E.y;
+            *reinterpret_cast<float2*>(&Bs[buf][2 * rr][2 * cc]) = make_float2(E.x, ey);
+            *reinterpret_cast<float2*>(&Bs[buf][2 * rr + 1][2 * cc]) = make_float2(-ey, E.x);
         }
     };
 
@@ -891,30 +887,36 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-    if (kc0 < kc1) {
-        gload(kc0);
-        sstore(0);
-    }
+    // XPD chunks in flight: chunk kc + XPD - 1 is loaded while chunk kc is
+    // multiplied from LDS and chunk kc + 1 stored; the loop runs a multiple of
+    // XPD chunks (the padding is zero).
+    float2 ra[XPD][4], rb[XPD][2];
+#pragma unroll
+    for (int u = 0; u < XPD - 1; ++u) gload(kc0 + u, ra[u], rb[u]);
+    sstore(0, ra[0], rb[0]);
     __syncthreads();
-    for (int kc = kc0; kc < kc1; ++kc) {
-        const int buf = (kc - kc0) & 1;
-        const bool more = kc + 1 < kc1;
-        if (more) gload(kc + 1);
+    for (int kb = kc0; kb < kc1; kb += XPD) {
 #pragma unroll
-        for (int kk = 0; kk < GBK; kk += 4) {
-            float av[2], bv[2];
+        for (int u = 0; u < XPD; ++u) {
+            const int kc = kb + u;
+            const int buf = (kc - kc0) & 1;
+            gload(kc + XPD - 1, ra[(u + XPD - 1) % XPD], rb[(u + XPD - 1) % XPD]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[buf][wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int kk = 0; kk < GBK; kk += 4) {
+                float av[2], bv[2];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+                for (int a = 0; a < 2; ++a) av[a] = As[buf][wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+            sstore(buf ^ 1, ra[(u + 1) % XPD], rb[(u + 1) % XPD]);
+            __syncthreads();
         }
-        if (more) sstore(buf ^ 1);
-        __syncthreads();
     }
 
     // Epilogue.
@@ -952,19 +954,16 @@ __global__ __launch_bounds__(256) void xgemm_f32_kernel(
 }
 
 // ------------------------------------------------------------------------
-// Reduced-precision x-stage GEMMs on v_mfma_f32_16x16x32_{bf16,f16}: the same
-// real 2x2-block form and tiling as the FP32 kernel, with BK = 32 real K per
-// chunk (one MFMA per 16x16 block and product term).
+// Reduced-precision x-stage GEMMs on v_mfma_f32_16x16x32_{bf16,f16}, same
+// real 2x2-block form as the FP32 kernel:
 //   ENC 1, split-BF16: each FP32 operand x = hi + lo, hi = bf16(x),
 //          lo = bf16(x - hi); C = hi*hi + hi*lo + lo*hi with FP32 accumulation
 //          (the lo*lo term, ~2^-16 relative, is dropped).
 //   ENC 2, FP16: one product of FP16-rounded operands, FP32 accumulation
 //          (operands must stay below 65504 in magnitude: |U|, |w| and the
 //          unit-modulus phases do for these problems).
-// Operands are stored k-contiguous in LDS (A row-major, B transposed) so a
-// lane's 8-element fragment is one 128-bit LDS read. MFMA 16x16x32 operand
-// layout: A lane l -> (row l%16, k 8(l/16)..+7), B lane l -> (k 8(l/16)..+7,
-// col l%16), D as for the FP32 instruction.
+// MFMA 16x16x32 operand layout: A lane l -> (row l%16, k 8(l/16)..+7),
+// B lane l -> (k 8(l/16)..+7, col l%16), D as for the FP32 instruction.
 // ------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -980,8 +979,6 @@ __device__ __forceinline__ float bf16_bits_to_float(unsigned short b)
 {
     return __uint_as_float((unsigned int)b << 16);
 }
-
-constexpr int XPAD = 8;   // 16-bit elements of row padding (keeps 16-byte alignment)
 
 template <int ENC>
 struct MxOps;
@@ -1015,134 +1012,190 @@ struct MxOps<2> {
     }
 };
 
-template <int DIR, int MODE, int ENC>
-__global__ __launch_bounds__(256) void xgemm_mx_kernel(
-    const float2* __restrict__ Ain, const float2* __restrict__ extab,
-    const float2* __restrict__ data, float2* __restrict__ out, double* __restrict__ red, int M,
-    int nx, int nk, int chunks_per_split, size_t out_stride)
+// ------------------------------------------------------------------------
+// Reduced-precision x-stage GEMMs without LDS. The real-form phase matrix
+// (Bf forward, Ba adjoint, as above) is fixed for a context, so it is split
+// once at bind into B-fragment tables in the MFMA operand order:
+//   bfrag[((kb NCB + cb) NT + t) 64 + l] = 8 16-bit values of term t of
+//   B[32 kb + 8(l/16) + e][16 cb + l%16], e = 0..7 (zero beyond Kr, Nr),
+// with kb the 32-row K block, cb the 16-column block, t = hi / lo (ENC 1) or
+// the FP16 value (ENC 2). One wave computes a 16 x 32 output tile over all
+// of K: its A fragment (row l%16, 8 consecutive real k = 4 complex elements,
+// two 16-byte loads) is split in registers and its B fragments are single
+// 16-byte loads, so waves share nothing, need no barrier, and a launch has
+// M/16 x Nr/32 waves to hide load latency with.
+// ------------------------------------------------------------------------
+template <int DIR, int ENC>
+__global__ void build_bfrag_kernel(const float2* __restrict__ extab, uint4* __restrict__ out,
+                                   int nx, int nk)
 {
+    constexpr int NT = MxOps<ENC>::TERMS;
+    const int Kr = DIR == 0 ? 2 * nx : 2 * nk, Nr = DIR == 0 ? 2 * nk : 2 * nx;
+    const int KB = (Kr + 31) / 32, NCB = (Nr + 15) / 16;
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)KB * NCB * 64) return;
+    const int l = (int)(g % 64), cb = (int)((g / 64) % NCB), kb = (int)(g / (64 * (size_t)NCB));
+    const int col = 16 * cb + (l & 15);
+    unsigned short h[8], lo[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int kr = 32 * kb + 8 * (l >> 4) + e;
+        float v = 0.f;
+        if (kr < Kr && col < Nr) {
+            const int a = kr & 1, b = col & 1;
+            const float2 E = DIR == 0 ? extab[(size_t)(col >> 1) * nx + (kr >> 1)]
+                                      : extab[(size_t)(kr >> 1) * nx + (col >> 1)];
+            // Bf = [[Er, Ei], [-Ei, Er]], Ba = [[Er, -Ei], [Ei, Er]] (row a, column b).
+            v = (a == b) ? E.x : ((DIR == 0) == (a == 0) ? E.y : -E.y);
+        }
+        MxOps<ENC>::split(v, &h[e], &lo[e]);
+    }
+    const size_t base = ((size_t)kb * NCB + cb) * NT * 64 + l;
+    out[base] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                           h[6] | (h[7] << 16));
+    if constexpr (NT > 1)
+        out[base + 64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
+                                    lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
+}
+
+template <int DIR, int MODE, int ENC, int KS, int RW>
+__global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
+    const float2* __restrict__ Ain, const uint4* __restrict__ bfrag,
+    const float2* __restrict__ data, float2* __restrict__ out, double* __restrict__ red, int M,
+    int nx, int nk)
+{
+    // A wave's tile is 16 RW rows x 32 columns. KS waves per block share one
+    // tile and take every KS-th K block; their sums meet in LDS.
     using Ops = MxOps<ENC>;
     constexpr int NT = Ops::TERMS;
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][NT][GBM][GBK + XPAD];
-    __shared__ __attribute__((aligned(16))) unsigned short Bt[2][NT][GBN][GBK + XPAD];
-    __shared__ double rs[4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * GBM, c0 = blockIdx.x * GBN;
+    __shared__ f4 part[KS > 1 ? KS - 1 : 1][RW][2][64];
+    const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
     const int Kr = DIR == 0 ? 2 * nx : 2 * nk;
     const int Nr = DIR == 0 ? 2 * nk : 2 * nx;
-    const int Ka = DIR == 0 ? nx : nk;
-    const int nchunk = (Kr + GBK - 1) / GBK;
-    const int kc0 = blockIdx.z * chunks_per_split;
-    const int kc1 = min(nchunk, kc0 + chunks_per_split);
-
-    float2 ra[4], rb[2];
-    auto gload = [&](int kc) {
-        const int k0 = kc * GBK;
+    const int Ka = Kr / 2;
+    const int KB = (Kr + 31) / 32, NCB = (Nr + 15) / 16;
+    const int cb0 = 2 * blockIdx.x;
+    const int m0 = 16 * RW * blockIdx.y;
+    const int kq = 4 * (lane >> 4);
+    const bool vec = (Ka & 1) == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0;   // 16-byte loads
+    int rowc[RW];
+    bool rowok[RW];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int r = e >> 4, cc = e & 15;
-            const int m = m0 + r, kcol = k0 / 2 + cc;
-            ra[i] = (m < M && kcol < Ka) ? Ain[(size_t)m * Ka + kcol] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int e = tid + 256 * i;
-            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
-            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
-            const int kr = k0 / 2 + rr, kcol = c0 / 2 + cc;
-            float2 E = make_float2(0.f, 0.f);
-            if (DIR == 0) {
-                if (kr < nx && kcol < nk) E = extab[(size_t)kcol * nx + kr];
-            } else {
-                if (kr < nk && kcol < nx) E = extab[(size_t)kr * nx + kcol];
-            }
-            rb[i] = E;
-        }
-    };
-    auto put = [&](unsigned short (*dst)[GBM][GBK + XPAD], int row, int k, float x) {
-        unsigned short h, l;
-        Ops::split(x, &h, &l);
-        dst[0][row][k] = h;
-        if constexpr (NT > 1) dst[1][row][k] = l;
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int r = e >> 4, cc = e & 15;
-            put(As[buf], r, 2 * cc, ra[i].x);
-            put(As[buf], r, 2 * cc + 1, ra[i].y);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int e = tid + 256 * i;
-            const int rr = DIR == 0 ? (e & 15) : (e >> 5);
-            const int cc = DIR == 0 ? (e >> 4) : (e & 31);
-            const float2 E = rb[i];
-            // B[2rr + a][2cc + b] stored transposed at Bt[2cc + b][2rr + a].
-            put(Bt[buf], 2 * cc, 2 * rr, E.x);
-            put(Bt[buf], 2 * cc + 1, 2 * rr + 1, E.x);
-            put(Bt[buf], 2 * cc + 1, 2 * rr, DIR == 0 ? E.y : -E.y);
-            put(Bt[buf], 2 * cc, 2 * rr + 1, DIR == 0 ? -E.y : E.y);
-        }
-    };
-
-    f4 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-
-    if (kc0 < kc1) {
-        gload(kc0);
-        sstore(0);
+    for (int r = 0; r < RW; ++r) {
+        const int row = m0 + 16 * r + (lane & 15);
+        rowok[r] = row < M;
+        rowc[r] = rowok[r] ? row : 0;
     }
-    __syncthreads();
-    const int kq = 8 * (lane >> 4);
-    for (int kc = kc0; kc < kc1; ++kc) {
-        const int buf = (kc - kc0) & 1;
-        const bool more = kc + 1 < kc1;
-        if (more) gload(kc + 1);
-        uint4 af[NT][2], bf[NT][2];
+
+    auto load_a = [&](int kb, float2 (&a)[RW][4]) {
+        const int k0 = 16 * kb + kq;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int r = 0; r < RW; ++r) {
+            const float2* __restrict__ arow = Ain + (size_t)rowc[r] * Ka;
+            if (vec && rowok[r] && k0 + 3 < Ka) {
+                const float4 u = *reinterpret_cast<const float4*>(arow + k0);
+                const float4 w = *reinterpret_cast<const float4*>(arow + k0 + 2);
+                a[r][0] = make_float2(u.x, u.y);
+                a[r][1] = make_float2(u.z, u.w);
+                a[r][2] = make_float2(w.x, w.y);
+                a[r][3] = make_float2(w.z, w.w);
+            } else {
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                af[t][a] = *reinterpret_cast<const uint4*>(&As[buf][t][wm * 32 + a * 16 + (lane & 15)][kq]);
+                for (int e = 0; e < 4; ++e)
+                    a[r][e] = (rowok[r] && k0 + e < Ka) ? arow[k0 + e] : make_float2(0.f, 0.f);
+            }
+        }
+    };
+    auto load_b = [&](int kb, uint4 (&b)[2][NT]) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                bf[t][b] = *reinterpret_cast<const uint4*>(&Bt[buf][t][wn * 32 + b * 16 + (lane & 15)][kq]);
+        for (int c = 0; c < 2; ++c) {
+            const int cb = cb0 + c < NCB ? cb0 + c : NCB - 1;   // clamped; its output is not stored
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[c][t] = bfrag[(((size_t)kb * NCB + cb) * NT + t) * 64 + lane];
+        }
+    };
+
+    f4 acc[RW][2];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+    float2 a_cur[RW][4], a_nxt[RW][4];
+    uint4 b_cur[2][NT], b_nxt[2][NT];
+    if (kw < KB) {
+        load_a(kw, a_cur);
+        load_b(kw, b_cur);
+    }
+    for (int kb = kw; kb < KB; kb += KS) {
+        if (kb + KS < KB) {
+            load_a(kb + KS, a_nxt);
+            load_b(kb + KS, b_nxt);
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int r = 0; r < RW; ++r) {
+            unsigned short hh[8], ll[8];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                if constexpr (NT > 1) {
-                    acc[a][b] = Ops::mma(af[1][a], bf[0][b], acc[a][b]);   // lo * hi
-                    acc[a][b] = Ops::mma(af[0][a], bf[1][b], acc[a][b]);   // hi * lo
-                }
-                acc[a][b] = Ops::mma(af[0][a], bf[0][b], acc[a][b]);       // hi * hi
+            for (int e = 0; e < 4; ++e) {
+                Ops::split(a_cur[r][e].x, &hh[2 * e], &ll[2 * e]);
+                Ops::split(a_cur[r][e].y, &hh[2 * e + 1], &ll[2 * e + 1]);
             }
-        if (more) sstore(buf ^ 1);
+            const uint4 ah = make_uint4(hh[0] | (hh[1] << 16), hh[2] | (hh[3] << 16),
+                                        hh[4] | (hh[5] << 16), hh[6] | (hh[7] << 16));
+            uint4 al = make_uint4(0u, 0u, 0u, 0u);
+            if constexpr (NT > 1)
+                al = make_uint4(ll[0] | (ll[1] << 16), ll[2] | (ll[3] << 16), ll[4] | (ll[5] << 16),
+                                ll[6] | (ll[7] << 16));
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if constexpr (NT > 1) {
+                    acc[r][c] = Ops::mma(al, b_cur[c][0], acc[r][c]);   // lo * hi
+                    acc[r][c] = Ops::mma(ah, b_cur[c][1], acc[r][c]);   // hi * lo
+                }
+                acc[r][c] = Ops::mma(ah, b_cur[c][0], acc[r][c]);       // hi * hi
+            }
+        }
+        if (kb + KS < KB) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a_cur[r][e] = a_nxt[r][e];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) b_cur[c][t] = b_nxt[c][t];
+        }
+    }
+    if constexpr (KS > 1) {
+        if (kw > 0) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                part[kw - 1][r][0][lane] = acc[r][0];
+                part[kw - 1][r][1][lane] = acc[r][1];
+            }
+        }
         __syncthreads();
+        if (kw > 0) return;
+#pragma unroll
+        for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                acc[r][0] += part[w][r][0][lane];
+                acc[r][1] += part[w][r][1][lane];
+            }
     }
 
     double sq = 0.0;
-    float* o = reinterpret_cast<float*>(out) + blockIdx.z * out_stride;
+    float* o = reinterpret_cast<float*>(out);
     const float* dd = reinterpret_cast<const float*>(data);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int m = m0 + wm * 32 + a * 16 + 4 * (lane >> 4) + i;
-                const int c = c0 + wn * 32 + b * 16 + (lane & 15);
-                if (m < M && c < Nr) {
-                    const size_t idx = (size_t)m * Nr + c;
-                    const float val = acc[a][b][i];
+                const int m = m0 + 16 * r + 4 * (lane >> 4) + i;
+                const int col = 16 * (cb0 + c) + (lane & 15);
+                if (m < M && col < Nr) {
+                    const size_t idx = (size_t)m * Nr + col;
+                    const float val = acc[r][c][i];
                     if (DIR == 0 && MODE == 0) {
                         const float rv = dd[idx] - val;
                         o[idx] = rv;
@@ -1156,23 +1209,15 @@ __global__ __launch_bounds__(256) void xgemm_mx_kernel(
             }
     if (DIR == 0 && MODE == 0) {
         for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
-        if (lane == 0) rs[wave] = sq;
-        __syncthreads();
-        if (tid == 0) red[blockIdx.y * gridDim.x + blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+        if (lane == 0) red[blockIdx.y * gridDim.x + blockIdx.x] = sq;
     }
 }
 
 template <int DIR, int MODE>
-void xgemm_any(int enc, dim3 grid, hipStream_t s, const float2* A, const float2* extab,
-               const float2* data, float2* out, double* red, int M, int nx, int nk, int per,
-               size_t stride)
+void xgemm_any(dim3 grid, hipStream_t s, const float2* A, const float2* extab, const float2* data,
+               float2* out, double* red, int M, int nx, int nk, int per, size_t stride)
 {
-    if (enc == 1)
-        xgemm_mx_kernel<DIR, MODE, 1><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
-    else if (enc == 2)
-        xgemm_mx_kernel<DIR, MODE, 2><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
-    else
-        xgemm_f32_kernel<DIR, MODE><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
+    xgemm_f32_kernel<DIR, MODE><<<grid, 256, 0, s>>>(A, extab, data, out, red, M, nx, nk, per, stride);
 }
 
 template <int MODE, int CC, typename TT>
@@ -1402,33 +1447,94 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
     return hipGetLastError();
 }
 
+size_t bfrag_bytes(const Dims& d, int dir, int enc)
+{
+    const int Kr = dir == 0 ? 2 * d.nx : 2 * d.nk, Nr = dir == 0 ? 2 * d.nk : 2 * d.nx;
+    return (size_t)ceil_div(Kr, 32) * ceil_div(Nr, 16) * (enc == 1 ? 2 : 1) * 64 * sizeof(uint4);
+}
+
+int xgemm_direct_blocks(const Dims& d) { return ceil_div(2 * d.nk, 32) * ceil_div(d.C * d.T, 16); }   // >= any RW
+
+hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void* a1, void* f2,
+                              void* a2, hipStream_t s)
+{
+    auto grid = [&](int dir) {
+        const int Kr = dir == 0 ? 2 * d.nx : 2 * d.nk, Nr = dir == 0 ? 2 * d.nk : 2 * d.nx;
+        return (unsigned)ceil_div(ceil_div(Kr, 32) * ceil_div(Nr, 16) * 64, 256);
+    };
+    build_bfrag_kernel<0, 1><<<grid(0), 256, 0, s>>>(extab, (uint4*)f1, d.nx, d.nk);
+    build_bfrag_kernel<1, 1><<<grid(1), 256, 0, s>>>(extab, (uint4*)a1, d.nx, d.nk);
+    build_bfrag_kernel<0, 2><<<grid(0), 256, 0, s>>>(extab, (uint4*)f2, d.nx, d.nk);
+    build_bfrag_kernel<1, 2><<<grid(1), 256, 0, s>>>(extab, (uint4*)a2, d.nx, d.nk);
+    return hipGetLastError();
+}
+
+// Tiles of 32 rows x 32 columns per wave; 2 waves per tile split K in the
+// forward (K = 2 nx), 4 in the adjoint (K = 2 nk). Measured at 224 x 224 with
+// 1120 TRs (HIP-event times, forward / adjoint): 16 x 32 tiles with 1 wave
+// 16 / 23 us, 16 x 32 with 4 waves 16 / 15, 32 x 32 with 2 waves 15.4 / 17.4,
+// with 4 waves 16.4 / 13.1, 64 x 32 with 4 waves 18.9 / 14.7; the LDS-tiled
+// kernel 19 / 25 (including its split-K sum).
+constexpr int XRW = 2;
+
+template <int DIR, int MODE>
+void xgemm_direct(int enc, const Dims& d, const float2* A, const void* bfrag, const float2* data,
+                  float2* out, double* red, int* nred, hipStream_t s)
+{
+    const int Nr = DIR == 0 ? 2 * d.nk : 2 * d.nx;
+    dim3 grid(ceil_div(Nr, 32), ceil_div(d.C * d.T, 16 * XRW));
+    if (nred) *nred = grid.x * grid.y;
+    constexpr int KS = DIR == 0 ? 2 : 4;
+    if (enc == 1)
+        xgemm_direct_kernel<DIR, MODE, 1, KS, XRW><<<grid, 64 * KS, 0, s>>>(
+            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+    else
+        xgemm_direct_kernel<DIR, MODE, 2, KS, XRW><<<grid, 64 * KS, 0, s>>>(
+            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+}
+
 hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, const float2* U,
-                            const float2* extab, const float2* data, float2* out, double* red,
-                            int* nred, hipStream_t s)
+                            const float2* extab, const void* bfrag, const float2* data, float2* out,
+                            double* red, int* nred, hipStream_t s)
 {
     (void)p;
     const int M = d.C * d.T;
+    if (enc != 0) {
+        if (bfrag == nullptr) return hipErrorInvalidValue;
+        if (mode == 0)
+            xgemm_direct<0, 0>(enc, d, U, bfrag, data, out, red, nred, s);
+        else if (mode == 1)
+            xgemm_direct<0, 1>(enc, d, U, bfrag, data, out, red, nred, s);
+        else
+            xgemm_direct<0, 2>(enc, d, U, bfrag, data, out, red, nred, s);
+        return hipGetLastError();
+    }
     dim3 grid(ceil_div(2 * d.nk, GBN), ceil_div(M, GBM), 1);
     if (nred) *nred = grid.x * grid.y;
     const int chunks = ceil_div(2 * d.nx, GBK);
     if (mode == 0)
-        xgemm_any<0, 0>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 0>(grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else if (mode == 1)
-        xgemm_any<0, 1>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 1>(grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     else
-        xgemm_any<0, 2>(enc, grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
+        xgemm_any<0, 2>(grid, s, U, extab, data, out, red, M, d.nx, d.nk, chunks, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2* w,
-                            const float2* extab, float2* W, hipStream_t s)
+                            const float2* extab, const void* bfrag, float2* W, hipStream_t s)
 {
     const int M = d.C * d.T;
+    if (enc != 0) {   // no K split: W complete in partial 0
+        if (bfrag == nullptr) return hipErrorInvalidValue;
+        xgemm_direct<1, 0>(enc, d, w, bfrag, nullptr, W, nullptr, nullptr, s);
+        return hipGetLastError();
+    }
     const int kchunks = ceil_div(2 * d.nk, GBK);
     const int per = ceil_div(kchunks, p.ksplit_adj);
     dim3 grid(ceil_div(2 * d.nx, GBN), ceil_div(M, GBM), p.ksplit_adj);
     const size_t stride = (size_t)M * 2 * d.nx;   // floats per partial
-    xgemm_any<1, 0>(enc, grid, s, w, extab, nullptr, W, nullptr, M, d.nx, d.nk, per, stride);
+    xgemm_any<1, 0>(grid, s, w, extab, nullptr, W, nullptr, M, d.nx, d.nk, per, stride);
     if (p.ksplit_adj > 1) {
         const size_t count = (size_t)M * d.nx;
         wsum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(W, p.ksplit_adj, count);

@@ -78,13 +78,25 @@ hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void
 // x-stage forward GEMM: s[c][n][k] = sum_ix Ex[k][ix] U[c][n][ix].
 // mode 0: out = data - s and per-block FP64 sums of |out|^2 into red;
 // mode 1: out = -s; mode 2: out = s.
+// enc 0: the LDS-tiled FP32 kernel (extab); enc 1 / 2: the LDS-free kernel
+// on the B-fragment table of this direction and encoding (bfrag; required).
 hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, const float2* U,
-                            const float2* extab, const float2* data, float2* out, double* red,
-                            int* nred, hipStream_t s);
+                            const float2* extab, const void* bfrag, const float2* data, float2* out,
+                            double* red, int* nred, hipStream_t s);
 
-// x-stage adjoint GEMM: W[z][c][n][ix] = partial z of sum_k conj(Ex[k][ix]) w[c][n][k].
+// x-stage adjoint GEMM: W[z][c][n][ix] = partial z of sum_k conj(Ex[k][ix]) w[c][n][k]
+// (one partial, complete, on the LDS-free path).
 hipError_t launch_xgemm_adj(const Dims& d, const YPlan& p, int enc, const float2* w,
-                            const float2* extab, float2* W, hipStream_t s);
+                            const float2* extab, const void* bfrag, float2* W, hipStream_t s);
+
+// B-fragment tables of the LDS-free reduced-precision x-GEMMs: bytes per
+// table (dir 0 forward, 1 adjoint; enc 1 split-BF16, 2 FP16), their build
+// from the phase table (f1/a1: split-BF16 forward/adjoint, f2/a2: FP16), and
+// the number of FP64 partials the forward kernel writes in mode 0.
+size_t bfrag_bytes(const Dims& d, int dir, int enc);
+hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void* a1, void* f2,
+                              void* a2, hipStream_t s);
+int xgemm_direct_blocks(const Dims& d);
 
 // Adjoint y-stage: partial sums over TR chunks of
 // A_p[j] = sum_n mu_p[n][j] conj(Ey[n][iy]) sum_c conj(coil_c[j]) W_c[n][ix]

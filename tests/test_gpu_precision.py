@@ -106,3 +106,61 @@ def test_maps_error_by_precision(setup, oracle_lib):
     assert res[0][0] <= 1e-4
     assert res[1][0] <= 1e-3
     assert res[2][0] <= 5e-2
+
+
+def _shape_cases():
+    rng = np.random.default_rng(83)
+    T = 45
+    # nx odd (no paired A loads in the forward), nk odd (an odd number of
+    # 16-column blocks and a ragged last K block in the adjoint).
+    ragged = I.make_problem(37, 19, T, 51, 9, flip_deg=rng.uniform(5, 70, T),
+                            ky_line=rng.integers(0, 19, T))
+    coils = I.make_problem(24, 20, 30, 48, 8, n_coils=4, flip_deg=rng.uniform(5, 70, 30))
+    mask = (rng.uniform(size=coils.nv) > 0.2).astype(np.uint8)
+    return {"ragged_odd": (ragged, None, None), "coils_mask": (coils, I.coil_maps(24, 20, 4), mask)}
+
+
+@pytest.mark.parametrize("name", ["ragged_odd", "coils_mask"])
+@pytest.mark.parametrize("enc", [1, 2])
+def test_reduced_precision_shapes(oracle_lib, name, enc):
+    """The reduced-precision contractions on partial tiles, coils and a mask,
+    and with an operand that is not 16-byte aligned, against the oracle."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_13244_amd.binding import Context
+    prob, coil, mask = _shape_cases()[name]
+    th = I.iid_maps(prob.nv, seed=14, b1=np.full(prob.nv, 1.05))
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    print(f"\n[{NAME[enc]} {name}] nx={prob.nx} ny={prob.ny} nk={prob.n_read} T={prob.n_tr} "
+          f"C={prob.n_coils}", flush=True)
+    ctx = Context(prob, coil=None if coil is None else dev(coil, torch.complex64),
+                  mask=None if mask is None else dev(mask, torch.uint8))
+    ctx.set_encoding(enc)
+    ora = oracle_lib.epg(prob, th)
+    thd = dev(th, torch.float32)
+    v, wv = I.probe_vectors(prob)
+    jv = ctx.jv(thd, dev(v, torch.float32)).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, dev(wv, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
+    jhw_ref = oracle_lib.jhw(prob, th, ora, wv, coil=coil, mask=mask)
+    e_jhw = _rel(jhw, jhw_ref)
+    # w at an 8-byte offset: element loads instead of 16-byte loads.
+    buf = torch.zeros(wv.size + 1, dtype=torch.complex64, device="cuda")
+    w_off = buf[1:].view(wv.shape)
+    w_off.copy_(dev(wv, torch.complex64))
+    e_off = _rel(ctx.jhw(thd, w_off, reuse=True).cpu().numpy().astype(np.float64), jhw_ref)
+    d = oracle_lib.signal(prob, th, ora, coil=coil, mask=mask)
+    th1 = th.copy()
+    th1[0] += 0.05
+    th1 = th1.astype(np.float32).astype(np.float64)
+    _, r_ref = oracle_lib.residual(prob, th1, d, coil=coil, mask=mask)
+    f, r = ctx.residual(dev(th1, torch.float32), dev(d, torch.complex64))
+    e_r = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(d))
+    f_ref = 0.5 * float(np.linalg.norm(r_ref) ** 2)
+    e_f = abs(f - f_ref) / f_ref
+    ctx.close()
+    print(f"  jv {e_jv:.2e} jhw {e_jhw:.2e} (offset w {e_off:.2e}) residual {e_r:.2e} f {e_f:.2e}",
+          flush=True)
+    assert max(e_jv, e_jhw, e_off, e_r) <= BOUND[enc]
+    assert e_f <= 2 * BOUND[enc]

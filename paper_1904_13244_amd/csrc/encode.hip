@@ -278,13 +278,14 @@ void ystage_fwd_wide_kernel(
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const TT* b = trains + toff[t] + j;
-                // Streaming loads: the trains are read once per product; the
-                // voxel weights and y-phases shared across blocks stay in L2.
-                m0[t] = __builtin_nontemporal_load((const V4*)b);
+                // Plain loads: with the adjoint's, measured faster than
+                // non-temporal ones (each kernel then starts on trains the
+                // other left in the caches).
+                m0[t] = *(const V4*)b;
                 if constexpr (MODE == 1) {
-                    m1[t] = __builtin_nontemporal_load((const V4*)(b + plane));
-                    m2[t] = __builtin_nontemporal_load((const V4*)(b + 2 * plane));
-                    m3[t] = __builtin_nontemporal_load((const V4*)(b + 3 * plane));
+                    m1[t] = *(const V4*)(b + plane);
+                    m2[t] = *(const V4*)(b + 2 * plane);
+                    m3[t] = *(const V4*)(b + 3 * plane);
                 }
             }
             if (mask != nullptr) {   // masked voxels: zero weights (selects, not products)
@@ -607,6 +608,123 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
         for (int p = 0; p < NTRAIN; ++p) {
             dst[(2 * p) * (size_t)nv] = on ? acc[u][p].x : 0.f;
             dst[(2 * p + 1) * (size_t)nv] = on ? acc[u][p].y : 0.f;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Adjoint y-stage, wide layout (FP16 trains, one coil, nx a multiple of 4
+// and at most 256, 8-byte aligned trains). A block covers one image row for
+// one TR chunk; each lane owns 4 adjacent columns (one 8-byte load per train
+// and TR) and the block's NWA waves take every NWA-th TR of the chunk, so a
+// block has NWA times the loads in flight of a one-wave row while the
+// partial sums per chunk stay those of the kernel above. The waves' sums meet
+// in LDS once at the end. Ey[n, iy] is uniform per wave (scalar loads); W
+// rows come through L2.
+// ------------------------------------------------------------------------
+constexpr int NWA = 8;   // waves per block
+
+template <int NB, int R>
+__global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
+    const _Float16* __restrict__ trains, const uint8_t* __restrict__ mask,
+    const float2* __restrict__ eytab, const float2* __restrict__ W, float* __restrict__ apart,
+    int nx, int ny, int nv, int T, int n_per_chunk)
+{
+    // R image rows per block share each TR's W (loaded once per wave and TR).
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    extern __shared__ float red_s[];   // [NWA][8][nx], one row at a time
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int iy0 = blockIdx.x * R;
+    const int chunk = blockIdx.y;
+    const int n0 = chunk * n_per_chunk;
+    const int n1 = min(T, n0 + n_per_chunk);
+    const int x0 = 4 * lane;
+    const bool colok = x0 < nx;
+    const int xc = colok ? x0 : 0;
+    const size_t plane = (size_t)T * nv;
+    int jr[R], iyr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        iyr[r] = min(iy0 + r, ny - 1);   // rows past the end repeat the last; not stored
+        jr[r] = iyr[r] * nx + xc;
+    }
+
+    float acc[R][4][4][2];   // [row][train][column][re, im]
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][p][c][0] = acc[r][p][c][1] = 0.f;
+
+    // TRs n0 + wave + NWA k, NB at a time (loads first; padding TRs read the
+    // chunk's first TR with a zero weight).
+    for (int nb = n0 + wave; nb < n1; nb += NWA * NB) {
+        h4 mu[NB][R][4];
+        float4 w01[NB], w23[NB];
+        float2 ey[NB][R];
+        float keep[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int nr = nb + NWA * b;
+            const int n = nr < n1 ? nr : n0;
+            keep[b] = nr < n1 ? 1.f : 0.f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const _Float16* t0 = trains + (size_t)n * nv + jr[r];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    mu[b][r][p] = *(const h4*)(t0 + p * plane);
+                ey[b][r] = eytab[(size_t)n * ny + iyr[r]];
+            }
+            const float4* wr = reinterpret_cast<const float4*>(W + (size_t)n * nx + xc);
+            w01[b] = wr[0];
+            w23[b] = wr[1];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float2 wc[4] = {make_float2(w01[b].x * keep[b], w01[b].y * keep[b]),
+                                  make_float2(w01[b].z * keep[b], w01[b].w * keep[b]),
+                                  make_float2(w23[b].x * keep[b], w23[b].y * keep[b]),
+                                  make_float2(w23[b].z * keep[b], w23[b].w * keep[b])};
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float2 V = cmulconj(ey[b][r], wc[c]);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const float m = (float)mu[b][r][p][c];
+                        acc[r][p][c][0] = fmaf(m, V.x, acc[r][p][c][0]);
+                        acc[r][p][c][1] = fmaf(m, V.y, acc[r][p][c][1]);
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r > 0) __syncthreads();   // the previous row's sums have been read
+        if (colok) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    *reinterpret_cast<float4*>(&red_s[((size_t)wave * 8 + 2 * p + q) * nx + x0]) =
+                        make_float4(acc[r][p][0][q], acc[r][p][1][q], acc[r][p][2][q], acc[r][p][3][q]);
+        }
+        __syncthreads();
+        const int iy = iy0 + r;
+        if (iy < ny) {
+            float* dst = apart + (size_t)chunk * 8 * nv + (size_t)iy * nx;
+            for (int o = threadIdx.x; o < 8 * nx; o += NWA * 64) {
+                const int v = o / nx, x = o % nx;
+                float sum = red_s[(size_t)v * nx + x];
+#pragma unroll
+                for (int w = 1; w < NWA; ++w) sum += red_s[((size_t)w * 8 + v) * nx + x];
+                const bool on = mask == nullptr || mask[(size_t)iy * nx + x] != 0;
+                dst[(size_t)v * nv + x] = on ? sum : 0.f;
+            }
         }
     }
 }
@@ -1311,6 +1429,17 @@ hipError_t adj_launch(const Dims& d, const YPlan& p, const TT* trains, const flo
     // FP16 pairs (nx even, one coil): 512 voxels per block, twice the TRs
     // per batch, so the bytes in flight match the FP32 kernel.
     if constexpr (std::is_same<TT, _Float16>::value && CC == 1) {
+        if (NTRAIN == 4 && d.nx % 4 == 0 && d.nx <= 256 && ((uintptr_t)trains & 7) == 0 &&
+            ((uintptr_t)W & 15) == 0) {
+            // 2 rows per block, 1 TR per wave in flight (measured at 224 x 224:
+            // rows x TRs 1 x 1: 108 us, 2 x 1: 96, 2 x 2: 110, 3 x 1: 128 with
+            // 8 chunks; the pair kernel below 107).
+            dim3 grid(ceil_div(d.ny, 2), p.adj_chunks);
+            const size_t lds = (size_t)NWA * 8 * d.nx * sizeof(float);
+            ystage_adj_wide_kernel<1, 2><<<grid, NWA * 64, lds, s>>>(
+                trains, mask, eytab, W, apart, d.nx, d.ny, d.nv, d.T, p.adj_per_chunk);
+            return hipGetLastError();
+        }
         if (d.nx % 2 == 0) {
             dim3 grid(ceil_div(d.nv, 512), p.adj_chunks);
             const int rows = std::min(d.ny, 512 / d.nx + 2);
@@ -1386,7 +1515,11 @@ YPlan make_yplan(const Dims& d)
     // blocks in flight to stream the trains near the HBM limit, with partial
     // sums of 8 chunks x 8 floats per voxel.
     p.r_adj = 1;
-    p.adj_chunks = std::min(8, d.T);
+    // One coil: 9 chunks (measured at 224 x 224, 1120 TRs, per chunk count
+    // 4 / 5 / 8 / 9 / 12: FP16 wide kernel 92 / 104 / 96 / 92 / 98 us, FP32
+    // 183 / 162 / 171 / 162 / 169 us). Coils: 8 (the 256 x 256, 8-coil GN step
+    // took 1.6 ms longer with 9).
+    p.adj_chunks = std::min(d.C == 1 ? 9 : 8, d.T);
     // LDS staging of the y-phases: chunk TRs x rows of a block (<= 64 KB;
     // rows of the 512-voxel blocks of the FP16 pair kernel).
     const int rows = std::min(d.ny, 512 / d.nx + 2);

@@ -65,8 +65,8 @@ def algorithmic(kind, prob, tb=4):
 
 
 def surrogate_work(prob, width=256, depth=4, bytes_per_value=2):
-    """Per launch of the fused inference with all four trains: (flop, bytes
-    written). Multiply-adds of the first layer, the hidden layers and the
+    """Per linearisation through the network with all four trains (hidden-layer
+    kernel + output-layer kernel): (flop, bytes written). Multiply-adds of the first layer, the hidden layers and the
     4 n_tr imaginary outputs; the trains written once (FP16 by default)."""
     macs = 3 * width + (depth - 1) * width * width + 4 * prob.n_tr * width
     return 2 * macs * prob.nv, 4 * bytes_per_value * prob.n_tr * prob.nv
@@ -268,7 +268,7 @@ def main():
                          "heldout_rel_err": dict(zip(["m", "dm_dlnT1", "dm_dlnT2", "dm_dB1"],
                                                      trep.val_rel_err))},
             "inference_roofline": None if t is None else {
-                "kernel": "surrogate (fused inference, all four trains, FP16 out)",
+                "kernel": "surrogate (hidden-layer + output-layer kernels, all four trains, FP16 out)",
                 "bound": "hbm", "achieved": wbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": wbytes / t / 1e9 / HBM_PEAK_GBS,
                 "mfma_tflops": flop / t / 1e12, "mfma_frac": flop / t / 1e12 / BF16_MFMA_PEAK_TFLOPS,

@@ -22,6 +22,7 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
     size_t trains, trial_m, upart, W, apart, r, y, vec, red, scal, seq, eytab, extab;
     size_t bf[2][2];   // B-fragment tables [direction][split-BF16, FP16]
+    size_t hbuf;       // surrogate hidden activations, BF16 [nv][256]
     size_t cx, csv, cp, cth, fb, total;
     int n_red;
     YPlan yp;
@@ -161,6 +162,7 @@ Layout make_layout(const Dims& d)
     L.cp = take(nv * sizeof(float2));
     L.cth = take(5 * nv * sizeof(float));
     L.fb = take((64 + nv) * sizeof(int));
+    L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.total = o;
     return L;
 }
@@ -221,7 +223,8 @@ mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, bool 
         return MRSTAT_OK;
     }
     const int skind = tangents ? MRSTAT_K_SURR : MRSTAT_K_SURR_VALUE;
-    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, ctx->f16, s)));
+    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, ctx->f16,
+                                                    ctx->at<uint16_t>(ctx->L.hbuf), s)));
     HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_box_compact(d, theta, mlp_box_lo(ctx->surr),
                                                        mlp_box_hi(ctx->surr), ctx->mask, ctx->fb_idx(),
                                                        ctx->fb_count(slot), s)));

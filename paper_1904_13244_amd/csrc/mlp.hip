@@ -298,9 +298,11 @@ typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 // PF: 0 = weights loaded per tile, activations (A fragments) in registers;
 // 1 = two tiles of weights in flight, activations in registers; 2 / 3 = two
 // / three tiles of weights in flight, activations read from LDS per tile
-// (frees the registers that hold them, so more weight loads are in flight).
+// (frees the registers that hold them, so more weight loads are in flight);
+// 4 = hidden layers only, the last activations stored to a.hout (BF16
+// [voxel][WIDTH]) for the separate output-layer kernel, 4 waves per SIMD.
 template <int WIDTH, int NV, int PF, bool F16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF >= 2 ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 4 : (PF >= 2 ? 2 : 1))))
 void mlp_infer_kernel(InferArgs a)
 {
     constexpr int HP = WIDTH + 8, KS = WIDTH / 32, MT = WIDTH / 64, VT = NV / 16;
@@ -372,6 +374,16 @@ void mlp_infer_kernel(InferArgs a)
         }
         __syncthreads();
         cur = nxt;
+    }
+
+    if constexpr (PF == 4) {   // export the activations, one 16-byte piece per thread
+        for (int e = tid; e < NV * (WIDTH / 8); e += 256) {
+            const int v = e / (WIDTH / 8), q = e % (WIDTH / 8);
+            if (j0 + v < a.n)
+                *reinterpret_cast<uint4*>(a.hout + (size_t)(j0 + v) * WIDTH + 8 * q) =
+                    *reinterpret_cast<const uint4*>(&Hs[cur][v][8 * q]);
+        }
+        return;
     }
 
     // Output layer: A = activations^T (voxel rows), in registers (PF < 3)
@@ -472,6 +484,117 @@ void mlp_infer_kernel(InferArgs a)
     }
 }
 
+// ------------------------------------------------------------------------
+// Output layer as its own kernel (width 256): out = (Wout H + b) * scale for
+// a slice of 128 MW output rows per workgroup. Each of the 8 waves keeps its
+// 16 MW output rows' weights in registers as MFMA B fragments (32 MW VGPRs)
+// for the whole launch; the workgroup streams 64-voxel tiles of the
+// activations through double-buffered LDS (the next tile's loads are in
+// flight while the current one is multiplied) and writes 4 consecutive
+// voxels per store as in the fused kernel. A tile of activations is read
+// once per output slice (9 slices for 4 trains of 1120 TRs) instead of each
+// voxel tile re-reading all output weights.
+// ------------------------------------------------------------------------
+template <bool F16, int MW>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
+{
+    constexpr int WIDTH = 256, KB = WIDTH / 32, NVT = 64;
+    // Activation tiles in MFMA A-fragment order: [buffer][16-voxel tile][K
+    // block][lane], 16 bytes per lane, so every fragment read is one
+    // contiguous, conflict-free 1 KB wave access.
+    __shared__ uint4 Hf[2][NVT / 16][KB][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
+    // MW 16-row output tiles per wave: a slice of 128 MW rows per workgroup.
+    const int o0 = blockIdx.x * 128 * MW + wave * 16 * MW;
+    uint4 wf[MW][KB];
+    float bias[MW], scl[MW];
+    int orow[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+        const int o = o0 + 16 * m + lr;
+        orow[m] = o;
+        const int oc = min(o, a.m_out - 1);   // rows past the end: clamped, never stored
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+            wf[m][kb] = *reinterpret_cast<const uint4*>(a.Wout + (size_t)oc * WIDTH + 32 * kb + lk);
+        bias[m] = a.bout[oc];
+        scl[m] = a.head_scale[oc / a.T];
+    }
+    const int n_tiles = (a.n + NVT - 1) / NVT;
+    const bool vec_ok = (a.ld_out % 4) == 0;
+    // Tile loads: 32 fragments of 64 x 16 bytes; wave w loads fragments
+    // w, w + 8, w + 16, w + 24, each lane the piece it will be read from.
+    uint4 hr[4];
+    auto gload = [&](int t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = wave + 8 * i, vt = f / KB, kb = f % KB;
+            const int j = min(t * NVT + vt * 16 + lr, a.n - 1);
+            hr[i] = *reinterpret_cast<const uint4*>(H + (size_t)j * WIDTH + 32 * kb + lk);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = wave + 8 * i;
+            Hf[buf][f / KB][f % KB][lane] = hr[i];
+        }
+    };
+    int t = blockIdx.y;
+    if (t < n_tiles) {
+        gload(t);
+        sstore(0);
+    }
+    __syncthreads();
+    using OT = typename std::conditional<F16, _Float16, float>::type;
+    for (int buf = 0; t < n_tiles; t += gridDim.y, buf ^= 1) {
+        const bool more = t + (int)gridDim.y < n_tiles;
+        if (more) gload(t + gridDim.y);
+        // One 16-voxel tile at a time (accumulators for MW output tiles).
+#pragma unroll
+        for (int vt = 0; vt < 4; ++vt) {
+            f4 acc[MW];
+#pragma unroll
+            for (int m = 0; m < MW; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const uint4 af = Hf[buf][vt][kb][lane];
+#pragma unroll
+                for (int m = 0; m < MW; ++m)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, af), __builtin_bit_cast(bf16x8, wf[m][kb]), acc[m], 0, 0, 0);
+            }
+            // D: lane holds voxels 4 (lane / 16) + i of the tile, output row lr.
+            const int jv = t * NVT + vt * 16 + 4 * (lane >> 4);
+#pragma unroll
+            for (int m = 0; m < MW; ++m) {
+                const int o = orow[m];
+                if (o < a.m_out) {
+                    const int p = o / a.T, nt = o - p * a.T;
+                    OT* dst = static_cast<OT*>(a.out) + (size_t)p * a.plane + (size_t)nt * a.ld_out;
+                    const float y0 = (acc[m][0] + bias[m]) * scl[m], y1 = (acc[m][1] + bias[m]) * scl[m];
+                    const float y2 = (acc[m][2] + bias[m]) * scl[m], y3 = (acc[m][3] + bias[m]) * scl[m];
+                    if (vec_ok && jv + 3 < a.n) {
+                        if constexpr (F16)
+                            *reinterpret_cast<h4v*>(dst + jv) = h4v{(_Float16)y0, (_Float16)y1, (_Float16)y2, (_Float16)y3};
+                        else
+                            *reinterpret_cast<f4*>(dst + jv) = f4{y0, y1, y2, y3};
+                    } else {
+                        if (jv < a.n) dst[jv] = (OT)y0;
+                        if (jv + 1 < a.n) dst[jv + 1] = (OT)y1;
+                        if (jv + 2 < a.n) dst[jv + 2] = (OT)y2;
+                        if (jv + 3 < a.n) dst[jv + 3] = (OT)y3;
+                    }
+                }
+            }
+        }
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gemm_bf16(bool ta, bool tb, int epi, const GemmArgs& g, hipStream_t s)
@@ -530,7 +653,7 @@ bool infer_fused_supported(int width, int depth) { return (width == 64 || width 
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s)
 {
     if (tile == 0) tile = width == 256 ? -64 : 64;
-    const int grid = ceil_div(a.n, tile < 0 ? -tile : tile);
+    const int grid = ceil_div(a.n, tile > 1000 ? tile - 1000 : (tile < 0 ? -tile : tile));
 #define INFER(W_, NV_, T_, PF_)                                              \
     if (width == W_ && tile == T_) {                                         \
         if (a.f16) mlp_infer_kernel<W_, NV_, PF_, true><<<grid, 256, 0, s>>>(a);   \
@@ -543,6 +666,9 @@ hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t
     INFER(128, 32, 32, 1)
     INFER(256, 64, 64, 0)
     INFER(256, 32, 32, 1)
+    // Hidden layers only (a.hout): tile 1000 + voxels.
+    INFER(256, 64, 1064, 4)
+    INFER(256, 32, 1032, 4)
     // Negative tile: the same voxel tile with activations read from LDS and
     // three weight tiles in flight.
     INFER(64, 64, -64, 3)
@@ -551,6 +677,23 @@ hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t
     INFER(256, 32, -32, 3)
 #undef INFER
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_out(const InferArgs& a, const uint16_t* H, hipStream_t s)
+{
+    // Voxel-tile groups: one workgroup per CU over all output slices, a
+    // single round.
+    // 4 output tiles per wave (512-row slices): 203 us at 224 x 224, 1120 TRs,
+    // FP16 out, against 229 us with 2 (256-row slices, twice the activation
+    // reads).
+    constexpr int MW = 4;
+    const int slices = ceil_div(a.m_out, 128 * MW);
+    const int tiles = ceil_div(a.n, 64);
+    const int groups = std::max(1, std::min(tiles, 256 / slices));
+    dim3 grid(slices, groups);
+    if (a.f16) mlp_out_kernel<true, MW><<<grid, 512, 0, s>>>(a, H);
+    else mlp_out_kernel<false, MW><<<grid, 512, 0, s>>>(a, H);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s)

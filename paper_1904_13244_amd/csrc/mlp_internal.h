@@ -57,11 +57,17 @@ struct InferArgs {
     void* out;                     // out[p * plane + n * ld_out + voxel], float or _Float16
     int64_t ld_out, plane;
     bool f16;                      // trains stored as FP16
+    uint16_t* hout;                // non-null: store the last hidden activations here
+                                   // (BF16 [voxel][width]) and skip the output layer
 };
 bool infer_fused_supported(int width, int depth);
 // tile: voxels per workgroup, 32 or 64 (activations in registers), -32 or
 // -64 (activations read from LDS); 0 = default.
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s);
+// Output layer alone (width 256) from activations H (BF16 [voxel][256], as
+// stored by launch_mlp_infer with a.hout): same outputs and layout as the
+// fused kernel.
+hipError_t launch_mlp_out(const InferArgs& a, const uint16_t* H, hipStream_t s);
 
 hipError_t launch_gemm_bf16(bool ta, bool tb, int epi, const GemmArgs& g, hipStream_t s);
 int gemm_tiles(int M, int N);
@@ -80,8 +86,10 @@ hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 // theta rows (ln T1, ln T2, B1) have leading dimension ld_theta, into
 // out[p][n_tr][ld_out] (float, or _Float16 when f16) for p < 4 (all_trains)
 // or p = 0 only.
+// hbuf (optional, n x 256 BF16): for width 256, the hidden layers and the
+// output layer run as two kernels through it.
 hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n, void* out,
-                            int64_t ld_out, bool all_trains, bool f16, hipStream_t s);
+                            int64_t ld_out, bool all_trains, bool f16, uint16_t* hbuf, hipStream_t s);
 const float* mlp_box_lo(mrstat_mlp net);
 const float* mlp_box_hi(mrstat_mlp net);
 int mlp_n_tr(mrstat_mlp net);

@@ -138,7 +138,7 @@ Layout make_layout(const Dims& d)
     L.yp = make_yplan(d);
     const int M = d.C * d.T;
     const int gemm_blocks = std::max(ceil_div(2 * d.nk, 64) * ceil_div(M, 64), xgemm_direct_blocks(d));
-    L.n_red = std::max(3 * RED_BLOCKS, gemm_blocks);
+    L.n_red = std::max({3 * RED_BLOCKS, gemm_blocks, cg_partials(d)});
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     const size_t nv = d.nv, T = d.T;
@@ -253,9 +253,11 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
+    int nby = 1;
     HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
                    launch_ystage_fwd(d, p, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask,
-                                     ctx->deytab(), ctx->upart(), s)));
+                                     ctx->deytab(), ctx->upart(), &nby, s)));
+    if (nby > 1) HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_usum(d, ctx->upart(), nby, s)));
     int nred = 0;
     HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(d, p, ctx->enc, mode_x, ctx->upart(),
                                                    ctx->dextab(), ctx->bfrag(0), (const float2*)data, (float2*)out,
@@ -265,8 +267,10 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
     return MRSTAT_OK;
 }
 
+// With dir non-null the finish kernel also leaves the CG curvature partials
+// of dir . g in ctx->red().
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, int param_mask,
-                      hipStream_t s)
+                      hipStream_t s, const float* dir = nullptr)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
@@ -274,7 +278,8 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
                                                    ctx->bfrag(1), ctx->W(), s)));
     HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 4, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g, s)));
+    HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
+                                                      dir, dir ? ctx->red() : nullptr, s)));
     return MRSTAT_OK;
 }
 
@@ -557,7 +562,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     for (int it = 0; it < o->n_cg; ++it) {
         st = forward(ctx, 1, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
         if (st != MRSTAT_OK) return st;
-        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s);
+        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s, dir);
         if (st != MRSTAT_OK) return st;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), it, s)));
     }

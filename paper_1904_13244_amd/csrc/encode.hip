@@ -874,29 +874,63 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 
 // g from A: g_q = -Im(conj(rho) A_{q+1}) for q = lnT1, lnT2, B1;
 // g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho).
-__global__ void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
-                                  const float* __restrict__ theta,
-                                  const uint8_t* __restrict__ mask, int param_mask,
-                                  float* __restrict__ g, int nv)
+template <bool CURV>
+__global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
+                                                         const float* __restrict__ theta,
+                                                         const uint8_t* __restrict__ mask, int param_mask,
+                                                         float* __restrict__ g, int nv,
+                                                         const float* __restrict__ dir,
+                                                         double* __restrict__ part)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nv) return;
-    float A[8];
+    double cd = 0.0, dd = 0.0;
+    if (j < nv) {
+        float A[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) A[q] = 0.f;
-    for (int ch = 0; ch < n_chunk; ++ch)
+        for (int q = 0; q < 8; ++q) A[q] = 0.f;
+        for (int ch = 0; ch < n_chunk; ++ch)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
-    const bool on = mask == nullptr || mask[j] != 0;
-    const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
-    // Rows of parameters outside param_mask are zero.
+            for (int q = 0; q < 8; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
+        const bool on = mask == nullptr || mask[j] != 0;
+        const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
+        // Rows of parameters outside param_mask are zero.
+        float gq[5];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const float ar = A[2 * (q + 1)], ai = A[2 * (q + 1) + 1];
-        g[(size_t)q * nv + j] = (on && ((param_mask >> q) & 1)) ? -(rr * ai - ri * ar) : 0.f;
+        for (int q = 0; q < 3; ++q) {
+            const float ar = A[2 * (q + 1)], ai = A[2 * (q + 1) + 1];
+            gq[q] = (on && ((param_mask >> q) & 1)) ? -(rr * ai - ri * ar) : 0.f;
+        }
+        gq[3] = (on && ((param_mask >> 3) & 1)) ? -A[1] : 0.f;
+        gq[4] = (on && ((param_mask >> 4) & 1)) ? A[0] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            g[(size_t)q * nv + j] = gq[q];
+            if constexpr (CURV) {
+                const double dv = dir[(size_t)q * nv + j];
+                cd += dv * (double)gq[q];
+                dd += dv * dv;
+            }
+        }
     }
-    g[3 * (size_t)nv + j] = (on && ((param_mask >> 3) & 1)) ? -A[1] : 0.f;
-    g[4 * (size_t)nv + j] = (on && ((param_mask >> 4) & 1)) ? A[0] : 0.f;
+    if constexpr (CURV) {
+        // CG curvature partials of this block's voxels, dir . g and dir . dir
+        // in FP64, one pair per block (all threads reach the barrier).
+        __shared__ double sh[2][4];
+        for (int off = 32; off > 0; off >>= 1) {
+            cd += __shfl_xor(cd, off);
+            dd += __shfl_xor(dd, off);
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) {
+            sh[0][wave] = cd;
+            sh[1][wave] = dd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+            part[gridDim.x + blockIdx.x] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+        }
+    }
 }
 
 // CGLS adjoint of the rho-linear map: (M^H w)_j = sum_n conj(m_j[n]) V = -i A_0.
@@ -1567,14 +1601,17 @@ hipError_t adj_typed(const Dims& d, const YPlan& p, const TT* trains, int ntr_tr
 
 hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void* trains, bool f16,
                              const float* theta, const float* v, const float2* coil,
-                             const uint8_t* mask, const float2* eytab, float2* upart,
+                             const uint8_t* mask, const float2* eytab, float2* upart, int* nby,
                              hipStream_t s)
 {
-    int nby = 1;
-    const hipError_t e =
-        f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, &nby, s)
-            : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, &nby, s);
-    if (e != hipSuccess || nby == 1) return e;
+    *nby = 1;
+    return f16 ? fwd_typed(d, p, mode, static_cast<const _Float16*>(trains), theta, v, coil, mask, eytab, upart, nby, s)
+               : fwd_typed(d, p, mode, static_cast<const float*>(trains), theta, v, coil, mask, eytab, upart, nby, s);
+}
+
+hipError_t launch_usum(const Dims& d, float2* upart, int nby, hipStream_t s)
+{
+    if (nby <= 1) return hipSuccess;
     const size_t count = (size_t)d.C * d.T * d.nx;
     usum_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(upart, nby, count);
     return hipGetLastError();
@@ -1684,10 +1721,15 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 }
 
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
-                             const uint8_t* mask, int param_mask, float* g, hipStream_t s)
+                             const uint8_t* mask, int param_mask, float* g, const float* dir,
+                             double* part, hipStream_t s)
 {
-    jhw_finish_kernel<<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask,
-                                                         g, d.nv);
+    if (dir != nullptr)
+        jhw_finish_kernel<true><<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask,
+                                                                   param_mask, g, d.nv, dir, part);
+    else
+        jhw_finish_kernel<false><<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask,
+                                                                    param_mask, g, d.nv, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -72,8 +72,11 @@ hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo
 // partials when nby > 1 and is summed into its first block.
 hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void* trains, bool f16,
                              const float* theta, const float* v, const float2* coil,
-                             const uint8_t* mask, const float2* eytab, float2* upart,
+                             const uint8_t* mask, const float2* eytab, float2* upart, int* nby,
                              hipStream_t s);
+// Sums the nby row-block partials of U written by the forward y-stage into
+// partial 0 (nothing to do for nby = 1).
+hipError_t launch_usum(const Dims& d, float2* upart, int nby, hipStream_t s);
 
 // x-stage forward GEMM: s[c][n][k] = sum_ix Ex[k][ix] U[c][n][ix].
 // mode 0: out = data - s and per-block FP64 sums of |out|^2 into red;
@@ -107,8 +110,11 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 
 // g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order); rows of
 // parameters outside param_mask (and masked voxels) are zero.
+// With dir non-null, also the CG curvature partials dir . g and dir . dir
+// (FP64, ceil(nv / 256) pairs: part[b] and part[nblocks + b]).
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
-                             const uint8_t* mask, int param_mask, float* g, hipStream_t s);
+                             const uint8_t* mask, int param_mask, float* g, const float* dir,
+                             double* part, hipStream_t s);
 
 // CGLS helper: A^H w = -i A_0 from the one-train partials.
 hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
@@ -133,10 +139,12 @@ enum : int {
 
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
                           double* scal, double* partials, hipStream_t s);
-// One CG iteration after q = Re(J^H J) dir (iter = iteration index from 0;
-// partials hold at least 3 RED_BLOCKS doubles).
+// One CG iteration after q = Re(J^H J) dir, whose curvature partials the
+// finish kernel left in partials ([2][nv / 256 blocks]); iter = iteration
+// index from 0; partials hold at least cg_partials(d) doubles.
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s);
+int cg_partials(const Dims& d);
 hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float* step, float t,
                                   const float* lo, const float* hi, int param_mask,
                                   const uint8_t* mask, float* trial, hipStream_t s);

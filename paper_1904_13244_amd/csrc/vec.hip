@@ -115,26 +115,6 @@ __global__ __launch_bounds__(RB) void cg_init_finish(const double* __restrict__ 
     }
 }
 
-// Partial sums of dir.q and dir.dir.
-__global__ __launch_bounds__(RB) void cg_curv_kernel(const float* __restrict__ dir,
-                                                     const float* __restrict__ q, size_t n,
-                                                     double* __restrict__ part)
-{
-    __shared__ double sh[RB / 64];
-    double a = 0.0, b = 0.0;
-    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
-        const double d = dir[i];
-        a += d * (double)q[i];
-        b += d * d;
-    }
-    a = block_sum(a, sh);
-    b = block_sum(b, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = a;
-        part[gridDim.x + blockIdx.x] = b;
-    }
-}
-
 // Every block reduces the same partials in the same fixed order (the result
 // is identical in all blocks); thread 0's sums are broadcast through LDS.
 __device__ __forceinline__ void reduce_pair(const double* __restrict__ part, int n, double* sh,
@@ -394,15 +374,17 @@ hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res
     return hipGetLastError();
 }
 
+int cg_partials(const Dims& d) { return 2 * ((d.nv + 255) / 256) + RED_BLOCKS; }
+
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s)
 {
-    // partials: curvature pairs [2][RED_BLOCKS], then res.res [RED_BLOCKS].
+    // partials: curvature pairs [2][nb] from the finish kernel, then res.res
+    // [RED_BLOCKS].
     const size_t n = (size_t)5 * d.nv;
-    double* rrp = partials + 2 * RED_BLOCKS;
-    cg_curv_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, n, partials);
-    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, RED_BLOCKS, scal,
-                                             iter & 1, rrp);
+    const int nb = (d.nv + 255) / 256;
+    double* rrp = partials + 2 * nb;
+    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp);
     cg_dir_kernel<<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1);
     return hipGetLastError();
 }

@@ -1210,23 +1210,23 @@ __global__ void build_bfrag_kernel(const float2* __restrict__ extab, uint4* __re
                                     lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
 }
 
-template <int DIR, int MODE, int ENC, int KS, int RW>
+template <int DIR, int MODE, int ENC, int KS, int RW, int CW>
 __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
     const float2* __restrict__ Ain, const uint4* __restrict__ bfrag,
     const float2* __restrict__ data, float2* __restrict__ out, double* __restrict__ red, int M,
     int nx, int nk)
 {
-    // A wave's tile is 16 RW rows x 32 columns. KS waves per block share one
+    // A wave's tile is 16 RW rows x 16 CW columns. KS waves per block share one
     // tile and take every KS-th K block; their sums meet in LDS.
     using Ops = MxOps<ENC>;
     constexpr int NT = Ops::TERMS;
-    __shared__ f4 part[KS > 1 ? KS - 1 : 1][RW][2][64];
+    __shared__ f4 part[KS > 1 ? KS - 1 : 1][RW][CW][64];
     const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
     const int Kr = DIR == 0 ? 2 * nx : 2 * nk;
     const int Nr = DIR == 0 ? 2 * nk : 2 * nx;
     const int Ka = Kr / 2;
     const int KB = (Kr + 31) / 32, NCB = (Nr + 15) / 16;
-    const int cb0 = 2 * blockIdx.x;
+    const int cb0 = CW * blockIdx.x;
     const int m0 = 16 * RW * blockIdx.y;
     const int kq = 4 * (lane >> 4);
     const bool vec = (Ka & 1) == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0;   // 16-byte loads
@@ -1258,20 +1258,22 @@ __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
             }
         }
     };
-    auto load_b = [&](int kb, uint4 (&b)[2][NT]) {
+    auto load_b = [&](int kb, uint4 (&b)[CW][NT]) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < CW; ++c) {
             const int cb = cb0 + c < NCB ? cb0 + c : NCB - 1;   // clamped; its output is not stored
 #pragma unroll
             for (int t = 0; t < NT; ++t) b[c][t] = bfrag[(((size_t)kb * NCB + cb) * NT + t) * 64 + lane];
         }
     };
 
-    f4 acc[RW][2];
+    f4 acc[RW][CW];
 #pragma unroll
-    for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int c = 0; c < CW; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
     float2 a_cur[RW][4], a_nxt[RW][4];
-    uint4 b_cur[2][NT], b_nxt[2][NT];
+    uint4 b_cur[CW][NT], b_nxt[CW][NT];
     if (kw < KB) {
         load_a(kw, a_cur);
         load_b(kw, b_cur);
@@ -1296,7 +1298,7 @@ __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
                 al = make_uint4(ll[0] | (ll[1] << 16), ll[2] | (ll[3] << 16), ll[4] | (ll[5] << 16),
                                 ll[6] | (ll[7] << 16));
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
+            for (int c = 0; c < CW; ++c) {
                 if constexpr (NT > 1) {
                     acc[r][c] = Ops::mma(al, b_cur[c][0], acc[r][c]);   // lo * hi
                     acc[r][c] = Ops::mma(ah, b_cur[c][1], acc[r][c]);   // hi * lo
@@ -1310,7 +1312,7 @@ __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
 #pragma unroll
                 for (int e = 0; e < 4; ++e) a_cur[r][e] = a_nxt[r][e];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < CW; ++c)
 #pragma unroll
                 for (int t = 0; t < NT; ++t) b_cur[c][t] = b_nxt[c][t];
         }
@@ -1318,20 +1320,18 @@ __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
     if constexpr (KS > 1) {
         if (kw > 0) {
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                part[kw - 1][r][0][lane] = acc[r][0];
-                part[kw - 1][r][1][lane] = acc[r][1];
-            }
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) part[kw - 1][r][c][lane] = acc[r][c];
         }
         __syncthreads();
         if (kw > 0) return;
 #pragma unroll
         for (int w = 0; w < KS - 1; ++w)
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                acc[r][0] += part[w][r][0][lane];
-                acc[r][1] += part[w][r][1][lane];
-            }
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) acc[r][c] += part[w][r][c][lane];
     }
 
     double sq = 0.0;
@@ -1340,7 +1340,7 @@ __global__ __launch_bounds__(64 * KS) void xgemm_direct_kernel(
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < CW; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = m0 + 16 * r + 4 * (lane >> 4) + i;
@@ -1623,7 +1623,7 @@ size_t bfrag_bytes(const Dims& d, int dir, int enc)
     return (size_t)ceil_div(Kr, 32) * ceil_div(Nr, 16) * (enc == 1 ? 2 : 1) * 64 * sizeof(uint4);
 }
 
-int xgemm_direct_blocks(const Dims& d) { return ceil_div(2 * d.nk, 32) * ceil_div(d.C * d.T, 16); }   // >= any RW
+int xgemm_direct_blocks(const Dims& d) { return ceil_div(2 * d.nk, 16) * ceil_div(d.C * d.T, 16); }   // >= any tile
 
 hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void* a1, void* f2,
                               void* a2, hipStream_t s)
@@ -1645,21 +1645,21 @@ hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void
 // 16 / 23 us, 16 x 32 with 4 waves 16 / 15, 32 x 32 with 2 waves 15.4 / 17.4,
 // with 4 waves 16.4 / 13.1, 64 x 32 with 4 waves 18.9 / 14.7; the LDS-tiled
 // kernel 19 / 25 (including its split-K sum).
-constexpr int XRW = 2;
+constexpr int XRW = 2, XCW = 2;   // 16 x 32 column tiles per wave: 21 / 19 us, 64: 17 / 13
 
 template <int DIR, int MODE>
 void xgemm_direct(int enc, const Dims& d, const float2* A, const void* bfrag, const float2* data,
                   float2* out, double* red, int* nred, hipStream_t s)
 {
     const int Nr = DIR == 0 ? 2 * d.nk : 2 * d.nx;
-    dim3 grid(ceil_div(Nr, 32), ceil_div(d.C * d.T, 16 * XRW));
+    dim3 grid(ceil_div(Nr, 16 * XCW), ceil_div(d.C * d.T, 16 * XRW));
     if (nred) *nred = grid.x * grid.y;
     constexpr int KS = DIR == 0 ? 2 : 4;
     if (enc == 1)
-        xgemm_direct_kernel<DIR, MODE, 1, KS, XRW><<<grid, 64 * KS, 0, s>>>(
+        xgemm_direct_kernel<DIR, MODE, 1, KS, XRW, XCW><<<grid, 64 * KS, 0, s>>>(
             A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
     else
-        xgemm_direct_kernel<DIR, MODE, 2, KS, XRW><<<grid, 64 * KS, 0, s>>>(
+        xgemm_direct_kernel<DIR, MODE, 2, KS, XRW, XCW><<<grid, 64 * KS, 0, s>>>(
             A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
 }
 

@@ -566,19 +566,13 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         if (st != MRSTAT_OK) return st;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), it, s)));
     }
+    // The report's scalars are read with the first line-search trial's: one
+    // host synchronisation per trial. The Armijo test and the update of theta
+    // run on the device.
     double hs[16];
     int32_t nfb = 0;
     HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
     if (ctx->surr) HIP_TRY(hipMemcpyAsync(&nfb, ctx->fb_count(0), sizeof(nfb), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    rep->n_fallback = nfb;
-    const double f0 = 0.5 * hs[SC_F0];
-    rep->f0 = f0;
-    rep->f1 = f0;
-    rep->gnorm = std::sqrt(hs[SC_G2]);
-    rep->cg_iters = (int32_t)hs[SC_ITERS];
-    if (!std::isfinite(f0) || !std::isfinite(rep->gnorm))
-        return fail(ctx, MRSTAT_ERR_NONFINITE, "objective or gradient is not finite");
 
     // Backtracking line search on the projected step.
     float t = 1.f;
@@ -590,17 +584,26 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
         if (st != MRSTAT_OK) return st;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_pred_dot(d, g, trial, d_theta, ctx->red(), sc + SC_PRED, s)));
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_accept(d, sc, o->armijo_c1, trial, d_theta, s)));
         double h3[16];
         HIP_TRY(hipMemcpyAsync(h3, sc, sizeof(h3), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const double ft = 0.5 * h3[SC_FT], pred = h3[SC_PRED];
+        if (k == 0) {
+            rep->n_fallback = nfb;
+            const double f0 = 0.5 * hs[SC_F0];
+            rep->f0 = f0;
+            rep->f1 = f0;
+            rep->gnorm = std::sqrt(hs[SC_G2]);
+            rep->cg_iters = (int32_t)hs[SC_ITERS];
+            // A non-finite f0 or gradient fails every Armijo test, so theta
+            // is unchanged here.
+            if (!std::isfinite(f0) || !std::isfinite(rep->gnorm))
+                return fail(ctx, MRSTAT_ERR_NONFINITE, "objective or gradient is not finite");
+        }
         rep->ls_trials++;
-        if (std::isfinite(ft) && ft <= f0 + o->armijo_c1 * pred) {
-            HIP_TRY(hipMemcpyAsync(d_theta, trial, (size_t)5 * d.nv * sizeof(float),
-                                   hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
+        if (h3[SC_ACC] != 0.0) {
             rep->accepted = 1;
-            rep->f1 = ft;
+            rep->f1 = 0.5 * h3[SC_FT];
             rep->t = t;
             rep->step_norm = std::sqrt(h3[SC_SN]);
             ctx->lin_valid = false;

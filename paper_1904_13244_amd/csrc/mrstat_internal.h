@@ -133,7 +133,7 @@ hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* part
 // Device-resident scalar block (doubles); slot numbers shared with vec.hip.
 constexpr int SCAL_DOUBLES = 64;
 enum : int {
-    SC_RR = 0, SC_ITERS = 6, SC_F0 = 8, SC_G2 = 9, SC_PRED = 10, SC_SN = 11, SC_FT = 14,
+    SC_RR = 0, SC_ITERS = 6, SC_F0 = 8, SC_G2 = 9, SC_PRED = 10, SC_SN = 11, SC_ACC = 13, SC_FT = 14,
     SC_STAGE = 30, SC_CDONE = 25
 };
 
@@ -150,6 +150,11 @@ hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float
                                   const uint8_t* mask, float* trial, hipStream_t s);
 hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, const float* theta,
                            double* partials, double* out, hipStream_t s);
+// Armijo test on the device, f(trial) <= f0 + c1 pred with f(trial) finite
+// (f = SC_FT / 2, f0 = SC_F0 / 2, pred = SC_PRED); when it holds theta = trial. The outcome
+// goes to SC_ACC (1 or 0).
+hipError_t launch_ls_accept(const Dims& d, double* scal, double c1, const float* trial, float* theta,
+                            hipStream_t s);
 
 // CGLS (complex unknown per voxel).
 hipError_t launch_set_rho(const Dims& d, const float* theta_in, const float2* p, float* theta_out,

@@ -250,6 +250,20 @@ __global__ __launch_bounds__(RB) void pred_kernel(const float* __restrict__ g,
     }
 }
 
+// Every block takes the same decision from the same scalars; block 0
+// records it.
+__global__ void ls_accept_kernel(double* __restrict__ sc, double c1, const float* __restrict__ trial,
+                                 float* __restrict__ theta, size_t n)
+{
+    // SC_FT and SC_F0 hold |r|^2 = 2 f.
+    const double ft = 0.5 * sc[SC_FT], f0 = 0.5 * sc[SC_F0], pred = sc[SC_PRED];
+    const bool acc = isfinite(ft) && ft <= f0 + c1 * pred;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_ACC] = acc ? 1.0 : 0.0;
+    if (!acc) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        theta[i] = trial[i];
+}
+
 __global__ __launch_bounds__(RB) void sum2_kernel(const double* __restrict__ part, int n,
                                                   double* __restrict__ out)
 {
@@ -404,6 +418,13 @@ hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, co
     const size_t n = (size_t)5 * d.nv;
     pred_kernel<<<RED_BLOCKS, RB, 0, s>>>(g, trial, theta, n, partials);
     sum2_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_accept(const Dims& d, double* scal, double c1, const float* trial, float* theta,
+                            hipStream_t s)
+{
+    ls_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, c1, trial, theta, (size_t)5 * d.nv);
     return hipGetLastError();
 }
 

@@ -1645,7 +1645,9 @@ hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void
 // 16 / 23 us, 16 x 32 with 4 waves 16 / 15, 32 x 32 with 2 waves 15.4 / 17.4,
 // with 4 waves 16.4 / 13.1, 64 x 32 with 4 waves 18.9 / 14.7; the LDS-tiled
 // kernel 19 / 25 (including its split-K sum).
-constexpr int XRW = 2, XCW = 2;   // 16 x 32 column tiles per wave: 21 / 19 us, 64: 17 / 13
+// 32 x 32 tiles per wave; 32 x 16 measured 21 / 19 us (forward / adjoint),
+// 32 x 64 17 / 13 us, against 15 / 13 us.
+constexpr int XRW = 2, XCW = 2;
 
 template <int DIR, int MODE>
 void xgemm_direct(int enc, const Dims& d, const float2* A, const void* bfrag, const float2* data,

@@ -298,11 +298,9 @@ typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 // PF: 0 = weights loaded per tile, activations (A fragments) in registers;
 // 1 = two tiles of weights in flight, activations in registers; 2 / 3 = two
 // / three tiles of weights in flight, activations read from LDS per tile
-// (frees the registers that hold them, so more weight loads are in flight);
-// 4 = hidden layers only, the last activations stored to a.hout (BF16
-// [voxel][WIDTH]) for the separate output-layer kernel, 4 waves per SIMD.
+// (frees the registers that hold them, so more weight loads are in flight).
 template <int WIDTH, int NV, int PF, bool F16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 4 : (PF >= 2 ? 2 : 1))))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF >= 2 ? 2 : 1)))
 void mlp_infer_kernel(InferArgs a)
 {
     constexpr int HP = WIDTH + 8, KS = WIDTH / 32, MT = WIDTH / 64, VT = NV / 16;
@@ -374,16 +372,6 @@ void mlp_infer_kernel(InferArgs a)
         }
         __syncthreads();
         cur = nxt;
-    }
-
-    if constexpr (PF == 4) {   // export the activations, one 16-byte piece per thread
-        for (int e = tid; e < NV * (WIDTH / 8); e += 256) {
-            const int v = e / (WIDTH / 8), q = e % (WIDTH / 8);
-            if (j0 + v < a.n)
-                *reinterpret_cast<uint4*>(a.hout + (size_t)(j0 + v) * WIDTH + 8 * q) =
-                    *reinterpret_cast<const uint4*>(&Hs[cur][v][8 * q]);
-        }
-        return;
     }
 
     // Output layer: A = activations^T (voxel rows), in registers (PF < 3)
@@ -481,6 +469,97 @@ void mlp_infer_kernel(InferArgs a)
             load_b(b0, tile);
             tile_out(b0, tile);
         }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Hidden layers as their own kernel (width 256): a workgroup of 8 waves takes
+// a tile of NV voxels at a time. Activations of the tile live in LDS in MFMA
+// B-fragment order ([16-voxel tile][K block][lane], 16 bytes per lane). For
+// each hidden layer, wave w loads the layer's weights of units [32 w, 32 w
+// + 32) into registers as A fragments (once per tile and layer: 128 KB per
+// workgroup instead of per 32-voxel tile), multiplies them against every
+// voxel of the tile with the sums in registers, and after a barrier writes
+// GELU(sum + bias) back over the activations (BF16, 8-byte stores of 4 units).
+// The first layer runs in FP32 from theta; the last activations go to
+// a.hout as BF16 [voxel][256]. Same roundings as the fused kernel.
+// ------------------------------------------------------------------------
+template <int NV>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void mlp_hidden_kernel(InferArgs a)
+{
+    constexpr int WIDTH = 256, KB = WIDTH / 32, VT = NV / 16;
+    __shared__ uint4 Hf[VT][KB][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);
+    const int n_tiles = (a.n + NV - 1) / NV;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int j0 = tile * NV;
+        // Layer 1: thread -> (voxel v, 8 units q); one 16-byte fragment piece each.
+        for (int e = tid; e < NV * (WIDTH / 8); e += 512) {
+            const int v = e % NV, q = e / NV;
+            const int j = min(j0 + v, a.n - 1);
+            const float x0 = 2.f * (a.theta[j] - a.lo[0]) / (a.hi[0] - a.lo[0]) - 1.f;
+            const float x1 = 2.f * (a.theta[a.ldth + j] - a.lo[1]) / (a.hi[1] - a.lo[1]) - 1.f;
+            const float x2 = 2.f * (a.theta[2 * a.ldth + j] - a.lo[2]) / (a.hi[2] - a.lo[2]) - 1.f;
+            float h[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int u = 8 * q + r;
+                h[r] = gelu(fmaf(a.W1[3 * u], x0, fmaf(a.W1[3 * u + 1], x1, fmaf(a.W1[3 * u + 2], x2, a.b1[u]))));
+            }
+            Hf[v / 16][q / 4][(v % 16) + 16 * (q % 4)] =
+                make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
+        }
+        __syncthreads();
+        for (int l = 0; l < a.n_hidden; ++l) {
+            const uint16_t* __restrict__ W = a.Wh[l];
+            uint4 wf[2][KB];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    wf[m][kb] = *reinterpret_cast<const uint4*>(W + (size_t)(32 * wave + 16 * m + lr) * WIDTH +
+                                                                32 * kb + lk);
+            f4 acc[2][VT];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int vt = 0; vt < VT; ++vt) acc[m][vt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int vt = 0; vt < VT; ++vt)
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const uint4 bf = Hf[vt][kb][lane];
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+                        acc[m][vt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, wf[m][kb]), __builtin_bit_cast(bf16x8, bf), acc[m][vt], 0, 0, 0);
+                }
+            __syncthreads();   // every wave has read the layer's inputs
+            // D: lane holds units 32 w + 16 m + 4 (lane / 16) + i of voxel lr.
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int u0 = 32 * wave + 16 * m + 4 * (lane >> 4);
+                const float c0 = a.bh[l][u0], c1 = a.bh[l][u0 + 1], c2 = a.bh[l][u0 + 2], c3 = a.bh[l][u0 + 3];
+                const int kb = u0 / 32, slot = lr + 16 * ((u0 % 32) / 8), half = (u0 % 8) / 4;
+#pragma unroll
+                for (int vt = 0; vt < VT; ++vt) {
+                    const f4 z = acc[m][vt];
+                    uint2* dst = reinterpret_cast<uint2*>(&Hf[vt][kb][slot]) + half;
+                    *dst = make_uint2(pack2(gelu(z[0] + c0), gelu(z[1] + c1)), pack2(gelu(z[2] + c2), gelu(z[3] + c3)));
+                }
+            }
+            __syncthreads();
+        }
+        // Last activations to a.hout, 16 bytes per thread and store.
+        for (int e = tid; e < NV * (WIDTH / 8); e += 512) {
+            const int v = e / (WIDTH / 8), q = e % (WIDTH / 8);
+            if (j0 + v < a.n)
+                *reinterpret_cast<uint4*>(a.hout + (size_t)(j0 + v) * WIDTH + 8 * q) =
+                    Hf[v / 16][q / 4][(v % 16) + 16 * (q % 4)];
+        }
+        __syncthreads();   // the next tile overwrites Hf
     }
 }
 
@@ -653,7 +732,7 @@ bool infer_fused_supported(int width, int depth) { return (width == 64 || width 
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s)
 {
     if (tile == 0) tile = width == 256 ? -64 : 64;
-    const int grid = ceil_div(a.n, tile > 1000 ? tile - 1000 : (tile < 0 ? -tile : tile));
+    const int grid = ceil_div(a.n, tile < 0 ? -tile : tile);
 #define INFER(W_, NV_, T_, PF_)                                              \
     if (width == W_ && tile == T_) {                                         \
         if (a.f16) mlp_infer_kernel<W_, NV_, PF_, true><<<grid, 256, 0, s>>>(a);   \
@@ -666,9 +745,6 @@ hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t
     INFER(128, 32, 32, 1)
     INFER(256, 64, 64, 0)
     INFER(256, 32, 32, 1)
-    // Hidden layers only (a.hout): tile 1000 + voxels.
-    INFER(256, 64, 1064, 4)
-    INFER(256, 32, 1032, 4)
     // Negative tile: the same voxel tile with activations read from LDS and
     // three weight tiles in flight.
     INFER(64, 64, -64, 3)
@@ -677,6 +753,17 @@ hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t
     INFER(256, 32, -32, 3)
 #undef INFER
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_hidden(const InferArgs& a, hipStream_t s)
+{
+    // 208-voxel tiles (240 VGPRs): 242 tiles at 224 x 224 fill one round of
+    // the 256 CUs. Measured there: 72 us; tiles of 112 / 128 / 224 voxels 85 /
+    // 88 / 76 us; the fused kernel's hidden layers on 32-voxel tiles 108 us.
+    constexpr int NV = 208;
+    const int tiles = ceil_div(a.n, NV);
+    mlp_hidden_kernel<NV><<<std::min(tiles, 256), 512, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_mlp_out(const InferArgs& a, const uint16_t* H, hipStream_t s)

@@ -230,9 +230,7 @@ hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta
         a.f16 = f16;
         if (hbuf != nullptr && W == 256) {
             a.hout = hbuf;
-            // Hidden layers on 32-voxel tiles, 4 waves per SIMD (107 us at
-            // 224 x 224 against 150 us for 64-voxel tiles at 1 wave per SIMD).
-            const hipError_t e = launch_mlp_infer(W, 1032, a, s);
+            const hipError_t e = launch_mlp_hidden(a, s);
             if (e != hipSuccess) return e;
             a.hout = nullptr;
             return launch_mlp_out(a, hbuf, s);

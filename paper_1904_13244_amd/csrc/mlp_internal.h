@@ -57,17 +57,19 @@ struct InferArgs {
     void* out;                     // out[p * plane + n * ld_out + voxel], float or _Float16
     int64_t ld_out, plane;
     bool f16;                      // trains stored as FP16
-    uint16_t* hout;                // non-null: store the last hidden activations here
-                                   // (BF16 [voxel][width]) and skip the output layer
+    uint16_t* hout;                // launch_mlp_hidden: the last hidden activations
+                                   // (BF16 [voxel][width])
 };
 bool infer_fused_supported(int width, int depth);
 // tile: voxels per workgroup, 32 or 64 (activations in registers), -32 or
 // -64 (activations read from LDS); 0 = default.
 hipError_t launch_mlp_infer(int width, int tile, const InferArgs& a, hipStream_t s);
 // Output layer alone (width 256) from activations H (BF16 [voxel][256], as
-// stored by launch_mlp_infer with a.hout): same outputs and layout as the
-// fused kernel.
+// stored by launch_mlp_hidden): same outputs and layout as the fused kernel.
 hipError_t launch_mlp_out(const InferArgs& a, const uint16_t* H, hipStream_t s);
+// Hidden layers alone (width 256): the last activations to a.hout (BF16
+// [voxel][256]), weights of one layer at a time in registers.
+hipError_t launch_mlp_hidden(const InferArgs& a, hipStream_t s);
 
 hipError_t launch_gemm_bf16(bool ta, bool tb, int epi, const GemmArgs& g, hipStream_t s);
 int gemm_tiles(int M, int N);

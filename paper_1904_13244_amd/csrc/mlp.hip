@@ -768,19 +768,33 @@ hipError_t launch_mlp_hidden(const InferArgs& a, hipStream_t s)
 
 hipError_t launch_mlp_out(const InferArgs& a, const uint16_t* H, hipStream_t s)
 {
-    // Voxel-tile groups: one workgroup per CU over all output slices, a
-    // single round.
-    // 4 output tiles per wave (512-row slices): 203 us at 224 x 224, 1120 TRs,
-    // FP16 out, against 229 us with 2 (256-row slices, twice the activation
-    // reads).
-    constexpr int MW = 4;
+    // 2, 3 or 4 output tiles per wave (slices of 256, 384 or 512 rows): the
+    // fewest rows computed, then the widest slice (fewest activation reads).
+    // 4 trains of 1120 TRs: 512-row slices (203 us against 229 us for 256);
+    // m only: 384-row slices (1152 rows computed instead of 1536).
+    int MW = 4, best = 1 << 30;
+    for (int mw = 4; mw >= 2; --mw) {
+        const int rows = ceil_div(a.m_out, 128 * mw) * 128 * mw;
+        if (rows < best) {
+            best = rows;
+            MW = mw;
+        }
+    }
     const int slices = ceil_div(a.m_out, 128 * MW);
     const int tiles = ceil_div(a.n, 64);
+    // Voxel-tile groups: one workgroup per CU over all output slices, a
+    // single round.
     const int groups = std::max(1, std::min(tiles, 256 / slices));
     dim3 grid(slices, groups);
-    if (a.f16) mlp_out_kernel<true, MW><<<grid, 512, 0, s>>>(a, H);
-    else mlp_out_kernel<false, MW><<<grid, 512, 0, s>>>(a, H);
-    return hipGetLastError();
+#define OUT_CASE(M_)                                                            \
+    if (MW == M_) {                                                             \
+        if (a.f16) mlp_out_kernel<true, M_><<<grid, 512, 0, s>>>(a, H);         \
+        else mlp_out_kernel<false, M_><<<grid, 512, 0, s>>>(a, H);              \
+        return hipGetLastError();                                               \
+    }
+    OUT_CASE(4) OUT_CASE(3) OUT_CASE(2)
+#undef OUT_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s)

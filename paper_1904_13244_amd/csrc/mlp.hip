@@ -605,21 +605,24 @@ void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
     const bool vec_ok = (a.ld_out % 4) == 0;
     // Tile loads: 32 fragments of 64 x 16 bytes; wave w loads fragments
     // w, w + 8, w + 16, w + 24, each lane the piece it will be read from.
-    uint4 hr[4];
+    // (Four named registers: an array here was placed in LDS by the compiler.)
+    uint4 hr0, hr1, hr2, hr3;
+    auto piece = [&](int t, int i) {
+        const int f = wave + 8 * i, vt = f / KB, kb = f % KB;
+        const int j = min(t * NVT + vt * 16 + lr, a.n - 1);
+        return *reinterpret_cast<const uint4*>(H + (size_t)j * WIDTH + 32 * kb + lk);
+    };
     auto gload = [&](int t) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = wave + 8 * i, vt = f / KB, kb = f % KB;
-            const int j = min(t * NVT + vt * 16 + lr, a.n - 1);
-            hr[i] = *reinterpret_cast<const uint4*>(H + (size_t)j * WIDTH + 32 * kb + lk);
-        }
+        hr0 = piece(t, 0);
+        hr1 = piece(t, 1);
+        hr2 = piece(t, 2);
+        hr3 = piece(t, 3);
     };
     auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = wave + 8 * i;
-            Hf[buf][f / KB][f % KB][lane] = hr[i];
-        }
+        Hf[buf][wave / KB][wave % KB][lane] = hr0;
+        Hf[buf][(wave + 8) / KB][(wave + 8) % KB][lane] = hr1;
+        Hf[buf][(wave + 16) / KB][(wave + 16) % KB][lane] = hr2;
+        Hf[buf][(wave + 24) / KB][(wave + 24) % KB][lane] = hr3;
     };
     int t = blockIdx.y;
     if (t < n_tiles) {

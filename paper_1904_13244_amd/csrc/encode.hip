@@ -1649,20 +1649,33 @@ hipError_t launch_build_bfrag(const Dims& d, const float2* extab, void* f1, void
 // 32 x 64 17 / 13 us, against 15 / 13 us.
 constexpr int XRW = 2, XCW = 2;
 
+// Many rows (coils x TRs >= 4096): 64 x 64 tiles per wave, which halves the
+// operand reads through L2, and fewer waves per tile (there are tiles enough).
+constexpr int XBIG_M = 4096, XBRW = 4, XBCW = 4;
+
+template <int DIR, int MODE, int RW, int CW, int KS>
+void xgemm_direct_t(int enc, const Dims& d, const float2* A, const void* bfrag, const float2* data,
+                    float2* out, double* red, int* nred, hipStream_t s)
+{
+    const int Nr = DIR == 0 ? 2 * d.nk : 2 * d.nx;
+    dim3 grid(ceil_div(Nr, 16 * CW), ceil_div(d.C * d.T, 16 * RW));
+    if (nred) *nred = grid.x * grid.y;
+    if (enc == 1)
+        xgemm_direct_kernel<DIR, MODE, 1, KS, RW, CW><<<grid, 64 * KS, 0, s>>>(
+            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+    else
+        xgemm_direct_kernel<DIR, MODE, 2, KS, RW, CW><<<grid, 64 * KS, 0, s>>>(
+            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+}
+
 template <int DIR, int MODE>
 void xgemm_direct(int enc, const Dims& d, const float2* A, const void* bfrag, const float2* data,
                   float2* out, double* red, int* nred, hipStream_t s)
 {
-    const int Nr = DIR == 0 ? 2 * d.nk : 2 * d.nx;
-    dim3 grid(ceil_div(Nr, 16 * XCW), ceil_div(d.C * d.T, 16 * XRW));
-    if (nred) *nred = grid.x * grid.y;
-    constexpr int KS = DIR == 0 ? 2 : 4;
-    if (enc == 1)
-        xgemm_direct_kernel<DIR, MODE, 1, KS, XRW, XCW><<<grid, 64 * KS, 0, s>>>(
-            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+    if (d.C * d.T >= XBIG_M)
+        xgemm_direct_t<DIR, MODE, XBRW, XBCW, DIR == 0 ? 1 : 2>(enc, d, A, bfrag, data, out, red, nred, s);
     else
-        xgemm_direct_kernel<DIR, MODE, 2, KS, XRW, XCW><<<grid, 64 * KS, 0, s>>>(
-            A, (const uint4*)bfrag, data, out, red, d.C * d.T, d.nx, d.nk);
+        xgemm_direct_t<DIR, MODE, XRW, XCW, DIR == 0 ? 2 : 4>(enc, d, A, bfrag, data, out, red, nred, s);
 }
 
 hipError_t launch_xgemm_fwd(const Dims& d, const YPlan& p, int enc, int mode, const float2* U,

@@ -117,10 +117,14 @@ def _shape_cases():
                             ky_line=rng.integers(0, 19, T))
     coils = I.make_problem(24, 20, 30, 48, 8, n_coils=4, flip_deg=rng.uniform(5, 70, 30))
     mask = (rng.uniform(size=coils.nv) > 0.2).astype(np.uint8)
-    return {"ragged_odd": (ragged, None, None), "coils_mask": (coils, I.coil_maps(24, 20, 4), mask)}
+    # 8 coils x 530 TRs = 4240 rows: the large-tile x-GEMM, ragged in rows and columns.
+    many = I.make_problem(20, 12, 530, 40, 6, n_coils=8, flip_deg=rng.uniform(5, 70, 530))
+    mask8 = (rng.uniform(size=many.nv) > 0.2).astype(np.uint8)
+    return {"ragged_odd": (ragged, None, None), "coils_mask": (coils, I.coil_maps(24, 20, 4), mask),
+            "coils_many_rows": (many, I.coil_maps(20, 12, 8), mask8)}
 
 
-@pytest.mark.parametrize("name", ["ragged_odd", "coils_mask"])
+@pytest.mark.parametrize("name", ["ragged_odd", "coils_mask", "coils_many_rows"])
 @pytest.mark.parametrize("enc", [1, 2])
 def test_reduced_precision_shapes(oracle_lib, name, enc):
     """The reduced-precision contractions on partial tiles, coils and a mask,

@@ -353,7 +353,7 @@ void ystage_fwd_wide_kernel(
 // registers. The next TR's trains are loaded before that barrier. Layout as
 // G = 0 above: two rows of 32 columns per wave, R row steps per lane.
 // ------------------------------------------------------------------------
-template <int MODE, int R, int CC, typename TT>
+template <int MODE, int R, int CC, typename TT, int TB>
 __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
     const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
@@ -362,10 +362,10 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
 {
     constexpr int RS = 2 * FW;
     constexpr int NT = MODE == 1 ? 4 : 1;
-    // LDS: two buffers of per-wave sums [CC][FW][32], then the block's
-    // y-phases [TRs per chunk][RS R].
+    // LDS: two buffers of per-wave sums [TB][CC][FW][32] (TB TRs per
+    // barrier), then the block's y-phases [TRs per chunk][RS R].
     extern __shared__ float2 lds[];
-    float2* eys = lds + 2 * CC * FW * 32;
+    float2* eys = lds + 2 * TB * CC * FW * 32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int xl = lane & 31, half = lane >> 5;
     const int ix = blockIdx.x * 32 + xl;
@@ -417,40 +417,46 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
     float nxt[R][NT];
     load_tr(nxt, n0);
     int buf = 0;
-    for (int n = n0; n < n1; ++n) {
-        float cur[R][NT];
+    for (int nb = n0; nb < n1; nb += TB) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int tb = 0; tb < TB; ++tb) {
+            // TRs past the chunk repeat its last TR; their sums are not stored.
+            const int n = min(nb + tb, n1 - 1);
+            float cur[R][NT];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) cur[r][q] = nxt[r][q];
-        load_tr(nxt, min(n + 1, n1 - 1));
-        const float2* eyrow = eys + (size_t)(n - n0) * RS * R + 2 * wave + half;
-        float2 acc[CC];
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < CC; ++c) acc[c] = make_float2(0.f, 0.f);
+                for (int q = 0; q < NT; ++q) cur[r][q] = nxt[r][q];
+            load_tr(nxt, min(n + 1, n1 - 1));
+            const float2* eyrow = eys + (size_t)(n - n0) * RS * R + 2 * wave + half;
+            float2 acc[CC];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float2 x;
-            if constexpr (MODE == 0) {
-                x = make_float2(P[r].x * cur[r][0], P[r].y * cur[r][0]);
-            } else {
-                const float a = fmaf(v0[r], cur[r][1], fmaf(v1[r], cur[r][2], v2[r] * cur[r][3]));
-                x = make_float2(fmaf(P[r].x, a, Q[r].x * cur[r][0]), fmaf(P[r].y, a, Q[r].y * cur[r][0]));
+            for (int c = 0; c < CC; ++c) acc[c] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x;
+                if constexpr (MODE == 0) {
+                    x = make_float2(P[r].x * cur[r][0], P[r].y * cur[r][0]);
+                } else {
+                    const float a = fmaf(v0[r], cur[r][1], fmaf(v1[r], cur[r][2], v2[r] * cur[r][3]));
+                    x = make_float2(fmaf(P[r].x, a, Q[r].x * cur[r][0]), fmaf(P[r].y, a, Q[r].y * cur[r][0]));
+                }
+                const float2 z = cmul(eyrow[RS * r], x);
+#pragma unroll
+                for (int c = 0; c < CC; ++c) acc[c] = cfma(cw[r][c], z, acc[c]);
             }
-            const float2 z = cmul(eyrow[RS * r], x);
+            float2* red = lds + (size_t)(buf * TB + tb) * CC * FW * 32;
 #pragma unroll
-            for (int c = 0; c < CC; ++c) acc[c] = cfma(cw[r][c], z, acc[c]);
-        }
-        float2* red = lds + buf * CC * FW * 32;
-#pragma unroll
-        for (int c = 0; c < CC; ++c) {
-            const float2 t = shfl_xor2(acc[c], 32);
-            if (half == 0) red[(c * FW + wave) * 32 + xl] = make_float2(acc[c].x + t.x, acc[c].y + t.y);
+            for (int c = 0; c < CC; ++c) {
+                const float2 t = shfl_xor2(acc[c], 32);
+                if (half == 0) red[(c * FW + wave) * 32 + xl] = make_float2(acc[c].x + t.x, acc[c].y + t.y);
+            }
         }
         __syncthreads();
-        // Reduce this TR across the waves (the next TR writes the other buffer).
-        for (int o = threadIdx.x; o < CC * 32; o += blockDim.x) {
-            const int c = o >> 5, l = o & 31;
+        // Reduce these TRs across the waves (the next batch writes the other buffer).
+        for (int o = threadIdx.x; o < TB * CC * 32; o += blockDim.x) {
+            const int tb = o / (CC * 32), c = (o >> 5) % CC, l = o & 31;
+            const float2* red = lds + (size_t)(buf * TB + tb) * CC * FW * 32;
             float2 sum = red[(c * FW) * 32 + l];
 #pragma unroll
             for (int w = 1; w < FW; ++w) {
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
                 sum.y += t.y;
             }
             const int oix = blockIdx.x * 32 + l;
-            if (oix < nx && c < C) U[(((size_t)yb * C + c) * T + n) * nx + oix] = sum;
+            if (oix < nx && c < C && nb + tb < n1) U[(((size_t)yb * C + c) * T + nb + tb) * nx + oix] = sum;
         }
         buf ^= 1;
     }
@@ -1424,10 +1430,19 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* t
     if constexpr (CC > 1) {
         // Coils: per-TR reduction, long TR chunks.
         dim3 grid(ceil_div(d.nx, 32), p.nbyc, ceil_div(d.T, p.fwd_trc));
-        const size_t lds = (size_t)(2 * CC * FW * 32 + p.fwd_trc * 2 * FW * p.r_fwdc) * sizeof(float2);
+        // TRs per barrier (LDS 2 TB CC 16 KB): 2 for up to 8 coils (256 x 256,
+        // 8 coils, 1280 TRs: FP16 trains 329 -> 261 us, FP32 395 -> 350 us).
+        constexpr int TB = CC <= 8 ? 2 : 1;
+        const size_t lds = (size_t)(2 * TB * CC * FW * 32 + p.fwd_trc * 2 * FW * p.r_fwdc) * sizeof(float2);
 #define FWDC_CASE(RR)                                                                           \
     if (p.r_fwdc == RR) {                                                                       \
-        ystage_fwd_coil_kernel<MODE, RR, CC, TT><<<grid, FW * 64, lds, s>>>(                    \
+        if (lds > 65536) {                                                                      \
+            const hipError_t ea = hipFuncSetAttribute(                                          \
+                reinterpret_cast<const void*>(&ystage_fwd_coil_kernel<MODE, RR, CC, TT, TB>),   \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                          \
+            if (ea != hipSuccess) return ea;                                                    \
+        }                                                                                       \
+        ystage_fwd_coil_kernel<MODE, RR, CC, TT, TB><<<grid, FW * 64, lds, s>>>(                \
             trains, theta, v, coil, mask, eytab, U, d.nx, d.ny, d.nv, d.T, d.C, p.fwd_trc);     \
         return hipGetLastError();                                                               \
     }

@@ -43,33 +43,36 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0    # dense
 FP32_VALU_PEAK_TFLOPS = 157.3     # published vector peak (packed); see the design doc
 
 # Algorithmic work per launch (the design doc derives each figure).
-EPG_FLOP_PER_STATE_TR = 67        # value 13 + ln T1 15 + ln T2 17 + B1 22 (real form)
+EPG_FLOP_PER_STATE_TR = {4: 67,   # value 13 + ln T1 15 + ln T2 17 + B1 22 (real form)
+                         3: 45}   # B1 held fixed: no B1 tangent
 # Kernel kinds traced in the timed region (the roofline candidates).
 TRACED_KINDS = ["epg", "epg_value", "ystage_fwd_signal", "ystage_fwd_jv", "ystage_adj",
                 "surrogate", "surrogate_value"]
 
 
-def algorithmic(kind, prob, tb=4):
+def algorithmic(kind, prob, tb=4, ntr=4):
     """(unit, amount per launch, bound) for a kernel kind; tb = bytes per
-    stored train value."""
+    stored train value, ntr = trains of the linearisation (4, or 3 when B1 is
+    held fixed: no dm/dB1 train)."""
     T, nv, nx, C = prob.n_tr, prob.nv, prob.nx, prob.n_coils
-    if kind == "ystage_fwd_jv":   # 4 trains + per-voxel weights in, U out
-        return "bytes", 4 * tb * T * nv + 28 * nv + 8 * C * T * nx, "hbm"
+    if kind == "ystage_fwd_jv":   # ntr trains + rho and ntr + 1 direction rows in, U out
+        return "bytes", ntr * tb * T * nv + (8 + 4 * (ntr + 1)) * nv + 8 * C * T * nx, "hbm"
     if kind == "ystage_fwd_signal":   # m train + rho in, U out
         return "bytes", tb * T * nv + 8 * nv + 8 * C * T * nx, "hbm"
-    if kind == "ystage_adj":      # 4 trains + W in
-        return "bytes", 4 * tb * T * nv + 8 * C * T * nx, "hbm"
+    if kind == "ystage_adj":      # ntr trains + W in
+        return "bytes", ntr * tb * T * nv + 8 * C * T * nx, "hbm"
     if kind == "epg":
-        return "flop", EPG_FLOP_PER_STATE_TR * prob.n_states * T * nv, "alu"
+        return "flop", EPG_FLOP_PER_STATE_TR[ntr] * prob.n_states * T * nv, "alu"
     return None
 
 
-def surrogate_work(prob, width=256, depth=4, bytes_per_value=2):
-    """Per linearisation through the network with all four trains (hidden-layer
-    kernel + output-layer kernel): (flop, bytes written). Multiply-adds of the first layer, the hidden layers and the
-    4 n_tr imaginary outputs; the trains written once (FP16 by default)."""
-    macs = 3 * width + (depth - 1) * width * width + 4 * prob.n_tr * width
-    return 2 * macs * prob.nv, 4 * bytes_per_value * prob.n_tr * prob.nv
+def surrogate_work(prob, width=256, depth=4, bytes_per_value=2, ntr=4):
+    """Per linearisation through the network with ntr trains (hidden-layer
+    kernel + output-layer kernel): (flop, bytes written). Multiply-adds of the
+    first layer, the hidden layers and the ntr n_tr imaginary outputs; the
+    trains written once (FP16 by default)."""
+    macs = 3 * width + (depth - 1) * width * width + ntr * prob.n_tr * width
+    return 2 * macs * prob.nv, ntr * bytes_per_value * prob.n_tr * prob.nv
 
 
 def measured_traffic(kind):
@@ -138,12 +141,12 @@ def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=8):
                        f"t_step = t_lin + (n_cg + 1) t_pair = {t_step:.1f} s")}
 
 
-def roofline_for(kernels, prob, tb):
-    cand = [k for k in kernels if algorithmic(k, prob, tb)]
+def roofline_for(kernels, prob, tb, ntr):
+    cand = [k for k in kernels if algorithmic(k, prob, tb, ntr)]
     if not cand:
         return None
     rk = max(cand, key=lambda k: kernels[k]["ms_per_step"])
-    unit, amount, bound = algorithmic(rk, prob, tb)
+    unit, amount, bound = algorithmic(rk, prob, tb, ntr)
     t = kernels[rk]["avg_ms"] * 1e-3
     if unit == "bytes":
         ach = amount / t / 1e9
@@ -189,6 +192,8 @@ def main():
     th0[2] += 0.02 * rng.standard_normal(prob.nv)
     vv, ww = I.probe_vectors(prob, work.param_mask)
     vd, wd = dev(vv, torch.float32), dev(ww, torch.complex64)
+    # B1 held fixed: the GN step's linearisation has no dm/dB1 train.
+    ntr = 4 if (work.param_mask >> 2) & 1 else 3
 
     def run_form(net, enc, lo, hi, trains):
         ctx.set_surrogate(net)
@@ -246,7 +251,7 @@ def main():
         return {"value": args.n_cg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                 "kernels": kernels, "step_breakdown_untimed": breakdown,
                 "dominant_kernel": max(breakdown, key=lambda k: breakdown[k]["ms"]),
-                "roofline": roofline_for(kernels, prob, 2 if trains == B.TRAINS_FP16 else 4),
+                "roofline": roofline_for(kernels, prob, 2 if trains == B.TRAINS_FP16 else 4, ntr),
                 "pair_cached_ms": pair_ms,
                 "pairs_per_s_cached": 1e3 / pair_ms, "linearise_ms": lin_ms,
                 "gn_report_last": rep.as_dict()}
@@ -262,7 +267,7 @@ def main():
         hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
         f = run_form(net, B.ENC_SPLIT_BF16, lo, hi, B.TRAINS_FP16)
         forms["surrogate_split_bf16"] = f
-        flop, wbytes = surrogate_work(prob)
+        flop, wbytes = surrogate_work(prob, ntr=ntr)
         k = f["kernels"].get("surrogate")
         t = k["avg_ms"] * 1e-3 if k else None
         surr_info = {
@@ -272,7 +277,8 @@ def main():
                          "heldout_rel_err": dict(zip(["m", "dm_dlnT1", "dm_dlnT2", "dm_dB1"],
                                                      trep.val_rel_err))},
             "inference_roofline": None if t is None else {
-                "kernel": "surrogate (hidden-layer + output-layer kernels, all four trains, FP16 out)",
+                "kernel": (f"surrogate (hidden-layer + output-layer kernels, {ntr} trains, "
+                           "FP16 out)"),
                 "bound": "hbm", "achieved": wbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": wbytes / t / 1e9 / HBM_PEAK_GBS,
                 "mfma_tflops": flop / t / 1e12, "mfma_frac": flop / t / 1e12 / BF16_MFMA_PEAK_TFLOPS,
@@ -295,7 +301,8 @@ def main():
         "dtype": "fp32+bf16" if chosen.startswith("surrogate") else "fp32",
         "data": "synthetic",
         "config": {"workload": ("224x224 brain-like phantom, 1120 TRs (224 lines x 5 sweeps), "
-                                "448 readout samples, K=32 EPG states, 1 coil; one GN step = "
+                                "448 readout samples, K=32 EPG states, 1 coil; T1, T2, rho fitted "
+                                "with B1 known (no dm/dB1 train); one GN step = "
                                 "linearise + r + g + 20 CG pairs + 1 line-search trial"),
                    "form": {"surrogate_split_bf16": "surrogate trains (BF16 MFMA network, EPG "
                                                     "fallback, FP16 storage) + split-BF16 MFMA "

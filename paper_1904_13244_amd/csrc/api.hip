@@ -49,6 +49,7 @@ struct mrstat_ctx_s {
     const uint8_t* mask = nullptr;
     bool bound = false;
     bool lin_valid = false;
+    int lin_ntr = 4;              // trains of the linearisation: 4, or 3 without dm/dB1
     std::string err;
     // kernel tracing
     struct Rec { int kind; hipEvent_t a, b; };
@@ -209,21 +210,24 @@ mrstat_status check_ready(mrstat_ctx ctx)
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // ----------------------------------------------------------- kernel sequences
-// Trains at theta into out ([4][T][nv] with tangents, else the m train
-// [T][nv]): by the EPG, or by the surrogate with the EPG for the voxels
-// outside its box (their count in fb_count(slot)).
-mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, bool tangents, int slot,
+// Trains at theta into out ([ntr][T][nv]: m, then dm/dlnT1, dm/dlnT2 and,
+// with ntr = 4, dm/dB1; ntr = 1: the m train only): by the EPG, or by the
+// surrogate with the EPG for the voxels outside its box (their count in
+// fb_count(slot)).
+mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, int ntr, int slot,
                             hipStream_t s)
 {
     const Dims& d = ctx->d;
+    const bool tangents = ntr > 1;
+    const int ntan = ntr - 1;   // tangent trains: 3, 2 or 0
     const int kind = tangents ? MRSTAT_K_EPG : MRSTAT_K_EPG_VALUE;
     if (!ctx->surr) {
-        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, tangents, ctx->epg_lanes,
+        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, ntan, ctx->epg_lanes,
                                         ctx->f16, s)));
         return MRSTAT_OK;
     }
     const int skind = tangents ? MRSTAT_K_SURR : MRSTAT_K_SURR_VALUE;
-    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, tangents, ctx->f16,
+    HIP_TRY(TRACED(skind, mlp_infer_trains(ctx->surr, theta, d.nv, d.nv, out, d.nv, ntr, ctx->f16,
                                                     ctx->at<uint16_t>(ctx->L.hbuf), s)));
     HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_box_compact(d, theta, mlp_box_lo(ctx->surr),
                                                        mlp_box_hi(ctx->surr), ctx->mask, ctx->fb_idx(),
@@ -231,17 +235,21 @@ mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, bool 
     // A short list of scattered voxels is latency bound: spread each voxel's
     // states over the most lanes unless a split was set explicitly.
     const int fb_lanes = ctx->epg_lanes ? ctx->epg_lanes : (d.K <= 8 ? 2 : d.K <= 16 ? 4 : 8);
-    HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, tangents, fb_lanes,
+    HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, ntan, fb_lanes,
                                          ctx->f16, ctx->fb_idx(), ctx->fb_count(slot), s)));
     return MRSTAT_OK;
 }
 
-mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s)
+// Linearisation with all four trains (ntr = 4) or, for fits that hold B1
+// fixed, without dm/dB1 (ntr = 3): their Jacobian has no B1 column, so
+// that train is neither simulated nor streamed.
+mrstat_status linearise(mrstat_ctx ctx, const float* theta, hipStream_t s, int ntr = 4)
 {
     ctx->lin_valid = false;
-    mrstat_status st = simulate_into(ctx, theta, ctx->trains(), true, 0, s);
+    mrstat_status st = simulate_into(ctx, theta, ctx->trains(), ntr, 0, s);
     if (st != MRSTAT_OK) return st;
     ctx->lin_valid = true;
+    ctx->lin_ntr = ntr;
     return MRSTAT_OK;
 }
 
@@ -268,15 +276,19 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
 }
 
 // With dir non-null the finish kernel also leaves the CG curvature partials
-// of dir . g in ctx->red().
+// of dir . g in ctx->red(). Without the dm/dB1 train (a linearisation with 3
+// trains) B1 must lie outside param_mask.
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, int param_mask,
                       hipStream_t s, const float* dir = nullptr)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
+    const int ntr = ctx->lin_ntr;
+    if (ntr < 4 && ((param_mask >> 2) & 1))
+        return fail(ctx, MRSTAT_ERR_STATE, "linearisation holds no dm/dB1 train");
     HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
                                                    ctx->bfrag(1), ctx->W(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 4, ctx->coil, ctx->mask,
+    HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, ntr, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
     HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
                                                       dir, dir ? ctx->red() : nullptr, s)));
@@ -472,14 +484,17 @@ mrstat_status mrstat_simulate(mrstat_ctx ctx, const float* d_theta, float* d_tra
     return MRSTAT_OK;
 }
 
-static mrstat_status prepare(mrstat_ctx ctx, const float* d_theta, int32_t reuse, hipStream_t s)
+// need_all: the call uses every Jacobian column, so a linearisation without
+// the dm/dB1 train (left by a B1-fixed GN step) is redone at the same theta.
+static mrstat_status prepare(mrstat_ctx ctx, const float* d_theta, int32_t reuse, hipStream_t s,
+                             bool need_all = true)
 {
     mrstat_status st = check_ready(ctx);
     if (st != MRSTAT_OK) return st;
     if (!d_theta) return fail(ctx, MRSTAT_ERR_ARG, "theta is NULL");
     if (reuse) {
         if (!ctx->lin_valid) return fail(ctx, MRSTAT_ERR_STATE, "reuse requested without a linearisation");
-        return MRSTAT_OK;
+        if (!need_all || ctx->lin_ntr == 4) return MRSTAT_OK;
     }
     return linearise(ctx, d_theta, s);
 }
@@ -488,7 +503,7 @@ mrstat_status mrstat_residual(mrstat_ctx ctx, const float* d_theta, int32_t reus
                               const void* d_data, void* d_r, double* h_f, mrstat_stream stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    mrstat_status st = prepare(ctx, d_theta, reuse, s);
+    mrstat_status st = prepare(ctx, d_theta, reuse, s, false);
     if (st != MRSTAT_OK) return st;
     if (!d_data || !d_r) return fail(ctx, MRSTAT_ERR_ARG, "data or r is NULL");
     if (!aligned(d_data, 8) || !aligned(d_r, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
@@ -549,8 +564,10 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     float* trial = ctx->vec(5);
     double* sc = ctx->scal();
 
-    // Linearise at theta; r, f, g = Re(J^H r).
-    st = linearise(ctx, d_theta, s);
+    // Linearise at theta; r, f, g = Re(J^H r). With B1 outside param_mask the
+    // Jacobian has no B1 column: no dm/dB1 train (J v in y-stage mode 3).
+    const int ntr = ((o->param_mask >> 2) & 1) ? 4 : 3;
+    st = linearise(ctx, d_theta, s, ntr);
     if (st != MRSTAT_OK) return st;
     st = forward(ctx, 0, 0, ctx->trains(), d_theta, nullptr, d_data, ctx->r(), sc + SC_F0, s);
     if (st != MRSTAT_OK) return st;
@@ -560,7 +577,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     // CG on Re(J^H J) p = -g with device-resident FP64 scalars.
     HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s)));
     for (int it = 0; it < o->n_cg; ++it) {
-        st = forward(ctx, 1, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
+        st = forward(ctx, ntr == 4 ? 1 : 3, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
         if (st != MRSTAT_OK) return st;
         st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s, dir);
         if (st != MRSTAT_OK) return st;
@@ -579,7 +596,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     for (int k = 0; k < o->n_ls_max; ++k) {
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi,
                                                                o->param_mask, ctx->mask, trial, s)));
-        st = simulate_into(ctx, trial, ctx->trial_m(), false, 1, s);
+        st = simulate_into(ctx, trial, ctx->trial_m(), 1, 1, s);
         if (st != MRSTAT_OK) return st;
         st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
         if (st != MRSTAT_OK) return st;

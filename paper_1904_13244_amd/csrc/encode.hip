@@ -13,6 +13,8 @@
 //   mode 0 (signal):   x = rho m           = i rho mu
 //   mode 1 (J v dir.): x = sum_q D_q v_q   = i (rho a + nu mu),
 //                      a = v0 mu1 + v1 mu2 + v2 mu3, nu = v3 + i v4
+//   mode 3 (J v dir., B1 held fixed): as mode 1 with v2 = 0, so the dm/dB1
+//                      train is neither needed nor read
 // (D_q = d(rho m)/d alpha_q, the Jacobian columns of the Theory section).
 //
 // Lane layout of both y-stages: a wave covers 32 consecutive ix (lanes 0-31
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
     }
     __syncthreads();
 
+    constexpr bool JV = MODE != 0, DB1 = MODE == 1;   // J v direction; with the dm/dB1 train
     float2 P[R], Q[R];
     float v0[R], v1[R], v2[R];
     int jr[R], iyr[R];
@@ -124,12 +127,12 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
         const bool on = ok && (mask == nullptr || mask[j] != 0);
         const float rr = on ? theta[3 * nv + j] : 0.f, ri = on ? theta[4 * nv + j] : 0.f;
         P[r] = make_float2(-ri, rr);   // i rho
-        if constexpr (MODE == 1) {
+        if constexpr (JV) {
             const float nr = on ? v[3 * nv + j] : 0.f, ni = on ? v[4 * nv + j] : 0.f;
             Q[r] = make_float2(-ni, nr);   // i nu
             v0[r] = on ? v[j] : 0.f;
             v1[r] = on ? v[nv + j] : 0.f;
-            v2[r] = on ? v[2 * nv + j] : 0.f;
+            if constexpr (DB1) v2[r] = on ? v[2 * nv + j] : 0.f;
         }
         if constexpr (CC > 1) {
 #pragma unroll
@@ -151,11 +154,11 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             mu[r] = (float)b0[jr[r]];
-            if constexpr (MODE == 1) {
+            if constexpr (JV) {
                 m1[r] = (float)b1[jr[r]];
                 m2[r] = (float)b2[jr[r]];
-                m3[r] = (float)b3[jr[r]];
             }
+            if constexpr (DB1) m3[r] = (float)b3[jr[r]];
             ey[r] = eyrow[RS * r];
         }
         float2 acc[CC];
@@ -167,7 +170,8 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
             if constexpr (MODE == 0) {
                 x = make_float2(P[r].x * mu[r], P[r].y * mu[r]);
             } else {
-                const float a = fmaf(v0[r], m1[r], fmaf(v1[r], m2[r], v2[r] * m3[r]));
+                const float a = DB1 ? fmaf(v0[r], m1[r], fmaf(v1[r], m2[r], v2[r] * m3[r]))
+                                    : fmaf(v0[r], m1[r], v1[r] * m2[r]);
                 x = make_float2(fmaf(P[r].x, a, Q[r].x * mu[r]), fmaf(P[r].y, a, Q[r].y * mu[r]));
             }
             const float2 z = cmul(ey[r], x);
@@ -233,6 +237,7 @@ void ystage_fwd_wide_kernel(
     int nx, int ny, int nv, int T, int rows)
 {
     typedef typename Vec4<TT>::T V4;
+    constexpr bool JV = MODE != 0, DB1 = MODE == 1;   // J v direction; with the dm/dB1 train
     // LDS: per-wave sums [NWW][NT][nx], then the slab's y-phases [NT][rows].
     extern __shared__ float2 lds[];
     float2* eys = lds + (size_t)NWW * NT * nx;
@@ -267,12 +272,12 @@ void ystage_fwd_wide_kernel(
             f4 pr = *(const f4*)(theta + 3 * (size_t)nv + j);
             f4 pi = *(const f4*)(theta + 4 * (size_t)nv + j);
             f4 qr, qi, w0, w1, w2;
-            if constexpr (MODE == 1) {
+            if constexpr (JV) {
                 qr = *(const f4*)(v + 3 * (size_t)nv + j);
                 qi = *(const f4*)(v + 4 * (size_t)nv + j);
                 w0 = *(const f4*)(v + j);
                 w1 = *(const f4*)(v + (size_t)nv + j);
-                w2 = *(const f4*)(v + 2 * (size_t)nv + j);
+                if constexpr (DB1) w2 = *(const f4*)(v + 2 * (size_t)nv + j);
             }
             V4 m0[NT], m1[NT], m2[NT], m3[NT];
 #pragma unroll
@@ -282,11 +287,11 @@ void ystage_fwd_wide_kernel(
                 // non-temporal ones (each kernel then starts on trains the
                 // other left in the caches).
                 m0[t] = *(const V4*)b;
-                if constexpr (MODE == 1) {
+                if constexpr (JV) {
                     m1[t] = *(const V4*)(b + plane);
                     m2[t] = *(const V4*)(b + 2 * plane);
-                    m3[t] = *(const V4*)(b + 3 * plane);
                 }
+                if constexpr (DB1) m3[t] = *(const V4*)(b + 3 * plane);
             }
             if (mask != nullptr) {   // masked voxels: zero weights (selects, not products)
                 const uchar4 mk = *(const uchar4*)(mask + j);
@@ -295,13 +300,13 @@ void ystage_fwd_wide_kernel(
                 for (int c = 0; c < 4; ++c) {
                     pr[c] = on[c] ? pr[c] : 0.f;
                     pi[c] = on[c] ? pi[c] : 0.f;
-                    if constexpr (MODE == 1) {
+                    if constexpr (JV) {
                         qr[c] = on[c] ? qr[c] : 0.f;
                         qi[c] = on[c] ? qi[c] : 0.f;
                         w0[c] = on[c] ? w0[c] : 0.f;
                         w1[c] = on[c] ? w1[c] : 0.f;
-                        w2[c] = on[c] ? w2[c] : 0.f;
                     }
+                    if constexpr (DB1) w2[c] = on[c] ? w2[c] : 0.f;
                 }
             }
 #pragma unroll
@@ -310,12 +315,14 @@ void ystage_fwd_wide_kernel(
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float mu = (float)m0[t][c];
-                    float2 x;   // i rho mu (mode 0); i (rho a + nu mu) (mode 1)
+                    float2 x;   // i rho mu (mode 0); i (rho a + nu mu) (modes 1, 3)
                     if constexpr (MODE == 0) {
                         x = make_float2(-pi[c] * mu, pr[c] * mu);
                     } else {
-                        const float a = fmaf(w0[c], (float)m1[t][c],
-                                             fmaf(w1[c], (float)m2[t][c], w2[c] * (float)m3[t][c]));
+                        const float a =
+                            DB1 ? fmaf(w0[c], (float)m1[t][c],
+                                       fmaf(w1[c], (float)m2[t][c], w2[c] * (float)m3[t][c]))
+                                : fmaf(w0[c], (float)m1[t][c], w1[c] * (float)m2[t][c]);
                         x = make_float2(-fmaf(pi[c], a, qi[c] * mu), fmaf(pr[c], a, qr[c] * mu));
                     }
                     acc[t][c] = cfma(ey, x, acc[t][c]);
@@ -361,7 +368,7 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
     int n_per_chunk)
 {
     constexpr int RS = 2 * FW;
-    constexpr int NT = MODE == 1 ? 4 : 1;
+    constexpr int NT = MODE == 0 ? 1 : (MODE == 1 ? 4 : 3);   // trains read per voxel and TR
     // LDS: two buffers of per-wave sums [TB][CC][FW][32] (TB TRs per
     // barrier), then the block's y-phases [TRs per chunk][RS R].
     extern __shared__ float2 lds[];
@@ -394,12 +401,12 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
         const bool on = ok && (mask == nullptr || mask[j] != 0);
         const float rr = on ? theta[3 * nv + j] : 0.f, ri = on ? theta[4 * nv + j] : 0.f;
         P[r] = make_float2(-ri, rr);   // i rho
-        if constexpr (MODE == 1) {
+        if constexpr (NT > 1) {
             const float nr = on ? v[3 * nv + j] : 0.f, ni = on ? v[4 * nv + j] : 0.f;
             Q[r] = make_float2(-ni, nr);   // i nu
             v0[r] = on ? v[j] : 0.f;
             v1[r] = on ? v[nv + j] : 0.f;
-            v2[r] = on ? v[2 * nv + j] : 0.f;
+            if constexpr (NT == 4) v2[r] = on ? v[2 * nv + j] : 0.f;
         }
 #pragma unroll
         for (int c = 0; c < CC; ++c)
@@ -438,7 +445,11 @@ __global__ __launch_bounds__(1024) void ystage_fwd_coil_kernel(
                 if constexpr (MODE == 0) {
                     x = make_float2(P[r].x * cur[r][0], P[r].y * cur[r][0]);
                 } else {
-                    const float a = fmaf(v0[r], cur[r][1], fmaf(v1[r], cur[r][2], v2[r] * cur[r][3]));
+                    float a;
+                    if constexpr (NT == 4)
+                        a = fmaf(v0[r], cur[r][1], fmaf(v1[r], cur[r][2], v2[r] * cur[r][3]));
+                    else
+                        a = fmaf(v0[r], cur[r][1], v1[r] * cur[r][2]);
                     x = make_float2(fmaf(P[r].x, a, Q[r].x * cur[r][0]), fmaf(P[r].y, a, Q[r].y * cur[r][0]));
                 }
                 const float2 z = cmul(eyrow[RS * r], x);
@@ -496,6 +507,10 @@ __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
 // (indices clamped to the chunk, contributions of padding TRs zeroed).
 // Partials per chunk are combined in chunk order by the finish kernel.
 // ------------------------------------------------------------------------
+
+// Complex partials per chunk in apart: NTRAIN = 1 (m only) packs one; 3 (no
+// dm/dB1 train) keeps the four-train layout with the B1 pair left unwritten.
+__host__ __device__ constexpr int apart_planes(int ntrain) { return ntrain == 1 ? 1 : 4; }
 
 template <int NTRAIN, int CC, int NBA, typename TT, int VX>
 __global__ __launch_bounds__(256) void ystage_adj_kernel(
@@ -609,7 +624,7 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
 #pragma unroll
     for (int u = 0; u < VX; ++u) {
         const bool on = mask == nullptr || mask[j + u] != 0;
-        float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j + u;
+        float* dst = apart + (size_t)chunk * 2 * apart_planes(NTRAIN) * nv + j + u;
 #pragma unroll
         for (int p = 0; p < NTRAIN; ++p) {
             dst[(2 * p) * (size_t)nv] = on ? acc[u][p].x : 0.f;
@@ -630,15 +645,17 @@ __global__ __launch_bounds__(256) void ystage_adj_kernel(
 // ------------------------------------------------------------------------
 constexpr int NWA = 8;   // waves per block
 
-template <int NB, int R>
+template <int NB, int R, int NTR>
 __global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
     const _Float16* __restrict__ trains, const uint8_t* __restrict__ mask,
     const float2* __restrict__ eytab, const float2* __restrict__ W, float* __restrict__ apart,
     int nx, int ny, int nv, int T, int n_per_chunk)
 {
-    // R image rows per block share each TR's W (loaded once per wave and TR).
+    // R image rows per block share each TR's W (loaded once per wave and TR);
+    // NTR trains (4, or 3 without dm/dB1).
     typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-    extern __shared__ float red_s[];   // [NWA][8][nx], one row at a time
+    constexpr int NV2 = 2 * NTR;       // real values per voxel and chunk
+    extern __shared__ float red_s[];   // [NWA][NV2][nx], one row at a time
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int iy0 = blockIdx.x * R;
@@ -656,18 +673,18 @@ __global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
         jr[r] = iyr[r] * nx + xc;
     }
 
-    float acc[R][4][4][2];   // [row][train][column][re, im]
+    float acc[R][NTR][4][2];   // [row][train][column][re, im]
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < NTR; ++p)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[r][p][c][0] = acc[r][p][c][1] = 0.f;
 
     // TRs n0 + wave + NWA k, NB at a time (loads first; padding TRs read the
     // chunk's first TR with a zero weight).
     for (int nb = n0 + wave; nb < n1; nb += NWA * NB) {
-        h4 mu[NB][R][4];
+        h4 mu[NB][R][NTR];
         float4 w01[NB], w23[NB];
         float2 ey[NB][R];
         float keep[NB];
@@ -680,7 +697,7 @@ __global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
             for (int r = 0; r < R; ++r) {
                 const _Float16* t0 = trains + (size_t)n * nv + jr[r];
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
+                for (int p = 0; p < NTR; ++p)
                     mu[b][r][p] = *(const h4*)(t0 + p * plane);
                 ey[b][r] = eytab[(size_t)n * ny + iyr[r]];
             }
@@ -700,7 +717,7 @@ __global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
                 for (int c = 0; c < 4; ++c) {
                     const float2 V = cmulconj(ey[b][r], wc[c]);
 #pragma unroll
-                    for (int p = 0; p < 4; ++p) {
+                    for (int p = 0; p < NTR; ++p) {
                         const float m = (float)mu[b][r][p][c];
                         acc[r][p][c][0] = fmaf(m, V.x, acc[r][p][c][0]);
                         acc[r][p][c][1] = fmaf(m, V.y, acc[r][p][c][1]);
@@ -713,21 +730,21 @@ __global__ __launch_bounds__(NWA * 64) void ystage_adj_wide_kernel(
         if (r > 0) __syncthreads();   // the previous row's sums have been read
         if (colok) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int p = 0; p < NTR; ++p)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    *reinterpret_cast<float4*>(&red_s[((size_t)wave * 8 + 2 * p + q) * nx + x0]) =
+                    *reinterpret_cast<float4*>(&red_s[((size_t)wave * NV2 + 2 * p + q) * nx + x0]) =
                         make_float4(acc[r][p][0][q], acc[r][p][1][q], acc[r][p][2][q], acc[r][p][3][q]);
         }
         __syncthreads();
         const int iy = iy0 + r;
         if (iy < ny) {
             float* dst = apart + (size_t)chunk * 8 * nv + (size_t)iy * nx;
-            for (int o = threadIdx.x; o < 8 * nx; o += NWA * 64) {
+            for (int o = threadIdx.x; o < NV2 * nx; o += NWA * 64) {
                 const int v = o / nx, x = o % nx;
                 float sum = red_s[(size_t)v * nx + x];
 #pragma unroll
-                for (int w = 1; w < NWA; ++w) sum += red_s[((size_t)w * 8 + v) * nx + x];
+                for (int w = 1; w < NWA; ++w) sum += red_s[((size_t)w * NV2 + v) * nx + x];
                 const bool on = mask == nullptr || mask[(size_t)iy * nx + x] != 0;
                 dst[(size_t)v * nv + x] = on ? sum : 0.f;
             }
@@ -855,7 +872,7 @@ __global__ __launch_bounds__(256) void ystage_adj_coil_kernel(
         if (!ok[u]) continue;
         const int j = jr[u];
         const bool on = mask == nullptr || mask[j] != 0;
-        float* dst = apart + (size_t)chunk * 2 * NTRAIN * nv + j;
+        float* dst = apart + (size_t)chunk * 2 * apart_planes(NTRAIN) * nv + j;
 #pragma unroll
         for (int p = 0; p < NTRAIN; ++p) {
             dst[(2 * p) * (size_t)nv] = on ? acc[u][p].x : 0.f;
@@ -894,9 +911,17 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
         float A[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) A[q] = 0.f;
-        for (int ch = 0; ch < n_chunk; ++ch)
+        // The dm/dB1 pair (A[6], A[7]) is read only when B1 is reconstructed
+        // (without it the adjoint y-stage may leave that pair unwritten).
+        const bool b1 = (param_mask >> 2) & 1;
+        for (int ch = 0; ch < n_chunk; ++ch) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
+            for (int q = 0; q < 6; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
+            if (b1) {
+                A[6] += apart[((size_t)ch * 8 + 6) * nv + j];
+                A[7] += apart[((size_t)ch * 8 + 7) * nv + j];
+            }
+        }
         const bool on = mask == nullptr || mask[j] != 0;
         const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
         // Rows of parameters outside param_mask are zero.
@@ -1478,14 +1503,14 @@ hipError_t adj_launch(const Dims& d, const YPlan& p, const TT* trains, const flo
     // FP16 pairs (nx even, one coil): 512 voxels per block, twice the TRs
     // per batch, so the bytes in flight match the FP32 kernel.
     if constexpr (std::is_same<TT, _Float16>::value && CC == 1) {
-        if (NTRAIN == 4 && d.nx % 4 == 0 && d.nx <= 256 && ((uintptr_t)trains & 7) == 0 &&
+        if (NTRAIN >= 3 && d.nx % 4 == 0 && d.nx <= 256 && ((uintptr_t)trains & 7) == 0 &&
             ((uintptr_t)W & 15) == 0) {
             // 2 rows per block, 1 TR per wave in flight (measured at 224 x 224:
             // rows x TRs 1 x 1: 108 us, 2 x 1: 96, 2 x 2: 110, 3 x 1: 128 with
             // 8 chunks; the pair kernel below 107).
             dim3 grid(ceil_div(d.ny, 2), p.adj_chunks);
-            const size_t lds = (size_t)NWA * 8 * d.nx * sizeof(float);
-            ystage_adj_wide_kernel<1, 2><<<grid, NWA * 64, lds, s>>>(
+            const size_t lds = (size_t)NWA * 2 * NTRAIN * d.nx * sizeof(float);
+            ystage_adj_wide_kernel<1, 2, (NTRAIN >= 3 ? NTRAIN : 4)><<<grid, NWA * 64, lds, s>>>(
                 trains, mask, eytab, W, apart, d.nx, d.ny, d.nv, d.T, p.adj_per_chunk);
             return hipGetLastError();
         }
@@ -1589,14 +1614,17 @@ hipError_t fwd_typed(const Dims& d, const YPlan& p, int mode, const TT* trains, 
                      const float* v, const float2* coil, const uint8_t* mask, const float2* eytab,
                      float2* upart, int* nby, hipStream_t s)
 {
-    if (d.C == 1)
-        return mode == 0 ? fwd_R<0, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
-                         : fwd_R<1, 1>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
-    if (d.C <= 8)
-        return mode == 0 ? fwd_R<0, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
-                         : fwd_R<1, 8>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
-    return mode == 0 ? fwd_R<0, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s)
-                     : fwd_R<1, 16>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s);
+#define FWD_MODES(CC_)                                                                           \
+    switch (mode) {                                                                              \
+        case 0: return fwd_R<0, CC_>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s); \
+        case 1: return fwd_R<1, CC_>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s); \
+        case 3: return fwd_R<3, CC_>(d, p, trains, theta, v, coil, mask, eytab, upart, nby, s); \
+        default: return hipErrorInvalidValue;                                                   \
+    }
+    if (d.C == 1) FWD_MODES(1)
+    if (d.C <= 8) FWD_MODES(8)
+    FWD_MODES(16)
+#undef FWD_MODES
 }
 
 template <typename TT>
@@ -1609,6 +1637,12 @@ hipError_t adj_typed(const Dims& d, const YPlan& p, const TT* trains, int ntr_tr
         if (d.C <= 8) return adj_launch<4, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
         return adj_launch<4, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
     }
+    if (ntr_trains == 3) {
+        if (d.C == 1) return adj_launch<3, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
+        if (d.C <= 8) return adj_launch<3, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
+        return adj_launch<3, 16>(d, p, trains, coil, mask, eytab, W, apart, s);
+    }
+    if (ntr_trains != 1) return hipErrorInvalidValue;
     if (d.C == 1) return adj_launch<1, 1>(d, p, trains, coil, mask, eytab, W, apart, s);
     if (d.C <= 8) return adj_launch<1, 8>(d, p, trains, coil, mask, eytab, W, apart, s);
     return adj_launch<1, 16>(d, p, trains, coil, mask, eytab, W, apart, s);

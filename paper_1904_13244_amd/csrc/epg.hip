@@ -1,6 +1,8 @@
 // EPG linearisation kernel: one voxel per group of L lanes, the K states of
 // the voxel split over the group (S = Kcap / L consecutive orders per lane),
-// value and three tangent state vectors in registers.
+// value and NTAN tangent state vectors in registers (NTAN = 3: ln T1, ln T2,
+// B1; 2: ln T1, ln T2 only, for fits with B1 held fixed, whose Jacobian has
+// no B1 column; 0: value only).
 //
 // Model: gradient-spoiled transient-state sequence; per TR an instantaneous RF
 // pulse of angle B1 * alpha_n about an axis at RF phase phi_n in {0, pi},
@@ -56,7 +58,7 @@ __device__ __forceinline__ void clear_above(float (&f)[S], int base, int K)
 // outputs are left untouched); whole blocks past the list exit at once.
 // TT: element type of the stored trains (float, or _Float16 rounded to
 // nearest from the FP32 recursion).
-template <int S, int L, bool TANG, bool MASKED, bool LIST, typename TT>
+template <int S, int L, int NTAN, bool MASKED, bool LIST, typename TT>
 __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ theta,
                                                   const float2* __restrict__ seq,
                                                   TT* __restrict__ out, int nv, int T,
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
     const float taui = st.tinv * rT1;
     const float E1i = expf(-taui), R1i = -expm1f(-taui);
 
+    constexpr bool TANG = NTAN > 0, TB1 = NTAN == 3;
     float f[S], g[S], z[S];
     float f1[S], g1[S], z1[S];   // d/d ln T1
     float f2[S], g2[S], z2[S];   // d/d ln T2
@@ -102,8 +105,8 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
         if constexpr (TANG) {
             f1[i] = g1[i] = z1[i] = 0.f;
             f2[i] = g2[i] = z2[i] = 0.f;
-            f3[i] = g3[i] = z3[i] = 0.f;
         }
+        if constexpr (TB1) f3[i] = g3[i] = z3[i] = 0.f;
     }
     // Ideal inversion of the equilibrium Z_0 = 1, then relaxation over t_inv.
     if (lead) {
@@ -133,13 +136,15 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
             if constexpr (TANG) {
                 const float rp1 = fmaf(c2, f1[0], fmaf(s2, g1[0], -sgsa * z1[0]));
                 const float rp2 = fmaf(c2, f2[0], fmaf(s2, g2[0], -sgsa * z2[0]));
-                const float drp = fmaf(-0.5f * sa, f[0] - g[0], -sg * ca * z[0]);
-                const float rp3 = fmaf(c2, f3[0], fmaf(s2, g3[0], fmaf(alpha, drp, -sgsa * z3[0])));
                 if (store) {
                     o0[plane + (size_t)n * nv] = (TT)(ke * rp1);
                     o0[2 * plane + (size_t)n * nv] = (TT)(ke * fmaf(tau2e, rp, rp2));
-                    o0[3 * plane + (size_t)n * nv] = (TT)(ke * rp3);
                 }
+            }
+            if constexpr (TB1) {
+                const float drp = fmaf(-0.5f * sa, f[0] - g[0], -sg * ca * z[0]);
+                const float rp3 = fmaf(c2, f3[0], fmaf(s2, g3[0], fmaf(alpha, drp, -sgsa * z3[0])));
+                if (store) o0[3 * plane + (size_t)n * nv] = (TT)(ke * rp3);
             }
         }
 
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
                     const float c = fmaf(D, w2, G * z2[i]);
                     f2[i] = a; g2[i] = b; z2[i] = c;
                 }
-                {   // B1: the RF coefficients depend on a = B1 alpha
+                if constexpr (TB1) {   // B1: the RF coefficients depend on a = B1 alpha
                     const float w3 = f3[i] - g3[i];
                     const float t3 = fmaf(dA, w, -dC * z[i]);
                     const float Cz3 = Cc * z3[i];
@@ -203,17 +208,19 @@ __global__ __launch_bounds__(256) void epg_kernel(const float* __restrict__ thet
         if constexpr (TANG) {
             shift_orders<S, L>(f1, g1, lead, last);
             shift_orders<S, L>(f2, g2, lead, last);
-            shift_orders<S, L>(f3, g3, lead, last);
             if constexpr (MASKED) {
                 clear_above<S>(f1, base, K);
                 clear_above<S>(f2, base, K);
-                clear_above<S>(f3, base, K);
             }
+        }
+        if constexpr (TB1) {
+            shift_orders<S, L>(f3, g3, lead, last);
+            if constexpr (MASKED) clear_above<S>(f3, base, K);
         }
     }
 }
 
-template <int S, int L, bool TANG, bool LIST, typename TT>
+template <int S, int L, int NTAN, bool LIST, typename TT>
 hipError_t launch_sl(const Dims& d, SeqTimes st, const float* theta, const float2* seq, TT* out,
                      const int* idx, const int* count, hipStream_t s)
 {
@@ -221,20 +228,20 @@ hipError_t launch_sl(const Dims& d, SeqTimes st, const float* theta, const float
     const int block = 256;
     const int grid = (int)((threads + block - 1) / block);
     if (d.K == S * L)
-        epg_kernel<S, L, TANG, false, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
+        epg_kernel<S, L, NTAN, false, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
                                                                        st, idx, count);
     else
-        epg_kernel<S, L, TANG, true, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
+        epg_kernel<S, L, NTAN, true, LIST, TT><<<grid, block, 0, s>>>(theta, seq, out, d.nv, d.T, d.K,
                                                                       st, idx, count);
     return hipGetLastError();
 }
 
-template <bool TANG, bool LIST, typename TT>
+template <int NTAN, bool LIST, typename TT>
 hipError_t launch_any(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
                       TT* out, int lanes, const int* idx, const int* count, hipStream_t s)
 {
     const int K = d.K;
-#define SL(S_, L_) launch_sl<S_, L_, TANG, LIST, TT>(d, st, theta, seq, out, idx, count, s)
+#define SL(S_, L_) launch_sl<S_, L_, NTAN, LIST, TT>(d, st, theta, seq, out, idx, count, s)
     if (K <= 8) {
         if (lanes == 2) return SL(4, 2);
         return SL(8, 1);
@@ -292,32 +299,39 @@ __global__ void half_to_float_kernel(const _Float16* __restrict__ in, float* __r
 
 }  // namespace
 
+template <bool LIST, typename TT>
+hipError_t launch_ntan(const Dims& d, SeqTimes st, const float* theta, const float2* seq, TT* out,
+                       int ntan, int lanes, const int* idx, const int* count, hipStream_t s)
+{
+    switch (ntan) {
+        case 0: return launch_any<0, LIST>(d, st, theta, seq, out, lanes, idx, count, s);
+        case 2: return launch_any<2, LIST>(d, st, theta, seq, out, lanes, idx, count, s);
+        case 3: return launch_any<3, LIST>(d, st, theta, seq, out, lanes, idx, count, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <bool LIST>
 hipError_t launch_typed(const Dims& d, SeqTimes st, const float* theta, const float2* seq, void* out,
-                        bool tangents, int lanes, bool f16, const int* idx, const int* count,
+                        int ntan, int lanes, bool f16, const int* idx, const int* count,
                         hipStream_t s)
 {
-    if (f16) {
-        _Float16* o = static_cast<_Float16*>(out);
-        return tangents ? launch_any<true, LIST>(d, st, theta, seq, o, lanes, idx, count, s)
-                        : launch_any<false, LIST>(d, st, theta, seq, o, lanes, idx, count, s);
-    }
-    float* o = static_cast<float*>(out);
-    return tangents ? launch_any<true, LIST>(d, st, theta, seq, o, lanes, idx, count, s)
-                    : launch_any<false, LIST>(d, st, theta, seq, o, lanes, idx, count, s);
+    if (f16)
+        return launch_ntan<LIST>(d, st, theta, seq, static_cast<_Float16*>(out), ntan, lanes, idx, count, s);
+    return launch_ntan<LIST>(d, st, theta, seq, static_cast<float*>(out), ntan, lanes, idx, count, s);
 }
 
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      void* out, bool tangents, int lanes, bool f16, hipStream_t s)
+                      void* out, int ntan, int lanes, bool f16, hipStream_t s)
 {
-    return launch_typed<false>(d, st, theta, seq, out, tangents, lanes, f16, nullptr, nullptr, s);
+    return launch_typed<false>(d, st, theta, seq, out, ntan, lanes, f16, nullptr, nullptr, s);
 }
 
 hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                           void* out, bool tangents, int lanes, bool f16, const int* idx,
+                           void* out, int ntan, int lanes, bool f16, const int* idx,
                            const int* count, hipStream_t s)
 {
-    return launch_typed<true>(d, st, theta, seq, out, tangents, lanes, f16, idx, count, s);
+    return launch_typed<true>(d, st, theta, seq, out, ntan, lanes, f16, idx, count, s);
 }
 
 hipError_t launch_trains_to_f32(const void* in, bool f16, float* out, size_t n, hipStream_t s)

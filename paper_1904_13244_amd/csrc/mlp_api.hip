@@ -198,9 +198,10 @@ namespace mrstat {
 // dimension ld_theta, written as [rows/T][T][ld_out] (all four trains, or the
 // m train only) in chunks of the network's batch size.
 hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n,
-                            void* out, int64_t ld_out, bool all_trains, bool f16, uint16_t* hbuf,
+                            void* out, int64_t ld_out, int n_trains, bool f16, uint16_t* hbuf,
                             hipStream_t s)
 {
+    if (n_trains < 1 || n_trains > 4) return hipErrorInvalidValue;
     const int W = net->width, B = net->B, T = net->T, L = net->depth;
     if (infer_fused_supported(W, L)) {
         InferArgs a;
@@ -223,7 +224,7 @@ hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta
         a.bout = net->w32() + net->off_bo + (size_t)4 * T;
         a.head_scale = net->dscale();
         a.T = T;
-        a.m_out = all_trains ? 4 * T : T;
+        a.m_out = n_trains * T;
         a.out = out;
         a.ld_out = ld_out;
         a.plane = (int64_t)T * ld_out;
@@ -246,7 +247,7 @@ hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta
         g.lda = W;
         g.B = net->H(L - 1);
         g.ldb = B;
-        g.M = all_trains ? 4 * T : T;
+        g.M = n_trains * T;
         g.N = nc;
         g.K = W;
         g.ldo = ld_out;
@@ -450,7 +451,7 @@ mrstat_status mrstat_mlp_predict(mrstat_mlp net, const float* d_theta, int64_t l
     if (!net || !d_theta || !d_out || n < 1) return MRSTAT_ERR_ARG;
     if (!net->ws) return mfail(net, MRSTAT_ERR_WORKSPACE, "network has no workspace");
     if (ld_theta < n) return mfail(net, MRSTAT_ERR_ARG, "leading dimension below n");
-    MTRY(mlp_infer_trains(net, d_theta, ld_theta, n, d_out, n, true, false, nullptr, (hipStream_t)stream));
+    MTRY(mlp_infer_trains(net, d_theta, ld_theta, n, d_out, n, 4, false, nullptr, (hipStream_t)stream));
     return MRSTAT_OK;
 }
 

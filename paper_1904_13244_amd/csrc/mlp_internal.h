@@ -86,12 +86,12 @@ hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 
 // Surrogate inference for the context (mlp_api.hip): trains of n voxels whose
 // theta rows (ln T1, ln T2, B1) have leading dimension ld_theta, into
-// out[p][n_tr][ld_out] (float, or _Float16 when f16) for p < 4 (all_trains)
-// or p = 0 only.
+// out[p][n_tr][ld_out] (float, or _Float16 when f16) for p < n_trains
+// (4: m and the three derivatives; 3: without dm/dB1; 1: m only).
 // hbuf (optional, n x 256 BF16): for width 256, the hidden layers and the
 // output layer run as two kernels through it.
 hipError_t mlp_infer_trains(mrstat_mlp net, const float* theta, int64_t ld_theta, int n, void* out,
-                            int64_t ld_out, bool all_trains, bool f16, uint16_t* hbuf, hipStream_t s);
+                            int64_t ld_out, int n_trains, bool f16, uint16_t* hbuf, hipStream_t s);
 const float* mlp_box_lo(mrstat_mlp net);
 const float* mlp_box_hi(mrstat_mlp net);
 int mlp_n_tr(mrstat_mlp net);

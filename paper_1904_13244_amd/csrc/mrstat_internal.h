@@ -46,16 +46,17 @@ YPlan make_yplan(const Dims& d);
 // All launchers enqueue on `s` and return the launch status.
 
 // EPG linearisation. theta [5][nv]; seq[n] = (flip angle [rad], RF sign +-1);
-// out: tangents ? [4][T][nv] : [T][nv] (imaginary parts of m, dm/dlnT1,
-// dm/dlnT2, dm/dB1), float or (f16) _Float16. lanes = lanes per voxel
+// out: planes [T][nv] of the imaginary parts of m, dm/dlnT1, dm/dlnT2, dm/dB1
+// in a [4][T][nv] buffer, the first 1 + ntan of them written (ntan = 3, 2 or
+// 0 tangent trains), float or (f16) _Float16. lanes = lanes per voxel
 // (0 = automatic).
 hipError_t launch_epg(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                      void* out, bool tangents, int lanes, bool f16, hipStream_t s);
+                      void* out, int ntan, int lanes, bool f16, hipStream_t s);
 
 // EPG on the voxels idx[0 .. *count) only (same output layout; other voxels
 // untouched). The grid covers nv voxels; blocks past the list exit at once.
 hipError_t launch_epg_list(const Dims& d, SeqTimes st, const float* theta, const float2* seq,
-                           void* out, bool tangents, int lanes, bool f16, const int* idx,
+                           void* out, int ntan, int lanes, bool f16, const int* idx,
                            const int* count, hipStream_t s);
 
 // n stored train elements (float or _Float16) to float.
@@ -68,8 +69,9 @@ hipError_t launch_box_compact(const Dims& d, const float* theta, const float* lo
 
 // Forward y-stage: U[c][n][ix] = sum over rows iy of Ey[n][iy] * coil_c[j] *
 // x[n][j], with x = i rho m (mode 0) or x = i (rho sum_q v_q dm_q +
-// (v3 + i v4) m) (mode 1, the J v direction). upart holds nby row-block
-// partials when nby > 1 and is summed into its first block.
+// (v3 + i v4) m) (mode 1, the J v direction; mode 3: the same with v2 taken
+// as 0 and the dm/dB1 train not read). upart holds nby row-block partials
+// when nby > 1 and is summed into its first block.
 hipError_t launch_ystage_fwd(const Dims& d, const YPlan& p, int mode, const void* trains, bool f16,
                              const float* theta, const float* v, const float2* coil,
                              const uint8_t* mask, const float2* eytab, float2* upart, int* nby,
@@ -103,13 +105,15 @@ int xgemm_direct_blocks(const Dims& d);
 
 // Adjoint y-stage: partial sums over TR chunks of
 // A_p[j] = sum_n mu_p[n][j] conj(Ey[n][iy]) sum_c conj(coil_c[j]) W_c[n][ix]
-// (p = 0..3 for m and the three tangents; ntr_trains = 4 or 1).
+// (p < ntr_trains: 4 = m and the three tangents, 3 = without dm/dB1, whose
+// pair in the four-train chunk layout is then left unwritten, 1 = m only).
 hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, bool f16, int ntr_trains,
                              const float2* coil, const uint8_t* mask, const float2* eytab,
                              const float2* W, float* apart, hipStream_t s);
 
 // g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order); rows of
-// parameters outside param_mask (and masked voxels) are zero.
+// parameters outside param_mask (and masked voxels) are zero, and the dm/dB1
+// partials are read only when B1 is in param_mask.
 // With dir non-null, also the CG curvature partials dir . g and dir . dir
 // (FP64, ceil(nv / 256) pairs: part[b] and part[nblocks + b]).
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,

@@ -88,6 +88,11 @@ def _config1():
 
 CASES = {"config1": _config1, "ragged": _ragged, "coils_mask": _coils, "even_ragged": _even_ragged,
          "wide_mask": _wide_mask, "wide_max": _wide_max}
+# Cases with more real data than unknowns (T1, T2, rho per voxel): there one
+# GN step with B1 held fixed (trains without dm/dB1: the wide, general and
+# coil layouts of the forward y-stage in its three-train mode, and the
+# three-train adjoint) is compared with the oracle's.
+GN_CASES = ("config1", "ragged", "coils_mask")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -132,6 +137,14 @@ def test_f16_trains_and_products(torch_gpu, oracle_lib, name):
     e_off = _rel(jv_off, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
     print(f"  jv with theta at a 4-byte offset {e_off:.2e}", flush=True)
     assert e_off <= 1e-3
+    if name in GN_CASES:
+        t_ora, _ = oracle_lib.gn_step(prob, th0, s, n_cg=4, param_mask=0b11011, lo=I.GN_LO,
+                                      hi=I.GN_HI, coil=coil, mask=mask)
+        t_gpu = _dev(torch, th0, torch.float32)
+        rep = ctx.gn_step(t_gpu, _dev(torch, s, torch.complex64), 4, 0b11011, I.GN_LO, I.GN_HI)
+        e_gn = _rel(t_gpu.cpu().numpy(), t_ora)
+        print(f"  gn step (B1 fixed) theta {e_gn:.2e}, accepted {rep.accepted}", flush=True)
+        assert e_gn <= 1e-3
     # Switching back restores the FP32 path exactly (within its own bar).
     ctx.set_train_precision(B.TRAINS_FP32)
     got32 = ctx.simulate(thd).cpu().numpy().astype(np.float64)

@@ -178,12 +178,14 @@ mrstat_status mrstat_residual(mrstat_ctx ctx, const float *d_theta, int32_t reus
                               const void *d_data, void *d_r, double *h_f, mrstat_stream stream);
 
 /* d_out = J v for v float32 [5][Nv]; complex64 [n_coils][n_tr][n_read].
- * All five parameter rows are used. */
+ * All five parameter rows are used (a reused linearisation without the
+ * dm/dB1 train, left by a B1-fixed mrstat_gn_step, is redone first). */
 mrstat_status mrstat_jv(mrstat_ctx ctx, const float *d_theta, int32_t reuse_linearization,
                         const float *d_v, void *d_out, mrstat_stream stream);
 
 /* d_out = Re(J^H w) for w complex64 [n_coils][n_tr][n_read]; float32 [5][Nv]
- * (Algorithm 4: all N_p partial derivatives of a voxel together). */
+ * (Algorithm 4: all N_p partial derivatives of a voxel together; a reused
+ * three-train linearisation is redone first, as for mrstat_jv). */
 mrstat_status mrstat_jhw(mrstat_ctx ctx, const float *d_theta, int32_t reuse_linearization,
                          const void *d_w, float *d_out, mrstat_stream stream);
 
@@ -193,7 +195,11 @@ mrstat_status mrstat_jhw(mrstat_ctx ctx, const float *d_theta, int32_t reuse_lin
  * theta_t = P(theta + t p), P the box projection of (ln T1, ln T2, B1),
  * accepting the first t with f(theta_t) <= f + c1 g^T (theta_t - theta).
  * d_theta is updated in place only when a trial is accepted. Inactive
- * parameters (param_mask) and masked voxels never change. Synchronises. */
+ * parameters (param_mask) and masked voxels never change. With B1 (bit 2)
+ * outside param_mask the Jacobian has no B1 column, and the step's
+ * linearisation holds no dm/dB1 train (neither simulated nor streamed); a
+ * later mrstat_jv / mrstat_jhw that reuses it simulates the trains again at
+ * the same theta. Synchronises. */
 mrstat_status mrstat_gn_step(mrstat_ctx ctx, float *d_theta, const void *d_data,
                              const mrstat_gn_opts *opts, mrstat_gn_report *h_rep,
                              mrstat_stream stream);
@@ -216,13 +222,13 @@ typedef enum {
     MRSTAT_K_EPG = 0,        /* EPG with tangents (linearisation) */
     MRSTAT_K_EPG_VALUE = 1,  /* EPG value only (line-search trials) */
     MRSTAT_K_YFWD_SIG = 2,   /* forward y-stage of the signal (m train only) */
-    MRSTAT_K_YFWD_JV = 3,    /* forward y-stage of J v (all four trains) */
+    MRSTAT_K_YFWD_JV = 3,    /* forward y-stage of J v (four trains, or three with B1 fixed) */
     MRSTAT_K_XFWD = 4,       /* forward x-stage GEMM (+ residual epilogue) */
     MRSTAT_K_XADJ = 5,       /* adjoint x-stage GEMM */
     MRSTAT_K_YADJ = 6,       /* adjoint y-stage (train streaming) */
     MRSTAT_K_FINISH = 7,     /* gradient assembly from the adjoint partials */
     MRSTAT_K_VECTOR = 8,     /* CG / line-search / CGLS vector kernels and reductions */
-    MRSTAT_K_SURR = 9,       /* surrogate inference of all four trains (+ box test) */
+    MRSTAT_K_SURR = 9,       /* surrogate inference of the linearisation's trains (+ box test) */
     MRSTAT_K_SURR_VALUE = 10,/* surrogate inference of the m train (line-search trials) */
     MRSTAT_K_COUNT = 11
 } mrstat_kernel_kind;

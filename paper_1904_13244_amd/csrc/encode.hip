@@ -908,22 +908,38 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     double cd = 0.0, dd = 0.0;
     if (j < nv) {
+        const bool on = mask == nullptr || mask[j] != 0;
+        const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
         float A[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) A[q] = 0.f;
         // The dm/dB1 pair (A[6], A[7]) is read only when B1 is reconstructed
         // (without it the adjoint y-stage may leave that pair unwritten).
+        // Chunks go three at a time with all their loads issued first (one
+        // wave per 64 voxels is all the kernel has); sums stay in chunk order.
         const bool b1 = (param_mask >> 2) & 1;
-        for (int ch = 0; ch < n_chunk; ++ch) {
+        auto load = [&](int ch, float (&t)[8]) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) A[q] += apart[((size_t)ch * 8 + q) * nv + j];
-            if (b1) {
-                A[6] += apart[((size_t)ch * 8 + 6) * nv + j];
-                A[7] += apart[((size_t)ch * 8 + 7) * nv + j];
-            }
+            for (int q = 0; q < 6; ++q) t[q] = apart[((size_t)ch * 8 + q) * nv + j];
+            t[6] = b1 ? apart[((size_t)ch * 8 + 6) * nv + j] : 0.f;
+            t[7] = b1 ? apart[((size_t)ch * 8 + 7) * nv + j] : 0.f;
+        };
+        int ch = 0;
+        for (; ch + 3 <= n_chunk; ch += 3) {
+            float t[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) load(ch + c, t[c]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) A[q] += t[c][q];
         }
-        const bool on = mask == nullptr || mask[j] != 0;
-        const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
+        for (; ch < n_chunk; ++ch) {
+            float t[8];
+            load(ch, t);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) A[q] += t[q];
+        }
         // Rows of parameters outside param_mask are zero.
         float gq[5];
 #pragma unroll

@@ -25,6 +25,7 @@ __device__ __forceinline__ int done_slot(int par) { return par ? S_DONE1 : S_DON
 namespace {
 
 constexpr int RB = 256;   // threads per reduction block
+constexpr int PF = 2;     // vector elements per thread loaded ahead in the CG kernels
 
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
@@ -151,10 +152,24 @@ __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ d
 {
     __shared__ double sh[RB / 64];
     __shared__ double bc[2];
+    // This thread's first PF elements and the scalars are loaded before the
+    // reduction of the partials (they do not depend on alpha).
+    const size_t i0 = (size_t)blockIdx.x * RB + threadIdx.x, stride = (size_t)gridDim.x * RB;
+    float rp[PF], dp[PF], sp[PF], qp[PF];
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const size_t i = i0 + e * stride;
+        const bool ok = i < n;
+        rp[e] = ok ? res[i] : 0.f;
+        dp[e] = ok ? dir[i] : 0.f;
+        sp[e] = ok ? step[i] : 0.f;
+        qp[e] = ok ? q[i] : 0.f;
+    }
+    const double done = sc[done_slot(par)], rr = sc[rr_slot(par)];
     double kappa, dd;
     reduce_pair(curv, nblk, sh, bc, kappa, dd);
-    const bool upd = sc[done_slot(par)] == 0.0 && !(kappa <= 1e-30 * dd);
-    const double alpha = upd ? sc[rr_slot(par)] / kappa : 0.0;
+    const bool upd = done == 0.0 && !(kappa <= 1e-30 * dd);
+    const double alpha = upd ? rr / kappa : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc[S_KAPPA] = kappa;
         sc[S_DD] = dd;
@@ -163,7 +178,19 @@ __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ d
     }
     const float al = (float)alpha;
     double v = 0.0;
-    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const size_t i = i0 + e * stride;
+        if (i >= n) break;
+        float r = rp[e];
+        if (upd) {
+            step[i] = fmaf(al, dp[e], sp[e]);
+            r = fmaf(-al, qp[e], r);
+            res[i] = r;
+        }
+        v += (double)r * (double)r;
+    }
+    for (size_t i = i0 + PF * stride; i < n; i += stride) {
         float r = res[i];
         if (upd) {
             step[i] = fmaf(al, dir[i], step[i]);
@@ -186,14 +213,24 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
 {
     __shared__ double sh[RB / 64];
     __shared__ double bc[1];
+    // First PF elements and the scalars ahead of the reduction (as above).
+    const size_t i0 = (size_t)blockIdx.x * RB + threadIdx.x, stride = (size_t)gridDim.x * RB;
+    float rp[PF], dp[PF];
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const size_t i = i0 + e * stride;
+        const bool ok = i < n;
+        rp[e] = ok ? res[i] : 0.f;
+        dp[e] = ok ? dir[i] : 0.f;
+    }
+    const bool upd = sc[S_UPD] != 0.0;
+    const double rr = sc[rr_slot(par)];
     double v = 0.0;
     for (int i = threadIdx.x; i < nblk; i += RB) v += part[i];
     v = block_sum(v, sh);
     if (threadIdx.x == 0) bc[0] = v;
     __syncthreads();
     v = bc[0];
-    const bool upd = sc[S_UPD] != 0.0;
-    const double rr = sc[rr_slot(par)];
     const double beta = upd ? v / rr : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (upd) {
@@ -206,8 +243,12 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
     }
     if (!upd) return;
     const float b = (float)beta;
-    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB)
-        dir[i] = fmaf(b, dir[i], res[i]);
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const size_t i = i0 + e * stride;
+        if (i < n) dir[i] = fmaf(b, dp[e], rp[e]);
+    }
+    for (size_t i = i0 + PF * stride; i < n; i += stride) dir[i] = fmaf(b, dir[i], res[i]);
 }
 
 // trial = P(theta + t step): active ln T1, ln T2, B1 clamped to the box.

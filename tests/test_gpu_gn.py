@@ -71,6 +71,30 @@ def test_gn_iterations_match_oracle_config1(torch_gpu, oracle_lib, param_mask):
     ctx.close()
 
 
+def test_gn_step_coils_mask_matches_oracle(torch_gpu, oracle_lib):
+    """One B1-fixed GN step with 4 coils and a voxel mask (FP32 trains: the
+    coil y-stages in their three-train forms) against the oracle's."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    rng = np.random.default_rng(6)
+    prob = I.make_problem(24, 20, 60, 48, 16, n_coils=4, flip_deg=I.flips_sin2_sweeps(60, 20))
+    th = I.iid_maps(prob.nv, seed=5, b1=rng.uniform(0.8, 1.2, prob.nv))
+    coil = I.coil_maps(24, 20, 4)
+    mask = (rng.uniform(size=prob.nv) > 0.2).astype(np.uint8)
+    d = oracle_lib.signal(prob, th, oracle_lib.epg(prob, th, tangents=False), coil=coil, mask=mask)
+    th0 = _start(th)
+    t_ora, rep_o = oracle_lib.gn_step(prob, th0, d, n_cg=6, param_mask=0b11011, lo=I.GN_LO, hi=I.GN_HI,
+                                      coil=coil, mask=mask)
+    ctx = Context(prob, coil=_dev(torch, coil, torch.complex64), mask=_dev(torch, mask, torch.uint8))
+    t_gpu = _dev(torch, th0, torch.float32)
+    rep_g = ctx.gn_step(t_gpu, _dev(torch, d, torch.complex64), 6, 0b11011, I.GN_LO, I.GN_HI)
+    e = _rel(t_gpu.cpu().numpy().astype(np.float64), t_ora)
+    print(f"  coils + mask gn step: theta rel err {e:.2e}, t {rep_g.t}/{rep_o.t}", flush=True)
+    assert rep_g.accepted == rep_o.accepted and rep_g.t == rep_o.t
+    assert e <= 1e-4
+    ctx.close()
+
+
 def test_rho_init_matches_oracle(torch_gpu, oracle_lib):
     torch = torch_gpu
     from paper_1904_13244_amd.binding import Context

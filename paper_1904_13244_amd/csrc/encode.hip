@@ -488,7 +488,18 @@ __global__ void usum_kernel(float2* __restrict__ upart, int nby, size_t count)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     float2 s = upart[i];
-    for (int b = 1; b < nby; ++b) {
+    int b = 1;
+    for (; b + 4 <= nby; b += 4) {   // four partials' loads in flight, sums in block order
+        float2 t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = upart[(size_t)(b + k) * count + i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s.x += t[k].x;
+            s.y += t[k].y;
+        }
+    }
+    for (; b < nby; ++b) {
         const float2 t = upart[(size_t)b * count + i];
         s.x += t.x;
         s.y += t.y;
@@ -887,7 +898,15 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     float2 s = W[i];
-    for (int b = 1; b < nsplit; ++b) {
+    int b = 1;
+    for (; b + 2 <= nsplit; b += 2) {   // two partials' loads in flight, sums in split order
+        const float2 t0 = W[(size_t)b * count + i], t1 = W[(size_t)(b + 1) * count + i];
+        s.x += t0.x;
+        s.y += t0.y;
+        s.x += t1.x;
+        s.y += t1.y;
+    }
+    for (; b < nsplit; ++b) {
         const float2 t = W[(size_t)b * count + i];
         s.x += t.x;
         s.y += t.y;

@@ -40,9 +40,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Jv+Jᴴw pairs/s at 224², 1120 TRs: surrogate+split-BF16 vs plain FP32"
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0    # dense
-FP32_VALU_PEAK_TFLOPS = 157.3     # published vector peak (packed); see the design doc
+FP32_VALU_PEAK_TFLOPS = 157.3     # published vector peak (packed FP32; 78.6 unpacked)
 
-# Algorithmic work per launch (the design doc derives each figure).
+# Algorithmic work per launch, counted from the method's arithmetic.
 EPG_FLOP_PER_STATE_TR = {4: 67,   # value 13 + ln T1 15 + ln T2 17 + B1 22 (real form)
                          3: 45}   # B1 held fixed: no B1 tangent
 # Kernel kinds traced in the timed region (the roofline candidates).

@@ -603,6 +603,11 @@ void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
     }
     const int n_tiles = (a.n + NVT - 1) / NVT;
     const bool vec_ok = (a.ld_out % 4) == 0;
+    // FP16 output of whole tiles goes through a per-wave LDS transpose so
+    // that every store instruction writes 64 contiguous bytes of each of 16
+    // rows (instead of 32), in the half of Hf that no wave reads this tile.
+    const bool vec8_ok = F16 && (a.ld_out % 8) == 0 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0;
+    constexpr int SROW = NVT + 8;   // staging row pitch (halves), padded against bank conflicts
     // Tile loads: 32 fragments of 64 x 16 bytes; wave w loads fragments
     // w, w + 8, w + 16, w + 24, each lane the piece it will be read from.
     // (Four named registers: an array here was placed in LDS by the compiler.)
@@ -633,6 +638,8 @@ void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
     using OT = typename std::conditional<F16, _Float16, float>::type;
     for (int buf = 0; t < n_tiles; t += gridDim.y, buf ^= 1) {
         const bool more = t + (int)gridDim.y < n_tiles;
+        const bool stage = vec8_ok && t * NVT + NVT <= a.n;   // uniform per workgroup
+        uint2 pk[4][MW];                                      // FP16 results of the tile (staged path)
         if (more) gload(t + gridDim.y);
         // One 16-voxel tile at a time (accumulators for MW output tiles).
 #pragma unroll
@@ -650,6 +657,17 @@ void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
             }
             // D: lane holds voxels 4 (lane / 16) + i of the tile, output row lr.
             const int jv = t * NVT + vt * 16 + 4 * (lane >> 4);
+            if (stage) {
+#pragma unroll
+                for (int m = 0; m < MW; ++m) {
+                    const h4v hv = h4v{(_Float16)((acc[m][0] + bias[m]) * scl[m]),
+                                       (_Float16)((acc[m][1] + bias[m]) * scl[m]),
+                                       (_Float16)((acc[m][2] + bias[m]) * scl[m]),
+                                       (_Float16)((acc[m][3] + bias[m]) * scl[m])};
+                    pk[vt][m] = __builtin_bit_cast(uint2, hv);
+                }
+                continue;
+            }
 #pragma unroll
             for (int m = 0; m < MW; ++m) {
                 const int o = orow[m];
@@ -671,6 +689,34 @@ void mlp_out_kernel(InferArgs a, const uint16_t* __restrict__ H)
                     }
                 }
             }
+        }
+        if (stage) {
+            // Wave-private staging rows [16][SROW] in Hf[buf ^ 1]; LDS operations
+            // of one wave complete in order, the fences keep the compiler from
+            // moving them.
+            _Float16* S = reinterpret_cast<_Float16*>(&Hf[buf ^ 1][0][0][0]) + wave * 16 * SROW;
+            const int r = lane >> 2, c = lane & 3;
+#pragma unroll
+            for (int m = 0; m < MW; ++m) {
+#pragma unroll
+                for (int vt = 0; vt < 4; ++vt)
+                    *reinterpret_cast<uint2*>(S + lr * SROW + vt * 16 + 4 * (lane >> 4)) = pk[vt][m];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const uint4 v0 = *reinterpret_cast<const uint4*>(S + r * SROW + 8 * c);
+                const uint4 v1 = *reinterpret_cast<const uint4*>(S + r * SROW + 32 + 8 * c);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const int o = o0 + 16 * m + r;
+                if (o < a.m_out) {
+                    const int p = o / a.T, nt = o - p * a.T;
+                    _Float16* dst = static_cast<_Float16*>(a.out) + (size_t)p * a.plane + (size_t)nt * a.ld_out +
+                                    (size_t)t * NVT;
+                    *reinterpret_cast<uint4*>(dst + 8 * c) = v0;
+                    *reinterpret_cast<uint4*>(dst + 32 + 8 * c) = v1;
+                }
+            }
+            if (more) __syncthreads();   // every wave is done with Hf[buf ^ 1] before it is refilled
         }
         if (more) sstore(buf ^ 1);
         __syncthreads();

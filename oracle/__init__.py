@@ -58,6 +58,24 @@ class _GnReport(C.Structure):
                 ("cg_iters", C.c_int), ("ls_trials", C.c_int), ("accepted", C.c_int)]
 
 
+class _TrOpts(C.Structure):
+    _fields_ = [("n_cg", C.c_int), ("param_mask", C.c_int), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("eta", C.c_double), ("delta_max", C.c_double)]
+
+
+class _TrReport(C.Structure):
+    _fields_ = [("f0", C.c_double), ("f1", C.c_double), ("gnorm", C.c_double),
+                ("step_norm", C.c_double), ("rho", C.c_double), ("pred", C.c_double),
+                ("delta_in", C.c_double), ("delta_out", C.c_double), ("cg_iters", C.c_int),
+                ("exit_kind", C.c_int), ("accepted", C.c_int), ("n_reflected", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+TR_ITERS, TR_BOUNDARY, TR_CURVATURE, TR_ZERO = 0, 1, 2, 3
+
+
 @dataclass
 class GnReport:
     f0: float
@@ -94,6 +112,12 @@ def lib():
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         L.oracle_rho_init.argtypes = [P(_Problem), vp, vp, vp, vp, C.c_int]
+        L.oracle_steihaug_dense.argtypes = [C.c_int, vp, vp, C.c_double, C.c_int, vp, P(C.c_int)]
+        L.oracle_steihaug_dense.restype = C.c_int
+        L.oracle_reflect.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_reflect.restype = C.c_double
+        L.oracle_tr_step.argtypes = [P(_Problem), vp, vp, vp, vp, P(_TrOpts), P(C.c_double),
+                                     P(_TrReport)]
         _lib = L
     return _lib
 
@@ -266,3 +290,34 @@ def rho_init(prob, theta, data, n_iter=20, coil=None, mask=None):
     lib().oracle_rho_init(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), d.ctypes.data,
                           n_iter)
     return th
+
+
+def steihaug_dense(B, g, delta, n_cg):
+    """Steihaug truncated CG on a dense symmetric B; returns (p, exit kind, iters)."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    n = B.shape[0]
+    g = _f64(g, (n,))
+    p = np.zeros(n)
+    it = C.c_int(0)
+    kind = lib().oracle_steihaug_dense(n, B.ctypes.data, g.ctypes.data, float(delta), int(n_cg),
+                                       p.ctypes.data, C.byref(it))
+    return p, int(kind), int(it.value)
+
+
+def reflect(x, lo, hi):
+    return float(lib().oracle_reflect(float(x), float(lo), float(hi)))
+
+
+def tr_step(prob, theta, data, delta, n_cg, param_mask, lo, hi, eta=0.1, delta_max=1e3,
+            coil=None, mask=None):
+    """One trust-region inexact GN iteration; returns (theta_new, delta_new, report dict)."""
+    b = _Bound(prob)
+    th = _f64(theta, (5, b.nv)).copy()
+    d = _c128(data, _dshape(prob))
+    cl, mk = _coil(b, coil), _mask(b, mask)
+    o = _TrOpts(n_cg, param_mask, (C.c_double * 3)(*lo), (C.c_double * 3)(*hi), eta, delta_max)
+    dl = C.c_double(delta)
+    rep = _TrReport()
+    lib().oracle_tr_step(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), d.ctypes.data,
+                         C.byref(o), C.byref(dl), C.byref(rep))
+    return th, float(dl.value), rep.as_dict()

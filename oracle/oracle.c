@@ -21,6 +21,13 @@
  *   oracle_gn_step        dense solve of the normal equations on a tiny case;
  *                         noiseless exact recovery of the ground truth.
  *   oracle_rho_init       closed-form least-squares solution (uniform maps).
+ *   oracle_steihaug_dense Galerkin solutions of successive Krylov spaces and
+ *                         their monotone norms (boundary exit); the boundary
+ *                         Cauchy point on an indefinite model (curvature exit).
+ *   oracle_reflect        a particle bouncing between the walls, stepped in
+ *                         small increments.
+ *   oracle_tr_step        the ratio test from an explicit Jacobian; a model
+ *                         that is exact (rho fitted alone) gives rho = 1.
  */
 #include "oracle.h"
 
@@ -589,6 +596,215 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
         t *= 0.5;
     }
     free(tr); free(r); free(y); free(g); free(step); free(res); free(dir); free(q); free(trial);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trust-region inexact Gauss-Newton (Methods, Reconstructions): the model   */
+/* m(p) = f + g'p + 0.5 p' Re(J^H J) p is minimised approximately inside     */
+/* ||p|| <= delta by Steihaug's truncated CG (Nocedal & Wright, Algorithm    */
+/* 7.2); bounds are kept by reflecting the trial point at the box walls      */
+/* (the reflective path of Coleman & Li); the radius follows the ratio of    */
+/* actual to predicted decrease (Nocedal & Wright, Algorithm 4.1).           */
+/* ------------------------------------------------------------------------ */
+
+typedef void (*matvec_fn)(void *ctx, const double *x, double *y);
+
+/* tau >= 0 (or the other root) with ||z + tau d|| = delta. */
+static void boundary_roots(const double *z, const double *d, size_t n, double delta,
+                           double *t_lo, double *t_hi)
+{
+    double zz = dot(z, z, n), zd = dot(z, d, n), dd = dot(d, d, n);
+    double disc = sqrt(zd * zd + dd * (delta * delta - zz));
+    *t_hi = (-zd + disc) / dd;
+    *t_lo = (-zd - disc) / dd;
+}
+
+/* Model value g'p + 0.5 p'Bp (constant f dropped). */
+static double model_value(matvec_fn B, void *ctx, const double *g, const double *p, size_t n,
+                          double *tmp)
+{
+    B(ctx, p, tmp);
+    return dot(g, p, n) + 0.5 * dot(p, tmp, n);
+}
+
+/* Steihaug CG in Nocedal & Wright's notation: z_j iterates, r_j = g + B z_j
+ * the model gradient, d_j search directions, d_0 = -r_0. */
+static int steihaug(matvec_fn B, void *ctx, size_t n, const double *g, double delta, int n_cg,
+                    double *p, int *iters)
+{
+    double *z = (double *)calloc(n, sizeof(double));
+    double *r = (double *)malloc(n * sizeof(double));
+    double *d = (double *)malloc(n * sizeof(double));
+    double *Bd = (double *)malloc(n * sizeof(double));
+    double *tmp = (double *)malloc(n * sizeof(double));
+    int kind = ORACLE_TR_ITERS;
+    *iters = 0;
+    for (size_t i = 0; i < n; ++i) { r[i] = g[i]; d[i] = -g[i]; }
+    double rr = dot(r, r, n);
+    if (rr == 0.0) kind = ORACLE_TR_ZERO;
+    for (int j = 0; j < n_cg && kind == ORACLE_TR_ITERS; ++j) {
+        B(ctx, d, Bd);
+        double kappa = dot(d, Bd, n);
+        if (kappa <= 0.0) {
+            /* Of the two boundary points along d keep the lower model value. */
+            double tl, th;
+            boundary_roots(z, d, n, delta, &tl, &th);
+            double *pl = (double *)malloc(n * sizeof(double));
+            for (size_t i = 0; i < n; ++i) { p[i] = z[i] + th * d[i]; pl[i] = z[i] + tl * d[i]; }
+            if (model_value(B, ctx, g, pl, n, tmp) < model_value(B, ctx, g, p, n, tmp))
+                memcpy(p, pl, n * sizeof(double));
+            free(pl);
+            kind = ORACLE_TR_CURVATURE;
+            break;
+        }
+        double alpha = rr / kappa;
+        double zn2 = 0.0;
+        for (size_t i = 0; i < n; ++i) { double zi = z[i] + alpha * d[i]; zn2 += zi * zi; }
+        if (sqrt(zn2) >= delta) {
+            double tl, th;
+            boundary_roots(z, d, n, delta, &tl, &th);
+            for (size_t i = 0; i < n; ++i) p[i] = z[i] + th * d[i];
+            kind = ORACLE_TR_BOUNDARY;
+            break;
+        }
+        for (size_t i = 0; i < n; ++i) { z[i] += alpha * d[i]; r[i] += alpha * Bd[i]; }
+        *iters = j + 1;
+        double rr_new = dot(r, r, n);
+        if (rr_new == 0.0) { kind = ORACLE_TR_ZERO; break; }
+        double beta = rr_new / rr;
+        for (size_t i = 0; i < n; ++i) d[i] = -r[i] + beta * d[i];
+        rr = rr_new;
+    }
+    if (kind == ORACLE_TR_ITERS || kind == ORACLE_TR_ZERO) memcpy(p, z, n * sizeof(double));
+    free(z); free(r); free(d); free(Bd); free(tmp);
+    return kind;
+}
+
+typedef struct { int n; const double *B; } dense_ctx;
+
+static void dense_matvec(void *c, const double *x, double *y)
+{
+    const dense_ctx *dc = (const dense_ctx *)c;
+    for (int i = 0; i < dc->n; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < dc->n; ++k) acc += dc->B[(size_t)i * dc->n + k] * x[k];
+        y[i] = acc;
+    }
+}
+
+int oracle_steihaug_dense(int n, const double *B, const double *g, double delta, int n_cg,
+                          double *p, int *iters)
+{
+    dense_ctx c = {n, B};
+    return steihaug(dense_matvec, &c, (size_t)n, g, delta, n_cg, p, iters);
+}
+
+double oracle_reflect(double x, double lo, double hi)
+{
+    double w = hi - lo;
+    if (w <= 0.0) return lo;
+    if (x >= lo && x <= hi) return x;   /* inside: no wall is reached */
+    double y = fmod(x - lo, 2.0 * w);
+    if (y < 0.0) y += 2.0 * w;
+    if (y > w) y = 2.0 * w - y;
+    return lo + y;
+}
+
+/* Re(J^H J) x restricted to the active entries (masked rows and columns). */
+typedef struct {
+    const oracle_problem *p;
+    const double *theta;
+    const double complex *coil, *trains;
+    const unsigned char *mask;
+    int param_mask;
+    double complex *y;
+} normal_ctx;
+
+static void normal_matvec(void *c, const double *x, double *out)
+{
+    const normal_ctx *nc = (const normal_ctx *)c;
+    const int Nv = nvox(nc->p);
+    double *xm = (double *)malloc((size_t)NPAR * Nv * sizeof(double));
+    memcpy(xm, x, (size_t)NPAR * Nv * sizeof(double));
+    apply_masks(xm, Nv, nc->param_mask, nc->mask);
+    oracle_jv(nc->p, nc->theta, nc->coil, nc->mask, nc->trains, xm, nc->y);
+    oracle_jhw(nc->p, nc->theta, nc->coil, nc->mask, nc->trains, nc->y, out);
+    apply_masks(out, Nv, nc->param_mask, nc->mask);
+    free(xm);
+}
+
+void oracle_tr_step(const oracle_problem *p, double *theta,
+                    const double complex *coil, const unsigned char *mask,
+                    const double complex *data, const oracle_tr_opts *o, double *delta,
+                    oracle_tr_report *rep)
+{
+    const int Nv = nvox(p);
+    const size_t N = (size_t)NPAR * Nv, L = data_len(p);
+    double complex *tr = (double complex *)malloc(train_len(p) * sizeof(double complex));
+    double complex *r = (double complex *)malloc(L * sizeof(double complex));
+    double complex *y = (double complex *)malloc(L * sizeof(double complex));
+    double *g = (double *)malloc(N * sizeof(double));
+    double *step = (double *)malloc(N * sizeof(double));
+    double *trial = (double *)malloc(N * sizeof(double));
+    double *sv = (double *)malloc(N * sizeof(double));
+    memset(rep, 0, sizeof(*rep));
+    rep->delta_in = *delta;
+
+    /* Linearise: trains, r = d - s, f, g = Re(J^H r). */
+    oracle_epg(p, theta, 1, tr);
+    oracle_signal_separable(p, theta, coil, mask, tr, y);
+    double f0 = 0.0;
+    for (size_t i = 0; i < L; ++i) {
+        r[i] = data[i] - y[i];
+        f0 += creal(r[i]) * creal(r[i]) + cimag(r[i]) * cimag(r[i]);
+    }
+    f0 *= 0.5;
+    oracle_jhw(p, theta, coil, mask, tr, r, g);
+    apply_masks(g, Nv, o->param_mask, mask);
+    rep->f0 = f0;
+    rep->f1 = f0;
+    rep->gnorm = sqrt(dot(g, g, N));
+
+    /* Truncated CG inside the region. */
+    normal_ctx nc = {p, theta, coil, tr, mask, o->param_mask, y};
+    rep->exit_kind = steihaug(normal_matvec, &nc, N, g, *delta, o->n_cg, step, &rep->cg_iters);
+
+    /* Trial point: reflect the reconstructed, bounded entries into the box. */
+    for (size_t i = 0; i < N; ++i) trial[i] = theta[i] + step[i];
+    for (int q = 0; q < 3; ++q)
+        for (int j = 0; j < Nv; ++j) {
+            if (!((o->param_mask >> q) & 1) || !active(mask, j)) continue;
+            double *t = &trial[(size_t)q * Nv + j];
+            double rf = oracle_reflect(*t, o->lo[q], o->hi[q]);
+            if (rf != *t) rep->n_reflected++;
+            *t = rf;
+        }
+    for (size_t i = 0; i < N; ++i) sv[i] = trial[i] - theta[i];
+
+    /* Predicted decrease of the model at the taken step s, and the ratio. */
+    oracle_jv(p, theta, coil, mask, tr, sv, y);
+    double js2 = 0.0;
+    for (size_t i = 0; i < L; ++i) js2 += creal(y[i]) * creal(y[i]) + cimag(y[i]) * cimag(y[i]);
+    double pred = -(dot(g, sv, N) + 0.5 * js2);
+    double ft = oracle_residual(p, trial, coil, mask, data, NULL);
+    double rho = (f0 - ft) / pred;
+    if (!(pred > 0.0) || !isfinite(rho)) rho = -INFINITY;
+    rep->pred = pred;
+    rep->rho = rho;
+    rep->step_norm = sqrt(dot(sv, sv, N));
+
+    int at_boundary = rep->exit_kind == ORACLE_TR_BOUNDARY || rep->exit_kind == ORACLE_TR_CURVATURE;
+    if (rho < 0.25)
+        *delta = 0.25 * *delta;
+    else if (rho > 0.75 && at_boundary)
+        *delta = fmin(2.0 * *delta, o->delta_max);
+    rep->delta_out = *delta;
+    if (rho > o->eta) {
+        memcpy(theta, trial, N * sizeof(double));
+        rep->accepted = 1;
+        rep->f1 = ft;
+    }
+    free(tr); free(r); free(y); free(g); free(step); free(trial); free(sv);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -112,6 +112,57 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
                     const double complex *data, const oracle_gn_opts *o,
                     oracle_gn_report *rep);
 
+/* ------------------------------------------------------------------------
+ * Trust-region form of the inexact Gauss-Newton step (Methods,
+ * Reconstructions: a trust-region framework after Steihaug and Nocedal &
+ * Wright's Algorithm 7.2, with reflection at the feasible bounds after
+ * Coleman & Li).
+ * ------------------------------------------------------------------------ */
+
+/* How the truncated CG of the trust-region step ended. */
+enum {
+    ORACLE_TR_ITERS = 0,      /* the iteration count was reached inside the region */
+    ORACLE_TR_BOUNDARY = 1,   /* an iterate left the region: step cut at its boundary */
+    ORACLE_TR_CURVATURE = 2,  /* non-positive curvature: step to the boundary */
+    ORACLE_TR_ZERO = 3        /* zero model gradient: exact minimiser of the model */
+};
+
+/* Steihaug's truncated CG for min_p g'p + 0.5 p'Bp subject to ||p|| <= delta,
+ * B dense symmetric n x n (row-major), at most n_cg iterations from p = 0.
+ * Returns the exit kind (ORACLE_TR_*); *iters = completed CG updates. */
+int oracle_steihaug_dense(int n, const double *B, const double *g, double delta, int n_cg,
+                          double *p, int *iters);
+
+/* Reflection of x into [lo, hi]: the end point of the straight path from a
+ * point inside the box that bounces off the walls (a fold with period
+ * 2 (hi - lo)); lo == hi gives lo. */
+double oracle_reflect(double x, double lo, double hi);
+
+typedef struct {
+    int n_cg;            /* CG iteration limit of the truncated solve */
+    int param_mask;      /* bit p set = parameter p is reconstructed */
+    double lo[3], hi[3]; /* box of ln T1, ln T2, B1, enforced by reflection */
+    double eta;          /* acceptance: rho > eta */
+    double delta_max;    /* cap of the trust radius */
+} oracle_tr_opts;
+
+typedef struct {
+    double f0, f1, gnorm, step_norm, rho, pred, delta_in, delta_out;
+    int cg_iters, exit_kind, accepted, n_reflected;
+} oracle_tr_report;
+
+/* One trust-region inexact Gauss-Newton iteration at trust radius *delta
+ * (updated in place): Steihaug CG on Re(J^H J) p = -g within ||p|| <= delta,
+ * trial = reflection of theta + p into the box, ratio
+ * rho = (f(theta) - f(trial)) / (model decrease at s = trial - theta), where
+ * the model decrease is -(g's + 0.5 ||J s||^2); theta = trial when
+ * rho > eta; the radius is quartered when rho < 1/4 and doubled (up to
+ * delta_max) when rho > 3/4 and the CG stopped at the boundary. */
+void oracle_tr_step(const oracle_problem *p, double *theta,
+                    const double complex *coil, const unsigned char *mask,
+                    const double complex *data, const oracle_tr_opts *o, double *delta,
+                    oracle_tr_report *rep);
+
 /* Proton-density initialisation: least-squares solution of M(alpha0) rho = d
  * by CGLS (equal to LSQR in exact arithmetic), n_iter iterations from rho = 0.
  * theta's rows 0..2 are used, rows 3..4 are overwritten. */

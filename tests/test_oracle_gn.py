@@ -102,3 +102,97 @@ def test_rho_init_is_least_squares(oracle_lib):
     got = out[3] + 1j * out[4]
     assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
     assert np.array_equal(out[:3], th[:3])
+
+
+def _galerkin_step(H, g, k):
+    """Minimiser of the quadratic model 0.5 p'Hp + g'p over the Krylov space
+    span{g, Hg, ..., H^{k-1} g} (orthonormal basis by twice-repeated
+    Gram-Schmidt)."""
+    V = [g / np.linalg.norm(g)]
+    for _ in range(k - 1):
+        u = H @ V[-1]
+        for _ in range(2):
+            for b in V:
+                u -= (b @ u) * b
+        V.append(u / np.linalg.norm(u))
+    V = np.stack(V, axis=1)
+    return V @ np.linalg.solve(V.T @ H @ V, -(V.T @ g))
+
+
+def test_projected_armijo_backtracking(oracle_lib):
+    """The line search of the GN step, reproduced in numpy from its
+    definition: trial points alpha_t = P(alpha + t p) for t = 1, 1/2, ...,
+    with P clamping only the reconstructed ln T1, ln T2, B1 entries of
+    unmasked voxels to the box, and the first alpha_t with
+    f(alpha_t) <= f + c1 g'(alpha_t - alpha) accepted (the sufficient-
+    decrease test on the projected step). The case is built so that the full
+    step is rejected, the half step is accepted with active entries clamped,
+    an inactive row (B1) lies outside its box interval and a masked voxel's
+    ln T1 lies above the box: an Armijo test on the unprojected step, a clamp
+    of inactive rows or of masked voxels, or a wrong step sequence gives a
+    different accepted point."""
+    rng = np.random.default_rng(4)
+    prob = I.make_problem(4, 3, 24, 8, 8, flip_deg=I.flips_sin2_sweeps(24, 3, seed=3),
+                          t_inv=0.01)
+    nv = prob.nv
+    th_true = I.iid_maps(nv, seed=3)
+    th0 = th_true.copy()
+    th0[:2] += 0.2 * rng.standard_normal((2, nv))
+    th0[3:] += 0.2 * rng.standard_normal((2, nv))
+    mask = np.ones(nv, dtype=np.uint8)
+    mask[5] = 0
+    th0[0, 5] = np.log(20.0)                      # masked voxel, above the ln T1 box
+    d = oracle_lib.signal(prob, th_true, oracle_lib.epg(prob, th_true, tangents=False), mask=mask)
+    pmask, k, c1 = 0b11011, 4, 0.6
+
+    J = oracle_lib.jacobian(prob, th0, oracle_lib.epg(prob, th0), mask=mask)
+    act = np.zeros((5, nv), dtype=bool)
+    for q in range(5):
+        act[q] = bool((pmask >> q) & 1) & (mask == 1)
+    act = act.reshape(-1)
+    Ja = J[:, act]
+    f0, r = oracle_lib.residual(prob, th0, d, mask=mask)
+    H = (Ja.conj().T @ Ja).real
+    ga = (Ja.conj().T @ r.reshape(-1)).real
+    p = np.zeros(5 * nv)
+    p[act] = _galerkin_step(H, ga, k)
+    g = np.zeros(5 * nv)
+    g[act] = ga
+
+    # Box: ln T1 capped below where a third of the half-step trial points
+    # land; B1 (not reconstructed) has a box that excludes its value 1.
+    half = th0.reshape(-1) + 0.5 * p
+    hi_t1 = float(np.quantile(half[:nv][mask == 1], 0.66))
+    lo = [I.GN_LO[0], I.GN_LO[1], 1.1]
+    hi = [hi_t1, I.GN_HI[1], 1.5]
+
+    def project(x):
+        x = x.copy().reshape(5, nv)
+        for q in range(3):
+            if (pmask >> q) & 1:
+                sel = mask == 1
+                x[q, sel] = np.clip(x[q, sel], lo[q], hi[q])
+        return x.reshape(-1)
+
+    expect, t_acc, trials = None, 0.0, 0
+    t = 1.0
+    for _ in range(8):
+        trial = project(th0.reshape(-1) + t * p)
+        ft, _ = oracle_lib.residual(prob, trial.reshape(5, nv), d, mask=mask)
+        trials += 1
+        if ft <= f0 + c1 * (g @ (trial - th0.reshape(-1))):
+            expect, t_acc = trial, t
+            break
+        t *= 0.5
+    # Preconditions of the case: backtracking happened and clamps are active.
+    assert t_acc == 0.5 and trials == 2
+    unclamped = th0.reshape(-1) + t_acc * p
+    assert np.count_nonzero(expect != unclamped) >= 3
+
+    got, rep = oracle_lib.gn_step(prob, th0, d, n_cg=k, param_mask=pmask, lo=lo, hi=hi,
+                                  n_ls_max=8, armijo_c1=c1, mask=mask)
+    assert rep.accepted == 1 and rep.t == t_acc and rep.ls_trials == trials
+    assert np.linalg.norm(got.reshape(-1) - expect) <= 1e-8 * np.linalg.norm(expect)
+    assert np.array_equal(got[2], th0[2])          # inactive B1 row untouched (1.0 < lo)
+    assert got[0, 5] == th0[0, 5]                  # masked voxel untouched
+    assert abs(rep.step_norm - np.linalg.norm(expect - th0.reshape(-1))) <= 1e-8 * rep.step_norm

@@ -189,3 +189,94 @@ def test_line_search_failure_leaves_theta_unchanged(torch_gpu, oracle_lib):
     rep = ctx.gn_step(th, data, 5, 0b11011, I.GN_LO, I.GN_HI)
     assert rep.accepted == 1 and rep.t == 1.0 and rep.f1 < rep.f0
     ctx.close()
+
+
+def test_cg_breakdown_at_truth(torch_gpu, oracle_lib):
+    """At the noiseless truth r = 0 exactly, so g = 0 and CG stops before its
+    first iteration (zero residual): no CG iterations on either side and a
+    zero step, so theta stays exactly where it is. Each side's data is its own
+    signal at that theta (the oracle's in FP64, the library's in FP32), which
+    makes r vanish bit for bit on both."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    w = I.config(1)
+    prob = w.problem
+    th = w.theta.astype(np.float32).astype(np.float64)
+    d_o = oracle_lib.signal(prob, th, oracle_lib.epg(prob, th, tangents=False))
+    th_o, rep_o = oracle_lib.gn_step(prob, th, d_o, n_cg=w.n_cg, param_mask=w.param_mask,
+                                     lo=I.GN_LO, hi=I.GN_HI)
+    assert rep_o.gnorm == 0.0 and rep_o.cg_iters == 0 and np.array_equal(th_o, th)
+    ctx = Context(prob)
+    th_g = _dev(torch, th, torch.float32)
+    zeros = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+    f, r = ctx.residual(th_g, zeros)
+    d_g = (-r).contiguous()
+    before = th_g.clone()
+    rep = ctx.gn_step(th_g, d_g, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI)
+    print(f"  at truth: gpu {rep.as_dict()}; oracle cg {rep_o.cg_iters} t {rep_o.t}", flush=True)
+    assert rep.f0 == 0.0 and rep.gnorm == 0.0 and rep.cg_iters == 0
+    assert rep.step_norm == 0.0
+    assert torch.equal(th_g, before)
+    ctx.close()
+
+
+def test_nan_in_data_leaves_theta_unchanged(torch_gpu, oracle_lib):
+    """A NaN sample in d makes f non-finite: the step reports
+    MRSTAT_ERR_NONFINITE, theta is untouched, and the context stays usable
+    (the next step on clean data equals a fresh context's step bit for bit)."""
+    torch = torch_gpu
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    w = I.config(1)
+    prob = w.problem
+    d = oracle_lib.signal(prob, w.theta, oracle_lib.epg(prob, w.theta, tangents=False))
+    th0 = _start(w.theta)
+    bad = d.copy()
+    bad[0, 5, 3] = np.nan
+    ctx = Context(prob)
+    th = _dev(torch, th0, torch.float32)
+    before = th.clone()
+    with pytest.raises(B.MrstatError) as ei:
+        ctx.gn_step(th, _dev(torch, bad, torch.complex64), w.n_cg, w.param_mask, I.GN_LO, I.GN_HI)
+    assert ei.value.status == B.ERR_NONFINITE
+    assert torch.equal(th, before)
+    dd = _dev(torch, d, torch.complex64)
+    rep = ctx.gn_step(th, dd, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI)
+    fresh = Context(prob)
+    th2 = before.clone()
+    rep2 = fresh.gn_step(th2, dd, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI)
+    assert rep.accepted == rep2.accepted == 1 and rep.f1 == rep2.f1
+    assert torch.equal(th, th2)
+    ctx.close()
+    fresh.close()
+
+
+def test_resume_equivalence(torch_gpu, oracle_lib):
+    """Iterations 1..k, then theta through host memory into a new context for
+    iterations k+1..n, equal iterations 1..n on one context bit for bit: a
+    GN step depends on nothing but theta and the data (every reduction runs
+    in a fixed order), so a reconstruction can be checkpointed and resumed."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    w = I.config(1)
+    prob = w.problem
+    d = oracle_lib.signal(prob, w.theta, oracle_lib.epg(prob, w.theta, tangents=False))
+    dd = _dev(torch, d, torch.complex64)
+    th0 = _dev(torch, _start(w.theta), torch.float32)
+    n, k = 4, 2
+    a = Context(prob)
+    th_a = th0.clone()
+    reps_a = [a.gn_step(th_a, dd, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI).as_dict() for _ in range(n)]
+    a.close()
+    b = Context(prob)
+    th_b = th0.clone()
+    reps_b = [b.gn_step(th_b, dd, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI).as_dict() for _ in range(k)]
+    b.close()
+    saved = th_b.cpu().numpy().copy()                 # the checkpoint
+    c = Context(prob)
+    th_c = _dev(torch, saved, torch.float32)
+    reps_b += [c.gn_step(th_c, dd, w.n_cg, w.param_mask, I.GN_LO, I.GN_HI).as_dict()
+               for _ in range(n - k)]
+    c.close()
+    assert reps_a == reps_b
+    assert torch.equal(th_a, th_c)

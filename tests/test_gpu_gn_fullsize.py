@@ -1,0 +1,85 @@
+"""One inexact Gauss-Newton step at the benchmark's full size (224 x 224
+voxels, 1120 TRs, 448 readout samples, K = 32) against the FP64 oracle's step
+(Algorithm 6; eq. 4 solved by 20 CG iterations; the projected line search).
+
+Two linearisations: B1 reconstructed (all four trains, five parameters) and
+B1 held fixed (three trains: the step streams no dm/dB1 train). Two forms of
+the products, both the ones the benchmark times:
+  * plain: FP32 trains from the EPG, FP32 encoding contraction on MFMA;
+  * contraction form: the EPG's trains stored in FP16 (the wide FP16
+    y-stages) with the split-BF16 encoding contraction.
+Both sides start from the same FP32-representable point near the phantom's
+truth with noiseless data from the oracle. The step's error in theta is the
+FP32 (or FP16-train) rounding of every product, carried through 20 CG
+iterations; the report's step length and CG count must agree exactly.
+Bars: plain 1e-5 relative (the plain path's target), contraction form 1e-3
+(FP16 trains round each stored value to 2^-11 relative).
+"""
+import numpy as np
+import pytest
+
+from paper_1904_13244_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N_CG = 20
+BAR = {"plain": 1e-5, "fp16_trains_split_bf16": 1e-3}
+_ORACLE = {}
+
+
+@pytest.fixture(scope="module")
+def setup(oracle_lib):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_13244_amd import binding
+    binding.lib()
+    w = I.config(3)
+    prob = w.problem
+    print(f"\n[gn full size] {w.name}: oracle data", flush=True)
+    d = oracle_lib.signal(prob, w.theta, oracle_lib.epg(prob, w.theta, tangents=False))
+    rng = np.random.default_rng(I.SEED_PROBE)
+    th0 = w.theta.copy()
+    th0[0] += 0.05 * rng.standard_normal(prob.nv)
+    th0[1] += 0.05 * rng.standard_normal(prob.nv)
+    th0[2] += 0.02 * rng.standard_normal(prob.nv)
+    th0 = th0.astype(np.float32).astype(np.float64)
+    return dict(torch=torch, w=w, prob=prob, d=d, th0=th0)
+
+
+def _oracle_step(oracle_lib, s, mask):
+    if mask not in _ORACLE:
+        print(f"  oracle GN step, param_mask {mask:#07b}", flush=True)
+        _ORACLE[mask] = oracle_lib.gn_step(s["prob"], s["th0"], s["d"], n_cg=N_CG, param_mask=mask,
+                                           lo=I.GN_LO, hi=I.GN_HI)
+    return _ORACLE[mask]
+
+
+@pytest.mark.parametrize("form", ["plain", "fp16_trains_split_bf16"])
+@pytest.mark.parametrize("mask", [0b11111, 0b11011])
+def test_gn_step_full_size_matches_oracle(setup, oracle_lib, mask, form):
+    torch = setup["torch"]
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    prob = setup["prob"]
+    th_o, rep_o = _oracle_step(oracle_lib, setup, mask)
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    ctx = Context(prob)
+    if form != "plain":
+        ctx.set_train_precision(B.TRAINS_FP16)
+        ctx.set_encoding(B.ENC_SPLIT_BF16)
+    th = dev(setup["th0"], torch.float32)
+    rep = ctx.gn_step(th, dev(setup["d"], torch.complex64), N_CG, mask, I.GN_LO, I.GN_HI)
+    ctx.close()
+    got = th.cpu().numpy().astype(np.float64)
+    th0 = setup["th0"]
+    e = float(np.linalg.norm(got - th_o) / np.linalg.norm(th_o))
+    e_step = float(np.linalg.norm((got - th0) - (th_o - th0)) / np.linalg.norm(th_o - th0))
+    ef = abs(rep.f0 - rep_o.f0) / rep_o.f0
+    print(f"  [{form}, mask {mask:#07b}] theta rel err {e:.2e} (step {e_step:.2e}); "
+          f"f0 rel {ef:.2e}; t {rep.t}/{rep_o.t}; cg {rep.cg_iters}/{rep_o.cg_iters}; "
+          f"f1 {rep.f1:.6e}/{rep_o.f1:.6e}", flush=True)
+    assert rep.accepted == rep_o.accepted == 1
+    assert rep.t == rep_o.t and rep.cg_iters == rep_o.cg_iters
+    assert e <= BAR[form], (form, mask, e)
+    assert ef <= BAR[form], (form, mask, ef)

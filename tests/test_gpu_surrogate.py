@@ -9,8 +9,6 @@ Tolerances: 1e-5 normwise where the EPG decides (the plain path's bar),
 2e-2 where the network does (its BF16 activations; derivation in
 tests/test_gpu_mlp.py).
 """
-import time
-
 import numpy as np
 import pytest
 
@@ -155,40 +153,6 @@ def test_surrogate_shape_mismatch_rejected(setup):
         other.close()
 
 
-def test_linearisation_time_surrogate_vs_epg_full_size(torch_gpu):
-    """At 224 x 224 voxels and 1120 TRs the surrogate's linearisation (all
-    four trains of every voxel, inside the box) takes a fraction of the EPG's.
-    Timed with the library's kernel tracing."""
-    torch = torch_gpu
-    from paper_1904_13244_amd.binding import Context, Surrogate
-    w = I.config(3)
-    prob = w.problem
-    th = np.asarray(w.theta, dtype=np.float32).copy()
-    lo, hi = np.array(I.SURR_LO), np.array(I.SURR_HI)
-    th[:3] = np.clip(th[:3], lo[:, None] + 1e-3, hi[:, None] - 1e-3)
-    net = Surrogate(prob.n_tr, 256, 4, 4096)
-    net.set_scaling(I.SURR_LO, I.SURR_HI, [0.1, 0.1, 0.05, 0.2])
-    net.set_params(torch.from_numpy(I.mlp_init_params(prob.n_tr).astype(np.float32)).cuda())
-    ctx = Context(prob)
-    thd = _dev(torch, th, torch.float32)
-    times = {}
-    for name, sur in (("epg", None), ("surrogate", net)):
-        ctx.set_surrogate(sur)
-        ctx.linearise(thd)
-        ctx.profile(True)
-        for _ in range(3):
-            ctx.linearise(thd)
-        prof = ctx.profile_read()
-        ctx.profile(False)
-        times[name] = sum(ms for k, (n, ms) in prof.items()) / 3
-    print(f"\n[linearise 224x224x1120] EPG {times['epg']:.3f} ms, surrogate {times['surrogate']:.3f} ms "
-          f"({times['epg'] / times['surrogate']:.1f}x)", flush=True)
-    assert ctx.fallback_count() == 0
-    assert times["surrogate"] < times["epg"] / 3
-    ctx.close()
-    net.close()
-
-
 @pytest.mark.parametrize("f16", [False, True])
 def test_width256_split_inference(torch_gpu, oracle_lib, f16):
     """Width-256 networks run the hidden layers and the output layer as two
@@ -241,3 +205,55 @@ def test_width256_split_inference(torch_gpu, oracle_lib, f16):
     net.close()
     print(f"\n[width 256 f16={f16}] trains rel {['%.2e' % e for e in errs]}, residual {e_r:.2e}", flush=True)
     assert max(errs) <= 2e-2 and e_r <= 2e-2
+
+
+def test_width192_chunked_inference_and_fp16_refusal(torch_gpu):
+    """Widths other than 64, 128 and 256 infer layer by layer in batch-size
+    chunks (hidden layers, then the output-layer GEMM with the inference
+    epilogue). Their predictions and routed trains match the FP64 network on
+    the same BF16-rounded weights (three chunks of 128 voxels, the last one
+    ragged); FP16 train storage with such a network is refused in either
+    order of the two calls."""
+    torch = torch_gpu
+    from oracle import mlp as M
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context, Surrogate
+    rng = np.random.default_rng(71)
+    n_tr, width, depth, batch = 48, 192, 2, 128
+    prob = I.make_problem(20, 15, n_tr, 32, 8, flip_deg=I.flips_sin2_sweeps(n_tr, 15))
+    nv = prob.nv
+    lo, hi = np.array(I.SURR_LO), np.array(I.SURR_HI)
+    th = I.iid_maps(nv, seed=72, b1=rng.uniform(0.8, 1.2, nv))
+    th[:3] = np.clip(th[:3], lo[:, None] + 1e-3, hi[:, None] - 1e-3)
+    th = th.astype(np.float32).astype(np.float64)
+    flat = I.mlp_init_params(n_tr, width, depth, seed=73).astype(np.float32)
+    scale = np.array([0.2, 0.15, 0.05, 0.3], dtype=np.float32)
+    net = Surrogate(n_tr, width, depth, batch)
+    net.set_scaling(I.SURR_LO, I.SURR_HI, scale)
+    net.set_params(torch.from_numpy(flat).cuda())
+    parts = M.unpack(flat.astype(np.float64), n_tr, width, depth)
+    for l in range(1, depth + 1):
+        parts[2 * l] = _bf16(parts[2 * l])
+    y, _ = M.forward(np.concatenate([p.reshape(-1) for p in parts]),
+                     M.normalise_inputs(th[:3], I.SURR_LO, I.SURR_HI), n_tr, width, depth)
+    ref = y[4 * n_tr:].reshape(4, n_tr, nv) * scale.astype(np.float64)[:, None, None]
+    thd = _dev(torch, th, torch.float32)
+    pred = net.predict(thd[:3].contiguous()).cpu().numpy().astype(np.float64)
+    ctx = Context(prob)
+    ctx.set_surrogate(net)
+    routed = ctx.simulate(thd).cpu().numpy().astype(np.float64)
+    assert ctx.fallback_count() == 0
+    e_pred = max(_rel(pred[p], ref[p]) for p in range(4))
+    e_routed = max(_rel(routed[p], ref[p]) for p in range(4))
+    print(f"\n[width 192] predict {e_pred:.2e}, routed {e_routed:.2e}", flush=True)
+    assert e_pred <= 2e-2 and e_routed <= 2e-2
+    with pytest.raises(B.MrstatError) as e1:
+        ctx.set_train_precision(B.TRAINS_FP16)
+    assert e1.value.status == B.ERR_UNSUPPORTED
+    ctx.set_surrogate(None)
+    ctx.set_train_precision(B.TRAINS_FP16)
+    with pytest.raises(B.MrstatError) as e2:
+        ctx.set_surrogate(net)
+    assert e2.value.status == B.ERR_UNSUPPORTED
+    ctx.close()
+    net.close()

@@ -1,17 +1,18 @@
-"""What the trained surrogate gains, and what it costs in map accuracy.
+"""What the trained surrogate costs in map accuracy.
 
 At the 224 x 224, 1120-TR workload and at the 256 x 256, 8-coil, 1280-TR
 workload (noise at SNR 50) the network is trained on the GPU by the library's
 own kernels (2M box samples simulated by the library's EPG), then the same
-Gauss-Newton reconstruction (T1, T2, rho; B1 known; head mask; from the
-standard initial guess with rho from CGLS) runs twice: plain (FP32 EPG
-trains, FP32 encoding contraction) and surrogate (network trains stored in
-FP16, EPG outside the box, split-BF16 encoding contraction). The plain run is
-the reference the surrogate is judged against: EPG judges the surrogate's
-maps, stated as T1/T2 MAPE over the head. Bars (from measurement with
-margin): held-out train error <= 2 % for m and the T1/T2 derivatives,
-<= 15 % for dm/dB1 (not used with B1 known); maps within 2 % (T1) and 3 %
-(T2) MAPE of the plain maps; the surrogate GN step at least 1.2x faster.
+Gauss-Newton reconstruction (all five parameters: T1, T2, B1 and rho; head
+mask; from the standard initial guess T1 = 1 s, T2 = 0.1 s, B1 = 1 with rho
+from CGLS) runs twice: plain (FP32 EPG trains, FP32 encoding contraction) and
+surrogate (network trains stored in FP16, EPG outside the box, split-BF16
+encoding contraction). The plain run is the reference the surrogate is judged
+against: EPG judges the surrogate's maps, stated as T1, T2 and B1 MAPE over
+the head. Bars (from measurement with margin): held-out train error <= 2 %
+for every train; maps within 2 % (T1), 3 % (T2) and 1 % (B1) MAPE of the
+plain maps. Step times are printed for information only (the benchmark
+reports the speed of both forms).
 """
 import time
 
@@ -33,25 +34,27 @@ def torch_gpu():
     return torch
 
 
-def _mape(a, b, sel):
-    return 100.0 * float(np.mean(np.abs(np.exp(a[sel]) - np.exp(b[sel])) / np.exp(b[sel])))
+def _mape(a, b, sel, log=True):
+    f = np.exp if log else (lambda x: x)
+    return 100.0 * float(np.mean(np.abs(f(a[sel]) - f(b[sel])) / f(b[sel])))
 
 
 @pytest.mark.parametrize("cfg", [4, 5])
-def test_trained_surrogate_maps_and_speed(torch_gpu, cfg):
+def test_trained_surrogate_maps(torch_gpu, cfg):
     """cfg 4: 224 x 224, 1120 TRs, noiseless, 10 GN x 20 CG; cfg 5: 256 x 256,
     8 coils, 1280 TRs, SNR 50, 15 GN x 30 CG."""
     torch = torch_gpu
     from paper_1904_13244_amd import binding as B
     from paper_1904_13244_amd.binding import Context
-    from paper_1904_13244_amd.surrogate import train_surrogate
+    from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT, train_surrogate
     w = I.config(cfg)
     prob, head = w.problem, w.extra["head"]
     print(f"\n[surrogate maps] {w.name}", flush=True)
-    net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=40)
+    net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=RECIPE_EPOCHS,
+                               head_weight=RECIPE_HEAD_WEIGHT)
     print(f"  trained {rep.steps} steps in {rep.seconds_train:.1f} s; held-out rel err "
           f"{['%.2e' % e for e in rep.val_rel_err]}", flush=True)
-    assert max(rep.val_rel_err[:3]) <= 2e-2 and rep.val_rel_err[3] <= 0.15
+    assert max(rep.val_rel_err) <= 2e-2
 
     dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
     coil = None if w.coil is None else dev(w.coil, torch.complex64)
@@ -64,7 +67,7 @@ def test_trained_surrogate_maps_and_speed(torch_gpu, cfg):
         s_norm = float(torch.linalg.vector_norm(d))
         d = d + dev(n * (s_norm / (w.snr * np.linalg.norm(n))), torch.complex64)
     th0 = I.initial_theta(prob.nv)
-    th0[2] = w.theta[2]                      # B1 known
+    assert w.param_mask == 0b11111           # B1 fitted from the initial guess B1 = 1
     box_lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
     box_hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
     maps, ms = {}, {}
@@ -84,14 +87,15 @@ def test_trained_surrogate_maps_and_speed(torch_gpu, cfg):
         torch.cuda.synchronize()
         ms[name] = 1e3 * (time.perf_counter() - t0) / w.n_gn
         maps[name] = th.cpu().numpy().astype(np.float64)
-        print(f"  [{name}] {ms[name]:.2f} ms/GN step; T1 MAPE vs truth "
+        print(f"  [{name}] {ms[name]:.2f} ms/GN step; MAPE vs truth T1 "
               f"{_mape(maps[name][0], w.theta[0], head):.3f} %, T2 "
-              f"{_mape(maps[name][1], w.theta[1], head):.3f} %", flush=True)
+              f"{_mape(maps[name][1], w.theta[1], head):.3f} %, B1 "
+              f"{_mape(maps[name][2], w.theta[2], head, log=False):.3f} %", flush=True)
     t1 = _mape(maps["surrogate"][0], maps["plain"][0], head)
     t2 = _mape(maps["surrogate"][1], maps["plain"][1], head)
-    print(f"  surrogate vs plain maps: T1 MAPE {t1:.3f} %, T2 MAPE {t2:.3f} %; "
-          f"speedup {ms['plain'] / ms['surrogate']:.2f}x", flush=True)
-    assert t1 <= 2.0 and t2 <= 3.0
-    assert ms["plain"] / ms["surrogate"] >= 1.2
+    b1 = _mape(maps["surrogate"][2], maps["plain"][2], head, log=False)
+    print(f"  surrogate vs plain maps: T1 MAPE {t1:.3f} %, T2 MAPE {t2:.3f} %, B1 MAPE {b1:.3f} %; "
+          f"step time ratio {ms['plain'] / ms['surrogate']:.2f}", flush=True)
+    assert t1 <= 2.0 and t2 <= 3.0 and b1 <= 1.0
     ctx.close()
     net.close()

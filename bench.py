@@ -5,24 +5,27 @@ Workload: 224x224 brain-like phantom (B1 in [0.8, 1.2]), 1120 TRs
 (224 phase-encode lines x 5 sweeps, sine-squared flip train 0-70 degrees),
 448 readout samples per TR (2x oversampled), K = 32 EPG states, one coil.
 
-Step: one inexact Gauss-Newton iteration through the C ABI (mrstat_gn_step):
-linearisation (trains and their derivatives), residual and objective,
-gradient g = Re(J^H r), n_cg = 20 CG iterations (each one J v + one J^H w
-pair with FP64 reductions) and one line-search trial (value-only trains +
-residual). Metric: J v + J^H w pairs per second, GN-amortised (n_cg pairs per
-step), for two forms on the same workload and starting point:
+Step: one inexact Gauss-Newton iteration through the C ABI (mrstat_gn_step)
+fitting all five parameters (ln T1, ln T2, B1, Re rho, Im rho): linearisation
+(m and its derivatives in ln T1, ln T2 and B1: four trains), residual and
+objective, gradient g = Re(J^H r), n_cg = 20 CG iterations (each one J v + one
+J^H w pair with FP64 reductions) and one line-search trial (value-only trains
++ residual). Metric: J v + J^H w pairs per second, GN-amortised (n_cg pairs
+per step), for two forms on the same workload and starting point:
   - surrogate + split-BF16 (the reported value): the learned network gives
     the trains (BF16 MFMA, EPG fallback outside its box, iterates projected
     onto that box), stored in FP16; the encoding contraction runs in
     split-BF16 on MFMA;
   - plain FP32: EPG trains, FP32 MFMA encoding contraction.
-The network is trained first, untimed, on 2M EPG samples the library
-simulates itself.
+The same two forms are also timed with B1 held known (three trains, no
+dm/dB1), reported as a labelled variant. The network is trained first,
+untimed, on 2M EPG samples the library simulates itself.
 
 The JSON line also reports, for the dominant kernel, its roofline from HIP
 events taken live over the timed region, the surrogate inference kernel's
-roofline, and the FP64 CPU oracle timed on a bounded sample of the same
-workload on this host.
+roofline, fresh-pair times (every product re-linearises), the surrogate's
+linearisation with a share of voxels outside its box, and the FP64 CPU oracle
+timed on a bounded sample of the same workload on this host.
 """
 from __future__ import annotations
 
@@ -48,6 +51,7 @@ EPG_FLOP_PER_STATE_TR = {4: 67,   # value 13 + ln T1 15 + ln T2 17 + B1 22 (real
 # Kernel kinds traced in the timed region (the roofline candidates).
 TRACED_KINDS = ["epg", "epg_value", "ystage_fwd_signal", "ystage_fwd_jv", "ystage_adj",
                 "surrogate", "surrogate_value"]
+
 
 
 def algorithmic(kind, prob, tb=4, ntr=4):
@@ -99,18 +103,65 @@ def parse():
     ap.add_argument("--n-cg", type=int, default=20)
     ap.add_argument("--epg-lanes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-b1-known", action="store_true",
+                    help="skip the B1-known (three-train) variant")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--train-epochs", type=int, default=40)
+    ap.add_argument("--train-epochs", type=int, default=None,
+                    help="epochs of surrogate training (default: the library's recipe)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--form", choices=["both", "surrogate", "plain"], default="both")
     return ap.parse_args()
 
 
-def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=8):
-    """The oracle as it stands, on this host: EPG with tangents on a voxel
-    sample (scaled to all voxels) plus n_pairs full-size J v + J^H w pairs
-    (about 7 s of CPU work at 224 x 224, 1120 TRs on 16 threads)."""
+def _host_cpu():
+    """Host CPU description from lscpu (model, sockets, cores per socket)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "cpus": info.get("CPU(s)"),
+            "nproc": os.cpu_count()}
+
+
+_ONE_THREAD = r"""
+import sys, time, json
+import numpy as np
+sys.path.insert(0, {root!r})
+import oracle
+from paper_1904_13244_amd import inputs as I
+w = I.config(3)
+prob = w.problem
+S = {nvox}
+sel = np.linspace(0, prob.nv - 1, S).astype(np.int64)
+sub = I.make_problem(S, 1, prob.n_tr, prob.n_read, prob.n_states, flip_deg=prob.flip_deg)
+t0 = time.perf_counter(); oracle.epg(sub, w.theta[:, sel]); t_lin = (time.perf_counter() - t0) * prob.nv / S
+t0 = time.perf_counter(); oracle.epg(sub, w.theta[:, sel], tangents=False)
+t_val = (time.perf_counter() - t0) * prob.nv / S
+trains = np.full((4, prob.n_tr, prob.nv), 1e-3 + 1e-3j, dtype=np.complex128)
+v, ww = I.probe_vectors(prob)
+t0 = time.perf_counter(); y = oracle.jv(prob, w.theta, trains, v); oracle.jhw(prob, w.theta, trains, y)
+t_pair = time.perf_counter() - t0
+print(json.dumps(dict(threads=oracle.num_threads(), t_lin=t_lin, t_val=t_val, t_pair=t_pair)))
+"""
+
+
+def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=6, n_vox_1t=1024):
+    """The oracle as it stands, on this host: EPG with tangents (and the
+    value-only EPG of the line-search trial) on a voxel sample scaled to all
+    voxels, plus full-size J v + J^H w pairs, on all host threads; the same
+    with one thread (a smaller voxel sample and one pair, in a child process).
+    GN-amortised like the GPU step: t_step = t_lin + (n_cg + 1) t_pair +
+    t_trial, the gradient costing about one pair and the trial a value-only
+    EPG plus a residual (about half a pair)."""
+    import subprocess
+
     import oracle
     from paper_1904_13244_amd import inputs as I
 
@@ -122,6 +173,9 @@ def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=8):
     t0 = time.perf_counter()
     oracle.epg(sub, work.theta[:, sel])
     t_sample = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.epg(sub, work.theta[:, sel], tangents=False)
+    t_val = (time.perf_counter() - t0) * prob.nv / S
     t_lin = t_sample * prob.nv / S
     trains = np.full((4, prob.n_tr, prob.nv), 1e-3 + 1e-3j, dtype=np.complex128)
     v, w = I.probe_vectors(prob)
@@ -132,13 +186,28 @@ def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=8):
     t_pairs = time.perf_counter() - t0
     t_pair = t_pairs / n_pairs
     del trains
-    t_step = t_lin + (n_cg + 1) * t_pair   # residual + gradient cost about one pair
+    t_step = t_lin + (n_cg + 1) * t_pair + t_val + 0.5 * t_pair
+    one = None
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _ONE_THREAD.format(root=ROOT, nvox=n_vox_1t)],
+                           capture_output=True, text=True, env=env, timeout=300)
+        o = json.loads(r.stdout.strip().splitlines()[-1])
+        t1 = o["t_lin"] + (n_cg + 1.5) * o["t_pair"] + o["t_val"]
+        one = {"value": n_cg / t1, "cores": o["threads"],
+               "sample": (f"EPG on {n_vox_1t} voxels scaled to {prob.nv} "
+                          f"({o['t_lin']:.1f} s with tangents, {o['t_val']:.1f} s value-only), "
+                          f"one full-size pair ({o['t_pair']:.1f} s)")}
+    except Exception as e:   # the one-thread leg is context, never fatal
+        one = {"error": str(e)[:200]}
     return {"value": n_cg / t_step, "unit": "pairs/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": (f"FP64 oracle: EPG with tangents on {S} of {prob.nv} voxels "
-                       f"({t_sample:.2f} s, scaled x{prob.nv / S:.2f}) + {n_pairs} full-size "
-                       f"Jv + J^H w pairs ({t_pairs:.2f} s); GN-amortised with n_cg = {n_cg}: "
-                       f"t_step = t_lin + (n_cg + 1) t_pair = {t_step:.1f} s")}
+            "sample": (f"FP64 oracle, all five parameters (four trains): EPG with tangents on {S} "
+                       f"of {prob.nv} voxels ({t_sample:.2f} s, scaled x{prob.nv / S:.2f}), the "
+                       f"value-only EPG on the same sample (scaled: {t_val:.2f} s), {n_pairs} "
+                       f"full-size Jv + J^H w pairs ({t_pairs:.2f} s); GN-amortised with n_cg = "
+                       f"{n_cg}: t_step = t_lin + (n_cg + 1.5) t_pair + t_value = {t_step:.1f} s"),
+            "one_thread": one, "host": _host_cpu()}
 
 
 def roofline_for(kernels, prob, tb, ntr):
@@ -152,7 +221,7 @@ def roofline_for(kernels, prob, tb, ntr):
         ach = amount / t / 1e9
         return {"kernel": rk, "bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": measured_traffic(rk + ("_f16" if tb == 2 else "_f32")),
+                "traffic": measured_traffic(f"{rk}_{'f16' if tb == 2 else 'f32'}_{ntr}tr"),
                 "algorithmic_bytes_per_launch": amount}
     ach = amount / t / 1e12
     return {"kernel": rk, "bound": bound, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
@@ -192,17 +261,16 @@ def main():
     th0[2] += 0.02 * rng.standard_normal(prob.nv)
     vv, ww = I.probe_vectors(prob, work.param_mask)
     vd, wd = dev(vv, torch.float32), dev(ww, torch.complex64)
-    # B1 held fixed: the GN step's linearisation has no dm/dB1 train.
-    ntr = 4 if (work.param_mask >> 2) & 1 else 3
 
-    def run_form(net, enc, lo, hi, trains):
+    def run_form(net, enc, lo, hi, trains, param_mask):
+        ntr = 4 if (param_mask >> 2) & 1 else 3
         ctx.set_surrogate(net)
         ctx.set_encoding(enc)
         ctx.set_train_precision(trains)
         theta = dev(th0, torch.float32)
 
         def step():
-            return ctx.gn_step(theta, data, args.n_cg, work.param_mask, lo, hi, n_ls_max=1)
+            return ctx.gn_step(theta, data, args.n_cg, param_mask, lo, hi, n_ls_max=1)
 
         for _ in range(args.warmup):
             step()
@@ -227,58 +295,86 @@ def main():
         full = ctx.profile_read()
         ctx.profile(False)
         breakdown = {k: {"launches": n, "ms": ms} for k, (n, ms) in full.items() if n}
-        # Cached pair (reuse = 1) and linearisation, outside the timed loop.
+        out = {"value": args.n_cg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+               "kernels": kernels, "step_breakdown_untimed": breakdown,
+               "dominant_kernel": max(breakdown, key=lambda k: breakdown[k]["ms"]),
+               "roofline": roofline_for(kernels, prob, 2 if trains == B.TRAINS_FP16 else 4, ntr),
+               "gn_report_last": rep.as_dict()}
+        if ntr < 4:
+            return out
+        # Outside the timed loop, all four trains: the cached pair (reuse = 1),
+        # the linearisation, and the fresh pair (reuse = 0: J v and J^H w
+        # each simulate the trains again, the strict matrix-free practice).
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def timed(fn, reps):
+            fn()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
         ctx.linearise(theta)
         jv_out = torch.empty(prob.data_shape, dtype=torch.complex64, device="cuda")
         g_out = torch.empty((5, prob.nv), dtype=torch.float32, device="cuda")
-        for _ in range(3):
-            ctx.jv(theta, vd, reuse=True, out=jv_out)
-            ctx.jhw(theta, wd, reuse=True, out=g_out)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
-            ctx.jv(theta, vd, reuse=True, out=jv_out)
-            ctx.jhw(theta, wd, reuse=True, out=g_out)
-        e1.record()
-        torch.cuda.synchronize()
-        pair_ms = e0.elapsed_time(e1) / 20
-        e0.record()
-        for _ in range(5):
-            ctx.linearise(theta)
-        e1.record()
-        torch.cuda.synchronize()
-        lin_ms = e0.elapsed_time(e1) / 5
-        return {"value": args.n_cg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
-                "kernels": kernels, "step_breakdown_untimed": breakdown,
-                "dominant_kernel": max(breakdown, key=lambda k: breakdown[k]["ms"]),
-                "roofline": roofline_for(kernels, prob, 2 if trains == B.TRAINS_FP16 else 4, ntr),
-                "pair_cached_ms": pair_ms,
-                "pairs_per_s_cached": 1e3 / pair_ms, "linearise_ms": lin_ms,
-                "gn_report_last": rep.as_dict()}
 
+        def pair(reuse):
+            ctx.jv(theta, vd, reuse=reuse, out=jv_out)
+            ctx.jhw(theta, wd, reuse=reuse, out=g_out)
+
+        out["pair_cached_ms"] = timed(lambda: pair(True), 20)
+        out["pairs_per_s_cached"] = 1e3 / out["pair_cached_ms"]
+        out["linearise_ms"] = timed(lambda: ctx.linearise(theta), 5)
+        out["pair_fresh_ms"] = timed(lambda: pair(False), 5)
+        out["pairs_per_s_fresh"] = 1e3 / out["pair_fresh_ms"]
+        if net is not None:
+            # Linearisation with a share of voxels outside the network's box:
+            # those take the EPG (index-list kernel) after the network.
+            fb = {}
+            for share in (0.01, 0.1):
+                th_out = theta.clone()
+                k = int(share * prob.nv)
+                idx = torch.from_numpy(np.random.default_rng(9).choice(prob.nv, k, replace=False)).cuda()
+                th_out[0, idx] = float(np.log(6.0))        # T1 = 6 s, above the box
+                t_ms = timed(lambda: ctx.linearise(th_out), 5)
+                fb[f"{share:.0%}"] = {"voxels": ctx.fallback_count(), "linearise_ms": t_ms}
+            out["linearise_with_fallback"] = fb
+        return out
+
+    masks = {"b1_fitted": 0b11111}
+    if not args.no_b1_known:
+        masks["b1_known"] = 0b11011
     forms = {}
     if args.form in ("both", "plain"):
-        forms["plain_fp32"] = run_form(None, B.ENC_FP32, I.GN_LO, I.GN_HI, B.TRAINS_FP32)
+        for mname, pm in masks.items():
+            forms[("plain_fp32", mname)] = run_form(None, B.ENC_FP32, I.GN_LO, I.GN_HI, B.TRAINS_FP32, pm)
     surr_info = None
     if args.form in ("both", "surrogate"):
         from paper_1904_13244_amd.surrogate import train_surrogate
-        net, trep = train_surrogate(torch, prob, n_samples=args.train_samples, epochs=args.train_epochs)
+        from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT
+        epochs = args.train_epochs or RECIPE_EPOCHS
+        net, trep = train_surrogate(torch, prob, n_samples=args.train_samples, epochs=epochs,
+                                    head_weight=RECIPE_HEAD_WEIGHT)
         lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
         hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
-        f = run_form(net, B.ENC_SPLIT_BF16, lo, hi, B.TRAINS_FP16)
-        forms["surrogate_split_bf16"] = f
-        flop, wbytes = surrogate_work(prob, ntr=ntr)
+        for mname, pm in masks.items():
+            forms[("surrogate_split_bf16", mname)] = run_form(net, B.ENC_SPLIT_BF16, lo, hi,
+                                                              B.TRAINS_FP16, pm)
+        f = forms[("surrogate_split_bf16", "b1_fitted")]
+        flop, wbytes = surrogate_work(prob, ntr=4)
         k = f["kernels"].get("surrogate")
         t = k["avg_ms"] * 1e-3 if k else None
         surr_info = {
             "training": {"samples": trep.n_samples, "steps": trep.steps, "batch": net.batch,
+                         "epochs": epochs, "head_weight": list(RECIPE_HEAD_WEIGHT),
                          "seconds_data": trep.seconds_data, "seconds_train": trep.seconds_train,
                          "loss_first": trep.loss_first, "loss_last": trep.loss_last,
                          "heldout_rel_err": dict(zip(["m", "dm_dlnT1", "dm_dlnT2", "dm_dB1"],
                                                      trep.val_rel_err))},
             "inference_roofline": None if t is None else {
-                "kernel": (f"surrogate (hidden-layer + output-layer kernels, {ntr} trains, "
-                           "FP16 out)"),
+                "kernel": "surrogate (hidden-layer + output-layer kernels, 4 trains, FP16 out)",
                 "bound": "hbm", "achieved": wbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": wbytes / t / 1e9 / HBM_PEAK_GBS,
                 "mfma_tflops": flop / t / 1e12, "mfma_frac": flop / t / 1e12 / BF16_MFMA_PEAK_TFLOPS,
@@ -292,38 +388,42 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    chosen = "surrogate_split_bf16" if "surrogate_split_bf16" in forms else "plain_fp32"
-    c = forms[chosen]
+    chosen = "surrogate_split_bf16" if ("surrogate_split_bf16", "b1_fitted") in forms else "plain_fp32"
+    c = forms[(chosen, "b1_fitted")]
+    form_desc = {"surrogate_split_bf16": ("surrogate trains (BF16 MFMA network, EPG fallback, FP16 "
+                                          "storage) + split-BF16 MFMA encoding contraction"),
+                 "plain_fp32": "plain FP32 EPG + FP32 MFMA encoding contraction"}
+    keep = ("value", "ms_per_step", "roofline", "kernels", "step_breakdown_untimed", "pair_cached_ms",
+            "pairs_per_s_cached", "linearise_ms", "pair_fresh_ms", "pairs_per_s_fresh",
+            "linearise_with_fallback", "gn_report_last")
     out = {
         "metric": METRIC, "value": c["value"], "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": c["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32+bf16" if chosen.startswith("surrogate") else "fp32",
+        "dtype": ("fp32 (BF16 MFMA network, FP16 train storage, split-BF16 contraction)"
+                  if chosen.startswith("surrogate") else "fp32"),
         "data": "synthetic",
         "config": {"workload": ("224x224 brain-like phantom, 1120 TRs (224 lines x 5 sweeps), "
-                                "448 readout samples, K=32 EPG states, 1 coil; T1, T2, rho fitted "
-                                "with B1 known (no dm/dB1 train); one GN step = "
+                                "448 readout samples, K=32 EPG states, 1 coil; all five parameters "
+                                "fitted (T1, T2, B1, complex rho: four trains); one GN step = "
                                 "linearise + r + g + 20 CG pairs + 1 line-search trial"),
-                   "form": {"surrogate_split_bf16": "surrogate trains (BF16 MFMA network, EPG "
-                                                    "fallback, FP16 storage) + split-BF16 MFMA "
-                                                    "encoding contraction",
-                            "plain_fp32": "plain FP32 EPG + FP32 MFMA encoding contraction"}[chosen],
-                   "n_cg": args.n_cg, "parallelism": "single GPU"},
+                   "form": form_desc[chosen], "n_cg": args.n_cg, "parallelism": "single GPU"},
         "roofline": c["roofline"],
-        "dominant_kernel": c["dominant_kernel"],
-        "kernels": c["kernels"],
-        "step_breakdown_untimed": c["step_breakdown_untimed"],
-        "pair_cached_ms": c["pair_cached_ms"],
-        "pairs_per_s_cached": c["pairs_per_s_cached"],
-        "linearise_ms": c["linearise_ms"],
-        "gn_report_last": c["gn_report_last"],
     }
-    if "plain_fp32" in forms and chosen != "plain_fp32":
-        p = forms["plain_fp32"]
-        out["plain_fp32"] = {k: p[k] for k in ("value", "ms_per_step", "pair_cached_ms",
-                                               "pairs_per_s_cached", "linearise_ms", "roofline",
-                                               "kernels", "step_breakdown_untimed")}
+    out.update({k: c[k] for k in keep if k in c and k not in ("value", "ms_per_step", "roofline")})
+    if chosen != "plain_fp32" and ("plain_fp32", "b1_fitted") in forms:
+        p = forms[("plain_fp32", "b1_fitted")]
+        out["plain_fp32"] = {k: p[k] for k in keep if k in p}
         out["speedup_vs_plain_fp32"] = c["value"] / p["value"]
+    if "b1_known" in masks:
+        bk = {"workload": "the same step with B1 known (T1, T2, rho fitted): three trains, no dm/dB1"}
+        for form in ("surrogate_split_bf16", "plain_fp32"):
+            if (form, "b1_known") in forms:
+                f = forms[(form, "b1_known")]
+                bk[form] = {k: f[k] for k in ("value", "ms_per_step", "roofline", "step_breakdown_untimed")}
+        if "surrogate_split_bf16" in bk and "plain_fp32" in bk:
+            bk["speedup_vs_plain_fp32"] = bk["surrogate_split_bf16"]["value"] / bk["plain_fp32"]["value"]
+        out["variant_b1_known"] = bk
     if surr_info:
         out["surrogate"] = surr_info
     ctx.close()

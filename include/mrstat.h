@@ -269,7 +269,11 @@ mrstat_status mrstat_profile_select(mrstat_ctx ctx, uint32_t kind_mask);
  * A network is not thread-safe, and a context using it as surrogate shares
  * its workspace: do not train and reconstruct with one network at once.
  * Requirements: n_tr a multiple of 8; width a multiple of 64, <= 1024;
- * 1 <= depth <= 16; batch a multiple of 64.
+ * 1 <= depth <= 16; batch a multiple of 64. Inference of widths 64, 128
+ * and 256 (depth <= 16) runs in fused kernels that can store FP16 trains;
+ * other widths run layer by layer in batch-size chunks and write FP32 only,
+ * so a context with FP16 trains refuses them (MRSTAT_ERR_UNSUPPORTED from
+ * mrstat_set_surrogate or mrstat_set_train_precision).
  * ------------------------------------------------------------------------ */
 mrstat_status mrstat_mlp_create(int32_t n_tr, int32_t width, int32_t depth, int32_t batch,
                                 mrstat_mlp *out);

@@ -386,17 +386,18 @@ const char* mrstat_last_error(mrstat_ctx ctx)
 
 size_t mrstat_workspace_bytes(mrstat_ctx ctx) { return ctx ? ctx->L.total : 0; }
 
-mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const void* d_coil,
-                          const uint8_t* d_mask, mrstat_stream stream)
+}  // extern "C"
+
+namespace {
+
+// Attaches ws (at least ctx->L.total bytes, 256-byte aligned), uploads the
+// tables, builds the B-fragment tables and clears the device scalars.
+mrstat_status bind_impl(mrstat_ctx ctx, char* ws, const void* d_coil, const uint8_t* d_mask,
+                        hipStream_t s)
 {
-    if (!ctx) return MRSTAT_ERR_ARG;
-    if (!d_ws) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace pointer is NULL");
-    if (!aligned(d_ws, 256)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < ctx->L.total) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace too small");
     if (ctx->d.C > 1 && !d_coil) return fail(ctx, MRSTAT_ERR_ARG, "coil maps required when n_coils > 1");
     if (d_coil && !aligned(d_coil, 8)) return fail(ctx, MRSTAT_ERR_ARG, "coil maps must be 8-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    ctx->ws = (char*)d_ws;
+    ctx->ws = ws;
     ctx->coil = (const float2*)d_coil;
     ctx->mask = d_mask;
     ctx->bound = false;
@@ -416,6 +417,20 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const voi
     return MRSTAT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const void* d_coil,
+                          const uint8_t* d_mask, mrstat_stream stream)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (!d_ws) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (!aligned(d_ws, 256)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < ctx->L.total) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace too small");
+    return bind_impl(ctx, (char*)d_ws, d_coil, d_mask, (hipStream_t)stream);
+}
+
 mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)
 {
     if (!ctx) return MRSTAT_ERR_ARG;
@@ -430,6 +445,9 @@ mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec)
     if (!ctx) return MRSTAT_ERR_ARG;
     if (prec != MRSTAT_TRAINS_FP32 && prec != MRSTAT_TRAINS_FP16)
         return fail(ctx, MRSTAT_ERR_ARG, "unknown train precision");
+    if (prec == MRSTAT_TRAINS_FP16 && ctx->surr && !mlp_writes_f16(ctx->surr))
+        return fail(ctx, MRSTAT_ERR_UNSUPPORTED,
+                    "FP16 trains need a surrogate of width 64, 128 or 256 (the other widths infer in FP32)");
     ctx->f16 = prec == MRSTAT_TRAINS_FP16;
     ctx->lin_valid = false;
     return MRSTAT_OK;
@@ -451,6 +469,9 @@ mrstat_status mrstat_set_surrogate(mrstat_ctx ctx, mrstat_mlp net)
         if (!mlp_ready(net)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "surrogate network has no workspace");
         if (mlp_n_tr(net) != ctx->d.T)
             return fail(ctx, MRSTAT_ERR_SHAPE, "surrogate network was built for another number of TRs");
+        if (ctx->f16 && !mlp_writes_f16(net))
+            return fail(ctx, MRSTAT_ERR_UNSUPPORTED,
+                        "FP16 trains need a surrogate of width 64, 128 or 256 (the other widths infer in FP32)");
     }
     ctx->surr = net;
     ctx->lin_valid = false;

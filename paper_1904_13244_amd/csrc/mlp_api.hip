@@ -266,6 +266,7 @@ const float* mlp_box_lo(mrstat_mlp net) { return net->lo; }
 const float* mlp_box_hi(mrstat_mlp net) { return net->hi; }
 int mlp_n_tr(mrstat_mlp net) { return net->T; }
 bool mlp_ready(mrstat_mlp net) { return net && net->ws != nullptr; }
+bool mlp_writes_f16(mrstat_mlp net) { return infer_fused_supported(net->width, net->depth); }
 
 }  // namespace mrstat
 

@@ -96,5 +96,8 @@ const float* mlp_box_lo(mrstat_mlp net);
 const float* mlp_box_hi(mrstat_mlp net);
 int mlp_n_tr(mrstat_mlp net);
 bool mlp_ready(mrstat_mlp net);
+// True when the network's inference can store FP16 trains (the fused widths
+// 64, 128 and 256; the chunked path of other widths writes FP32 only).
+bool mlp_writes_f16(mrstat_mlp net);
 
 }  // namespace mrstat

@@ -245,7 +245,9 @@ def initial_theta(nv: int) -> np.ndarray:
 
 def config(idx: int) -> Workload:
     """The five workloads: 1 small plain case, 2 128^2 FP32 case, 3 224^2
-    precision case, 4 surrogate (224^2 sequence), 5 256^2 with 8 coils."""
+    precision case, 4 surrogate (224^2 sequence), 5 256^2 with 8 coils.
+    The two small cases hold B1 known (T1, T2, rho fitted); the three large
+    ones fit B1 as well."""
     if idx == 1:
         prob = make_problem(32, 32, 128, 32, 16, flip_deg=flips_config1(128))
         return Workload("32x32, 128 TRs, Nk 32, K 16, 1 coil", prob, iid_maps(prob.nv),
@@ -258,14 +260,15 @@ def config(idx: int) -> Workload:
     if idx in (3, 4):
         prob = make_problem(224, 224, 1120, 448, 32)
         th, head = brain_phantom(224, 224, b1_range=(0.8, 1.2))
-        # T1, T2 and rho reconstructed, B1 known (the paper's simulation setting).
+        # All five parameters reconstructed, B1 included (as for the paper's
+        # scanner data); B1-known fits pass param_mask 0b11011 themselves.
         return Workload("224x224 phantom, 1120 TRs, Nk 448, K 32", prob, th, None, None,
-                        10, 20, 0b11011, {"head": head})
+                        10, 20, 0b11111, {"head": head})
     if idx == 5:
         prob = make_problem(256, 256, 1280, 512, 32, n_coils=8)
         th, head = brain_phantom(256, 256, b1_range=(0.8, 1.2))
         return Workload("256x256 phantom, 8 coils, 1280 TRs, Nk 512, K 32, SNR 50", prob, th,
-                        coil_maps(256, 256, 8), 50.0, 15, 30, 0b11011, {"head": head})
+                        coil_maps(256, 256, 8), 50.0, 15, 30, 0b11111, {"head": head})
     raise ValueError(idx)
 
 

@@ -4,7 +4,8 @@ Data: (ln T1, ln T2, B1) drawn over the training box (T1, T2 log-uniform, B1
 uniform), their EPG trains simulated by the library itself (mrstat_simulate on
 a data-generation context with the same sequence), kept resident in HBM in
 chunks of `chunk` samples. Scaling: head scale s_p = RMS of train p over the
-first chunk (mrstat_mlp_fit_scaling). Optimisation: Adam on mini-batches
+first chunk (mrstat_mlp_fit_scaling), divided by the square root of an
+optional per-head loss weight. Optimisation: Adam on mini-batches
 (mrstat_mlp_train_step), learning rate on a cosine schedule from lr to lr_min,
 batches visited in a seeded random order each epoch. Validation: relative
 error of the predicted trains on a held-out chunk, per train.
@@ -22,6 +23,12 @@ import numpy as np
 
 from . import inputs as I
 from .binding import Context, Surrogate
+
+
+# The training recipe the benchmark and the map studies use: epochs over the
+# 2M samples and the loss weight of each train (m, dm/dlnT1, dm/dlnT2, dm/dB1).
+RECIPE_EPOCHS = 40
+RECIPE_HEAD_WEIGHT = (1.0, 1.0, 1.0, 1.0)
 
 
 @dataclass
@@ -64,7 +71,12 @@ def make_dataset(torch, prob, n_chunks, chunk, seed):
 
 def train_surrogate(torch, prob: I.Problem, n_samples=2_000_000, width=256, depth=4, batch=4096,
                     epochs=8, lr=1e-3, lr_min=1e-5, chunk=65536, seed=I.SEED_SURR,
+                    head_weight=(1.0, 1.0, 1.0, 1.0),
                     log=None) -> tuple[Surrogate, TrainReport]:
+    """head_weight[p] multiplies train p's share of the mean squared error:
+    its head scale becomes RMS_p / sqrt(head_weight[p]), so the normalised
+    targets, and the network's outputs before the scale is applied again,
+    grow by sqrt(head_weight[p])."""
     if chunk % batch:
         raise ValueError("chunk must be a multiple of batch")
     n_chunks = max(1, math.ceil(n_samples / chunk))
@@ -74,7 +86,9 @@ def train_surrogate(torch, prob: I.Problem, n_samples=2_000_000, width=256, dept
     t_data = time.perf_counter() - t0
 
     net = Surrogate(prob.n_tr, width, depth, batch)
-    scales = net.fit_scaling(trains[0], I.SURR_LO, I.SURR_HI)
+    rms = net.fit_scaling(trains[0], I.SURR_LO, I.SURR_HI)
+    scales = [r / math.sqrt(wt) for r, wt in zip(rms, head_weight)]
+    net.set_scaling(I.SURR_LO, I.SURR_HI, scales)
     net.set_params(torch.from_numpy(I.mlp_init_params(prob.n_tr, width, depth).astype(np.float32))
                    .cuda())
     per_chunk = chunk // batch

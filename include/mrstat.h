@@ -150,6 +150,27 @@ size_t mrstat_workspace_bytes(mrstat_ctx ctx);
 mrstat_status mrstat_bind(mrstat_ctx ctx, void *d_ws, size_t ws_bytes,
                           const void *d_coil, const uint8_t *d_mask, mrstat_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mrstat_bind
+ * with the library's own static workspace of MRSTAT_STATIC_WORKSPACE_BYTES
+ * (64 MiB) on the current device instead of a caller-provided one. The
+ * library allocates nothing here or later; every device the library is
+ * loaded on holds that array until the process ends. Arguments as for
+ * mrstat_bind. Errors: MRSTAT_ERR_WORKSPACE (with the bytes needed) when
+ * mrstat_workspace_bytes(ctx) exceeds the maximum; MRSTAT_ERR_HIP if the
+ * array's device address cannot be looked up.
+ * One array per device is shared by every context bound to it: a call binds
+ * ctx to it and takes it from any context bound before on that device, whose
+ * later calls then return MRSTAT_ERR_STATE (re-bind to use it again). The
+ * array keeps the last call's contents; the binding rewrites the tables and
+ * clears the device scalars, and every other part of the workspace is
+ * written before it is read. Calls on contexts of one device that overlap in
+ * time (other host threads, other streams) race on the array.
+ * Synchronises the stream. */
+#define MRSTAT_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+mrstat_status mrstat_bind_static(mrstat_ctx ctx, const void *d_coil, const uint8_t *d_mask,
+                                 mrstat_stream stream);
+
 mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc);
 /* Train storage precision (default FP32). Invalidates the linearisation. */
 mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec);

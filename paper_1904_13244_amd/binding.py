@@ -70,6 +70,7 @@ def lib():
             "mrstat_last_error": ([vp], C.c_char_p),
             "mrstat_workspace_bytes": ([vp], C.c_size_t),
             "mrstat_bind": ([vp, vp, C.c_size_t, vp, vp, vp], C.c_int),
+            "mrstat_bind_static": ([vp, vp, vp, vp], C.c_int),
             "mrstat_set_encoding": ([vp, C.c_int], C.c_int),
             "mrstat_set_epg_lanes": ([vp, i32], C.c_int),
             "mrstat_set_train_precision": ([vp, C.c_int], C.c_int),
@@ -120,7 +121,7 @@ def exported_symbols():
             "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
-            "mrstat_profile_select"]
+            "mrstat_profile_select", "mrstat_bind_static"]
 
 
 def _check(status, ctx=None):
@@ -162,6 +163,10 @@ def mrstat_workspace_bytes(ctx):
 
 def mrstat_bind(ctx, ws_ptr, ws_bytes, coil_ptr, mask_ptr, stream):
     _check(lib().mrstat_bind(ctx, ws_ptr, ws_bytes, coil_ptr, mask_ptr, stream), ctx)
+
+
+def mrstat_bind_static(ctx, coil_ptr, mask_ptr, stream):
+    _check(lib().mrstat_bind_static(ctx, coil_ptr, mask_ptr, stream), ctx)
 
 
 def mrstat_set_encoding(ctx, enc):
@@ -319,6 +324,7 @@ class Context:
     prob: object
     coil: object = None      # torch complex64 [C][Nv] on the GPU, or None
     mask: object = None      # torch uint8 [Nv] on the GPU, or None
+    static: bool = False     # True: the library's static workspace (mrstat_bind_static)
 
     def __post_init__(self):
         import torch
@@ -326,17 +332,21 @@ class Context:
         self.h = mrstat_create(self.prob)
         self.ws_bytes = mrstat_workspace_bytes(self.h)
         self.dev = torch.device("cuda", torch.cuda.current_device())
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
-        base = self.ws.data_ptr()
-        self.ws_ptr = (base + 255) // 256 * 256
         nv = self.prob.nx * self.prob.ny
         if self.coil is not None:
             self._expect(self.coil, torch.complex64, (self.prob.n_coils, nv))
         if self.mask is not None:
             self._expect(self.mask, torch.uint8, (nv,))
-        mrstat_bind(self.h, self.ws_ptr, self.ws_bytes,
-                    self.coil.data_ptr() if self.coil is not None else None,
-                    self.mask.data_ptr() if self.mask is not None else None, self.stream)
+        coil = self.coil.data_ptr() if self.coil is not None else None
+        mask = self.mask.data_ptr() if self.mask is not None else None
+        if self.static:
+            self.ws = None
+            mrstat_bind_static(self.h, coil, mask, self.stream)
+            return
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        mrstat_bind(self.h, self.ws_ptr, self.ws_bytes, coil, mask, self.stream)
 
     # -- helpers
     @property

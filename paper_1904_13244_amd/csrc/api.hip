@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,8 @@ struct mrstat_ctx_s {
     const float2* coil = nullptr;
     const uint8_t* mask = nullptr;
     bool bound = false;
+    int static_dev = -1;          // device whose static workspace this context uses (-1: none)
+    uint64_t static_gen = 0;      // claim number of that binding
     bool lin_valid = false;
     int lin_ntr = 4;              // trains of the linearisation: 4, or 3 without dm/dB1
     std::string err;
@@ -200,10 +203,48 @@ void build_tables(mrstat_ctx c, const mrstat_problem* p)
     }
 }
 
+// The library's own workspace for callers that cannot allocate device memory
+// (mrstat_bind_static). Each device the library runs on holds one copy of this
+// array from the load of the code object until the process ends. In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address comes from hipGetSymbolAddress once per device (static_ws_ptr), and
+// only that address is ever passed to kernels or copies.
+constexpr size_t kStaticWsBytes = MRSTAT_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_ptr[kMaxDevices] = {};        // device address of `scratch` per device
+uint64_t g_static_owner[kMaxDevices] = {};   // claim number of the context bound to it
+uint64_t g_static_claims = 0;
+
+// Device address of the static workspace on the current device (looked up
+// once per device, with that device current). Caller holds g_static_mu.
+hipError_t static_ws_ptr(int dev, char** out)
+{
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_static_ptr[dev];
+    return hipSuccess;
+}
+
 mrstat_status check_ready(mrstat_ctx ctx)
 {
     if (!ctx) return MRSTAT_ERR_ARG;
     if (!ctx->bound) return fail(ctx, MRSTAT_ERR_WORKSPACE, "context has no workspace (mrstat_bind)");
+    if (ctx->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[ctx->static_dev] != ctx->static_gen) {
+            ctx->bound = false;
+            return fail(ctx, MRSTAT_ERR_STATE,
+                        "the static workspace of device " + std::to_string(ctx->static_dev) +
+                            " was bound to another context since (mrstat_bind_static)");
+        }
+    }
     return MRSTAT_OK;
 }
 
@@ -428,7 +469,30 @@ mrstat_status mrstat_bind(mrstat_ctx ctx, void* d_ws, size_t ws_bytes, const voi
     if (!d_ws) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace pointer is NULL");
     if (!aligned(d_ws, 256)) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < ctx->L.total) return fail(ctx, MRSTAT_ERR_WORKSPACE, "workspace too small");
+    ctx->static_dev = -1;
     return bind_impl(ctx, (char*)d_ws, d_coil, d_mask, (hipStream_t)stream);
+}
+
+mrstat_status mrstat_bind_static(mrstat_ctx ctx, const void* d_coil, const uint8_t* d_mask,
+                                 mrstat_stream stream)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (ctx->L.total > kStaticWsBytes)
+        return fail(ctx, MRSTAT_ERR_WORKSPACE,
+                    "problem needs " + std::to_string(ctx->L.total) + " bytes of workspace; the static "
+                    "workspace holds " + std::to_string(kStaticWsBytes) + " (use mrstat_bind)");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ctx, MRSTAT_ERR_ARG, "device index out of range");
+    char* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        HIP_TRY(static_ws_ptr(dev, &ws));
+        g_static_owner[dev] = ++g_static_claims;
+        ctx->static_dev = dev;
+        ctx->static_gen = g_static_owner[dev];
+    }
+    return bind_impl(ctx, ws, d_coil, d_mask, (hipStream_t)stream);
 }
 
 mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)

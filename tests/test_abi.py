@@ -75,3 +75,18 @@ def test_workspace_and_unbound_calls():
         assert B.lib().mrstat_set_epg_lanes(h, 2) == B.OK
     finally:
         B.mrstat_destroy(h)
+
+
+def test_bind_static_refuses_oversized_workspace_on_host():
+    """The size check of mrstat_bind_static comes before any HIP call: a
+    workspace beyond MRSTAT_STATIC_WORKSPACE_BYTES (64 MiB) is refused with
+    MRSTAT_ERR_WORKSPACE and a message naming the bytes needed."""
+    h = B.mrstat_create(I.config(3).problem)
+    try:
+        need = B.mrstat_workspace_bytes(h)
+        assert need > (64 << 20)
+        assert B.lib().mrstat_bind_static(h, None, None, None) == B.ERR_WORKSPACE
+        msg = B.lib().mrstat_last_error(h).decode()
+        assert str(need) in msg and str(64 << 20) in msg
+    finally:
+        B.mrstat_destroy(h)

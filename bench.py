@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-b1-known", action="store_true",
                     help="skip the B1-known (three-train) variant")
+    ap.add_argument("--no-noncartesian", action="store_true",
+                    help="skip the golden-angle radial contraction measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--train-epochs", type=int, default=None,
@@ -208,6 +210,64 @@ def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=6, n_vox_1t=1024):
                        f"full-size Jv + J^H w pairs ({t_pairs:.2f} s); GN-amortised with n_cg = "
                        f"{n_cg}: t_step = t_lin + (n_cg + 1.5) t_pair + t_value = {t_step:.1f} s"),
             "one_thread": one, "host": _host_cpu()}
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3    # dense FP32 matrix
+
+
+def noncartesian(torch, work, reps=5):
+    """Golden-angle radial sampling of the same workload (one spoke of 448
+    samples per TR, 1120 spokes): the voxel x sample contraction on the
+    matrix cores (FP32 and split-BF16) for a cached J v + J^H w pair, timed
+    per kernel with the library's HIP-event tracing. Algorithmic work per
+    product: 8 T nk nx ny flop (complex multiply-adds); split-BF16 issues three
+    BF16 products per algorithmic one."""
+    import dataclasses
+
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd import inputs as I
+    from paper_1904_13244_amd.binding import Context
+
+    prob = dataclasses.replace(work.problem, traj=I.radial_golden(work.problem.n_tr, work.problem.n_read,
+                                                                  work.problem.nx, work.problem.ny))
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    ctx = Context(prob)
+    th = dev(work.theta, torch.float32)
+    v, w = I.probe_vectors(prob)
+    vd, wd = dev(v, torch.float32), dev(w, torch.complex64)
+    flop = 8.0 * prob.n_tr * prob.n_read * prob.nx * prob.ny
+    out = {"workload": (f"{prob.nx}x{prob.ny}, {prob.n_tr} golden-angle radial spokes of {prob.n_read} "
+                        "samples, K=32, FP32 trains"),
+           "algorithmic_flop_per_product": flop}
+    for name, enc, passes, peak in (("fp32", B.ENC_FP32, 1, FP32_MFMA_PEAK_TFLOPS),
+                                    ("split_bf16", B.ENC_SPLIT_BF16, 3, BF16_MFMA_PEAK_TFLOPS)):
+        ctx.set_encoding(enc)
+        ctx.linearise(th)
+        jv = ctx.jv(th, vd, reuse=True)
+        g = ctx.jhw(th, wd, reuse=True)
+        torch.cuda.synchronize()
+        ctx.profile_select(["nc_fwd", "nc_adj", "jhw_finish"])
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.jv(th, vd, reuse=True, out=jv)
+            ctx.jhw(th, wd, reuse=True, out=g)
+        torch.cuda.synchronize()
+        pair_ms = 1e3 * (time.perf_counter() - t0) / reps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ctx.profile_select(None)
+        res = {"pair_ms": pair_ms, "pairs_per_s": 1e3 / pair_ms}
+        for k in ("nc_fwd", "nc_adj"):
+            n, ms = prof[k]
+            t = ms / n * 1e-3
+            ach = flop / t / 1e12
+            res[k] = {"avg_ms": ms / n, "algorithmic_tflops": ach,
+                      "mfma_tflops_issued": passes * ach, "peak_tflops": peak,
+                      "frac": passes * ach / peak}
+        out[name] = res
+    ctx.close()
+    return out
 
 
 def roofline_for(kernels, prob, tb, ntr):
@@ -353,10 +413,10 @@ def main():
     surr_info = None
     if args.form in ("both", "surrogate"):
         from paper_1904_13244_amd.surrogate import train_surrogate
-        from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT
+        from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT, RECIPE_LR
         epochs = args.train_epochs or RECIPE_EPOCHS
         net, trep = train_surrogate(torch, prob, n_samples=args.train_samples, epochs=epochs,
-                                    head_weight=RECIPE_HEAD_WEIGHT)
+                                    lr=RECIPE_LR, head_weight=RECIPE_HEAD_WEIGHT)
         lo = tuple(max(a, b) for a, b in zip(I.GN_LO, I.SURR_LO))
         hi = tuple(min(a, b) for a, b in zip(I.GN_HI, I.SURR_HI))
         for mname, pm in masks.items():
@@ -368,7 +428,7 @@ def main():
         t = k["avg_ms"] * 1e-3 if k else None
         surr_info = {
             "training": {"samples": trep.n_samples, "steps": trep.steps, "batch": net.batch,
-                         "epochs": epochs, "head_weight": list(RECIPE_HEAD_WEIGHT),
+                         "epochs": epochs, "lr": RECIPE_LR, "head_weight": list(RECIPE_HEAD_WEIGHT),
                          "seconds_data": trep.seconds_data, "seconds_train": trep.seconds_train,
                          "loss_first": trep.loss_first, "loss_last": trep.loss_last,
                          "heldout_rel_err": dict(zip(["m", "dm_dlnT1", "dm_dlnT2", "dm_dB1"],
@@ -427,6 +487,8 @@ def main():
     if surr_info:
         out["surrogate"] = surr_info
     ctx.close()
+    if not args.no_noncartesian:
+        out["noncartesian"] = noncartesian(torch, work)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.n_cg)
     print(json.dumps(out), flush=True)

@@ -134,6 +134,20 @@ typedef struct {
 
 /* Validates the problem and builds the host context (no device work). */
 mrstat_status mrstat_create(const mrstat_problem *prob, mrstat_ctx *out);
+
+/* The same for non-Cartesian sampling (the method is not tied to Cartesian
+ * trajectories: Introduction, Discussion): sample k of TR n lies at
+ * (kx, ky)[n * n_read + k], host FP64 arrays in cycles per field of view
+ * (the Cartesian grid is kx = (k - n_read/2) nx / n_read, ky = l(n) - ny/2),
+ * read during the call only. The encoding phase is
+ *     E[n,k,j] = exp(-2 pi i (kx (ix - nx/2) / nx + ky (iy - ny/2) / ny))
+ * and every call of the context evaluates the voxel x sample contraction
+ * directly on the matrix cores (FP32 or split-BF16; FP16 is refused) with
+ * the phases generated on the fly; ky_line is ignored and n_read may be below
+ * nx. Requirements as mrstat_create, plus nx <= 256 (MRSTAT_ERR_SHAPE) and
+ * finite coordinates (MRSTAT_ERR_ARG). */
+mrstat_status mrstat_create_traj(const mrstat_problem *prob, const double *kx, const double *ky,
+                                 mrstat_ctx *out);
 void mrstat_destroy(mrstat_ctx ctx);
 const char *mrstat_last_error(mrstat_ctx ctx);
 
@@ -225,6 +239,58 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float *d_theta, const void *d_data,
                              const mrstat_gn_opts *opts, mrstat_gn_report *h_rep,
                              mrstat_stream stream);
 
+/* Trust-region form of the Gauss-Newton iteration (Methods, Reconstructions:
+ * the paper's trust-region framework after Steihaug and Nocedal & Wright's
+ * Algorithm 7.2, with reflection at the feasible bounds after Coleman & Li).
+ * One call: linearise at theta; r, f, g = Re(J^H r); Steihaug's truncated CG
+ * on the model m(p) = f + g'p + p' Re(J^H J) p / 2 inside ||p|| <= delta
+ * (at most n_cg iterations; stops on reaching the boundary, on non-positive
+ * curvature or on a zero residual), Euclidean norm over the parameter vector
+ * (inactive rows and masked voxels are zero); trial = theta + p with the
+ * reconstructed ln T1, ln T2, B1 entries of unmasked voxels reflected into
+ * [lo, hi] (the end point of the path bouncing off the box walls);
+ * rho = (f(theta) - f(trial)) / pred with pred = -(g's + ||J s||^2 / 2) at
+ * s = trial - theta (-infinity when pred <= 0 or rho is not finite);
+ * theta = trial when rho > eta. The radius (Nocedal & Wright Algorithm 4.1):
+ * *h_delta becomes delta / 4 when rho < 1/4, min(2 delta, delta_max) when
+ * rho > 3/4 and the CG stopped at the boundary, else stays. FP64 scalars on
+ * the device as in mrstat_gn_step. Errors: MRSTAT_ERR_ARG for options
+ * outside their ranges (n_cg >= 0, 0 <= eta < 1, 0 < delta <= delta_max,
+ * lo <= hi); MRSTAT_ERR_NONFINITE (theta and *h_delta unchanged) when f or
+ * g is not finite. Synchronises. */
+typedef struct {
+    int32_t n_cg;         /* CG iteration limit of the truncated solve */
+    int32_t param_mask;   /* bit p set = parameter p is reconstructed */
+    float lo[3], hi[3];   /* box of ln T1, ln T2, B1, kept by reflection */
+    double eta;           /* acceptance threshold on rho */
+    double delta_max;     /* cap of the trust radius */
+} mrstat_tr_opts;
+
+enum {
+    MRSTAT_TR_ITERS = 0,      /* n_cg iterations inside the region */
+    MRSTAT_TR_BOUNDARY = 1,   /* an iterate would leave the region: step on the boundary */
+    MRSTAT_TR_CURVATURE = 2,  /* non-positive curvature: step to the boundary */
+    MRSTAT_TR_ZERO = 3        /* zero residual of the model: its minimiser */
+};
+
+typedef struct {
+    double f0, f1;        /* f at the incoming theta and at the returned one */
+    double gnorm;         /* ||g|| */
+    double step_norm;     /* ||s||, s = trial - theta (after reflection) */
+    double rho;           /* actual / predicted decrease */
+    double pred;          /* predicted decrease -(g's + ||J s||^2 / 2) */
+    double delta_in, delta_out;   /* trust radius before and after */
+    int32_t cg_iters;     /* completed CG updates */
+    int32_t exit_kind;    /* MRSTAT_TR_* */
+    int32_t accepted;     /* 1 if theta was updated */
+    int32_t n_reflected;  /* trial entries that were reflected at a wall */
+    int32_t n_fallback;   /* surrogate fallbacks of the linearisation */
+} mrstat_tr_report;
+
+mrstat_status mrstat_tr_step(mrstat_ctx ctx, float *d_theta, const void *d_data,
+                             const mrstat_tr_opts *opts, double *h_delta, mrstat_tr_report *h_rep,
+                             mrstat_stream stream);
+
 /* Proton-density initialisation (Methods, Reconstructions): least-squares
  * rho solving M(alpha0) rho = d for the current (T1, T2, B1) rows of theta,
  * by n_iter CGLS iterations from rho = 0 (CGLS equals LSQR in exact
@@ -251,7 +317,9 @@ typedef enum {
     MRSTAT_K_VECTOR = 8,     /* CG / line-search / CGLS vector kernels and reductions */
     MRSTAT_K_SURR = 9,       /* surrogate inference of the linearisation's trains (+ box test) */
     MRSTAT_K_SURR_VALUE = 10,/* surrogate inference of the m train (line-search trials) */
-    MRSTAT_K_COUNT = 11
+    MRSTAT_K_NC_FWD = 11,    /* non-Cartesian forward contraction (signal, residual, J v) */
+    MRSTAT_K_NC_ADJ = 12,    /* non-Cartesian adjoint contraction with the trains */
+    MRSTAT_K_COUNT = 13
 } mrstat_kernel_kind;
 
 mrstat_status mrstat_profile_enable(mrstat_ctx ctx, int32_t on);

@@ -8,7 +8,9 @@ seeded input generators, which hold none of the method's arithmetic.
 The arithmetic lives in ``oracle.c`` (plain C99, double / double complex,
 OpenMP over independent voxels or rows). This module only marshals numpy
 arrays. Problem objects are duck-typed: anything with the attributes nx, ny,
-n_tr, n_read, n_states, n_coils, tr, te, t_inv, flip_deg, rf_phase, ky_line.
+n_tr, n_read, n_states, n_coils, tr, te, t_inv, flip_deg, rf_phase, ky_line,
+and optionally traj = (kx, ky), each [n_tr][n_read] in cycles per field of view
+(non-Cartesian sampling; None or absent = the Cartesian grid).
 
 Paper: van der Heide et al., arXiv 1904.13244 (MR-STAT, matrix-free inexact
 Gauss-Newton). Conventions: theta is [5][Nv] = (ln T1, ln T2, B1, Re rho,
@@ -44,7 +46,8 @@ class _Problem(C.Structure):
                 ("n_states", C.c_int), ("n_coils", C.c_int),
                 ("tr", C.c_double), ("te", C.c_double), ("t_inv", C.c_double),
                 ("flip_deg", C.POINTER(C.c_double)), ("rf_phase", C.POINTER(C.c_double)),
-                ("ky_line", C.POINTER(C.c_int))]
+                ("ky_line", C.POINTER(C.c_int)), ("kx", C.POINTER(C.c_double)),
+                ("ky", C.POINTER(C.c_double))]
 
 
 class _GnOpts(C.Structure):
@@ -131,11 +134,19 @@ class _Bound:
         self.ky = np.ascontiguousarray(prob.ky_line, dtype=np.int32)
         assert self.flip.shape == (prob.n_tr,) and self.phase.shape == (prob.n_tr,)
         assert self.ky.shape == (prob.n_tr,)
+        traj = getattr(prob, "traj", None)
+        kxp = kyp = None
+        if traj is not None:
+            self.kx = np.ascontiguousarray(traj[0], dtype=np.float64)
+            self.kyt = np.ascontiguousarray(traj[1], dtype=np.float64)
+            assert self.kx.shape == (prob.n_tr, prob.n_read) == self.kyt.shape
+            kxp = self.kx.ctypes.data_as(C.POINTER(C.c_double))
+            kyp = self.kyt.ctypes.data_as(C.POINTER(C.c_double))
         self.s = _Problem(prob.nx, prob.ny, prob.n_tr, prob.n_read, prob.n_states,
                           prob.n_coils, prob.tr, prob.te, prob.t_inv,
                           self.flip.ctypes.data_as(C.POINTER(C.c_double)),
                           self.phase.ctypes.data_as(C.POINTER(C.c_double)),
-                          self.ky.ctypes.data_as(C.POINTER(C.c_int)))
+                          self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp)
         self.nv = prob.nx * prob.ny
         self.prob = prob
 

@@ -220,7 +220,11 @@ void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
 /* Encoding. Voxel positions x = ix - nx/2, y = iy - ny/2 (voxel units);      */
 /* readout sample k has kx = (k - n_read/2)/n_read cycles per voxel, TR n     */
 /* samples phase-encode line ky = (l(n) - ny/2)/ny. E = exp(-2 pi i k.r).     */
+/* A non-Cartesian problem gives (kx, ky) per sample in cycles per field of   */
+/* view instead; its sums are taken directly over the voxels.                 */
 /* ------------------------------------------------------------------------ */
+
+static int non_cartesian(const oracle_problem *p) { return p->kx != NULL; }
 
 static double complex phase_x(const oracle_problem *p, int k, int ix)
 {
@@ -236,6 +240,11 @@ static double complex phase_y(const oracle_problem *p, int n, int iy)
 
 double complex oracle_phase(const oracle_problem *p, int n, int k, int ix, int iy)
 {
+    if (non_cartesian(p)) {
+        size_t s = (size_t)n * p->n_read + k;
+        return cexp(-2.0 * PI * I * (p->kx[s] * (double)(ix - p->nx / 2) / (double)p->nx +
+                                     p->ky[s] * (double)(iy - p->ny / 2) / (double)p->ny));
+    }
     double kx = (double)(k - p->n_read / 2) / (double)p->n_read;
     double ky = (double)(p->ky_line[n] - p->ny / 2) / (double)p->ny;
     return cexp(-2.0 * PI * I * (kx * (double)(ix - p->nx / 2) +
@@ -303,11 +312,39 @@ void oracle_signal_direct(const oracle_problem *p, const double *theta,
  * a weight function; shared by the signal and J v. */
 typedef double complex (*voxel_value_fn)(const void *ctx, int n, int j);
 
+/* The same sum taken directly over the voxels with the phase of each sample
+ * (any trajectory). */
+static void encode_direct(const oracle_problem *p, const double complex *coil,
+                          const unsigned char *mask, voxel_value_fn xval,
+                          const void *ctx, double complex *s)
+{
+    const int Nv = nvox(p), C = p->n_coils;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int n = 0; n < p->n_tr; ++n) {
+        double complex *x = (double complex *)malloc((size_t)Nv * sizeof(double complex));
+        for (int j = 0; j < Nv; ++j) x[j] = active(mask, j) ? xval(ctx, n, j) : 0.0;
+        for (int c = 0; c < C; ++c)
+            for (int k = 0; k < p->n_read; ++k) {
+                double complex acc = 0.0;
+                for (int j = 0; j < Nv; ++j)
+                    if (active(mask, j))
+                        acc += coil_at(coil, c, Nv, j) * x[j] *
+                               oracle_phase(p, n, k, j % p->nx, j / p->nx);
+                s[((size_t)c * p->n_tr + n) * p->n_read + k] = acc;
+            }
+        free(x);
+    }
+}
+
 static void encode_separable(const oracle_problem *p, const double complex *coil,
                              const unsigned char *mask, voxel_value_fn xval,
                              const void *ctx, double complex *s)
 {
     const int Nv = nvox(p), C = p->n_coils;
+    if (non_cartesian(p)) {
+        encode_direct(p, coil, mask, xval, ctx, s);
+        return;
+    }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int n = 0; n < p->n_tr; ++n) {
         double complex *U = (double complex *)calloc((size_t)C * p->nx, sizeof(double complex));
@@ -382,6 +419,24 @@ static void adjoint_encode(const oracle_problem *p, const double complex *coil,
                            double complex *V)
 {
     const int Nv = nvox(p), C = p->n_coils;
+    if (non_cartesian(p)) {
+        /* Direct: V[n][j] = sum_c conj(C_c[j]) sum_k conj(E[n,k,j]) w_c[n,k]. */
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int n = 0; n < p->n_tr; ++n)
+            for (int j = 0; j < Nv; ++j) {
+                double complex acc = 0.0;
+                if (active(mask, j))
+                    for (int c = 0; c < C; ++c) {
+                        double complex sc = 0.0;
+                        for (int k = 0; k < p->n_read; ++k)
+                            sc += conj(oracle_phase(p, n, k, j % p->nx, j / p->nx)) *
+                                  w[((size_t)c * p->n_tr + n) * p->n_read + k];
+                        acc += conj(coil_at(coil, c, Nv, j)) * sc;
+                    }
+                V[(size_t)n * Nv + j] = acc;
+            }
+        return;
+    }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int n = 0; n < p->n_tr; ++n) {
         double complex *W = (double complex *)calloc((size_t)C * p->nx, sizeof(double complex));

@@ -42,6 +42,11 @@ typedef struct {
     const double *flip_deg;   /* [n_tr] flip angle per TR, degrees */
     const double *rf_phase;   /* [n_tr] RF phase per TR, radians */
     const int *ky_line;       /* [n_tr] phase-encode line sampled in each TR */
+    /* Non-Cartesian sampling (Introduction and Discussion: the method is not
+     * tied to Cartesian trajectories): when kx is not NULL, sample k of TR n
+     * sits at (kx, ky)[n * n_read + k] in cycles per field of view, and the
+     * encoding is evaluated as a direct sum; ky_line is then unused. */
+    const double *kx, *ky;
 } oracle_problem;
 
 typedef struct {
@@ -66,7 +71,10 @@ int oracle_num_threads(void);
 void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
                 double complex *trains);
 
-/* Encoding phase E[n,k,j] of sample k of the readout in TR n for voxel j. */
+/* Encoding phase E[n,k,j] of sample k of the readout in TR n for voxel j:
+ * exp(-2 pi i (kx (ix - nx/2) / nx + ky (iy - ny/2) / ny)) with (kx, ky) in
+ * cycles per field of view; on the Cartesian grid kx = (k - n_read/2) nx /
+ * n_read and ky = l(n) - ny/2. */
 double complex oracle_phase(const oracle_problem *p, int n, int k, int ix, int iy);
 
 /* All phases of TR n: out[k][j] = E[n,k,j], [n_read][Nv]. */

@@ -53,6 +53,24 @@ class GnReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrOpts(C.Structure):
+    _fields_ = [("n_cg", C.c_int32), ("param_mask", C.c_int32), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3), ("eta", C.c_double), ("delta_max", C.c_double)]
+
+
+class TrReport(C.Structure):
+    _fields_ = [("f0", C.c_double), ("f1", C.c_double), ("gnorm", C.c_double),
+                ("step_norm", C.c_double), ("rho", C.c_double), ("pred", C.c_double),
+                ("delta_in", C.c_double), ("delta_out", C.c_double), ("cg_iters", C.c_int32),
+                ("exit_kind", C.c_int32), ("accepted", C.c_int32), ("n_reflected", C.c_int32),
+                ("n_fallback", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+TR_ITERS, TR_BOUNDARY, TR_CURVATURE, TR_ZERO = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -66,6 +84,7 @@ def lib():
         vp, i32, P = C.c_void_p, C.c_int32, C.POINTER
         sig = {
             "mrstat_create": ([P(Problem), P(vp)], C.c_int),
+            "mrstat_create_traj": ([P(Problem), vp, vp, P(vp)], C.c_int),
             "mrstat_destroy": ([vp], None),
             "mrstat_last_error": ([vp], C.c_char_p),
             "mrstat_workspace_bytes": ([vp], C.c_size_t),
@@ -80,6 +99,7 @@ def lib():
             "mrstat_jhw": ([vp, vp, i32, vp, vp, vp], C.c_int),
             "mrstat_gn_step": ([vp, vp, vp, P(GnOpts), P(GnReport), vp], C.c_int),
             "mrstat_rho_init": ([vp, vp, vp, i32, vp], C.c_int),
+            "mrstat_tr_step": ([vp, vp, vp, P(TrOpts), P(C.c_double), P(TrReport), vp], C.c_int),
             "mrstat_profile_enable": ([vp, i32], C.c_int),
             "mrstat_profile_read": ([vp, P(i32), P(C.c_double)], C.c_int),
             "mrstat_profile_select": ([vp, C.c_uint32], C.c_int),
@@ -121,7 +141,7 @@ def exported_symbols():
             "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
-            "mrstat_profile_select", "mrstat_bind_static"]
+            "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj"]
 
 
 def _check(status, ctx=None):
@@ -139,7 +159,9 @@ def _check_mlp(status, net):
 # --------------------------------------------------------------- C-named calls
 def mrstat_create(prob):
     """prob: object with nx, ny, n_tr, n_read, n_states, n_coils, tr, te, t_inv,
-    flip_deg, rf_phase, ky_line. Returns (ctx handle, keep-alive arrays)."""
+    flip_deg, rf_phase, ky_line and optionally traj = (kx, ky) [n_tr][n_read]
+    cycles per field of view (non-Cartesian: mrstat_create_traj). Returns
+    the context handle."""
     flip = np.ascontiguousarray(prob.flip_deg, dtype=np.float64)
     phase = np.ascontiguousarray(prob.rf_phase, dtype=np.float64)
     ky = np.ascontiguousarray(prob.ky_line, dtype=np.int32)
@@ -149,7 +171,15 @@ def mrstat_create(prob):
                 phase.ctypes.data_as(C.POINTER(C.c_double)),
                 ky.ctypes.data_as(C.POINTER(C.c_int32)))
     h = C.c_void_p()
-    _check(lib().mrstat_create(C.byref(s), C.byref(h)))
+    traj = getattr(prob, "traj", None)
+    if traj is None:
+        _check(lib().mrstat_create(C.byref(s), C.byref(h)))
+    else:
+        kx = np.ascontiguousarray(traj[0], dtype=np.float64)
+        ky = np.ascontiguousarray(traj[1], dtype=np.float64)
+        if kx.shape != (prob.n_tr, prob.n_read) or ky.shape != kx.shape:
+            raise ValueError("trajectory arrays must be [n_tr][n_read]")
+        _check(lib().mrstat_create_traj(C.byref(s), kx.ctypes.data, ky.ctypes.data, C.byref(h)))
     return h
 
 
@@ -204,6 +234,15 @@ def mrstat_gn_step(ctx, theta_ptr, data_ptr, opts: GnOpts, stream) -> GnReport:
     rep = GnReport()
     _check(lib().mrstat_gn_step(ctx, theta_ptr, data_ptr, C.byref(opts), C.byref(rep), stream), ctx)
     return rep
+
+
+def mrstat_tr_step(ctx, theta_ptr, data_ptr, opts: TrOpts, delta, stream):
+    """Returns (new trust radius, TrReport)."""
+    rep = TrReport()
+    dl = C.c_double(delta)
+    _check(lib().mrstat_tr_step(ctx, theta_ptr, data_ptr, C.byref(opts), C.byref(dl), C.byref(rep),
+                                stream), ctx)
+    return dl.value, rep
 
 
 def mrstat_rho_init(ctx, theta_ptr, data_ptr, n_iter, stream):
@@ -294,7 +333,7 @@ def mrstat_mlp_predict(net, theta_ptr, ld_theta, n, out_ptr, stream):
 
 KERNEL_KINDS = ["epg", "epg_value", "ystage_fwd_signal", "ystage_fwd_jv", "xgemm_fwd",
                 "xgemm_adj", "ystage_adj", "jhw_finish", "vector", "surrogate",
-                "surrogate_value"]
+                "surrogate_value", "nc_fwd", "nc_adj"]
 
 
 def mrstat_profile_enable(ctx, on):
@@ -451,6 +490,15 @@ class Context:
         o = GnOpts(int(n_cg), int(n_ls_max), int(param_mask), (C.c_float * 3)(*lo),
                    (C.c_float * 3)(*hi), float(armijo_c1))
         return mrstat_gn_step(self.h, theta.data_ptr(), data.data_ptr(), o, self.stream)
+
+    def tr_step(self, theta, data, delta, n_cg, param_mask, lo, hi, eta=0.1, delta_max=1e3):
+        """One trust-region step; returns (new radius, TrReport)."""
+        T = self.torch
+        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(data, T.complex64, self.data_shape)
+        o = TrOpts(int(n_cg), int(param_mask), (C.c_float * 3)(*lo), (C.c_float * 3)(*hi),
+                   float(eta), float(delta_max))
+        return mrstat_tr_step(self.h, theta.data_ptr(), data.data_ptr(), o, float(delta), self.stream)
 
     def rho_init(self, theta, data, n_iter=20):
         T = self.torch

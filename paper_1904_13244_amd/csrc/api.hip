@@ -25,6 +25,7 @@ struct Layout {
     size_t bf[2][2];   // B-fragment tables [direction][split-BF16, FP16]
     size_t hbuf;       // surrogate hidden activations, BF16 [nv][256]
     size_t cx, csv, cp, cth, fb, total;
+    size_t ax, ay;     // non-Cartesian trajectory tables, FP64 [T][nk] (0 bytes otherwise)
     int n_red;
     YPlan yp;
 };
@@ -39,6 +40,8 @@ struct mrstat_ctx_s {
     std::vector<float2> seq;      // (flip [rad], RF sign)
     std::vector<float2> eytab;    // [T][ny]
     std::vector<float2> extab;    // [nk][nx]
+    bool nc = false;              // non-Cartesian trajectory (kx, ky per sample)
+    std::vector<double> ax, ay;   // [T][nk] kx / nx, ky / ny
     Layout L{};
     mrstat_enc enc = MRSTAT_ENC_FP32;
     int epg_lanes = 0;
@@ -77,6 +80,8 @@ struct mrstat_ctx_s {
     const float2* dseq() const { return at<float2>(L.seq); }
     const float2* deytab() const { return at<float2>(L.eytab); }
     const float2* dextab() const { return at<float2>(L.extab); }
+    const double* dax() const { return at<double>(L.ax); }
+    const double* day() const { return at<double>(L.ay); }
     // B-fragment table of the current encoding for direction dir (null for FP32).
     const void* bfrag(int dir) const { return enc == 0 ? nullptr : (const void*)(ws + L.bf[dir][enc - 1]); }
     int* fb_count(int slot) const { return at<int>(L.fb) + slot; }   // 0: linearisation, 1: value
@@ -136,13 +141,19 @@ hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
 
 #define TRACED(kind, call) traced(ctx, (kind), s, [&]() { return (call); })
 
-Layout make_layout(const Dims& d)
+Layout make_layout(const Dims& d, bool nc)
 {
     Layout L{};
     L.yp = make_yplan(d);
+    if (nc) {
+        // The non-Cartesian adjoint's TR chunks replace the y-stage's in the
+        // partial-sum layout the gradient assembly reads.
+        const int per = ceil_div(d.T, nc_adj_chunks(d));
+        L.yp.adj_chunks = ceil_div(d.T, per);
+    }
     const int M = d.C * d.T;
     const int gemm_blocks = std::max(ceil_div(2 * d.nk, 64) * ceil_div(M, 64), xgemm_direct_blocks(d));
-    L.n_red = std::max({3 * RED_BLOCKS, gemm_blocks, cg_partials(d)});
+    L.n_red = std::max({3 * RED_BLOCKS, gemm_blocks, cg_partials(d), tr_partials(d), nc ? nc_fwd_blocks(d) : 0});
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     const size_t nv = d.nv, T = d.T;
@@ -167,6 +178,8 @@ Layout make_layout(const Dims& d)
     L.cth = take(5 * nv * sizeof(float));
     L.fb = take((64 + nv) * sizeof(int));
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
+    L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
+    L.ay = take(nc ? T * d.nk * sizeof(double) : 0);
     L.total = o;
     return L;
 }
@@ -302,6 +315,15 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
+    if (ctx->nc) {
+        int nred = 0;
+        HIP_TRY(TRACED(MRSTAT_K_NC_FWD, launch_nc_fwd(d, ctx->enc, mode_y, mode_x, trains, ctx->f16, theta, v,
+                                                      ctx->coil, ctx->mask, ctx->dax(), ctx->day(),
+                                                      (const float2*)data, (float2*)out, ctx->red(), &nred, s)));
+        if (mode_x == 0 && f_out)
+            HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_sum_partials(ctx->red(), nred, f_out, s)));
+        return MRSTAT_OK;
+    }
     int nby = 1;
     HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
                    launch_ystage_fwd(d, p, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask,
@@ -320,19 +342,27 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
 // of dir . g in ctx->red(). Without the dm/dB1 train (a linearisation with 3
 // trains) B1 must lie outside param_mask.
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, int param_mask,
-                      hipStream_t s, const float* dir = nullptr)
+                      hipStream_t s, const float* dir = nullptr, const float* step = nullptr)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
     const int ntr = ctx->lin_ntr;
     if (ntr < 4 && ((param_mask >> 2) & 1))
         return fail(ctx, MRSTAT_ERR_STATE, "linearisation holds no dm/dB1 train");
+    if (ctx->nc) {
+        HIP_TRY(TRACED(MRSTAT_K_NC_ADJ, launch_nc_adj(d, ctx->enc, ntr, p.adj_chunks, ctx->trains(), ctx->f16,
+                                                      ctx->coil, ctx->mask, ctx->dax(), ctx->day(),
+                                                      (const float2*)w, ctx->apart(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
+                                                          dir, dir ? ctx->red() : nullptr, s, step)));
+        return MRSTAT_OK;
+    }
     HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
                                                    ctx->bfrag(1), ctx->W(), s)));
     HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, ntr, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
     HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
-                                                      dir, dir ? ctx->red() : nullptr, s)));
+                                                      dir, dir ? ctx->red() : nullptr, s, step)));
     return MRSTAT_OK;
 }
 
@@ -340,15 +370,28 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
 
 extern "C" {
 
-mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
+}  // extern "C"
+
+namespace {
+
+mrstat_status create_impl(const mrstat_problem* p, const double* kx, const double* ky, mrstat_ctx* out)
 {
     mrstat_ctx ctx = nullptr;
     if (!p || !out) return fail(nullptr, MRSTAT_ERR_ARG, "null problem or output pointer");
     *out = nullptr;
+    const bool nc = kx != nullptr || ky != nullptr;
+    if (nc) {
+        if (!kx || !ky) return fail(nullptr, MRSTAT_ERR_ARG, "kx and ky must both be given");
+        if (p->nx > 256) return fail(nullptr, MRSTAT_ERR_SHAPE, "non-Cartesian encoding needs nx <= 256");
+        if (p->n_tr >= 1 && p->n_read >= 1)
+            for (size_t i = 0; i < (size_t)p->n_tr * p->n_read; ++i)
+                if (!std::isfinite(kx[i]) || !std::isfinite(ky[i]))
+                    return fail(nullptr, MRSTAT_ERR_ARG, "non-finite trajectory coordinate");
+    }
     if (!p->flip_deg) return fail(nullptr, MRSTAT_ERR_ARG, "flip_deg is NULL");
     if (p->nx < 1 || p->ny < 1 || p->n_tr < 1 || p->n_read < 1)
         return fail(nullptr, MRSTAT_ERR_SHAPE, "sizes must be positive");
-    if (p->n_read < p->nx) return fail(nullptr, MRSTAT_ERR_SHAPE, "n_read must be >= nx");
+    if (!nc && p->n_read < p->nx) return fail(nullptr, MRSTAT_ERR_SHAPE, "n_read must be >= nx");
     if (p->n_states < 1 || p->n_states > 64)
         return fail(nullptr, MRSTAT_ERR_SHAPE, "n_states must be in [1, 64]");
     if (p->n_coils < 1 || p->n_coils > 16)
@@ -360,7 +403,7 @@ mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
         return fail(nullptr, MRSTAT_ERR_ARG, "timing must satisfy 0 <= te <= tr, tr > 0, t_inv >= 0");
     for (int n = 0; n < p->n_tr; ++n) {
         if (!std::isfinite(p->flip_deg[n])) return fail(nullptr, MRSTAT_ERR_ARG, "non-finite flip angle");
-        if (p->ky_line && (p->ky_line[n] < 0 || p->ky_line[n] >= p->ny))
+        if (!nc && p->ky_line && (p->ky_line[n] < 0 || p->ky_line[n] >= p->ny))
             return fail(nullptr, MRSTAT_ERR_ARG, "ky_line out of [0, ny)");
         if (p->rf_phase_rad) {
             const double ph = p->rf_phase_rad[n];
@@ -374,10 +417,43 @@ mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
     if (!ctx) return fail(nullptr, MRSTAT_ERR_ARG, "out of host memory");
     ctx->d = Dims{p->nx, p->ny, p->nx * p->ny, p->n_tr, p->n_read, p->n_states, p->n_coils};
     ctx->st = SeqTimes{(float)p->tr_s, (float)p->te_s, (float)p->t_inv_s};
-    build_tables(ctx, p);
-    ctx->L = make_layout(ctx->d);
+    if (nc) {
+        // The Cartesian tables are built for a ky_line of n mod ny (unused).
+        mrstat_problem q = *p;
+        q.ky_line = nullptr;
+        build_tables(ctx, &q);
+        ctx->nc = true;
+        const size_t ns = (size_t)p->n_tr * p->n_read;
+        ctx->ax.resize(ns);
+        ctx->ay.resize(ns);
+        for (size_t i = 0; i < ns; ++i) {
+            ctx->ax[i] = kx[i] / (double)p->nx;
+            ctx->ay[i] = ky[i] / (double)p->ny;
+        }
+    } else {
+        build_tables(ctx, p);
+    }
+    ctx->L = make_layout(ctx->d, nc);
     *out = ctx;
     return MRSTAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrstat_status mrstat_create(const mrstat_problem* p, mrstat_ctx* out)
+{
+    return create_impl(p, nullptr, nullptr, out);
+}
+
+mrstat_status mrstat_create_traj(const mrstat_problem* p, const double* kx, const double* ky, mrstat_ctx* out)
+{
+    if (!kx || !ky) {
+        if (out) *out = nullptr;
+        return fail(nullptr, MRSTAT_ERR_ARG, "kx or ky is NULL");
+    }
+    return create_impl(p, kx, ky, out);
 }
 
 void mrstat_destroy(mrstat_ctx ctx)
@@ -449,6 +525,12 @@ mrstat_status bind_impl(mrstat_ctx ctx, char* ws, const void* d_coil, const uint
                            ctx->eytab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.extab, ctx->extab.data(),
                            ctx->extab.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    if (ctx->nc) {
+        HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.ax, ctx->ax.data(), ctx->ax.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.ay, ctx->ay.data(), ctx->ay.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(launch_build_bfrag(ctx->d, ctx->dextab(), ctx->ws + ctx->L.bf[0][0], ctx->ws + ctx->L.bf[1][0],
                                ctx->ws + ctx->L.bf[0][1], ctx->ws + ctx->L.bf[1][1], s));
     // Device scalars start from zero.
@@ -500,6 +582,8 @@ mrstat_status mrstat_set_encoding(mrstat_ctx ctx, mrstat_enc enc)
     if (!ctx) return MRSTAT_ERR_ARG;
     if (enc != MRSTAT_ENC_FP32 && enc != MRSTAT_ENC_SPLIT_BF16 && enc != MRSTAT_ENC_FP16)
         return fail(ctx, MRSTAT_ERR_ARG, "unknown encoding precision");
+    if (ctx->nc && enc == MRSTAT_ENC_FP16)
+        return fail(ctx, MRSTAT_ERR_UNSUPPORTED, "non-Cartesian encoding runs in FP32 or split-BF16");
     ctx->enc = enc;
     return MRSTAT_OK;
 }
@@ -716,6 +800,101 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     return MRSTAT_OK;
 }
 
+mrstat_status mrstat_tr_step(mrstat_ctx ctx, float* d_theta, const void* d_data, const mrstat_tr_opts* o,
+                             double* h_delta, mrstat_tr_report* rep, mrstat_stream stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    mrstat_status st = check_ready(ctx);
+    if (st != MRSTAT_OK) return st;
+    if (!d_theta || !d_data || !o || !h_delta || !rep) return fail(ctx, MRSTAT_ERR_ARG, "null argument");
+    if (!aligned(d_data, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
+    const double delta = *h_delta;
+    if (o->n_cg < 0 || o->param_mask < 0 || o->param_mask > 31 || !(o->eta >= 0.0 && o->eta < 1.0) ||
+        !(o->delta_max > 0.0) || !std::isfinite(o->delta_max) || !(delta > 0.0) || !(delta <= o->delta_max))
+        return fail(ctx, MRSTAT_ERR_ARG, "invalid trust-region options or radius");
+    for (int q = 0; q < 3; ++q)
+        if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    std::memset(rep, 0, sizeof(*rep));
+    rep->delta_in = delta;
+    rep->delta_out = delta;
+    const Dims& d = ctx->d;
+    float* g = ctx->vec(0);
+    float* step = ctx->vec(1);
+    float* res = ctx->vec(2);
+    float* dir = ctx->vec(3);
+    float* q = ctx->vec(4);
+    float* trial = ctx->vec(5);
+    float* sv = q;   // q is free once CG has ended
+    double* sc = ctx->scal();
+
+    // Linearise at theta; r, f, g = Re(J^H r) (no dm/dB1 train with B1 fixed).
+    const int ntr = ((o->param_mask >> 2) & 1) ? 4 : 3;
+    const int mode_jv = ntr == 4 ? 1 : 3;
+    st = linearise(ctx, d_theta, s, ntr);
+    if (st != MRSTAT_OK) return st;
+    st = forward(ctx, 0, 0, ctx->trains(), d_theta, nullptr, d_data, ctx->r(), sc + SC_F0, s);
+    if (st != MRSTAT_OK) return st;
+    st = adjoint(ctx, d_theta, ctx->r(), g, o->param_mask, s);
+    if (st != MRSTAT_OK) return st;
+
+    // Steihaug CG inside ||p|| <= delta.
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_init(d, g, step, res, dir, sc, ctx->red(), s)));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_init(sc, delta * delta, s)));
+    for (int it = 0; it < o->n_cg; ++it) {
+        st = forward(ctx, mode_jv, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
+        if (st != MRSTAT_OK) return st;
+        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s, dir, step);
+        if (st != MRSTAT_OK) return st;
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_update(d, q, step, res, dir, sc, ctx->red(), it, s)));
+    }
+
+    // Trial point reflected into the box, the model's predicted decrease at
+    // s = trial - theta (g . s and |J s|^2 at the linearisation), f(trial).
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_trial(d, d_theta, step, o->lo, o->hi, o->param_mask, ctx->mask,
+                                                    trial, sv, sc, ctx->red(), s)));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_dot(g, sv, (size_t)5 * d.nv, ctx->red(), sc + SC_GS, s)));
+    st = forward(ctx, mode_jv, 1, ctx->trains(), d_theta, sv, nullptr, ctx->y(), nullptr, s);
+    if (st != MRSTAT_OK) return st;
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_dot_c(ctx->y(), ctx->y(), (size_t)d.C * d.T * d.nk, ctx->red(),
+                                                 sc + SC_JS2, s)));
+    st = simulate_into(ctx, trial, ctx->trial_m(), 1, 1, s);
+    if (st != MRSTAT_OK) return st;
+    st = forward(ctx, 0, 0, ctx->trial_m(), trial, nullptr, d_data, ctx->y(), sc + SC_FT, s);
+    if (st != MRSTAT_OK) return st;
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_accept(d, sc, o->eta, trial, d_theta, s)));
+
+    double hs[48];
+    int32_t nfb = 0;
+    HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+    if (ctx->surr) HIP_TRY(hipMemcpyAsync(&nfb, ctx->fb_count(0), sizeof(nfb), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rep->f0 = 0.5 * hs[SC_F0];
+    rep->gnorm = std::sqrt(hs[SC_G2]);
+    rep->cg_iters = (int32_t)hs[SC_ITERS];
+    rep->exit_kind = (int32_t)hs[SC_EXIT];
+    rep->n_reflected = (int32_t)hs[SC_NREF];
+    rep->n_fallback = nfb;
+    rep->pred = hs[SC_PRED];
+    rep->rho = hs[SC_RHO];
+    rep->step_norm = std::sqrt(hs[SC_SS]);
+    rep->accepted = hs[SC_ACC] != 0.0;
+    rep->f1 = rep->accepted ? 0.5 * hs[SC_FT] : rep->f0;
+    // A non-finite f0 or gradient gives a ratio of -inf, so theta is
+    // unchanged; the radius is kept.
+    if (!std::isfinite(rep->f0) || !std::isfinite(rep->gnorm))
+        return fail(ctx, MRSTAT_ERR_NONFINITE, "objective or gradient is not finite");
+    const bool at_boundary = rep->exit_kind == MRSTAT_TR_BOUNDARY || rep->exit_kind == MRSTAT_TR_CURVATURE;
+    double nd = delta;
+    if (rep->rho < 0.25)
+        nd = 0.25 * delta;
+    else if (rep->rho > 0.75 && at_boundary)
+        nd = std::min(2.0 * delta, o->delta_max);
+    rep->delta_out = nd;
+    *h_delta = nd;
+    if (rep->accepted) ctx->lin_valid = false;
+    return MRSTAT_OK;
+}
+
 mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data, int32_t n_iter,
                               mrstat_stream stream)
 {
@@ -739,9 +918,16 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     // M^H w for the rho-linear map: adjoint y-stage on the m train only.
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
         const YPlan& p = ctx->L.yp;
-        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->bfrag(1), ctx->W(), s)));
-        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 1, ctx->coil, ctx->mask,
-                                                        ctx->deytab(), ctx->W(), ctx->apart(), s)));
+        if (ctx->nc) {
+            HIP_TRY(TRACED(MRSTAT_K_NC_ADJ, launch_nc_adj(d, ctx->enc, 1, p.adj_chunks, ctx->trains(), ctx->f16,
+                                                          ctx->coil, ctx->mask, ctx->dax(), ctx->day(), w,
+                                                          ctx->apart(), s)));
+        } else {
+            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, w, ctx->dextab(), ctx->bfrag(1),
+                                                           ctx->W(), s)));
+            HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, 1, ctx->coil,
+                                                            ctx->mask, ctx->deytab(), ctx->W(), ctx->apart(), s)));
+        }
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_rho_adj_finish(d, p, ctx->apart(), ctx->mask, out, s)));
         return MRSTAT_OK;
     };

@@ -916,16 +916,19 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 
 // g from A: g_q = -Im(conj(rho) A_{q+1}) for q = lnT1, lnT2, B1;
 // g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho).
-template <bool CURV>
+// CURV: 0 = gradient only; 1 = also the CG curvature partials dir . g and
+// dir . dir; 2 = also step . dir (the trust-region CG's boundary test).
+template <int CURV>
 __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
                                                          const float* __restrict__ theta,
                                                          const uint8_t* __restrict__ mask, int param_mask,
                                                          float* __restrict__ g, int nv,
                                                          const float* __restrict__ dir,
+                                                         const float* __restrict__ step,
                                                          double* __restrict__ part)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    double cd = 0.0, dd = 0.0;
+    double cd = 0.0, dd = 0.0, sd = 0.0;
     if (j < nv) {
         const bool on = mask == nullptr || mask[j] != 0;
         const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
@@ -971,30 +974,36 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             g[(size_t)q * nv + j] = gq[q];
-            if constexpr (CURV) {
+            if constexpr (CURV > 0) {
                 const double dv = dir[(size_t)q * nv + j];
                 cd += dv * (double)gq[q];
                 dd += dv * dv;
+                if constexpr (CURV > 1) sd += (double)step[(size_t)q * nv + j] * dv;
             }
         }
     }
-    if constexpr (CURV) {
-        // CG curvature partials of this block's voxels, dir . g and dir . dir
-        // in FP64, one pair per block (all threads reach the barrier).
-        __shared__ double sh[2][4];
+    if constexpr (CURV > 0) {
+        // CG curvature partials of this block's voxels (dir . g, dir . dir
+        // and, for the trust region, step . dir) in FP64, one per block and
+        // kind (all threads reach the barrier).
+        __shared__ double sh[3][4];
         for (int off = 32; off > 0; off >>= 1) {
             cd += __shfl_xor(cd, off);
             dd += __shfl_xor(dd, off);
+            if constexpr (CURV > 1) sd += __shfl_xor(sd, off);
         }
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0) {
             sh[0][wave] = cd;
             sh[1][wave] = dd;
+            sh[2][wave] = sd;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             part[blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
             part[gridDim.x + blockIdx.x] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+            if constexpr (CURV > 1)
+                part[2 * gridDim.x + blockIdx.x] = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
         }
     }
 }
@@ -1821,14 +1830,18 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, int param_mask, float* g, const float* dir,
-                             double* part, hipStream_t s)
+                             double* part, hipStream_t s, const float* step)
 {
-    if (dir != nullptr)
-        jhw_finish_kernel<true><<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask,
-                                                                   param_mask, g, d.nv, dir, part);
+    const int nb = ceil_div(d.nv, 256);
+    if (dir != nullptr && step != nullptr)
+        jhw_finish_kernel<2><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
+                                                dir, step, part);
+    else if (dir != nullptr)
+        jhw_finish_kernel<1><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
+                                                dir, nullptr, part);
     else
-        jhw_finish_kernel<false><<<ceil_div(d.nv, 256), 256, 0, s>>>(apart, p.adj_chunks, theta, mask,
-                                                                    param_mask, g, d.nv, nullptr, nullptr);
+        jhw_finish_kernel<0><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
+                                                nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 

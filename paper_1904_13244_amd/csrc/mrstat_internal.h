@@ -17,6 +17,24 @@ struct Dims {
     int C;            // coils
 };
 
+// ---------------------------------------------------------------- non-Cartesian
+// Encoding by an arbitrary trajectory (noncart.hip): ax, ay [T][nk] FP64 =
+// kx / nx and ky / ny (kx, ky in cycles per field of view); nx <= 256.
+// Forward: mode_y 0 (signal, m train) or 1 / 3 (J v direction, with or
+// without dm/dB1); mode_x as for launch_xgemm_fwd (0 residual with FP64
+// partials into red, their count in *nred; 1 -s; 2 s). enc 0 FP32 MFMA, 1
+// split-BF16 MFMA. Adjoint: chunk partials of A_p = sum_n mu_p V (ntr 4, 3
+// or 1) in the Cartesian adjoint's layout, with `chunks` TR chunks.
+int nc_adj_chunks(const Dims& d);
+int nc_fwd_blocks(const Dims& d);
+hipError_t launch_nc_fwd(const Dims& d, int enc, int mode_y, int mode_x, const void* trains, bool f16,
+                         const float* theta, const float* v, const float2* coil, const uint8_t* mask,
+                         const double* ax, const double* ay, const float2* data, float2* out, double* red,
+                         int* nred, hipStream_t s);
+hipError_t launch_nc_adj(const Dims& d, int enc, int ntr, int chunks, const void* trains, bool f16,
+                         const float2* coil, const uint8_t* mask, const double* ax, const double* ay,
+                         const float2* w, float* apart, hipStream_t s);
+
 // Per-voxel EPG timing constants shared by all voxels.
 struct SeqTimes {
     float tr, te, tinv;
@@ -115,10 +133,11 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 // parameters outside param_mask (and masked voxels) are zero, and the dm/dB1
 // partials are read only when B1 is in param_mask.
 // With dir non-null, also the CG curvature partials dir . g and dir . dir
-// (FP64, ceil(nv / 256) pairs: part[b] and part[nblocks + b]).
+// (FP64, one per block of 256 voxels: part[b] and part[nblocks + b]); with
+// step non-null as well, step . dir in part[2 nblocks + b].
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, int param_mask, float* g, const float* dir,
-                             double* part, hipStream_t s);
+                             double* part, hipStream_t s, const float* step = nullptr);
 
 // CGLS helper: A^H w = -i A_0 from the one-train partials.
 hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
@@ -138,7 +157,11 @@ hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* part
 constexpr int SCAL_DOUBLES = 64;
 enum : int {
     SC_RR = 0, SC_ITERS = 6, SC_F0 = 8, SC_G2 = 9, SC_PRED = 10, SC_SN = 11, SC_ACC = 13, SC_FT = 14,
-    SC_STAGE = 30, SC_CDONE = 25
+    SC_STAGE = 30, SC_CDONE = 25,
+    // trust-region step: |step|^2, radius^2, exit kind, g . s, |J s|^2,
+    // reflected entries, ratio, |s|^2
+    SC_ZZ = 32, SC_DELTA2 = 33, SC_EXIT = 35, SC_GS = 36, SC_JS2 = 37, SC_NREF = 38,
+    SC_SS = 39, SC_RHO = 40
 };
 
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
@@ -149,6 +172,29 @@ hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s);
 int cg_partials(const Dims& d);
+
+// Trust-region CG (Steihaug): after launch_cg_init, launch_tr_init sets
+// |step|^2 = 0, the radius^2 and the exit kind (zero gradient or not).
+// launch_tr_update is one iteration after q = Re(J^H J) dir with the finish
+// kernel's three curvature partials (dir . q, dir . dir, step . dir): an
+// iterate that would leave the region, or a direction of non-positive
+// curvature, moves the step to the boundary and stops CG (exit kind in
+// SC_EXIT: 0 iteration count, 1 boundary, 2 curvature, 3 zero residual).
+hipError_t launch_tr_init(double* scal, double delta2, hipStream_t s);
+hipError_t launch_tr_update(const Dims& d, const float* q, float* step, float* res, float* dir,
+                            double* scal, double* partials, int iter, hipStream_t s);
+int tr_partials(const Dims& d);
+// trial = theta + step with the active ln T1, ln T2, B1 of unmasked voxels
+// reflected into [lo, hi] (a fold at the walls); sv = trial - theta; the
+// number of reflected entries to SC_NREF and |sv|^2 to SC_SS.
+hipError_t launch_tr_trial(const Dims& d, const float* theta, const float* step, const float* lo,
+                           const float* hi, int param_mask, const uint8_t* mask, float* trial,
+                           float* sv, double* scal, double* partials, hipStream_t s);
+// ratio = (f0 - ft) / (-(g . s + |J s|^2 / 2)) from the scalars (SC_F0 and
+// SC_FT hold 2 f), -inf when the prediction is not positive or the ratio not
+// finite; theta = trial when ratio > eta. SC_RHO and SC_ACC record them.
+hipError_t launch_tr_accept(const Dims& d, double* scal, double eta, const float* trial, float* theta,
+                            hipStream_t s);
 hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float* step, float t,
                                   const float* lo, const float* hi, int param_mask,
                                   const uint8_t* mask, float* trial, hipStream_t s);

@@ -1,0 +1,552 @@
+// Non-Cartesian encoding: the voxel x sample contraction for any k-space
+// trajectory (the method's non-Cartesian extensibility: Introduction,
+// Discussion). Sample k of TR n sits at (kx, ky) cycles per field of view and
+//     E[n,k,j] = exp(-2 pi i (ax[n,k] (ix - nx/2) + ay[n,k] (iy - ny/2))),
+// ax = kx / nx, ay = ky / ny (FP64 tables). The phase still factors into an x
+// and a y part, so per TR the contraction is a dense complex GEMM:
+//   forward  s[k] = sum_iy Ey[k,iy] P[k,iy],  P = Ex X^T (nk x ny, K = nx),
+//            X[iy,ix] the voxel values of the TR;
+//   adjoint  V[iy,ix] = sum_k G[k,iy] H[k,ix],  G = conj(Ey) w, H = conj(Ex),
+//            then A_p[j] += mu_p[n,j] V[j] over the TRs of a chunk.
+// Both run on the matrix cores in the real 2 x 2-block form of a complex
+// product, with every phase generated on the fly (argument reduced in FP64,
+// sin/cos of the reduced fraction in FP32):
+//   ENC 0: v_mfma_f32_16x16x4_f32 (FP32 operands);
+//   ENC 1: v_mfma_f32_16x16x32_bf16 on split operands, hi*hi + hi*lo + lo*hi.
+// MFMA operand layouts (as in encode.hip): 16x16x4 f32: A lane l -> (row
+// l%16, k l/16), B lane l -> (k l/16, col l%16); 16x16x32: A lane l -> (row
+// l%16, k 8(l/16)..+7), B lane l -> (k 8(l/16)..+7, col l%16); D lane l ->
+// (rows 4(l/16)+i, col l%16) for both.
+#include "mrstat_internal.h"
+
+#include <algorithm>
+
+namespace mrstat {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// exp(-2 pi i a x) for an FP64 coefficient a and an integer position x: the
+// product is reduced to a fraction of a cycle in FP64, then sin and cos of pi
+// times twice that fraction in FP32.
+__device__ __forceinline__ float2 phase_of(double a, int x)
+{
+    const double t = a * (double)x;
+    const double f = t - rint(t);   // [-0.5, 0.5]
+    float sn, cs;
+    sincospif((float)(-2.0 * f), &sn, &cs);
+    return make_float2(cs, sn);
+}
+
+__device__ __forceinline__ unsigned int bf16_rne(float x)
+{
+    const unsigned int u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// (re, im) -> hi word (bf16 re | bf16 im << 16) and lo word of the remainders.
+__device__ __forceinline__ uint2 split_pair(float re, float im)
+{
+    const unsigned int hr = bf16_rne(re), hi = bf16_rne(im);
+    const unsigned int lr = bf16_rne(re - __uint_as_float(hr << 16));
+    const unsigned int li = bf16_rne(im - __uint_as_float(hi << 16));
+    return make_uint2(hr | (hi << 16), lr | (li << 16));
+}
+
+__device__ __forceinline__ f4 mma_bf16(const uint4& a, const uint4& b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   c, 0, 0, 0);
+}
+
+// Real-form B words of the forward and adjoint: a word holds (re, im) of one
+// complex operand entry; column parity b = 0 needs (re, -im), b = 1 (im, re).
+__device__ __forceinline__ uint4 bform(uint4 w, int b)
+{
+    if (b == 0) return make_uint4(w.x ^ 0x80000000u, w.y ^ 0x80000000u, w.z ^ 0x80000000u, w.w ^ 0x80000000u);
+    return make_uint4((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16), (w.z >> 16) | (w.z << 16),
+                      (w.w >> 16) | (w.w << 16));
+}
+
+template <typename TT>
+__device__ __forceinline__ float ld_train(const TT* p) { return (float)*p; }
+
+// ------------------------------------------------------------------------
+// Forward: a block of 4 waves per (TR n, 64 samples, coil); wave w owns
+// samples k0 = 64 kt + 16 w .. +15. Its A fragments (Ex of its 16 samples
+// over all nx columns, KS K-steps) are generated once and kept in registers;
+// the voxel values X of 32 image rows at a time are built in LDS from the
+// trains (ENC 1: split into bf16 hi/lo words), then each wave multiplies
+// them for 4 column blocks of 8 rows, and the epilogue applies Ey and sums
+// over the rows. Blocks are dealt so that the sample tiles of one TR share an
+// XCD (its trains come through one L2).
+// MODE 0: out = data - s (and FP64 partials of |out|^2); 1: out = -s; 2: s.
+// NTRV: voxel values from the m train (1: x = i rho mu0) or from the J v
+// direction (4: all tangents; 3: without dm/dB1, whose direction entry is 0).
+// ------------------------------------------------------------------------
+constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
+constexpr int NC_KS1 = 16;    // BF16 K-steps of 32 real k: nx <= 256
+constexpr int NC_ROWS = 32;   // image rows per LDS tile
+
+template <int ENC, int MODE, int NTRV, typename TT>
+__global__ __launch_bounds__(256) void nc_fwd_kernel(
+    const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
+    const float2* __restrict__ coil, const uint8_t* __restrict__ mask, const double* __restrict__ ax,
+    const double* __restrict__ ay, const float2* __restrict__ data, float2* __restrict__ out,
+    double* __restrict__ red, int nx, int ny, int nv, int T, int nk, int KT, int nxp)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char nc_smem[];
+    __shared__ double rs[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bid = blockIdx.x;
+    const int slot = bid >> 3;
+    const int kt = slot % KT;
+    const int n = (slot / KT) * 8 + (bid & 7);
+    const int c = blockIdx.y;
+    const size_t red_at = (size_t)c * gridDim.x + bid;
+    if (n >= T) {
+        if (MODE == 0 && tid == 0) red[red_at] = 0.0;
+        return;
+    }
+    const int k0 = kt * 64 + wave * 16;
+    const int krow = k0 + (lane & 15);
+    const bool krow_ok = krow < nk;
+    const double axk = krow_ok ? ax[(size_t)n * nk + krow] : 0.0;
+    const int h = lane >> 4;   // 0..3
+
+    // A fragments: Ex[krow][ix] in the real form A'[k][2 ix + a] = (re, im).
+    float a0[ENC == 0 ? NC_KS0 : 1];
+    uint4 ahi[ENC == 1 ? NC_KS1 : 1], alo[ENC == 1 ? NC_KS1 : 1];
+    int KS;
+    if constexpr (ENC == 0) {
+        KS = (2 * nx + 3) / 4;
+#pragma unroll
+        for (int s = 0; s < NC_KS0; ++s) {
+            float val = 0.f;
+            const int ix = 2 * s + (h >> 1);
+            if (s < KS && krow_ok && ix < nx) {
+                const float2 e = phase_of(axk, ix - nx / 2);
+                val = (h & 1) ? e.y : e.x;
+            }
+            a0[s] = val;
+        }
+    } else {
+        KS = (2 * nx + 31) / 32;
+#pragma unroll
+        for (int s = 0; s < NC_KS1; ++s) {
+            unsigned int hw[4], lw[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int ix = 16 * s + 4 * h + m;
+                float2 e = make_float2(0.f, 0.f);
+                if (s < KS && krow_ok && ix < nx) e = phase_of(axk, ix - nx / 2);
+                const uint2 w = split_pair(e.x, e.y);
+                hw[m] = w.x;
+                lw[m] = w.y;
+            }
+            ahi[s] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            alo[s] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+    }
+
+    float sacc[4] = {0.f, 0.f, 0.f, 0.f};
+    const int b = lane & 1;
+    const size_t plane = (size_t)T * nv;
+    float2* xs0 = reinterpret_cast<float2*>(nc_smem);               // ENC 0: [ROWS][nxp]
+    uint2* xs1 = reinterpret_cast<uint2*>(nc_smem);                 // ENC 1: [ROWS][nxp] (hi, lo)
+    for (int iy0 = 0; iy0 < ny; iy0 += NC_ROWS) {
+        __syncthreads();   // the previous tile has been read
+        for (int e = tid; e < NC_ROWS * nxp; e += 256) {
+            const int r = e / nxp, ix = e % nxp;
+            const int iy = iy0 + r;
+            float xr = 0.f, xi = 0.f;
+            if (ix < nx && iy < ny) {
+                const int j = iy * nx + ix;
+                if (mask == nullptr || mask[j] != 0) {
+                    const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
+                    const float mu0 = ld_train(trains + (size_t)n * nv + j);
+                    if constexpr (NTRV == 1) {
+                        xr = -ri * mu0;
+                        xi = rr * mu0;
+                    } else {
+                        float t = 0.f;
+#pragma unroll
+                        for (int q = 0; q < NTRV - 1; ++q)
+                            t = fmaf(v[(size_t)q * nv + j], ld_train(trains + (q + 1) * plane + (size_t)n * nv + j), t);
+                        const float v3 = v[3 * (size_t)nv + j], v4 = v[4 * (size_t)nv + j];
+                        // x = i (rho t + (v3 + i v4) mu0)
+                        xr = -(ri * t + v4 * mu0);
+                        xi = rr * t + v3 * mu0;
+                    }
+                    if (coil != nullptr) {
+                        const float2 cc = coil[(size_t)c * nv + j];
+                        const float tr = cc.x * xr - cc.y * xi;
+                        xi = cc.x * xi + cc.y * xr;
+                        xr = tr;
+                    }
+                }
+            }
+            if constexpr (ENC == 0)
+                xs0[e] = make_float2(xr, xi);
+            else
+                xs1[e] = split_pair(xr, xi);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int cb = 0; cb < NC_ROWS / 8; ++cb) {
+            const int rl = 8 * cb + ((lane & 15) >> 1);   // tile row of this lane's column
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (ENC == 0) {
+#pragma unroll
+                for (int s = 0; s < NC_KS0; ++s) {
+                    if (s < KS) {
+                        const int ix = 2 * s + (h >> 1);
+                        const float2 x = xs0[rl * nxp + ix];
+                        const int a = h & 1;
+                        const float bv = a == 0 ? (b == 0 ? x.x : x.y) : (b == 0 ? -x.y : x.x);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], bv, acc, 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NC_KS1; ++s) {
+                    if (s < KS) {
+                        const uint2* src = xs1 + rl * nxp + 16 * s + 4 * h;
+                        const uint2 p0 = src[0], p1 = src[1], p2 = src[2], p3 = src[3];
+                        const uint4 bh = bform(make_uint4(p0.x, p1.x, p2.x, p3.x), b);
+                        const uint4 bl = bform(make_uint4(p0.y, p1.y, p2.y, p3.y), b);
+                        acc = mma_bf16(ahi[s], bh, acc);
+                        acc = mma_bf16(ahi[s], bl, acc);
+                        acc = mma_bf16(alo[s], bh, acc);
+                    }
+                }
+            }
+            // Epilogue of this column block: P[k, iy] (re in even lanes, im in
+            // odd) times Ey[k, iy], summed into the lane's running row sums.
+            const int iy = iy0 + rl;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float own = acc[i];
+                const float oth = __shfl_xor(own, 1);
+                const float pr = b == 0 ? own : oth, pi = b == 0 ? oth : own;
+                const int k = k0 + 4 * h + i;
+                if (k < nk && iy < ny) {
+                    const float2 ey = phase_of(ay[(size_t)n * nk + k], iy - ny / 2);
+                    sacc[i] += b == 0 ? pr * ey.x - pi * ey.y : pr * ey.y + pi * ey.x;
+                }
+            }
+        }
+    }
+    // Sum over the 8 column lanes of each parity: lanes 0 and 1 of each
+    // 16-lane group then hold (re, im) of s for rows 4 h + i.
+    double sq = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float vv = sacc[i];
+        vv += __shfl_xor(vv, 2);
+        vv += __shfl_xor(vv, 4);
+        vv += __shfl_xor(vv, 8);
+        const int k = k0 + 4 * h + i;
+        if ((lane & 14) == 0 && k < nk) {
+            const size_t idx = ((size_t)c * T + n) * nk + k;
+            float* o = reinterpret_cast<float*>(out) + 2 * idx + b;
+            if constexpr (MODE == 0) {
+                const float rv = reinterpret_cast<const float*>(data)[2 * idx + b] - vv;
+                *o = rv;
+                sq += (double)rv * (double)rv;
+            } else if constexpr (MODE == 1) {
+                *o = -vv;
+            } else {
+                *o = vv;
+            }
+        }
+    }
+    if constexpr (MODE == 0) {
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        if (lane == 0) rs[wave] = sq;
+        __syncthreads();
+        if (tid == 0) red[red_at] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Adjoint: a block of 4 waves per (tile of 64 image rows x 32 columns, TR
+// chunk); wave w owns rows 16 w .. +15 of the tile, 4 column blocks of 8
+// columns. For each TR and coil the samples go in chunks of 64: the block
+// writes G[k][row] = conj(Ey[k][iy]) w_c[k] and H[k][col] = conj(Ex[k][ix])
+// into LDS (as [row][k] and [col][k], so a lane's 4 consecutive samples are
+// adjacent), then the waves multiply; each coil's product is weighted by
+// conj(C_c[j]) per voxel, and after the TR the epilogue adds mu_p[n,j] V[j]
+// to the lane's running sums. Chunk partials: apart[chunk][2 p + (re, im)][j]
+// with 8 planes per chunk (2 for the m train alone), the layout of the
+// Cartesian adjoint, so the same gradient assembly follows.
+// ------------------------------------------------------------------------
+constexpr int NCA_TY = 64, NCA_TX = 32, NCA_KC = 64;
+
+template <int ENC, int NTR, typename TT>
+__global__ __launch_bounds__(256) void nc_adj_kernel(
+    const TT* __restrict__ trains, const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
+    const double* __restrict__ ax, const double* __restrict__ ay, const float2* __restrict__ w,
+    float* __restrict__ apart, int nx, int ny, int nv, int T, int nk, int C, int n_per_chunk, int ntx)
+{
+    // LDS: G [TY][KC] and H [TX][KC] entries of 8 bytes: ENC 0 (re, im) FP32,
+    // ENC 1 (hi word, lo word).
+    __shared__ __attribute__((aligned(16))) uint2 gs[NCA_TY * NCA_KC];
+    __shared__ __attribute__((aligned(16))) uint2 hs[NCA_TX * NCA_KC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = blockIdx.x;
+    const int iy_base = (tile / ntx) * NCA_TY, ix_base = (tile % ntx) * NCA_TX;
+    const int chunk = blockIdx.y;
+    const int n0 = chunk * n_per_chunk, n1 = min(T, n0 + n_per_chunk);
+    const int h = lane >> 4, b = lane & 1;
+    const size_t plane = (size_t)T * nv;
+
+    // This lane's outputs: rows iy_base + 16 wave + 4 h + i, column
+    // ix_base + 8 cb + (lane & 15) / 2, part b (0 re, 1 im).
+    float aacc[4][4][NTR];   // [cb][i][train]
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int p = 0; p < NTR; ++p) aacc[cb][i][p] = 0.f;
+
+    for (int n = n0; n < n1; ++n) {
+        f4 vacc[4];   // V of this TR (summed over coils with their weights)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) vacc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < C; ++c) {
+            f4 cacc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) cacc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int kc0 = 0; kc0 < nk; kc0 += NCA_KC) {
+                __syncthreads();   // the previous chunk's tables have been read
+                // G: 64 rows x 64 samples; H: 32 columns x 64 samples.
+                for (int e = tid; e < (NCA_TY + NCA_TX) * NCA_KC; e += 256) {
+                    const bool isg = e < NCA_TY * NCA_KC;
+                    const int e2 = isg ? e : e - NCA_TY * NCA_KC;
+                    const int r = e2 / NCA_KC, kk = e2 % NCA_KC;
+                    const int k = kc0 + kk;
+                    float2 val = make_float2(0.f, 0.f);
+                    if (k < nk) {
+                        if (isg) {
+                            const int iy = iy_base + r;
+                            if (iy < ny) {
+                                const float2 ey = phase_of(ay[(size_t)n * nk + k], iy - ny / 2);
+                                const float2 ww = w[((size_t)c * T + n) * nk + k];
+                                // conj(ey) * w
+                                val = make_float2(ey.x * ww.x + ey.y * ww.y, ey.x * ww.y - ey.y * ww.x);
+                            }
+                        } else {
+                            const int ix = ix_base + r;
+                            if (ix < nx) {
+                                const float2 ex = phase_of(ax[(size_t)n * nk + k], ix - nx / 2);
+                                val = make_float2(ex.x, -ex.y);
+                            }
+                        }
+                    }
+                    uint2 st;
+                    if constexpr (ENC == 0)
+                        st = make_uint2(__float_as_uint(val.x), __float_as_uint(val.y));
+                    else
+                        st = split_pair(val.x, val.y);
+                    (isg ? gs : hs)[e2] = st;
+                }
+                __syncthreads();
+                const int grow = 16 * wave + (lane & 15);   // A row (image row in the tile)
+                if constexpr (ENC == 0) {
+                    // K-steps of 2 samples (4 real k): lane k' = 4 s + h ->
+                    // sample 2 s + h / 2, part a = h & 1.
+#pragma unroll 4
+                    for (int s = 0; s < NCA_KC / 2; ++s) {
+                        const int kk = 2 * s + (h >> 1), a = h & 1;
+                        const uint2 gv = gs[grow * NCA_KC + kk];
+                        const float av = __uint_as_float(a ? gv.y : gv.x);
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb) {
+                            const int col = 8 * cb + ((lane & 15) >> 1);
+                            const uint2 hv = hs[col * NCA_KC + kk];
+                            const float hr = __uint_as_float(hv.x), hi = __uint_as_float(hv.y);
+                            const float bv = a == 0 ? (b == 0 ? hr : hi) : (b == 0 ? -hi : hr);
+                            cacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, cacc[cb], 0, 0, 0);
+                        }
+                    }
+                } else {
+                    // K-steps of 16 samples: lane's samples 16 s + 4 h + m.
+#pragma unroll
+                    for (int s = 0; s < NCA_KC / 16; ++s) {
+                        const uint2* gp = gs + grow * NCA_KC + 16 * s + 4 * h;
+                        const uint2 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3];
+                        const uint4 ah = make_uint4(g0.x, g1.x, g2.x, g3.x);
+                        const uint4 al = make_uint4(g0.y, g1.y, g2.y, g3.y);
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb) {
+                            const int col = 8 * cb + ((lane & 15) >> 1);
+                            const uint2* hp = hs + col * NCA_KC + 16 * s + 4 * h;
+                            const uint2 q0 = hp[0], q1 = hp[1], q2 = hp[2], q3 = hp[3];
+                            const uint4 bh = bform(make_uint4(q0.x, q1.x, q2.x, q3.x), b);
+                            const uint4 bl = bform(make_uint4(q0.y, q1.y, q2.y, q3.y), b);
+                            cacc[cb] = mma_bf16(ah, bh, cacc[cb]);
+                            cacc[cb] = mma_bf16(ah, bl, cacc[cb]);
+                            cacc[cb] = mma_bf16(al, bh, cacc[cb]);
+                        }
+                    }
+                }
+            }
+            // Coil weight conj(C_c[j]) per voxel (1 without coils).
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float own = cacc[cb][i];
+                    const float oth = __shfl_xor(own, 1);
+                    if (coil == nullptr) {
+                        vacc[cb][i] += own;
+                    } else {
+                        const float vr = b == 0 ? own : oth, vi = b == 0 ? oth : own;
+                        const int iy = iy_base + 16 * wave + 4 * h + i;
+                        const int ix = ix_base + 8 * cb + ((lane & 15) >> 1);
+                        float2 cc = make_float2(0.f, 0.f);
+                        if (iy < ny && ix < nx) cc = coil[(size_t)c * nv + (size_t)iy * nx + ix];
+                        // conj(cc) * (vr + i vi)
+                        vacc[cb][i] += b == 0 ? cc.x * vr + cc.y * vi : cc.x * vi - cc.y * vr;
+                    }
+                }
+        }
+        // A_p += mu_p[n, j] V[j] (the lane's part of V).
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int iy = iy_base + 16 * wave + 4 * h + i;
+                const int ix = ix_base + 8 * cb + ((lane & 15) >> 1);
+                if (iy < ny && ix < nx) {
+                    const size_t j = (size_t)iy * nx + ix;
+#pragma unroll
+                    for (int p = 0; p < NTR; ++p)
+                        aacc[cb][i][p] = fmaf(ld_train(trains + p * plane + (size_t)n * nv + j), vacc[cb][i],
+                                              aacc[cb][i][p]);
+                }
+            }
+    }
+    const int planes = NTR == 1 ? 2 : 8;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int iy = iy_base + 16 * wave + 4 * h + i;
+            const int ix = ix_base + 8 * cb + ((lane & 15) >> 1);
+            if (iy < ny && ix < nx) {
+                const size_t j = (size_t)iy * nx + ix;
+                const bool on = mask == nullptr || mask[j] != 0;
+                float* dst = apart + (size_t)chunk * planes * nv + j;
+#pragma unroll
+                for (int p = 0; p < NTR; ++p) dst[(size_t)(2 * p + b) * nv] = on ? aacc[cb][i][p] : 0.f;
+            }
+        }
+}
+
+template <int ENC, int MODE, int NTRV, typename TT>
+hipError_t fwd_launch(const Dims& d, const TT* trains, const float* theta, const float* v, const float2* coil,
+                      const uint8_t* mask, const double* ax, const double* ay, const float2* data,
+                      float2* out, double* red, int* nred, hipStream_t s)
+{
+    const int KT = ceil_div(d.nk, 64);
+    const int nxp = ceil_div(d.nx, 16) * 16;
+    const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
+    const size_t lds = (size_t)NC_ROWS * nxp * 8;
+    nc_fwd_kernel<ENC, MODE, NTRV, TT><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, ax, ay, data, out,
+                                                               red, d.nx, d.ny, d.nv, d.T, d.nk, KT, nxp);
+    if (nred) *nred = (int)(grid.x * grid.y);
+    return hipGetLastError();
+}
+
+template <int ENC, typename TT>
+hipError_t fwd_mode(const Dims& d, int mode_y, int mode_x, const TT* trains, const float* theta,
+                    const float* v, const float2* coil, const uint8_t* mask, const double* ax,
+                    const double* ay, const float2* data, float2* out, double* red, int* nred,
+                    hipStream_t s)
+{
+#define NC_FWD(MX, NT) fwd_launch<ENC, MX, NT, TT>(d, trains, theta, v, coil, mask, ax, ay, data, out, red, nred, s)
+    if (mode_y == 0) {
+        if (mode_x == 0) return NC_FWD(0, 1);
+        if (mode_x == 1) return NC_FWD(1, 1);
+        return NC_FWD(2, 1);
+    }
+    const bool four = mode_y == 1;
+    if (mode_x == 0) return four ? NC_FWD(0, 4) : NC_FWD(0, 3);
+    if (mode_x == 1) return four ? NC_FWD(1, 4) : NC_FWD(1, 3);
+    return four ? NC_FWD(2, 4) : NC_FWD(2, 3);
+#undef NC_FWD
+}
+
+template <int ENC, typename TT>
+hipError_t adj_typed(const Dims& d, int ntr, int chunks, const TT* trains, const float2* coil,
+                     const uint8_t* mask, const double* ax, const double* ay, const float2* w, float* apart,
+                     hipStream_t s)
+{
+    // Exactly `chunks` chunks (the count the gradient assembly sums), each
+    // holding at least one TR.
+    const int per = ceil_div(d.T, chunks);
+    const int nch = ceil_div(d.T, per);
+    if (chunks < 1 || nch != chunks) return hipErrorInvalidValue;
+    const int ntx = ceil_div(d.nx, NCA_TX);
+    const dim3 grid(ntx * ceil_div(d.ny, NCA_TY), nch);
+#define NC_ADJ(NT) nc_adj_kernel<ENC, NT, TT><<<grid, 256, 0, s>>>(trains, coil, mask, ax, ay, w, apart, d.nx, \
+                                                                  d.ny, d.nv, d.T, d.nk, d.C, per, ntx)
+    if (ntr == 1)
+        NC_ADJ(1);
+    else if (ntr == 3)
+        NC_ADJ(3);
+    else
+        NC_ADJ(4);
+#undef NC_ADJ
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int nc_adj_chunks(const Dims& d)
+{
+    // Enough blocks to fill the chip at least twice with partial sums kept
+    // modest (chunks x 8 floats per voxel).
+    const int tiles = ceil_div(d.nx, NCA_TX) * ceil_div(d.ny, NCA_TY);
+    int ch = std::max(1, ceil_div(512, tiles));
+    ch = std::min(ch, 32);
+    return std::min(ch, d.T);
+}
+
+int nc_fwd_blocks(const Dims& d) { return 8 * ceil_div(d.nk, 64) * ceil_div(d.T, 8) * d.C; }
+
+hipError_t launch_nc_fwd(const Dims& d, int enc, int mode_y, int mode_x, const void* trains, bool f16,
+                         const float* theta, const float* v, const float2* coil, const uint8_t* mask,
+                         const double* ax, const double* ay, const float2* data, float2* out, double* red,
+                         int* nred, hipStream_t s)
+{
+    if (d.nx > 256) return hipErrorInvalidValue;
+    if (enc == 0)
+        return f16 ? fwd_mode<0>(d, mode_y, mode_x, static_cast<const _Float16*>(trains), theta, v, coil, mask, ax,
+                                 ay, data, out, red, nred, s)
+                   : fwd_mode<0>(d, mode_y, mode_x, static_cast<const float*>(trains), theta, v, coil, mask, ax, ay,
+                                 data, out, red, nred, s);
+    return f16 ? fwd_mode<1>(d, mode_y, mode_x, static_cast<const _Float16*>(trains), theta, v, coil, mask, ax, ay,
+                             data, out, red, nred, s)
+               : fwd_mode<1>(d, mode_y, mode_x, static_cast<const float*>(trains), theta, v, coil, mask, ax, ay,
+                             data, out, red, nred, s);
+}
+
+hipError_t launch_nc_adj(const Dims& d, int enc, int ntr, int chunks, const void* trains, bool f16,
+                         const float2* coil, const uint8_t* mask, const double* ax, const double* ay,
+                         const float2* w, float* apart, hipStream_t s)
+{
+    if (enc == 0)
+        return f16 ? adj_typed<0>(d, ntr, chunks, static_cast<const _Float16*>(trains), coil, mask, ax, ay, w,
+                                  apart, s)
+                   : adj_typed<0>(d, ntr, chunks, static_cast<const float*>(trains), coil, mask, ax, ay, w, apart, s);
+    return f16 ? adj_typed<1>(d, ntr, chunks, static_cast<const _Float16*>(trains), coil, mask, ax, ay, w, apart, s)
+               : adj_typed<1>(d, ntr, chunks, static_cast<const float*>(trains), coil, mask, ax, ay, w, apart, s);
+}
+
+}  // namespace mrstat

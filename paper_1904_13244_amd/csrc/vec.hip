@@ -206,10 +206,14 @@ __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ d
 // beta = rr_new / rr, dir = res + beta dir. Block 0 records rr_new and beta,
 // counts the iteration and writes rr and the stop flag for the next
 // iteration (a zero residual, or a stopped iteration, stops CG).
+// With TR (the trust-region CG) block 0 also records |step|^2 from the step
+// kernel's partials (zzp) and marks a zero residual as the exit kind.
+template <bool TR>
 __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ res,
                                                     float* __restrict__ dir, size_t n,
                                                     const double* __restrict__ part, int nblk,
-                                                    double* __restrict__ sc, int par)
+                                                    double* __restrict__ sc, int par,
+                                                    const double* __restrict__ zzp)
 {
     __shared__ double sh[RB / 64];
     __shared__ double bc[1];
@@ -232,6 +236,11 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
     __syncthreads();
     v = bc[0];
     const double beta = upd ? v / rr : 0.0;
+    double zz = 0.0;
+    if constexpr (TR) {
+        for (int i = threadIdx.x; i < nblk; i += RB) zz += zzp[i];
+        zz = block_sum(zz, sh);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (upd) {
             sc[S_RRNEW] = v;
@@ -240,6 +249,10 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
         }
         sc[rr_slot(par ^ 1)] = upd ? v : rr;
         sc[done_slot(par ^ 1)] = (!upd || v == 0.0) ? 1.0 : 0.0;
+        if constexpr (TR) {
+            sc[SC_ZZ] = zz;
+            if (upd && v == 0.0) sc[SC_EXIT] = 3.0;
+        }
     }
     if (!upd) return;
     const float b = (float)beta;
@@ -249,6 +262,195 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
         if (i < n) dir[i] = fmaf(b, dp[e], rp[e]);
     }
     for (size_t i = i0 + PF * stride; i < n; i += stride) dir[i] = fmaf(b, dir[i], res[i]);
+}
+
+// ------------------------------------------------------------ trust region
+// Steihaug's truncated CG (Nocedal & Wright Algorithm 7.2) on the same
+// vectors as the CG above: step = z, res = -(g + B z), dir = the search
+// direction.
+
+__global__ void tr_init_kernel(double* __restrict__ sc, double delta2)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    sc[SC_ZZ] = 0.0;
+    sc[SC_DELTA2] = delta2;
+    sc[SC_EXIT] = (sc[S_RR] == 0.0) ? 3.0 : 0.0;
+}
+
+// The three curvature partials (dir . q, dir . dir, step . dir) reduced in
+// every block in one fixed order; broadcast through LDS.
+__device__ __forceinline__ void reduce_triple(const double* __restrict__ part, int n, double* sh,
+                                              double* bc, double& a, double& b, double& c)
+{
+    a = b = c = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB) {
+        a += part[i];
+        b += part[n + i];
+        c += part[2 * n + i];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        bc[0] = a;
+        bc[1] = b;
+        bc[2] = c;
+    }
+    __syncthreads();
+    a = bc[0];
+    b = bc[1];
+    c = bc[2];
+}
+
+// One Steihaug iteration. kappa = dir . B dir; with kappa <= 0 the step
+// moves along dir to the boundary point of lower model value (the model
+// changes by -t rr + t^2 kappa / 2 along a CG direction, res . dir = rr);
+// otherwise alpha = rr / kappa, and if |step + alpha dir| would reach the
+// radius the step stops on the boundary instead (|step|^2, step . dir and
+// dir . dir give the root); else the usual CG update of step and res. Every
+// block takes the same decision; block 0 records it. Partials of res . res
+// and step . step for the direction kernel.
+__global__ __launch_bounds__(RB) void tr_step_kernel(const float* __restrict__ dir,
+                                                     const float* __restrict__ q,
+                                                     float* __restrict__ step,
+                                                     float* __restrict__ res, size_t n,
+                                                     const double* __restrict__ curv, int nblk,
+                                                     double* __restrict__ sc, int par,
+                                                     double* __restrict__ part_rr,
+                                                     double* __restrict__ part_zz)
+{
+    __shared__ double sh[RB / 64];
+    __shared__ double bc[3];
+    const size_t i0 = (size_t)blockIdx.x * RB + threadIdx.x, stride = (size_t)gridDim.x * RB;
+    const double done = sc[done_slot(par)], rr = sc[rr_slot(par)];
+    const double zz = sc[SC_ZZ], d2 = sc[SC_DELTA2];
+    double kappa, dd, zd;
+    reduce_triple(curv, nblk, sh, bc, kappa, dd, zd);
+    int mode = 0;          // 0 nothing, 1 interior update, 2 move to the boundary
+    double coef = 0.0;
+    double exitk = 0.0;
+    if (done == 0.0) {
+        const double disc = sqrt(fmax(zd * zd + dd * (d2 - zz), 0.0));
+        const double t_hi = (-zd + disc) / dd, t_lo = (-zd - disc) / dd;
+        if (!(kappa > 0.0)) {
+            const double m_hi = -t_hi * rr + 0.5 * t_hi * t_hi * kappa;
+            const double m_lo = -t_lo * rr + 0.5 * t_lo * t_lo * kappa;
+            coef = m_lo < m_hi ? t_lo : t_hi;
+            mode = 2;
+            exitk = 2.0;
+        } else {
+            const double alpha = rr / kappa;
+            if (zz + 2.0 * alpha * zd + alpha * alpha * dd >= d2) {
+                coef = t_hi;
+                mode = 2;
+                exitk = 1.0;
+            } else {
+                coef = alpha;
+                mode = 1;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_KAPPA] = kappa;
+        sc[S_DD] = dd;
+        sc[S_UPD] = mode == 1 ? 1.0 : 0.0;
+        sc[S_ALPHA] = mode == 1 ? coef : 0.0;
+        if (mode == 2) sc[SC_EXIT] = exitk;
+    }
+    const float c = (float)coef;
+    double vr = 0.0, vz = 0.0;
+    for (size_t i = i0; i < n; i += stride) {
+        float z = step[i], r = res[i];
+        if (mode != 0) {
+            z = fmaf(c, dir[i], z);
+            step[i] = z;
+        }
+        if (mode == 1) {
+            r = fmaf(-c, q[i], r);
+            res[i] = r;
+        }
+        vr += (double)r * (double)r;
+        vz += (double)z * (double)z;
+    }
+    vr = block_sum(vr, sh);
+    vz = block_sum(vz, sh);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = vr;
+        part_zz[blockIdx.x] = vz;
+    }
+}
+
+// Reflection into [lo, hi]: the end point of the straight path that bounces
+// off the walls (a fold with period 2 (hi - lo)); inside values pass as they
+// are.
+__device__ __forceinline__ float reflect_box(float x, float lo, float hi, bool& moved)
+{
+    moved = false;
+    if (x >= lo && x <= hi) return x;
+    moved = true;
+    const float w = hi - lo;
+    if (!(w > 0.f)) return lo;
+    float y = fmodf(x - lo, 2.f * w);
+    if (y < 0.f) y += 2.f * w;
+    if (y > w) y = 2.f * w - y;
+    return lo + y;
+}
+
+__global__ __launch_bounds__(RB) void tr_trial_kernel(const float* __restrict__ theta,
+                                                      const float* __restrict__ step, float lo0,
+                                                      float lo1, float lo2, float hi0, float hi1,
+                                                      float hi2, int param_mask,
+                                                      const uint8_t* __restrict__ mask,
+                                                      float* __restrict__ trial,
+                                                      float* __restrict__ sv, int nv,
+                                                      double* __restrict__ part)
+{
+    __shared__ double sh[RB / 64];
+    const size_t n = (size_t)5 * nv;
+    double cnt = 0.0, ss = 0.0;
+    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+        const int q = (int)(i / nv), j = (int)(i % nv);
+        const float th = theta[i];
+        float x = th + step[i];
+        const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
+        if (q < 3 && on) {
+            bool moved;
+            x = reflect_box(x, q == 0 ? lo0 : (q == 1 ? lo1 : lo2), q == 0 ? hi0 : (q == 1 ? hi1 : hi2),
+                            moved);
+            cnt += moved ? 1.0 : 0.0;
+        }
+        const float t = on ? x : th;
+        const float d = t - th;
+        trial[i] = t;
+        sv[i] = d;
+        ss += (double)d * (double)d;
+    }
+    cnt = block_sum(cnt, sh);
+    ss = block_sum(ss, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = cnt;
+        part[gridDim.x + blockIdx.x] = ss;
+    }
+}
+
+// Ratio of actual to predicted decrease and the acceptance (every block
+// takes the same decision; block 0 records it).
+__global__ void tr_accept_kernel(double* __restrict__ sc, double eta, const float* __restrict__ trial,
+                                 float* __restrict__ theta, size_t n)
+{
+    const double f0 = 0.5 * sc[SC_F0], ft = 0.5 * sc[SC_FT];
+    const double pred = -(sc[SC_GS] + 0.5 * sc[SC_JS2]);
+    double rho = (f0 - ft) / pred;
+    if (!(pred > 0.0) || !isfinite(rho)) rho = -INFINITY;
+    const bool acc = rho > eta;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[SC_RHO] = rho;
+        sc[SC_PRED] = pred;
+        sc[SC_ACC] = acc ? 1.0 : 0.0;
+    }
+    if (!acc) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        theta[i] = trial[i];
 }
 
 // trial = P(theta + t step): active ln T1, ln T2, B1 clamped to the box.
@@ -440,7 +642,46 @@ hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* r
     const int nb = (d.nv + 255) / 256;
     double* rrp = partials + 2 * nb;
     cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp);
-    cg_dir_kernel<<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1);
+    cg_dir_kernel<false><<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1, nullptr);
+    return hipGetLastError();
+}
+
+int tr_partials(const Dims& d) { return 3 * ((d.nv + 255) / 256) + 2 * RED_BLOCKS; }
+
+hipError_t launch_tr_init(double* scal, double delta2, hipStream_t s)
+{
+    tr_init_kernel<<<1, 64, 0, s>>>(scal, delta2);
+    return hipGetLastError();
+}
+
+hipError_t launch_tr_update(const Dims& d, const float* q, float* step, float* res, float* dir,
+                            double* scal, double* partials, int iter, hipStream_t s)
+{
+    // partials: curvature triples [3][nb] from the finish kernel, then
+    // res.res and step.step [RED_BLOCKS] each.
+    const size_t n = (size_t)5 * d.nv;
+    const int nb = (d.nv + 255) / 256;
+    double* rrp = partials + 3 * nb;
+    double* zzp = rrp + RED_BLOCKS;
+    tr_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp, zzp);
+    cg_dir_kernel<true><<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1, zzp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tr_trial(const Dims& d, const float* theta, const float* step, const float* lo,
+                           const float* hi, int param_mask, const uint8_t* mask, float* trial,
+                           float* sv, double* scal, double* partials, hipStream_t s)
+{
+    tr_trial_kernel<<<RED_BLOCKS, RB, 0, s>>>(theta, step, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
+                                              param_mask, mask, trial, sv, d.nv, partials);
+    sum2_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal + SC_NREF);
+    return hipGetLastError();
+}
+
+hipError_t launch_tr_accept(const Dims& d, double* scal, double eta, const float* trial, float* theta,
+                            hipStream_t s)
+{
+    tr_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, eta, trial, theta, (size_t)5 * d.nv);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ class Problem:
     flip_deg: np.ndarray
     rf_phase: np.ndarray
     ky_line: np.ndarray
+    traj: tuple | None = None     # (kx, ky) [n_tr][n_read] cycles per FOV; None = Cartesian
 
     @property
     def nv(self) -> int:
@@ -96,6 +97,29 @@ def make_problem(nx, ny, n_tr, n_read, n_states, n_coils=1, tr=0.008, te=0.004,
     return Problem(nx, ny, n_tr, n_read, n_states, n_coils, float(tr), float(te),
                    float(t_inv), np.asarray(flip_deg, dtype=np.float64),
                    np.asarray(rf_phase, dtype=np.float64), np.asarray(ky_line, dtype=np.int32))
+
+
+GOLDEN_ANGLE_DEG = 180.0 * (np.sqrt(5.0) - 1.0) / 2.0   # about 111.246 degrees
+
+
+def radial_golden(n_tr: int, n_read: int, nx: int, ny: int) -> tuple:
+    """Golden-angle radial sampling: one spoke through the k-space centre per
+    TR at angle n * 111.246 degrees, n_read samples spaced nx / n_read (ny /
+    n_read) cycles per field of view along x (y), from -nx/2 (-ny/2).
+    Returns (kx, ky), each [n_tr][n_read]."""
+    phi = np.deg2rad(GOLDEN_ANGLE_DEG) * np.arange(n_tr)
+    s = np.arange(n_read) - n_read // 2
+    kx = (s * (nx / n_read))[None, :] * np.cos(phi)[:, None]
+    ky = (s * (ny / n_read))[None, :] * np.sin(phi)[:, None]
+    return kx, ky
+
+
+def cartesian_traj(prob: "Problem") -> tuple:
+    """The Cartesian samples of prob written as a trajectory (cycles per
+    field of view): kx = (k - n_read/2) nx / n_read, ky = l(n) - ny/2."""
+    kx = np.tile((np.arange(prob.n_read) - prob.n_read // 2) * (prob.nx / prob.n_read), (prob.n_tr, 1))
+    ky = np.repeat((prob.ky_line.astype(np.float64) - prob.ny // 2)[:, None], prob.n_read, axis=1)
+    return kx, ky
 
 
 def pack_theta(T1, T2, B1, rho) -> np.ndarray:

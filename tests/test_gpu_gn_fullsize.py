@@ -83,3 +83,35 @@ def test_gn_step_full_size_matches_oracle(setup, oracle_lib, mask, form):
     assert rep.t == rep_o.t and rep.cg_iters == rep_o.cg_iters
     assert e <= BAR[form], (form, mask, e)
     assert ef <= BAR[form], (form, mask, ef)
+
+
+@pytest.mark.parametrize("form", ["plain", "fp16_trains_split_bf16"])
+def test_tr_step_full_size_matches_oracle(setup, oracle_lib, form):
+    """One trust-region step (five parameters) whose radius, 0.6 of the
+    oracle's 20-iteration GN step, stops the Steihaug CG at its boundary."""
+    torch = setup["torch"]
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    prob, th0 = setup["prob"], setup["th0"]
+    th_gn, _ = _oracle_step(oracle_lib, setup, 0b11111)
+    delta = 0.6 * float(np.linalg.norm(th_gn - th0))
+    if "tr" not in _ORACLE:
+        print("  oracle trust-region step", flush=True)
+        _ORACLE["tr"] = oracle_lib.tr_step(prob, th0, setup["d"], delta, N_CG, 0b11111, I.GN_LO, I.GN_HI)
+    th_o, d_o, rep_o = _ORACLE["tr"]
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    ctx = Context(prob)
+    if form != "plain":
+        ctx.set_train_precision(B.TRAINS_FP16)
+        ctx.set_encoding(B.ENC_SPLIT_BF16)
+    th = dev(th0, torch.float32)
+    d_g, rep = ctx.tr_step(th, dev(setup["d"], torch.complex64), delta, N_CG, 0b11111, I.GN_LO, I.GN_HI)
+    ctx.close()
+    got = th.cpu().numpy().astype(np.float64)
+    e = float(np.linalg.norm(got - th_o) / np.linalg.norm(th_o))
+    print(f"  [tr {form}] exit {rep.exit_kind}/{rep_o['exit_kind']} cg {rep.cg_iters}/{rep_o['cg_iters']} "
+          f"rho {rep.rho:.6f}/{rep_o['rho']:.6f} delta {d_g:.4g}/{d_o:.4g} theta rel err {e:.2e}", flush=True)
+    assert rep_o["exit_kind"] == B.TR_BOUNDARY and rep.exit_kind == rep_o["exit_kind"]
+    assert rep.cg_iters == rep_o["cg_iters"] and rep.accepted == rep_o["accepted"] == 1
+    assert d_g == d_o
+    assert e <= BAR[form], (form, e)

@@ -46,11 +46,11 @@ def test_trained_surrogate_maps(torch_gpu, cfg):
     torch = torch_gpu
     from paper_1904_13244_amd import binding as B
     from paper_1904_13244_amd.binding import Context
-    from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT, train_surrogate
+    from paper_1904_13244_amd.surrogate import RECIPE_EPOCHS, RECIPE_HEAD_WEIGHT, RECIPE_LR, train_surrogate
     w = I.config(cfg)
     prob, head = w.problem, w.extra["head"]
     print(f"\n[surrogate maps] {w.name}", flush=True)
-    net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=RECIPE_EPOCHS,
+    net, rep = train_surrogate(torch, prob, n_samples=2_000_000, epochs=RECIPE_EPOCHS, lr=RECIPE_LR,
                                head_weight=RECIPE_HEAD_WEIGHT)
     print(f"  trained {rep.steps} steps in {rep.seconds_train:.1f} s; held-out rel err "
           f"{['%.2e' % e for e in rep.val_rel_err]}", flush=True)

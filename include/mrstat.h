@@ -195,6 +195,23 @@ mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec);
  * in practice: every order is updated by the same arithmetic). */
 mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
 
+/* Signal model of the linearisation: the gradient-spoiled EPG (n_iso = 0,
+ * the default) or the balanced isochromat model of the paper's own sequence
+ * (Methods, Pulse Sequence and Reconstructions; Supporting Information S2):
+ * a balanced transient-state gradient echo on resonance (no spoiling; RF
+ * phases 0 / pi as for every context, alternating for the paper's sequence),
+ * whose voxel magnetisation is sum_q weight[q] m_q over n_iso isochromats,
+ * isochromat q seeing the flip angle scaled by scale[q] (the slice profile
+ * of the RF pulse). Each isochromat follows the S2 update: an instantaneous
+ * rotation about the RF axis, decay and regrowth, ideal inversion first;
+ * derivatives in ln T1, ln T2 and B1 in forward mode. The trains have the
+ * layout of the EPG's, and every call of the context (and the surrogate's
+ * fallback) uses the model set here. Host arrays [n_iso] read during the
+ * call; 0 <= n_iso <= 32; non-finite entries give MRSTAT_ERR_ARG.
+ * Invalidates the linearisation. */
+mrstat_status mrstat_set_isochromats(mrstat_ctx ctx, int32_t n_iso, const double *h_scale,
+                                     const double *h_weight);
+
 /* Linearise at theta: EPG trains m, dm/dlnT1, dm/dlnT2, dm/dB1 per voxel and
  * TR into the workspace; if d_trains != NULL also copy them out as float32
  * [4][n_tr][Nv] holding the imaginary parts (the real parts are exactly 0

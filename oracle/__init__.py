@@ -9,8 +9,9 @@ The arithmetic lives in ``oracle.c`` (plain C99, double / double complex,
 OpenMP over independent voxels or rows). This module only marshals numpy
 arrays. Problem objects are duck-typed: anything with the attributes nx, ny,
 n_tr, n_read, n_states, n_coils, tr, te, t_inv, flip_deg, rf_phase, ky_line,
-and optionally traj = (kx, ky), each [n_tr][n_read] in cycles per field of view
-(non-Cartesian sampling; None or absent = the Cartesian grid).
+optionally traj = (kx, ky), each [n_tr][n_read] in cycles per field of view
+(non-Cartesian sampling; None or absent = the Cartesian grid), and optionally
+iso = (scale, weight) [n_iso] (the balanced isochromat model; None = EPG).
 
 Paper: van der Heide et al., arXiv 1904.13244 (MR-STAT, matrix-free inexact
 Gauss-Newton). Conventions: theta is [5][Nv] = (ln T1, ln T2, B1, Re rho,
@@ -47,7 +48,8 @@ class _Problem(C.Structure):
                 ("tr", C.c_double), ("te", C.c_double), ("t_inv", C.c_double),
                 ("flip_deg", C.POINTER(C.c_double)), ("rf_phase", C.POINTER(C.c_double)),
                 ("ky_line", C.POINTER(C.c_int)), ("kx", C.POINTER(C.c_double)),
-                ("ky", C.POINTER(C.c_double))]
+                ("ky", C.POINTER(C.c_double)), ("n_iso", C.c_int),
+                ("iso_scale", C.POINTER(C.c_double)), ("iso_weight", C.POINTER(C.c_double))]
 
 
 class _GnOpts(C.Structure):
@@ -115,6 +117,8 @@ def lib():
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         L.oracle_rho_init.argtypes = [P(_Problem), vp, vp, vp, vp, C.c_int]
+        L.oracle_isochromat.argtypes = [P(_Problem), C.c_double, C.c_double, C.c_double, C.c_double,
+                                        vp, vp, vp, vp]
         L.oracle_steihaug_dense.argtypes = [C.c_int, vp, vp, C.c_double, C.c_int, vp, P(C.c_int)]
         L.oracle_steihaug_dense.restype = C.c_int
         L.oracle_reflect.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -142,11 +146,20 @@ class _Bound:
             assert self.kx.shape == (prob.n_tr, prob.n_read) == self.kyt.shape
             kxp = self.kx.ctypes.data_as(C.POINTER(C.c_double))
             kyp = self.kyt.ctypes.data_as(C.POINTER(C.c_double))
+        iso = getattr(prob, "iso", None)
+        n_iso, sp, wp = 0, None, None
+        if iso is not None:
+            self.iso_s = np.ascontiguousarray(iso[0], dtype=np.float64)
+            self.iso_w = np.ascontiguousarray(iso[1], dtype=np.float64)
+            assert self.iso_s.shape == self.iso_w.shape and self.iso_s.ndim == 1
+            n_iso = self.iso_s.size
+            sp = self.iso_s.ctypes.data_as(C.POINTER(C.c_double))
+            wp = self.iso_w.ctypes.data_as(C.POINTER(C.c_double))
         self.s = _Problem(prob.nx, prob.ny, prob.n_tr, prob.n_read, prob.n_states,
                           prob.n_coils, prob.tr, prob.te, prob.t_inv,
                           self.flip.ctypes.data_as(C.POINTER(C.c_double)),
                           self.phase.ctypes.data_as(C.POINTER(C.c_double)),
-                          self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp)
+                          self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp, n_iso, sp, wp)
         self.nv = prob.nx * prob.ny
         self.prob = prob
 
@@ -332,3 +345,13 @@ def tr_step(prob, theta, data, delta, n_cg, param_mask, lo, hi, eta=0.1, delta_m
     lib().oracle_tr_step(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), d.ctypes.data,
                          C.byref(o), C.byref(dl), C.byref(rep))
     return th, float(dl.value), rep.as_dict()
+
+
+def isochromat(prob, lnT1, lnT2, B1, scale=1.0):
+    """One isochromat of the balanced model: [4][n_tr] complex (m and its
+    derivatives in ln T1, ln T2, B1)."""
+    b = _Bound(prob)
+    out = np.zeros((4, prob.n_tr), dtype=np.complex128)
+    lib().oracle_isochromat(C.byref(b.s), float(lnT1), float(lnT2), float(B1), float(scale),
+                            out[0].ctypes.data, out[1].ctypes.data, out[2].ctypes.data, out[3].ctypes.data)
+    return out

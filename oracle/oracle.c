@@ -203,6 +203,121 @@ static void epg_simulate_voxel(const oracle_problem *p, double lnT1, double lnT2
     free(buf);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Balanced isochromat model (Supporting Information S2). Each isochromat is   */
+/* a vector m = (mx, my, mz). The RF of TR n rotates it by theta = B1 alpha_n  */
+/* scale about k = (cos phi_n, sin phi_n, 0) (Rodrigues: m cos theta +          */
+/* (k x m) sin theta + (k . m) k (1 - cos theta)); decay and regrowth over      */
+/* tau multiply (mx, my) by E2 and mz by E1 and add 1 - E1 to mz. With a        */
+/* balanced sequence on resonance nothing else moves the magnetisation.        */
+/* Tangents in ln T1, ln T2 and B1 are carried through both updates in          */
+/* forward mode (zero at the start).                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double v[3]; } vec3;
+
+static vec3 rodrigues(vec3 m, const double k[3], double c, double s)
+{
+    double kdm = k[0] * m.v[0] + k[1] * m.v[1] + k[2] * m.v[2];
+    double cr[3] = {k[1] * m.v[2] - k[2] * m.v[1], k[2] * m.v[0] - k[0] * m.v[2],
+                    k[0] * m.v[1] - k[1] * m.v[0]};
+    vec3 o;
+    for (int i = 0; i < 3; ++i) o.v[i] = c * m.v[i] + s * cr[i] + (1.0 - c) * kdm * k[i];
+    return o;
+}
+
+/* d/dtheta of the rotated vector for fixed m: -s m + c (k x m) + s (k . m) k. */
+static vec3 rodrigues_dtheta(vec3 m, const double k[3], double c, double s)
+{
+    double kdm = k[0] * m.v[0] + k[1] * m.v[1] + k[2] * m.v[2];
+    double cr[3] = {k[1] * m.v[2] - k[2] * m.v[1], k[2] * m.v[0] - k[0] * m.v[2],
+                    k[0] * m.v[1] - k[1] * m.v[0]};
+    vec3 o;
+    for (int i = 0; i < 3; ++i) o.v[i] = -s * m.v[i] + c * cr[i] + s * kdm * k[i];
+    return o;
+}
+
+/* Decay and regrowth over tau with tangents d[0] (ln T1), d[1] (ln T2),
+ * d[2] (B1). */
+static void iso_relax(vec3 *m, vec3 d[3], double tau, double T1, double T2, int tang)
+{
+    double E1 = exp(-tau / T1), E2 = exp(-tau / T2);
+    double dE1 = (tau / T1) * E1, dE2 = (tau / T2) * E2;   /* d/dlnT1 E1, d/dlnT2 E2 */
+    if (tang) {
+        for (int q = 0; q < 3; ++q) {
+            d[q].v[0] *= E2;
+            d[q].v[1] *= E2;
+            d[q].v[2] *= E1;
+        }
+        d[0].v[2] += dE1 * (m->v[2] - 1.0);   /* d(E1 mz + 1 - E1)/dlnT1 */
+        d[1].v[0] += dE2 * m->v[0];
+        d[1].v[1] += dE2 * m->v[1];
+    }
+    m->v[0] *= E2;
+    m->v[1] *= E2;
+    m->v[2] = E1 * m->v[2] + (1.0 - E1);
+}
+
+void oracle_isochromat(const oracle_problem *p, double lnT1, double lnT2, double B1, double scale,
+                       double complex *m, double complex *dm1, double complex *dm2,
+                       double complex *dm3)
+{
+    const int tang = dm1 != NULL;
+    double T1 = exp(lnT1), T2 = exp(lnT2);
+    vec3 x = {{0.0, 0.0, 1.0}};          /* equilibrium (S2) */
+    vec3 d[3] = {{{0, 0, 0}}, {{0, 0, 0}}, {{0, 0, 0}}};
+    x.v[2] = -x.v[2];                    /* ideal non-selective inversion */
+    iso_relax(&x, d, p->t_inv, T1, T2, tang);
+    for (int n = 0; n < p->n_tr; ++n) {
+        double phi = p->rf_phase ? p->rf_phase[n] : 0.0;
+        double k[3] = {cos(phi), sin(phi), 0.0};
+        double a = p->flip_deg[n] * PI / 180.0 * scale;   /* d theta / d B1 */
+        double th = B1 * a, c = cos(th), s = sin(th);
+        if (tang) {
+            vec3 dB = rodrigues_dtheta(x, k, c, s);
+            for (int q = 0; q < 3; ++q) d[q] = rodrigues(d[q], k, c, s);
+            for (int i = 0; i < 3; ++i) d[2].v[i] += a * dB.v[i];
+        }
+        x = rodrigues(x, k, c, s);
+        iso_relax(&x, d, p->te, T1, T2, tang);
+        double complex dem = cexp(-I * phi);
+        m[n] = (x.v[0] + I * x.v[1]) * dem;
+        if (tang) {
+            dm1[n] = (d[0].v[0] + I * d[0].v[1]) * dem;
+            dm2[n] = (d[1].v[0] + I * d[1].v[1]) * dem;
+            dm3[n] = (d[2].v[0] + I * d[2].v[1]) * dem;
+        }
+        iso_relax(&x, d, p->tr - p->te, T1, T2, tang);
+    }
+}
+
+/* Voxel trains of the balanced model: the weighted sum over the isochromats
+ * of the slice profile. */
+static void iso_simulate_voxel(const oracle_problem *p, double lnT1, double lnT2, double B1,
+                               int tang, double complex *m, double complex *dm1,
+                               double complex *dm2, double complex *dm3, size_t stride)
+{
+    const int T = p->n_tr;
+    double complex *b = (double complex *)malloc((size_t)4 * T * sizeof(double complex));
+    for (int n = 0; n < T; ++n) {
+        m[(size_t)n * stride] = 0.0;
+        if (tang) dm1[(size_t)n * stride] = dm2[(size_t)n * stride] = dm3[(size_t)n * stride] = 0.0;
+    }
+    for (int q = 0; q < p->n_iso; ++q) {
+        oracle_isochromat(p, lnT1, lnT2, B1, p->iso_scale[q], b, tang ? b + T : NULL, b + 2 * T, b + 3 * T);
+        double w = p->iso_weight[q];
+        for (int n = 0; n < T; ++n) {
+            m[(size_t)n * stride] += w * b[n];
+            if (tang) {
+                dm1[(size_t)n * stride] += w * b[T + n];
+                dm2[(size_t)n * stride] += w * b[2 * T + n];
+                dm3[(size_t)n * stride] += w * b[3 * T + n];
+            }
+        }
+    }
+    free(b);
+}
+
 void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
                 double complex *trains)
 {
@@ -210,9 +325,14 @@ void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
     const size_t plane = (size_t)p->n_tr * Nv;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int j = 0; j < Nv; ++j) {
-        epg_simulate_voxel(p, theta[j], theta[Nv + j], theta[2 * Nv + j], with_tangents,
-                           trains + j, trains + plane + j, trains + 2 * plane + j,
-                           trains + 3 * plane + j, (size_t)Nv);
+        if (p->n_iso > 0)
+            iso_simulate_voxel(p, theta[j], theta[Nv + j], theta[2 * Nv + j], with_tangents,
+                               trains + j, trains + plane + j, trains + 2 * plane + j,
+                               trains + 3 * plane + j, (size_t)Nv);
+        else
+            epg_simulate_voxel(p, theta[j], theta[Nv + j], theta[2 * Nv + j], with_tangents,
+                               trains + j, trains + plane + j, trains + 2 * plane + j,
+                               trains + 3 * plane + j, (size_t)Nv);
     }
 }
 

@@ -47,6 +47,14 @@ typedef struct {
      * sits at (kx, ky)[n * n_read + k] in cycles per field of view, and the
      * encoding is evaluated as a direct sum; ky_line is then unused. */
     const double *kx, *ky;
+    /* Balanced isochromat signal model (Methods, Pulse Sequence and
+     * Reconstructions; Supporting Information S2): when n_iso > 0 the trains
+     * come from n_iso isochromats per voxel instead of the EPG, isochromat q
+     * seeing the flip angle scaled by iso_scale[q] (the slice profile) and
+     * entering the voxel's magnetisation with weight iso_weight[q]; no
+     * spoiling and no off-resonance (a balanced sequence on resonance). */
+    int n_iso;
+    const double *iso_scale, *iso_weight;
 } oracle_problem;
 
 typedef struct {
@@ -63,6 +71,15 @@ typedef struct {
 } oracle_gn_report;
 
 int oracle_num_threads(void);
+
+/* One isochromat of the balanced model: n_tr demodulated transverse
+ * magnetisations at TE (and their derivatives in ln T1, ln T2, B1 when
+ * dm1 != NULL) for flip angles scaled by `scale`; the Supporting Information
+ * S2 update (Rodrigues rotation about the RF axis, then decay and regrowth)
+ * with forward-mode tangents. */
+void oracle_isochromat(const oracle_problem *p, double lnT1, double lnT2, double B1, double scale,
+                       double complex *m, double complex *dm1, double complex *dm2,
+                       double complex *dm3);
 
 /* EPG simulation with forward-mode tangents (Supporting Information S2
  * pattern, applied to the extended-phase-graph states).

@@ -92,6 +92,7 @@ def lib():
             "mrstat_bind_static": ([vp, vp, vp, vp], C.c_int),
             "mrstat_set_encoding": ([vp, C.c_int], C.c_int),
             "mrstat_set_epg_lanes": ([vp, i32], C.c_int),
+            "mrstat_set_isochromats": ([vp, i32, P(C.c_double), P(C.c_double)], C.c_int),
             "mrstat_set_train_precision": ([vp, C.c_int], C.c_int),
             "mrstat_simulate": ([vp, vp, vp, vp], C.c_int),
             "mrstat_residual": ([vp, vp, i32, vp, vp, P(C.c_double), vp], C.c_int),
@@ -141,7 +142,8 @@ def exported_symbols():
             "mrstat_mlp_set_scaling", "mrstat_mlp_fit_scaling", "mrstat_mlp_set_params",
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
-            "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj"]
+            "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj",
+            "mrstat_set_isochromats"]
 
 
 def _check(status, ctx=None):
@@ -205,6 +207,15 @@ def mrstat_set_encoding(ctx, enc):
 
 def mrstat_set_train_precision(ctx, prec):
     _check(lib().mrstat_set_train_precision(ctx, int(prec)), ctx)
+
+
+def mrstat_set_isochromats(ctx, scale, weight):
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    wt = np.ascontiguousarray(weight, dtype=np.float64)
+    if sc.shape != wt.shape or sc.ndim != 1:
+        raise ValueError("scale and weight must be 1-d arrays of one length")
+    _check(lib().mrstat_set_isochromats(ctx, int(sc.size), sc.ctypes.data_as(C.POINTER(C.c_double)),
+                                        wt.ctypes.data_as(C.POINTER(C.c_double))), ctx)
 
 
 def mrstat_set_epg_lanes(ctx, lanes):
@@ -378,6 +389,9 @@ class Context:
             self._expect(self.mask, torch.uint8, (nv,))
         coil = self.coil.data_ptr() if self.coil is not None else None
         mask = self.mask.data_ptr() if self.mask is not None else None
+        iso = getattr(self.prob, "iso", None)
+        if iso is not None:
+            mrstat_set_isochromats(self.h, iso[0], iso[1])
         if self.static:
             self.ws = None
             mrstat_bind_static(self.h, coil, mask, self.stream)

@@ -46,6 +46,7 @@ struct mrstat_ctx_s {
     mrstat_enc enc = MRSTAT_ENC_FP32;
     int epg_lanes = 0;
     mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
+    IsoProfile iso{};             // balanced isochromat model when iso.n > 0 (else the EPG)
     bool f16 = false;             // trains stored as FP16
     // bound device state
     char* ws = nullptr;
@@ -276,8 +277,12 @@ mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, int n
     const int ntan = ntr - 1;   // tangent trains: 3, 2 or 0
     const int kind = tangents ? MRSTAT_K_EPG : MRSTAT_K_EPG_VALUE;
     if (!ctx->surr) {
-        HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, ntan, ctx->epg_lanes,
-                                        ctx->f16, s)));
+        if (ctx->iso.n > 0)
+            HIP_TRY(TRACED(kind, launch_iso(d, ctx->st, theta, ctx->dseq(), out, ntan, ctx->f16, ctx->iso,
+                                            nullptr, nullptr, s)));
+        else
+            HIP_TRY(TRACED(kind, launch_epg(d, ctx->st, theta, ctx->dseq(), out, ntan, ctx->epg_lanes,
+                                            ctx->f16, s)));
         return MRSTAT_OK;
     }
     const int skind = tangents ? MRSTAT_K_SURR : MRSTAT_K_SURR_VALUE;
@@ -288,6 +293,11 @@ mrstat_status simulate_into(mrstat_ctx ctx, const float* theta, void* out, int n
                                                        ctx->fb_count(slot), s)));
     // A short list of scattered voxels is latency bound: spread each voxel's
     // states over the most lanes unless a split was set explicitly.
+    if (ctx->iso.n > 0) {
+        HIP_TRY(TRACED(kind, launch_iso(d, ctx->st, theta, ctx->dseq(), out, ntan, ctx->f16, ctx->iso,
+                                        ctx->fb_idx(), ctx->fb_count(slot), s)));
+        return MRSTAT_OK;
+    }
     const int fb_lanes = ctx->epg_lanes ? ctx->epg_lanes : (d.K <= 8 ? 2 : d.K <= 16 ? 4 : 8);
     HIP_TRY(TRACED(kind, launch_epg_list(d, ctx->st, theta, ctx->dseq(), out, ntan, fb_lanes,
                                          ctx->f16, ctx->fb_idx(), ctx->fb_count(slot), s)));
@@ -597,6 +607,26 @@ mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec)
         return fail(ctx, MRSTAT_ERR_UNSUPPORTED,
                     "FP16 trains need a surrogate of width 64, 128 or 256 (the other widths infer in FP32)");
     ctx->f16 = prec == MRSTAT_TRAINS_FP16;
+    ctx->lin_valid = false;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_set_isochromats(mrstat_ctx ctx, int32_t n_iso, const double* h_scale,
+                                     const double* h_weight)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (n_iso < 0 || n_iso > MAX_ISOCHROMATS)
+        return fail(ctx, MRSTAT_ERR_ARG, "n_iso must be in [0, 32]");
+    if (n_iso > 0 && (!h_scale || !h_weight)) return fail(ctx, MRSTAT_ERR_ARG, "scale or weight is NULL");
+    IsoProfile p{};
+    p.n = n_iso;
+    for (int q = 0; q < n_iso; ++q) {
+        if (!std::isfinite(h_scale[q]) || !std::isfinite(h_weight[q]))
+            return fail(ctx, MRSTAT_ERR_ARG, "non-finite isochromat scale or weight");
+        p.scale[q] = (float)h_scale[q];
+        p.weight[q] = (float)h_weight[q];
+    }
+    ctx->iso = p;
     ctx->lin_valid = false;
     return MRSTAT_OK;
 }

@@ -40,6 +40,22 @@ struct SeqTimes {
     float tr, te, tinv;
 };
 
+// ---------------------------------------------------------------- balanced isochromat model
+// Slice profile of the balanced isochromat model (iso.hip): isochromat q has
+// the flip angle scaled by scale[q] and weight weight[q]; n in [1, 32].
+constexpr int MAX_ISOCHROMATS = 32;
+struct IsoProfile {
+    int n;
+    float scale[MAX_ISOCHROMATS];
+    float weight[MAX_ISOCHROMATS];
+};
+// Trains of the balanced isochromat model, same outputs and layout as
+// launch_epg (ntan 3, 2 or 0); with idx non-null only the voxels
+// idx[0 .. *count) (the surrogate's fallback list).
+hipError_t launch_iso(const Dims& d, SeqTimes st, const float* theta, const float2* seq, void* out, int ntan,
+                      bool f16, const IsoProfile& prof, const int* idx, const int* count, hipStream_t s);
+
+
 // Tiling of the encoding kernels, chosen per problem on the host.
 struct YPlan {
     int r_fwd;        // forward y-stage: row steps per lane (32 r_fwd rows per block)

@@ -39,6 +39,7 @@ class Problem:
     rf_phase: np.ndarray
     ky_line: np.ndarray
     traj: tuple | None = None     # (kx, ky) [n_tr][n_read] cycles per FOV; None = Cartesian
+    iso: tuple | None = None      # (flip scale, weight) [n_iso]: balanced isochromat model; None = EPG
 
     @property
     def nv(self) -> int:
@@ -120,6 +121,23 @@ def cartesian_traj(prob: "Problem") -> tuple:
     kx = np.tile((np.arange(prob.n_read) - prob.n_read // 2) * (prob.nx / prob.n_read), (prob.n_tr, 1))
     ky = np.repeat((prob.ky_line.astype(np.float64) - prob.ny // 2)[:, None], prob.n_read, axis=1)
     return kx, ky
+
+
+def slice_profile_gaussian(n_iso: int, z_max: float = 1.5) -> tuple:
+    """Slice profile of a Gaussian RF envelope for the balanced isochromat
+    model: n_iso positions z uniformly spaced over [-z_max, z_max] slice
+    thicknesses (cell centres), flip-angle scale exp(-4 ln 2 z^2) (full width
+    at half maximum one slice thickness: the small-tip profile of a Gaussian
+    pulse is Gaussian) and weight dz (a midpoint sum over z).
+    Returns (scale, weight), each [n_iso]."""
+    dz = 2.0 * z_max / n_iso
+    z = -z_max + dz * (np.arange(n_iso) + 0.5)
+    return np.exp(-4.0 * np.log(2.0) * z * z), np.full(n_iso, dz)
+
+
+def balanced_phases(n_tr: int) -> np.ndarray:
+    """RF phase alternating 0 / 180 degrees (the paper's balanced sequence)."""
+    return np.pi * (np.arange(n_tr) % 2)
 
 
 def pack_theta(T1, T2, B1, rho) -> np.ndarray:

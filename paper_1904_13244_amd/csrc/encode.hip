@@ -217,20 +217,17 @@ __global__ __launch_bounds__(1024) void ystage_fwd_kernel(
 // and at most 256, 16-byte aligned operands). Each lane owns 4 consecutive
 // columns, so one load moves 4 train elements (8 bytes) and a wave covers a
 // whole row. Loop order is the transpose of the kernels above: a
-// block takes NT TRs and a slab of rows; its waves walk the slab's rows
-// (wave w: rows y0 + w, y0 + w + NWW, ...), loading each voxel's weights
+// block takes NT TRs and a slab of rows; its NW waves walk the slab's rows
+// (wave w: rows y0 + w, y0 + w + NW, ...), loading each voxel's weights
 // (from L2: they are shared by every TR chunk) and its NT TRs of trains, and
 // keep the NT per-column sums in registers. One LDS reduction across the
-// waves per block; few row slabs (often one) so U needs few or no partial
-// sums.
+// waves per block; U partial sums per row slab.
 // ------------------------------------------------------------------------
-constexpr int NWW = 8;   // waves per block
-
 template <typename TT> struct Vec4;
 template <> struct Vec4<_Float16> { typedef _Float16 T __attribute__((ext_vector_type(4))); };
 
-template <int MODE, int NT, typename TT>
-__global__ __launch_bounds__(NWW * 64) __attribute__((amdgpu_waves_per_eu(4)))
+template <int MODE, int NT, int NW, typename TT>
+__global__ __launch_bounds__(NW * 64)
 void ystage_fwd_wide_kernel(
     const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
     const uint8_t* __restrict__ mask, const float2* __restrict__ eytab, float2* __restrict__ U,
@@ -238,9 +235,9 @@ void ystage_fwd_wide_kernel(
 {
     typedef typename Vec4<TT>::T V4;
     constexpr bool JV = MODE != 0, DB1 = MODE == 1;   // J v direction; with the dm/dB1 train
-    // LDS: per-wave sums [NWW][NT][nx], then the slab's y-phases [NT][rows].
+    // LDS: per-wave sums [NW][NT][nx], then the slab's y-phases [NT][rows].
     extern __shared__ float2 lds[];
-    float2* eys = lds + (size_t)NWW * NT * nx;
+    float2* eys = lds + (size_t)NW * NT * nx;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x0 = 4 * lane;
     const bool colok = x0 < nx;
@@ -267,7 +264,7 @@ void ystage_fwd_wide_kernel(
     for (int t = 0; t < NT; ++t) toff[t] = (size_t)(n0 + (t < nt ? t : 0)) * nv;
 
     if (colok) {
-        for (int iy = y0 + wave; iy < y1; iy += NWW) {
+        for (int iy = y0 + wave; iy < y1; iy += NW) {
             const int j = iy * nx + x0;
             f4 pr = *(const f4*)(theta + 3 * (size_t)nv + j);
             f4 pi = *(const f4*)(theta + 4 * (size_t)nv + j);
@@ -341,7 +338,7 @@ void ystage_fwd_wide_kernel(
         const int t = o / nx, ix = o % nx;
         float2 s = lds[(size_t)t * nx + ix];
 #pragma unroll
-        for (int w = 1; w < NWW; ++w) {
+        for (int w = 1; w < NW; ++w) {
             const float2 u = lds[((size_t)w * NT + t) * nx + ix];
             s.x += u.x;
             s.y += u.y;
@@ -1455,22 +1452,26 @@ hipError_t fwd_R(const Dims& d, const YPlan& p, const TT* trains, const float* t
     // Wide layout (FP16 trains) when the plan allows it and every operand is
     // 16-byte aligned.
     if constexpr (CC == 1 && sizeof(TT) == 2) {
+        // NT TRs x NW waves per block (the plan's), fewer TRs when their
+        // per-wave sums would not fit in 64 KB of LDS.
         int ntw = MODE == 0 ? p.ntws16 : p.ntw16;
-        // At most 64 KB of LDS per block.
-        while (ntw >= 2 && (size_t)ntw * (NWW * d.nx + p.roww) * sizeof(float2) > 65536) ntw /= 2;
+        const int nw = p.nww;
+        auto lds_of = [&](int nt, int w) { return (size_t)nt * (w * d.nx + p.roww) * sizeof(float2); };
+        while (ntw >= 2 && lds_of(ntw, nw) > 65536) ntw /= 2;
         auto al = [](const void* q, uintptr_t a) { return ((uintptr_t)q & (a - 1)) == 0; };
         if (ntw >= 2 && al(trains, 16) && al(theta, 16) && (MODE == 0 || al(v, 16)) &&
             (mask == nullptr || al(mask, 4))) {
             dim3 grid(p.nbyw, ceil_div(d.T, ntw));
-            const size_t lds = (size_t)ntw * (NWW * d.nx + p.roww) * sizeof(float2);
+            const size_t lds = lds_of(ntw, nw);
             *nby_used = p.nbyw;
-#define FWDW_CASE(NN)                                                                           \
-    if (ntw == NN) {                                                                            \
-        ystage_fwd_wide_kernel<MODE, NN, TT><<<grid, NWW * 64, lds, s>>>(                       \
+#define FWDW_CASE(NN, WW)                                                                       \
+    if (ntw == NN && nw == WW) {                                                                \
+        ystage_fwd_wide_kernel<MODE, NN, WW, TT><<<grid, WW * 64, lds, s>>>(                    \
             trains, theta, v, mask, eytab, U, d.nx, d.ny, d.nv, d.T, p.roww);                   \
         return hipGetLastError();                                                               \
     }
-            FWDW_CASE(2) FWDW_CASE(4)
+            FWDW_CASE(8, 4) FWDW_CASE(4, 4) FWDW_CASE(2, 4) FWDW_CASE(8, 8) FWDW_CASE(4, 8)
+            FWDW_CASE(2, 8)
 #undef FWDW_CASE
             return hipErrorInvalidValue;
         }
@@ -1623,9 +1624,15 @@ YPlan make_yplan(const Dims& d)
     const bool wide = d.C == 1 && d.nx % 4 == 0 && d.nx <= 256;
     // FP16 trains only (with FP32 trains the kernel's registers allow just 2
     // TRs per block in mode 1, slower than the layouts above). Measured at
-    // 224 x 224: 4 TRs per block, 8 slabs of 28 rows.
+    // 224 x 224, 1120 TRs, four trains, inside GN steps (TRs x waves per
+    // block, row slabs: forward time): 4 x 8, 8 slabs 87.5 us; 8 x 4 98.4;
+    // 4 x 4 89.8; 2 x 8 95.3; 2 x 4 97.7; 4 x 8 with 4 slabs 91.4, with 16
+    // 91.4. Standalone, with the trains not in cache, 8 x 4 led (93 against
+    // 116 us): inside the CG loop each y-stage starts on trains the other
+    // just read, and that order favours 4 x 8.
     p.ntw16 = wide ? 4 : 0;
     p.ntws16 = wide ? 4 : 0;
+    p.nww = 8;
     p.nbyw = std::min(d.ny, std::max(8, ceil_div(d.ny, 256)));   // <= 256 rows per slab
     p.roww = ceil_div(d.ny, p.nbyw);
     p.nbyw = ceil_div(d.ny, p.roww);
@@ -1635,7 +1642,8 @@ YPlan make_yplan(const Dims& d)
     p.r_adj = 1;
     // One coil: 9 chunks (measured at 224 x 224, 1120 TRs, per chunk count
     // 4 / 5 / 8 / 9 / 12: FP16 wide kernel 92 / 104 / 96 / 92 / 98 us, FP32
-    // 183 / 162 / 171 / 162 / 169 us). Coils: 8 (the 256 x 256, 8-coil GN step
+    // 183 / 162 / 171 / 162 / 169 us; inside GN steps, four FP16 trains:
+    // 4 / 9 / 18 chunks 88.0 / 82.3 / 83.7 us). Coils: 8 (the 256 x 256, 8-coil GN step
     // took 1.6 ms longer with 9).
     p.adj_chunks = std::min(d.C == 1 ? 9 : 8, d.T);
     // LDS staging of the y-phases: chunk TRs x rows of a block (<= 64 KB;

@@ -70,6 +70,7 @@ struct YPlan {
     int ntw16, ntws16, nbyw, roww;       // forward y-stage, wide layout (FP16 trains): TRs per
                                          // block in mode 1 / mode 0 (0 = off), row slabs, rows
                                          // per slab
+    int nww;                             // waves per block of the wide forward y-stage (4 or 8)
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

@@ -195,6 +195,40 @@ mrstat_status mrstat_set_train_precision(mrstat_ctx ctx, mrstat_trains prec);
  * in practice: every order is updated by the same arithmetic). */
 mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
 
+/* Readout dynamics (Discussion: the volumetric signal model follows T2 decay
+ * and Delta B0 phase accumulation during each readout). Creates a Cartesian,
+ * single-coil context like mrstat_create whose sample k of every readout is
+ * taken at TE + tau_k, tau_k = (k - n_read/2) dwell_s, and whose voxel j's
+ * magnetisation carries exp(-tau_k / T2_j) exp(-2 pi i db0_j (TE + tau_k))
+ * (db0 in Hz from mrstat_set_db0, zero until set; the precession has the
+ * sense of the encoding phase). The residual, J v, J^H w (whose ln T2 column
+ * gains the readout decay's tau_k / T2 term), the GN and trust-region steps
+ * and the rho initialisation all use this model; the linearisation (the
+ * trains at TE) is unchanged, since for the gradient-spoiled EPG model an
+ * off-resonance changes the echo by its phase only. On the GPU the factor
+ * exp(lambda tau), lambda = -1/T2 - 2 pi i db0, is expanded in powers of
+ * tau / tau_max (tau_max = (n_read/2) dwell_s) with as many terms (8 to 32,
+ * mrstat_readout_terms) as keep the remainder below 1e-7 for T2 >= min_t2_s
+ * and |db0| <= max_abs_db0_hz; every product then streams the trains once per
+ * term set and runs its x-GEMMs over all terms. GN and trust-region steps
+ * refuse an ln T2 box below ln(min_t2_s) (MRSTAT_ERR_ARG); values of db0 or
+ * T2 outside the bounds lose the stated accuracy. n_coils must be 1, nx <= 256,
+ * n_read >= 2 (else MRSTAT_ERR_UNSUPPORTED / MRSTAT_ERR_SHAPE); the encoding
+ * is Cartesian and the problem is validated as by mrstat_create. */
+mrstat_status mrstat_create_readout(const mrstat_problem *p, double dwell_s, double min_t2_s,
+                                    double max_abs_db0_hz, mrstat_ctx *out);
+
+/* Off-resonance map of a readout-dynamics context: device float [Nv] in Hz,
+ * read by every product while set (not copied; the caller keeps it alive);
+ * NULL = zero. MRSTAT_ERR_STATE for a context without readout dynamics, or
+ * for a map on a context set to the balanced isochromat model (whose echo an
+ * off-resonance changes beyond a phase; its T2 decay during the readout is
+ * modelled). */
+mrstat_status mrstat_set_db0(mrstat_ctx ctx, const float *d_db0);
+
+/* Terms of the readout-dynamics expansion (0 for other contexts). */
+mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t *h_terms);
+
 /* Signal model of the linearisation: the gradient-spoiled EPG (n_iso = 0,
  * the default) or the balanced isochromat model of the paper's own sequence
  * (Methods, Pulse Sequence and Reconstructions; Supporting Information S2):
@@ -207,7 +241,8 @@ mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
  * derivatives in ln T1, ln T2 and B1 in forward mode. The trains have the
  * layout of the EPG's, and every call of the context (and the surrogate's
  * fallback) uses the model set here. Host arrays [n_iso] read during the
- * call; 0 <= n_iso <= 32; non-finite entries give MRSTAT_ERR_ARG.
+ * call; 0 <= n_iso <= 32; non-finite entries give MRSTAT_ERR_ARG; n_iso > 0
+ * while an off-resonance map is set gives MRSTAT_ERR_STATE.
  * Invalidates the linearisation. */
 mrstat_status mrstat_set_isochromats(mrstat_ctx ctx, int32_t n_iso, const double *h_scale,
                                      const double *h_weight);

@@ -49,7 +49,8 @@ class _Problem(C.Structure):
                 ("flip_deg", C.POINTER(C.c_double)), ("rf_phase", C.POINTER(C.c_double)),
                 ("ky_line", C.POINTER(C.c_int)), ("kx", C.POINTER(C.c_double)),
                 ("ky", C.POINTER(C.c_double)), ("n_iso", C.c_int),
-                ("iso_scale", C.POINTER(C.c_double)), ("iso_weight", C.POINTER(C.c_double))]
+                ("iso_scale", C.POINTER(C.c_double)), ("iso_weight", C.POINTER(C.c_double)),
+                ("dwell", C.c_double), ("db0", C.POINTER(C.c_double))]
 
 
 class _GnOpts(C.Structure):
@@ -155,11 +156,21 @@ class _Bound:
             n_iso = self.iso_s.size
             sp = self.iso_s.ctypes.data_as(C.POINTER(C.c_double))
             wp = self.iso_w.ctypes.data_as(C.POINTER(C.c_double))
+        dwell = float(getattr(prob, "dwell", 0.0) or 0.0)
+        db0 = getattr(prob, "db0", None)
+        bp = None
+        if db0 is not None:
+            if n_iso:
+                raise ValueError("the balanced isochromat model is not combined with off-resonance")
+            self.db0 = np.ascontiguousarray(db0, dtype=np.float64)
+            assert self.db0.shape == (prob.nx * prob.ny,)
+            bp = self.db0.ctypes.data_as(C.POINTER(C.c_double))
         self.s = _Problem(prob.nx, prob.ny, prob.n_tr, prob.n_read, prob.n_states,
                           prob.n_coils, prob.tr, prob.te, prob.t_inv,
                           self.flip.ctypes.data_as(C.POINTER(C.c_double)),
                           self.phase.ctypes.data_as(C.POINTER(C.c_double)),
-                          self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp, n_iso, sp, wp)
+                          self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp, n_iso, sp, wp,
+                          dwell, bp)
         self.nv = prob.nx * prob.ny
         self.prob = prob
 

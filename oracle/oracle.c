@@ -346,6 +346,26 @@ void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
 
 static int non_cartesian(const oracle_problem *p) { return p->kx != NULL; }
 
+/* Readout dynamics (see oracle_problem): on when samples carry the factor
+ * exp(-tau_k / T2_j) exp(-2 pi i db0_j (TE + tau_k)). */
+static int readout_on(const oracle_problem *p) { return p->dwell != 0.0 || p->db0 != NULL; }
+
+static double readout_tau(const oracle_problem *p, int k)
+{
+    return (double)(k - p->n_read / 2) * p->dwell;
+}
+
+/* The factor of voxel j at sample k (1 when readout dynamics are off). */
+static double complex readout_factor(const oracle_problem *p, const double *theta, int j, int k)
+{
+    if (!readout_on(p)) return 1.0;
+    const int Nv = p->nx * p->ny;
+    const double tau = readout_tau(p, k);
+    const double r2 = exp(-theta[(size_t)Nv + j]);   /* 1 / T2, theta row 1 = ln T2 */
+    const double f = p->db0 ? p->db0[j] : 0.0;
+    return cexp(-tau * r2 - 2.0 * PI * I * f * (p->te + tau));
+}
+
 static double complex phase_x(const oracle_problem *p, int k, int ix)
 {
     double kx = (double)(k - p->n_read / 2) / (double)p->n_read;
@@ -421,7 +441,8 @@ void oracle_signal_direct(const oracle_problem *p, const double *theta,
                 if (!active(mask, j)) continue;
                 int ix = j % p->nx, iy = j / p->nx;
                 acc += coil_at(coil, c, Nv, j) * rho_of(theta, Nv, j) *
-                       trains[(size_t)n * Nv + j] * oracle_phase(p, n, k, ix, iy);
+                       trains[(size_t)n * Nv + j] * oracle_phase(p, n, k, ix, iy) *
+                       readout_factor(p, theta, j, k);
             }
             s[(size_t)row * p->n_read + k] = acc;
         }
@@ -453,6 +474,38 @@ static void encode_direct(const oracle_problem *p, const double complex *coil,
                 s[((size_t)c * p->n_tr + n) * p->n_read + k] = acc;
             }
         free(x);
+    }
+}
+
+/* With readout dynamics every sample has its own factor per voxel:
+ * s_c[n,k] = sum_j C_c[j] (x0[n,j] + tau_k x1[n,j]) F[k,j] E[n,k,j], F the
+ * readout factor; x1 carries the readout decay's share of the ln T2 column
+ * (zero for the signal). Direct sum. */
+static void encode_readout(const oracle_problem *p, const double *theta, const double complex *coil,
+                           const unsigned char *mask, voxel_value_fn x0val, voxel_value_fn x1val,
+                           const void *ctx, double complex *s)
+{
+    const int Nv = nvox(p), C = p->n_coils;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int n = 0; n < p->n_tr; ++n) {
+        double complex *x0 = (double complex *)malloc((size_t)Nv * sizeof(double complex));
+        double complex *x1 = (double complex *)malloc((size_t)Nv * sizeof(double complex));
+        for (int j = 0; j < Nv; ++j) {
+            x0[j] = active(mask, j) ? x0val(ctx, n, j) : 0.0;
+            x1[j] = (active(mask, j) && x1val) ? x1val(ctx, n, j) : 0.0;
+        }
+        for (int c = 0; c < C; ++c)
+            for (int k = 0; k < p->n_read; ++k) {
+                const double tau = readout_tau(p, k);
+                double complex acc = 0.0;
+                for (int j = 0; j < Nv; ++j)
+                    if (active(mask, j))
+                        acc += coil_at(coil, c, Nv, j) * (x0[j] + tau * x1[j]) *
+                               readout_factor(p, theta, j, k) * oracle_phase(p, n, k, j % p->nx, j / p->nx);
+                s[((size_t)c * p->n_tr + n) * p->n_read + k] = acc;
+            }
+        free(x0);
+        free(x1);
     }
 }
 
@@ -508,7 +561,10 @@ void oracle_signal_separable(const oracle_problem *p, const double *theta,
                              const double complex *trains, double complex *s)
 {
     xval_ctx c = {p, theta, trains, NULL};
-    encode_separable(p, coil, mask, xval_signal, &c, s);
+    if (readout_on(p))
+        encode_readout(p, theta, coil, mask, xval_signal, NULL, &c, s);
+    else
+        encode_separable(p, coil, mask, xval_signal, &c, s);
 }
 
 /* J v = -(d s / d alpha) v (Theory: dr/dalpha_i = -d(rho_j m_j)/dalpha_i). */
@@ -522,23 +578,64 @@ static double complex xval_jv(const void *vc, int n, int j)
     return acc;
 }
 
+/* The readout decay's share of the ln T2 column, times v: d/dlnT2 of
+ * exp(-tau / T2) is (tau / T2) exp(-tau / T2), so the term is
+ * rho m (1 / T2) v_lnT2, multiplied by tau_k in the encoding. */
+static double complex xval_jv_tau(const void *vc, int n, int j)
+{
+    const xval_ctx *c = (const xval_ctx *)vc;
+    int Nv = nvox(c->p);
+    const double r2 = exp(-c->theta[(size_t)Nv + j]);
+    return rho_of(c->theta, Nv, j) * c->trains[(size_t)n * Nv + j] * r2 * c->v[(size_t)Nv + j];
+}
+
 void oracle_jv(const oracle_problem *p, const double *theta,
                const double complex *coil, const unsigned char *mask,
                const double complex *trains, const double *v, double complex *out)
 {
     xval_ctx c = {p, theta, trains, v};
-    encode_separable(p, coil, mask, xval_jv, &c, out);
+    if (readout_on(p))
+        encode_readout(p, theta, coil, mask, xval_jv, xval_jv_tau, &c, out);
+    else
+        encode_separable(p, coil, mask, xval_jv, &c, out);
     size_t total = (size_t)p->n_coils * p->n_tr * p->n_read;
     for (size_t i = 0; i < total; ++i) out[i] = -out[i];
 }
 
 /* V[n][j] = sum_c conj(C_c[j]) sum_k conj(E[n,k,j]) w_c[n,k] (adjoint of the
  * encoding), evaluated as the x-sum then the y-phase. V is [n_tr][Nv]. */
-static void adjoint_encode(const oracle_problem *p, const double complex *coil,
+static void adjoint_encode(const oracle_problem *p, const double *theta, const double complex *coil,
                            const unsigned char *mask, const double complex *w,
-                           double complex *V)
+                           double complex *V, double complex *Vtau)
 {
     const int Nv = nvox(p), C = p->n_coils;
+    if (readout_on(p)) {
+        /* V[n][j] = sum_c conj(C_c[j]) sum_k conj(F[k,j] E[n,k,j]) w_c[n,k] and,
+         * when Vtau is given, the same sum with tau_k in each term. */
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int n = 0; n < p->n_tr; ++n)
+            for (int j = 0; j < Nv; ++j) {
+                double complex acc = 0.0, acct = 0.0;
+                if (active(mask, j))
+                    for (int c = 0; c < C; ++c) {
+                        double complex sc = 0.0, sct = 0.0;
+                        for (int k = 0; k < p->n_read; ++k) {
+                            const double complex t = conj(readout_factor(p, theta, j, k) *
+                                                          oracle_phase(p, n, k, j % p->nx, j / p->nx)) *
+                                                     w[((size_t)c * p->n_tr + n) * p->n_read + k];
+                            sc += t;
+                            sct += readout_tau(p, k) * t;
+                        }
+                        acc += conj(coil_at(coil, c, Nv, j)) * sc;
+                        acct += conj(coil_at(coil, c, Nv, j)) * sct;
+                    }
+                V[(size_t)n * Nv + j] = acc;
+                if (Vtau) Vtau[(size_t)n * Nv + j] = acct;
+            }
+        return;
+    }
+    if (Vtau)   /* no readout dynamics: tau plays no part */
+        for (size_t i = 0; i < (size_t)p->n_tr * Nv; ++i) Vtau[i] = 0.0;
     if (non_cartesian(p)) {
         /* Direct: V[n][j] = sum_c conj(C_c[j]) sum_k conj(E[n,k,j]) w_c[n,k]. */
 #pragma omp parallel for schedule(dynamic, 1)
@@ -591,18 +688,24 @@ void oracle_jhw(const oracle_problem *p, const double *theta,
 {
     const int Nv = nvox(p);
     double complex *V = (double complex *)malloc((size_t)p->n_tr * Nv * sizeof(double complex));
-    adjoint_encode(p, coil, mask, w, V);
+    double complex *Vt = (double complex *)malloc((size_t)p->n_tr * Nv * sizeof(double complex));
+    adjoint_encode(p, theta, coil, mask, w, V, Vt);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < Nv; ++j) {
         for (int q = 0; q < NPAR; ++q) {
             double complex acc = 0.0;
             if (active(mask, j))
-                for (int n = 0; n < p->n_tr; ++n)
+                for (int n = 0; n < p->n_tr; ++n) {
                     acc += conj(dcol(theta, trains, Nv, p->n_tr, q, n, j)) * V[(size_t)n * Nv + j];
+                    if (q == 1)   /* the readout decay's share of the ln T2 column */
+                        acc += conj(rho_of(theta, Nv, j) * trains[(size_t)n * Nv + j] *
+                                    exp(-theta[(size_t)Nv + j])) * Vt[(size_t)n * Nv + j];
+                }
             out[(size_t)q * Nv + j] = -creal(acc);
         }
     }
     free(V);
+    free(Vt);
 }
 
 void oracle_jacobian(const oracle_problem *p, const double *theta,
@@ -622,8 +725,12 @@ void oracle_jacobian(const oracle_problem *p, const double *theta,
                 double complex e = 0.0;
                 if (active(mask, j)) {
                     int ix = j % p->nx, iy = j / p->nx;
+                    double complex d = dcol(theta, trains, Nv, p->n_tr, q, n, j);
+                    if (q == 1)   /* the readout decay's share of the ln T2 column */
+                        d += rho_of(theta, Nv, j) * trains[(size_t)n * Nv + j] * exp(-theta[(size_t)Nv + j]) *
+                             readout_tau(p, k);
                     e = -coil_at(coil, c, Nv, j) * oracle_phase(p, n, k, ix, iy) *
-                        dcol(theta, trains, Nv, p->n_tr, q, n, j);
+                        readout_factor(p, theta, j, k) * d;
                 }
                 J[(size_t)row * cols + (size_t)q * Nv + j] = e;
             }
@@ -1008,7 +1115,7 @@ void oracle_rho_init(const oracle_problem *p, double *theta,
     /* A^H w */
 #define ADJ(w, out)                                                          \
     do {                                                                     \
-        adjoint_encode(p, coil, mask, (w), V);                               \
+        adjoint_encode(p, theta, coil, mask, (w), V, NULL);                  \
         for (int j = 0; j < Nv; ++j) {                                       \
             double complex acc = 0.0;                                        \
             for (int n = 0; n < p->n_tr; ++n)                                \

@@ -55,6 +55,20 @@ typedef struct {
      * spoiling and no off-resonance (a balanced sequence on resonance). */
     int n_iso;
     const double *iso_scale, *iso_weight;
+    /* Readout dynamics (Discussion: the volumetric model follows T2 decay and
+     * Delta B0 phase accumulation during each readout): sample k of every
+     * readout is taken at TE + tau_k, tau_k = (k - n_read / 2) dwell seconds,
+     * and voxel j's transverse magnetisation carries the factor
+     * exp(-tau_k / T2_j) exp(-2 pi i db0_j (TE + tau_k)) (db0 in Hz per voxel,
+     * NULL = 0; the precession has the sense of the encoding phase, which a
+     * gradient field adds the same way). Off when dwell == 0 and db0 == NULL.
+     * For the gradient-spoiled
+     * EPG model a uniform off-resonance changes the echo by that phase only
+     * (the spoiler's dephasing absorbs it between pulses); the balanced
+     * isochromat model is not combined with off-resonance (n_iso > 0 requires
+     * db0 == NULL). The encoding is then evaluated as a direct sum. */
+    double dwell;
+    const double *db0;
 } oracle_problem;
 
 typedef struct {

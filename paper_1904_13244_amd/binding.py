@@ -85,6 +85,10 @@ def lib():
         sig = {
             "mrstat_create": ([P(Problem), P(vp)], C.c_int),
             "mrstat_create_traj": ([P(Problem), vp, vp, P(vp)], C.c_int),
+            "mrstat_create_readout": ([P(Problem), C.c_double, C.c_double, C.c_double, P(vp)],
+                                      C.c_int),
+            "mrstat_set_db0": ([vp, vp], C.c_int),
+            "mrstat_readout_terms": ([vp, P(i32)], C.c_int),
             "mrstat_destroy": ([vp], None),
             "mrstat_last_error": ([vp], C.c_char_p),
             "mrstat_workspace_bytes": ([vp], C.c_size_t),
@@ -143,7 +147,8 @@ def exported_symbols():
             "mrstat_mlp_get_params", "mrstat_mlp_gradients", "mrstat_mlp_train_step",
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
             "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj",
-            "mrstat_set_isochromats"]
+            "mrstat_set_isochromats", "mrstat_create_readout", "mrstat_set_db0",
+            "mrstat_readout_terms"]
 
 
 def _check(status, ctx=None):
@@ -162,8 +167,9 @@ def _check_mlp(status, net):
 def mrstat_create(prob):
     """prob: object with nx, ny, n_tr, n_read, n_states, n_coils, tr, te, t_inv,
     flip_deg, rf_phase, ky_line and optionally traj = (kx, ky) [n_tr][n_read]
-    cycles per field of view (non-Cartesian: mrstat_create_traj). Returns
-    the context handle."""
+    cycles per field of view (non-Cartesian: mrstat_create_traj), and
+    optionally dwell > 0 with the bounds rd_min_t2, rd_max_db0 (readout
+    dynamics: mrstat_create_readout). Returns the context handle."""
     flip = np.ascontiguousarray(prob.flip_deg, dtype=np.float64)
     phase = np.ascontiguousarray(prob.rf_phase, dtype=np.float64)
     ky = np.ascontiguousarray(prob.ky_line, dtype=np.int32)
@@ -174,7 +180,13 @@ def mrstat_create(prob):
                 ky.ctypes.data_as(C.POINTER(C.c_int32)))
     h = C.c_void_p()
     traj = getattr(prob, "traj", None)
-    if traj is None:
+    dwell = float(getattr(prob, "dwell", 0.0) or 0.0)
+    if dwell > 0.0:
+        if traj is not None:
+            raise ValueError("readout dynamics take a Cartesian encoding")
+        _check(lib().mrstat_create_readout(C.byref(s), dwell, float(prob.rd_min_t2),
+                                           float(prob.rd_max_db0), C.byref(h)))
+    elif traj is None:
         _check(lib().mrstat_create(C.byref(s), C.byref(h)))
     else:
         kx = np.ascontiguousarray(traj[0], dtype=np.float64)
@@ -216,6 +228,16 @@ def mrstat_set_isochromats(ctx, scale, weight):
         raise ValueError("scale and weight must be 1-d arrays of one length")
     _check(lib().mrstat_set_isochromats(ctx, int(sc.size), sc.ctypes.data_as(C.POINTER(C.c_double)),
                                         wt.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+
+
+def mrstat_set_db0(ctx, db0_ptr):
+    _check(lib().mrstat_set_db0(ctx, db0_ptr), ctx)
+
+
+def mrstat_readout_terms(ctx):
+    n = C.c_int32()
+    _check(lib().mrstat_readout_terms(ctx, C.byref(n)), ctx)
+    return int(n.value)
 
 
 def mrstat_set_epg_lanes(ctx, lanes):
@@ -392,6 +414,14 @@ class Context:
         iso = getattr(self.prob, "iso", None)
         if iso is not None:
             mrstat_set_isochromats(self.h, iso[0], iso[1])
+        self.db0 = None
+        db0 = getattr(self.prob, "db0", None)
+        if db0 is not None and float(getattr(self.prob, "dwell", 0.0) or 0.0) > 0.0:
+            # the library reads the map in place: the context keeps it alive
+            self.db0 = torch.as_tensor(np.asarray(db0, dtype=np.float32)).to(self.dev)
+            if tuple(self.db0.shape) != (nv,):
+                raise ValueError(f"db0 must have shape ({nv},)")
+            mrstat_set_db0(self.h, self.db0.data_ptr())
         if self.static:
             self.ws = None
             mrstat_bind_static(self.h, coil, mask, self.stream)
@@ -449,6 +479,9 @@ class Context:
 
     def set_epg_lanes(self, lanes):
         mrstat_set_epg_lanes(self.h, lanes)
+
+    def readout_terms(self):
+        return mrstat_readout_terms(self.h)
 
     def set_train_precision(self, prec):
         mrstat_set_train_precision(self.h, prec)

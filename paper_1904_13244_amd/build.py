@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrstat.so")
-SOURCES = ["epg.hip", "iso.hip", "encode.hip", "noncart.hip", "vec.hip", "api.hip", "mlp.hip", "mlp_api.hip"]
+SOURCES = ["epg.hip", "iso.hip", "encode.hip", "noncart.hip", "readout.hip", "vec.hip", "api.hip", "mlp.hip",
+           "mlp_api.hip"]
 ARCH = os.environ.get("MRSTAT_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -26,8 +26,10 @@ struct Layout {
     size_t hbuf;       // surrogate hidden activations, BF16 [nv][256]
     size_t cx, csv, cp, cth, fb, total;
     size_t ax, ay;     // non-Cartesian trajectory tables, FP64 [T][nk] (0 bytes otherwise)
+    size_t rdU, rdY, rdw, rdW;   // readout-dynamics term buffers (0 bytes otherwise)
     int n_red;
     YPlan yp;
+    YPlan rdp;         // plan of the x-GEMMs over the readout-dynamics terms (nq terms as rows)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -47,6 +49,12 @@ struct mrstat_ctx_s {
     int epg_lanes = 0;
     mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
     IsoProfile iso{};             // balanced isochromat model when iso.n > 0 (else the EPG)
+    int rd_nq = 0;                // readout dynamics: expansion terms (0 = off)
+    float rd_tmax = 0.f;          // largest |tau| of a sample, seconds
+    float rd_dwell_u = 0.f;       // sample spacing in units of rd_tmax
+    double rd_min_t2 = 0.0;       // T2 bound of the expansion, seconds
+    double rd_max_db0 = 0.0;      // |db0| bound of the expansion, Hz
+    const float* rd_db0 = nullptr;   // off-resonance map [nv] in Hz (device, caller's; null = 0)
     bool f16 = false;             // trains stored as FP16
     // bound device state
     char* ws = nullptr;
@@ -87,6 +95,11 @@ struct mrstat_ctx_s {
     const void* bfrag(int dir) const { return enc == 0 ? nullptr : (const void*)(ws + L.bf[dir][enc - 1]); }
     int* fb_count(int slot) const { return at<int>(L.fb) + slot; }   // 0: linearisation, 1: value
     int* fb_idx() const { return at<int>(L.fb) + 64; }
+    float2* rdU() const { return at<float2>(L.rdU); }
+    float2* rdY() const { return at<float2>(L.rdY); }
+    float2* rdw() const { return at<float2>(L.rdw); }
+    float2* rdW() const { return at<float2>(L.rdW); }
+    Dims rd_dims() const { Dims q = d; q.C = rd_nq; return q; }   // the terms as rows of the x-GEMMs
 };
 
 namespace {
@@ -142,10 +155,13 @@ hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
 
 #define TRACED(kind, call) traced(ctx, (kind), s, [&]() { return (call); })
 
-Layout make_layout(const Dims& d, bool nc)
+Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
 {
     Layout L{};
     L.yp = make_yplan(d);
+    Dims dq = d;
+    dq.C = rd_nq > 0 ? rd_nq : 1;
+    L.rdp = make_yplan(dq);
     if (nc) {
         // The non-Cartesian adjoint's TR chunks replace the y-stage's in the
         // partial-sum layout the gradient assembly reads.
@@ -181,6 +197,11 @@ Layout make_layout(const Dims& d, bool nc)
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
     L.ay = take(nc ? T * d.nk * sizeof(double) : 0);
+    const size_t nq = rd_nq > 0 ? (size_t)rd_nq : 0;
+    L.rdU = take(nq * T * d.nx * sizeof(float2));
+    L.rdY = take(nq * T * d.nk * sizeof(float2));
+    L.rdw = take(nq * T * d.nk * sizeof(float2));
+    L.rdW = take((size_t)(nq ? L.rdp.ksplit_adj : 0) * nq * T * d.nx * sizeof(float2));
     L.total = o;
     return L;
 }
@@ -325,6 +346,23 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
+    if (ctx->rd_nq > 0) {
+        // Readout dynamics: the term sums, their x-GEMM, the per-sample weighting.
+        const int nq = ctx->rd_nq;
+        HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
+                       launch_rd_fwd(d, nq, mode_y, trains, ctx->f16, theta, v, ctx->mask, ctx->rd_db0,
+                                     ctx->deytab(), ctx->rdU(), ctx->st.te, ctx->rd_tmax, s)));
+        HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(ctx->rd_dims(), ctx->L.rdp, ctx->enc, 2, ctx->rdU(),
+                                                       ctx->dextab(), ctx->bfrag(0), nullptr, ctx->rdY(), nullptr,
+                                                       nullptr, s)));
+        int nred = 0;
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_combine(d, nq, mode_x, ctx->rdY(), ctx->rd_dwell_u,
+                                                          (const float2*)data, (float2*)out, ctx->red(), &nred,
+                                                          s)));
+        if (mode_x == 0 && f_out)
+            HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_sum_partials(ctx->red(), nred, f_out, s)));
+        return MRSTAT_OK;
+    }
     if (ctx->nc) {
         int nred = 0;
         HIP_TRY(TRACED(MRSTAT_K_NC_FWD, launch_nc_fwd(d, ctx->enc, mode_y, mode_x, trains, ctx->f16, theta, v,
@@ -359,6 +397,18 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     const int ntr = ctx->lin_ntr;
     if (ntr < 4 && ((param_mask >> 2) & 1))
         return fail(ctx, MRSTAT_ERR_STATE, "linearisation holds no dm/dB1 train");
+    if (ctx->rd_nq > 0) {
+        const int nq = ctx->rd_nq;
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nq, ctx->rd_dwell_u, (const float2*)w, ctx->rdw(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+                                                       ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
+                                                    ctx->mask, ctx->rd_db0, ctx->deytab(), ctx->rdW(),
+                                                    ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
+        HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
+                                                          dir, dir ? ctx->red() : nullptr, s, step)));
+        return MRSTAT_OK;
+    }
     if (ctx->nc) {
         HIP_TRY(TRACED(MRSTAT_K_NC_ADJ, launch_nc_adj(d, ctx->enc, ntr, p.adj_chunks, ctx->trains(), ctx->f16,
                                                       ctx->coil, ctx->mask, ctx->dax(), ctx->day(),
@@ -384,7 +434,8 @@ extern "C" {
 
 namespace {
 
-mrstat_status create_impl(const mrstat_problem* p, const double* kx, const double* ky, mrstat_ctx* out)
+mrstat_status create_impl(const mrstat_problem* p, const double* kx, const double* ky, mrstat_ctx* out,
+                          int rd_nq = 0)
 {
     mrstat_ctx ctx = nullptr;
     if (!p || !out) return fail(nullptr, MRSTAT_ERR_ARG, "null problem or output pointer");
@@ -443,7 +494,8 @@ mrstat_status create_impl(const mrstat_problem* p, const double* kx, const doubl
     } else {
         build_tables(ctx, p);
     }
-    ctx->L = make_layout(ctx->d, nc);
+    ctx->rd_nq = rd_nq;
+    ctx->L = make_layout(ctx->d, nc, rd_nq);
     *out = ctx;
     return MRSTAT_OK;
 }
@@ -464,6 +516,47 @@ mrstat_status mrstat_create_traj(const mrstat_problem* p, const double* kx, cons
         return fail(nullptr, MRSTAT_ERR_ARG, "kx or ky is NULL");
     }
     return create_impl(p, kx, ky, out);
+}
+
+mrstat_status mrstat_create_readout(const mrstat_problem* p, double dwell_s, double min_t2_s,
+                                    double max_abs_db0_hz, mrstat_ctx* out)
+{
+    if (out) *out = nullptr;
+    if (!p || !out) return fail(nullptr, MRSTAT_ERR_ARG, "null problem or output pointer");
+    if (!(std::isfinite(dwell_s) && dwell_s > 0.0) || !(std::isfinite(min_t2_s) && min_t2_s > 0.0) ||
+        !(std::isfinite(max_abs_db0_hz) && max_abs_db0_hz >= 0.0))
+        return fail(nullptr, MRSTAT_ERR_ARG, "dwell and min_t2 must be positive, max_abs_db0 >= 0");
+    if (p->n_coils != 1) return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout dynamics need one coil");
+    if (p->nx > 256 || p->n_read < 2) return fail(nullptr, MRSTAT_ERR_SHAPE, "readout dynamics need nx <= 256, n_read >= 2");
+    const double tmax = (double)(p->n_read / 2) * dwell_s;
+    const double bound = (1.0 / min_t2_s + 2.0 * kPi * max_abs_db0_hz) * tmax;
+    const int nq = rd_terms(bound);
+    if (nq == 0) return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout too long for the expansion (|lambda| tau > bound)");
+    mrstat_status st = create_impl(p, nullptr, nullptr, out, nq);
+    if (st != MRSTAT_OK) return st;
+    mrstat_ctx c = *out;
+    c->rd_tmax = (float)tmax;
+    c->rd_dwell_u = (float)(dwell_s / tmax);
+    c->rd_min_t2 = min_t2_s;
+    c->rd_max_db0 = max_abs_db0_hz;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_set_db0(mrstat_ctx ctx, const float* d_db0)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (ctx->rd_nq == 0) return fail(ctx, MRSTAT_ERR_STATE, "the context models no readout dynamics");
+    if (d_db0 && ctx->iso.n > 0)
+        return fail(ctx, MRSTAT_ERR_STATE, "an off-resonance map needs the gradient-spoiled model");
+    ctx->rd_db0 = d_db0;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t* h_terms)
+{
+    if (!ctx || !h_terms) return MRSTAT_ERR_ARG;
+    *h_terms = ctx->rd_nq;
+    return MRSTAT_OK;
 }
 
 void mrstat_destroy(mrstat_ctx ctx)
@@ -618,6 +711,8 @@ mrstat_status mrstat_set_isochromats(mrstat_ctx ctx, int32_t n_iso, const double
     if (n_iso < 0 || n_iso > MAX_ISOCHROMATS)
         return fail(ctx, MRSTAT_ERR_ARG, "n_iso must be in [0, 32]");
     if (n_iso > 0 && (!h_scale || !h_weight)) return fail(ctx, MRSTAT_ERR_ARG, "scale or weight is NULL");
+    if (n_iso > 0 && ctx->rd_db0)
+        return fail(ctx, MRSTAT_ERR_STATE, "the balanced model takes no off-resonance map");
     IsoProfile p{};
     p.n = n_iso;
     for (int q = 0; q < n_iso; ++q) {
@@ -753,6 +848,8 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         return fail(ctx, MRSTAT_ERR_ARG, "invalid GN options");
     for (int q = 0; q < 3; ++q)
         if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    if (ctx->rd_nq > 0 && ((o->param_mask >> 1) & 1) && o->lo[1] < std::log(ctx->rd_min_t2) - 1e-6)
+        return fail(ctx, MRSTAT_ERR_ARG, "the ln T2 box reaches below the readout expansion's min_t2");
     std::memset(rep, 0, sizeof(*rep));
     const Dims& d = ctx->d;
     float* g = ctx->vec(0);
@@ -844,6 +941,8 @@ mrstat_status mrstat_tr_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
         return fail(ctx, MRSTAT_ERR_ARG, "invalid trust-region options or radius");
     for (int q = 0; q < 3; ++q)
         if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    if (ctx->rd_nq > 0 && ((o->param_mask >> 1) & 1) && o->lo[1] < std::log(ctx->rd_min_t2) - 1e-6)
+        return fail(ctx, MRSTAT_ERR_ARG, "the ln T2 box reaches below the readout expansion's min_t2");
     std::memset(rep, 0, sizeof(*rep));
     rep->delta_in = delta;
     rep->delta_out = delta;
@@ -948,7 +1047,15 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     // M^H w for the rho-linear map: adjoint y-stage on the m train only.
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
         const YPlan& p = ctx->L.yp;
-        if (ctx->nc) {
+        if (ctx->rd_nq > 0) {
+            const int nq = ctx->rd_nq;
+            HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nq, ctx->rd_dwell_u, w, ctx->rdw(), s)));
+            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+                                                           ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
+            HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, 1, p.adj_chunks, ctx->trains(), ctx->f16,
+                                                        d_theta, ctx->mask, ctx->rd_db0, ctx->deytab(),
+                                                        ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
+        } else if (ctx->nc) {
             HIP_TRY(TRACED(MRSTAT_K_NC_ADJ, launch_nc_adj(d, ctx->enc, 1, p.adj_chunks, ctx->trains(), ctx->f16,
                                                           ctx->coil, ctx->mask, ctx->dax(), ctx->day(), w,
                                                           ctx->apart(), s)));

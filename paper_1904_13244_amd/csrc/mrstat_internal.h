@@ -40,6 +40,22 @@ struct SeqTimes {
     float tr, te, tinv;
 };
 
+// ---------------------------------------------------------------- readout dynamics
+// Term-wise y-stages and sample weighting of the readout-dynamics expansion
+// (readout.hip): U [nq][T][nx], Y [nq][T][nk] (x-GEMM of U), w_q [nq][T][nk],
+// W [nq][T][nx] (adjoint x-GEMM of w_q); apart as for the static adjoint.
+// rd_terms: the term count for a bound on |lambda| tau_max (0 = none fits).
+int rd_terms(double bound);
+hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
+                         const float* v, const uint8_t* mask, const float* db0, const float2* eytab, float2* U,
+                         float te, float tmax, hipStream_t s);
+hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
+                             float2* out, double* red, int* nred, hipStream_t s);
+hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s);
+hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
+                         const float* theta, const uint8_t* mask, const float* db0, const float2* eytab,
+                         const float2* W, float* apart, float te, float tmax, hipStream_t s);
+
 // ---------------------------------------------------------------- balanced isochromat model
 // Slice profile of the balanced isochromat model (iso.hip): isochromat q has
 // the flip angle scaled by scale[q] and weight weight[q]; n in [1, 32].

@@ -1,0 +1,397 @@
+// Readout dynamics (Discussion: the volumetric model follows T2 decay and
+// Delta B0 phase accumulation during each readout). Sample k of every readout
+// is taken at TE + tau_k, tau_k = (k - nk/2) dwell, and voxel j's transverse
+// magnetisation carries
+//     F[k, j] = exp(-tau_k / T2_j) exp(-2 pi i db0_j (TE + tau_k))
+//             = c_j exp(lambda_j tau_k),   lambda_j = -1/T2_j - 2 pi i db0_j,
+// c_j = exp(-2 pi i db0_j TE). F depends on voxel and sample together, so the
+// Cartesian encoding no longer factors into a y-stage per TR and one x-stage.
+// With u = tau / tau_max in [-1, 1] and L_j = lambda_j tau_max the factor is
+// expanded as exp(L_j u) = sum_{q < NQ} L_j^q u^q / q! (NQ chosen at context
+// creation so the remainder stays below 1e-7, the FP32 level, over the stated
+// T2 and db0 bounds), which restores the factorisation term by term:
+//     s[n,k] = sum_q (u_k^q / q!) sum_ix Ex[k,ix] U_q[n,ix],
+//     U_q[n,ix] = sum_iy Ey[n,iy] c_j (x[n,j] L_j^q + y[n,j] q L_j^(q-1)),
+// where x is the voxel weight of the static model and y the readout decay's
+// share of the ln T2 column (d/dlnT2 exp(-tau/T2) = (tau/T2) exp(-tau/T2):
+// y = i rho mu (tau_max / T2) v_lnT2, multiplied by u in the sum). The x-stage
+// of each term is the library's x-GEMM with the NQ terms as rows; this file
+// holds the term-wise y-stages and the per-sample weighting.
+//   forward:  rd_fwd_kernel (U_q) -> x-GEMM (Y_q = Ex U_q) -> rd_combine_kernel
+//             (s = sum_q u^q/q! Y_q, then r = d - s, -s or s);
+//   adjoint:  rd_expand_kernel (w_q = u^q/q! w) -> adjoint x-GEMM
+//             (W_q = Ex^H w_q) -> rd_adj_kernel: per voxel and TR
+//             V = sum_q conj(L)^q W_q, V' = sum_q (q+1) conj(L)^q W_(q+1),
+//             A_p += mu_p conj(c Ey) V, A_lnT2 += (tau_max/T2) mu_0 conj(c Ey) V'
+//             (the exact transpose of the truncated forward).
+// FP32 arithmetic; the sums of the expansion are in the dimensionless u and L
+// so no term over- or underflows.
+#include "mrstat_internal.h"
+
+#include <cmath>
+
+namespace mrstat {
+namespace {
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr int RD_NTB = 2;   // TRs per forward block
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ float2 cmulconj(float2 a, float2 b)   // conj(a) * b
+{
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x));
+}
+
+// Per-voxel quantities of the expansion: L = lambda tau_max, r2t = tau_max / T2
+// and c = exp(-2 pi i db0 TE).
+struct RdVoxel {
+    float2 L, c;
+    float r2t;
+};
+
+__device__ __forceinline__ RdVoxel rd_voxel(const float* __restrict__ theta, const float* __restrict__ db0,
+                                             int nv, int j, float te, float tmax)
+{
+    RdVoxel o;
+    const float r2 = expf(-theta[(size_t)nv + j]);   // theta row 1 = ln T2
+    const float f = db0 ? db0[j] : 0.f;
+    o.r2t = r2 * tmax;
+    o.L = make_float2(-o.r2t, -kTwoPi * f * tmax);
+    float sn, cs;
+    sincosf(kTwoPi * f * te, &sn, &cs);
+    o.c = make_float2(cs, -sn);
+    return o;
+}
+
+// Forward term sums. Block = 256 lanes, one image column per lane (nx <=
+// 256), RD_NTB TRs; the lanes walk all rows, keeping the NQ complex sums of
+// each TR in registers; U written once per (term, TR, column), no partials.
+// MODE as the static y-stages: 0 signal, 1 J v with four trains, 3 J v with
+// three (B1 held fixed).
+template <int MODE, int NQ, typename TT>
+__global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
+                                                     const float* __restrict__ v, const uint8_t* __restrict__ mask,
+                                                     const float* __restrict__ db0, const float2* __restrict__ eytab,
+                                                     float2* __restrict__ U, int nx, int ny, int nv, int T,
+                                                     float te, float tmax)
+{
+    constexpr bool JV = MODE != 0, DB1 = MODE == 1;
+    const int ix = threadIdx.x;
+    const bool colok = ix < nx;
+    const int n0 = blockIdx.x * RD_NTB;
+    const size_t plane = (size_t)T * nv;
+    float2 acc[RD_NTB][NQ];
+#pragma unroll
+    for (int t = 0; t < RD_NTB; ++t)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[t][q] = make_float2(0.f, 0.f);
+    if (colok) {
+        for (int iy = 0; iy < ny; ++iy) {
+            const int j = iy * nx + ix;
+            if (mask != nullptr && mask[j] == 0) continue;   // no contribution
+            const RdVoxel vx = rd_voxel(theta, db0, nv, j, te, tmax);
+            const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
+            float nr = 0.f, ni = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
+            if constexpr (JV) {
+                nr = v[3 * (size_t)nv + j];
+                ni = v[4 * (size_t)nv + j];
+                w0 = v[j];
+                w1 = v[(size_t)nv + j];
+                if constexpr (DB1) w2 = v[2 * (size_t)nv + j];
+            }
+#pragma unroll
+            for (int t = 0; t < RD_NTB; ++t) {
+                const int n = min(n0 + t, T - 1);   // TRs past the end are not stored
+                const TT* b = trains + (size_t)n * nv + j;
+                const float mu = (float)b[0];
+                float2 x, y = make_float2(0.f, 0.f);   // i rho mu / i (rho a + nu mu); i rho mu r2t v_lnT2
+                if constexpr (!JV) {
+                    x = make_float2(-ri * mu, rr * mu);
+                } else {
+                    const float m1 = (float)b[plane], m2 = (float)b[2 * plane];
+                    const float a = DB1 ? fmaf(w0, m1, fmaf(w1, m2, w2 * (float)b[3 * plane])) : fmaf(w0, m1, w1 * m2);
+                    x = make_float2(-fmaf(ri, a, ni * mu), fmaf(rr, a, nr * mu));
+                    const float yt = mu * vx.r2t * w1;
+                    y = make_float2(-ri * yt, rr * yt);
+                }
+                const float2 ec = cmul(eytab[(size_t)n * ny + iy], vx.c);
+                float2 tq = cmul(ec, x);   // z L^q
+                acc[t][0].x += tq.x;
+                acc[t][0].y += tq.y;
+                if constexpr (JV) {
+                    float2 sq = cmul(ec, y);   // zy L^(q-1)
+#pragma unroll
+                    for (int q = 1; q < NQ; ++q) {
+                        tq = cmul(tq, vx.L);
+                        acc[t][q].x += fmaf((float)q, sq.x, tq.x);
+                        acc[t][q].y += fmaf((float)q, sq.y, tq.y);
+                        sq = cmul(sq, vx.L);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 1; q < NQ; ++q) {
+                        tq = cmul(tq, vx.L);
+                        acc[t][q].x += tq.x;
+                        acc[t][q].y += tq.y;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RD_NTB; ++t) {
+            const int n = n0 + t;
+            if (n < T)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) U[((size_t)q * T + n) * nx + ix] = acc[t][q];
+        }
+    }
+}
+
+// s[n,k] = sum_q (u_k^q / q!) Y_q[n,k]; MODE 0: out = data - s and FP64
+// partials of |out|^2 per block; 1: out = -s; 2: out = s.
+template <int MODE>
+__global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restrict__ Y, int nq, float dwell_u,
+                                                         const float2* __restrict__ data, float2* __restrict__ out,
+                                                         double* __restrict__ red, int T, int nk)
+{
+    const size_t count = (size_t)T * nk;
+    double sq = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % nk);
+        const float u = (float)(k - nk / 2) * dwell_u;
+        float2 s = Y[i];
+        float cq = 1.f;
+        for (int q = 1; q < nq; ++q) {
+            cq *= u / (float)q;
+            const float2 y = Y[(size_t)q * count + i];
+            s.x = fmaf(cq, y.x, s.x);
+            s.y = fmaf(cq, y.y, s.y);
+        }
+        if constexpr (MODE == 0) {
+            const float2 d = data[i];
+            const float2 r = make_float2(d.x - s.x, d.y - s.y);
+            out[i] = r;
+            sq += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+        } else if constexpr (MODE == 1) {
+            out[i] = make_float2(-s.x, -s.y);
+        } else {
+            out[i] = s;
+        }
+    }
+    if constexpr (MODE == 0) {
+        __shared__ double sh[4];
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) red[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    }
+}
+
+// w_q[n,k] = (u_k^q / q!) w[n,k], q = 0 .. nq - 1.
+__global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict__ w, float2* __restrict__ wq, int nq,
+                                                        float dwell_u, int T, int nk)
+{
+    const size_t count = (size_t)T * nk;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % nk);
+        const float u = (float)(k - nk / 2) * dwell_u;
+        const float2 x = w[i];
+        float cq = 1.f;
+        wq[i] = x;
+        for (int q = 1; q < nq; ++q) {
+            cq *= u / (float)q;
+            wq[(size_t)q * count + i] = make_float2(cq * x.x, cq * x.y);
+        }
+    }
+}
+
+// Adjoint term sums: one thread per voxel (256-voxel blocks) and TR chunk;
+// per TR the Horner sums V and V' over the terms, then the chunk partials A_p
+// in the layout the gradient assembly reads ([chunk][2 NTR planes][nv]; NTR =
+// 1 writes the m pair only, for the proton-density initialisation).
+template <int NTR, int NQ, typename TT>
+__global__ __launch_bounds__(256) void rd_adj_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
+                                                     const uint8_t* __restrict__ mask, const float* __restrict__ db0,
+                                                     const float2* __restrict__ eytab, const float2* __restrict__ W,
+                                                     float* __restrict__ apart, int nx, int ny, int nv, int T,
+                                                     int n_per_chunk, float te, float tmax)
+{
+    constexpr int PL = NTR == 1 ? 2 : 8;   // planes per chunk
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (j >= nv) return;
+    float* dst = apart + (size_t)chunk * PL * nv + j;
+    const bool on = mask == nullptr || mask[j] != 0;
+    if (!on) {
+#pragma unroll
+        for (int p = 0; p < 2 * NTR; ++p) dst[(size_t)p * nv] = 0.f;
+        return;
+    }
+    const int ix = j % nx, iy = j / nx;
+    const RdVoxel vx = rd_voxel(theta, db0, nv, j, te, tmax);
+    const float2 Lc = make_float2(vx.L.x, -vx.L.y);   // conj(L)
+    const int n0 = chunk * n_per_chunk, n1 = min(T, n0 + n_per_chunk);
+    const size_t plane = (size_t)T * nv, wplane = (size_t)T * nx;
+    float2 A[NTR], At = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int p = 0; p < NTR; ++p) A[p] = make_float2(0.f, 0.f);
+    for (int n = n0; n < n1; ++n) {
+        const float2* w = W + (size_t)n * nx + ix;
+        // Horner from the last term: V = sum_q conj(L)^q W_q,
+        // V' = sum_{q < NQ-1} (q + 1) conj(L)^q W_(q+1).
+        float2 V = w[(size_t)(NQ - 1) * wplane], Vt = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = NQ - 2; q >= 0; --q) {
+            const float2 wq = w[(size_t)q * wplane];
+            if constexpr (NTR >= 3) {
+                const float2 wn = w[(size_t)(q + 1) * wplane];
+                Vt = cmul(Vt, Lc);
+                Vt.x = fmaf((float)(q + 1), wn.x, Vt.x);
+                Vt.y = fmaf((float)(q + 1), wn.y, Vt.y);
+            }
+            V = cmul(V, Lc);
+            V.x += wq.x;
+            V.y += wq.y;
+        }
+        const float2 ec = cmul(eytab[(size_t)n * ny + iy], vx.c);   // c Ey
+        V = cmulconj(ec, V);
+        const TT* b = trains + (size_t)n * nv + j;
+#pragma unroll
+        for (int p = 0; p < NTR; ++p) {
+            const float m = (float)b[p * plane];
+            A[p].x = fmaf(m, V.x, A[p].x);
+            A[p].y = fmaf(m, V.y, A[p].y);
+        }
+        if constexpr (NTR >= 3) {
+            Vt = cmulconj(ec, Vt);
+            const float m0 = (float)b[0] * vx.r2t;
+            At.x = fmaf(m0, Vt.x, At.x);
+            At.y = fmaf(m0, Vt.y, At.y);
+        }
+    }
+    if constexpr (NTR >= 3) {
+        A[2].x += At.x;   // the readout decay's share of the ln T2 column
+        A[2].y += At.y;
+    }
+#pragma unroll
+    for (int p = 0; p < NTR; ++p) {
+        dst[(size_t)(2 * p) * nv] = A[p].x;
+        dst[(size_t)(2 * p + 1) * nv] = A[p].y;
+    }
+}
+
+template <int NQ, typename TT>
+hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, const float* v, const uint8_t* mask,
+                 const float* db0, const float2* eytab, float2* U, float te, float tmax, hipStream_t s)
+{
+    const int blocks = ceil_div(d.T, RD_NTB);
+    switch (mode) {
+    case 0: rd_fwd_kernel<0, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
+    case 1: rd_fwd_kernel<1, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
+    case 3: rd_fwd_kernel<3, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NQ, typename TT>
+hipError_t adj_q(const Dims& d, int ntr, int chunks, const TT* trains, const float* theta, const uint8_t* mask,
+                 const float* db0, const float2* eytab, const float2* W, float* apart, float te, float tmax,
+                 hipStream_t s)
+{
+    const int per = ceil_div(d.T, chunks);
+    if (chunks < 1 || ceil_div(d.T, per) != chunks) return hipErrorInvalidValue;
+    const dim3 grid(ceil_div(d.nv, 256), chunks);
+#define RD_ADJ(NT) rd_adj_kernel<NT, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, mask, db0, eytab, W, apart, d.nx, \
+                                                                 d.ny, d.nv, d.T, per, te, tmax)
+    if (ntr == 1)
+        RD_ADJ(1);
+    else if (ntr == 3)
+        RD_ADJ(3);
+    else if (ntr == 4)
+        RD_ADJ(4);
+    else
+        return hipErrorInvalidValue;
+#undef RD_ADJ
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int rd_terms(double bound)
+{
+    // Smallest term count from {8, 12, 16, 20, 24, 32} whose remainder bound
+    // L^(NQ-1) / (NQ-1)! e^L (the ln T2 share's expansion stops one order
+    // earlier than the factor's) stays below 1e-7; 0 when none does.
+    const int choices[] = {8, 12, 16, 20, 24, 32};
+    for (int nq : choices) {
+        double t = std::exp(bound);
+        for (int q = 1; q <= nq - 1; ++q) t *= bound / q;
+        if (t <= 1e-7) return nq;
+    }
+    return 0;
+}
+
+#define RD_NQ_DISPATCH(NQ_VAR, CALL)                                     \
+    switch (NQ_VAR) {                                                    \
+    case 8: { constexpr int NQ = 8; return CALL; }                       \
+    case 12: { constexpr int NQ = 12; return CALL; }                     \
+    case 16: { constexpr int NQ = 16; return CALL; }                     \
+    case 20: { constexpr int NQ = 20; return CALL; }                     \
+    case 24: { constexpr int NQ = 24; return CALL; }                     \
+    case 32: { constexpr int NQ = 32; return CALL; }                     \
+    default: return hipErrorInvalidValue;                                \
+    }
+
+hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
+                         const float* v, const uint8_t* mask, const float* db0, const float2* eytab, float2* U,
+                         float te, float tmax, hipStream_t s)
+{
+    if (d.nx > 256) return hipErrorInvalidValue;
+    if (f16) {
+        const _Float16* tr = static_cast<const _Float16*>(trains);
+        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, eytab, U, te, tmax, s)))
+    }
+    const float* tr = static_cast<const float*>(trains);
+    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, eytab, U, te, tmax, s)))
+}
+
+hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
+                             float2* out, double* red, int* nred, hipStream_t s)
+{
+    const int blocks = RED_BLOCKS;
+    if (nred) *nred = blocks;
+    switch (mode) {
+    case 0: rd_combine_kernel<0><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
+    case 1: rd_combine_kernel<1><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
+    case 2: rd_combine_kernel<2><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s)
+{
+    rd_expand_kernel<<<RED_BLOCKS, 256, 0, s>>>(w, wq, nq, dwell_u, d.T, d.nk);
+    return hipGetLastError();
+}
+
+hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
+                         const float* theta, const uint8_t* mask, const float* db0, const float2* eytab,
+                         const float2* W, float* apart, float te, float tmax, hipStream_t s)
+{
+    if (f16) {
+        const _Float16* tr = static_cast<const _Float16*>(trains);
+        RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, eytab, W, apart, te, tmax, s)))
+    }
+    const float* tr = static_cast<const float*>(trains);
+    RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, eytab, W, apart, te, tmax, s)))
+}
+
+#undef RD_NQ_DISPATCH
+
+}  // namespace mrstat

@@ -40,6 +40,10 @@ class Problem:
     ky_line: np.ndarray
     traj: tuple | None = None     # (kx, ky) [n_tr][n_read] cycles per FOV; None = Cartesian
     iso: tuple | None = None      # (flip scale, weight) [n_iso]: balanced isochromat model; None = EPG
+    dwell: float = 0.0            # readout sample spacing [s]; > 0: T2 decay and off-resonance during readouts
+    db0: np.ndarray | None = None  # [Nv] off-resonance [Hz] (readout dynamics); None = 0
+    rd_min_t2: float = 0.005      # readout dynamics on the GPU: T2 [s] and |db0| [Hz] bounds
+    rd_max_db0: float = 200.0     # within which its expansion holds FP32 accuracy
 
     @property
     def nv(self) -> int:

@@ -90,3 +90,65 @@ def test_bind_static_refuses_oversized_workspace_on_host():
         assert str(need) in msg and str(64 << 20) in msg
     finally:
         B.mrstat_destroy(h)
+
+
+def _expected_terms(prob):
+    """Smallest term count of 8, 12, 16, 20, 24, 32 whose remainder bound
+    e^b b^(NQ-1) / (NQ-1)! is at most 1e-7, b = (1 / min_t2 + 2 pi max|db0|)
+    tau_max, tau_max = (n_read / 2) dwell (0: none)."""
+    import math
+    b = (1.0 / prob.rd_min_t2 + 2 * math.pi * prob.rd_max_db0) * (prob.n_read // 2) * prob.dwell
+    for nq in (8, 12, 16, 20, 24, 32):
+        if math.exp(b) * b ** (nq - 1) / math.factorial(nq - 1) <= 1e-7:
+            return nq
+    return 0
+
+
+def test_readout_context_terms_and_refusals():
+    """mrstat_create_readout on the host: the expansion's term count follows
+    the stated remainder criterion, and invalid requests are refused before
+    any device work."""
+    import dataclasses
+    base = I.make_problem(20, 18, 12, 40, 8)
+    seen = set()
+    for n_read, dwell, db0 in ((20, 1 / 85.6e3, 0.0), (40, 1 / 85.6e3, 200.0), (150, 1 / 85.6e3, 200.0),
+                               (448, 1 / 85.6e3, 100.0), (448, 1 / 85.6e3, 200.0), (150, 4 / 85.6e3, 200.0)):
+        prob = dataclasses.replace(I.shrink(base, n_read=n_read), dwell=dwell, rd_max_db0=db0)
+        want = _expected_terms(prob)
+        assert want > 0
+        h = B.mrstat_create(prob)
+        try:
+            assert B.mrstat_readout_terms(h) == want, (n_read, dwell, db0)
+        finally:
+            B.mrstat_destroy(h)
+        seen.add(want)
+    assert seen == {8, 12, 16, 20, 24, 32}
+    # a readout too long for the expansion, more coils, wide images, bad bounds
+    too_long = dataclasses.replace(I.shrink(base, n_read=448), dwell=1 / 85.6e3, rd_max_db0=600.0)
+    assert _expected_terms(too_long) == 0 and _status(too_long) == B.ERR_UNSUPPORTED
+    rd = dataclasses.replace(base, dwell=1 / 85.6e3)
+    assert _status(I.shrink(rd, n_coils=2)) == B.ERR_UNSUPPORTED
+    assert _status(I.shrink(rd, nx=300, n_read=600)) == B.ERR_SHAPE
+    assert _status(dataclasses.replace(rd, rd_min_t2=0.0)) == B.ERR_ARG
+    assert _status(dataclasses.replace(rd, rd_max_db0=-1.0)) == B.ERR_ARG
+    # the off-resonance map: readout contexts only, and not with the balanced model
+    h = B.mrstat_create(base)
+    try:
+        assert B.mrstat_readout_terms(h) == 0
+        assert B.lib().mrstat_set_db0(h, C.c_void_p(4096)) == B.ERR_STATE
+    finally:
+        B.mrstat_destroy(h)
+    scale, weight = I.slice_profile_gaussian(5)
+    h = B.mrstat_create(rd)
+    try:
+        fake = C.c_void_p(4096)   # stored only: no product runs on this context
+        assert B.lib().mrstat_set_db0(h, fake) == B.OK
+        sc = np.ascontiguousarray(scale, dtype=np.float64)
+        wt = np.ascontiguousarray(weight, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        assert B.lib().mrstat_set_isochromats(h, 5, sc.ctypes.data_as(dp), wt.ctypes.data_as(dp)) == B.ERR_STATE
+        assert B.lib().mrstat_set_db0(h, None) == B.OK
+        assert B.lib().mrstat_set_isochromats(h, 5, sc.ctypes.data_as(dp), wt.ctypes.data_as(dp)) == B.OK
+        assert B.lib().mrstat_set_db0(h, fake) == B.ERR_STATE
+    finally:
+        B.mrstat_destroy(h)

@@ -50,7 +50,8 @@ class _Problem(C.Structure):
                 ("ky_line", C.POINTER(C.c_int)), ("kx", C.POINTER(C.c_double)),
                 ("ky", C.POINTER(C.c_double)), ("n_iso", C.c_int),
                 ("iso_scale", C.POINTER(C.c_double)), ("iso_weight", C.POINTER(C.c_double)),
-                ("dwell", C.c_double), ("db0", C.POINTER(C.c_double))]
+                ("dwell", C.c_double), ("db0", C.POINTER(C.c_double)),
+                ("db0_unit", C.c_double), ("db0_box", C.c_double)]
 
 
 class _GnOpts(C.Structure):
@@ -165,13 +166,20 @@ class _Bound:
             self.db0 = np.ascontiguousarray(db0, dtype=np.float64)
             assert self.db0.shape == (prob.nx * prob.ny,)
             bp = self.db0.ctypes.data_as(C.POINTER(C.c_double))
+        unit = float(getattr(prob, "db0_unit", 0.0) or 0.0)
+        box = 0.0
+        if unit > 0.0:
+            if bp is not None or n_iso:
+                raise ValueError("a fitted Delta B0 takes no map and no isochromat model")
+            box = float(getattr(prob, "rd_max_db0", 0.0) or 0.0)
         self.s = _Problem(prob.nx, prob.ny, prob.n_tr, prob.n_read, prob.n_states,
                           prob.n_coils, prob.tr, prob.te, prob.t_inv,
                           self.flip.ctypes.data_as(C.POINTER(C.c_double)),
                           self.phase.ctypes.data_as(C.POINTER(C.c_double)),
                           self.ky.ctypes.data_as(C.POINTER(C.c_int)), kxp, kyp, n_iso, sp, wp,
-                          dwell, bp)
+                          dwell, bp, unit, box)
         self.nv = prob.nx * prob.ny
+        self.np = 6 if unit > 0.0 else 5
         self.prob = prob
 
 
@@ -223,7 +231,7 @@ def phases(prob, n):
 def epg(prob, theta, tangents=True):
     """Trains [4][n_tr][Nv] complex: m, dm/dlnT1, dm/dlnT2, dm/dB1."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     out = np.zeros((4, prob.n_tr, b.nv), dtype=np.complex128)
     lib().oracle_epg(C.byref(b.s), th.ctypes.data, 1 if tangents else 0, out.ctypes.data)
     return out
@@ -231,7 +239,7 @@ def epg(prob, theta, tangents=True):
 
 def signal_direct(prob, theta, trains, coil=None, mask=None):
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     tr = _c128(trains, (4, prob.n_tr, b.nv))
     cl, mk = _coil(b, coil), _mask(b, mask)
     out = np.zeros(_dshape(prob), dtype=np.complex128)
@@ -243,7 +251,7 @@ def signal_direct(prob, theta, trains, coil=None, mask=None):
 def signal(prob, theta, trains, coil=None, mask=None):
     """Separable evaluation of the same sum as signal_direct."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     tr = _c128(trains, (4, prob.n_tr, b.nv))
     cl, mk = _coil(b, coil), _mask(b, mask)
     out = np.zeros(_dshape(prob), dtype=np.complex128)
@@ -254,9 +262,9 @@ def signal(prob, theta, trains, coil=None, mask=None):
 
 def jv(prob, theta, trains, v, coil=None, mask=None):
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     tr = _c128(trains, (4, prob.n_tr, b.nv))
-    vv = _f64(v, (5, b.nv))
+    vv = _f64(v, (b.np, b.nv))
     cl, mk = _coil(b, coil), _mask(b, mask)
     out = np.zeros(_dshape(prob), dtype=np.complex128)
     lib().oracle_jv(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), tr.ctypes.data,
@@ -266,11 +274,11 @@ def jv(prob, theta, trains, v, coil=None, mask=None):
 
 def jhw(prob, theta, trains, w, coil=None, mask=None):
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     tr = _c128(trains, (4, prob.n_tr, b.nv))
     ww = _c128(w, _dshape(prob))
     cl, mk = _coil(b, coil), _mask(b, mask)
-    out = np.zeros((5, b.nv), dtype=np.float64)
+    out = np.zeros((b.np, b.nv), dtype=np.float64)
     lib().oracle_jhw(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), tr.ctypes.data,
                      ww.ctypes.data, out.ctypes.data)
     return out
@@ -278,11 +286,11 @@ def jhw(prob, theta, trains, w, coil=None, mask=None):
 
 def jacobian(prob, theta, trains, coil=None, mask=None):
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     tr = _c128(trains, (4, prob.n_tr, b.nv))
     cl, mk = _coil(b, coil), _mask(b, mask)
     rows = prob.n_coils * prob.n_tr * prob.n_read
-    out = np.zeros((rows, 5 * b.nv), dtype=np.complex128)
+    out = np.zeros((rows, b.np * b.nv), dtype=np.complex128)
     lib().oracle_jacobian(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk),
                           tr.ctypes.data, out.ctypes.data)
     return out
@@ -291,7 +299,7 @@ def jacobian(prob, theta, trains, coil=None, mask=None):
 def residual(prob, theta, data, coil=None, mask=None):
     """Returns (f, r) with r = d - s(theta), f = 0.5 ||r||^2."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv))
+    th = _f64(theta, (b.np, b.nv))
     d = _c128(data, _dshape(prob))
     cl, mk = _coil(b, coil), _mask(b, mask)
     r = np.zeros(_dshape(prob), dtype=np.complex128)
@@ -304,7 +312,7 @@ def gn_step(prob, theta, data, n_cg, param_mask, lo, hi, n_ls_max=8, armijo_c1=1
             coil=None, mask=None):
     """One inexact GN iteration; returns (theta_new, GnReport)."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv)).copy()
+    th = _f64(theta, (b.np, b.nv)).copy()
     d = _c128(data, _dshape(prob))
     cl, mk = _coil(b, coil), _mask(b, mask)
     o = _GnOpts(n_cg, n_ls_max, param_mask, (C.c_double * 3)(*lo), (C.c_double * 3)(*hi),
@@ -319,7 +327,7 @@ def gn_step(prob, theta, data, n_cg, param_mask, lo, hi, n_ls_max=8, armijo_c1=1
 def rho_init(prob, theta, data, n_iter=20, coil=None, mask=None):
     """CGLS least-squares rho for fixed (T1, T2, B1); returns a new theta."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv)).copy()
+    th = _f64(theta, (b.np, b.nv)).copy()
     d = _c128(data, _dshape(prob))
     cl, mk = _coil(b, coil), _mask(b, mask)
     lib().oracle_rho_init(C.byref(b.s), th.ctypes.data, _ptr(cl), _ptr(mk), d.ctypes.data,
@@ -347,7 +355,7 @@ def tr_step(prob, theta, data, delta, n_cg, param_mask, lo, hi, eta=0.1, delta_m
             coil=None, mask=None):
     """One trust-region inexact GN iteration; returns (theta_new, delta_new, report dict)."""
     b = _Bound(prob)
-    th = _f64(theta, (5, b.nv)).copy()
+    th = _f64(theta, (b.np, b.nv)).copy()
     d = _c128(data, _dshape(prob))
     cl, mk = _coil(b, coil), _mask(b, mask)
     o = _TrOpts(n_cg, param_mask, (C.c_double * 3)(*lo), (C.c_double * 3)(*hi), eta, delta_max)

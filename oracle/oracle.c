@@ -48,7 +48,6 @@ int oracle_num_threads(void)
 #endif
 }
 
-#define NPAR 5
 static const double PI = 3.14159265358979323846;
 
 static int nvox(const oracle_problem *p) { return p->nx * p->ny; }
@@ -348,7 +347,20 @@ static int non_cartesian(const oracle_problem *p) { return p->kx != NULL; }
 
 /* Readout dynamics (see oracle_problem): on when samples carry the factor
  * exp(-tau_k / T2_j) exp(-2 pi i db0_j (TE + tau_k)). */
-static int readout_on(const oracle_problem *p) { return p->dwell != 0.0 || p->db0 != NULL; }
+static int readout_on(const oracle_problem *p)
+{
+    return p->dwell != 0.0 || p->db0 != NULL || p->db0_unit > 0.0;
+}
+
+/* Parameters per voxel: 5, or 6 with Delta B0 reconstructed. */
+static int npar(const oracle_problem *p) { return p->db0_unit > 0.0 ? 6 : 5; }
+
+/* Off-resonance of voxel j in Hz: the fitted row, the given map, or 0. */
+static double db0_of(const oracle_problem *p, const double *theta, int j)
+{
+    if (p->db0_unit > 0.0) return theta[(size_t)5 * p->nx * p->ny + j] * p->db0_unit;
+    return p->db0 ? p->db0[j] : 0.0;
+}
 
 static double readout_tau(const oracle_problem *p, int k)
 {
@@ -362,7 +374,7 @@ static double complex readout_factor(const oracle_problem *p, const double *thet
     const int Nv = p->nx * p->ny;
     const double tau = readout_tau(p, k);
     const double r2 = exp(-theta[(size_t)Nv + j]);   /* 1 / T2, theta row 1 = ln T2 */
-    const double f = p->db0 ? p->db0[j] : 0.0;
+    const double f = db0_of(p, theta, j);
     return cexp(-tau * r2 - 2.0 * PI * I * f * (p->te + tau));
 }
 
@@ -412,18 +424,37 @@ static double complex rho_of(const double *theta, int Nv, int j)
 }
 
 /* D_q[n,j] = d(rho_j m_j[n]) / d alpha_{q,j} (Theory: dr/dalpha_i involves only
- * voxel j's rho_j m_j): q<3 -> rho dm/dtheta_q, q=3 -> m, q=4 -> i m. */
-static double complex dcol(const double *theta, const double complex *trains,
-                           int Nv, int n_tr, int q, int n, int j)
+ * voxel j's rho_j m_j): q<3 -> rho dm/dtheta_q, q=3 -> m, q=4 -> i m. With
+ * readout dynamics the sample's derivative of rho m F is F (D_q + tau_k D'_q):
+ * q=5 (Delta B0) has D_5 = -2 pi i db0_unit TE rho m here and its tau part in
+ * dcol_tau. */
+static double complex dcol(const oracle_problem *p, const double *theta, const double complex *trains,
+                           int q, int n, int j)
 {
-    const size_t plane = (size_t)n_tr * Nv;
+    const int Nv = nvox(p);
+    const size_t plane = (size_t)p->n_tr * Nv;
     double complex m = trains[(size_t)n * Nv + j];
     switch (q) {
     case 0: case 1: case 2:
         return rho_of(theta, Nv, j) * trains[(size_t)(q + 1) * plane + (size_t)n * Nv + j];
     case 3: return m;
-    default: return I * m;
+    case 4: return I * m;
+    default: return -2.0 * PI * I * p->db0_unit * p->te * rho_of(theta, Nv, j) * m;
     }
+}
+
+/* D'_q: the factor of tau_k in the readout dynamics' share of the derivative.
+ * d/dlnT2 exp(-tau / T2) = (tau / T2) exp(-tau / T2) gives D'_1 = rho m / T2;
+ * d/dtheta_5 exp(-2 pi i db0 (TE + tau)) gives D'_5 = -2 pi i db0_unit rho m;
+ * the other parameters do not enter the factor. */
+static double complex dcol_tau(const oracle_problem *p, const double *theta, const double complex *trains,
+                               int q, int n, int j)
+{
+    const int Nv = nvox(p);
+    const double complex rm = rho_of(theta, Nv, j) * trains[(size_t)n * Nv + j];
+    if (q == 1) return rm * exp(-theta[(size_t)Nv + j]);
+    if (q == 5) return -2.0 * PI * I * p->db0_unit * rm;
+    return 0.0;
 }
 
 void oracle_signal_direct(const oracle_problem *p, const double *theta,
@@ -573,20 +604,21 @@ static double complex xval_jv(const void *vc, int n, int j)
     const xval_ctx *c = (const xval_ctx *)vc;
     int Nv = nvox(c->p);
     double complex acc = 0.0;
-    for (int q = 0; q < NPAR; ++q)
-        acc += dcol(c->theta, c->trains, Nv, c->p->n_tr, q, n, j) * c->v[(size_t)q * Nv + j];
+    for (int q = 0; q < npar(c->p); ++q)
+        acc += dcol(c->p, c->theta, c->trains, q, n, j) * c->v[(size_t)q * Nv + j];
     return acc;
 }
 
-/* The readout decay's share of the ln T2 column, times v: d/dlnT2 of
- * exp(-tau / T2) is (tau / T2) exp(-tau / T2), so the term is
- * rho m (1 / T2) v_lnT2, multiplied by tau_k in the encoding. */
+/* The readout dynamics' share of J v: sum_q D'_q v_q (the ln T2 and Delta B0
+ * columns), multiplied by tau_k in the encoding. */
 static double complex xval_jv_tau(const void *vc, int n, int j)
 {
     const xval_ctx *c = (const xval_ctx *)vc;
     int Nv = nvox(c->p);
-    const double r2 = exp(-c->theta[(size_t)Nv + j]);
-    return rho_of(c->theta, Nv, j) * c->trains[(size_t)n * Nv + j] * r2 * c->v[(size_t)Nv + j];
+    double complex acc = 0.0;
+    for (int q = 0; q < npar(c->p); ++q)
+        acc += dcol_tau(c->p, c->theta, c->trains, q, n, j) * c->v[(size_t)q * Nv + j];
+    return acc;
 }
 
 void oracle_jv(const oracle_problem *p, const double *theta,
@@ -692,15 +724,12 @@ void oracle_jhw(const oracle_problem *p, const double *theta,
     adjoint_encode(p, theta, coil, mask, w, V, Vt);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < Nv; ++j) {
-        for (int q = 0; q < NPAR; ++q) {
+        for (int q = 0; q < npar(p); ++q) {
             double complex acc = 0.0;
             if (active(mask, j))
-                for (int n = 0; n < p->n_tr; ++n) {
-                    acc += conj(dcol(theta, trains, Nv, p->n_tr, q, n, j)) * V[(size_t)n * Nv + j];
-                    if (q == 1)   /* the readout decay's share of the ln T2 column */
-                        acc += conj(rho_of(theta, Nv, j) * trains[(size_t)n * Nv + j] *
-                                    exp(-theta[(size_t)Nv + j])) * Vt[(size_t)n * Nv + j];
-                }
+                for (int n = 0; n < p->n_tr; ++n)   /* V' holds the tau-weighted sums */
+                    acc += conj(dcol(p, theta, trains, q, n, j)) * V[(size_t)n * Nv + j] +
+                           conj(dcol_tau(p, theta, trains, q, n, j)) * Vt[(size_t)n * Nv + j];
             out[(size_t)q * Nv + j] = -creal(acc);
         }
     }
@@ -714,21 +743,19 @@ void oracle_jacobian(const oracle_problem *p, const double *theta,
 {
     const int Nv = nvox(p);
     const int rows = p->n_coils * p->n_tr * p->n_read;
-    const size_t cols = (size_t)NPAR * Nv;
+    const size_t cols = (size_t)npar(p) * Nv;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int row = 0; row < rows; ++row) {
         int k = row % p->n_read;
         int n = (row / p->n_read) % p->n_tr;
         int c = row / (p->n_read * p->n_tr);
-        for (int q = 0; q < NPAR; ++q)
+        for (int q = 0; q < npar(p); ++q)
             for (int j = 0; j < Nv; ++j) {
                 double complex e = 0.0;
                 if (active(mask, j)) {
                     int ix = j % p->nx, iy = j / p->nx;
-                    double complex d = dcol(theta, trains, Nv, p->n_tr, q, n, j);
-                    if (q == 1)   /* the readout decay's share of the ln T2 column */
-                        d += rho_of(theta, Nv, j) * trains[(size_t)n * Nv + j] * exp(-theta[(size_t)Nv + j]) *
-                             readout_tau(p, k);
+                    double complex d = dcol(p, theta, trains, q, n, j);
+                    if (readout_on(p)) d += dcol_tau(p, theta, trains, q, n, j) * readout_tau(p, k);
                     e = -coil_at(coil, c, Nv, j) * oracle_phase(p, n, k, ix, iy) *
                         readout_factor(p, theta, j, k) * d;
                 }
@@ -780,25 +807,47 @@ static double dot(const double *a, const double *b, size_t n)
     return s;
 }
 
-static void apply_masks(double *x, int Nv, int param_mask, const unsigned char *mask)
+static void apply_masks(const oracle_problem *p, double *x, int param_mask, const unsigned char *mask)
 {
-    for (int q = 0; q < NPAR; ++q)
+    const int Nv = nvox(p);
+    for (int q = 0; q < npar(p); ++q)
         for (int j = 0; j < Nv; ++j)
             if (!((param_mask >> q) & 1) || !active(mask, j)) x[(size_t)q * Nv + j] = 0.0;
 }
 
-/* Box projection of the reconstructed (active) ln T1, ln T2, B1 entries onto
- * the attainable intervals; inactive parameters and masked voxels are left as
- * they are. */
-static void project(double *theta, int Nv, const oracle_gn_opts *o, const unsigned char *mask)
+/* Box of parameter row q (ln T1, ln T2, B1 from the options; a fitted
+ * Delta B0 within +-db0_box Hz); 0 for the unbounded rows. */
+static int box_of(const oracle_problem *p, const double *lo3, const double *hi3, int q,
+                  double *lo, double *hi)
 {
-    for (int q = 0; q < 3; ++q)
+    if (q < 3) {
+        *lo = lo3[q];
+        *hi = hi3[q];
+        return 1;
+    }
+    if (q == 5 && p->db0_box > 0.0) {
+        *hi = p->db0_box / p->db0_unit;
+        *lo = -*hi;
+        return 1;
+    }
+    return 0;
+}
+
+/* Box projection of the reconstructed (active) bounded entries onto their
+ * intervals; inactive parameters and masked voxels are left as they are. */
+static void project(const oracle_problem *p, double *theta, const oracle_gn_opts *o, const unsigned char *mask)
+{
+    const int Nv = nvox(p);
+    for (int q = 0; q < npar(p); ++q) {
+        double lo, hi;
+        if (!box_of(p, o->lo, o->hi, q, &lo, &hi)) continue;
         for (int j = 0; j < Nv; ++j) {
             if (!((o->param_mask >> q) & 1) || !active(mask, j)) continue;
             double *t = &theta[(size_t)q * Nv + j];
-            if (*t < o->lo[q]) *t = o->lo[q];
-            if (*t > o->hi[q]) *t = o->hi[q];
+            if (*t < lo) *t = lo;
+            if (*t > hi) *t = hi;
         }
+    }
 }
 
 void oracle_gn_step(const oracle_problem *p, double *theta,
@@ -807,7 +856,7 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
                     oracle_gn_report *rep)
 {
     const int Nv = nvox(p);
-    const size_t N = (size_t)NPAR * Nv, L = data_len(p);
+    const size_t N = (size_t)npar(p) * Nv, L = data_len(p);
     double complex *tr = (double complex *)malloc(train_len(p) * sizeof(double complex));
     double complex *r = (double complex *)malloc(L * sizeof(double complex));
     double complex *y = (double complex *)malloc(L * sizeof(double complex));
@@ -830,7 +879,7 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
     }
     f0 *= 0.5;
     oracle_jhw(p, theta, coil, mask, tr, r, g);
-    apply_masks(g, Nv, o->param_mask, mask);
+    apply_masks(p, g, o->param_mask, mask);
     rep->f0 = f0;
     rep->gnorm = sqrt(dot(g, g, N));
 
@@ -841,7 +890,7 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
         if (rr == 0.0) break;
         oracle_jv(p, theta, coil, mask, tr, dir, y);
         oracle_jhw(p, theta, coil, mask, tr, y, q);
-        apply_masks(q, Nv, o->param_mask, mask);
+        apply_masks(p, q, o->param_mask, mask);
         double kappa = dot(dir, q, N);
         if (kappa <= 1e-30 * dot(dir, dir, N)) break;
         double a = rr / kappa;
@@ -858,7 +907,7 @@ void oracle_gn_step(const oracle_problem *p, double *theta,
     rep->f1 = f0;
     for (int k = 0; k < o->n_ls_max; ++k) {
         for (size_t i = 0; i < N; ++i) trial[i] = theta[i] + t * step[i];
-        project(trial, Nv, o, mask);
+        project(p, trial, o, mask);
         double ft = oracle_residual(p, trial, coil, mask, data, NULL);
         double pred = 0.0, sn = 0.0;
         for (size_t i = 0; i < N; ++i) {
@@ -1006,12 +1055,12 @@ static void normal_matvec(void *c, const double *x, double *out)
 {
     const normal_ctx *nc = (const normal_ctx *)c;
     const int Nv = nvox(nc->p);
-    double *xm = (double *)malloc((size_t)NPAR * Nv * sizeof(double));
-    memcpy(xm, x, (size_t)NPAR * Nv * sizeof(double));
-    apply_masks(xm, Nv, nc->param_mask, nc->mask);
+    double *xm = (double *)malloc((size_t)npar(nc->p) * Nv * sizeof(double));
+    memcpy(xm, x, (size_t)npar(nc->p) * Nv * sizeof(double));
+    apply_masks(nc->p, xm, nc->param_mask, nc->mask);
     oracle_jv(nc->p, nc->theta, nc->coil, nc->mask, nc->trains, xm, nc->y);
     oracle_jhw(nc->p, nc->theta, nc->coil, nc->mask, nc->trains, nc->y, out);
-    apply_masks(out, Nv, nc->param_mask, nc->mask);
+    apply_masks(nc->p, out, nc->param_mask, nc->mask);
     free(xm);
 }
 
@@ -1021,7 +1070,7 @@ void oracle_tr_step(const oracle_problem *p, double *theta,
                     oracle_tr_report *rep)
 {
     const int Nv = nvox(p);
-    const size_t N = (size_t)NPAR * Nv, L = data_len(p);
+    const size_t N = (size_t)npar(p) * Nv, L = data_len(p);
     double complex *tr = (double complex *)malloc(train_len(p) * sizeof(double complex));
     double complex *r = (double complex *)malloc(L * sizeof(double complex));
     double complex *y = (double complex *)malloc(L * sizeof(double complex));
@@ -1042,7 +1091,7 @@ void oracle_tr_step(const oracle_problem *p, double *theta,
     }
     f0 *= 0.5;
     oracle_jhw(p, theta, coil, mask, tr, r, g);
-    apply_masks(g, Nv, o->param_mask, mask);
+    apply_masks(p, g, o->param_mask, mask);
     rep->f0 = f0;
     rep->f1 = f0;
     rep->gnorm = sqrt(dot(g, g, N));
@@ -1053,14 +1102,17 @@ void oracle_tr_step(const oracle_problem *p, double *theta,
 
     /* Trial point: reflect the reconstructed, bounded entries into the box. */
     for (size_t i = 0; i < N; ++i) trial[i] = theta[i] + step[i];
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < npar(p); ++q) {
+        double lo, hi;
+        if (!box_of(p, o->lo, o->hi, q, &lo, &hi)) continue;
         for (int j = 0; j < Nv; ++j) {
             if (!((o->param_mask >> q) & 1) || !active(mask, j)) continue;
             double *t = &trial[(size_t)q * Nv + j];
-            double rf = oracle_reflect(*t, o->lo[q], o->hi[q]);
+            double rf = oracle_reflect(*t, lo, hi);
             if (rf != *t) rep->n_reflected++;
             *t = rf;
         }
+    }
     for (size_t i = 0; i < N; ++i) sv[i] = trial[i] - theta[i];
 
     /* Predicted decrease of the model at the taken step s, and the ratio. */
@@ -1109,7 +1161,7 @@ void oracle_rho_init(const oracle_problem *p, double *theta,
     double complex *x = (double complex *)calloc(Nv, sizeof(double complex));
     double complex *sv = (double complex *)malloc(Nv * sizeof(double complex));
     double complex *pv = (double complex *)malloc(Nv * sizeof(double complex));
-    double *th = (double *)malloc((size_t)NPAR * Nv * sizeof(double));
+    double *th = (double *)malloc((size_t)npar(p) * Nv * sizeof(double));
     oracle_epg(p, theta, 0, tr);
 
     /* A^H w */
@@ -1124,7 +1176,7 @@ void oracle_rho_init(const oracle_problem *p, double *theta,
         }                                                                    \
     } while (0)
 
-    memcpy(th, theta, (size_t)NPAR * Nv * sizeof(double));
+    memcpy(th, theta, (size_t)npar(p) * Nv * sizeof(double));
     for (size_t i = 0; i < L; ++i) res[i] = data[i];
     ADJ(res, sv);
     double gamma = 0.0;

@@ -16,9 +16,10 @@
  *
  * Conventions (the paper's statement of the problem, Theory section):
  *   voxel j = iy*nx + ix, Nv = nx*ny;
- *   parameter vector alpha in R^{5 Nv}, voxel j's parameters at j + p*Nv
- *   (parameter-major layout of the Theory section), with
- *   p = 0: ln T1 [s], 1: ln T2 [s], 2: B1 [a.u.], 3: Re rho, 4: Im rho
+ *   parameter vector alpha in R^{5 Nv} (R^{6 Nv} with Delta B0 fitted),
+ *   voxel j's parameters at j + p*Nv (parameter-major layout of the Theory
+ *   section), with p = 0: ln T1 [s], 1: ln T2 [s], 2: B1 [a.u.], 3: Re rho,
+ *   4: Im rho, 5: Delta B0 / db0_unit
  *   (log scaling of T1 and T2 as in the Methods / Reconstructions section);
  *   r = d - s, f = 0.5 ||r||^2, J = dr/dalpha, g = Re(J^H r).
  */
@@ -69,6 +70,13 @@ typedef struct {
      * db0 == NULL). The encoding is then evaluated as a direct sum. */
     double dwell;
     const double *db0;
+    /* Delta B0 as a reconstructed parameter (the Discussion's extension of the
+     * parameter set): when db0_unit > 0 the parameter vector has a sixth row,
+     * p = 5, and voxel j's off-resonance is theta[5 Nv + j] * db0_unit Hz in
+     * the readout factor above (db0 must then be NULL). The GN line search and
+     * the trust region keep |theta_5| db0_unit <= db0_box Hz (no bound when
+     * db0_box <= 0), as they keep ln T1, ln T2 and B1 in their box. */
+    double db0_unit, db0_box;
 } oracle_problem;
 
 typedef struct {
@@ -97,7 +105,7 @@ void oracle_isochromat(const oracle_problem *p, double lnT1, double lnT2, double
 
 /* EPG simulation with forward-mode tangents (Supporting Information S2
  * pattern, applied to the extended-phase-graph states).
- * theta: [5][Nv]; trains out: [4][n_tr][Nv] complex = m, dm/dlnT1, dm/dlnT2,
+ * theta: [Np][Nv] (Np = 5, or 6 with Delta B0 fitted); trains out: [4][n_tr][Nv] complex = m, dm/dlnT1, dm/dlnT2,
  * dm/dB1. If with_tangents == 0 only train 0 is written. */
 void oracle_epg(const oracle_problem *p, const double *theta, int with_tangents,
                 double complex *trains);
@@ -124,12 +132,12 @@ void oracle_signal_separable(const oracle_problem *p, const double *theta,
                              const double complex *coil, const unsigned char *mask,
                              const double complex *trains, double complex *s);
 
-/* J v for real v [5][Nv]; out [C][n_tr][n_read]. J = dr/dalpha = -ds/dalpha. */
+/* J v for real v [Np][Nv]; out [C][n_tr][n_read]. J = dr/dalpha = -ds/dalpha. */
 void oracle_jv(const oracle_problem *p, const double *theta,
                const double complex *coil, const unsigned char *mask,
                const double complex *trains, const double *v, double complex *out);
 
-/* Re(J^H w) for w [C][n_tr][n_read]; out [5][Nv]. */
+/* Re(J^H w) for w [C][n_tr][n_read]; out [Np][Nv]. */
 void oracle_jhw(const oracle_problem *p, const double *theta,
                 const double complex *coil, const unsigned char *mask,
                 const double complex *trains, const double complex *w, double *out);

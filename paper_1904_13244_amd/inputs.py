@@ -44,6 +44,8 @@ class Problem:
     db0: np.ndarray | None = None  # [Nv] off-resonance [Hz] (readout dynamics); None = 0
     rd_min_t2: float = 0.005      # readout dynamics on the GPU: T2 [s] and |db0| [Hz] bounds
     rd_max_db0: float = 200.0     # within which its expansion holds FP32 accuracy
+    db0_unit: float = 0.0         # > 0: Delta B0 fitted as theta row 5, in units of db0_unit Hz
+                                  # (db0 then None; its box is +-rd_max_db0 Hz)
 
     @property
     def nv(self) -> int:
@@ -259,11 +261,17 @@ def coil_maps(nx, ny, n_coils, seed=SEED_PHANTOM + 10):
     return maps.reshape(n_coils, nx * ny).astype(np.complex128)
 
 
-def probe_vectors(prob: Problem, param_mask=0b11111, seed=SEED_PROBE):
+def n_params(prob: Problem) -> int:
+    """Parameter rows: 5, or 6 with Delta B0 fitted."""
+    return 6 if (getattr(prob, "db0_unit", 0.0) or 0.0) > 0.0 else 5
+
+
+def probe_vectors(prob: Problem, param_mask=0b111111, seed=SEED_PROBE):
     """v ~ N(0,1) on the active parameters, w ~ CN(0,1) in data space."""
     rng = np.random.default_rng(seed)
-    v = rng.standard_normal((5, prob.nv))
-    for q in range(5):
+    npar = n_params(prob)
+    v = rng.standard_normal((npar, prob.nv))
+    for q in range(npar):
         if not (param_mask >> q) & 1:
             v[q] = 0.0
     w = (rng.standard_normal(prob.data_shape) + 1j * rng.standard_normal(prob.data_shape)) / np.sqrt(2)

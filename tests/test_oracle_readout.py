@@ -20,6 +20,12 @@ and voxel j's magnetisation carries exp(-tau_k / T2_j) exp(-2 pi i db0_j
     Jacobian (the ln T2 column carries the readout decay's tau_k term), the
     products J v and Re(J^H w) against the explicit Jacobian, the adjoint
     identity, and noiseless recovery by the GN iteration.
+  * Delta B0 as a sixth parameter (theta row 5 times db0_unit Hz): the row in
+    place of the map gives the map's signal and first five Jacobian rows; its
+    column against finite differences and against the closed form
+    -2 pi i db0_unit (TE + tau_k) times the voxel's samples; products against
+    the explicit six-parameter Jacobian; the +-rd_max_db0 box in the line
+    search; noiseless recovery with Delta B0 fitted.
 """
 import dataclasses
 
@@ -169,3 +175,114 @@ def test_noiseless_recovery_with_readout_dynamics(oracle_lib):
         th, rep = oracle_lib.gn_step(prob, th, d, n_cg=40, param_mask=0b11011, lo=I.GN_LO, hi=I.GN_HI)
     err = np.linalg.norm(th - th_true) / np.linalg.norm(th_true)
     assert err <= 1e-6, err
+
+
+# --------------------------------------------------------------------------
+# Delta B0 as a reconstructed sixth parameter (db0_unit > 0): theta row 5
+# times db0_unit is the voxel's off-resonance in Hz.
+
+def _fitted(seed=21, nx=6, ny=5, n_tr=24, n_read=12, coils=1):
+    prob, th, coil, rng = _case(seed=seed, nx=nx, ny=ny, n_tr=n_tr, n_read=n_read, coils=coils)
+    unit = 1.0 / (2 * np.pi * prob.te)     # theta_5 = the off-resonance phase at TE in radians
+    fit = dataclasses.replace(prob, db0=None, db0_unit=unit, rd_max_db0=200.0)
+    th6 = np.vstack([th, (prob.db0 / unit)[None, :]])
+    return prob, fit, th, th6, coil, rng
+
+
+def test_fitted_row_equals_the_map(oracle_lib):
+    """The sixth row in place of the map gives the same signal, and the
+    first five rows of J v, Re(J^H w) and J are those of the map's model."""
+    prob, fit, th, th6, coil, rng = _fitted(coils=2)
+    tr = oracle_lib.epg(prob, th)
+    a = oracle_lib.signal(prob, th, tr, coil=coil)
+    b = oracle_lib.signal(fit, th6, tr, coil=coil)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(a)
+    v, w = I.probe_vectors(fit)
+    v[5] = 0.0
+    assert np.allclose(oracle_lib.jv(fit, th6, tr, v, coil=coil), oracle_lib.jv(prob, th, tr, v[:5], coil=coil),
+                       rtol=0, atol=1e-12 * np.abs(a).max())
+    g6 = oracle_lib.jhw(fit, th6, tr, w, coil=coil)
+    g5 = oracle_lib.jhw(prob, th, tr, w, coil=coil)
+    assert np.linalg.norm(g6[:5] - g5) <= 1e-12 * np.linalg.norm(g5)
+
+
+def test_offresonance_column_finite_differences(oracle_lib):
+    prob, fit, th, th6, coil, rng = _fitted(seed=22, coils=2)
+    tr = oracle_lib.epg(fit, th6)
+    J = oracle_lib.jacobian(fit, th6, tr, coil=coil)
+    assert J.shape[1] == 6 * fit.nv
+    d = np.zeros(fit.data_shape, dtype=np.complex128)
+    for j in rng.choice(fit.nv, 6, replace=False):
+        col = 5 * fit.nv + int(j)
+        h = 1e-6
+        tp, tm = th6.copy(), th6.copy()
+        tp[5, j] += h
+        tm[5, j] -= h
+        fd = ((oracle_lib.residual(fit, tp, d, coil=coil)[1] - oracle_lib.residual(fit, tm, d, coil=coil)[1])
+              / (2 * h)).reshape(-1)
+        assert np.linalg.norm(J[:, col] - fd) <= 1e-7 * np.linalg.norm(fd), j
+
+
+def test_offresonance_column_closed_form(oracle_lib):
+    """d/dtheta_5 of voxel j's samples is -2 pi i db0_unit (TE + tau_k) times
+    them, and voxel j's samples are -rho_j times its Re rho column."""
+    prob, fit, th, th6, coil, rng = _fitted(seed=23)
+    tr = oracle_lib.epg(fit, th6)
+    J = oracle_lib.jacobian(fit, th6, tr)
+    tau = (np.arange(fit.n_read) - fit.n_read // 2) * fit.dwell
+    fac = np.tile(-2j * np.pi * fit.db0_unit * (fit.te + tau), fit.n_tr)
+    for j in range(0, fit.nv, 7):
+        rho = th6[3, j] + 1j * th6[4, j]
+        samples = -rho * J[:, 3 * fit.nv + j]
+        ref = -fac * samples
+        assert np.linalg.norm(J[:, 5 * fit.nv + j] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_six_parameter_products_and_adjoint(oracle_lib):
+    prob, fit, th, th6, coil, rng = _fitted(seed=24, coils=2)
+    mask = (rng.uniform(size=fit.nv) > 0.2).astype(np.uint8)
+    tr = oracle_lib.epg(fit, th6)
+    J = oracle_lib.jacobian(fit, th6, tr, coil=coil, mask=mask)
+    v, w = I.probe_vectors(fit)
+    jv = oracle_lib.jv(fit, th6, tr, v, coil=coil, mask=mask).reshape(-1)
+    jhw = oracle_lib.jhw(fit, th6, tr, w, coil=coil, mask=mask).reshape(-1)
+    assert np.linalg.norm(jv - J @ v.reshape(-1)) <= 1e-12 * np.linalg.norm(jv)
+    ref = (J.conj().T @ w.reshape(-1)).real
+    assert np.linalg.norm(jhw - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_offresonance_box_in_the_line_search(oracle_lib):
+    """A GN step whose step in theta_5 leaves +-rd_max_db0 Hz is projected
+    onto the box (with B1 and T1 held, only theta_5 and rho move)."""
+    prob, fit, th, th6, coil, rng = _fitted(seed=25)
+    tight = dataclasses.replace(fit, rd_max_db0=40.0)
+    th_true = th6.copy()
+    th_true[5] = np.clip(th_true[5], -30.0 / fit.db0_unit, 30.0 / fit.db0_unit)
+    d = oracle_lib.signal(tight, th_true, oracle_lib.epg(tight, th_true, tangents=False))
+    start = th_true.copy()
+    start[5] = 0.0
+    th1, rep = oracle_lib.gn_step(tight, start, d, n_cg=20, param_mask=0b111000, lo=I.GN_LO, hi=I.GN_HI)
+    assert rep.accepted
+    assert np.all(np.abs(th1[5]) * fit.db0_unit <= 40.0 + 1e-9)
+    assert np.array_equal(th1[:3], start[:3])
+
+
+def test_noiseless_recovery_with_offresonance_fitted(oracle_lib):
+    """With one echo time the off-resonance phase at TE is shared with rho's
+    phase: Delta B0 is told apart only by its phase ramp across the readout
+    (a shift of db0 / (pixel bandwidth) along x). On this 6-pixel grid that
+    needs a long readout (12 samples of 0.2 ms) and CG run to the number of
+    unknowns (200 >= 5 x 36); then GN converges quadratically to the truth."""
+    prob, fit, th, th6, coil, rng = _fitted(seed=26, nx=6, ny=6, n_tr=48, n_read=12)
+    fit = dataclasses.replace(fit, dwell=2e-4)
+    d = oracle_lib.signal(fit, th6, oracle_lib.epg(fit, th6, tangents=False))
+    x = th6.copy()
+    r2 = np.random.default_rng(27)
+    x[:2] += 0.05 * r2.standard_normal((2, fit.nv))
+    x[5] += 0.3 * r2.standard_normal(fit.nv)     # about 12 Hz at TE = 4 ms
+    errs = []
+    for _ in range(12):
+        x, rep = oracle_lib.gn_step(fit, x, d, n_cg=200, param_mask=0b111011, lo=I.GN_LO, hi=I.GN_HI)
+        errs.append(np.linalg.norm(x - th6) / np.linalg.norm(th6))
+    assert errs[-1] <= 1e-6, errs
+    assert errs[6] <= 1e-3 * errs[1]   # superlinear

@@ -20,10 +20,12 @@
  *                             + (l(n) - ny/2)(iy - ny/2)/ny ])
  * (voxel j = iy*nx + ix, readout sample k, TR n sampling line l(n)).
  *
- * Parameters. theta is float32 [5][Nv], Nv = nx*ny, in the paper's
+ * Parameters. theta is float32 [Np][Nv], Nv = nx*ny, in the paper's
  * parameter-major layout (voxel j's parameters at j + p*Nv, Theory section):
  *     p = 0: ln T1 [s], 1: ln T2 [s], 2: B1 [a.u.], 3: Re rho, 4: Im rho
- * (log scaling of T1 and T2: Methods, Reconstructions).
+ * (log scaling of T1 and T2: Methods, Reconstructions), Np = 5; a context
+ * that fits Delta B0 (mrstat_fit_db0) has Np = 6 with p = 5: Delta B0 in
+ * units of its hz_per_unit. Directions v, gradients and param_mask follow Np.
  *
  * Sign conventions (Theory): r = d - s, f = 0.5 ||r||^2, J = dr/dalpha
  * (so J = -ds/dalpha), gradient g = Re(J^H r).
@@ -114,8 +116,9 @@ typedef struct {
                              early exit only on breakdown (zero residual or
                              non-positive curvature) */
     int32_t n_ls_max;     /* backtracking trials t = 1, 1/2, ... (>= 1) */
-    int32_t param_mask;   /* bit p set = parameter p is reconstructed */
-    float lo[3], hi[3];   /* projection box for ln T1, ln T2, B1 */
+    int32_t param_mask;   /* bit p set = parameter p is reconstructed (p < Np) */
+    float lo[3], hi[3];   /* projection box for ln T1, ln T2, B1 (a fitted Delta B0
+                             keeps to +-max_abs_db0_hz of mrstat_create_readout) */
     double armijo_c1;     /* sufficient decrease: f(a_t) <= f + c1 g^T (a_t - a) */
 } mrstat_gn_opts;
 
@@ -226,6 +229,20 @@ mrstat_status mrstat_create_readout(const mrstat_problem *p, double dwell_s, dou
  * modelled). */
 mrstat_status mrstat_set_db0(mrstat_ctx ctx, const float *d_db0);
 
+/* Delta B0 as a reconstructed parameter (the Discussion's extension of the
+ * parameter set) on a readout-dynamics context: with hz_per_unit > 0 theta,
+ * J v directions and Re(J^H w) gain a sixth row, p = 5, and voxel j's
+ * off-resonance is theta[5 Nv + j] * hz_per_unit Hz in the readout factor
+ * (the map of mrstat_set_db0 is then not read); the signal's derivative is
+ * ds/dtheta_5 = -2 pi i hz_per_unit (TE + tau_k) times voxel j's term of s,
+ * and GN and trust-region steps keep |Delta B0| within max_abs_db0_hz
+ * (param_mask bit 5). hz_per_unit = 0 returns to five rows.
+ * With one echo time the off-resonance phase at TE is shared with rho's
+ * phase: Delta B0 is determined by the phase ramp across each readout only.
+ * MRSTAT_ERR_STATE for other contexts or with the balanced model;
+ * MRSTAT_ERR_ARG for a negative or non-finite hz_per_unit. */
+mrstat_status mrstat_fit_db0(mrstat_ctx ctx, double hz_per_unit);
+
 /* Terms of the readout-dynamics expansion (0 for other contexts). */
 mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t *h_terms);
 
@@ -264,13 +281,13 @@ mrstat_status mrstat_simulate(mrstat_ctx ctx, const float *d_theta, float *d_tra
 mrstat_status mrstat_residual(mrstat_ctx ctx, const float *d_theta, int32_t reuse_linearization,
                               const void *d_data, void *d_r, double *h_f, mrstat_stream stream);
 
-/* d_out = J v for v float32 [5][Nv]; complex64 [n_coils][n_tr][n_read].
- * All five parameter rows are used (a reused linearisation without the
+/* d_out = J v for v float32 [Np][Nv]; complex64 [n_coils][n_tr][n_read].
+ * All Np parameter rows are used (a reused linearisation without the
  * dm/dB1 train, left by a B1-fixed mrstat_gn_step, is redone first). */
 mrstat_status mrstat_jv(mrstat_ctx ctx, const float *d_theta, int32_t reuse_linearization,
                         const float *d_v, void *d_out, mrstat_stream stream);
 
-/* d_out = Re(J^H w) for w complex64 [n_coils][n_tr][n_read]; float32 [5][Nv]
+/* d_out = Re(J^H w) for w complex64 [n_coils][n_tr][n_read]; float32 [Np][Nv]
  * (Algorithm 4: all N_p partial derivatives of a voxel together; a reused
  * three-train linearisation is redone first, as for mrstat_jv). */
 mrstat_status mrstat_jhw(mrstat_ctx ctx, const float *d_theta, int32_t reuse_linearization,
@@ -312,8 +329,9 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float *d_theta, const void *d_data,
  * g is not finite. Synchronises. */
 typedef struct {
     int32_t n_cg;         /* CG iteration limit of the truncated solve */
-    int32_t param_mask;   /* bit p set = parameter p is reconstructed */
-    float lo[3], hi[3];   /* box of ln T1, ln T2, B1, kept by reflection */
+    int32_t param_mask;   /* bit p set = parameter p is reconstructed (p < Np) */
+    float lo[3], hi[3];   /* box of ln T1, ln T2, B1, kept by reflection (a fitted
+                             Delta B0: +-max_abs_db0_hz) */
     double eta;           /* acceptance threshold on rho */
     double delta_max;     /* cap of the trust radius */
 } mrstat_tr_opts;

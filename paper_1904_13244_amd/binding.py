@@ -89,6 +89,7 @@ def lib():
                                       C.c_int),
             "mrstat_set_db0": ([vp, vp], C.c_int),
             "mrstat_readout_terms": ([vp, P(i32)], C.c_int),
+            "mrstat_fit_db0": ([vp, C.c_double], C.c_int),
             "mrstat_destroy": ([vp], None),
             "mrstat_last_error": ([vp], C.c_char_p),
             "mrstat_workspace_bytes": ([vp], C.c_size_t),
@@ -148,7 +149,7 @@ def exported_symbols():
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
             "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj",
             "mrstat_set_isochromats", "mrstat_create_readout", "mrstat_set_db0",
-            "mrstat_readout_terms"]
+            "mrstat_readout_terms", "mrstat_fit_db0"]
 
 
 def _check(status, ctx=None):
@@ -232,6 +233,10 @@ def mrstat_set_isochromats(ctx, scale, weight):
 
 def mrstat_set_db0(ctx, db0_ptr):
     _check(lib().mrstat_set_db0(ctx, db0_ptr), ctx)
+
+
+def mrstat_fit_db0(ctx, hz_per_unit):
+    _check(lib().mrstat_fit_db0(ctx, float(hz_per_unit)), ctx)
 
 
 def mrstat_readout_terms(ctx):
@@ -414,6 +419,11 @@ class Context:
         iso = getattr(self.prob, "iso", None)
         if iso is not None:
             mrstat_set_isochromats(self.h, iso[0], iso[1])
+        self.np = 5
+        unit = float(getattr(self.prob, "db0_unit", 0.0) or 0.0)
+        if unit > 0.0:
+            mrstat_fit_db0(self.h, unit)
+            self.np = 6
         self.db0 = None
         db0 = getattr(self.prob, "db0", None)
         if db0 is not None and float(getattr(self.prob, "dwell", 0.0) or 0.0) > 0.0:
@@ -488,7 +498,7 @@ class Context:
 
     def simulate(self, theta, trains=None):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         if trains is None:
             trains = T.empty((4, self.prob.n_tr, self.nv), dtype=T.float32, device=self.dev)
         self._expect(trains, T.float32, (4, self.prob.n_tr, self.nv))
@@ -496,12 +506,12 @@ class Context:
         return trains
 
     def linearise(self, theta):
-        self._expect(theta, self.torch.float32, (5, self.nv))
+        self._expect(theta, self.torch.float32, (self.np, self.nv))
         mrstat_simulate(self.h, theta.data_ptr(), None, self.stream)
 
     def residual(self, theta, data, reuse=False, out=None, want_f=True):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         self._expect(data, T.complex64, self.data_shape)
         if out is None:
             out = T.empty(self.data_shape, dtype=T.complex64, device=self.dev)
@@ -512,8 +522,8 @@ class Context:
 
     def jv(self, theta, v, reuse=False, out=None):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
-        self._expect(v, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
+        self._expect(v, T.float32, (self.np, self.nv))
         if out is None:
             out = T.empty(self.data_shape, dtype=T.complex64, device=self.dev)
         self._expect(out, T.complex64, self.data_shape)
@@ -522,17 +532,17 @@ class Context:
 
     def jhw(self, theta, w, reuse=False, out=None):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         self._expect(w, T.complex64, self.data_shape)
         if out is None:
-            out = T.empty((5, self.nv), dtype=T.float32, device=self.dev)
-        self._expect(out, T.float32, (5, self.nv))
+            out = T.empty((self.np, self.nv), dtype=T.float32, device=self.dev)
+        self._expect(out, T.float32, (self.np, self.nv))
         mrstat_jhw(self.h, theta.data_ptr(), reuse, w.data_ptr(), out.data_ptr(), self.stream)
         return out
 
     def gn_step(self, theta, data, n_cg, param_mask, lo, hi, n_ls_max=8, armijo_c1=1e-4):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         self._expect(data, T.complex64, self.data_shape)
         o = GnOpts(int(n_cg), int(n_ls_max), int(param_mask), (C.c_float * 3)(*lo),
                    (C.c_float * 3)(*hi), float(armijo_c1))
@@ -541,7 +551,7 @@ class Context:
     def tr_step(self, theta, data, delta, n_cg, param_mask, lo, hi, eta=0.1, delta_max=1e3):
         """One trust-region step; returns (new radius, TrReport)."""
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         self._expect(data, T.complex64, self.data_shape)
         o = TrOpts(int(n_cg), int(param_mask), (C.c_float * 3)(*lo), (C.c_float * 3)(*hi),
                    float(eta), float(delta_max))
@@ -549,7 +559,7 @@ class Context:
 
     def rho_init(self, theta, data, n_iter=20):
         T = self.torch
-        self._expect(theta, T.float32, (5, self.nv))
+        self._expect(theta, T.float32, (self.np, self.nv))
         self._expect(data, T.complex64, self.data_shape)
         mrstat_rho_init(self.h, theta.data_ptr(), data.data_ptr(), n_iter, self.stream)
         return theta

@@ -55,6 +55,7 @@ struct mrstat_ctx_s {
     double rd_min_t2 = 0.0;       // T2 bound of the expansion, seconds
     double rd_max_db0 = 0.0;      // |db0| bound of the expansion, Hz
     const float* rd_db0 = nullptr;   // off-resonance map [nv] in Hz (device, caller's; null = 0)
+    float db0_unit = 0.f;         // Delta B0 fitted as theta row 5 in these Hz (d.np == 6), else 0
     bool f16 = false;             // trains stored as FP16
     // bound device state
     char* ws = nullptr;
@@ -83,7 +84,7 @@ struct mrstat_ctx_s {
     float* apart() const { return at<float>(L.apart); }
     float2* r() const { return at<float2>(L.r); }
     float2* y() const { return at<float2>(L.y); }
-    float* vec(int i) const { return at<float>(L.vec) + (size_t)i * 5 * d.nv; }
+    float* vec(int i) const { return at<float>(L.vec) + (size_t)i * d.np * d.nv; }
     double* red() const { return at<double>(L.red); }
     double* scal() const { return at<double>(L.scal); }
     const float2* dseq() const { return at<float2>(L.seq); }
@@ -168,6 +169,9 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
         const int per = ceil_div(d.T, nc_adj_chunks(d));
         L.yp.adj_chunks = ceil_div(d.T, per);
     }
+    // Readout-dynamics contexts may fit Delta B0: room for six parameter rows
+    // and ten partial planes per adjoint chunk.
+    const size_t npmax = rd_nq > 0 ? 6 : 5, plmax = rd_nq > 0 ? 10 : 8;
     const int M = d.C * d.T;
     const int gemm_blocks = std::max(ceil_div(2 * d.nk, 64) * ceil_div(M, 64), xgemm_direct_blocks(d));
     L.n_red = std::max({3 * RED_BLOCKS, gemm_blocks, cg_partials(d), tr_partials(d), nc ? nc_fwd_blocks(d) : 0});
@@ -178,10 +182,10 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     L.trial_m = take(T * nv * sizeof(float));
     L.upart = take((size_t)std::max({L.yp.nby, L.yp.nby16, L.yp.nbyc, L.yp.nbyw}) * d.C * T * d.nx * sizeof(float2));
     L.W = take((size_t)L.yp.ksplit_adj * d.C * T * d.nx * sizeof(float2));
-    L.apart = take((size_t)L.yp.adj_chunks * 8 * nv * sizeof(float));
+    L.apart = take((size_t)L.yp.adj_chunks * plmax * nv * sizeof(float));
     L.r = take((size_t)d.C * T * d.nk * sizeof(float2));
     L.y = take((size_t)d.C * T * d.nk * sizeof(float2));
-    L.vec = take(6 * 5 * nv * sizeof(float));
+    L.vec = take(6 * npmax * nv * sizeof(float));
     L.red = take((size_t)L.n_red * sizeof(double));
     L.scal = take(SCAL_DOUBLES * sizeof(double));
     L.seq = take(T * sizeof(float2));
@@ -192,7 +196,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     L.cx = take(nv * sizeof(float2));
     L.csv = take(nv * sizeof(float2));
     L.cp = take(nv * sizeof(float2));
-    L.cth = take(5 * nv * sizeof(float));
+    L.cth = take(npmax * nv * sizeof(float));
     L.fb = take((64 + nv) * sizeof(int));
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
@@ -351,7 +355,7 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
         const int nq = ctx->rd_nq;
         HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
                        launch_rd_fwd(d, nq, mode_y, trains, ctx->f16, theta, v, ctx->mask, ctx->rd_db0,
-                                     ctx->deytab(), ctx->rdU(), ctx->st.te, ctx->rd_tmax, s)));
+                                     ctx->db0_unit, ctx->deytab(), ctx->rdU(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(ctx->rd_dims(), ctx->L.rdp, ctx->enc, 2, ctx->rdU(),
                                                        ctx->dextab(), ctx->bfrag(0), nullptr, ctx->rdY(), nullptr,
                                                        nullptr, s)));
@@ -403,8 +407,8 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
         HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                        ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
         HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
-                                                    ctx->mask, ctx->rd_db0, ctx->deytab(), ctx->rdW(),
-                                                    ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
+                                                    ctx->mask, ctx->rd_db0, ctx->db0_unit, ctx->deytab(),
+                                                    ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
                                                           dir, dir ? ctx->red() : nullptr, s, step)));
         return MRSTAT_OK;
@@ -427,10 +431,6 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
 }
 
 }  // namespace
-
-extern "C" {
-
-}  // extern "C"
 
 namespace {
 
@@ -549,6 +549,19 @@ mrstat_status mrstat_set_db0(mrstat_ctx ctx, const float* d_db0)
     if (d_db0 && ctx->iso.n > 0)
         return fail(ctx, MRSTAT_ERR_STATE, "an off-resonance map needs the gradient-spoiled model");
     ctx->rd_db0 = d_db0;
+    return MRSTAT_OK;
+}
+
+mrstat_status mrstat_fit_db0(mrstat_ctx ctx, double hz_per_unit)
+{
+    if (!ctx) return MRSTAT_ERR_ARG;
+    if (ctx->rd_nq == 0) return fail(ctx, MRSTAT_ERR_STATE, "the context models no readout dynamics");
+    if (!(std::isfinite(hz_per_unit) && hz_per_unit >= 0.0))
+        return fail(ctx, MRSTAT_ERR_ARG, "hz_per_unit must be finite and >= 0");
+    if (hz_per_unit > 0.0 && ctx->iso.n > 0)
+        return fail(ctx, MRSTAT_ERR_STATE, "Delta B0 is not fitted with the balanced model");
+    ctx->db0_unit = (float)hz_per_unit;
+    ctx->d.np = hz_per_unit > 0.0 ? 6 : 5;
     return MRSTAT_OK;
 }
 
@@ -711,8 +724,8 @@ mrstat_status mrstat_set_isochromats(mrstat_ctx ctx, int32_t n_iso, const double
     if (n_iso < 0 || n_iso > MAX_ISOCHROMATS)
         return fail(ctx, MRSTAT_ERR_ARG, "n_iso must be in [0, 32]");
     if (n_iso > 0 && (!h_scale || !h_weight)) return fail(ctx, MRSTAT_ERR_ARG, "scale or weight is NULL");
-    if (n_iso > 0 && ctx->rd_db0)
-        return fail(ctx, MRSTAT_ERR_STATE, "the balanced model takes no off-resonance map");
+    if (n_iso > 0 && (ctx->rd_db0 || ctx->d.np == 6))
+        return fail(ctx, MRSTAT_ERR_STATE, "the balanced model takes no off-resonance map or fit");
     IsoProfile p{};
     p.n = n_iso;
     for (int q = 0; q < n_iso; ++q) {
@@ -832,8 +845,32 @@ mrstat_status mrstat_jhw(mrstat_ctx ctx, const float* d_theta, int32_t reuse, co
     if (st != MRSTAT_OK) return st;
     if (!d_w || !d_out) return fail(ctx, MRSTAT_ERR_ARG, "w or out is NULL");
     if (!aligned(d_w, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
-    return adjoint(ctx, d_theta, d_w, d_out, 31, s);
+    return adjoint(ctx, d_theta, d_w, d_out, (1 << ctx->d.np) - 1, s);
 }
+
+}  // extern "C"
+
+namespace {
+
+// The six-row box of the line search and the trust region: the caller's
+// ln T1, ln T2, B1 intervals, the rho rows unbounded (not read), and a fitted
+// Delta B0 within the readout expansion's +-max_abs_db0 Hz.
+void param_box(mrstat_ctx ctx, const float* lo3, const float* hi3, float* lo6, float* hi6)
+{
+    for (int q = 0; q < 3; ++q) {
+        lo6[q] = lo3[q];
+        hi6[q] = hi3[q];
+    }
+    lo6[3] = lo6[4] = -INFINITY;
+    hi6[3] = hi6[4] = INFINITY;
+    const float b = ctx->d.np == 6 ? (float)(ctx->rd_max_db0 / ctx->db0_unit) : INFINITY;
+    lo6[5] = -b;
+    hi6[5] = b;
+}
+
+}  // namespace
+
+extern "C" {
 
 mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
                              const mrstat_gn_opts* o, mrstat_gn_report* rep, mrstat_stream stream)
@@ -843,11 +880,13 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     if (st != MRSTAT_OK) return st;
     if (!d_theta || !d_data || !o || !rep) return fail(ctx, MRSTAT_ERR_ARG, "null argument");
     if (!aligned(d_data, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
-    if (o->n_cg < 0 || o->n_ls_max < 1 || o->param_mask < 0 || o->param_mask > 31 ||
+    if (o->n_cg < 0 || o->n_ls_max < 1 || o->param_mask < 0 || o->param_mask >= (1 << ctx->d.np) ||
         !(o->armijo_c1 >= 0.0 && o->armijo_c1 < 1.0))
         return fail(ctx, MRSTAT_ERR_ARG, "invalid GN options");
     for (int q = 0; q < 3; ++q)
         if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    float lo6[6], hi6[6];
+    param_box(ctx, o->lo, o->hi, lo6, hi6);
     if (ctx->rd_nq > 0 && ((o->param_mask >> 1) & 1) && o->lo[1] < std::log(ctx->rd_min_t2) - 1e-6)
         return fail(ctx, MRSTAT_ERR_ARG, "the ln T2 box reaches below the readout expansion's min_t2");
     std::memset(rep, 0, sizeof(*rep));
@@ -890,7 +929,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     // Backtracking line search on the projected step.
     float t = 1.f;
     for (int k = 0; k < o->n_ls_max; ++k) {
-        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_trial_masked(d, d_theta, step, t, o->lo, o->hi,
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_ls_trial_masked(d, d_theta, step, t, lo6, hi6,
                                                                o->param_mask, ctx->mask, trial, s)));
         st = simulate_into(ctx, trial, ctx->trial_m(), 1, 1, s);
         if (st != MRSTAT_OK) return st;
@@ -936,11 +975,14 @@ mrstat_status mrstat_tr_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     if (!d_theta || !d_data || !o || !h_delta || !rep) return fail(ctx, MRSTAT_ERR_ARG, "null argument");
     if (!aligned(d_data, 8)) return fail(ctx, MRSTAT_ERR_ARG, "complex arrays must be 8-byte aligned");
     const double delta = *h_delta;
-    if (o->n_cg < 0 || o->param_mask < 0 || o->param_mask > 31 || !(o->eta >= 0.0 && o->eta < 1.0) ||
-        !(o->delta_max > 0.0) || !std::isfinite(o->delta_max) || !(delta > 0.0) || !(delta <= o->delta_max))
+    if (o->n_cg < 0 || o->param_mask < 0 || o->param_mask >= (1 << ctx->d.np) ||
+        !(o->eta >= 0.0 && o->eta < 1.0) || !(o->delta_max > 0.0) || !std::isfinite(o->delta_max) ||
+        !(delta > 0.0) || !(delta <= o->delta_max))
         return fail(ctx, MRSTAT_ERR_ARG, "invalid trust-region options or radius");
     for (int q = 0; q < 3; ++q)
         if (!(o->lo[q] <= o->hi[q])) return fail(ctx, MRSTAT_ERR_ARG, "invalid parameter box");
+    float lo6[6], hi6[6];
+    param_box(ctx, o->lo, o->hi, lo6, hi6);
     if (ctx->rd_nq > 0 && ((o->param_mask >> 1) & 1) && o->lo[1] < std::log(ctx->rd_min_t2) - 1e-6)
         return fail(ctx, MRSTAT_ERR_ARG, "the ln T2 box reaches below the readout expansion's min_t2");
     std::memset(rep, 0, sizeof(*rep));
@@ -979,9 +1021,9 @@ mrstat_status mrstat_tr_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
 
     // Trial point reflected into the box, the model's predicted decrease at
     // s = trial - theta (g . s and |J s|^2 at the linearisation), f(trial).
-    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_trial(d, d_theta, step, o->lo, o->hi, o->param_mask, ctx->mask,
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_tr_trial(d, d_theta, step, lo6, hi6, o->param_mask, ctx->mask,
                                                     trial, sv, sc, ctx->red(), s)));
-    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_dot(g, sv, (size_t)5 * d.nv, ctx->red(), sc + SC_GS, s)));
+    HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_dot(g, sv, (size_t)d.np * d.nv, ctx->red(), sc + SC_GS, s)));
     st = forward(ctx, mode_jv, 1, ctx->trains(), d_theta, sv, nullptr, ctx->y(), nullptr, s);
     if (st != MRSTAT_OK) return st;
     HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_dot_c(ctx->y(), ctx->y(), (size_t)d.C * d.T * d.nk, ctx->red(),
@@ -1053,8 +1095,9 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
             HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                            ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
             HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, 1, p.adj_chunks, ctx->trains(), ctx->f16,
-                                                        d_theta, ctx->mask, ctx->rd_db0, ctx->deytab(),
-                                                        ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
+                                                        d_theta, ctx->mask, ctx->rd_db0, ctx->db0_unit,
+                                                        ctx->deytab(), ctx->rdW(), ctx->apart(), ctx->st.te,
+                                                        ctx->rd_tmax, s)));
         } else if (ctx->nc) {
             HIP_TRY(TRACED(MRSTAT_K_NC_ADJ, launch_nc_adj(d, ctx->enc, 1, p.adj_chunks, ctx->trains(), ctx->f16,
                                                           ctx->coil, ctx->mask, ctx->dax(), ctx->day(), w,

@@ -912,10 +912,11 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 }
 
 // g from A: g_q = -Im(conj(rho) A_{q+1}) for q = lnT1, lnT2, B1;
-// g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho).
+// g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho); with NP = 6 also
+// g_5 = -Im(conj(rho) A_5) (Delta B0, chunks of 10 planes).
 // CURV: 0 = gradient only; 1 = also the CG curvature partials dir . g and
 // dir . dir; 2 = also step . dir (the trust-region CG's boundary test).
-template <int CURV>
+template <int CURV, int NP>
 __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
                                                          const float* __restrict__ theta,
                                                          const uint8_t* __restrict__ mask, int param_mask,
@@ -924,43 +925,49 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
                                                          const float* __restrict__ step,
                                                          double* __restrict__ part)
 {
+    constexpr int PL = NP == 6 ? 10 : 8;   // planes per chunk
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     double cd = 0.0, dd = 0.0, sd = 0.0;
     if (j < nv) {
         const bool on = mask == nullptr || mask[j] != 0;
         const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
-        float A[8];
+        float A[PL];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) A[q] = 0.f;
+        for (int q = 0; q < PL; ++q) A[q] = 0.f;
         // The dm/dB1 pair (A[6], A[7]) is read only when B1 is reconstructed
-        // (without it the adjoint y-stage may leave that pair unwritten).
+        // (without it the adjoint y-stage may leave that pair unwritten), the
+        // Delta B0 pair only when Delta B0 is.
         // Chunks go three at a time with all their loads issued first (one
         // wave per 64 voxels is all the kernel has); sums stay in chunk order.
-        const bool b1 = (param_mask >> 2) & 1;
-        auto load = [&](int ch, float (&t)[8]) {
+        const bool b1 = (param_mask >> 2) & 1, f5 = (param_mask >> 5) & 1;
+        auto load = [&](int ch, float (&t)[PL]) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) t[q] = apart[((size_t)ch * 8 + q) * nv + j];
-            t[6] = b1 ? apart[((size_t)ch * 8 + 6) * nv + j] : 0.f;
-            t[7] = b1 ? apart[((size_t)ch * 8 + 7) * nv + j] : 0.f;
+            for (int q = 0; q < 6; ++q) t[q] = apart[((size_t)ch * PL + q) * nv + j];
+            t[6] = b1 ? apart[((size_t)ch * PL + 6) * nv + j] : 0.f;
+            t[7] = b1 ? apart[((size_t)ch * PL + 7) * nv + j] : 0.f;
+            if constexpr (NP == 6) {
+                t[8] = f5 ? apart[((size_t)ch * PL + 8) * nv + j] : 0.f;
+                t[9] = f5 ? apart[((size_t)ch * PL + 9) * nv + j] : 0.f;
+            }
         };
         int ch = 0;
         for (; ch + 3 <= n_chunk; ch += 3) {
-            float t[3][8];
+            float t[3][PL];
 #pragma unroll
             for (int c = 0; c < 3; ++c) load(ch + c, t[c]);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int q = 0; q < 8; ++q) A[q] += t[c][q];
+                for (int q = 0; q < PL; ++q) A[q] += t[c][q];
         }
         for (; ch < n_chunk; ++ch) {
-            float t[8];
+            float t[PL];
             load(ch, t);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) A[q] += t[q];
+            for (int q = 0; q < PL; ++q) A[q] += t[q];
         }
         // Rows of parameters outside param_mask are zero.
-        float gq[5];
+        float gq[NP];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const float ar = A[2 * (q + 1)], ai = A[2 * (q + 1) + 1];
@@ -968,8 +975,9 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
         }
         gq[3] = (on && ((param_mask >> 3) & 1)) ? -A[1] : 0.f;
         gq[4] = (on && ((param_mask >> 4) & 1)) ? A[0] : 0.f;
+        if constexpr (NP == 6) gq[5] = (on && f5) ? -(rr * A[9] - ri * A[8]) : 0.f;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < NP; ++q) {
             g[(size_t)q * nv + j] = gq[q];
             if constexpr (CURV > 0) {
                 const double dv = dir[(size_t)q * nv + j];
@@ -1841,15 +1849,22 @@ hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, 
                              double* part, hipStream_t s, const float* step)
 {
     const int nb = ceil_div(d.nv, 256);
-    if (dir != nullptr && step != nullptr)
-        jhw_finish_kernel<2><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
-                                                dir, step, part);
-    else if (dir != nullptr)
-        jhw_finish_kernel<1><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
-                                                dir, nullptr, part);
-    else
-        jhw_finish_kernel<0><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv,
-                                                nullptr, nullptr, nullptr);
+#define FINISH(NP)                                                                                       \
+    if (dir != nullptr && step != nullptr)                                                               \
+        jhw_finish_kernel<2, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
+                                                    dir, step, part);                                    \
+    else if (dir != nullptr)                                                                             \
+        jhw_finish_kernel<1, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
+                                                    dir, nullptr, part);                                 \
+    else                                                                                                 \
+        jhw_finish_kernel<0, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
+                                                    nullptr, nullptr, nullptr);
+    if (d.np == 6) {
+        FINISH(6)
+    } else {
+        FINISH(5)
+    }
+#undef FINISH
     return hipGetLastError();
 }
 

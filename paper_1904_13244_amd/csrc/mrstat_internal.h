@@ -15,6 +15,7 @@ struct Dims {
     int nk;           // readout samples
     int K;            // EPG states
     int C;            // coils
+    int np = 5;       // parameter rows: 5, or 6 with Delta B0 fitted (row 5)
 };
 
 // ---------------------------------------------------------------- non-Cartesian
@@ -46,15 +47,20 @@ struct SeqTimes {
 // W [nq][T][nx] (adjoint x-GEMM of w_q); apart as for the static adjoint.
 // rd_terms: the term count for a bound on |lambda| tau_max (0 = none fits).
 int rd_terms(double bound);
+// With d.np == 6 the off-resonance is theta row 5 times db0_unit Hz (db0 is
+// then not read) and J v gains that row's column.
 hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
-                         const float* v, const uint8_t* mask, const float* db0, const float2* eytab, float2* U,
-                         float te, float tmax, hipStream_t s);
+                         const float* v, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float2* eytab, float2* U, float te, float tmax, hipStream_t s);
 hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
                              float2* out, double* red, int* nred, hipStream_t s);
 hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s);
+// Chunk partials in the gradient assembly's layout; with d.np == 6 (ntr 3 or
+// 4) the Delta B0 pair follows as planes 8 and 9 of each chunk.
 hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
-                         const float* theta, const uint8_t* mask, const float* db0, const float2* eytab,
-                         const float2* W, float* apart, float te, float tmax, hipStream_t s);
+                         const float* theta, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float2* eytab, const float2* W, float* apart, float te, float tmax,
+                         hipStream_t s);
 
 // ---------------------------------------------------------------- balanced isochromat model
 // Slice profile of the balanced isochromat model (iso.hip): isochromat q has
@@ -162,9 +168,10 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
                              const float2* coil, const uint8_t* mask, const float2* eytab,
                              const float2* W, float* apart, hipStream_t s);
 
-// g[5][nv] = Re(J^H w) from the chunk partials (sums in chunk order); rows of
-// parameters outside param_mask (and masked voxels) are zero, and the dm/dB1
-// partials are read only when B1 is in param_mask.
+// g[np][nv] = Re(J^H w) from the chunk partials (sums in chunk order; 8
+// planes per chunk, 10 with Delta B0 fitted); rows of parameters outside
+// param_mask (and masked voxels) are zero, and the dm/dB1 partials are read
+// only when B1 is in param_mask.
 // With dir non-null, also the CG curvature partials dir . g and dir . dir
 // (FP64, one per block of 256 voxels: part[b] and part[nblocks + b]); with
 // step non-null as well, step . dir in part[2 nblocks + b].
@@ -217,7 +224,9 @@ hipError_t launch_tr_init(double* scal, double delta2, hipStream_t s);
 hipError_t launch_tr_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s);
 int tr_partials(const Dims& d);
-// trial = theta + step with the active ln T1, ln T2, B1 of unmasked voxels
+// Boxes lo[6], hi[6] per parameter row; rows 0-2 (ln T1, ln T2, B1) and,
+// with d.np == 6, row 5 (Delta B0) are bounded, the rho rows are not.
+// trial = theta + step with the active bounded entries of unmasked voxels
 // reflected into [lo, hi] (a fold at the walls); sv = trial - theta; the
 // number of reflected entries to SC_NREF and |sv|^2 to SC_SS.
 hipError_t launch_tr_trial(const Dims& d, const float* theta, const float* step, const float* lo,

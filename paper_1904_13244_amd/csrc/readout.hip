@@ -54,11 +54,11 @@ struct RdVoxel {
 };
 
 __device__ __forceinline__ RdVoxel rd_voxel(const float* __restrict__ theta, const float* __restrict__ db0,
-                                             int nv, int j, float te, float tmax)
+                                             float db0_unit, int nv, int j, float te, float tmax)
 {
     RdVoxel o;
     const float r2 = expf(-theta[(size_t)nv + j]);   // theta row 1 = ln T2
-    const float f = db0 ? db0[j] : 0.f;
+    const float f = db0 ? db0[j] * db0_unit : 0.f;
     o.r2t = r2 * tmax;
     o.L = make_float2(-o.r2t, -kTwoPi * f * tmax);
     float sn, cs;
@@ -71,13 +71,16 @@ __device__ __forceinline__ RdVoxel rd_voxel(const float* __restrict__ theta, con
 // 256), RD_NTB TRs; the lanes walk all rows, keeping the NQ complex sums of
 // each TR in registers; U written once per (term, TR, column), no partials.
 // MODE as the static y-stages: 0 signal, 1 J v with four trains, 3 J v with
-// three (B1 held fixed).
+// three (B1 held fixed). db0 (Hz per db0_unit) is the map or theta row 5;
+// with Delta B0 fitted (fit, J v only) the direction's row 5 adds
+// -2 pi i db0_unit (TE + tau) rho mu v_5 to the voxel's derivative: its TE
+// part joins x, its tau part y.
 template <int MODE, int NQ, typename TT>
 __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
                                                      const float* __restrict__ v, const uint8_t* __restrict__ mask,
-                                                     const float* __restrict__ db0, const float2* __restrict__ eytab,
-                                                     float2* __restrict__ U, int nx, int ny, int nv, int T,
-                                                     float te, float tmax)
+                                                     const float* __restrict__ db0, float db0_unit, int fit,
+                                                     const float2* __restrict__ eytab, float2* __restrict__ U,
+                                                     int nx, int ny, int nv, int T, float te, float tmax)
 {
     constexpr bool JV = MODE != 0, DB1 = MODE == 1;
     const int ix = threadIdx.x;
@@ -93,15 +96,20 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
         for (int iy = 0; iy < ny; ++iy) {
             const int j = iy * nx + ix;
             if (mask != nullptr && mask[j] == 0) continue;   // no contribution
-            const RdVoxel vx = rd_voxel(theta, db0, nv, j, te, tmax);
+            const RdVoxel vx = rd_voxel(theta, db0, db0_unit, nv, j, te, tmax);
             const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
-            float nr = 0.f, ni = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
+            float nr = 0.f, ni = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f, cte = 0.f, ctau = 0.f;
             if constexpr (JV) {
                 nr = v[3 * (size_t)nv + j];
                 ni = v[4 * (size_t)nv + j];
                 w0 = v[j];
                 w1 = v[(size_t)nv + j];
                 if constexpr (DB1) w2 = v[2 * (size_t)nv + j];
+                if (fit) {   // 2 pi db0_unit v_5 times TE, and times tau_max
+                    const float w5 = kTwoPi * db0_unit * v[5 * (size_t)nv + j];
+                    cte = w5 * te;
+                    ctau = w5 * tmax;
+                }
             }
 #pragma unroll
             for (int t = 0; t < RD_NTB; ++t) {
@@ -114,9 +122,10 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
                 } else {
                     const float m1 = (float)b[plane], m2 = (float)b[2 * plane];
                     const float a = DB1 ? fmaf(w0, m1, fmaf(w1, m2, w2 * (float)b[3 * plane])) : fmaf(w0, m1, w1 * m2);
-                    x = make_float2(-fmaf(ri, a, ni * mu), fmaf(rr, a, nr * mu));
-                    const float yt = mu * vx.r2t * w1;
-                    y = make_float2(-ri * yt, rr * yt);
+                    // i (rho a + nu mu) + rho mu cte; i rho mu r2t w1 + rho mu ctau
+                    const float e = mu * cte, et = mu * ctau, yt = mu * vx.r2t * w1;
+                    x = make_float2(fmaf(rr, e, -fmaf(ri, a, ni * mu)), fmaf(ri, e, fmaf(rr, a, nr * mu)));
+                    y = make_float2(fmaf(rr, et, -ri * yt), fmaf(ri, et, rr * yt));
                 }
                 const float2 ec = cmul(eytab[(size_t)n * ny + iy], vx.c);
                 float2 tq = cmul(ec, x);   // z L^q
@@ -211,32 +220,37 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
 
 // Adjoint term sums: one thread per voxel (256-voxel blocks) and TR chunk;
 // per TR the Horner sums V and V' over the terms, then the chunk partials A_p
-// in the layout the gradient assembly reads ([chunk][2 NTR planes][nv]; NTR =
-// 1 writes the m pair only, for the proton-density initialisation).
+// in the layout the gradient assembly reads ([chunk][pl planes][nv], pl = 8,
+// or 10 with Delta B0 fitted; NTR = 1 writes the m pair only, 2 planes, for
+// the proton-density initialisation). With Delta B0 fitted (fit, NTR >= 3)
+// its pair is A_5 = 2 pi i db0_unit sum_n mu conj(c Ey) (TE V + tau_max V').
 template <int NTR, int NQ, typename TT>
 __global__ __launch_bounds__(256) void rd_adj_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
                                                      const uint8_t* __restrict__ mask, const float* __restrict__ db0,
-                                                     const float2* __restrict__ eytab, const float2* __restrict__ W,
-                                                     float* __restrict__ apart, int nx, int ny, int nv, int T,
-                                                     int n_per_chunk, float te, float tmax)
+                                                     float db0_unit, int fit, const float2* __restrict__ eytab,
+                                                     const float2* __restrict__ W, float* __restrict__ apart,
+                                                     int nx, int ny, int nv, int T, int n_per_chunk, float te,
+                                                     float tmax)
 {
-    constexpr int PL = NTR == 1 ? 2 : 8;   // planes per chunk
+    const bool f5 = NTR >= 3 && fit;
+    const int pl = NTR == 1 ? 2 : (f5 ? 10 : 8);   // planes per chunk
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int chunk = blockIdx.y;
     if (j >= nv) return;
-    float* dst = apart + (size_t)chunk * PL * nv + j;
+    float* dst = apart + (size_t)chunk * pl * nv + j;
     const bool on = mask == nullptr || mask[j] != 0;
     if (!on) {
 #pragma unroll
         for (int p = 0; p < 2 * NTR; ++p) dst[(size_t)p * nv] = 0.f;
+        if (f5) dst[(size_t)8 * nv] = dst[(size_t)9 * nv] = 0.f;
         return;
     }
     const int ix = j % nx, iy = j / nx;
-    const RdVoxel vx = rd_voxel(theta, db0, nv, j, te, tmax);
+    const RdVoxel vx = rd_voxel(theta, db0, db0_unit, nv, j, te, tmax);
     const float2 Lc = make_float2(vx.L.x, -vx.L.y);   // conj(L)
     const int n0 = chunk * n_per_chunk, n1 = min(T, n0 + n_per_chunk);
     const size_t plane = (size_t)T * nv, wplane = (size_t)T * nx;
-    float2 A[NTR], At = make_float2(0.f, 0.f);
+    float2 A[NTR], At = make_float2(0.f, 0.f), Af = make_float2(0.f, 0.f);
 #pragma unroll
     for (int p = 0; p < NTR; ++p) A[p] = make_float2(0.f, 0.f);
     for (int n = n0; n < n1; ++n) {
@@ -268,9 +282,13 @@ __global__ __launch_bounds__(256) void rd_adj_kernel(const TT* __restrict__ trai
         }
         if constexpr (NTR >= 3) {
             Vt = cmulconj(ec, Vt);
-            const float m0 = (float)b[0] * vx.r2t;
+            const float mu = (float)b[0], m0 = mu * vx.r2t;
             At.x = fmaf(m0, Vt.x, At.x);
             At.y = fmaf(m0, Vt.y, At.y);
+            if (f5) {
+                Af.x = fmaf(mu, fmaf(te, V.x, tmax * Vt.x), Af.x);
+                Af.y = fmaf(mu, fmaf(te, V.y, tmax * Vt.y), Af.y);
+            }
         }
     }
     if constexpr (NTR >= 3) {
@@ -282,32 +300,44 @@ __global__ __launch_bounds__(256) void rd_adj_kernel(const TT* __restrict__ trai
         dst[(size_t)(2 * p) * nv] = A[p].x;
         dst[(size_t)(2 * p + 1) * nv] = A[p].y;
     }
+    if (f5) {   // times 2 pi i db0_unit
+        const float k = kTwoPi * db0_unit;
+        dst[(size_t)8 * nv] = -k * Af.y;
+        dst[(size_t)9 * nv] = k * Af.x;
+    }
 }
 
 template <int NQ, typename TT>
 hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, const float* v, const uint8_t* mask,
-                 const float* db0, const float2* eytab, float2* U, float te, float tmax, hipStream_t s)
+                 const float* db0, float db0_unit, const float2* eytab, float2* U, float te, float tmax,
+                 hipStream_t s)
 {
     const int blocks = ceil_div(d.T, RD_NTB);
+    const int fit = d.np == 6;
+#define RD_FWD(M)                                                                                           \
+    rd_fwd_kernel<M, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, db0_unit, fit, eytab, U, d.nx, \
+                                                    d.ny, d.nv, d.T, te, tmax)
     switch (mode) {
-    case 0: rd_fwd_kernel<0, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
-    case 1: rd_fwd_kernel<1, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
-    case 3: rd_fwd_kernel<3, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, eytab, U, d.nx, d.ny, d.nv, d.T, te, tmax); break;
+    case 0: RD_FWD(0); break;
+    case 1: RD_FWD(1); break;
+    case 3: RD_FWD(3); break;
     default: return hipErrorInvalidValue;
     }
+#undef RD_FWD
     return hipGetLastError();
 }
 
 template <int NQ, typename TT>
 hipError_t adj_q(const Dims& d, int ntr, int chunks, const TT* trains, const float* theta, const uint8_t* mask,
-                 const float* db0, const float2* eytab, const float2* W, float* apart, float te, float tmax,
-                 hipStream_t s)
+                 const float* db0, float db0_unit, const float2* eytab, const float2* W, float* apart, float te,
+                 float tmax, hipStream_t s)
 {
     const int per = ceil_div(d.T, chunks);
     if (chunks < 1 || ceil_div(d.T, per) != chunks) return hipErrorInvalidValue;
     const dim3 grid(ceil_div(d.nv, 256), chunks);
-#define RD_ADJ(NT) rd_adj_kernel<NT, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, mask, db0, eytab, W, apart, d.nx, \
-                                                                 d.ny, d.nv, d.T, per, te, tmax)
+    const int fit = d.np == 6;
+#define RD_ADJ(NT) rd_adj_kernel<NT, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, mask, db0, db0_unit, fit, eytab, W, \
+                                                                 apart, d.nx, d.ny, d.nv, d.T, per, te, tmax)
     if (ntr == 1)
         RD_ADJ(1);
     else if (ntr == 3)
@@ -347,17 +377,29 @@ int rd_terms(double bound)
     default: return hipErrorInvalidValue;                                \
     }
 
+// The off-resonance source: theta row 5 in units of db0_unit Hz when Delta
+// B0 is fitted, else the map (Hz, or none).
+static void rd_source(const Dims& d, const float* theta, const float*& db0, float& unit)
+{
+    if (d.np == 6) {
+        db0 = theta + (size_t)5 * d.nv;
+    } else {
+        unit = 1.f;
+    }
+}
+
 hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
-                         const float* v, const uint8_t* mask, const float* db0, const float2* eytab, float2* U,
-                         float te, float tmax, hipStream_t s)
+                         const float* v, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float2* eytab, float2* U, float te, float tmax, hipStream_t s)
 {
     if (d.nx > 256) return hipErrorInvalidValue;
+    rd_source(d, theta, db0, db0_unit);
     if (f16) {
         const _Float16* tr = static_cast<const _Float16*>(trains);
-        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, eytab, U, te, tmax, s)))
+        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, db0_unit, eytab, U, te, tmax, s)))
     }
     const float* tr = static_cast<const float*>(trains);
-    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, eytab, U, te, tmax, s)))
+    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, db0_unit, eytab, U, te, tmax, s)))
 }
 
 hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
@@ -381,15 +423,18 @@ hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* 
 }
 
 hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
-                         const float* theta, const uint8_t* mask, const float* db0, const float2* eytab,
-                         const float2* W, float* apart, float te, float tmax, hipStream_t s)
+                         const float* theta, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float2* eytab, const float2* W, float* apart, float te, float tmax,
+                         hipStream_t s)
 {
+    rd_source(d, theta, db0, db0_unit);
     if (f16) {
         const _Float16* tr = static_cast<const _Float16*>(trains);
-        RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, eytab, W, apart, te, tmax, s)))
+        RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, db0_unit, eytab, W, apart, te, tmax,
+                                      s)))
     }
     const float* tr = static_cast<const float*>(trains);
-    RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, eytab, W, apart, te, tmax, s)))
+    RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, db0_unit, eytab, W, apart, te, tmax, s)))
 }
 
 #undef RD_NQ_DISPATCH

@@ -2,7 +2,8 @@
 // deterministic FP64 reductions (fixed grid, fixed order), the CG recurrences
 // on Re(J^H J) p = -g (eq. 4) with every scalar kept in device memory, the
 // projected line-search trial, and the CGLS recurrences of the proton-density
-// initialisation. Vectors are FP32 [5][Nv]; dots, norms, alpha and beta FP64.
+// initialisation. Vectors are FP32 [np][Nv] (np = 5, or 6 with Delta B0
+// fitted); dots, norms, alpha and beta FP64.
 #include "mrstat_internal.h"
 
 namespace mrstat {
@@ -380,6 +381,24 @@ __global__ __launch_bounds__(RB) void tr_step_kernel(const float* __restrict__ d
     }
 }
 
+// The parameter box by value: rows 0-2 (ln T1, ln T2, B1) and 5 (Delta B0)
+// are bounded, the rho rows 3 and 4 are not.
+struct Box6 {
+    float lo[6], hi[6];
+};
+
+__host__ __device__ __forceinline__ bool bounded_row(int q) { return q < 3 || q == 5; }
+
+Box6 box6(const float* lo, const float* hi)
+{
+    Box6 b;
+    for (int q = 0; q < 6; ++q) {
+        b.lo[q] = lo[q];
+        b.hi[q] = hi[q];
+    }
+    return b;
+}
+
 // Reflection into [lo, hi]: the end point of the straight path that bounces
 // off the walls (a fold with period 2 (hi - lo)); inside values pass as they
 // are.
@@ -397,26 +416,24 @@ __device__ __forceinline__ float reflect_box(float x, float lo, float hi, bool& 
 }
 
 __global__ __launch_bounds__(RB) void tr_trial_kernel(const float* __restrict__ theta,
-                                                      const float* __restrict__ step, float lo0,
-                                                      float lo1, float lo2, float hi0, float hi1,
-                                                      float hi2, int param_mask,
+                                                      const float* __restrict__ step, Box6 box,
+                                                      int param_mask,
                                                       const uint8_t* __restrict__ mask,
                                                       float* __restrict__ trial,
-                                                      float* __restrict__ sv, int nv,
+                                                      float* __restrict__ sv, int nv, int np,
                                                       double* __restrict__ part)
 {
     __shared__ double sh[RB / 64];
-    const size_t n = (size_t)5 * nv;
+    const size_t n = (size_t)np * nv;
     double cnt = 0.0, ss = 0.0;
     for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
         const int q = (int)(i / nv), j = (int)(i % nv);
         const float th = theta[i];
         float x = th + step[i];
         const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
-        if (q < 3 && on) {
+        if (bounded_row(q) && on) {
             bool moved;
-            x = reflect_box(x, q == 0 ? lo0 : (q == 1 ? lo1 : lo2), q == 0 ? hi0 : (q == 1 ? hi1 : hi2),
-                            moved);
+            x = reflect_box(x, box.lo[q], box.hi[q], moved);
             cnt += moved ? 1.0 : 0.0;
         }
         const float t = on ? x : th;
@@ -453,22 +470,17 @@ __global__ void tr_accept_kernel(double* __restrict__ sc, double eta, const floa
         theta[i] = trial[i];
 }
 
-// trial = P(theta + t step): active ln T1, ln T2, B1 clamped to the box.
+// trial = P(theta + t step): active bounded entries clamped to the box.
 __global__ void ls_trial_kernel(const float* __restrict__ theta, const float* __restrict__ step,
-                                float t, float lo0, float lo1, float lo2, float hi0, float hi1,
-                                float hi2, int param_mask, const uint8_t* __restrict__ mask,
-                                float* __restrict__ trial, int nv)
+                                float t, Box6 box, int param_mask, const uint8_t* __restrict__ mask,
+                                float* __restrict__ trial, int nv, int np)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)5 * nv) return;
+    if (i >= (size_t)np * nv) return;
     const int q = (int)(i / nv), j = (int)(i % nv);
     float x = fmaf(t, step[i], theta[i]);
     const bool on = ((param_mask >> q) & 1) && (mask == nullptr || mask[j] != 0);
-    if (q < 3 && on) {
-        const float lo = q == 0 ? lo0 : (q == 1 ? lo1 : lo2);
-        const float hi = q == 0 ? hi0 : (q == 1 ? hi1 : hi2);
-        x = fminf(fmaxf(x, lo), hi);
-    }
+    if (bounded_row(q) && on) x = fminf(fmaxf(x, box.lo[q]), box.hi[q]);
     trial[i] = on ? x : theta[i];
 }
 
@@ -526,12 +538,12 @@ __global__ __launch_bounds__(RB) void sum2_kernel(const double* __restrict__ par
 
 // ------------------------------------------------------------------ CGLS
 __global__ void set_rho_kernel(const float* __restrict__ th, const float2* __restrict__ p,
-                               float* __restrict__ out, int nv)
+                               float* __restrict__ out, int nv, int np)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)5 * nv) return;
+    if (i >= (size_t)np * nv) return;
     const int q = (int)(i / nv), j = (int)(i % nv);
-    out[i] = q < 3 ? th[i] : (q == 3 ? p[j].x : p[j].y);
+    out[i] = q == 3 ? p[j].x : (q == 4 ? p[j].y : th[i]);
 }
 
 // x += a p (complex per voxel), a = gamma / qq; stop when qq == 0.
@@ -625,7 +637,7 @@ hipError_t launch_dot_c(const float2* a, const float2* b, size_t n, double* part
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
                           double* scal, double* partials, hipStream_t s)
 {
-    const size_t n = (size_t)5 * d.nv;
+    const size_t n = (size_t)d.np * d.nv;
     cg_init_kernel<<<RED_BLOCKS, RB, 0, s>>>(g, step, res, dir, n, partials);
     cg_init_finish<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal);
     return hipGetLastError();
@@ -638,7 +650,7 @@ hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* r
 {
     // partials: curvature pairs [2][nb] from the finish kernel, then res.res
     // [RED_BLOCKS].
-    const size_t n = (size_t)5 * d.nv;
+    const size_t n = (size_t)d.np * d.nv;
     const int nb = (d.nv + 255) / 256;
     double* rrp = partials + 2 * nb;
     cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp);
@@ -659,7 +671,7 @@ hipError_t launch_tr_update(const Dims& d, const float* q, float* step, float* r
 {
     // partials: curvature triples [3][nb] from the finish kernel, then
     // res.res and step.step [RED_BLOCKS] each.
-    const size_t n = (size_t)5 * d.nv;
+    const size_t n = (size_t)d.np * d.nv;
     const int nb = (d.nv + 255) / 256;
     double* rrp = partials + 3 * nb;
     double* zzp = rrp + RED_BLOCKS;
@@ -672,8 +684,8 @@ hipError_t launch_tr_trial(const Dims& d, const float* theta, const float* step,
                            const float* hi, int param_mask, const uint8_t* mask, float* trial,
                            float* sv, double* scal, double* partials, hipStream_t s)
 {
-    tr_trial_kernel<<<RED_BLOCKS, RB, 0, s>>>(theta, step, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
-                                              param_mask, mask, trial, sv, d.nv, partials);
+    tr_trial_kernel<<<RED_BLOCKS, RB, 0, s>>>(theta, step, box6(lo, hi), param_mask, mask, trial, sv, d.nv,
+                                              d.np, partials);
     sum2_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, scal + SC_NREF);
     return hipGetLastError();
 }
@@ -681,7 +693,7 @@ hipError_t launch_tr_trial(const Dims& d, const float* theta, const float* step,
 hipError_t launch_tr_accept(const Dims& d, double* scal, double eta, const float* trial, float* theta,
                             hipStream_t s)
 {
-    tr_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, eta, trial, theta, (size_t)5 * d.nv);
+    tr_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, eta, trial, theta, (size_t)d.np * d.nv);
     return hipGetLastError();
 }
 
@@ -689,15 +701,15 @@ hipError_t launch_ls_trial_masked(const Dims& d, const float* theta, const float
                                   const float* lo, const float* hi, int param_mask,
                                   const uint8_t* mask, float* trial, hipStream_t s)
 {
-    ls_trial_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(
-        theta, step, t, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], param_mask, mask, trial, d.nv);
+    ls_trial_kernel<<<grid_for((size_t)d.np * d.nv), 256, 0, s>>>(theta, step, t, box6(lo, hi), param_mask,
+                                                                  mask, trial, d.nv, d.np);
     return hipGetLastError();
 }
 
 hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, const float* theta,
                            double* partials, double* out, hipStream_t s)
 {
-    const size_t n = (size_t)5 * d.nv;
+    const size_t n = (size_t)d.np * d.nv;
     pred_kernel<<<RED_BLOCKS, RB, 0, s>>>(g, trial, theta, n, partials);
     sum2_kernel<<<1, RB, 0, s>>>(partials, RED_BLOCKS, out);
     return hipGetLastError();
@@ -706,14 +718,14 @@ hipError_t launch_pred_dot(const Dims& d, const float* g, const float* trial, co
 hipError_t launch_ls_accept(const Dims& d, double* scal, double c1, const float* trial, float* theta,
                             hipStream_t s)
 {
-    ls_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, c1, trial, theta, (size_t)5 * d.nv);
+    ls_accept_kernel<<<RED_BLOCKS, 256, 0, s>>>(scal, c1, trial, theta, (size_t)d.np * d.nv);
     return hipGetLastError();
 }
 
 hipError_t launch_set_rho(const Dims& d, const float* theta_in, const float2* p, float* theta_out,
                           hipStream_t s)
 {
-    set_rho_kernel<<<grid_for((size_t)5 * d.nv), 256, 0, s>>>(theta_in, p, theta_out, d.nv);
+    set_rho_kernel<<<grid_for((size_t)d.np * d.nv), 256, 0, s>>>(theta_in, p, theta_out, d.nv, d.np);
     return hipGetLastError();
 }
 

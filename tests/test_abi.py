@@ -152,3 +152,30 @@ def test_readout_context_terms_and_refusals():
         assert B.lib().mrstat_set_db0(h, fake) == B.ERR_STATE
     finally:
         B.mrstat_destroy(h)
+
+
+def test_fit_db0_refusals_on_the_host():
+    """mrstat_fit_db0: readout-dynamics contexts only, not with the balanced
+    model, a finite non-negative unit."""
+    import dataclasses
+    base = I.make_problem(20, 18, 12, 40, 8)
+    h = B.mrstat_create(base)
+    try:
+        assert B.lib().mrstat_fit_db0(h, 10.0) == B.ERR_STATE
+    finally:
+        B.mrstat_destroy(h)
+    h = B.mrstat_create(dataclasses.replace(base, dwell=1 / 85.6e3))
+    try:
+        for bad in (-1.0, float("nan"), float("inf")):
+            assert B.lib().mrstat_fit_db0(h, bad) == B.ERR_ARG
+        assert B.lib().mrstat_fit_db0(h, 10.0) == B.OK
+        scale, weight = I.slice_profile_gaussian(3)
+        sc = np.ascontiguousarray(scale, dtype=np.float64)
+        wt = np.ascontiguousarray(weight, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        assert B.lib().mrstat_set_isochromats(h, 3, sc.ctypes.data_as(dp), wt.ctypes.data_as(dp)) == B.ERR_STATE
+        assert B.lib().mrstat_fit_db0(h, 0.0) == B.OK
+        assert B.lib().mrstat_set_isochromats(h, 3, sc.ctypes.data_as(dp), wt.ctypes.data_as(dp)) == B.OK
+        assert B.lib().mrstat_fit_db0(h, 10.0) == B.ERR_STATE
+    finally:
+        B.mrstat_destroy(h)

@@ -133,10 +133,12 @@ def test_products_match_oracle(case, oracle_lib):
     e_r, e_f, e_jv, e_rows, jv, jhw = _products(case, oracle_lib)
     print(f"  residual {e_r:.2e} f {e_f:.2e} jv {e_jv:.2e} jhw rows {['%.1e' % e for e in e_rows]}", flush=True)
     assert max([e_r, e_f, e_jv] + e_rows) <= TOL
-    # the adjoint identity <w, J v> = v . Re(J^H w) on the GPU's own products
+    # the adjoint identity <w, J v> = v . Re(J^H w) on the GPU's own products,
+    # to the rounding scale of the inner products (|w| |J v|: the two sides
+    # can be small by cancellation)
     lhs = np.vdot(case["w"].reshape(-1), jv.reshape(-1)).real
     rhs = float(np.dot(case["v"].reshape(-1), jhw.reshape(-1)))
-    assert abs(lhs - rhs) <= TOL * max(abs(lhs), abs(rhs))
+    assert abs(lhs - rhs) <= TOL * np.linalg.norm(case["w"]) * np.linalg.norm(jv)
 
 
 @pytest.mark.parametrize("enc,bar", [(1, 1e-4)])
@@ -259,10 +261,12 @@ def test_t2_box_below_the_bound_is_refused(torch_gpu):
     ctx.close()
 
 
-def test_fullsize_sampled(torch_gpu, oracle_lib):
+@pytest.mark.parametrize("fit", [False, True])
+def test_fullsize_sampled(torch_gpu, oracle_lib, fit):
     """224 x 224 phantom, 1120 TRs, 448 samples at 85.6 kHz (24 terms), a
-    smooth off-resonance field of +-150 Hz: the GPU runs the whole image's
-    kernels with 160 voxels masked in; the oracle's direct sum covers those."""
+    smooth off-resonance field of +-150 Hz (a map, or theta row 5 with Delta
+    B0 fitted): the GPU runs the whole image's kernels with 160 voxels masked
+    in; the oracle's direct sum covers those."""
     torch = torch_gpu
     from paper_1904_13244_amd.binding import Context
     w = I.config(3)
@@ -276,12 +280,16 @@ def test_fullsize_sampled(torch_gpu, oracle_lib):
     mask[sel] = 1
     th = w.theta.copy()
     th[1, sel] = np.log(rng.uniform(0.01, 0.15, sel.size))
+    if fit:
+        unit = 1.0 / (2 * np.pi * prob.te)
+        prob = dataclasses.replace(prob, db0=None, db0_unit=unit)
+        th = np.vstack([th, (db0 / unit)[None, :]])
     th = th.astype(np.float32).astype(np.float64)
     # oracle trains on the masked-in voxels only (the others do not enter)
     sub = I.make_problem(sel.size, 1, prob.n_tr, sel.size, prob.n_states, tr=prob.tr, te=prob.te,
                          t_inv=prob.t_inv, flip_deg=prob.flip_deg, rf_phase=prob.rf_phase)
     ora = np.zeros((4, prob.n_tr, prob.nv), np.complex128)
-    ora[:, :, sel] = oracle_lib.epg(sub, th[:, sel])
+    ora[:, :, sel] = oracle_lib.epg(sub, th[:5, sel])
     ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
     assert ctx.readout_terms() == 24
     thd = _dev(torch, th, torch.float32)
@@ -297,9 +305,148 @@ def test_fullsize_sampled(torch_gpu, oracle_lib):
     e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, mask=mask))
     jhw = ctx.jhw(thd, _dev(torch, wv, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
     ref = oracle_lib.jhw(prob, th, ora, wv, mask=mask)
-    e_rows = [_rel(jhw[q][sel], ref[q][sel]) for q in range(5)]
+    e_rows = [_rel(jhw[q][sel], ref[q][sel]) for q in range(th.shape[0])]
     zero_out = float(np.abs(jhw[:, mask == 0]).max())
     ctx.close()
-    print(f"\n  [readout 224x224x1120, 448 samples, 160 voxels] trains {e_tr:.1e} signal {e_s:.1e} "
+    print(f"\n  [readout 224x224x1120, 448 samples, 160 voxels, Delta B0 {'fitted' if fit else 'map'}] "
+          f"trains {e_tr:.1e} signal {e_s:.1e} "
           f"jv {e_jv:.1e} jhw rows {['%.1e' % e for e in e_rows]}", flush=True)
     assert max([e_tr, e_s, e_jv] + e_rows) <= TOL and zero_out == 0.0
+
+
+# --------------------------------------------------------------------------
+# Delta B0 fitted as the sixth parameter (mrstat_fit_db0): theta row 5 times
+# db0_unit Hz, here db0_unit = 1 / (2 pi TE), so that row 5 is the
+# off-resonance phase at the echo in radians.
+
+def _fit_case(name):
+    prob, th, mask = _case(name)
+    unit = 1.0 / (2 * np.pi * prob.te)
+    fit = dataclasses.replace(prob, db0=None, db0_unit=unit)
+    th6 = np.vstack([th, (prob.db0 / unit)[None, :]]).astype(np.float32).astype(np.float64)
+    return fit, th6, mask
+
+
+@pytest.mark.parametrize("name", ["small", "ragged", "quarter_bandwidth"])
+def test_fitted_offresonance_products(torch_gpu, oracle_lib, name):
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    prob, th, mask = _fit_case(name)
+    ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
+    assert ctx.np == 6
+    ora = oracle_lib.epg(prob, th)
+    s = oracle_lib.signal(prob, th, ora, mask=mask)
+    n = I.unit_noise(prob)
+    d = s + n * (np.linalg.norm(s) / (50.0 * np.linalg.norm(n)))
+    th1 = th.copy()
+    th1[5] += 0.2
+    th1 = th1.astype(np.float32).astype(np.float64)
+    f_ref, r_ref = oracle_lib.residual(prob, th1, d, mask=mask)
+    f, r = ctx.residual(_dev(torch, th1, torch.float32), _dev(torch, d, torch.complex64))
+    e_r = float(np.linalg.norm(r.cpu().numpy().astype(np.complex128) - r_ref) / np.linalg.norm(d))
+    v, w = I.probe_vectors(prob)
+    thd = _dev(torch, th, torch.float32)
+    ctx.linearise(thd)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    ctx.close()
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, mask=mask))
+    ref = oracle_lib.jhw(prob, th, ora, w, mask=mask)
+    e_rows = [_rel(jhw[q], ref[q]) for q in range(6)]
+    print(f"\n  [Delta B0 fitted, {name}] residual {e_r:.2e} jv {e_jv:.2e} "
+          f"jhw rows {['%.1e' % e for e in e_rows]}", flush=True)
+    assert max([e_r, e_jv] + e_rows) <= TOL
+    lhs = np.vdot(w.reshape(-1), jv.reshape(-1)).real   # adjoint identity, scale |w| |J v|
+    rhs = float(np.dot(v.reshape(-1), jhw.reshape(-1)))
+    assert abs(lhs - rhs) <= TOL * np.linalg.norm(w) * np.linalg.norm(jv)
+
+
+def test_fitted_offresonance_steps_match_oracle(torch_gpu, oracle_lib):
+    """GN steps with Delta B0 fitted (B1 known, then fitted), a trust-region
+    step and the rho initialisation, from the same start as the oracle."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    prob, th_true, mask = _fit_case("small")
+    d = oracle_lib.signal(prob, th_true, oracle_lib.epg(prob, th_true, tangents=False), mask=mask)
+    rng = np.random.default_rng(63)
+    th0 = th_true.copy()
+    th0[:2] += 0.05 * rng.standard_normal((2, prob.nv))
+    th0[5] += 0.3 * rng.standard_normal(prob.nv)
+    th0 = th0.astype(np.float32).astype(np.float64)
+    ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
+    dd = _dev(torch, d, torch.complex64)
+    for pm in (0b111011, 0b111111, 0b100000):
+        th_o, rep_o = oracle_lib.gn_step(prob, th0, d, n_cg=10, param_mask=pm, lo=I.GN_LO, hi=I.GN_HI,
+                                         mask=mask)
+        th_g = _dev(torch, th0, torch.float32)
+        rep = ctx.gn_step(th_g, dd, 10, pm, I.GN_LO, I.GN_HI)
+        e = _rel(th_g.cpu().numpy().astype(np.float64), th_o)
+        print(f"\n  [Delta B0 fitted gn, mask {pm:#08b}] t {rep.t}/{rep_o.t} cg {rep.cg_iters}/{rep_o.cg_iters} "
+              f"theta {e:.2e}", flush=True)
+        assert rep.t == rep_o.t and rep.cg_iters == rep_o.cg_iters and e <= TOL
+    th_o, do, rep_o = oracle_lib.tr_step(prob, th0, d, 1.0, 10, 0b111011, I.GN_LO, I.GN_HI, mask=mask)
+    th_g = _dev(torch, th0, torch.float32)
+    dg, rep = ctx.tr_step(th_g, dd, 1.0, 10, 0b111011, I.GN_LO, I.GN_HI)
+    e = _rel(th_g.cpu().numpy().astype(np.float64), th_o)
+    print(f"  [Delta B0 fitted tr] exit {rep.exit_kind}/{rep_o['exit_kind']} cg {rep.cg_iters}/{rep_o['cg_iters']} "
+          f"refl {rep.n_reflected}/{rep_o['n_reflected']} delta {dg:.4g}/{do:.4g} theta {e:.2e}", flush=True)
+    assert rep.exit_kind == rep_o["exit_kind"] and rep.cg_iters == rep_o["cg_iters"] and dg == do
+    assert rep.n_reflected == rep_o["n_reflected"] and e <= TOL
+    ref = oracle_lib.rho_init(prob, th0, d, n_iter=5, mask=mask)
+    got = ctx.rho_init(_dev(torch, th0, torch.float32), dd, n_iter=5).cpu().numpy().astype(np.float64)
+    e = _rel(got[3:5], ref[3:5])
+    print(f"  [Delta B0 fitted rho init] {e:.2e}", flush=True)
+    assert e <= TOL and np.array_equal(got[[0, 1, 2, 5]], th0[[0, 1, 2, 5]])
+    ctx.close()
+
+
+def test_fitted_offresonance_box(torch_gpu, oracle_lib):
+    """A step that would leave +-rd_max_db0 Hz is projected (line search) or
+    reflected (trust region) at the same entries as by the oracle."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    prob, th_true, mask = _fit_case("small")
+    tight = dataclasses.replace(prob, rd_max_db0=30.0)   # below part of the truth
+    lim = 50.0 / prob.db0_unit
+    th_true[5] = np.clip(th_true[5], -lim, lim).astype(np.float32)
+    d = oracle_lib.signal(tight, th_true, oracle_lib.epg(tight, th_true, tangents=False), mask=mask)
+    th0 = th_true.copy()
+    th0[5] = 0.0
+    ctx = Context(tight, mask=_dev(torch, mask, torch.uint8))
+    dd = _dev(torch, d, torch.complex64)
+    th_o, rep_o = oracle_lib.gn_step(tight, th0, d, n_cg=20, param_mask=0b100000, lo=I.GN_LO, hi=I.GN_HI,
+                                     mask=mask)
+    th_g = _dev(torch, th0, torch.float32)
+    rep = ctx.gn_step(th_g, dd, 20, 0b100000, I.GN_LO, I.GN_HI)
+    g = th_g.cpu().numpy().astype(np.float64)
+    at_wall_o = np.abs(np.abs(th_o[5]) * prob.db0_unit - 30.0) <= 1e-3
+    at_wall_g = np.abs(np.abs(g[5]) * prob.db0_unit - 30.0) <= 1e-3
+    print(f"\n  [Delta B0 box, gn] t {rep.t}/{rep_o.t} at the wall {at_wall_g.sum()}/{at_wall_o.sum()} "
+          f"theta {_rel(g, th_o):.2e}", flush=True)
+    assert at_wall_o.sum() > 0
+    assert rep.t == rep_o.t and np.array_equal(at_wall_g, at_wall_o) and _rel(g, th_o) <= TOL
+    assert np.all(np.abs(g[5]) * prob.db0_unit <= 30.0 * (1 + 1e-6))
+    th_o, do, rep_o = oracle_lib.tr_step(tight, th0, d, 8.0, 20, 0b100000, I.GN_LO, I.GN_HI, delta_max=8.0,
+                                         mask=mask)
+    th_g = _dev(torch, th0, torch.float32)
+    dg, rep = ctx.tr_step(th_g, dd, 8.0, 20, 0b100000, I.GN_LO, I.GN_HI, delta_max=8.0)
+    print(f"  [Delta B0 box, tr] reflected {rep.n_reflected}/{rep_o['n_reflected']} exit "
+          f"{rep.exit_kind}/{rep_o['exit_kind']}", flush=True)
+    assert rep_o["n_reflected"] > 0
+    assert rep.n_reflected == rep_o["n_reflected"] and rep.exit_kind == rep_o["exit_kind"]
+    assert _rel(th_g.cpu().numpy().astype(np.float64), th_o) <= TOL
+    ctx.close()
+
+
+def test_bit5_needs_the_fit(torch_gpu):
+    torch = torch_gpu
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd.binding import Context
+    prob, th, mask = _case("small")
+    ctx = Context(prob)
+    thd = _dev(torch, th, torch.float32)
+    dd = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+    with pytest.raises(B.MrstatError) as e:
+        ctx.gn_step(thd, dd, 5, 0b111011, I.GN_LO, I.GN_HI)
+    assert e.value.status == B.ERR_ARG
+    ctx.close()

@@ -107,6 +107,8 @@ def parse():
                     help="skip the B1-known (three-train) variant")
     ap.add_argument("--no-noncartesian", action="store_true",
                     help="skip the golden-angle radial contraction measurement")
+    ap.add_argument("--no-readout-dynamics", action="store_true",
+                    help="skip the readout-dynamics (T2 decay and off-resonance per sample) measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--train-epochs", type=int, default=None,
@@ -267,6 +269,81 @@ def noncartesian(torch, work, reps=5):
                       "frac": passes * ach / peak}
         out[name] = res
     ctx.close()
+    return out
+
+
+def readout_dynamics(torch, work, n_cg, steps=3):
+    """The benchmark workload with T2 decay and off-resonance during every
+    readout (448 samples at 85.6 kHz: 24 expansion terms for T2 >= 5 ms and
+    |Delta B0| <= 200 Hz) and a smooth +-150 Hz off-resonance field: GN steps
+    (five parameters with the field as a map; six with Delta B0 fitted) and
+    the cached J v + J^H w pair with per-kernel times; plain EPG, FP32 trains,
+    split-BF16 contraction. The x-GEMMs carry the expansion terms as rows:
+    8 NQ T nx nk algorithmic flop per product."""
+    import dataclasses
+
+    from paper_1904_13244_amd import binding as B
+    from paper_1904_13244_amd import inputs as I
+    from paper_1904_13244_amd.binding import Context
+
+    p0 = work.problem
+    yy, xx = np.meshgrid(np.linspace(-1, 1, p0.ny), np.linspace(-1, 1, p0.nx), indexing="ij")
+    db0 = (150.0 * (0.6 * xx + 0.3 * yy * yy - 0.1 * xx * yy)).reshape(-1)
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    out = {"workload": ("224x224 phantom, 1120 TRs, 448 samples at 85.6 kHz with T2 decay and "
+                        "off-resonance during each readout, K=32, plain EPG, FP32 trains, split-BF16 "
+                        "contraction")}
+    unit = 1.0 / (2 * np.pi * p0.te)
+    for name, prob, theta in (
+            ("db0_map", dataclasses.replace(p0, dwell=1 / 85.6e3, db0=db0), work.theta),
+            ("db0_fitted", dataclasses.replace(p0, dwell=1 / 85.6e3, db0_unit=unit),
+             np.vstack([work.theta, (db0 / unit)[None, :]]))):
+        ctx = Context(prob)
+        ctx.set_encoding(B.ENC_SPLIT_BF16)
+        th_true = dev(theta, torch.float32)
+        zeros = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+        _, r = ctx.residual(th_true, zeros)
+        data = (-r).contiguous()
+        th0 = theta.copy()
+        rng = np.random.default_rng(I.SEED_PROBE)
+        th0[0] += 0.05 * rng.standard_normal(prob.nv)
+        th0[1] += 0.05 * rng.standard_normal(prob.nv)
+        pm = 0b11111 if name == "db0_map" else 0b111111
+        th = dev(th0, torch.float32)
+        ctx.gn_step(th, data, n_cg, pm, I.GN_LO, I.GN_HI, n_ls_max=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rep = ctx.gn_step(th, data, n_cg, pm, I.GN_LO, I.GN_HI, n_ls_max=1)
+        torch.cuda.synchronize()
+        step_ms = 1e3 * (time.perf_counter() - t0) / steps
+        v, w = I.probe_vectors(prob)
+        vd, wd = dev(v, torch.float32), dev(w, torch.complex64)
+        ctx.linearise(th)
+        jv = ctx.jv(th, vd, reuse=True)
+        g = ctx.jhw(th, wd, reuse=True)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            ctx.jv(th, vd, reuse=True, out=jv)
+            ctx.jhw(th, wd, reuse=True, out=g)
+        torch.cuda.synchronize()
+        pair_ms = 1e3 * (time.perf_counter() - t0) / 10
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        nq = ctx.readout_terms()
+        flop = 8.0 * nq * prob.n_tr * prob.nx * prob.n_read
+        kern = {k: {"launches": n, "avg_ms": ms / n} for k, (n, ms) in prof.items() if n}
+        for k in ("xgemm_fwd", "xgemm_adj"):
+            if k in kern:
+                ach = flop / (kern[k]["avg_ms"] * 1e-3) / 1e12
+                kern[k].update({"algorithmic_tflops": ach, "mfma_tflops_issued": 3 * ach,
+                                "peak_tflops": BF16_MFMA_PEAK_TFLOPS, "frac": 3 * ach / BF16_MFMA_PEAK_TFLOPS})
+        out[name] = {"terms": nq, "gn_step_ms": step_ms, "pairs_per_s_gn": n_cg * 1e3 / step_ms,
+                     "pair_cached_ms": pair_ms, "kernels_per_pair": kern, "param_mask": pm,
+                     "gn_report_last": rep.as_dict()}
+        ctx.close()
     return out
 
 
@@ -489,6 +566,8 @@ def main():
     ctx.close()
     if not args.no_noncartesian:
         out["noncartesian"] = noncartesian(torch, work)
+    if not args.no_readout_dynamics:
+        out["readout_dynamics"] = readout_dynamics(torch, work, args.n_cg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.n_cg)
     print(json.dumps(out), flush=True)

@@ -225,8 +225,8 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
     }
 }
 
-// Adjoint term sums: one thread per voxel (256-voxel blocks) and TR chunk;
-// per TR the sums V and V' over the terms (the voxel's power coefficients
+// Adjoint term sums: one thread per pair of voxels of a column and TR chunk;
+// per TR the sums V and V' over the terms (each voxel's power coefficients
 // held in registers across its TRs), then the chunk partials A_p
 // in the layout the gradient assembly reads ([chunk][pl planes][nv], pl = 8,
 // or 10 with Delta B0 fitted; NTR = 1 writes the m pair only, 2 planes, for
@@ -235,7 +235,13 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
 // Measured at 224 x 224, 1120 TRs, 24 terms (per J^H w): the Horner form
 // 0.83 ms; the power coefficients in registers with the term loads batched
 // (two waves per SIMD) 0.80; with a tile of 64 columns x 4 rows per block
-// for cache reuse of W 0.92; double-buffered term loads need 256 registers.
+// for cache reuse of W 0.92; double-buffered term loads need 256 registers;
+// two voxels of a column per thread, sharing each TR's term loads, 0.59.
+// Voxels per thread of the adjoint (rows iy, iy + hy, ... of one column):
+// two while each voxel's coefficients and the loaded terms fit the registers.
+template <int NQ>
+constexpr int rd_adj_rows() { return NQ <= 24 ? 2 : 1; }
+
 template <int NTR, int NQ, typename TT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void rd_adj_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
                                                      const uint8_t* __restrict__ mask, const float* __restrict__ db0,
@@ -246,34 +252,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 {
     const bool f5 = NTR >= 3 && fit;
     const int pl = NTR == 1 ? 2 : (f5 ? 10 : 8);   // planes per chunk
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    // A thread takes rows iy, iy + hy, ... of column ix: they read the same
+    // term values W_q[n][ix], loaded once per TR for all of them.
+    constexpr int R = rd_adj_rows<NQ>();
+    const int hy = (ny + R - 1) / R;
+    const int jp = blockIdx.x * blockDim.x + threadIdx.x;
     const int chunk = blockIdx.y;
-    if (j >= nv) return;
-    float* dst = apart + (size_t)chunk * pl * nv + j;
-    const bool on = mask == nullptr || mask[j] != 0;
-    if (!on) {
-#pragma unroll
-        for (int p = 0; p < 2 * NTR; ++p) dst[(size_t)p * nv] = 0.f;
-        if (f5) dst[(size_t)8 * nv] = dst[(size_t)9 * nv] = 0.f;
-        return;
-    }
-    const int ix = j % nx, iy = j / nx;
-    const RdVoxel vx = rd_voxel(theta, db0, db0_unit, nv, j, te, tmax);
+    if (jp >= hy * nx) return;
+    const int ix = jp % nx, iy0 = jp / nx;
     const int n0 = chunk * n_per_chunk, n1 = min(T, n0 + n_per_chunk);
     const size_t plane = (size_t)T * nv, wplane = (size_t)T * nx;
-    // The voxel's coefficients, fixed over its TRs: conj(L)^q and, for the
-    // ln T2 / Delta B0 share, q conj(L)^(q-1).
-    float2 Pc[NQ], Qc[NQ];
-    Pc[0] = make_float2(1.f, 0.f);
-    Qc[0] = make_float2(0.f, 0.f);
+    int jv[R], iyv[R];
+    bool on[R];
+    RdVoxel vx[R];
+    // Each voxel's coefficients, fixed over its TRs: conj(L)^q.
+    float2 Pc[R][NQ];
+    float2 A[R][NTR], At[R], Af[R];
 #pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-        Pc[q] = cmul(Pc[q - 1], make_float2(vx.L.x, -vx.L.y));
-        Qc[q] = make_float2((float)q * Pc[q - 1].x, (float)q * Pc[q - 1].y);
+    for (int r = 0; r < R; ++r) {
+        iyv[r] = iy0 + r * hy;
+        jv[r] = iyv[r] < ny ? iyv[r] * nx + ix : -1;
+        on[r] = jv[r] >= 0 && (mask == nullptr || mask[jv[r]] != 0);
+        vx[r] = rd_voxel(theta, db0, db0_unit, nv, on[r] ? jv[r] : jp % nv, te, tmax);
+        Pc[r][0] = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) Pc[r][q] = cmul(Pc[r][q - 1], make_float2(vx[r].L.x, -vx[r].L.y));
+#pragma unroll
+        for (int p = 0; p < NTR; ++p) A[r][p] = make_float2(0.f, 0.f);
+        At[r] = Af[r] = make_float2(0.f, 0.f);
     }
-    float2 A[NTR], At = make_float2(0.f, 0.f), Af = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int p = 0; p < NTR; ++p) A[p] = make_float2(0.f, 0.f);
     for (int n = n0; n < n1; ++n) {
         const float2* w = W + (size_t)n * nx + ix;
         // V = sum_q conj(L)^q W_q, V' = sum_q q conj(L)^(q-1) W_q; the TR's
@@ -281,45 +288,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         float2 wv[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) wv[q] = w[(size_t)q * wplane];
-        float2 V = wv[0], Vt = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            cmac(V, wv[q], Pc[q]);
-            if constexpr (NTR >= 3) cmac(Vt, wv[q], Qc[q]);
-        }
-        const float2 ec = cmul(eytab[(size_t)n * ny + iy], vx.c);   // c Ey
-        V = cmulconj(ec, V);
-        const TT* b = trains + (size_t)n * nv + j;
+        for (int r = 0; r < R; ++r) {
+            if (!on[r]) continue;
+            float2 V = wv[0], Vt = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int p = 0; p < NTR; ++p) {
-            const float m = (float)b[p * plane];
-            A[p].x = fmaf(m, V.x, A[p].x);
-            A[p].y = fmaf(m, V.y, A[p].y);
-        }
-        if constexpr (NTR >= 3) {
-            Vt = cmulconj(ec, Vt);
-            const float mu = (float)b[0], m0 = mu * vx.r2t;
-            At.x = fmaf(m0, Vt.x, At.x);
-            At.y = fmaf(m0, Vt.y, At.y);
-            if (f5) {
-                Af.x = fmaf(mu, fmaf(te, V.x, tmax * Vt.x), Af.x);
-                Af.y = fmaf(mu, fmaf(te, V.y, tmax * Vt.y), Af.y);
+            for (int q = 1; q < NQ; ++q) {
+                cmac(V, wv[q], Pc[r][q]);
+                if constexpr (NTR >= 3)
+                    cmac(Vt, make_float2((float)q * wv[q].x, (float)q * wv[q].y), Pc[r][q - 1]);
+            }
+            const float2 ec = cmul(eytab[(size_t)n * ny + iyv[r]], vx[r].c);   // c Ey
+            V = cmulconj(ec, V);
+            const TT* b = trains + (size_t)n * nv + jv[r];
+#pragma unroll
+            for (int p = 0; p < NTR; ++p) {
+                const float m = (float)b[p * plane];
+                A[r][p].x = fmaf(m, V.x, A[r][p].x);
+                A[r][p].y = fmaf(m, V.y, A[r][p].y);
+            }
+            if constexpr (NTR >= 3) {
+                Vt = cmulconj(ec, Vt);
+                const float mu = (float)b[0], m0 = mu * vx[r].r2t;
+                At[r].x = fmaf(m0, Vt.x, At[r].x);
+                At[r].y = fmaf(m0, Vt.y, At[r].y);
+                if (f5) {
+                    Af[r].x = fmaf(mu, fmaf(te, V.x, tmax * Vt.x), Af[r].x);
+                    Af[r].y = fmaf(mu, fmaf(te, V.y, tmax * Vt.y), Af[r].y);
+                }
             }
         }
     }
-    if constexpr (NTR >= 3) {
-        A[2].x += At.x;   // the readout decay's share of the ln T2 column
-        A[2].y += At.y;
-    }
 #pragma unroll
-    for (int p = 0; p < NTR; ++p) {
-        dst[(size_t)(2 * p) * nv] = A[p].x;
-        dst[(size_t)(2 * p + 1) * nv] = A[p].y;
-    }
-    if (f5) {   // times 2 pi i db0_unit
-        const float k = kTwoPi * db0_unit;
-        dst[(size_t)8 * nv] = -k * Af.y;
-        dst[(size_t)9 * nv] = k * Af.x;
+    for (int r = 0; r < R; ++r) {
+        if (jv[r] < 0) continue;
+        float* dst = apart + (size_t)chunk * pl * nv + jv[r];
+        if constexpr (NTR >= 3) {
+            A[r][2].x += At[r].x;   // the readout decay's share of the ln T2 column
+            A[r][2].y += At[r].y;
+        }
+#pragma unroll
+        for (int p = 0; p < NTR; ++p) {   // zeros for a masked voxel
+            dst[(size_t)(2 * p) * nv] = A[r][p].x;
+            dst[(size_t)(2 * p + 1) * nv] = A[r][p].y;
+        }
+        if (f5) {   // times 2 pi i db0_unit
+            const float k = kTwoPi * db0_unit;
+            dst[(size_t)8 * nv] = -k * Af[r].y;
+            dst[(size_t)9 * nv] = k * Af[r].x;
+        }
     }
 }
 
@@ -350,7 +367,8 @@ hipError_t adj_q(const Dims& d, int ntr, int chunks, const TT* trains, const flo
 {
     const int per = ceil_div(d.T, chunks);
     if (chunks < 1 || ceil_div(d.T, per) != chunks) return hipErrorInvalidValue;
-    const dim3 grid(ceil_div(d.nv, 256), chunks);
+    constexpr int R = rd_adj_rows<NQ>();
+    const dim3 grid(ceil_div((d.ny + R - 1) / R * d.nx, 256), chunks);
     const int fit = d.np == 6;
 #define RD_ADJ(NT) rd_adj_kernel<NT, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, mask, db0, db0_unit, fit, eytab, W, \
                                                                  apart, d.nx, d.ny, d.nv, d.T, per, te, tmax)

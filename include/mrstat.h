@@ -215,9 +215,11 @@ mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
  * and |db0| <= max_abs_db0_hz; every product then streams the trains once per
  * term set and runs its x-GEMMs over all terms. GN and trust-region steps
  * refuse an ln T2 box below ln(min_t2_s) (MRSTAT_ERR_ARG); values of db0 or
- * T2 outside the bounds lose the stated accuracy. n_coils must be 1, nx <= 256,
- * n_read >= 2 (else MRSTAT_ERR_UNSUPPORTED / MRSTAT_ERR_SHAPE); the encoding
- * is Cartesian and the problem is validated as by mrstat_create. */
+ * T2 outside the bounds lose the stated accuracy. With coils (the maps of
+ * mrstat_bind) the term sums and x-GEMMs carry n_coils x terms rows.
+ * nx <= 256 and n_read >= 2 (else MRSTAT_ERR_SHAPE); a bound that no term
+ * count meets gives MRSTAT_ERR_UNSUPPORTED; the encoding is Cartesian and the
+ * problem is validated as by mrstat_create. */
 mrstat_status mrstat_create_readout(const mrstat_problem *p, double dwell_s, double min_t2_s,
                                     double max_abs_db0_hz, mrstat_ctx *out);
 

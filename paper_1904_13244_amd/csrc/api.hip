@@ -100,7 +100,7 @@ struct mrstat_ctx_s {
     float2* rdY() const { return at<float2>(L.rdY); }
     float2* rdw() const { return at<float2>(L.rdw); }
     float2* rdW() const { return at<float2>(L.rdW); }
-    Dims rd_dims() const { Dims q = d; q.C = rd_nq; return q; }   // the terms as rows of the x-GEMMs
+    Dims rd_dims() const { Dims q = d; q.C = rd_nq * d.C; return q; }   // coils x terms as rows of the x-GEMMs
 };
 
 namespace {
@@ -161,7 +161,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     Layout L{};
     L.yp = make_yplan(d);
     Dims dq = d;
-    dq.C = rd_nq > 0 ? rd_nq : 1;
+    dq.C = rd_nq > 0 ? rd_nq * d.C : 1;
     L.rdp = make_yplan(dq);
     if (nc) {
         // The non-Cartesian adjoint's TR chunks replace the y-stage's in the
@@ -201,7 +201,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
     L.ay = take(nc ? T * d.nk * sizeof(double) : 0);
-    const size_t nq = rd_nq > 0 ? (size_t)rd_nq : 0;
+    const size_t nq = rd_nq > 0 ? (size_t)rd_nq * d.C : 0;   // rows per TR: coils x terms
     L.rdU = take(nq * T * d.nx * sizeof(float2));
     L.rdY = take(nq * T * d.nk * sizeof(float2));
     L.rdw = take(nq * T * d.nk * sizeof(float2));
@@ -354,7 +354,7 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
         // Readout dynamics: the term sums, their x-GEMM, the per-sample weighting.
         const int nq = ctx->rd_nq;
         HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
-                       launch_rd_fwd(d, nq, mode_y, trains, ctx->f16, theta, v, ctx->mask, ctx->rd_db0,
+                       launch_rd_fwd(d, nq, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask, ctx->rd_db0,
                                      ctx->db0_unit, ctx->deytab(), ctx->rdU(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(ctx->rd_dims(), ctx->L.rdp, ctx->enc, 2, ctx->rdU(),
                                                        ctx->dextab(), ctx->bfrag(0), nullptr, ctx->rdY(), nullptr,
@@ -407,7 +407,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
         HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                        ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
         HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
-                                                    ctx->mask, ctx->rd_db0, ctx->db0_unit, ctx->deytab(),
+                                                    ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit, ctx->deytab(),
                                                     ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
                                                           dir, dir ? ctx->red() : nullptr, s, step)));
@@ -526,7 +526,6 @@ mrstat_status mrstat_create_readout(const mrstat_problem* p, double dwell_s, dou
     if (!(std::isfinite(dwell_s) && dwell_s > 0.0) || !(std::isfinite(min_t2_s) && min_t2_s > 0.0) ||
         !(std::isfinite(max_abs_db0_hz) && max_abs_db0_hz >= 0.0))
         return fail(nullptr, MRSTAT_ERR_ARG, "dwell and min_t2 must be positive, max_abs_db0 >= 0");
-    if (p->n_coils != 1) return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout dynamics need one coil");
     if (p->nx > 256 || p->n_read < 2) return fail(nullptr, MRSTAT_ERR_SHAPE, "readout dynamics need nx <= 256, n_read >= 2");
     const double tmax = (double)(p->n_read / 2) * dwell_s;
     const double bound = (1.0 / min_t2_s + 2.0 * kPi * max_abs_db0_hz) * tmax;
@@ -1095,7 +1094,7 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
             HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                            ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
             HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, 1, p.adj_chunks, ctx->trains(), ctx->f16,
-                                                        d_theta, ctx->mask, ctx->rd_db0, ctx->db0_unit,
+                                                        d_theta, ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit,
                                                         ctx->deytab(), ctx->rdW(), ctx->apart(), ctx->st.te,
                                                         ctx->rd_tmax, s)));
         } else if (ctx->nc) {

@@ -49,8 +49,9 @@ struct SeqTimes {
 int rd_terms(double bound);
 // With d.np == 6 the off-resonance is theta row 5 times db0_unit Hz (db0 is
 // then not read) and J v gains that row's column.
+// Coils (coil != null, [C][nv]): U, Y, w_q and W_q hold C x nq rows, coil-major.
 hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
-                         const float* v, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float* v, const float2* coil, const uint8_t* mask, const float* db0, float db0_unit,
                          const float2* eytab, float2* U, float te, float tmax, hipStream_t s);
 hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
                              float2* out, double* red, int* nred, hipStream_t s);
@@ -58,8 +59,8 @@ hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* 
 // Chunk partials in the gradient assembly's layout; with d.np == 6 (ntr 3 or
 // 4) the Delta B0 pair follows as planes 8 and 9 of each chunk.
 hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
-                         const float* theta, const uint8_t* mask, const float* db0, float db0_unit,
-                         const float2* eytab, const float2* W, float* apart, float te, float tmax,
+                         const float* theta, const float2* coil, const uint8_t* mask, const float* db0,
+                         float db0_unit, const float2* eytab, const float2* W, float* apart, float te, float tmax,
                          hipStream_t s);
 
 // ---------------------------------------------------------------- balanced isochromat model

@@ -50,6 +50,11 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b)   // acc +
     acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
 }
 
+__device__ __forceinline__ float2 cfmaconj(float2 a, float2 b, float2 acc)   // acc + conj(a) * b
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(-a.y, b.x, acc.y)));
+}
+
 __device__ __forceinline__ float2 cmulconj(float2 a, float2 b)   // conj(a) * b
 {
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x));
@@ -86,7 +91,8 @@ __device__ __forceinline__ RdVoxel rd_voxel(const float* __restrict__ theta, con
 // part joins x, its tau part y.
 template <int MODE, int NQ, typename TT>
 __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
-                                                     const float* __restrict__ v, const uint8_t* __restrict__ mask,
+                                                     const float* __restrict__ v, const float2* __restrict__ coil,
+                                                     const uint8_t* __restrict__ mask,
                                                      const float* __restrict__ db0, float db0_unit, int fit,
                                                      const float2* __restrict__ eytab, float2* __restrict__ U,
                                                      int nx, int ny, int nv, int T, float te, float tmax)
@@ -95,6 +101,7 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
     const int ix = threadIdx.x;
     const bool colok = ix < nx;
     const int n0 = blockIdx.x * RD_NTB;
+    const int c = blockIdx.y;   // coil: its sums are rows c NQ .. c NQ + NQ - 1
     const size_t plane = (size_t)T * nv;
     float2 acc[RD_NTB][NQ];
 #pragma unroll
@@ -105,7 +112,8 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
         for (int iy = 0; iy < ny; ++iy) {
             const int j = iy * nx + ix;
             if (mask != nullptr && mask[j] == 0) continue;   // no contribution
-            const RdVoxel vx = rd_voxel(theta, db0, db0_unit, nv, j, te, tmax);
+            RdVoxel vx = rd_voxel(theta, db0, db0_unit, nv, j, te, tmax);
+            if (coil != nullptr) vx.c = cmul(vx.c, coil[(size_t)c * nv + j]);   // the coil weight joins c
             const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
             float nr = 0.f, ni = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f, cte = 0.f, ctau = 0.f;
             if constexpr (JV) {
@@ -162,28 +170,30 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
             const int n = n0 + t;
             if (n < T)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) U[((size_t)q * T + n) * nx + ix] = acc[t][q];
+                for (int q = 0; q < NQ; ++q) U[(((size_t)c * NQ + q) * T + n) * nx + ix] = acc[t][q];
         }
     }
 }
 
-// s[n,k] = sum_q (u_k^q / q!) Y_q[n,k]; MODE 0: out = data - s and FP64
+// s_c[n,k] = sum_q (u_k^q / q!) Y_cq[n,k]; MODE 0: out = data - s and FP64
 // partials of |out|^2 per block; 1: out = -s; 2: out = s.
 template <int MODE>
 __global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restrict__ Y, int nq, float dwell_u,
                                                          const float2* __restrict__ data, float2* __restrict__ out,
-                                                         double* __restrict__ red, int T, int nk)
+                                                         double* __restrict__ red, int C, int T, int nk)
 {
     const size_t count = (size_t)T * nk;
     double sq = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(i % nk);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < C * count; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = i / count, ii = i % count;
+        const int k = (int)(ii % nk);
         const float u = (float)(k - nk / 2) * dwell_u;
-        float2 s = Y[i];
+        const float2* yc = Y + c * nq * count + ii;
+        float2 s = yc[0];
         float cq = 1.f;
         for (int q = 1; q < nq; ++q) {
             cq *= u / (float)q;
-            const float2 y = Y[(size_t)q * count + i];
+            const float2 y = yc[(size_t)q * count];
             s.x = fmaf(cq, y.x, s.x);
             s.y = fmaf(cq, y.y, s.y);
         }
@@ -207,20 +217,22 @@ __global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restric
     }
 }
 
-// w_q[n,k] = (u_k^q / q!) w[n,k], q = 0 .. nq - 1.
+// w_cq[n,k] = (u_k^q / q!) w_c[n,k], q = 0 .. nq - 1.
 __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict__ w, float2* __restrict__ wq, int nq,
-                                                        float dwell_u, int T, int nk)
+                                                        float dwell_u, int C, int T, int nk)
 {
     const size_t count = (size_t)T * nk;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(i % nk);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < C * count; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = i / count, ii = i % count;
+        const int k = (int)(ii % nk);
         const float u = (float)(k - nk / 2) * dwell_u;
         const float2 x = w[i];
+        float2* wc = wq + c * nq * count + ii;
         float cq = 1.f;
-        wq[i] = x;
+        wc[0] = x;
         for (int q = 1; q < nq; ++q) {
             cq *= u / (float)q;
-            wq[(size_t)q * count + i] = make_float2(cq * x.x, cq * x.y);
+            wc[(size_t)q * count] = make_float2(cq * x.x, cq * x.y);
         }
     }
 }
@@ -242,12 +254,13 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
 template <int NQ>
 constexpr int rd_adj_rows() { return NQ <= 24 ? 2 : 1; }
 
-template <int NTR, int NQ, typename TT>
+template <int NTR, int NQ, typename TT, bool MC>   // MC: coil maps (C >= 1 weighted coils)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void rd_adj_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
+                                                     const float2* __restrict__ coil,
                                                      const uint8_t* __restrict__ mask, const float* __restrict__ db0,
                                                      float db0_unit, int fit, const float2* __restrict__ eytab,
                                                      const float2* __restrict__ W, float* __restrict__ apart,
-                                                     int nx, int ny, int nv, int T, int n_per_chunk, float te,
+                                                     int nx, int ny, int nv, int T, int C, int n_per_chunk, float te,
                                                      float tmax)
 {
     const bool f5 = NTR >= 3 && fit;
@@ -281,42 +294,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         for (int p = 0; p < NTR; ++p) A[r][p] = make_float2(0.f, 0.f);
         At[r] = Af[r] = make_float2(0.f, 0.f);
     }
+    // Per TR and voxel: A_p += mu_p conj(c Ey) V, the ln T2 share with V' and
+    // the Delta B0 pair with both (V, V' already summed over the coils).
+    auto accumulate = [&](int n, int r, float2 V, float2 Vt) {
+        const float2 ec = cmul(eytab[(size_t)n * ny + iyv[r]], vx[r].c);   // c Ey
+        V = cmulconj(ec, V);
+        const TT* b = trains + (size_t)n * nv + jv[r];
+#pragma unroll
+        for (int p = 0; p < NTR; ++p) {
+            const float m = (float)b[p * plane];
+            A[r][p].x = fmaf(m, V.x, A[r][p].x);
+            A[r][p].y = fmaf(m, V.y, A[r][p].y);
+        }
+        if constexpr (NTR >= 3) {
+            Vt = cmulconj(ec, Vt);
+            const float mu = (float)b[0], m0 = mu * vx[r].r2t;
+            At[r].x = fmaf(m0, Vt.x, At[r].x);
+            At[r].y = fmaf(m0, Vt.y, At[r].y);
+            if (f5) {
+                Af[r].x = fmaf(mu, fmaf(te, V.x, tmax * Vt.x), Af[r].x);
+                Af[r].y = fmaf(mu, fmaf(te, V.y, tmax * Vt.y), Af[r].y);
+            }
+        }
+    };
+    // V = sum_q conj(L)^q W_q and V' = sum_q q conj(L)^(q-1) W_q of one coil,
+    // from its TR's term values loaded together (all in flight at once).
+    auto term_sums = [&](const float2 (&wv)[NQ], int r, float2& V, float2& Vt) {
+        V = wv[0];
+        Vt = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            cmac(V, wv[q], Pc[r][q]);
+            if constexpr (NTR >= 3) cmac(Vt, make_float2((float)q * wv[q].x, (float)q * wv[q].y), Pc[r][q - 1]);
+        }
+    };
     for (int n = n0; n < n1; ++n) {
-        const float2* w = W + (size_t)n * nx + ix;
-        // V = sum_q conj(L)^q W_q, V' = sum_q q conj(L)^(q-1) W_q; the TR's
-        // term values are loaded together first (all in flight at once).
         float2 wv[NQ];
+        if constexpr (!MC) {
+            const float2* w = W + (size_t)n * nx + ix;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) wv[q] = w[(size_t)q * wplane];
+            for (int q = 0; q < NQ; ++q) wv[q] = w[(size_t)q * wplane];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!on[r]) continue;
-            float2 V = wv[0], Vt = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int q = 1; q < NQ; ++q) {
-                cmac(V, wv[q], Pc[r][q]);
-                if constexpr (NTR >= 3)
-                    cmac(Vt, make_float2((float)q * wv[q].x, (float)q * wv[q].y), Pc[r][q - 1]);
+            for (int r = 0; r < R; ++r) {
+                if (!on[r]) continue;
+                float2 V, Vt;
+                term_sums(wv, r, V, Vt);
+                accumulate(n, r, V, Vt);
             }
-            const float2 ec = cmul(eytab[(size_t)n * ny + iyv[r]], vx[r].c);   // c Ey
-            V = cmulconj(ec, V);
-            const TT* b = trains + (size_t)n * nv + jv[r];
+        } else {
+            // Coils: V and V' weighted by conj(C_c) and summed over c first.
+            float2 V[R], Vt[R];
 #pragma unroll
-            for (int p = 0; p < NTR; ++p) {
-                const float m = (float)b[p * plane];
-                A[r][p].x = fmaf(m, V.x, A[r][p].x);
-                A[r][p].y = fmaf(m, V.y, A[r][p].y);
-            }
-            if constexpr (NTR >= 3) {
-                Vt = cmulconj(ec, Vt);
-                const float mu = (float)b[0], m0 = mu * vx[r].r2t;
-                At[r].x = fmaf(m0, Vt.x, At[r].x);
-                At[r].y = fmaf(m0, Vt.y, At[r].y);
-                if (f5) {
-                    Af[r].x = fmaf(mu, fmaf(te, V.x, tmax * Vt.x), Af[r].x);
-                    Af[r].y = fmaf(mu, fmaf(te, V.y, tmax * Vt.y), Af[r].y);
+            for (int r = 0; r < R; ++r) V[r] = Vt[r] = make_float2(0.f, 0.f);
+            for (int c = 0; c < C; ++c) {
+                const float2* w = W + (size_t)c * NQ * wplane + (size_t)n * nx + ix;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) wv[q] = w[(size_t)q * wplane];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (!on[r]) continue;
+                    float2 Vc, Vtc;
+                    term_sums(wv, r, Vc, Vtc);
+                    const float2 cw = coil[(size_t)c * nv + jv[r]];
+                    V[r] = cfmaconj(cw, Vc, V[r]);
+                    Vt[r] = cfmaconj(cw, Vtc, Vt[r]);
                 }
             }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (on[r]) accumulate(n, r, V[r], Vt[r]);
         }
     }
 #pragma unroll
@@ -341,15 +387,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 }
 
 template <int NQ, typename TT>
-hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, const float* v, const uint8_t* mask,
-                 const float* db0, float db0_unit, const float2* eytab, float2* U, float te, float tmax,
-                 hipStream_t s)
+hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, const float* v, const float2* coil,
+                 const uint8_t* mask, const float* db0, float db0_unit, const float2* eytab, float2* U, float te,
+                 float tmax, hipStream_t s)
 {
-    const int blocks = ceil_div(d.T, RD_NTB);
+    const dim3 grid(ceil_div(d.T, RD_NTB), d.C);
     const int fit = d.np == 6;
-#define RD_FWD(M)                                                                                           \
-    rd_fwd_kernel<M, NQ, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, db0, db0_unit, fit, eytab, U, d.nx, \
-                                                    d.ny, d.nv, d.T, te, tmax)
+#define RD_FWD(M)                                                                                                 \
+    rd_fwd_kernel<M, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, v, coil, mask, db0, db0_unit, fit, eytab, U, d.nx, \
+                                                  d.ny, d.nv, d.T, te, tmax)
     switch (mode) {
     case 0: RD_FWD(0); break;
     case 1: RD_FWD(1); break;
@@ -361,25 +407,35 @@ hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, 
 }
 
 template <int NQ, typename TT>
-hipError_t adj_q(const Dims& d, int ntr, int chunks, const TT* trains, const float* theta, const uint8_t* mask,
-                 const float* db0, float db0_unit, const float2* eytab, const float2* W, float* apart, float te,
-                 float tmax, hipStream_t s)
+hipError_t adj_q(const Dims& d, int ntr, int chunks, const TT* trains, const float* theta, const float2* coil,
+                 const uint8_t* mask, const float* db0, float db0_unit, const float2* eytab, const float2* W,
+                 float* apart, float te, float tmax, hipStream_t s)
 {
     const int per = ceil_div(d.T, chunks);
     if (chunks < 1 || ceil_div(d.T, per) != chunks) return hipErrorInvalidValue;
     constexpr int R = rd_adj_rows<NQ>();
     const dim3 grid(ceil_div((d.ny + R - 1) / R * d.nx, 256), chunks);
     const int fit = d.np == 6;
-#define RD_ADJ(NT) rd_adj_kernel<NT, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, mask, db0, db0_unit, fit, eytab, W, \
-                                                                 apart, d.nx, d.ny, d.nv, d.T, per, te, tmax)
-    if (ntr == 1)
-        RD_ADJ(1);
-    else if (ntr == 3)
-        RD_ADJ(3);
-    else if (ntr == 4)
-        RD_ADJ(4);
-    else
+    // Without coil maps there is one unweighted coil.
+    if (coil == nullptr && d.C != 1) return hipErrorInvalidValue;
+#define RD_ADJ(NT, MC) rd_adj_kernel<NT, NQ, TT, MC><<<grid, 256, 0, s>>>(trains, theta, coil, mask, db0, db0_unit, fit, \
+                                                                         eytab, W, apart, d.nx, d.ny, d.nv, d.T, d.C, \
+                                                                         per, te, tmax)
+#define RD_ADJ_NT(MC)         \
+    if (ntr == 1)             \
+        RD_ADJ(1, MC);        \
+    else if (ntr == 3)        \
+        RD_ADJ(3, MC);        \
+    else if (ntr == 4)        \
+        RD_ADJ(4, MC);        \
+    else                      \
         return hipErrorInvalidValue;
+    if (coil != nullptr) {
+        RD_ADJ_NT(true)
+    } else {
+        RD_ADJ_NT(false)
+    }
+#undef RD_ADJ_NT
 #undef RD_ADJ
     return hipGetLastError();
 }
@@ -423,17 +479,17 @@ static void rd_source(const Dims& d, const float* theta, const float*& db0, floa
 }
 
 hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
-                         const float* v, const uint8_t* mask, const float* db0, float db0_unit,
+                         const float* v, const float2* coil, const uint8_t* mask, const float* db0, float db0_unit,
                          const float2* eytab, float2* U, float te, float tmax, hipStream_t s)
 {
     if (d.nx > 256) return hipErrorInvalidValue;
     rd_source(d, theta, db0, db0_unit);
     if (f16) {
         const _Float16* tr = static_cast<const _Float16*>(trains);
-        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, db0_unit, eytab, U, te, tmax, s)))
+        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
     }
     const float* tr = static_cast<const float*>(trains);
-    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, mask, db0, db0_unit, eytab, U, te, tmax, s)))
+    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
 }
 
 hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
@@ -442,9 +498,9 @@ hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, f
     const int blocks = RED_BLOCKS;
     if (nred) *nred = blocks;
     switch (mode) {
-    case 0: rd_combine_kernel<0><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
-    case 1: rd_combine_kernel<1><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
-    case 2: rd_combine_kernel<2><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.T, d.nk); break;
+    case 0: rd_combine_kernel<0><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
+    case 1: rd_combine_kernel<1><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
+    case 2: rd_combine_kernel<2><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -452,23 +508,24 @@ hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, f
 
 hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s)
 {
-    rd_expand_kernel<<<RED_BLOCKS, 256, 0, s>>>(w, wq, nq, dwell_u, d.T, d.nk);
+    rd_expand_kernel<<<RED_BLOCKS, 256, 0, s>>>(w, wq, nq, dwell_u, d.C, d.T, d.nk);
     return hipGetLastError();
 }
 
 hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
-                         const float* theta, const uint8_t* mask, const float* db0, float db0_unit,
-                         const float2* eytab, const float2* W, float* apart, float te, float tmax,
+                         const float* theta, const float2* coil, const uint8_t* mask, const float* db0,
+                         float db0_unit, const float2* eytab, const float2* W, float* apart, float te, float tmax,
                          hipStream_t s)
 {
     rd_source(d, theta, db0, db0_unit);
     if (f16) {
         const _Float16* tr = static_cast<const _Float16*>(trains);
-        RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, db0_unit, eytab, W, apart, te, tmax,
-                                      s)))
+        RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, coil, mask, db0, db0_unit, eytab, W, apart, te,
+                                      tmax, s)))
     }
     const float* tr = static_cast<const float*>(trains);
-    RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, mask, db0, db0_unit, eytab, W, apart, te, tmax, s)))
+    RD_NQ_DISPATCH(nq, (adj_q<NQ>(d, ntr, chunks, tr, theta, coil, mask, db0, db0_unit, eytab, W, apart, te, tmax,
+                                  s)))
 }
 
 #undef RD_NQ_DISPATCH

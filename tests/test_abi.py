@@ -123,11 +123,11 @@ def test_readout_context_terms_and_refusals():
             B.mrstat_destroy(h)
         seen.add(want)
     assert seen == {8, 12, 16, 20, 24, 32}
-    # a readout too long for the expansion, more coils, wide images, bad bounds
+    # a readout too long for the expansion, wide images, bad bounds; coils are taken
     too_long = dataclasses.replace(I.shrink(base, n_read=448), dwell=1 / 85.6e3, rd_max_db0=600.0)
     assert _expected_terms(too_long) == 0 and _status(too_long) == B.ERR_UNSUPPORTED
     rd = dataclasses.replace(base, dwell=1 / 85.6e3)
-    assert _status(I.shrink(rd, n_coils=2)) == B.ERR_UNSUPPORTED
+    assert _status(I.shrink(rd, n_coils=2)) == B.OK                  # coils: terms x coils rows
     assert _status(I.shrink(rd, nx=300, n_read=600)) == B.ERR_SHAPE
     assert _status(dataclasses.replace(rd, rd_min_t2=0.0)) == B.ERR_ARG
     assert _status(dataclasses.replace(rd, rd_max_db0=-1.0)) == B.ERR_ARG

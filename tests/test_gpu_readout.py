@@ -10,7 +10,7 @@ and off-resonance bounds) and sums the terms in FP32, so the plain path's
 bar holds: 1e-5 relative for the residual (against ||d||), J v and each row
 of Re(J^H w) with FP32 trains and the FP32 x-stage; FP16 trains take the
 static path's 1e-3, the split-BF16 x-stage its 1e-4. The cases span the term
-counts 12, 16, 20 and 32, ragged tiles and a mask; a full-size case
+counts 12, 16, 20 and 32, ragged tiles, a mask and three coils; a full-size case
 (224 x 224, 1120 TRs, 448 samples, 24 terms) checks 160 masked-in voxels
 against the oracle's direct sum. Every input is seeded; every expected value
 comes from the oracle.
@@ -450,3 +450,68 @@ def test_bit5_needs_the_fit(torch_gpu):
         ctx.gn_step(thd, dd, 5, 0b111011, I.GN_LO, I.GN_HI)
     assert e.value.status == B.ERR_ARG
     ctx.close()
+
+
+def _coil_case(seed=71):
+    """24 x 20 image, 3 coils (Gaussian sensitivities with linear phases), 50
+    TRs of 64 samples at 85.6 kHz (12 terms), 80 % mask."""
+    rng = np.random.default_rng(seed)
+    prob = I.make_problem(24, 20, 50, 64, 8, n_coils=3, tr=0.008, te=0.004, flip_deg=I.flips_sin2_sweeps(50, 20),
+                          ky_line=rng.integers(0, 20, 50))
+    prob = dataclasses.replace(prob, dwell=1 / BW, db0=rng.uniform(-150.0, 150.0, prob.nv))
+    th = _maps(prob, rng, seed + 1)
+    mask = (rng.uniform(size=prob.nv) > 0.2).astype(np.uint8)
+    return prob, th, mask, I.coil_maps(24, 20, 3)
+
+
+@pytest.mark.parametrize("fit", [False, True])
+def test_coils_products_steps_and_rho_init(torch_gpu, oracle_lib, fit):
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    prob, th, mask, coil = _coil_case()
+    if fit:
+        unit = 1.0 / (2 * np.pi * prob.te)
+        th = np.vstack([th, (prob.db0 / unit)[None, :]]).astype(np.float32).astype(np.float64)
+        prob = dataclasses.replace(prob, db0=None, db0_unit=unit)
+    ctx = Context(prob, coil=_dev(torch, coil, torch.complex64), mask=_dev(torch, mask, torch.uint8))
+    assert ctx.readout_terms() == 12
+    ora = oracle_lib.epg(prob, th)
+    s = oracle_lib.signal(prob, th, ora, coil=coil, mask=mask)
+    n = I.unit_noise(prob)
+    d = s + n * (np.linalg.norm(s) / (50.0 * np.linalg.norm(n)))
+    th1 = th.copy()
+    th1[0] += 0.05
+    th1 = th1.astype(np.float32).astype(np.float64)
+    _, r_ref = oracle_lib.residual(prob, th1, d, coil=coil, mask=mask)
+    dd = _dev(torch, d, torch.complex64)
+    _, r = ctx.residual(_dev(torch, th1, torch.float32), dd)
+    e_r = float(np.linalg.norm(r.cpu().numpy().astype(np.complex128) - r_ref) / np.linalg.norm(d))
+    v, w = I.probe_vectors(prob)
+    thd = _dev(torch, th, torch.float32)
+    ctx.linearise(thd)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
+    ref = oracle_lib.jhw(prob, th, ora, w, coil=coil, mask=mask)
+    e_rows = [_rel(jhw[q], ref[q]) for q in range(th.shape[0])]
+    print(f"\n  [readout, 3 coils, Delta B0 {'fitted' if fit else 'map'}] residual {e_r:.2e} jv {e_jv:.2e} "
+          f"jhw rows {['%.1e' % e for e in e_rows]}", flush=True)
+    assert max([e_r, e_jv] + e_rows) <= TOL
+    # one GN step from a perturbed start, and the rho initialisation
+    rng = np.random.default_rng(72)
+    th0 = th.copy()
+    th0[:2] += 0.05 * rng.standard_normal((2, prob.nv))
+    th0 = th0.astype(np.float32).astype(np.float64)
+    pm = 0b111011 if fit else 0b11011
+    th_o, rep_o = oracle_lib.gn_step(prob, th0, d, n_cg=10, param_mask=pm, lo=I.GN_LO, hi=I.GN_HI,
+                                     coil=coil, mask=mask)
+    th_g = _dev(torch, th0, torch.float32)
+    rep = ctx.gn_step(th_g, dd, 10, pm, I.GN_LO, I.GN_HI)
+    e = _rel(th_g.cpu().numpy().astype(np.float64), th_o)
+    ref = oracle_lib.rho_init(prob, th0, d, n_iter=5, coil=coil, mask=mask)
+    got = ctx.rho_init(_dev(torch, th0, torch.float32), dd, n_iter=5).cpu().numpy().astype(np.float64)
+    e_rho = _rel(got[3:5], ref[3:5])
+    ctx.close()
+    print(f"  [gn] t {rep.t}/{rep_o.t} cg {rep.cg_iters}/{rep_o.cg_iters} theta {e:.2e}; rho init {e_rho:.2e}",
+          flush=True)
+    assert rep.t == rep_o.t and rep.cg_iters == rep_o.cg_iters and e <= TOL and e_rho <= TOL

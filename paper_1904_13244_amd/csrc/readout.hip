@@ -36,7 +36,8 @@ namespace {
 constexpr float kTwoPi = 6.28318530717958647692f;
 // TRs per forward block. Measured at 224 x 224, 1120 TRs, 24 terms (J v):
 // the power chain per voxel and TR 0.67 ms; powers shared by the block's TRs
-// 0.55 with 2 TRs, 0.57 with 1.
+// 0.55 with 2 TRs, 0.57 with 1; the next row's inputs loaded while a row is
+// summed 0.75 (221 registers: two waves per SIMD instead of three).
 constexpr int RD_NTB = 2;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)

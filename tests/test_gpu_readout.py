@@ -515,3 +515,37 @@ def test_coils_products_steps_and_rho_init(torch_gpu, oracle_lib, fit):
     print(f"  [gn] t {rep.t}/{rep_o.t} cg {rep.cg_iters}/{rep_o.cg_iters} theta {e:.2e}; rho init {e_rho:.2e}",
           flush=True)
     assert rep.t == rep_o.t and rep.cg_iters == rep_o.cg_iters and e <= TOL and e_rho <= TOL
+
+
+def test_expansion_at_its_bounds(torch_gpu, oracle_lib):
+    """T2 = 5 ms in every voxel and |Delta B0| = 200 Hz (the context's bounds)
+    over a 448-sample readout at 85.6 kHz (|lambda| tau_max = 3.8, 24 terms):
+    the products still meet the plain path's bar against the oracle."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    rng = np.random.default_rng(81)
+    prob = I.make_problem(32, 16, 40, 448, 8, tr=0.008, te=0.004, flip_deg=I.flips_sin2_sweeps(40, 16),
+                          ky_line=rng.integers(0, 16, 40))
+    db0 = np.where(rng.uniform(size=prob.nv) < 0.5, -200.0, 200.0)
+    prob = dataclasses.replace(prob, dwell=1 / BW, db0=db0)
+    th = I.iid_maps(prob.nv, seed=82, b1=rng.uniform(0.8, 1.2, prob.nv))
+    th[1] = np.log(0.005)
+    th = th.astype(np.float32).astype(np.float64)
+    ctx = Context(prob)
+    assert ctx.readout_terms() == 24
+    ora = oracle_lib.epg(prob, th)
+    s = oracle_lib.signal(prob, th, ora)
+    zeros = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+    thd = _dev(torch, th, torch.float32)
+    _, r = ctx.residual(thd, zeros)
+    e_s = _rel(-r.cpu().numpy().astype(np.complex128), s)
+    v, w = I.probe_vectors(prob)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    ctx.close()
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v))
+    ref = oracle_lib.jhw(prob, th, ora, w)
+    e_rows = [_rel(jhw[q], ref[q]) for q in range(5)]
+    print(f"\n  [expansion at its bounds] signal {e_s:.2e} jv {e_jv:.2e} jhw rows {['%.1e' % e for e in e_rows]}",
+          flush=True)
+    assert max([e_s, e_jv] + e_rows) <= TOL

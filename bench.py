@@ -107,6 +107,8 @@ def parse():
                     help="skip the B1-known (three-train) variant")
     ap.add_argument("--no-noncartesian", action="store_true",
                     help="skip the golden-angle radial contraction measurement")
+    ap.add_argument("--no-isochromats", action="store_true",
+                    help="skip the balanced isochromat model's linearisation measurement")
     ap.add_argument("--no-readout-dynamics", action="store_true",
                     help="skip the readout-dynamics (T2 decay and off-resonance per sample) measurement")
     ap.add_argument("--calib-copy", action="store_true",
@@ -214,10 +216,32 @@ def cpu_baseline(work, n_cg, n_vox=16384, n_pairs=6, n_vox_1t=1024):
             "one_thread": one, "host": _host_cpu()}
 
 
+def oracle_pair_scaled(prob_small, theta_small, nv_full):
+    """The oracle's J v + J^H w pair on a smaller image with the same sequence,
+    readout and encoding kind, scaled to the full image by voxel count (its
+    direct sums cost T x nk x Nv per product); trains are constants (the cost
+    does not depend on their values). Returns (seconds per pair, sample text)."""
+    import oracle
+    from paper_1904_13244_amd import inputs as I
+
+    oracle.build(force=False)
+    npar = I.n_params(prob_small)
+    trains = np.full((4, prob_small.n_tr, prob_small.nv), 1e-3 + 1e-3j, dtype=np.complex128)
+    v, w = I.probe_vectors(prob_small)
+    t0 = time.perf_counter()
+    y = oracle.jv(prob_small, theta_small[:npar], trains, v)
+    oracle.jhw(prob_small, theta_small[:npar], trains, y)
+    t = time.perf_counter() - t0
+    scale = nv_full / prob_small.nv
+    return t * scale, (f"FP64 oracle, one Jv + J^H w pair on a {prob_small.nx}x{prob_small.ny} image with the "
+                       f"same sequence and readout ({t:.2f} s on {oracle.num_threads()} threads), scaled "
+                       f"x{scale:.0f} by voxel count")
+
+
 FP32_MFMA_PEAK_TFLOPS = 157.3    # dense FP32 matrix
 
 
-def noncartesian(torch, work, reps=5):
+def noncartesian(torch, work, reps=5, with_oracle=True):
     """Golden-angle radial sampling of the same workload (one spoke of 448
     samples per TR, 1120 spokes): the voxel x sample contraction on the
     matrix cores (FP32 and split-BF16) for a cached J v + J^H w pair, timed
@@ -269,10 +293,15 @@ def noncartesian(torch, work, reps=5):
                       "frac": passes * ach / peak}
         out[name] = res
     ctx.close()
+    if with_oracle:
+        small = I.make_problem(32, 32, prob.n_tr, prob.n_read, prob.n_states, flip_deg=prob.flip_deg)
+        small = dataclasses.replace(small, traj=I.radial_golden(prob.n_tr, prob.n_read, 32, 32))
+        t, sample = oracle_pair_scaled(small, I.iid_maps(small.nv), prob.nv)
+        out["cpu_baseline"] = {"value": 1.0 / t, "unit": "pairs/s", "kind": "oracle", "sample": sample}
     return out
 
 
-def readout_dynamics(torch, work, n_cg, steps=3):
+def readout_dynamics(torch, work, n_cg, steps=3, with_oracle=True):
     """The benchmark workload with T2 decay and off-resonance during every
     readout (448 samples at 85.6 kHz: 24 expansion terms for T2 >= 5 ms and
     |Delta B0| <= 200 Hz) and a smooth +-150 Hz off-resonance field: GN steps
@@ -349,6 +378,57 @@ def readout_dynamics(torch, work, n_cg, steps=3):
                      "pair_cached_ms": pair_ms, "kernels_per_pair": kern, "param_mask": pm,
                      "gn_report_last": rep.as_dict()}
         ctx.close()
+    if with_oracle:
+        small = I.make_problem(32, 32, p0.n_tr, p0.n_read, p0.n_states, flip_deg=p0.flip_deg)
+        yy, xx = np.meshgrid(np.linspace(-1, 1, 32), np.linspace(-1, 1, 32), indexing="ij")
+        small = dataclasses.replace(small, dwell=1 / 85.6e3,
+                                    db0=(150.0 * (0.6 * xx + 0.3 * yy * yy - 0.1 * xx * yy)).reshape(-1))
+        t, sample = oracle_pair_scaled(small, I.iid_maps(small.nv), p0.nv)
+        out["cpu_baseline"] = {"value": 1.0 / t, "unit": "pairs/s", "kind": "oracle", "sample": sample}
+    return out
+
+
+def isochromats(torch, work, n_iso=16, reps=3, with_oracle=True):
+    """The paper's balanced isochromat model (16 isochromats over the slice
+    profile, RF phases alternating 0 / pi) on the benchmark workload: the
+    linearisation (m and its three derivatives for every voxel and TR) on the
+    GPU, and the oracle's on a voxel sample scaled to all voxels. Work unit:
+    voxel-isochromat-TR updates."""
+    import dataclasses
+
+    from paper_1904_13244_amd import inputs as I
+    from paper_1904_13244_amd.binding import Context
+
+    prob = dataclasses.replace(work.problem, rf_phase=I.balanced_phases(work.problem.n_tr),
+                               iso=I.slice_profile_gaussian(n_iso))
+    ctx = Context(prob)
+    th = torch.as_tensor(np.ascontiguousarray(work.theta)).to("cuda", torch.float32)
+    ctx.linearise(th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.linearise(th)
+    torch.cuda.synchronize()
+    t_gpu = (time.perf_counter() - t0) / reps
+    ctx.close()
+    units = float(prob.nv) * n_iso * prob.n_tr
+    out = {"workload": (f"224x224, 1120 TRs, balanced sequence, {n_iso} isochromats per voxel (Gaussian slice "
+                        "profile), four trains"),
+           "linearise_ms": 1e3 * t_gpu, "voxel_isochromat_trs_per_s": units / t_gpu}
+    if with_oracle:
+        import oracle
+        oracle.build(force=False)
+        S = 4096
+        sel = np.linspace(0, prob.nv - 1, S).astype(np.int64)
+        sub = dataclasses.replace(I.make_problem(S, 1, prob.n_tr, S, prob.n_states, tr=prob.tr, te=prob.te,
+                                                 flip_deg=prob.flip_deg, rf_phase=prob.rf_phase), iso=prob.iso)
+        t0 = time.perf_counter()
+        oracle.epg(sub, work.theta[:, sel])
+        t = (time.perf_counter() - t0) * prob.nv / S
+        out["cpu_baseline"] = {"value": units / t, "unit": "voxel-isochromat-TRs/s", "kind": "oracle",
+                               "sample": (f"FP64 oracle isochromat linearisation of {S} voxels "
+                                          f"({t * S / prob.nv:.2f} s on {oracle.num_threads()} threads), scaled to "
+                                          f"{prob.nv} voxels: {t:.1f} s")}
     return out
 
 
@@ -573,9 +653,11 @@ def main():
         out["surrogate"] = surr_info
     ctx.close()
     if not args.no_noncartesian:
-        out["noncartesian"] = noncartesian(torch, work)
+        out["noncartesian"] = noncartesian(torch, work, with_oracle=not args.no_cpu_baseline)
     if not args.no_readout_dynamics:
-        out["readout_dynamics"] = readout_dynamics(torch, work, args.n_cg)
+        out["readout_dynamics"] = readout_dynamics(torch, work, args.n_cg, with_oracle=not args.no_cpu_baseline)
+    if not args.no_isochromats:
+        out["isochromats"] = isochromats(torch, work, with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.n_cg)
     print(json.dumps(out), flush=True)

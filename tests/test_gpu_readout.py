@@ -67,10 +67,10 @@ def _case(name):
                               rf_phase=np.pi * rng.integers(0, 2, T), t_inv=0.02, tr=0.0075,
                               te=0.003, ky_line=rng.integers(0, 29, T))
         dwell, seed = 1 / BW, 54
-    elif name == "half_bandwidth":   # 20 terms
+    elif name == "half_bandwidth":   # 20 terms; an odd TR count (a forward block's second TR unused)
         rng = np.random.default_rng(55)
-        prob = I.make_problem(24, 20, 50, 150, 8, tr=0.01, te=0.005, flip_deg=I.flips_sin2_sweeps(50, 20),
-                              ky_line=rng.integers(0, 20, 50))
+        prob = I.make_problem(24, 20, 51, 150, 8, tr=0.01, te=0.005, flip_deg=I.flips_sin2_sweeps(51, 20),
+                              ky_line=rng.integers(0, 20, 51))
         dwell, seed = 2 / BW, 56
     elif name == "quarter_bandwidth":   # 32 terms
         rng = np.random.default_rng(57)

@@ -14,16 +14,20 @@
 //     U_q[n,ix] = sum_iy Ey[n,iy] c_j (x[n,j] L_j^q + y[n,j] q L_j^(q-1)),
 // where x is the voxel weight of the static model and y the readout decay's
 // share of the ln T2 column (d/dlnT2 exp(-tau/T2) = (tau/T2) exp(-tau/T2):
-// y = i rho mu (tau_max / T2) v_lnT2, multiplied by u in the sum). The x-stage
-// of each term is the library's x-GEMM with the NQ terms as rows; this file
-// holds the term-wise y-stages and the per-sample weighting.
+// y = i rho mu (tau_max / T2) v_lnT2, multiplied by u in the sum). With Delta
+// B0 fitted (theta row 5, in units of db0_unit Hz) its column's factor
+// -2 pi i db0_unit (TE + tau) splits the same way: the TE part joins x, the
+// tau part y. With coils each coil's weight joins c_j. The x-stage of each
+// term is the library's x-GEMM with coils x terms as rows; this file holds the
+// term-wise y-stages and the per-sample weighting.
 //   forward:  rd_fwd_kernel (U_q) -> x-GEMM (Y_q = Ex U_q) -> rd_combine_kernel
 //             (s = sum_q u^q/q! Y_q, then r = d - s, -s or s);
 //   adjoint:  rd_expand_kernel (w_q = u^q/q! w) -> adjoint x-GEMM
 //             (W_q = Ex^H w_q) -> rd_adj_kernel: per voxel and TR
 //             V = sum_q conj(L)^q W_q, V' = sum_q q conj(L)^(q-1) W_q,
 //             A_p += mu_p conj(c Ey) V, A_lnT2 += (tau_max/T2) mu_0 conj(c Ey) V'
-//             (the exact transpose of the truncated forward).
+//             (V, V' summed over the coils with conj(C_c); the exact transpose
+//             of the truncated forward).
 // FP32 arithmetic; the sums of the expansion are in the dimensionless u and L
 // so no term over- or underflows.
 #include "mrstat_internal.h"

@@ -549,3 +549,33 @@ def test_expansion_at_its_bounds(torch_gpu, oracle_lib):
     print(f"\n  [expansion at its bounds] signal {e_s:.2e} jv {e_jv:.2e} jhw rows {['%.1e' % e for e in e_rows]}",
           flush=True)
     assert max([e_s, e_jv] + e_rows) <= TOL
+
+
+def test_balanced_isochromat_model_with_readout_decay(torch_gpu, oracle_lib):
+    """The balanced isochromat model (11 isochromats, RF phases 0 / pi) with T2
+    decay during each readout (no off-resonance map: the balanced model takes
+    none): products against the oracle's model."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    rng = np.random.default_rng(91)
+    T, ny = 60, 18
+    prob = I.make_problem(20, ny, T, 64, 8, tr=0.008, te=0.004, t_inv=0.01, rf_phase=I.balanced_phases(T),
+                          flip_deg=I.flips_sin2_sweeps(T, ny), ky_line=rng.integers(0, ny, T))
+    prob = dataclasses.replace(prob, iso=I.slice_profile_gaussian(11), dwell=4 / BW)
+    th = _maps(prob, rng, 92)
+    ctx = Context(prob)
+    ora = oracle_lib.epg(prob, th)
+    thd = _dev(torch, th, torch.float32)
+    zeros = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")
+    _, r = ctx.residual(thd, zeros)
+    e_s = _rel(-r.cpu().numpy().astype(np.complex128), oracle_lib.signal(prob, th, ora))
+    v, w = I.probe_vectors(prob)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    ctx.close()
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v))
+    ref = oracle_lib.jhw(prob, th, ora, w)
+    e_rows = [_rel(jhw[q], ref[q]) for q in range(5)]
+    print(f"\n  [balanced model + readout decay] signal {e_s:.2e} jv {e_jv:.2e} "
+          f"jhw rows {['%.1e' % e for e in e_rows]}", flush=True)
+    assert max([e_s, e_jv] + e_rows) <= TOL

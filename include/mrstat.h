@@ -210,10 +210,12 @@ mrstat_status mrstat_set_epg_lanes(mrstat_ctx ctx, int32_t lanes);
  * trains at TE) is unchanged, since for the gradient-spoiled EPG model an
  * off-resonance changes the echo by its phase only. On the GPU the factor
  * exp(lambda tau), lambda = -1/T2 - 2 pi i db0, is expanded in powers of
- * tau / tau_max (tau_max = (n_read/2) dwell_s) with as many terms (8 to 32,
- * mrstat_readout_terms) as keep the remainder below 1e-7 for T2 >= min_t2_s
- * and |db0| <= max_abs_db0_hz; every product then streams the trains once per
- * term set and runs its x-GEMMs over all terms. GN and trust-region steps
+ * tau / tau_max (tau_max = (n_read/2) dwell_s) for the forward products and
+ * in Chebyshev polynomials of tau / tau_max for the adjoint ones, each with as
+ * many terms (8 to 32; the power series' count from mrstat_readout_terms, the
+ * Chebyshev count at most that) as keep the remainder below 1e-7 for
+ * T2 >= min_t2_s and |db0| <= max_abs_db0_hz; every product then streams the
+ * trains once per term set and runs its x-GEMMs over all terms. GN and trust-region steps
  * refuse an ln T2 box below ln(min_t2_s) (MRSTAT_ERR_ARG); values of db0 or
  * T2 outside the bounds lose the stated accuracy. With coils (the maps of
  * mrstat_bind) the term sums and x-GEMMs carry n_coils x terms rows.
@@ -245,7 +247,8 @@ mrstat_status mrstat_set_db0(mrstat_ctx ctx, const float *d_db0);
  * MRSTAT_ERR_ARG for a negative or non-finite hz_per_unit. */
 mrstat_status mrstat_fit_db0(mrstat_ctx ctx, double hz_per_unit);
 
-/* Terms of the readout-dynamics expansion (0 for other contexts). */
+/* Terms of the readout-dynamics power series, the forward products' (0 for
+ * other contexts). */
 mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t *h_terms);
 
 /* Signal model of the linearisation: the gradient-spoiled EPG (n_iso = 0,

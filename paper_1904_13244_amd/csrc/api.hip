@@ -49,7 +49,8 @@ struct mrstat_ctx_s {
     int epg_lanes = 0;
     mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
     IsoProfile iso{};             // balanced isochromat model when iso.n > 0 (else the EPG)
-    int rd_nq = 0;                // readout dynamics: expansion terms (0 = off)
+    int rd_nq = 0;                // readout dynamics: forward (power series) terms (0 = off)
+    int rd_nc = 0;                // the adjoint's (Chebyshev) terms
     float rd_tmax = 0.f;          // largest |tau| of a sample, seconds
     float rd_dwell_u = 0.f;       // sample spacing in units of rd_tmax
     double rd_min_t2 = 0.0;       // T2 bound of the expansion, seconds
@@ -100,7 +101,8 @@ struct mrstat_ctx_s {
     float2* rdY() const { return at<float2>(L.rdY); }
     float2* rdw() const { return at<float2>(L.rdw); }
     float2* rdW() const { return at<float2>(L.rdW); }
-    Dims rd_dims() const { Dims q = d; q.C = rd_nq * d.C; return q; }   // coils x terms as rows of the x-GEMMs
+    Dims rd_dims() const { Dims q = d; q.C = rd_nq * d.C; return q; }       // coils x terms as rows of the x-GEMMs
+    Dims rd_dims_adj() const { Dims q = d; q.C = rd_nc * d.C; return q; }   // the adjoint's
 };
 
 namespace {
@@ -402,11 +404,11 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     if (ntr < 4 && ((param_mask >> 2) & 1))
         return fail(ctx, MRSTAT_ERR_STATE, "linearisation holds no dm/dB1 train");
     if (ctx->rd_nq > 0) {
-        const int nq = ctx->rd_nq;
-        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nq, ctx->rd_dwell_u, (const float2*)w, ctx->rdw(), s)));
-        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+        const int nc = ctx->rd_nc;
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nc, ctx->rd_dwell_u, (const float2*)w, ctx->rdw(), s)));
+        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims_adj(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                        ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
-        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
+        HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nc, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
                                                     ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit, ctx->deytab(),
                                                     ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
@@ -529,11 +531,13 @@ mrstat_status mrstat_create_readout(const mrstat_problem* p, double dwell_s, dou
     if (p->nx > 256 || p->n_read < 2) return fail(nullptr, MRSTAT_ERR_SHAPE, "readout dynamics need nx <= 256, n_read >= 2");
     const double tmax = (double)(p->n_read / 2) * dwell_s;
     const double bound = (1.0 / min_t2_s + 2.0 * kPi * max_abs_db0_hz) * tmax;
-    const int nq = rd_terms(bound);
-    if (nq == 0) return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout too long for the expansion (|lambda| tau > bound)");
+    const int nq = rd_terms(bound), nc = rd_cheb_terms(bound);
+    if (nq == 0 || nc == 0 || nc > nq)
+        return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout too long for the expansion (|lambda| tau > bound)");
     mrstat_status st = create_impl(p, nullptr, nullptr, out, nq);
     if (st != MRSTAT_OK) return st;
     mrstat_ctx c = *out;
+    c->rd_nc = nc;   // the adjoint's buffers, sized for nq rows, hold its nc <= nq
     c->rd_tmax = (float)tmax;
     c->rd_dwell_u = (float)(dwell_s / tmax);
     c->rd_min_t2 = min_t2_s;
@@ -1089,11 +1093,11 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
     auto adj_rho = [&](const float2* w, float2* out) -> mrstat_status {
         const YPlan& p = ctx->L.yp;
         if (ctx->rd_nq > 0) {
-            const int nq = ctx->rd_nq;
-            HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nq, ctx->rd_dwell_u, w, ctx->rdw(), s)));
-            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+            const int nc = ctx->rd_nc;
+            HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nc, ctx->rd_dwell_u, w, ctx->rdw(), s)));
+            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims_adj(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                            ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
-            HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nq, 1, p.adj_chunks, ctx->trains(), ctx->f16,
+            HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nc, 1, p.adj_chunks, ctx->trains(), ctx->f16,
                                                         d_theta, ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit,
                                                         ctx->deytab(), ctx->rdW(), ctx->apart(), ctx->st.te,
                                                         ctx->rd_tmax, s)));

@@ -45,8 +45,11 @@ struct SeqTimes {
 // Term-wise y-stages and sample weighting of the readout-dynamics expansion
 // (readout.hip): U [nq][T][nx], Y [nq][T][nk] (x-GEMM of U), w_q [nq][T][nk],
 // W [nq][T][nx] (adjoint x-GEMM of w_q); apart as for the static adjoint.
-// rd_terms: the term count for a bound on |lambda| tau_max (0 = none fits).
+// rd_terms: the forward's (power series) term count for a bound on
+// |lambda| tau_max; rd_cheb_terms: the adjoint's (Chebyshev) count (0 = none
+// fits).
 int rd_terms(double bound);
+int rd_cheb_terms(double bound);
 // With d.np == 6 the off-resonance is theta row 5 times db0_unit Hz (db0 is
 // then not read) and J v gains that row's column.
 // Coils (coil != null, [C][nv]): U, Y, w_q and W_q hold C x nq rows, coil-major.

@@ -22,12 +22,16 @@
 // term-wise y-stages and the per-sample weighting.
 //   forward:  rd_fwd_kernel (U_q) -> x-GEMM (Y_q = Ex U_q) -> rd_combine_kernel
 //             (s = sum_q u^q/q! Y_q, then r = d - s, -s or s);
-//   adjoint:  rd_expand_kernel (w_q = u^q/q! w) -> adjoint x-GEMM
-//             (W_q = Ex^H w_q) -> rd_adj_kernel: per voxel and TR
-//             V = sum_q conj(L)^q W_q, V' = sum_q q conj(L)^(q-1) W_q,
+//   adjoint:  the same factor in a Chebyshev basis, exp(L u) = sum_m a_m(L)
+//             T_m(u) and u exp(L u) = sum_m b_m(L) T_m(u), whose remainder
+//             meets the same bound with fewer terms (16 instead of 24 at
+//             |L| = 3.8); rd_expand_kernel (w_m = T_m(u) w) -> adjoint x-GEMM
+//             (W_m = Ex^H w_m) -> rd_adj_kernel: per voxel and TR
+//             V = sum_m conj(a_m) W_m, V' = sum_m conj(b_m) W_m,
 //             A_p += mu_p conj(c Ey) V, A_lnT2 += (tau_max/T2) mu_0 conj(c Ey) V'
-//             (V, V' summed over the coils with conj(C_c); the exact transpose
-//             of the truncated forward).
+//             (V, V' summed over the coils with conj(C_c)). Forward and
+//             adjoint each approximate the exact operator to the bound, so
+//             they are transposes of each other to that bound, not exactly.
 // FP32 arithmetic; the sums of the expansion are in the dimensionless u and L
 // so no term over- or underflows.
 #include "mrstat_internal.h"
@@ -222,8 +226,9 @@ __global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restric
     }
 }
 
-// w_cq[n,k] = (u_k^q / q!) w_c[n,k], q = 0 .. nq - 1.
-__global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict__ w, float2* __restrict__ wq, int nq,
+// The adjoint's expansion (Chebyshev): w_cm[n,k] = T_m(u_k) w_c[n,k],
+// m = 0 .. nc - 1, T_0 = 1, T_1 = u, T_(m+1) = 2 u T_m - T_(m-1).
+__global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict__ w, float2* __restrict__ wq, int nc,
                                                         float dwell_u, int C, int T, int nk)
 {
     const size_t count = (size_t)T * nk;
@@ -232,19 +237,73 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
         const int k = (int)(ii % nk);
         const float u = (float)(k - nk / 2) * dwell_u;
         const float2 x = w[i];
-        float2* wc = wq + c * nq * count + ii;
-        float cq = 1.f;
+        float2* wc = wq + c * nc * count + ii;
+        float tm1 = 1.f, tm = u;   // T_(m-1), T_m
         wc[0] = x;
-        for (int q = 1; q < nq; ++q) {
-            cq *= u / (float)q;
-            wc[(size_t)q * count] = make_float2(cq * x.x, cq * x.y);
+        if (nc > 1) wc[count] = make_float2(u * x.x, u * x.y);
+        for (int m = 2; m < nc; ++m) {
+            const float tn = fmaf(2.f * u, tm, -tm1);
+            tm1 = tm;
+            tm = tn;
+            wc[(size_t)m * count] = make_float2(tm * x.x, tm * x.y);
         }
     }
 }
 
+// Chebyshev coefficients of exp(L u) on [-1, 1]: a_m = eps_m I_m(L) (eps_0 =
+// 1, else 2; I_m the modified Bessel function, as a power series in FP64,
+// which for |L| <= 6 converges to 1e-17 within 20 terms); and those of
+// u exp(L u): u T_0 = T_1, u T_m = (T_(m+1) + T_(m-1)) / 2, so b_0 = a_1 / 2,
+// b_1 = a_0 + a_2 / 2, b_m = (a_(m-1) + a_(m+1)) / 2. Returned conjugated
+// (the adjoint's coefficients), NC of each.
+template <int NC>
+__device__ __forceinline__ void cheb_coeffs(float2 Lf, float2 (&ca)[NC], float2 (&cb)[NC])
+{
+    const double hx = 0.5 * (double)Lf.x, hy = 0.5 * (double)Lf.y;   // h = L / 2
+    const double h2x = hx * hx - hy * hy, h2y = 2.0 * hx * hy;       // h^2
+    double a[NC + 1][2];
+    double tx = 1.0, ty = 0.0;   // h^m / m!
+#pragma unroll
+    for (int m = 0; m <= NC; ++m) {
+        double sx = tx, sy = ty, ex = tx, ey = ty;
+        for (int j = 1; j <= 20; ++j) {
+            const double f = 1.0 / ((double)j * (double)(m + j));
+            const double nx = (ex * h2x - ey * h2y) * f, ny = (ex * h2y + ey * h2x) * f;
+            ex = nx;
+            ey = ny;
+            sx += ex;
+            sy += ey;
+        }
+        const double eps = m == 0 ? 1.0 : 2.0;
+        a[m][0] = eps * sx;
+        a[m][1] = eps * sy;
+        const double f = 1.0 / (double)(m + 1);
+        const double nx = (tx * hx - ty * hy) * f, ny = (tx * hy + ty * hx) * f;
+        tx = nx;
+        ty = ny;
+    }
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        ca[m] = make_float2((float)a[m][0], (float)-a[m][1]);
+        double bx, by;
+        if (m == 0) {
+            bx = 0.5 * a[1][0];
+            by = 0.5 * a[1][1];
+        } else if (m == 1) {
+            bx = a[0][0] + 0.5 * a[2][0];
+            by = a[0][1] + 0.5 * a[2][1];
+        } else {
+            bx = 0.5 * (a[m - 1][0] + a[m + 1][0]);
+            by = 0.5 * (a[m - 1][1] + a[m + 1][1]);
+        }
+        cb[m] = make_float2((float)bx, (float)-by);
+    }
+}
+
 // Adjoint term sums: one thread per pair of voxels of a column and TR chunk;
-// per TR the sums V and V' over the terms (each voxel's power coefficients
-// held in registers across its TRs), then the chunk partials A_p
+// per TR the sums V = sum_m conj(a_m) W_m and V' = sum_m conj(b_m) W_m over
+// the Chebyshev terms (each voxel's coefficients held in registers across
+// its TRs), then the chunk partials A_p
 // in the layout the gradient assembly reads ([chunk][pl planes][nv], pl = 8,
 // or 10 with Delta B0 fitted; NTR = 1 writes the m pair only, 2 planes, for
 // the proton-density initialisation). With Delta B0 fitted (fit, NTR >= 3)
@@ -253,11 +312,13 @@ __global__ __launch_bounds__(256) void rd_expand_kernel(const float2* __restrict
 // 0.83 ms; the power coefficients in registers with the term loads batched
 // (two waves per SIMD) 0.80; with a tile of 64 columns x 4 rows per block
 // for cache reuse of W 0.92; double-buffered term loads need 256 registers;
-// two voxels of a column per thread, sharing each TR's term loads, 0.59.
+// two voxels of a column per thread, sharing each TR's term loads, 0.59; the
+// Chebyshev form, 16 terms for the same bound, 0.52 (and its adjoint x-GEMM
+// 0.084 instead of 0.122).
 // Voxels per thread of the adjoint (rows iy, iy + hy, ... of one column):
 // two while each voxel's coefficients and the loaded terms fit the registers.
 template <int NQ>
-constexpr int rd_adj_rows() { return NQ <= 24 ? 2 : 1; }
+constexpr int rd_adj_rows() { return NQ <= 16 ? 2 : 1; }
 
 template <int NTR, int NQ, typename TT, bool MC>   // MC: coil maps (C >= 1 weighted coils)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void rd_adj_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
@@ -283,8 +344,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     int jv[R], iyv[R];
     bool on[R];
     RdVoxel vx[R];
-    // Each voxel's coefficients, fixed over its TRs: conj(L)^q.
-    float2 Pc[R][NQ];
+    // Each voxel's coefficients, fixed over its TRs: conj(a_m), conj(b_m).
+    float2 Ca[R][NQ], Cb[R][NQ];
     float2 A[R][NTR], At[R], Af[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -292,9 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         jv[r] = iyv[r] < ny ? iyv[r] * nx + ix : -1;
         on[r] = jv[r] >= 0 && (mask == nullptr || mask[jv[r]] != 0);
         vx[r] = rd_voxel(theta, db0, db0_unit, nv, on[r] ? jv[r] : jp % nv, te, tmax);
-        Pc[r][0] = make_float2(1.f, 0.f);
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) Pc[r][q] = cmul(Pc[r][q - 1], make_float2(vx[r].L.x, -vx[r].L.y));
+        cheb_coeffs<NQ>(vx[r].L, Ca[r], Cb[r]);
 #pragma unroll
         for (int p = 0; p < NTR; ++p) A[r][p] = make_float2(0.f, 0.f);
         At[r] = Af[r] = make_float2(0.f, 0.f);
@@ -322,15 +381,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             }
         }
     };
-    // V = sum_q conj(L)^q W_q and V' = sum_q q conj(L)^(q-1) W_q of one coil,
-    // from its TR's term values loaded together (all in flight at once).
+    // V = sum_m conj(a_m) W_m and V' = sum_m conj(b_m) W_m of one coil, from
+    // its TR's term values loaded together (all in flight at once).
     auto term_sums = [&](const float2 (&wv)[NQ], int r, float2& V, float2& Vt) {
-        V = wv[0];
+        V = make_float2(0.f, 0.f);
         Vt = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            cmac(V, wv[q], Pc[r][q]);
-            if constexpr (NTR >= 3) cmac(Vt, make_float2((float)q * wv[q].x, (float)q * wv[q].y), Pc[r][q - 1]);
+        for (int q = 0; q < NQ; ++q) {
+            cmac(V, wv[q], Ca[r][q]);
+            if constexpr (NTR >= 3) cmac(Vt, wv[q], Cb[r][q]);
         }
     };
     for (int n = n0; n < n1; ++n) {
@@ -457,6 +516,26 @@ int rd_terms(double bound)
         double t = std::exp(bound);
         for (int q = 1; q <= nq - 1; ++q) t *= bound / q;
         if (t <= 1e-7) return nq;
+    }
+    return 0;
+}
+
+int rd_cheb_terms(double bound)
+{
+    // Smallest term count NC from {8, 12, 16, 20, 24, 32} for the adjoint's
+    // Chebyshev expansion: its remainder (the u exp(L u) share, which drops
+    // a_NC, is the larger) is at most 2 sum_(m >= NC - 1) |I_m(L)| with
+    // |I_m(L)| <= (b/2)^m / m! e^(b^2 / (4 (m + 1))), b >= |L|, bounded by
+    // 2 (b/2)^(NC-1) / (NC-1)! e^(b^2 / (4 NC)) / (1 - b / (2 NC)); kept below
+    // 1e-7; 0 when none does.
+    const int choices[] = {8, 12, 16, 20, 24, 32};
+    for (int nc : choices) {
+        const double r = bound / (2.0 * nc);
+        if (r >= 1.0) continue;
+        double t = 2.0;
+        for (int m = 1; m <= nc - 1; ++m) t *= 0.5 * bound / m;
+        t *= std::exp(bound * bound / (4.0 * nc)) / (1.0 - r);
+        if (t <= 1e-7) return nc;
     }
     return 0;
 }

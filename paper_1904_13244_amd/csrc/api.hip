@@ -29,7 +29,7 @@ struct Layout {
     size_t rdU, rdY, rdw, rdW;   // readout-dynamics term buffers (0 bytes otherwise)
     int n_red;
     YPlan yp;
-    YPlan rdp;         // plan of the x-GEMMs over the readout-dynamics terms (nq terms as rows)
+    YPlan rdp;         // plan of the x-GEMMs over the readout-dynamics terms (nc Chebyshev rows)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -49,8 +49,8 @@ struct mrstat_ctx_s {
     int epg_lanes = 0;
     mrstat_mlp surr = nullptr;    // surrogate replacing the EPG inside its box (not owned)
     IsoProfile iso{};             // balanced isochromat model when iso.n > 0 (else the EPG)
-    int rd_nq = 0;                // readout dynamics: forward (power series) terms (0 = off)
-    int rd_nc = 0;                // the adjoint's (Chebyshev) terms
+    int rd_nq = 0;                // readout dynamics: power-series terms of the forward sums (0 = off)
+    int rd_nc = 0;                // Chebyshev terms: rows of the x-stages, the adjoint's sums
     float rd_tmax = 0.f;          // largest |tau| of a sample, seconds
     float rd_dwell_u = 0.f;       // sample spacing in units of rd_tmax
     double rd_min_t2 = 0.0;       // T2 bound of the expansion, seconds
@@ -101,8 +101,7 @@ struct mrstat_ctx_s {
     float2* rdY() const { return at<float2>(L.rdY); }
     float2* rdw() const { return at<float2>(L.rdw); }
     float2* rdW() const { return at<float2>(L.rdW); }
-    Dims rd_dims() const { Dims q = d; q.C = rd_nq * d.C; return q; }       // coils x terms as rows of the x-GEMMs
-    Dims rd_dims_adj() const { Dims q = d; q.C = rd_nc * d.C; return q; }   // the adjoint's
+    Dims rd_dims() const { Dims q = d; q.C = rd_nc * d.C; return q; }   // coils x terms as rows of the x-GEMMs
 };
 
 namespace {
@@ -158,12 +157,12 @@ hipError_t traced(mrstat_ctx ctx, int kind, hipStream_t s, F&& launch)
 
 #define TRACED(kind, call) traced(ctx, (kind), s, [&]() { return (call); })
 
-Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
+Layout make_layout(const Dims& d, bool nc, int rd_rows = 0)
 {
     Layout L{};
     L.yp = make_yplan(d);
     Dims dq = d;
-    dq.C = rd_nq > 0 ? rd_nq * d.C : 1;
+    dq.C = rd_rows > 0 ? rd_rows * d.C : 1;
     L.rdp = make_yplan(dq);
     if (nc) {
         // The non-Cartesian adjoint's TR chunks replace the y-stage's in the
@@ -173,7 +172,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     }
     // Readout-dynamics contexts may fit Delta B0: room for six parameter rows
     // and ten partial planes per adjoint chunk.
-    const size_t npmax = rd_nq > 0 ? 6 : 5, plmax = rd_nq > 0 ? 10 : 8;
+    const size_t npmax = rd_rows > 0 ? 6 : 5, plmax = rd_rows > 0 ? 10 : 8;
     const int M = d.C * d.T;
     const int gemm_blocks = std::max(ceil_div(2 * d.nk, 64) * ceil_div(M, 64), xgemm_direct_blocks(d));
     L.n_red = std::max({3 * RED_BLOCKS, gemm_blocks, cg_partials(d), tr_partials(d), nc ? nc_fwd_blocks(d) : 0});
@@ -203,7 +202,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_nq = 0)
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
     L.ay = take(nc ? T * d.nk * sizeof(double) : 0);
-    const size_t nq = rd_nq > 0 ? (size_t)rd_nq * d.C : 0;   // rows per TR: coils x terms
+    const size_t nq = rd_rows > 0 ? (size_t)rd_rows * d.C : 0;   // rows per TR: coils x terms
     L.rdU = take(nq * T * d.nx * sizeof(float2));
     L.rdY = take(nq * T * d.nk * sizeof(float2));
     L.rdw = take(nq * T * d.nk * sizeof(float2));
@@ -354,15 +353,15 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
     const YPlan& p = ctx->L.yp;
     if (ctx->rd_nq > 0) {
         // Readout dynamics: the term sums, their x-GEMM, the per-sample weighting.
-        const int nq = ctx->rd_nq;
+        const int nq = ctx->rd_nq, nc = ctx->rd_nc;
         HIP_TRY(TRACED(mode_y == 0 ? MRSTAT_K_YFWD_SIG : MRSTAT_K_YFWD_JV,
-                       launch_rd_fwd(d, nq, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask, ctx->rd_db0,
+                       launch_rd_fwd(d, nq, nc, mode_y, trains, ctx->f16, theta, v, ctx->coil, ctx->mask, ctx->rd_db0,
                                      ctx->db0_unit, ctx->deytab(), ctx->rdU(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_XFWD, launch_xgemm_fwd(ctx->rd_dims(), ctx->L.rdp, ctx->enc, 2, ctx->rdU(),
                                                        ctx->dextab(), ctx->bfrag(0), nullptr, ctx->rdY(), nullptr,
                                                        nullptr, s)));
         int nred = 0;
-        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_combine(d, nq, mode_x, ctx->rdY(), ctx->rd_dwell_u,
+        HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_combine(d, nc, mode_x, ctx->rdY(), ctx->rd_dwell_u,
                                                           (const float2*)data, (float2*)out, ctx->red(), &nred,
                                                           s)));
         if (mode_x == 0 && f_out)
@@ -392,11 +391,13 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
     return MRSTAT_OK;
 }
 
-// With dir non-null the finish kernel also leaves the CG curvature partials
-// of dir . g in ctx->red(). Without the dm/dB1 train (a linearisation with 3
-// trains) B1 must lie outside param_mask.
+// With dir non-null the finish kernel also leaves the CG partials in
+// ctx->red(): dir . g and dir . dir, with step . dir (the trust region's) or
+// res . res, res . g and g . g (the one-launch CG update's). Without the
+// dm/dB1 train (a linearisation with 3 trains) B1 must lie outside param_mask.
 mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* g, int param_mask,
-                      hipStream_t s, const float* dir = nullptr, const float* step = nullptr)
+                      hipStream_t s, const float* dir = nullptr, const float* step = nullptr,
+                      const float* res = nullptr)
 {
     const Dims& d = ctx->d;
     const YPlan& p = ctx->L.yp;
@@ -406,13 +407,13 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     if (ctx->rd_nq > 0) {
         const int nc = ctx->rd_nc;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nc, ctx->rd_dwell_u, (const float2*)w, ctx->rdw(), s)));
-        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims_adj(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+        HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                        ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
         HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nc, ntr, p.adj_chunks, ctx->trains(), ctx->f16, theta,
                                                     ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit, ctx->deytab(),
                                                     ctx->rdW(), ctx->apart(), ctx->st.te, ctx->rd_tmax, s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
-                                                          dir, dir ? ctx->red() : nullptr, s, step)));
+                                                          dir, dir ? ctx->red() : nullptr, s, step, res)));
         return MRSTAT_OK;
     }
     if (ctx->nc) {
@@ -420,7 +421,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
                                                       ctx->coil, ctx->mask, ctx->dax(), ctx->day(),
                                                       (const float2*)w, ctx->apart(), s)));
         HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
-                                                          dir, dir ? ctx->red() : nullptr, s, step)));
+                                                          dir, dir ? ctx->red() : nullptr, s, step, res)));
         return MRSTAT_OK;
     }
     HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(d, p, ctx->enc, (const float2*)w, ctx->dextab(),
@@ -428,7 +429,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
     HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_ystage_adj(d, p, ctx->trains(), ctx->f16, ntr, ctx->coil, ctx->mask,
                                                     ctx->deytab(), ctx->W(), ctx->apart(), s)));
     HIP_TRY(TRACED(MRSTAT_K_FINISH, launch_jhw_finish(d, p, ctx->apart(), theta, ctx->mask, param_mask, g,
-                                                      dir, dir ? ctx->red() : nullptr, s, step)));
+                                                      dir, dir ? ctx->red() : nullptr, s, step, res)));
     return MRSTAT_OK;
 }
 
@@ -437,7 +438,7 @@ mrstat_status adjoint(mrstat_ctx ctx, const float* theta, const void* w, float* 
 namespace {
 
 mrstat_status create_impl(const mrstat_problem* p, const double* kx, const double* ky, mrstat_ctx* out,
-                          int rd_nq = 0)
+                          int rd_nq = 0, int rd_nc = 0)
 {
     mrstat_ctx ctx = nullptr;
     if (!p || !out) return fail(nullptr, MRSTAT_ERR_ARG, "null problem or output pointer");
@@ -497,7 +498,8 @@ mrstat_status create_impl(const mrstat_problem* p, const double* kx, const doubl
         build_tables(ctx, p);
     }
     ctx->rd_nq = rd_nq;
-    ctx->L = make_layout(ctx->d, nc, rd_nq);
+    ctx->rd_nc = rd_nc;
+    ctx->L = make_layout(ctx->d, nc, rd_nc);
     *out = ctx;
     return MRSTAT_OK;
 }
@@ -534,10 +536,9 @@ mrstat_status mrstat_create_readout(const mrstat_problem* p, double dwell_s, dou
     const int nq = rd_terms(bound), nc = rd_cheb_terms(bound);
     if (nq == 0 || nc == 0 || nc > nq)
         return fail(nullptr, MRSTAT_ERR_UNSUPPORTED, "readout too long for the expansion (|lambda| tau > bound)");
-    mrstat_status st = create_impl(p, nullptr, nullptr, out, nq);
+    mrstat_status st = create_impl(p, nullptr, nullptr, out, nq, nc);
     if (st != MRSTAT_OK) return st;
     mrstat_ctx c = *out;
-    c->rd_nc = nc;   // the adjoint's buffers, sized for nq rows, hold its nc <= nq
     c->rd_tmax = (float)tmax;
     c->rd_dwell_u = (float)(dwell_s / tmax);
     c->rd_min_t2 = min_t2_s;
@@ -917,7 +918,7 @@ mrstat_status mrstat_gn_step(mrstat_ctx ctx, float* d_theta, const void* d_data,
     for (int it = 0; it < o->n_cg; ++it) {
         st = forward(ctx, ntr == 4 ? 1 : 3, 1, ctx->trains(), d_theta, dir, nullptr, ctx->y(), nullptr, s);
         if (st != MRSTAT_OK) return st;
-        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s, dir);
+        st = adjoint(ctx, d_theta, ctx->y(), q, o->param_mask, s, dir, nullptr, res);
         if (st != MRSTAT_OK) return st;
         HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_cg_update(d, q, step, res, dir, sc, ctx->red(), it, s)));
     }
@@ -1095,7 +1096,7 @@ mrstat_status mrstat_rho_init(mrstat_ctx ctx, float* d_theta, const void* d_data
         if (ctx->rd_nq > 0) {
             const int nc = ctx->rd_nc;
             HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_rd_expand(d, nc, ctx->rd_dwell_u, w, ctx->rdw(), s)));
-            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims_adj(), ctx->L.rdp, ctx->enc, ctx->rdw(),
+            HIP_TRY(TRACED(MRSTAT_K_XADJ, launch_xgemm_adj(ctx->rd_dims(), ctx->L.rdp, ctx->enc, ctx->rdw(),
                                                            ctx->dextab(), ctx->bfrag(1), ctx->rdW(), s)));
             HIP_TRY(TRACED(MRSTAT_K_YADJ, launch_rd_adj(d, nc, 1, p.adj_chunks, ctx->trains(), ctx->f16,
                                                         d_theta, ctx->coil, ctx->mask, ctx->rd_db0, ctx->db0_unit,

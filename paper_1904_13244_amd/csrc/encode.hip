@@ -914,8 +914,10 @@ __global__ void wsum_kernel(float2* __restrict__ W, int nsplit, size_t count)
 // g from A: g_q = -Im(conj(rho) A_{q+1}) for q = lnT1, lnT2, B1;
 // g_3 = -Im(A_0) (Re rho), g_4 = Re(A_0) (Im rho); with NP = 6 also
 // g_5 = -Im(conj(rho) A_5) (Delta B0, chunks of 10 planes).
-// CURV: 0 = gradient only; 1 = also the CG curvature partials dir . g and
-// dir . dir; 2 = also step . dir (the trust-region CG's boundary test).
+// CURV: 0 = gradient only; 2 = also the CG partials dir . g, dir . dir and
+// step . dir (the trust-region CG's, with its boundary test); 3 = dir . g,
+// dir . dir, res . res, res . g and g . g (what the one-launch CG update
+// needs for alpha and beta).
 template <int CURV, int NP>
 __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict__ apart, int n_chunk,
                                                          const float* __restrict__ theta,
@@ -923,11 +925,15 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
                                                          float* __restrict__ g, int nv,
                                                          const float* __restrict__ dir,
                                                          const float* __restrict__ step,
+                                                         const float* __restrict__ res,
                                                          double* __restrict__ part)
 {
     constexpr int PL = NP == 6 ? 10 : 8;   // planes per chunk
+    constexpr int NPART = CURV == 3 ? 5 : 3;   // partial kinds
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    double cd = 0.0, dd = 0.0, sd = 0.0;
+    double acc[NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) acc[k] = 0.0;
     if (j < nv) {
         const bool on = mask == nullptr || mask[j] != 0;
         const float rr = theta[3 * nv + j], ri = theta[4 * nv + j];
@@ -980,36 +986,35 @@ __global__ __launch_bounds__(256) void jhw_finish_kernel(const float* __restrict
         for (int q = 0; q < NP; ++q) {
             g[(size_t)q * nv + j] = gq[q];
             if constexpr (CURV > 0) {
-                const double dv = dir[(size_t)q * nv + j];
-                cd += dv * (double)gq[q];
-                dd += dv * dv;
-                if constexpr (CURV > 1) sd += (double)step[(size_t)q * nv + j] * dv;
+                const double dv = dir[(size_t)q * nv + j], gv = gq[q];
+                acc[0] += dv * gv;
+                acc[1] += dv * dv;
+                if constexpr (CURV == 2) acc[2] += (double)step[(size_t)q * nv + j] * dv;
+                if constexpr (CURV == 3) {
+                    const double rv = res[(size_t)q * nv + j];
+                    acc[2] += rv * rv;
+                    acc[3] += rv * gv;
+                    acc[4] += gv * gv;
+                }
             }
         }
     }
     if constexpr (CURV > 0) {
-        // CG curvature partials of this block's voxels (dir . g, dir . dir
-        // and, for the trust region, step . dir) in FP64, one per block and
-        // kind (all threads reach the barrier).
-        __shared__ double sh[3][4];
-        for (int off = 32; off > 0; off >>= 1) {
-            cd += __shfl_xor(cd, off);
-            dd += __shfl_xor(dd, off);
-            if constexpr (CURV > 1) sd += __shfl_xor(sd, off);
-        }
+        // CG partials of this block's voxels in FP64, one per block and kind
+        // ([NPART][gridDim.x]; all threads reach the barrier).
+        __shared__ double sh[NPART][4];
+#pragma unroll
+        for (int k = 0; k < NPART; ++k)
+            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0) {
-            sh[0][wave] = cd;
-            sh[1][wave] = dd;
-            sh[2][wave] = sd;
-        }
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k) sh[k][wave] = acc[k];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            part[blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
-            part[gridDim.x + blockIdx.x] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
-            if constexpr (CURV > 1)
-                part[2 * gridDim.x + blockIdx.x] = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
-        }
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NPART; ++k)
+                part[(size_t)k * gridDim.x + blockIdx.x] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
     }
 }
 
@@ -1846,19 +1851,20 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, int param_mask, float* g, const float* dir,
-                             double* part, hipStream_t s, const float* step)
+                             double* part, hipStream_t s, const float* step, const float* res)
 {
     const int nb = ceil_div(d.nv, 256);
+    if (dir != nullptr && step == nullptr && res == nullptr) return hipErrorInvalidValue;
 #define FINISH(NP)                                                                                       \
     if (dir != nullptr && step != nullptr)                                                               \
         jhw_finish_kernel<2, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
-                                                    dir, step, part);                                    \
+                                                    dir, step, nullptr, part);                           \
     else if (dir != nullptr)                                                                             \
-        jhw_finish_kernel<1, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
-                                                    dir, nullptr, part);                                 \
+        jhw_finish_kernel<3, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
+                                                    dir, nullptr, res, part);                            \
     else                                                                                                 \
         jhw_finish_kernel<0, NP><<<nb, 256, 0, s>>>(apart, p.adj_chunks, theta, mask, param_mask, g, d.nv, \
-                                                    nullptr, nullptr, nullptr);
+                                                    nullptr, nullptr, nullptr, nullptr);
     if (d.np == 6) {
         FINISH(6)
     } else {

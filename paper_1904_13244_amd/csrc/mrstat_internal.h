@@ -43,25 +43,25 @@ struct SeqTimes {
 
 // ---------------------------------------------------------------- readout dynamics
 // Term-wise y-stages and sample weighting of the readout-dynamics expansion
-// (readout.hip): U [nq][T][nx], Y [nq][T][nk] (x-GEMM of U), w_q [nq][T][nk],
-// W [nq][T][nx] (adjoint x-GEMM of w_q); apart as for the static adjoint.
-// rd_terms: the forward's (power series) term count for a bound on
-// |lambda| tau_max; rd_cheb_terms: the adjoint's (Chebyshev) count (0 = none
-// fits).
+// (readout.hip): nq power-series sums per voxel column and TR, economised to
+// nc Chebyshev rows V [nc][T][nx]; Y [nc][T][nk] (x-GEMM of V), w_m
+// [nc][T][nk], W [nc][T][nx] (adjoint x-GEMM of w_m); apart as for the static
+// adjoint. rd_terms: the power series' term count for a bound on
+// |lambda| tau_max; rd_cheb_terms: the Chebyshev count (0 = none fits).
 int rd_terms(double bound);
 int rd_cheb_terms(double bound);
 // With d.np == 6 the off-resonance is theta row 5 times db0_unit Hz (db0 is
 // then not read) and J v gains that row's column.
-// Coils (coil != null, [C][nv]): U, Y, w_q and W_q hold C x nq rows, coil-major.
-hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
+// Coils (coil != null, [C][nv]): V, Y, w_m and W_m hold C x nc rows, coil-major.
+hipError_t launch_rd_fwd(const Dims& d, int nq, int nc, int mode, const void* trains, bool f16, const float* theta,
                          const float* v, const float2* coil, const uint8_t* mask, const float* db0, float db0_unit,
                          const float2* eytab, float2* U, float te, float tmax, hipStream_t s);
-hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
+hipError_t launch_rd_combine(const Dims& d, int nc, int mode, const float2* Y, float dwell_u, const float2* data,
                              float2* out, double* red, int* nred, hipStream_t s);
-hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s);
+hipError_t launch_rd_expand(const Dims& d, int nc, float dwell_u, const float2* w, float2* wq, hipStream_t s);
 // Chunk partials in the gradient assembly's layout; with d.np == 6 (ntr 3 or
 // 4) the Delta B0 pair follows as planes 8 and 9 of each chunk.
-hipError_t launch_rd_adj(const Dims& d, int nq, int ntr, int chunks, const void* trains, bool f16,
+hipError_t launch_rd_adj(const Dims& d, int nc, int ntr, int chunks, const void* trains, bool f16,
                          const float* theta, const float2* coil, const uint8_t* mask, const float* db0,
                          float db0_unit, const float2* eytab, const float2* W, float* apart, float te, float tmax,
                          hipStream_t s);
@@ -176,12 +176,15 @@ hipError_t launch_ystage_adj(const Dims& d, const YPlan& p, const void* trains, 
 // planes per chunk, 10 with Delta B0 fitted); rows of parameters outside
 // param_mask (and masked voxels) are zero, and the dm/dB1 partials are read
 // only when B1 is in param_mask.
-// With dir non-null, also the CG curvature partials dir . g and dir . dir
-// (FP64, one per block of 256 voxels: part[b] and part[nblocks + b]); with
-// step non-null as well, step . dir in part[2 nblocks + b].
+// With dir non-null, also the CG partials dir . g and dir . dir (FP64, one
+// per block of 256 voxels: part[b] and part[nblocks + b]) and either, with
+// step non-null, step . dir in part[2 nblocks + b], or, with res non-null,
+// res . res, res . g and g . g in planes 2, 3 and 4 (dir with neither is
+// hipErrorInvalidValue).
 hipError_t launch_jhw_finish(const Dims& d, const YPlan& p, const float* apart, const float* theta,
                              const uint8_t* mask, int param_mask, float* g, const float* dir,
-                             double* part, hipStream_t s, const float* step = nullptr);
+                             double* part, hipStream_t s, const float* step = nullptr,
+                             const float* res = nullptr);
 
 // CGLS helper: A^H w = -i A_0 from the one-train partials.
 hipError_t launch_rho_adj_finish(const Dims& d, const YPlan& p, const float* apart,
@@ -210,9 +213,10 @@ enum : int {
 
 hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res, float* dir,
                           double* scal, double* partials, hipStream_t s);
-// One CG iteration after q = Re(J^H J) dir, whose curvature partials the
-// finish kernel left in partials ([2][nv / 256 blocks]); iter = iteration
-// index from 0; partials hold at least cg_partials(d) doubles.
+// One CG iteration after q = Re(J^H J) dir, in one launch: the finish
+// kernel left dir . q, dir . dir, res . res, res . q and q . q in partials
+// ([5][nv / 256 blocks]); iter = iteration index from 0; partials hold at
+// least cg_partials(d) doubles.
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s);
 int cg_partials(const Dims& d);

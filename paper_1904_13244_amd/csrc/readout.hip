@@ -17,15 +17,22 @@
 // y = i rho mu (tau_max / T2) v_lnT2, multiplied by u in the sum). With Delta
 // B0 fitted (theta row 5, in units of db0_unit Hz) its column's factor
 // -2 pi i db0_unit (TE + tau) splits the same way: the TE part joins x, the
-// tau part y. With coils each coil's weight joins c_j. The x-stage of each
-// term is the library's x-GEMM with coils x terms as rows; this file holds the
-// term-wise y-stages and the per-sample weighting.
-//   forward:  rd_fwd_kernel (U_q) -> x-GEMM (Y_q = Ex U_q) -> rd_combine_kernel
-//             (s = sum_q u^q/q! Y_q, then r = d - s, -s or s);
-//   adjoint:  the same factor in a Chebyshev basis, exp(L u) = sum_m a_m(L)
-//             T_m(u) and u exp(L u) = sum_m b_m(L) T_m(u), whose remainder
-//             meets the same bound with fewer terms (16 instead of 24 at
-//             |L| = 3.8); rd_expand_kernel (w_m = T_m(u) w) -> adjoint x-GEMM
+// tau part y. With coils each coil's weight joins c_j. The sample weights
+// u^q / q! are then re-expanded in Chebyshev polynomials (u^q = 2^(1-q)
+// sum_j binom(q, j) T_(q-2j)(u), the T_0 term halved), which turns the U_q
+// into NC <= NQ sums
+//     V_m = sum_q e_mq U_q,   s[n,k] = sum_(m < NC) T_m(u_k) sum_ix Ex[k,ix] V_m[n,ix],
+// dropping the Chebyshev terms from NC on, which stay below the same bound
+// (Chebyshev economisation): the x-stage and the per-sample sum carry NC rows
+// (16 instead of 24 at |L| = 3.8). The x-stage of each term is the library's
+// x-GEMM with coils x terms as rows; this file holds the term-wise y-stages
+// and the per-sample weighting.
+//   forward:  rd_fwd_kernel (U_q summed, then V_m) -> x-GEMM (Y_m = Ex V_m)
+//             -> rd_combine_kernel (s = sum_m T_m(u) Y_m, then r = d - s, -s
+//             or s);
+//   adjoint:  the same factor in the Chebyshev basis directly, exp(L u) =
+//             sum_m a_m(L) T_m(u) and u exp(L u) = sum_m b_m(L) T_m(u), NC
+//             terms; rd_expand_kernel (w_m = T_m(u) w) -> adjoint x-GEMM
 //             (W_m = Ex^H w_m) -> rd_adj_kernel: per voxel and TR
 //             V = sum_m conj(a_m) W_m, V' = sum_m conj(b_m) W_m,
 //             A_p += mu_p conj(c Ey) V, A_lnT2 += (tau_max/T2) mu_0 conj(c Ey) V'
@@ -90,9 +97,33 @@ __device__ __forceinline__ RdVoxel rd_voxel(const float* __restrict__ theta, con
     return o;
 }
 
+// e_mq: the share of T_m(u) in u^q / q!, (m == 0 ? 1 : 2) 2^-q binom(q, j)
+// / q! for m = q - 2j >= 0, else 0; built at compile time (FP64, rounded
+// once), indexed with unrolled constants so every entry is an immediate.
+template <int NQ>
+struct EconTable {
+    float e[NQ][NQ];
+    constexpr EconTable() : e{}
+    {
+        for (int q = 0; q < NQ; ++q) {
+            double w = 1.0;   // 2^-q / q!
+            for (int i = 1; i <= q; ++i) w *= 0.5 / i;
+            double bin = 1.0;   // binom(q, j)
+            for (int j = 0; 2 * j <= q; ++j) {
+                const int m = q - 2 * j;
+                e[m][q] = (float)((m == 0 ? 1.0 : 2.0) * w * bin);
+                bin = bin * (q - j) / (j + 1);
+            }
+        }
+    }
+};
+template <int NQ>
+__device__ constexpr EconTable<NQ> kEcon{};
+
 // Forward term sums. Block = 256 lanes, one image column per lane (nx <=
 // 256), RD_NTB TRs; the lanes walk all rows, keeping the NQ complex sums of
-// each TR in registers; U written once per (term, TR, column), no partials.
+// each TR in registers; then the NC economised sums V_m = sum_q e_mq U_q
+// written once per (term, TR, column), no partials.
 // MODE as the static y-stages: 0 signal, 1 J v with four trains, 3 J v with
 // three (B1 held fixed). db0 (Hz per db0_unit) is the map or theta row 5;
 // with Delta B0 fitted (fit, J v only) the direction's row 5 adds
@@ -104,13 +135,13 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
                                                      const uint8_t* __restrict__ mask,
                                                      const float* __restrict__ db0, float db0_unit, int fit,
                                                      const float2* __restrict__ eytab, float2* __restrict__ U,
-                                                     int nx, int ny, int nv, int T, float te, float tmax)
+                                                     int nc, int nx, int ny, int nv, int T, float te, float tmax)
 {
     constexpr bool JV = MODE != 0, DB1 = MODE == 1;
     const int ix = threadIdx.x;
     const bool colok = ix < nx;
     const int n0 = blockIdx.x * RD_NTB;
-    const int c = blockIdx.y;   // coil: its sums are rows c NQ .. c NQ + NQ - 1
+    const int c = blockIdx.y;   // coil: its sums are rows c nc .. c nc + nc - 1
     const size_t plane = (size_t)T * nv;
     float2 acc[RD_NTB][NQ];
 #pragma unroll
@@ -177,17 +208,25 @@ __global__ __launch_bounds__(256) void rd_fwd_kernel(const TT* __restrict__ trai
 #pragma unroll
         for (int t = 0; t < RD_NTB; ++t) {
             const int n = n0 + t;
-            if (n < T)
+            if (n >= T) continue;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) U[(((size_t)c * NQ + q) * T + n) * nx + ix] = acc[t][q];
+            for (int m = 0; m < NQ; ++m) {
+                float2 vm = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int q = m; q < NQ; q += 2) {
+                    vm.x = fmaf(kEcon<NQ>.e[m][q], acc[t][q].x, vm.x);
+                    vm.y = fmaf(kEcon<NQ>.e[m][q], acc[t][q].y, vm.y);
+                }
+                if (m < nc) U[(((size_t)c * nc + m) * T + n) * nx + ix] = vm;
+            }
         }
     }
 }
 
-// s_c[n,k] = sum_q (u_k^q / q!) Y_cq[n,k]; MODE 0: out = data - s and FP64
+// s_c[n,k] = sum_m T_m(u_k) Y_cm[n,k]; MODE 0: out = data - s and FP64
 // partials of |out|^2 per block; 1: out = -s; 2: out = s.
 template <int MODE>
-__global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restrict__ Y, int nq, float dwell_u,
+__global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restrict__ Y, int nc, float dwell_u,
                                                          const float2* __restrict__ data, float2* __restrict__ out,
                                                          double* __restrict__ red, int C, int T, int nk)
 {
@@ -197,14 +236,20 @@ __global__ __launch_bounds__(256) void rd_combine_kernel(const float2* __restric
         const size_t c = i / count, ii = i % count;
         const int k = (int)(ii % nk);
         const float u = (float)(k - nk / 2) * dwell_u;
-        const float2* yc = Y + c * nq * count + ii;
+        const float2* yc = Y + c * nc * count + ii;
         float2 s = yc[0];
-        float cq = 1.f;
-        for (int q = 1; q < nq; ++q) {
-            cq *= u / (float)q;
-            const float2 y = yc[(size_t)q * count];
-            s.x = fmaf(cq, y.x, s.x);
-            s.y = fmaf(cq, y.y, s.y);
+        float tm1 = 1.f, tm = u;   // T_(m-1), T_m
+        if (nc > 1) {
+            s.x = fmaf(u, yc[count].x, s.x);
+            s.y = fmaf(u, yc[count].y, s.y);
+        }
+        for (int m = 2; m < nc; ++m) {
+            const float tn = fmaf(2.f * u, tm, -tm1);
+            tm1 = tm;
+            tm = tn;
+            const float2 y = yc[(size_t)m * count];
+            s.x = fmaf(tm, y.x, s.x);
+            s.y = fmaf(tm, y.y, s.y);
         }
         if constexpr (MODE == 0) {
             const float2 d = data[i];
@@ -451,15 +496,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 }
 
 template <int NQ, typename TT>
-hipError_t fwd_q(const Dims& d, int mode, const TT* trains, const float* theta, const float* v, const float2* coil,
-                 const uint8_t* mask, const float* db0, float db0_unit, const float2* eytab, float2* U, float te,
-                 float tmax, hipStream_t s)
+hipError_t fwd_q(const Dims& d, int mode, int nc, const TT* trains, const float* theta, const float* v,
+                 const float2* coil, const uint8_t* mask, const float* db0, float db0_unit, const float2* eytab,
+                 float2* U, float te, float tmax, hipStream_t s)
 {
+    if (nc < 1 || nc > NQ) return hipErrorInvalidValue;
     const dim3 grid(ceil_div(d.T, RD_NTB), d.C);
     const int fit = d.np == 6;
 #define RD_FWD(M)                                                                                                 \
-    rd_fwd_kernel<M, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, v, coil, mask, db0, db0_unit, fit, eytab, U, d.nx, \
-                                                  d.ny, d.nv, d.T, te, tmax)
+    rd_fwd_kernel<M, NQ, TT><<<grid, 256, 0, s>>>(trains, theta, v, coil, mask, db0, db0_unit, fit, eytab, U, nc, \
+                                                  d.nx, d.ny, d.nv, d.T, te, tmax)
     switch (mode) {
     case 0: RD_FWD(0); break;
     case 1: RD_FWD(1); break;
@@ -562,7 +608,7 @@ static void rd_source(const Dims& d, const float* theta, const float*& db0, floa
     }
 }
 
-hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bool f16, const float* theta,
+hipError_t launch_rd_fwd(const Dims& d, int nq, int nc, int mode, const void* trains, bool f16, const float* theta,
                          const float* v, const float2* coil, const uint8_t* mask, const float* db0, float db0_unit,
                          const float2* eytab, float2* U, float te, float tmax, hipStream_t s)
 {
@@ -570,29 +616,29 @@ hipError_t launch_rd_fwd(const Dims& d, int nq, int mode, const void* trains, bo
     rd_source(d, theta, db0, db0_unit);
     if (f16) {
         const _Float16* tr = static_cast<const _Float16*>(trains);
-        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
+        RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, nc, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
     }
     const float* tr = static_cast<const float*>(trains);
-    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
+    RD_NQ_DISPATCH(nq, (fwd_q<NQ>(d, mode, nc, tr, theta, v, coil, mask, db0, db0_unit, eytab, U, te, tmax, s)))
 }
 
-hipError_t launch_rd_combine(const Dims& d, int nq, int mode, const float2* Y, float dwell_u, const float2* data,
+hipError_t launch_rd_combine(const Dims& d, int nc, int mode, const float2* Y, float dwell_u, const float2* data,
                              float2* out, double* red, int* nred, hipStream_t s)
 {
     const int blocks = RED_BLOCKS;
     if (nred) *nred = blocks;
     switch (mode) {
-    case 0: rd_combine_kernel<0><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
-    case 1: rd_combine_kernel<1><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
-    case 2: rd_combine_kernel<2><<<blocks, 256, 0, s>>>(Y, nq, dwell_u, data, out, red, d.C, d.T, d.nk); break;
+    case 0: rd_combine_kernel<0><<<blocks, 256, 0, s>>>(Y, nc, dwell_u, data, out, red, d.C, d.T, d.nk); break;
+    case 1: rd_combine_kernel<1><<<blocks, 256, 0, s>>>(Y, nc, dwell_u, data, out, red, d.C, d.T, d.nk); break;
+    case 2: rd_combine_kernel<2><<<blocks, 256, 0, s>>>(Y, nc, dwell_u, data, out, red, d.C, d.T, d.nk); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_rd_expand(const Dims& d, int nq, float dwell_u, const float2* w, float2* wq, hipStream_t s)
+hipError_t launch_rd_expand(const Dims& d, int nc, float dwell_u, const float2* w, float2* wq, hipStream_t s)
 {
-    rd_expand_kernel<<<RED_BLOCKS, 256, 0, s>>>(w, wq, nq, dwell_u, d.C, d.T, d.nk);
+    rd_expand_kernel<<<RED_BLOCKS, 256, 0, s>>>(w, wq, nc, dwell_u, d.C, d.T, d.nk);
     return hipGetLastError();
 }
 

@@ -117,44 +117,51 @@ __global__ __launch_bounds__(RB) void cg_init_finish(const double* __restrict__ 
     }
 }
 
-// Every block reduces the same partials in the same fixed order (the result
-// is identical in all blocks); thread 0's sums are broadcast through LDS.
-__device__ __forceinline__ void reduce_pair(const double* __restrict__ part, int n, double* sh,
-                                            double* bc, double& a, double& b)
+// K kinds of per-block partials ([K][n]) reduced by every block in one fixed
+// order (per thread in index order, then lane 0 of each wave's butterfly,
+// then the four waves in order): the sums are identical in all threads and
+// blocks.
+template <int K>
+__device__ __forceinline__ void reduce_kinds(const double* __restrict__ part, int n, double (&sh)[K][RB / 64],
+                                             double (&v)[K])
 {
-    a = 0.0;
-    b = 0.0;
-    for (int i = threadIdx.x; i < n; i += RB) {
-        a += part[i];
-        b += part[n + i];
-    }
-    a = block_sum(a, sh);
-    b = block_sum(b, sh);
-    if (threadIdx.x == 0) {
-        bc[0] = a;
-        bc[1] = b;
-    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int i = threadIdx.x; i < n; i += RB)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += part[(size_t)k * n + i];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k][wave] = v[k];
     __syncthreads();
-    a = bc[0];
-    b = bc[1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
 }
 
-// kappa = dir.q (from the curvature partials); stop on non-positive
-// curvature; alpha = rr / kappa; then step += alpha dir, res -= alpha q and
-// partial sums of res.res. Block 0 records kappa, dir.dir, alpha and UPD (the
-// iteration updates step, res and dir: CG not stopped before it).
-__global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ dir,
-                                                     const float* __restrict__ q,
-                                                     float* __restrict__ step,
-                                                     float* __restrict__ res, size_t n,
-                                                     const double* __restrict__ curv, int nblk,
-                                                     double* __restrict__ sc, int par,
-                                                     double* __restrict__ part)
+// One CG iteration in one launch. From the finish kernel's partials every
+// block forms kappa = dir . q, dir . dir, rr = res . res, res . q and q . q;
+// CG stops on non-positive curvature or a zero residual; alpha = rr / kappa,
+// and the updated residual's norm is known before any element changes,
+// |res - alpha q|^2 = rr - 2 alpha res . q + alpha^2 q . q, so beta = that / rr
+// and step += alpha dir, res -= alpha q, dir = res + beta dir take one pass.
+// rr itself is always the sum over the stored residual, so the formula's
+// rounding does not accumulate over iterations. Block 0 records kappa,
+// dir . dir, alpha, UPD (the iteration updated the vectors), the new rr and
+// beta, counts the iteration and writes the stop flag for the next one.
+__global__ __launch_bounds__(RB) void cg_update_kernel(const float* __restrict__ q,
+                                                       float* __restrict__ step,
+                                                       float* __restrict__ res,
+                                                       float* __restrict__ dir, size_t n,
+                                                       const double* __restrict__ curv, int nblk,
+                                                       double* __restrict__ sc, int par)
 {
-    __shared__ double sh[RB / 64];
-    __shared__ double bc[2];
-    // This thread's first PF elements and the scalars are loaded before the
-    // reduction of the partials (they do not depend on alpha).
+    __shared__ double sh[5][RB / 64];
+    // This thread's first PF elements and the stop flag are loaded before
+    // the reduction of the partials (they do not depend on it).
     const size_t i0 = (size_t)blockIdx.x * RB + threadIdx.x, stride = (size_t)gridDim.x * RB;
     float rp[PF], dp[PF], sp[PF], qp[PF];
 #pragma unroll
@@ -166,51 +173,56 @@ __global__ __launch_bounds__(RB) void cg_step_kernel(const float* __restrict__ d
         sp[e] = ok ? step[i] : 0.f;
         qp[e] = ok ? q[i] : 0.f;
     }
-    const double done = sc[done_slot(par)], rr = sc[rr_slot(par)];
-    double kappa, dd;
-    reduce_pair(curv, nblk, sh, bc, kappa, dd);
-    const bool upd = done == 0.0 && !(kappa <= 1e-30 * dd);
+    const double done = sc[done_slot(par)];
+    double v[5];
+    reduce_kinds<5>(curv, nblk, sh, v);
+    const double kappa = v[0], dd = v[1], rr = v[2], rq = v[3], qq = v[4];
+    const bool upd = done == 0.0 && rr != 0.0 && !(kappa <= 1e-30 * dd);
     const double alpha = upd ? rr / kappa : 0.0;
+    const float al = (float)alpha;
+    const double a = al;   // the step the elements take
+    double rn = fma(a * a, qq, fma(-2.0 * a, rq, rr));
+    if (rn < 0.0) rn = 0.0;
+    const double beta = upd ? rn / rr : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc[S_KAPPA] = kappa;
         sc[S_DD] = dd;
         sc[S_UPD] = upd ? 1.0 : 0.0;
         sc[S_ALPHA] = alpha;
+        if (upd) {
+            sc[S_RRNEW] = rn;
+            sc[S_BETA] = beta;
+            sc[S_ITERS] += 1.0;
+        }
+        sc[rr_slot(par ^ 1)] = upd ? rn : rr;
+        sc[done_slot(par ^ 1)] = (!upd || rn == 0.0) ? 1.0 : 0.0;
     }
-    const float al = (float)alpha;
-    double v = 0.0;
+    if (!upd) return;
+    const float b = (float)beta;
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
         const size_t i = i0 + e * stride;
         if (i >= n) break;
-        float r = rp[e];
-        if (upd) {
-            step[i] = fmaf(al, dp[e], sp[e]);
-            r = fmaf(-al, qp[e], r);
-            res[i] = r;
-        }
-        v += (double)r * (double)r;
+        const float r = fmaf(-al, qp[e], rp[e]);
+        step[i] = fmaf(al, dp[e], sp[e]);
+        res[i] = r;
+        dir[i] = fmaf(b, dp[e], r);
     }
     for (size_t i = i0 + PF * stride; i < n; i += stride) {
-        float r = res[i];
-        if (upd) {
-            step[i] = fmaf(al, dir[i], step[i]);
-            r = fmaf(-al, q[i], r);
-            res[i] = r;
-        }
-        v += (double)r * (double)r;
+        const float dv = dir[i];
+        const float r = fmaf(-al, q[i], res[i]);
+        step[i] = fmaf(al, dv, step[i]);
+        res[i] = r;
+        dir[i] = fmaf(b, dv, r);
     }
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// beta = rr_new / rr, dir = res + beta dir. Block 0 records rr_new and beta,
-// counts the iteration and writes rr and the stop flag for the next
-// iteration (a zero residual, or a stopped iteration, stops CG).
-// With TR (the trust-region CG) block 0 also records |step|^2 from the step
-// kernel's partials (zzp) and marks a zero residual as the exit kind.
-template <bool TR>
-__global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ res,
+// The trust-region CG's direction: beta = rr_new / rr from the step kernel's
+// res . res partials, dir = res + beta dir. Block 0 records rr_new, beta and
+// |step|^2 (from the step kernel's partials zzp), counts the iteration,
+// writes rr and the stop flag for the next iteration (a zero residual, or a
+// stopped iteration, stops CG) and marks a zero residual as the exit kind.
+__global__ __launch_bounds__(RB) void tr_dir_kernel(const float* __restrict__ res,
                                                     float* __restrict__ dir, size_t n,
                                                     const double* __restrict__ part, int nblk,
                                                     double* __restrict__ sc, int par,
@@ -218,7 +230,7 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
 {
     __shared__ double sh[RB / 64];
     __shared__ double bc[1];
-    // First PF elements and the scalars ahead of the reduction (as above).
+    // First PF elements and the scalars ahead of the reduction.
     const size_t i0 = (size_t)blockIdx.x * RB + threadIdx.x, stride = (size_t)gridDim.x * RB;
     float rp[PF], dp[PF];
 #pragma unroll
@@ -238,10 +250,8 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
     v = bc[0];
     const double beta = upd ? v / rr : 0.0;
     double zz = 0.0;
-    if constexpr (TR) {
-        for (int i = threadIdx.x; i < nblk; i += RB) zz += zzp[i];
-        zz = block_sum(zz, sh);
-    }
+    for (int i = threadIdx.x; i < nblk; i += RB) zz += zzp[i];
+    zz = block_sum(zz, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (upd) {
             sc[S_RRNEW] = v;
@@ -250,10 +260,8 @@ __global__ __launch_bounds__(RB) void cg_dir_kernel(const float* __restrict__ re
         }
         sc[rr_slot(par ^ 1)] = upd ? v : rr;
         sc[done_slot(par ^ 1)] = (!upd || v == 0.0) ? 1.0 : 0.0;
-        if constexpr (TR) {
-            sc[SC_ZZ] = zz;
-            if (upd && v == 0.0) sc[SC_EXIT] = 3.0;
-        }
+        sc[SC_ZZ] = zz;
+        if (upd && v == 0.0) sc[SC_EXIT] = 3.0;
     }
     if (!upd) return;
     const float b = (float)beta;
@@ -643,18 +651,15 @@ hipError_t launch_cg_init(const Dims& d, const float* g, float* step, float* res
     return hipGetLastError();
 }
 
-int cg_partials(const Dims& d) { return 2 * ((d.nv + 255) / 256) + RED_BLOCKS; }
+int cg_partials(const Dims& d) { return 5 * ((d.nv + 255) / 256); }
 
 hipError_t launch_cg_update(const Dims& d, const float* q, float* step, float* res, float* dir,
                             double* scal, double* partials, int iter, hipStream_t s)
 {
-    // partials: curvature pairs [2][nb] from the finish kernel, then res.res
-    // [RED_BLOCKS].
+    // partials: [5][nb] from the finish kernel.
     const size_t n = (size_t)d.np * d.nv;
     const int nb = (d.nv + 255) / 256;
-    double* rrp = partials + 2 * nb;
-    cg_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp);
-    cg_dir_kernel<false><<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1, nullptr);
+    cg_update_kernel<<<RED_BLOCKS, RB, 0, s>>>(q, step, res, dir, n, partials, nb, scal, iter & 1);
     return hipGetLastError();
 }
 
@@ -676,7 +681,7 @@ hipError_t launch_tr_update(const Dims& d, const float* q, float* step, float* r
     double* rrp = partials + 3 * nb;
     double* zzp = rrp + RED_BLOCKS;
     tr_step_kernel<<<RED_BLOCKS, RB, 0, s>>>(dir, q, step, res, n, partials, nb, scal, iter & 1, rrp, zzp);
-    cg_dir_kernel<true><<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1, zzp);
+    tr_dir_kernel<<<RED_BLOCKS, RB, 0, s>>>(res, dir, n, rrp, RED_BLOCKS, scal, iter & 1, zzp);
     return hipGetLastError();
 }
 

@@ -303,12 +303,12 @@ def noncartesian(torch, work, reps=5, with_oracle=True):
 
 def readout_dynamics(torch, work, n_cg, steps=3, with_oracle=True):
     """The benchmark workload with T2 decay and off-resonance during every
-    readout (448 samples at 85.6 kHz: 24 expansion terms for T2 >= 5 ms and
-    |Delta B0| <= 200 Hz) and a smooth +-150 Hz off-resonance field: GN steps
-    (five parameters with the field as a map; six with Delta B0 fitted) and
-    the cached J v + J^H w pair with per-kernel times; plain EPG, FP32 trains,
-    split-BF16 contraction. The x-GEMMs carry the expansion terms as rows:
-    8 NQ T nx nk algorithmic flop per product."""
+    readout (448 samples at 85.6 kHz: 24 power-series and 16 Chebyshev terms
+    for T2 >= 5 ms and |Delta B0| <= 200 Hz) and a smooth +-150 Hz
+    off-resonance field: GN steps (five parameters with the field as a map;
+    six with Delta B0 fitted) and the cached J v + J^H w pair with per-kernel
+    times; plain EPG, FP32 trains, split-BF16 contraction. The x-GEMMs carry
+    the Chebyshev terms as rows: 8 NC T nx nk algorithmic flop per product."""
     import dataclasses
 
     from paper_1904_13244_amd import binding as B
@@ -366,15 +366,15 @@ def readout_dynamics(torch, work, n_cg, steps=3, with_oracle=True):
         pairs(3)
         prof = ctx.profile_read()
         ctx.profile(False)
-        nq = ctx.readout_terms()
-        flop = 8.0 * nq * prob.n_tr * prob.nx * prob.n_read
+        nq, ncheb = ctx.readout_terms(), ctx.readout_cheb_terms()
+        flop = 8.0 * ncheb * prob.n_tr * prob.nx * prob.n_read
         kern = {k: {"launches": n, "avg_ms": ms / n} for k, (n, ms) in prof.items() if n}
         for k in ("xgemm_fwd", "xgemm_adj"):
             if k in kern:
                 ach = flop / (kern[k]["avg_ms"] * 1e-3) / 1e12
                 kern[k].update({"algorithmic_tflops": ach, "mfma_tflops_issued": 3 * ach,
                                 "peak_tflops": BF16_MFMA_PEAK_TFLOPS, "frac": 3 * ach / BF16_MFMA_PEAK_TFLOPS})
-        out[name] = {"terms": nq, "gn_step_ms": step_ms, "pairs_per_s_gn": n_cg * 1e3 / step_ms,
+        out[name] = {"terms": nq, "cheb_terms": ncheb, "gn_step_ms": step_ms, "pairs_per_s_gn": n_cg * 1e3 / step_ms,
                      "pair_cached_ms": pair_ms, "kernels_per_pair": kern, "param_mask": pm,
                      "gn_report_last": rep.as_dict()}
         ctx.close()

@@ -251,6 +251,11 @@ mrstat_status mrstat_fit_db0(mrstat_ctx ctx, double hz_per_unit);
  * other contexts). */
 mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t *h_terms);
 
+/* Terms of the readout-dynamics Chebyshev expansion: the rows per coil of the
+ * x-stages and the adjoint's term sums, at most mrstat_readout_terms (0 for
+ * other contexts). */
+mrstat_status mrstat_readout_cheb_terms(mrstat_ctx ctx, int32_t *h_terms);
+
 /* Signal model of the linearisation: the gradient-spoiled EPG (n_iso = 0,
  * the default) or the balanced isochromat model of the paper's own sequence
  * (Methods, Pulse Sequence and Reconstructions; Supporting Information S2):

@@ -89,6 +89,7 @@ def lib():
                                       C.c_int),
             "mrstat_set_db0": ([vp, vp], C.c_int),
             "mrstat_readout_terms": ([vp, P(i32)], C.c_int),
+            "mrstat_readout_cheb_terms": ([vp, P(i32)], C.c_int),
             "mrstat_fit_db0": ([vp, C.c_double], C.c_int),
             "mrstat_destroy": ([vp], None),
             "mrstat_last_error": ([vp], C.c_char_p),
@@ -149,7 +150,7 @@ def exported_symbols():
             "mrstat_mlp_predict", "mrstat_mlp_set_infer_tile", "mrstat_set_train_precision",
             "mrstat_profile_select", "mrstat_bind_static", "mrstat_tr_step", "mrstat_create_traj",
             "mrstat_set_isochromats", "mrstat_create_readout", "mrstat_set_db0",
-            "mrstat_readout_terms", "mrstat_fit_db0"]
+            "mrstat_readout_terms", "mrstat_readout_cheb_terms", "mrstat_fit_db0"]
 
 
 def _check(status, ctx=None):
@@ -242,6 +243,12 @@ def mrstat_fit_db0(ctx, hz_per_unit):
 def mrstat_readout_terms(ctx):
     n = C.c_int32()
     _check(lib().mrstat_readout_terms(ctx, C.byref(n)), ctx)
+    return int(n.value)
+
+
+def mrstat_readout_cheb_terms(ctx):
+    n = C.c_int32()
+    _check(lib().mrstat_readout_cheb_terms(ctx, C.byref(n)), ctx)
     return int(n.value)
 
 
@@ -492,6 +499,9 @@ class Context:
 
     def readout_terms(self):
         return mrstat_readout_terms(self.h)
+
+    def readout_cheb_terms(self):
+        return mrstat_readout_cheb_terms(self.h)
 
     def set_train_precision(self, prec):
         mrstat_set_train_precision(self.h, prec)

@@ -576,6 +576,13 @@ mrstat_status mrstat_readout_terms(mrstat_ctx ctx, int32_t* h_terms)
     return MRSTAT_OK;
 }
 
+mrstat_status mrstat_readout_cheb_terms(mrstat_ctx ctx, int32_t* h_terms)
+{
+    if (!ctx || !h_terms) return MRSTAT_ERR_ARG;
+    *h_terms = ctx->rd_nc;
+    return MRSTAT_OK;
+}
+
 void mrstat_destroy(mrstat_ctx ctx)
 {
     if (!ctx) return;

@@ -359,7 +359,9 @@ __device__ __forceinline__ void cheb_coeffs(float2 Lf, float2 (&ca)[NC], float2 
 // for cache reuse of W 0.92; double-buffered term loads need 256 registers;
 // two voxels of a column per thread, sharing each TR's term loads, 0.59; the
 // Chebyshev form, 16 terms for the same bound, 0.52 (and its adjoint x-GEMM
-// 0.084 instead of 0.122).
+// 0.084 instead of 0.122). TR chunks (HIP events, 16 terms): 9 chunks
+// 0.53-0.57, 18 0.55; 8, 16, 24 and 32 chunks with each XCD given its own
+// chunks (so its L2 holds only their term values) 0.58, 0.60, 0.58, 0.61.
 // Voxels per thread of the adjoint (rows iy, iy + hy, ... of one column):
 // two while each voxel's coefficients and the loaded terms fit the registers.
 template <int NQ>

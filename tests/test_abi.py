@@ -2,6 +2,7 @@
 every function include/mrstat.h declares, and validates problems and
 arguments before any device work."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -96,11 +97,21 @@ def _expected_terms(prob):
     """Smallest term count of 8, 12, 16, 20, 24, 32 whose remainder bound
     e^b b^(NQ-1) / (NQ-1)! is at most 1e-7, b = (1 / min_t2 + 2 pi max|db0|)
     tau_max, tau_max = (n_read / 2) dwell (0: none)."""
-    import math
     b = (1.0 / prob.rd_min_t2 + 2 * math.pi * prob.rd_max_db0) * (prob.n_read // 2) * prob.dwell
     for nq in (8, 12, 16, 20, 24, 32):
         if math.exp(b) * b ** (nq - 1) / math.factorial(nq - 1) <= 1e-7:
             return nq
+    return 0
+
+
+def _expected_cheb_terms(prob):
+    """The Chebyshev count for the same bound b: the fewest terms NC with
+    2 (b/2)^(NC-1) / (NC-1)! e^(b^2 / (4 NC)) / (1 - b / (2 NC)) <= 1e-7."""
+    b = (1.0 / prob.rd_min_t2 + 2 * math.pi * prob.rd_max_db0) * (prob.n_read // 2) * prob.dwell
+    for nc in (8, 12, 16, 20, 24, 32):
+        if b < 2 * nc and (2 * (b / 2) ** (nc - 1) / math.factorial(nc - 1) * math.exp(b * b / (4 * nc))
+                           / (1 - b / (2 * nc))) <= 1e-7:
+            return nc
     return 0
 
 
@@ -119,6 +130,8 @@ def test_readout_context_terms_and_refusals():
         h = B.mrstat_create(prob)
         try:
             assert B.mrstat_readout_terms(h) == want, (n_read, dwell, db0)
+            nc = B.mrstat_readout_cheb_terms(h)
+            assert nc == _expected_cheb_terms(prob) and 0 < nc <= want, (n_read, dwell, db0, nc)
         finally:
             B.mrstat_destroy(h)
         seen.add(want)
@@ -134,7 +147,7 @@ def test_readout_context_terms_and_refusals():
     # the off-resonance map: readout contexts only, and not with the balanced model
     h = B.mrstat_create(base)
     try:
-        assert B.mrstat_readout_terms(h) == 0
+        assert B.mrstat_readout_terms(h) == 0 and B.mrstat_readout_cheb_terms(h) == 0
         assert B.lib().mrstat_set_db0(h, C.c_void_p(4096)) == B.ERR_STATE
     finally:
         B.mrstat_destroy(h)

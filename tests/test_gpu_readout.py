@@ -87,6 +87,7 @@ def _case(name):
 
 
 TERMS = {"small": 12, "ragged": 16, "half_bandwidth": 20, "quarter_bandwidth": 32}
+CHEB_TERMS = {"small": 8, "ragged": 12, "half_bandwidth": 16, "quarter_bandwidth": 20}
 
 
 @pytest.fixture(scope="module", params=list(TERMS))
@@ -98,6 +99,7 @@ def case(request, torch_gpu, oracle_lib):
           f"dwell={prob.dwell:.3e}", flush=True)
     ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
     assert ctx.readout_terms() == TERMS[request.param]
+    assert ctx.readout_cheb_terms() == CHEB_TERMS[request.param]
     ora = oracle_lib.epg(prob, th)
     v, w = I.probe_vectors(prob)
     yield dict(name=request.param, prob=prob, th=th, mask=mask, ctx=ctx, ora=ora, v=v, w=w, torch=torch)
@@ -291,7 +293,7 @@ def test_fullsize_sampled(torch_gpu, oracle_lib, fit):
     ora = np.zeros((4, prob.n_tr, prob.nv), np.complex128)
     ora[:, :, sel] = oracle_lib.epg(sub, th[:5, sel])
     ctx = Context(prob, mask=_dev(torch, mask, torch.uint8))
-    assert ctx.readout_terms() == 24
+    assert ctx.readout_terms() == 24 and ctx.readout_cheb_terms() == 16
     thd = _dev(torch, th, torch.float32)
     ctx.linearise(thd)
     got = ctx.simulate(thd).cpu().numpy().astype(np.float64)
@@ -474,7 +476,7 @@ def test_coils_products_steps_and_rho_init(torch_gpu, oracle_lib, fit):
         th = np.vstack([th, (prob.db0 / unit)[None, :]]).astype(np.float32).astype(np.float64)
         prob = dataclasses.replace(prob, db0=None, db0_unit=unit)
     ctx = Context(prob, coil=_dev(torch, coil, torch.complex64), mask=_dev(torch, mask, torch.uint8))
-    assert ctx.readout_terms() == 12
+    assert ctx.readout_terms() == 12 and ctx.readout_cheb_terms() == 8
     ora = oracle_lib.epg(prob, th)
     s = oracle_lib.signal(prob, th, ora, coil=coil, mask=mask)
     n = I.unit_noise(prob)
@@ -532,7 +534,7 @@ def test_expansion_at_its_bounds(torch_gpu, oracle_lib):
     th[1] = np.log(0.005)
     th = th.astype(np.float32).astype(np.float64)
     ctx = Context(prob)
-    assert ctx.readout_terms() == 24
+    assert ctx.readout_terms() == 24 and ctx.readout_cheb_terms() == 16
     ora = oracle_lib.epg(prob, th)
     s = oracle_lib.signal(prob, th, ora)
     zeros = torch.zeros(prob.data_shape, dtype=torch.complex64, device="cuda")

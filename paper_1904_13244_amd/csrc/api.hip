@@ -26,6 +26,7 @@ struct Layout {
     size_t hbuf;       // surrogate hidden activations, BF16 [nv][256]
     size_t cx, csv, cp, cth, fb, total;
     size_t ax, ay;     // non-Cartesian trajectory tables, FP64 [T][nk] (0 bytes otherwise)
+    size_t ncx;        // non-Cartesian forward voxel values [T][nv] complex (0 bytes otherwise)
     size_t rdU, rdY, rdw, rdW;   // readout-dynamics term buffers (0 bytes otherwise)
     int n_red;
     YPlan yp;
@@ -92,6 +93,7 @@ struct mrstat_ctx_s {
     const float2* deytab() const { return at<float2>(L.eytab); }
     const float2* dextab() const { return at<float2>(L.extab); }
     const double* dax() const { return at<double>(L.ax); }
+    float2* ncx() const { return at<float2>(L.ncx); }
     const double* day() const { return at<double>(L.ay); }
     // B-fragment table of the current encoding for direction dir (null for FP32).
     const void* bfrag(int dir) const { return enc == 0 ? nullptr : (const void*)(ws + L.bf[dir][enc - 1]); }
@@ -202,6 +204,7 @@ Layout make_layout(const Dims& d, bool nc, int rd_rows = 0)
     L.hbuf = take(nv * 256 * sizeof(uint16_t));
     L.ax = take(nc ? T * d.nk * sizeof(double) : 0);
     L.ay = take(nc ? T * d.nk * sizeof(double) : 0);
+    L.ncx = take(nc ? T * nv * sizeof(float2) : 0);
     const size_t nq = rd_rows > 0 ? (size_t)rd_rows * d.C : 0;   // rows per TR: coils x terms
     L.rdU = take(nq * T * d.nx * sizeof(float2));
     L.rdY = take(nq * T * d.nk * sizeof(float2));
@@ -371,7 +374,7 @@ mrstat_status forward(mrstat_ctx ctx, int mode_y, int mode_x, const void* trains
     if (ctx->nc) {
         int nred = 0;
         HIP_TRY(TRACED(MRSTAT_K_NC_FWD, launch_nc_fwd(d, ctx->enc, mode_y, mode_x, trains, ctx->f16, theta, v,
-                                                      ctx->coil, ctx->mask, ctx->dax(), ctx->day(),
+                                                      ctx->coil, ctx->mask, ctx->dax(), ctx->day(), ctx->ncx(),
                                                       (const float2*)data, (float2*)out, ctx->red(), &nred, s)));
         if (mode_x == 0 && f_out)
             HIP_TRY(TRACED(MRSTAT_K_VECTOR, launch_sum_partials(ctx->red(), nred, f_out, s)));

@@ -28,10 +28,11 @@ struct Dims {
 // or 1) in the Cartesian adjoint's layout, with `chunks` TR chunks.
 int nc_adj_chunks(const Dims& d);
 int nc_fwd_blocks(const Dims& d);
+// X: workspace [T][nv] complex for the forward's voxel values.
 hipError_t launch_nc_fwd(const Dims& d, int enc, int mode_y, int mode_x, const void* trains, bool f16,
                          const float* theta, const float* v, const float2* coil, const uint8_t* mask,
-                         const double* ax, const double* ay, const float2* data, float2* out, double* red,
-                         int* nred, hipStream_t s);
+                         const double* ax, const double* ay, float2* X, const float2* data, float2* out,
+                         double* red, int* nred, hipStream_t s);
 hipError_t launch_nc_adj(const Dims& d, int enc, int ntr, int chunks, const void* trains, bool f16,
                          const float2* coil, const uint8_t* mask, const double* ax, const double* ay,
                          const float2* w, float* apart, hipStream_t s);

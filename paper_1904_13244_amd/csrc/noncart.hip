@@ -74,26 +74,60 @@ template <typename TT>
 __device__ __forceinline__ float ld_train(const TT* p) { return (float)*p; }
 
 // ------------------------------------------------------------------------
+// Voxel values of the forward, once per product: X[n][j] = i rho_j mu0[n,j]
+// (NTRV 1, the signal) or i (rho_j sum_p v_p dm_p/dtheta_p + (v3 + i v4) mu0)
+// (NTRV 4: all tangents; 3: without dm/dB1, whose direction entry is 0);
+// zero for masked voxels. A streaming pass over the trains.
+// ------------------------------------------------------------------------
+template <int NTRV, typename TT>
+__global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
+                                                   const float* __restrict__ v, const uint8_t* __restrict__ mask,
+                                                   float2* __restrict__ X, int nv, int T)
+{
+    const size_t count = (size_t)T * nv, plane = count;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i % nv);
+        float xr = 0.f, xi = 0.f;
+        if (mask == nullptr || mask[j] != 0) {
+            const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
+            const float mu0 = ld_train(trains + i);
+            if constexpr (NTRV == 1) {
+                xr = -ri * mu0;
+                xi = rr * mu0;
+            } else {
+                float t = 0.f;
+#pragma unroll
+                for (int q = 0; q < NTRV - 1; ++q) t = fmaf(v[(size_t)q * nv + j], ld_train(trains + (q + 1) * plane + i), t);
+                const float v3 = v[3 * (size_t)nv + j], v4 = v[4 * (size_t)nv + j];
+                // x = i (rho t + (v3 + i v4) mu0)
+                xr = -(ri * t + v4 * mu0);
+                xi = rr * t + v3 * mu0;
+            }
+        }
+        X[i] = make_float2(xr, xi);
+    }
+}
+
+// ------------------------------------------------------------------------
 // Forward: a block of 4 waves per (TR n, 64 samples, coil); wave w owns
 // samples k0 = 64 kt + 16 w .. +15. Its A fragments (Ex of its 16 samples
 // over all nx columns, KS K-steps) are generated once and kept in registers;
-// the voxel values X of 32 image rows at a time are built in LDS from the
-// trains (ENC 1: split into bf16 hi/lo words), then each wave multiplies
-// them for 4 column blocks of 8 rows, and the epilogue applies Ey and sums
-// over the rows. Blocks are dealt so that the sample tiles of one TR share an
-// XCD (its trains come through one L2).
+// the voxel values X of 32 image rows at a time are staged in LDS (times the
+// coil weight; ENC 1: split into bf16 hi/lo words), NC_XB of each thread's
+// loads issued together, then each wave multiplies them for 4 column blocks
+// of 8 rows, and the epilogue applies Ey and sums over the rows. Blocks are
+// dealt so that the sample tiles of one TR share an XCD (its voxel values
+// come through one L2).
 // MODE 0: out = data - s (and FP64 partials of |out|^2); 1: out = -s; 2: s.
-// NTRV: voxel values from the m train (1: x = i rho mu0) or from the J v
-// direction (4: all tangents; 3: without dm/dB1, whose direction entry is 0).
 // ------------------------------------------------------------------------
 constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
 constexpr int NC_KS1 = 16;    // BF16 K-steps of 32 real k: nx <= 256
 constexpr int NC_ROWS = 32;   // image rows per LDS tile
+constexpr int NC_XB = 7;      // voxel values per thread loaded together (32 x 224 = 256 x 4 x 7)
 
-template <int ENC, int MODE, int NTRV, typename TT>
+template <int ENC, int MODE>
 __global__ __launch_bounds__(256) void nc_fwd_kernel(
-    const TT* __restrict__ trains, const float* __restrict__ theta, const float* __restrict__ v,
-    const float2* __restrict__ coil, const uint8_t* __restrict__ mask, const double* __restrict__ ax,
+    const float2* __restrict__ X, const float2* __restrict__ coil, const double* __restrict__ ax,
     const double* __restrict__ ay, const float2* __restrict__ data, float2* __restrict__ out,
     double* __restrict__ red, int nx, int ny, int nv, int T, int nk, int KT, int nxp)
 {
@@ -153,45 +187,34 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
 
     float sacc[4] = {0.f, 0.f, 0.f, 0.f};
     const int b = lane & 1;
-    const size_t plane = (size_t)T * nv;
+    const float2* Xn = X + (size_t)n * nv;
     float2* xs0 = reinterpret_cast<float2*>(nc_smem);               // ENC 0: [ROWS][nxp]
     uint2* xs1 = reinterpret_cast<uint2*>(nc_smem);                 // ENC 1: [ROWS][nxp] (hi, lo)
+    const int tile_n = NC_ROWS * nxp;
     for (int iy0 = 0; iy0 < ny; iy0 += NC_ROWS) {
         __syncthreads();   // the previous tile has been read
-        for (int e = tid; e < NC_ROWS * nxp; e += 256) {
-            const int r = e / nxp, ix = e % nxp;
-            const int iy = iy0 + r;
-            float xr = 0.f, xi = 0.f;
-            if (ix < nx && iy < ny) {
-                const int j = iy * nx + ix;
-                if (mask == nullptr || mask[j] != 0) {
-                    const float rr = theta[3 * (size_t)nv + j], ri = theta[4 * (size_t)nv + j];
-                    const float mu0 = ld_train(trains + (size_t)n * nv + j);
-                    if constexpr (NTRV == 1) {
-                        xr = -ri * mu0;
-                        xi = rr * mu0;
-                    } else {
-                        float t = 0.f;
+        for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
+            float2 xv[NC_XB], cv[NC_XB];
 #pragma unroll
-                        for (int q = 0; q < NTRV - 1; ++q)
-                            t = fmaf(v[(size_t)q * nv + j], ld_train(trains + (q + 1) * plane + (size_t)n * nv + j), t);
-                        const float v3 = v[3 * (size_t)nv + j], v4 = v[4 * (size_t)nv + j];
-                        // x = i (rho t + (v3 + i v4) mu0)
-                        xr = -(ri * t + v4 * mu0);
-                        xi = rr * t + v3 * mu0;
-                    }
-                    if (coil != nullptr) {
-                        const float2 cc = coil[(size_t)c * nv + j];
-                        const float tr = cc.x * xr - cc.y * xi;
-                        xi = cc.x * xi + cc.y * xr;
-                        xr = tr;
-                    }
-                }
+            for (int u = 0; u < NC_XB; ++u) {
+                const int e = e0 + 256 * u;
+                const int r = e / nxp, ix = e % nxp, iy = iy0 + r;
+                const bool ok = e < tile_n && ix < nx && iy < ny;
+                const size_t j = ok ? (size_t)iy * nx + ix : 0;
+                xv[u] = ok ? Xn[j] : make_float2(0.f, 0.f);
+                cv[u] = coil != nullptr && ok ? coil[(size_t)c * nv + j] : make_float2(1.f, 0.f);
             }
-            if constexpr (ENC == 0)
-                xs0[e] = make_float2(xr, xi);
-            else
-                xs1[e] = split_pair(xr, xi);
+#pragma unroll
+            for (int u = 0; u < NC_XB; ++u) {
+                const int e = e0 + 256 * u;
+                if (e >= tile_n) break;
+                const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
+                const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
+                if constexpr (ENC == 0)
+                    xs0[e] = make_float2(xr, xi);
+                else
+                    xs1[e] = split_pair(xr, xi);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -448,38 +471,41 @@ __global__ __launch_bounds__(256) void nc_adj_kernel(
         }
 }
 
-template <int ENC, int MODE, int NTRV, typename TT>
-hipError_t fwd_launch(const Dims& d, const TT* trains, const float* theta, const float* v, const float2* coil,
-                      const uint8_t* mask, const double* ax, const double* ay, const float2* data,
-                      float2* out, double* red, int* nred, hipStream_t s)
+template <typename TT>
+hipError_t x_launch(const Dims& d, int mode_y, const TT* trains, const float* theta, const float* v,
+                    const uint8_t* mask, float2* X, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)std::min<size_t>(((size_t)d.T * d.nv + 255) / 256, 8192);
+    switch (mode_y) {
+    case 0: nc_x_kernel<1, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    case 1: nc_x_kernel<4, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    case 3: nc_x_kernel<3, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int ENC, int MODE>
+hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const double* ax, const double* ay,
+                      const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
     const int KT = ceil_div(d.nk, 64);
     const int nxp = ceil_div(d.nx, 16) * 16;
     const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
     const size_t lds = (size_t)NC_ROWS * nxp * 8;
-    nc_fwd_kernel<ENC, MODE, NTRV, TT><<<grid, 256, lds, s>>>(trains, theta, v, coil, mask, ax, ay, data, out,
-                                                               red, d.nx, d.ny, d.nv, d.T, d.nk, KT, nxp);
+    nc_fwd_kernel<ENC, MODE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T, d.nk,
+                                                    KT, nxp);
     if (nred) *nred = (int)(grid.x * grid.y);
     return hipGetLastError();
 }
 
-template <int ENC, typename TT>
-hipError_t fwd_mode(const Dims& d, int mode_y, int mode_x, const TT* trains, const float* theta,
-                    const float* v, const float2* coil, const uint8_t* mask, const double* ax,
-                    const double* ay, const float2* data, float2* out, double* red, int* nred,
-                    hipStream_t s)
+template <int ENC>
+hipError_t fwd_mode(const Dims& d, int mode_x, const float2* X, const float2* coil, const double* ax,
+                    const double* ay, const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
-#define NC_FWD(MX, NT) fwd_launch<ENC, MX, NT, TT>(d, trains, theta, v, coil, mask, ax, ay, data, out, red, nred, s)
-    if (mode_y == 0) {
-        if (mode_x == 0) return NC_FWD(0, 1);
-        if (mode_x == 1) return NC_FWD(1, 1);
-        return NC_FWD(2, 1);
-    }
-    const bool four = mode_y == 1;
-    if (mode_x == 0) return four ? NC_FWD(0, 4) : NC_FWD(0, 3);
-    if (mode_x == 1) return four ? NC_FWD(1, 4) : NC_FWD(1, 3);
-    return four ? NC_FWD(2, 4) : NC_FWD(2, 3);
-#undef NC_FWD
+    if (mode_x == 0) return fwd_launch<ENC, 0>(d, X, coil, ax, ay, data, out, red, nred, s);
+    if (mode_x == 1) return fwd_launch<ENC, 1>(d, X, coil, ax, ay, data, out, red, nred, s);
+    return fwd_launch<ENC, 2>(d, X, coil, ax, ay, data, out, red, nred, s);
 }
 
 template <int ENC, typename TT>
@@ -522,19 +548,15 @@ int nc_fwd_blocks(const Dims& d) { return 8 * ceil_div(d.nk, 64) * ceil_div(d.T,
 
 hipError_t launch_nc_fwd(const Dims& d, int enc, int mode_y, int mode_x, const void* trains, bool f16,
                          const float* theta, const float* v, const float2* coil, const uint8_t* mask,
-                         const double* ax, const double* ay, const float2* data, float2* out, double* red,
-                         int* nred, hipStream_t s)
+                         const double* ax, const double* ay, float2* X, const float2* data, float2* out,
+                         double* red, int* nred, hipStream_t s)
 {
     if (d.nx > 256) return hipErrorInvalidValue;
-    if (enc == 0)
-        return f16 ? fwd_mode<0>(d, mode_y, mode_x, static_cast<const _Float16*>(trains), theta, v, coil, mask, ax,
-                                 ay, data, out, red, nred, s)
-                   : fwd_mode<0>(d, mode_y, mode_x, static_cast<const float*>(trains), theta, v, coil, mask, ax, ay,
-                                 data, out, red, nred, s);
-    return f16 ? fwd_mode<1>(d, mode_y, mode_x, static_cast<const _Float16*>(trains), theta, v, coil, mask, ax, ay,
-                             data, out, red, nred, s)
-               : fwd_mode<1>(d, mode_y, mode_x, static_cast<const float*>(trains), theta, v, coil, mask, ax, ay,
-                             data, out, red, nred, s);
+    const hipError_t e = f16 ? x_launch(d, mode_y, static_cast<const _Float16*>(trains), theta, v, mask, X, s)
+                             : x_launch(d, mode_y, static_cast<const float*>(trains), theta, v, mask, X, s);
+    if (e != hipSuccess) return e;
+    return enc == 0 ? fwd_mode<0>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s)
+                    : fwd_mode<1>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s);
 }
 
 hipError_t launch_nc_adj(const Dims& d, int enc, int ntr, int chunks, const void* trains, bool f16,

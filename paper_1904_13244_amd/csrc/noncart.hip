@@ -40,6 +40,11 @@ __device__ __forceinline__ float2 phase_of(double a, int x)
     return make_float2(cs, sn);
 }
 
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
 __device__ __forceinline__ unsigned int bf16_rne(float x)
 {
     const unsigned int u = __float_as_uint(x);
@@ -124,6 +129,7 @@ constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
 constexpr int NC_KS1 = 16;    // BF16 K-steps of 32 real k: nx <= 256
 constexpr int NC_ROWS = 32;   // image rows per LDS tile
 constexpr int NC_XB = 7;      // voxel values per thread loaded together (32 x 224 = 256 x 4 x 7)
+static_assert(NC_ROWS == 32, "forward tile: 4 column blocks of 8 rows per lane group");
 
 template <int ENC, int MODE>
 __global__ __launch_bounds__(256) void nc_fwd_kernel(
@@ -154,28 +160,45 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
     float a0[ENC == 0 ? NC_KS0 : 1];
     uint4 ahi[ENC == 1 ? NC_KS1 : 1], alo[ENC == 1 ? NC_KS1 : 1];
     int KS;
+    // The phases along a row of Ex are a geometric sequence: a lane's columns
+    // come in groups whose first phase is taken from sin/cos and the others
+    // as its products with the phases of the group's offsets.
     if constexpr (ENC == 0) {
         KS = (2 * nx + 3) / 4;
+        // columns ix = 2 s + h/2, s = 8 g + o: phase(16 g + h/2) phase(2 o)
+        float2 off[8];
 #pragma unroll
-        for (int s = 0; s < NC_KS0; ++s) {
-            float val = 0.f;
-            const int ix = 2 * s + (h >> 1);
-            if (s < KS && krow_ok && ix < nx) {
-                const float2 e = phase_of(axk, ix - nx / 2);
-                val = (h & 1) ? e.y : e.x;
+        for (int o = 0; o < 8; ++o) off[o] = o == 0 ? make_float2(1.f, 0.f) : phase_of(axk, 2 * o);
+#pragma unroll
+        for (int g = 0; g < NC_KS0 / 8; ++g) {
+            const float2 base = (8 * g < KS && krow_ok) ? phase_of(axk, 16 * g + (h >> 1) - nx / 2)
+                                                        : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int s = 8 * g + o, ix = 2 * s + (h >> 1);
+                float val = 0.f;
+                if (s < KS && krow_ok && ix < nx) {
+                    const float2 e = cmul(base, off[o]);
+                    val = (h & 1) ? e.y : e.x;
+                }
+                a0[s] = val;
             }
-            a0[s] = val;
         }
     } else {
         KS = (2 * nx + 31) / 32;
+        // columns ix = 16 s + 4 h + m: phase(16 s + 4 h) phase(m)
+        float2 off[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) off[m] = m == 0 ? make_float2(1.f, 0.f) : phase_of(axk, m);
 #pragma unroll
         for (int s = 0; s < NC_KS1; ++s) {
+            const float2 base = (s < KS && krow_ok) ? phase_of(axk, 16 * s + 4 * h - nx / 2) : make_float2(0.f, 0.f);
             unsigned int hw[4], lw[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int ix = 16 * s + 4 * h + m;
                 float2 e = make_float2(0.f, 0.f);
-                if (s < KS && krow_ok && ix < nx) e = phase_of(axk, ix - nx / 2);
+                if (s < KS && krow_ok && ix < nx) e = cmul(base, off[m]);
                 const uint2 w = split_pair(e.x, e.y);
                 hw[m] = w.x;
                 lw[m] = w.y;
@@ -183,6 +206,18 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
             ahi[s] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             alo[s] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
         }
+    }
+    // Epilogue phases Ey[k][iy] of the lane's 4 samples, iy = iy0 + 8 cb + rb:
+    // phase(iy0 + rb) from sin/cos per tile, times phase(8 cb).
+    const int rb = (lane & 15) >> 1;
+    double ayv[4];
+    float2 eoff[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = k0 + 4 * h + i;
+        ayv[i] = k < nk ? ay[(size_t)n * nk + k] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) eoff[i][cb] = cb == 0 ? make_float2(1.f, 0.f) : phase_of(ayv[i], 8 * cb);
     }
 
     float sacc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -217,9 +252,12 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
             }
         }
         __syncthreads();
+        float2 ebase[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ebase[i] = phase_of(ayv[i], iy0 + rb - ny / 2);
 #pragma unroll
         for (int cb = 0; cb < NC_ROWS / 8; ++cb) {
-            const int rl = 8 * cb + ((lane & 15) >> 1);   // tile row of this lane's column
+            const int rl = 8 * cb + rb;   // tile row of this lane's column
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             if constexpr (ENC == 0) {
 #pragma unroll
@@ -256,7 +294,7 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
                 const float pr = b == 0 ? own : oth, pi = b == 0 ? oth : own;
                 const int k = k0 + 4 * h + i;
                 if (k < nk && iy < ny) {
-                    const float2 ey = phase_of(ay[(size_t)n * nk + k], iy - ny / 2);
+                    const float2 ey = cmul(ebase[i], eoff[i][cb]);
                     sacc[i] += b == 0 ? pr * ey.x - pi * ey.y : pr * ey.y + pi * ey.x;
                 }
             }
@@ -307,9 +345,12 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
 // Cartesian adjoint, so the same gradient assembly follows.
 // ------------------------------------------------------------------------
 constexpr int NCA_TY = 64, NCA_TX = 32, NCA_KC = 64;
+// The table build gives each of the 256 threads one sample and every 4th
+// row (column) of the tile.
+static_assert(256 / NCA_KC == 4 && NCA_TY % 16 == 0 && NCA_TX % 16 == 0, "adjoint table build layout");
 
 template <int ENC, int NTR, typename TT>
-__global__ __launch_bounds__(256) void nc_adj_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void nc_adj_kernel(
     const TT* __restrict__ trains, const float2* __restrict__ coil, const uint8_t* __restrict__ mask,
     const double* __restrict__ ax, const double* __restrict__ ay, const float2* __restrict__ w,
     float* __restrict__ apart, int nx, int ny, int nv, int T, int nk, int C, int n_per_chunk, int ntx)
@@ -346,36 +387,61 @@ __global__ __launch_bounds__(256) void nc_adj_kernel(
             for (int cb = 0; cb < 4; ++cb) cacc[cb] = f4{0.f, 0.f, 0.f, 0.f};
             for (int kc0 = 0; kc0 < nk; kc0 += NCA_KC) {
                 __syncthreads();   // the previous chunk's tables have been read
-                // G: 64 rows x 64 samples; H: 32 columns x 64 samples.
-                for (int e = tid; e < (NCA_TY + NCA_TX) * NCA_KC; e += 256) {
-                    const bool isg = e < NCA_TY * NCA_KC;
-                    const int e2 = isg ? e : e - NCA_TY * NCA_KC;
-                    const int r = e2 / NCA_KC, kk = e2 % NCA_KC;
+                // G: 64 rows x 64 samples; H: 32 columns x 64 samples. A
+                // thread takes one sample and every 4th row (column): the
+                // phases along them form a geometric sequence, so per sample
+                // three phases come from sin/cos (the first row, 4 and 16
+                // rows on) and the others from complex products of those.
+                {
+                    const int kk = tid % NCA_KC, r0 = tid / NCA_KC;
                     const int k = kc0 + kk;
-                    float2 val = make_float2(0.f, 0.f);
-                    if (k < nk) {
-                        if (isg) {
-                            const int iy = iy_base + r;
-                            if (iy < ny) {
-                                const float2 ey = phase_of(ay[(size_t)n * nk + k], iy - ny / 2);
-                                const float2 ww = w[((size_t)c * T + n) * nk + k];
-                                // conj(ey) * w
-                                val = make_float2(ey.x * ww.x + ey.y * ww.y, ey.x * ww.y - ey.y * ww.x);
+                    const bool kok = k < nk;
+                    const double ayk = kok ? ay[(size_t)n * nk + k] : 0.0;
+                    const double axk = kok ? ax[(size_t)n * nk + k] : 0.0;
+                    const float2 ww = kok ? w[((size_t)c * T + n) * nk + k] : make_float2(0.f, 0.f);
+                    auto store = [&](uint2* dst, float2 val) {
+                        if constexpr (ENC == 0)
+                            *dst = make_uint2(__float_as_uint(val.x), __float_as_uint(val.y));
+                        else
+                            *dst = split_pair(val.x, val.y);
+                    };
+                    {   // G[r][kk] = conj(Ey[k][iy]) w[k], iy = iy_base + r0 + 4 m
+                        const float2 s4 = phase_of(ayk, 4), s16 = phase_of(ayk, 16);
+                        const float2 s8 = cmul(s4, s4), s12 = cmul(s8, s4);
+                        float2 q = phase_of(ayk, iy_base + r0 - ny / 2);
+#pragma unroll 1
+                        for (int u = 0; u < NCA_TY / 16; ++u) {
+                            const float2 qv[4] = {q, cmul(q, s4), cmul(q, s8), cmul(q, s12)};
+#pragma unroll
+                            for (int v4 = 0; v4 < 4; ++v4) {
+                                const int r = r0 + 16 * u + 4 * v4;
+                                const float2 ey = qv[v4];
+                                float2 val = make_float2(0.f, 0.f);
+                                if (kok && iy_base + r < ny)   // conj(ey) * w
+                                    val = make_float2(ey.x * ww.x + ey.y * ww.y, ey.x * ww.y - ey.y * ww.x);
+                                store(gs + r * NCA_KC + kk, val);
                             }
-                        } else {
-                            const int ix = ix_base + r;
-                            if (ix < nx) {
-                                const float2 ex = phase_of(ax[(size_t)n * nk + k], ix - nx / 2);
-                                val = make_float2(ex.x, -ex.y);
-                            }
+                            q = cmul(q, s16);
                         }
                     }
-                    uint2 st;
-                    if constexpr (ENC == 0)
-                        st = make_uint2(__float_as_uint(val.x), __float_as_uint(val.y));
-                    else
-                        st = split_pair(val.x, val.y);
-                    (isg ? gs : hs)[e2] = st;
+                    {   // H[r][kk] = conj(Ex[k][ix]), ix = ix_base + r0 + 4 m
+                        const float2 s4 = phase_of(axk, 4), s16 = phase_of(axk, 16);
+                        const float2 s8 = cmul(s4, s4), s12 = cmul(s8, s4);
+                        float2 q = phase_of(axk, ix_base + r0 - nx / 2);
+#pragma unroll 1
+                        for (int u = 0; u < NCA_TX / 16; ++u) {
+                            const float2 qv[4] = {q, cmul(q, s4), cmul(q, s8), cmul(q, s12)};
+#pragma unroll
+                            for (int v4 = 0; v4 < 4; ++v4) {
+                                const int r = r0 + 16 * u + 4 * v4;
+                                const float2 ex = qv[v4];
+                                const float2 val = (kok && ix_base + r < nx) ? make_float2(ex.x, -ex.y)
+                                                                             : make_float2(0.f, 0.f);
+                                store(hs + r * NCA_KC + kk, val);
+                            }
+                            q = cmul(q, s16);
+                        }
+                    }
                 }
                 __syncthreads();
                 const int grow = 16 * wave + (lane & 15);   // A row (image row in the tile)

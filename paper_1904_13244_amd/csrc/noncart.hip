@@ -345,6 +345,11 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
 // Cartesian adjoint, so the same gradient assembly follows.
 // ------------------------------------------------------------------------
 constexpr int NCA_TY = 64, NCA_TX = 32, NCA_KC = 64;
+// LDS row stride of the tables: two entries of padding, so the rows (16 per
+// wave for G, 8 for H) that one MFMA operand read touches fall in different
+// banks (the unpadded stride of 512 bytes puts them all in one); 16-byte
+// aligned rows.
+constexpr int NCA_KCP = NCA_KC + 2;
 // The table build gives each of the 256 threads one sample and every 4th
 // row (column) of the tile.
 static_assert(256 / NCA_KC == 4 && NCA_TY % 16 == 0 && NCA_TX % 16 == 0, "adjoint table build layout");
@@ -357,8 +362,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 {
     // LDS: G [TY][KC] and H [TX][KC] entries of 8 bytes: ENC 0 (re, im) FP32,
     // ENC 1 (hi word, lo word).
-    __shared__ __attribute__((aligned(16))) uint2 gs[NCA_TY * NCA_KC];
-    __shared__ __attribute__((aligned(16))) uint2 hs[NCA_TX * NCA_KC];
+    __shared__ __attribute__((aligned(16))) uint2 gs[NCA_TY * NCA_KCP];
+    __shared__ __attribute__((aligned(16))) uint2 hs[NCA_TX * NCA_KCP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = blockIdx.x;
     const int iy_base = (tile / ntx) * NCA_TY, ix_base = (tile % ntx) * NCA_TX;
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
                                 float2 val = make_float2(0.f, 0.f);
                                 if (kok && iy_base + r < ny)   // conj(ey) * w
                                     val = make_float2(ey.x * ww.x + ey.y * ww.y, ey.x * ww.y - ey.y * ww.x);
-                                store(gs + r * NCA_KC + kk, val);
+                                store(gs + r * NCA_KCP + kk, val);
                             }
                             q = cmul(q, s16);
                         }
@@ -437,7 +442,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
                                 const float2 ex = qv[v4];
                                 const float2 val = (kok && ix_base + r < nx) ? make_float2(ex.x, -ex.y)
                                                                              : make_float2(0.f, 0.f);
-                                store(hs + r * NCA_KC + kk, val);
+                                store(hs + r * NCA_KCP + kk, val);
                             }
                             q = cmul(q, s16);
                         }
@@ -451,12 +456,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 #pragma unroll 4
                     for (int s = 0; s < NCA_KC / 2; ++s) {
                         const int kk = 2 * s + (h >> 1), a = h & 1;
-                        const uint2 gv = gs[grow * NCA_KC + kk];
+                        const uint2 gv = gs[grow * NCA_KCP + kk];
                         const float av = __uint_as_float(a ? gv.y : gv.x);
 #pragma unroll
                         for (int cb = 0; cb < 4; ++cb) {
                             const int col = 8 * cb + ((lane & 15) >> 1);
-                            const uint2 hv = hs[col * NCA_KC + kk];
+                            const uint2 hv = hs[col * NCA_KCP + kk];
                             const float hr = __uint_as_float(hv.x), hi = __uint_as_float(hv.y);
                             const float bv = a == 0 ? (b == 0 ? hr : hi) : (b == 0 ? -hi : hr);
                             cacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, cacc[cb], 0, 0, 0);
@@ -466,14 +471,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
                     // K-steps of 16 samples: lane's samples 16 s + 4 h + m.
 #pragma unroll
                     for (int s = 0; s < NCA_KC / 16; ++s) {
-                        const uint2* gp = gs + grow * NCA_KC + 16 * s + 4 * h;
+                        const uint2* gp = gs + grow * NCA_KCP + 16 * s + 4 * h;
                         const uint2 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3];
                         const uint4 ah = make_uint4(g0.x, g1.x, g2.x, g3.x);
                         const uint4 al = make_uint4(g0.y, g1.y, g2.y, g3.y);
 #pragma unroll
                         for (int cb = 0; cb < 4; ++cb) {
                             const int col = 8 * cb + ((lane & 15) >> 1);
-                            const uint2* hp = hs + col * NCA_KC + 16 * s + 4 * h;
+                            const uint2* hp = hs + col * NCA_KCP + 16 * s + 4 * h;
                             const uint2 q0 = hp[0], q1 = hp[1], q2 = hp[2], q3 = hp[3];
                             const uint4 bh = bform(make_uint4(q0.x, q1.x, q2.x, q3.x), b);
                             const uint4 bl = bform(make_uint4(q0.y, q1.y, q2.y, q3.y), b);
@@ -556,7 +561,9 @@ hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const 
                       const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
     const int KT = ceil_div(d.nk, 64);
-    const int nxp = ceil_div(d.nx, 16) * 16;
+    // LDS row stride: two entries of padding put the 8 rows that one B
+    // operand read touches in different banks; rows stay 16-byte aligned.
+    const int nxp = ceil_div(d.nx, 16) * 16 + 2;
     const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
     const size_t lds = (size_t)NC_ROWS * nxp * 8;
     nc_fwd_kernel<ENC, MODE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T, d.nk,

@@ -147,8 +147,9 @@ mrstat_status mrstat_create(const mrstat_problem *prob, mrstat_ctx *out);
  * and every call of the context evaluates the voxel x sample contraction
  * directly on the matrix cores (FP32 or split-BF16; FP16 is refused) with
  * the phases generated on the fly; ky_line is ignored and n_read may be below
- * nx. Requirements as mrstat_create, plus nx <= 256 (MRSTAT_ERR_SHAPE) and
- * finite coordinates (MRSTAT_ERR_ARG). */
+ * nx. The workspace (mrstat_workspace_bytes) then also holds the forward's
+ * voxel values, complex FP32 [n_tr][nx ny]. Requirements as mrstat_create,
+ * plus nx <= 256 (MRSTAT_ERR_SHAPE) and finite coordinates (MRSTAT_ERR_ARG). */
 mrstat_status mrstat_create_traj(const mrstat_problem *prob, const double *kx, const double *ky,
                                  mrstat_ctx *out);
 void mrstat_destroy(mrstat_ctx ctx);

@@ -127,16 +127,20 @@ __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains
 // ------------------------------------------------------------------------
 constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
 constexpr int NC_KS1 = 16;    // BF16 K-steps of 32 real k: nx <= 256
+constexpr int NC_KP = 2;      // K parts of 128 columns; one part's A fragments in registers at a time
+constexpr int NC_PCOLS = 128; // columns per K part
 constexpr int NC_ROWS = 32;   // image rows per LDS tile
-constexpr int NC_XB = 7;      // voxel values per thread loaded together (32 x 224 = 256 x 4 x 7)
+constexpr int NC_XB = 4;      // voxel values per thread loaded together
 static_assert(NC_ROWS == 32, "forward tile: 4 column blocks of 8 rows per lane group");
+static_assert(NC_KP * NC_PCOLS == 256 && NC_KS0 % NC_KP == 0 && NC_KS1 % NC_KP == 0, "forward K parts");
 
 template <int ENC, int MODE>
-__global__ __launch_bounds__(256) void nc_fwd_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void nc_fwd_kernel(
     const float2* __restrict__ X, const float2* __restrict__ coil, const double* __restrict__ ax,
     const double* __restrict__ ay, const float2* __restrict__ data, float2* __restrict__ out,
     double* __restrict__ red, int nx, int ny, int nv, int T, int nk, int KT, int nxp)
 {
+    constexpr int KS0P = NC_KS0 / NC_KP, KS1P = NC_KS1 / NC_KP;   // K-steps per part
     extern __shared__ __attribute__((aligned(16))) unsigned char nc_smem[];
     __shared__ double rs[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -155,69 +159,26 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
     const bool krow_ok = krow < nk;
     const double axk = krow_ok ? ax[(size_t)n * nk + krow] : 0.0;
     const int h = lane >> 4;   // 0..3
+    const int KS = ENC == 0 ? (2 * nx + 3) / 4 : (2 * nx + 31) / 32;
 
-    // A fragments: Ex[krow][ix] in the real form A'[k][2 ix + a] = (re, im).
-    float a0[ENC == 0 ? NC_KS0 : 1];
-    uint4 ahi[ENC == 1 ? NC_KS1 : 1], alo[ENC == 1 ? NC_KS1 : 1];
-    int KS;
     // The phases along a row of Ex are a geometric sequence: a lane's columns
     // come in groups whose first phase is taken from sin/cos and the others
     // as its products with the phases of the group's offsets.
-    if constexpr (ENC == 0) {
-        KS = (2 * nx + 3) / 4;
-        // columns ix = 2 s + h/2, s = 8 g + o: phase(16 g + h/2) phase(2 o)
-        float2 off[8];
+    float2 off[ENC == 0 ? 8 : 4];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) off[o] = o == 0 ? make_float2(1.f, 0.f) : phase_of(axk, 2 * o);
-#pragma unroll
-        for (int g = 0; g < NC_KS0 / 8; ++g) {
-            const float2 base = (8 * g < KS && krow_ok) ? phase_of(axk, 16 * g + (h >> 1) - nx / 2)
-                                                        : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                const int s = 8 * g + o, ix = 2 * s + (h >> 1);
-                float val = 0.f;
-                if (s < KS && krow_ok && ix < nx) {
-                    const float2 e = cmul(base, off[o]);
-                    val = (h & 1) ? e.y : e.x;
-                }
-                a0[s] = val;
-            }
-        }
-    } else {
-        KS = (2 * nx + 31) / 32;
-        // columns ix = 16 s + 4 h + m: phase(16 s + 4 h) phase(m)
-        float2 off[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) off[m] = m == 0 ? make_float2(1.f, 0.f) : phase_of(axk, m);
-#pragma unroll
-        for (int s = 0; s < NC_KS1; ++s) {
-            const float2 base = (s < KS && krow_ok) ? phase_of(axk, 16 * s + 4 * h - nx / 2) : make_float2(0.f, 0.f);
-            unsigned int hw[4], lw[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int ix = 16 * s + 4 * h + m;
-                float2 e = make_float2(0.f, 0.f);
-                if (s < KS && krow_ok && ix < nx) e = cmul(base, off[m]);
-                const uint2 w = split_pair(e.x, e.y);
-                hw[m] = w.x;
-                lw[m] = w.y;
-            }
-            ahi[s] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            alo[s] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-        }
-    }
+    for (int o = 0; o < (ENC == 0 ? 8 : 4); ++o)
+        off[o] = o == 0 ? make_float2(1.f, 0.f) : phase_of(axk, ENC == 0 ? 2 * o : o);
     // Epilogue phases Ey[k][iy] of the lane's 4 samples, iy = iy0 + 8 cb + rb:
-    // phase(iy0 + rb) from sin/cos per tile, times phase(8 cb).
+    // phase(iy0 + rb) from sin/cos per tile, times phase(8) once per column
+    // block.
     const int rb = (lane & 15) >> 1;
     double ayv[4];
-    float2 eoff[4][4];
+    float2 e8[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int k = k0 + 4 * h + i;
         ayv[i] = k < nk ? ay[(size_t)n * nk + k] : 0.0;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) eoff[i][cb] = cb == 0 ? make_float2(1.f, 0.f) : phase_of(ayv[i], 8 * cb);
+        e8[i] = phase_of(ayv[i], 8);
     }
 
     float sacc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -226,76 +187,123 @@ __global__ __launch_bounds__(256) void nc_fwd_kernel(
     float2* xs0 = reinterpret_cast<float2*>(nc_smem);               // ENC 0: [ROWS][nxp]
     uint2* xs1 = reinterpret_cast<uint2*>(nc_smem);                 // ENC 1: [ROWS][nxp] (hi, lo)
     const int tile_n = NC_ROWS * nxp;
-    for (int iy0 = 0; iy0 < ny; iy0 += NC_ROWS) {
-        __syncthreads();   // the previous tile has been read
-        for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
-            float2 xv[NC_XB], cv[NC_XB];
+    // K parts: columns [NC_PCOLS kp, NC_PCOLS (kp + 1)); the sums over the
+    // rows are linear in P, so each part's Ey-weighted sums simply add up.
+    for (int kp = 0; kp < NC_KP && kp * NC_PCOLS < nx; ++kp) {
+        const int cx0 = kp * NC_PCOLS;
+        // A fragments of this part: Ex[krow][ix] in the real form
+        // A'[k][2 ix + a] = (re, im).
+        float a0[ENC == 0 ? KS0P : 1];
+        uint4 ahi[ENC == 1 ? KS1P : 1], alo[ENC == 1 ? KS1P : 1];
+        if constexpr (ENC == 0) {
+            // columns ix = cx0 + 2 sl + h/2, sl = 8 g + o: phase(cx0 + 16 g + h/2) phase(2 o)
 #pragma unroll
-            for (int u = 0; u < NC_XB; ++u) {
-                const int e = e0 + 256 * u;
-                const int r = e / nxp, ix = e % nxp, iy = iy0 + r;
-                const bool ok = e < tile_n && ix < nx && iy < ny;
-                const size_t j = ok ? (size_t)iy * nx + ix : 0;
-                xv[u] = ok ? Xn[j] : make_float2(0.f, 0.f);
-                cv[u] = coil != nullptr && ok ? coil[(size_t)c * nv + j] : make_float2(1.f, 0.f);
+            for (int g = 0; g < KS0P / 8; ++g) {
+                const bool any = KS0P * kp + 8 * g < KS && krow_ok;
+                const float2 base = any ? phase_of(axk, cx0 + 16 * g + (h >> 1) - nx / 2) : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const int sl = 8 * g + o, ix = cx0 + 2 * sl + (h >> 1);
+                    float val = 0.f;
+                    if (KS0P * kp + sl < KS && krow_ok && ix < nx) {
+                        const float2 e = cmul(base, off[o]);
+                        val = (h & 1) ? e.y : e.x;
+                    }
+                    a0[sl] = val;
+                }
             }
+        } else {
+            // columns ix = cx0 + 16 sl + 4 h + m: phase(cx0 + 16 sl + 4 h) phase(m)
 #pragma unroll
-            for (int u = 0; u < NC_XB; ++u) {
-                const int e = e0 + 256 * u;
-                if (e >= tile_n) break;
-                const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
-                const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
-                if constexpr (ENC == 0)
-                    xs0[e] = make_float2(xr, xi);
-                else
-                    xs1[e] = split_pair(xr, xi);
+            for (int sl = 0; sl < KS1P; ++sl) {
+                const bool any = KS1P * kp + sl < KS && krow_ok;
+                const float2 base = any ? phase_of(axk, cx0 + 16 * sl + 4 * h - nx / 2) : make_float2(0.f, 0.f);
+                unsigned int hw[4], lw[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int ix = cx0 + 16 * sl + 4 * h + m;
+                    float2 e = make_float2(0.f, 0.f);
+                    if (any && ix < nx) e = cmul(base, off[m]);
+                    const uint2 w = split_pair(e.x, e.y);
+                    hw[m] = w.x;
+                    lw[m] = w.y;
+                }
+                ahi[sl] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+                alo[sl] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             }
         }
-        __syncthreads();
-        float2 ebase[4];
+        for (int iy0 = 0; iy0 < ny; iy0 += NC_ROWS) {
+            __syncthreads();   // the previous tile has been read
+            for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
+                float2 xv[NC_XB], cv[NC_XB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ebase[i] = phase_of(ayv[i], iy0 + rb - ny / 2);
-#pragma unroll
-        for (int cb = 0; cb < NC_ROWS / 8; ++cb) {
-            const int rl = 8 * cb + rb;   // tile row of this lane's column
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (ENC == 0) {
-#pragma unroll
-                for (int s = 0; s < NC_KS0; ++s) {
-                    if (s < KS) {
-                        const int ix = 2 * s + (h >> 1);
-                        const float2 x = xs0[rl * nxp + ix];
-                        const int a = h & 1;
-                        const float bv = a == 0 ? (b == 0 ? x.x : x.y) : (b == 0 ? -x.y : x.x);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], bv, acc, 0, 0, 0);
-                    }
+                for (int u = 0; u < NC_XB; ++u) {
+                    const int e = e0 + 256 * u;
+                    const int r = e / nxp, ixl = e % nxp, iy = iy0 + r, ix = cx0 + ixl;
+                    const bool ok = e < tile_n && ixl < NC_PCOLS && ix < nx && iy < ny;
+                    const size_t j = ok ? (size_t)iy * nx + ix : 0;
+                    xv[u] = ok ? Xn[j] : make_float2(0.f, 0.f);
+                    cv[u] = coil != nullptr && ok ? coil[(size_t)c * nv + j] : make_float2(1.f, 0.f);
                 }
-            } else {
 #pragma unroll
-                for (int s = 0; s < NC_KS1; ++s) {
-                    if (s < KS) {
-                        const uint2* src = xs1 + rl * nxp + 16 * s + 4 * h;
-                        const uint2 p0 = src[0], p1 = src[1], p2 = src[2], p3 = src[3];
-                        const uint4 bh = bform(make_uint4(p0.x, p1.x, p2.x, p3.x), b);
-                        const uint4 bl = bform(make_uint4(p0.y, p1.y, p2.y, p3.y), b);
-                        acc = mma_bf16(ahi[s], bh, acc);
-                        acc = mma_bf16(ahi[s], bl, acc);
-                        acc = mma_bf16(alo[s], bh, acc);
-                    }
+                for (int u = 0; u < NC_XB; ++u) {
+                    const int e = e0 + 256 * u;
+                    if (e >= tile_n) break;
+                    const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
+                    const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
+                    if constexpr (ENC == 0)
+                        xs0[e] = make_float2(xr, xi);
+                    else
+                        xs1[e] = split_pair(xr, xi);
                 }
             }
-            // Epilogue of this column block: P[k, iy] (re in even lanes, im in
-            // odd) times Ey[k, iy], summed into the lane's running row sums.
-            const int iy = iy0 + rl;
+            __syncthreads();
+            float2 ebase[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float own = acc[i];
-                const float oth = __shfl_xor(own, 1);
-                const float pr = b == 0 ? own : oth, pi = b == 0 ? oth : own;
-                const int k = k0 + 4 * h + i;
-                if (k < nk && iy < ny) {
-                    const float2 ey = cmul(ebase[i], eoff[i][cb]);
-                    sacc[i] += b == 0 ? pr * ey.x - pi * ey.y : pr * ey.y + pi * ey.x;
+            for (int i = 0; i < 4; ++i) ebase[i] = phase_of(ayv[i], iy0 + rb - ny / 2);
+#pragma unroll
+            for (int cb = 0; cb < NC_ROWS / 8; ++cb) {
+                const int rl = 8 * cb + rb;   // tile row of this lane's column
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (ENC == 0) {
+#pragma unroll
+                    for (int sl = 0; sl < KS0P; ++sl) {
+                        if (KS0P * kp + sl < KS) {
+                            const float2 x = xs0[rl * nxp + 2 * sl + (h >> 1)];
+                            const int a = h & 1;
+                            const float bv = a == 0 ? (b == 0 ? x.x : x.y) : (b == 0 ? -x.y : x.x);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[sl], bv, acc, 0, 0, 0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int sl = 0; sl < KS1P; ++sl) {
+                        if (KS1P * kp + sl < KS) {
+                            const uint2* src = xs1 + rl * nxp + 16 * sl + 4 * h;
+                            const uint2 p0 = src[0], p1 = src[1], p2 = src[2], p3 = src[3];
+                            const uint4 bh = bform(make_uint4(p0.x, p1.x, p2.x, p3.x), b);
+                            const uint4 bl = bform(make_uint4(p0.y, p1.y, p2.y, p3.y), b);
+                            acc = mma_bf16(ahi[sl], bh, acc);
+                            acc = mma_bf16(ahi[sl], bl, acc);
+                            acc = mma_bf16(alo[sl], bh, acc);
+                        }
+                    }
+                }
+                // Epilogue of this column block: P[k, iy] (re in even lanes, im
+                // in odd) times Ey[k, iy], summed into the lane's running row
+                // sums.
+                const int iy = iy0 + rl;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float own = acc[i];
+                    const float oth = __shfl_xor(own, 1);
+                    const float pr = b == 0 ? own : oth, pi = b == 0 ? oth : own;
+                    const int k = k0 + 4 * h + i;
+                    if (k < nk && iy < ny) {
+                        const float2 ey = ebase[i];
+                        sacc[i] += b == 0 ? pr * ey.x - pi * ey.y : pr * ey.y + pi * ey.x;
+                    }
+                    ebase[i] = cmul(ebase[i], e8[i]);   // the next column block's rows
                 }
             }
         }
@@ -566,9 +574,10 @@ hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const 
                       const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
     const int KT = ceil_div(d.nk, 64);
-    // LDS row stride: two entries of padding put the 8 rows that one B
-    // operand read touches in different banks; rows stay 16-byte aligned.
-    const int nxp = ceil_div(d.nx, 16) * 16 + 2;
+    // LDS row stride: one K part's columns and two entries of padding, which
+    // put the 8 rows that one B operand read touches in different banks; rows
+    // stay 16-byte aligned.
+    const int nxp = std::min(ceil_div(d.nx, 16) * 16, NC_PCOLS) + 2;
     const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
     const size_t lds = (size_t)NC_ROWS * nxp * 8;
     nc_fwd_kernel<ENC, MODE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T, d.nk,

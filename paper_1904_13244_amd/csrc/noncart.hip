@@ -122,20 +122,23 @@ __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains
 // loads issued together, then each wave multiplies them for 4 column blocks
 // of 8 rows, and the epilogue applies Ey and sums over the rows. Blocks are
 // dealt so that the sample tiles of one TR share an XCD (its voxel values
-// come through one L2).
+// come through one L2). K goes in parts of 64 columns (A fragments of one
+// part in registers: four waves per SIMD). Measured at 224 x 224, 1120 spokes
+// (FP32 / split-BF16): all of K at once 5.08 / 2.32 ms (two waves per SIMD),
+// two parts 4.14 / 2.07 (three), four 3.72 / 2.02.
 // MODE 0: out = data - s (and FP64 partials of |out|^2); 1: out = -s; 2: s.
 // ------------------------------------------------------------------------
 constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
 constexpr int NC_KS1 = 16;    // BF16 K-steps of 32 real k: nx <= 256
-constexpr int NC_KP = 2;      // K parts of 128 columns; one part's A fragments in registers at a time
-constexpr int NC_PCOLS = 128; // columns per K part
+constexpr int NC_KP = 4;      // K parts of 64 columns; one part's A fragments in registers at a time
+constexpr int NC_PCOLS = 64;  // columns per K part
 constexpr int NC_ROWS = 32;   // image rows per LDS tile
 constexpr int NC_XB = 4;      // voxel values per thread loaded together
 static_assert(NC_ROWS == 32, "forward tile: 4 column blocks of 8 rows per lane group");
 static_assert(NC_KP * NC_PCOLS == 256 && NC_KS0 % NC_KP == 0 && NC_KS1 % NC_KP == 0, "forward K parts");
 
 template <int ENC, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void nc_fwd_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void nc_fwd_kernel(
     const float2* __restrict__ X, const float2* __restrict__ coil, const double* __restrict__ ax,
     const double* __restrict__ ay, const float2* __restrict__ data, float2* __restrict__ out,
     double* __restrict__ red, int nx, int ny, int nv, int T, int nk, int KT, int nxp)

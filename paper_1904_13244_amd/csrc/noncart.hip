@@ -125,7 +125,8 @@ __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains
 // come through one L2). K goes in parts of 64 columns (A fragments of one
 // part in registers: four waves per SIMD). Measured at 224 x 224, 1120 spokes
 // (FP32 / split-BF16): all of K at once 5.08 / 2.32 ms (two waves per SIMD),
-// two parts 4.14 / 2.07 (three), four 3.72 / 2.02.
+// two parts 4.14 / 2.07 (three), four 3.72 / 2.02; the split-BF16 tile staged
+// in both lane-parity forms (no operand re-forming in the K loop) 1.91.
 // MODE 0: out = data - s (and FP64 partials of |out|^2); 1: out = -s; 2: s.
 // ------------------------------------------------------------------------
 constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
@@ -188,8 +189,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void n
     const int b = lane & 1;
     const float2* Xn = X + (size_t)n * nv;
     float2* xs0 = reinterpret_cast<float2*>(nc_smem);               // ENC 0: [ROWS][nxp]
-    uint2* xs1 = reinterpret_cast<uint2*>(nc_smem);                 // ENC 1: [ROWS][nxp] (hi, lo)
-    const int tile_n = NC_ROWS * nxp;
+    // ENC 1: [2][ROWS][nxp] (hi, lo) words already in the real-form B order of
+    // each lane parity (copy 0: (re, -im), copy 1: (im, re)); the copies are
+    // one entry apart in banks so the two parities do not collide.
+    uint2* xs1 = reinterpret_cast<uint2*>(nc_smem);
+    const int tile_n = NC_ROWS * nxp, copy1 = tile_n + 1;
     // K parts: columns [NC_PCOLS kp, NC_PCOLS (kp + 1)); the sums over the
     // rows are linear in P, so each part's Ey-weighted sums simply add up.
     for (int kp = 0; kp < NC_KP && kp * NC_PCOLS < nx; ++kp) {
@@ -254,10 +258,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void n
                     if (e >= tile_n) break;
                     const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
                     const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
-                    if constexpr (ENC == 0)
+                    if constexpr (ENC == 0) {
                         xs0[e] = make_float2(xr, xi);
-                    else
-                        xs1[e] = split_pair(xr, xi);
+                    } else {
+                        const uint2 w = split_pair(xr, xi);
+                        xs1[e] = make_uint2(w.x ^ 0x80000000u, w.y ^ 0x80000000u);
+                        xs1[copy1 + e] = make_uint2((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16));
+                    }
                 }
             }
             __syncthreads();
@@ -282,10 +289,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void n
 #pragma unroll
                     for (int sl = 0; sl < KS1P; ++sl) {
                         if (KS1P * kp + sl < KS) {
-                            const uint2* src = xs1 + rl * nxp + 16 * sl + 4 * h;
+                            const uint2* src = xs1 + b * copy1 + rl * nxp + 16 * sl + 4 * h;
                             const uint2 p0 = src[0], p1 = src[1], p2 = src[2], p3 = src[3];
-                            const uint4 bh = bform(make_uint4(p0.x, p1.x, p2.x, p3.x), b);
-                            const uint4 bl = bform(make_uint4(p0.y, p1.y, p2.y, p3.y), b);
+                            const uint4 bh = make_uint4(p0.x, p1.x, p2.x, p3.x);
+                            const uint4 bl = make_uint4(p0.y, p1.y, p2.y, p3.y);
                             acc = mma_bf16(ahi[sl], bh, acc);
                             acc = mma_bf16(ahi[sl], bl, acc);
                             acc = mma_bf16(alo[sl], bh, acc);
@@ -582,7 +589,7 @@ hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const 
     // stay 16-byte aligned.
     const int nxp = std::min(ceil_div(d.nx, 16) * 16, NC_PCOLS) + 2;
     const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
-    const size_t lds = (size_t)NC_ROWS * nxp * 8;
+    const size_t lds = (ENC == 1 ? 2 * (size_t)NC_ROWS * nxp + 1 : (size_t)NC_ROWS * nxp) * 8;
     nc_fwd_kernel<ENC, MODE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T, d.nk,
                                                     KT, nxp);
     if (nred) *nred = (int)(grid.x * grid.y);

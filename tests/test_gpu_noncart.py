@@ -83,6 +83,37 @@ def test_products_match_oracle(torch_gpu, oracle_lib, enc, coils):
         assert e <= BAR[enc]
 
 
+@pytest.mark.parametrize("enc,coils", [(0, 1), (1, 2)])
+def test_wide_image_k_parts(torch_gpu, oracle_lib, enc, coils):
+    """An image wider than one K part of the forward (200 columns: parts of
+    64, 64, 64 and 8), 9 rows (less than one staged row tile), 11 TRs (not a
+    multiple of the 8 TRs dealt per XCD) and 70 samples (a ragged sample
+    tile): products and residual against the oracle's direct sums."""
+    torch = torch_gpu
+    from paper_1904_13244_amd.binding import Context
+    prob, th, coil, mask = _radial_case(coils, seed=37, nx=200, ny=9, n_tr=11, n_read=70)
+    ora = oracle_lib.epg(prob, th)
+    v, w = I.probe_vectors(prob)
+    ctx = Context(prob, coil=None if coil is None else _dev(torch, coil, torch.complex64),
+                  mask=_dev(torch, mask, torch.uint8))
+    ctx.set_encoding(enc)
+    thd = _dev(torch, th, torch.float32)
+    d = oracle_lib.signal(prob, th, ora, coil=coil, mask=mask)
+    f_ref, r_ref = oracle_lib.residual(prob, th, 0.5 * d, coil=coil, mask=mask)
+    f, r = ctx.residual(thd, _dev(torch, 0.5 * d, torch.complex64))
+    e_r = float(np.linalg.norm(r.cpu().numpy() - r_ref) / np.linalg.norm(d))
+    ctx.linearise(thd)
+    jv = ctx.jv(thd, _dev(torch, v, torch.float32), reuse=True).cpu().numpy().astype(np.complex128)
+    jhw = ctx.jhw(thd, _dev(torch, w, torch.complex64), reuse=True).cpu().numpy().astype(np.float64)
+    e_jv = _rel(jv, oracle_lib.jv(prob, th, ora, v, coil=coil, mask=mask))
+    e_jhw = _rel(jhw, oracle_lib.jhw(prob, th, ora, w, coil=coil, mask=mask))
+    ctx.close()
+    print(f"\n  [radial 200x9, enc {enc}, {coils} coil(s)] residual {e_r:.2e} jv {e_jv:.2e} jhw {e_jhw:.2e}",
+          flush=True)
+    for e in (e_r, e_jv, e_jhw):
+        assert e <= BAR[enc]
+
+
 def test_fp16_trains(torch_gpu, oracle_lib):
     torch = torch_gpu
     from paper_1904_13244_amd import binding as B

@@ -82,9 +82,11 @@ __device__ __forceinline__ float ld_train(const TT* p) { return (float)*p; }
 // Voxel values of the forward, once per product: X[n][j] = i rho_j mu0[n,j]
 // (NTRV 1, the signal) or i (rho_j sum_p v_p dm_p/dtheta_p + (v3 + i v4) mu0)
 // (NTRV 4: all tangents; 3: without dm/dB1, whose direction entry is 0);
-// zero for masked voxels. A streaming pass over the trains.
+// zero for masked voxels. A streaming pass over the trains. SPLIT (the
+// split-BF16 forward without coil weights) stores each value already split
+// into its (hi, lo) words instead of the FP32 pair, the same 8 bytes.
 // ------------------------------------------------------------------------
-template <int NTRV, typename TT>
+template <int NTRV, typename TT, bool SPLIT>
 __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains, const float* __restrict__ theta,
                                                    const float* __restrict__ v, const uint8_t* __restrict__ mask,
                                                    float2* __restrict__ X, int nv, int T)
@@ -109,7 +111,10 @@ __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains
                 xi = rr * t + v3 * mu0;
             }
         }
-        X[i] = make_float2(xr, xi);
+        if constexpr (SPLIT)
+            reinterpret_cast<uint2*>(X)[i] = split_pair(xr, xi);
+        else
+            X[i] = make_float2(xr, xi);
     }
 }
 
@@ -126,7 +131,8 @@ __global__ __launch_bounds__(256) void nc_x_kernel(const TT* __restrict__ trains
 // part in registers: four waves per SIMD). Measured at 224 x 224, 1120 spokes
 // (FP32 / split-BF16): all of K at once 5.08 / 2.32 ms (two waves per SIMD),
 // two parts 4.14 / 2.07 (three), four 3.72 / 2.02; the split-BF16 tile staged
-// in both lane-parity forms (no operand re-forming in the K loop) 1.91.
+// in both lane-parity forms (no operand re-forming in the K loop) 1.91; without
+// coil weights the values split once by the voxel-value pass 1.68.
 // MODE 0: out = data - s (and FP64 partials of |out|^2); 1: out = -s; 2: s.
 // ------------------------------------------------------------------------
 constexpr int NC_KS0 = 128;   // FP32 K-steps of 4 real k: nx <= 256
@@ -138,7 +144,7 @@ constexpr int NC_XB = 4;      // voxel values per thread loaded together
 static_assert(NC_ROWS == 32, "forward tile: 4 column blocks of 8 rows per lane group");
 static_assert(NC_KP * NC_PCOLS == 256 && NC_KS0 % NC_KP == 0 && NC_KS1 % NC_KP == 0, "forward K parts");
 
-template <int ENC, int MODE>
+template <int ENC, int MODE, bool PRE>   // PRE: X holds split words (ENC 1, no coil weights)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void nc_fwd_kernel(
     const float2* __restrict__ X, const float2* __restrict__ coil, const double* __restrict__ ax,
     const double* __restrict__ ay, const float2* __restrict__ data, float2* __restrict__ out,
@@ -241,29 +247,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void n
         }
         for (int iy0 = 0; iy0 < ny; iy0 += NC_ROWS) {
             __syncthreads();   // the previous tile has been read
-            for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
-                float2 xv[NC_XB], cv[NC_XB];
+            if constexpr (PRE) {
+                // Split words from the voxel-value pass: only the two
+                // operand orders are formed here.
+                const uint2* Xw = reinterpret_cast<const uint2*>(Xn);
+                for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
+                    uint2 wv[NC_XB];
 #pragma unroll
-                for (int u = 0; u < NC_XB; ++u) {
-                    const int e = e0 + 256 * u;
-                    const int r = e / nxp, ixl = e % nxp, iy = iy0 + r, ix = cx0 + ixl;
-                    const bool ok = e < tile_n && ixl < NC_PCOLS && ix < nx && iy < ny;
-                    const size_t j = ok ? (size_t)iy * nx + ix : 0;
-                    xv[u] = ok ? Xn[j] : make_float2(0.f, 0.f);
-                    cv[u] = coil != nullptr && ok ? coil[(size_t)c * nv + j] : make_float2(1.f, 0.f);
-                }
+                    for (int u = 0; u < NC_XB; ++u) {
+                        const int e = e0 + 256 * u;
+                        const int r = e / nxp, ixl = e % nxp, iy = iy0 + r, ix = cx0 + ixl;
+                        const bool ok = e < tile_n && ixl < NC_PCOLS && ix < nx && iy < ny;
+                        wv[u] = ok ? Xw[(size_t)iy * nx + ix] : make_uint2(0u, 0u);
+                    }
 #pragma unroll
-                for (int u = 0; u < NC_XB; ++u) {
-                    const int e = e0 + 256 * u;
-                    if (e >= tile_n) break;
-                    const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
-                    const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
-                    if constexpr (ENC == 0) {
-                        xs0[e] = make_float2(xr, xi);
-                    } else {
-                        const uint2 w = split_pair(xr, xi);
+                    for (int u = 0; u < NC_XB; ++u) {
+                        const int e = e0 + 256 * u;
+                        if (e >= tile_n) break;
+                        const uint2 w = wv[u];
                         xs1[e] = make_uint2(w.x ^ 0x80000000u, w.y ^ 0x80000000u);
                         xs1[copy1 + e] = make_uint2((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16));
+                    }
+                }
+            } else {
+                for (int e0 = tid; e0 < tile_n; e0 += 256 * NC_XB) {
+                    float2 xv[NC_XB], cv[NC_XB];
+#pragma unroll
+                    for (int u = 0; u < NC_XB; ++u) {
+                        const int e = e0 + 256 * u;
+                        const int r = e / nxp, ixl = e % nxp, iy = iy0 + r, ix = cx0 + ixl;
+                        const bool ok = e < tile_n && ixl < NC_PCOLS && ix < nx && iy < ny;
+                        const size_t j = ok ? (size_t)iy * nx + ix : 0;
+                        xv[u] = ok ? Xn[j] : make_float2(0.f, 0.f);
+                        cv[u] = coil != nullptr && ok ? coil[(size_t)c * nv + j] : make_float2(1.f, 0.f);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NC_XB; ++u) {
+                        const int e = e0 + 256 * u;
+                        if (e >= tile_n) break;
+                        const float xr = cv[u].x * xv[u].x - cv[u].y * xv[u].y;
+                        const float xi = cv[u].x * xv[u].y + cv[u].y * xv[u].x;
+                        if constexpr (ENC == 0) {
+                            xs0[e] = make_float2(xr, xi);
+                        } else {
+                            const uint2 w = split_pair(xr, xi);
+                            xs1[e] = make_uint2(w.x ^ 0x80000000u, w.y ^ 0x80000000u);
+                            xs1[copy1 + e] = make_uint2((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16));
+                        }
                     }
                 }
             }
@@ -565,21 +595,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
         }
 }
 
-template <typename TT>
+template <typename TT, bool SPLIT>
 hipError_t x_launch(const Dims& d, int mode_y, const TT* trains, const float* theta, const float* v,
                     const uint8_t* mask, float2* X, hipStream_t s)
 {
     const unsigned blocks = (unsigned)std::min<size_t>(((size_t)d.T * d.nv + 255) / 256, 8192);
     switch (mode_y) {
-    case 0: nc_x_kernel<1, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
-    case 1: nc_x_kernel<4, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
-    case 3: nc_x_kernel<3, TT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    case 0: nc_x_kernel<1, TT, SPLIT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    case 1: nc_x_kernel<4, TT, SPLIT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
+    case 3: nc_x_kernel<3, TT, SPLIT><<<blocks, 256, 0, s>>>(trains, theta, v, mask, X, d.nv, d.T); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int ENC, int MODE>
+template <int ENC, int MODE, bool PRE>
 hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const double* ax, const double* ay,
                       const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
@@ -590,19 +620,19 @@ hipError_t fwd_launch(const Dims& d, const float2* X, const float2* coil, const 
     const int nxp = std::min(ceil_div(d.nx, 16) * 16, NC_PCOLS) + 2;
     const dim3 grid(8 * KT * ceil_div(d.T, 8), d.C);
     const size_t lds = (ENC == 1 ? 2 * (size_t)NC_ROWS * nxp + 1 : (size_t)NC_ROWS * nxp) * 8;
-    nc_fwd_kernel<ENC, MODE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T, d.nk,
-                                                    KT, nxp);
+    nc_fwd_kernel<ENC, MODE, PRE><<<grid, 256, lds, s>>>(X, coil, ax, ay, data, out, red, d.nx, d.ny, d.nv, d.T,
+                                                         d.nk, KT, nxp);
     if (nred) *nred = (int)(grid.x * grid.y);
     return hipGetLastError();
 }
 
-template <int ENC>
+template <int ENC, bool PRE>
 hipError_t fwd_mode(const Dims& d, int mode_x, const float2* X, const float2* coil, const double* ax,
                     const double* ay, const float2* data, float2* out, double* red, int* nred, hipStream_t s)
 {
-    if (mode_x == 0) return fwd_launch<ENC, 0>(d, X, coil, ax, ay, data, out, red, nred, s);
-    if (mode_x == 1) return fwd_launch<ENC, 1>(d, X, coil, ax, ay, data, out, red, nred, s);
-    return fwd_launch<ENC, 2>(d, X, coil, ax, ay, data, out, red, nred, s);
+    if (mode_x == 0) return fwd_launch<ENC, 0, PRE>(d, X, coil, ax, ay, data, out, red, nred, s);
+    if (mode_x == 1) return fwd_launch<ENC, 1, PRE>(d, X, coil, ax, ay, data, out, red, nred, s);
+    return fwd_launch<ENC, 2, PRE>(d, X, coil, ax, ay, data, out, red, nred, s);
 }
 
 template <int ENC, typename TT>
@@ -649,11 +679,22 @@ hipError_t launch_nc_fwd(const Dims& d, int enc, int mode_y, int mode_x, const v
                          double* red, int* nred, hipStream_t s)
 {
     if (d.nx > 256) return hipErrorInvalidValue;
-    const hipError_t e = f16 ? x_launch(d, mode_y, static_cast<const _Float16*>(trains), theta, v, mask, X, s)
-                             : x_launch(d, mode_y, static_cast<const float*>(trains), theta, v, mask, X, s);
+    // The split-BF16 forward without coil weights takes the values split once.
+    const bool pre = enc == 1 && coil == nullptr;
+    hipError_t e;
+    if (f16) {
+        const _Float16* tr = static_cast<const _Float16*>(trains);
+        e = pre ? x_launch<_Float16, true>(d, mode_y, tr, theta, v, mask, X, s)
+                : x_launch<_Float16, false>(d, mode_y, tr, theta, v, mask, X, s);
+    } else {
+        const float* tr = static_cast<const float*>(trains);
+        e = pre ? x_launch<float, true>(d, mode_y, tr, theta, v, mask, X, s)
+                : x_launch<float, false>(d, mode_y, tr, theta, v, mask, X, s);
+    }
     if (e != hipSuccess) return e;
-    return enc == 0 ? fwd_mode<0>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s)
-                    : fwd_mode<1>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s);
+    if (enc == 0) return fwd_mode<0, false>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s);
+    return pre ? fwd_mode<1, true>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s)
+               : fwd_mode<1, false>(d, mode_x, X, coil, ax, ay, data, out, red, nred, s);
 }
 
 hipError_t launch_nc_adj(const Dims& d, int enc, int ntr, int chunks, const void* trains, bool f16,

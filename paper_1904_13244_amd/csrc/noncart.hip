@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void n
 // with the phases by angle addition 13.3 / 3.3, padded rows 5.0 / 2.9; the
 // next chunk's trajectory and data values loaded ahead need 6 more registers:
 // 5.0 / 2.9 with 56 bytes per lane spilled at three waves per SIMD, 5.8 / 4.2
-// at two.
+// at two; H staged in both lane-parity operand orders (no re-forming in the K
+// loop, 68 KB of LDS: two blocks per CU instead of three) 3.6 (split-BF16).
 // ------------------------------------------------------------------------
 constexpr int NCA_TY = 64, NCA_TX = 32, NCA_KC = 64;
 // LDS row stride of the tables: two entries of padding, so the rows (16 per

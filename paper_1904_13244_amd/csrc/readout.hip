@@ -362,6 +362,8 @@ __device__ __forceinline__ void cheb_coeffs(float2 Lf, float2 (&ca)[NC], float2 
 // 0.084 instead of 0.122). TR chunks (HIP events, 16 terms): 9 chunks
 // 0.53-0.57, 18 0.55; 8, 16, 24 and 32 chunks with each XCD given its own
 // chunks (so its L2 holds only their term values) 0.58, 0.60, 0.58, 0.61.
+// V' from the a_m alone (u T_m = (T_(m-1) + T_(m+1)) / 2 moved onto the term
+// values: 201 registers instead of 233, still two waves per SIMD) 0.60.
 // Voxels per thread of the adjoint (rows iy, iy + hy, ... of one column):
 // two while each voxel's coefficients and the loaded terms fit the registers.
 template <int NQ>
